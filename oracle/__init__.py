@@ -1,0 +1,24 @@
+"""FP64 CPU oracle for the rank-structured supernodal Cholesky solver.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, independent
+restatement of what the method computes (NumPy / SciPy LAPACK, FP64).  Only
+``tests/``, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline`` leg
+may import or call it.  The product path (the HIP library and its Python
+binding) never imports it, and it imports nothing from the product.
+
+Parity status per function (what pins it, see the tests named ``test_oracle_*``):
+
+* ``ordering.nested_dissection`` / ``symbolic``: valid permutation, separator
+  property, union pattern contains the true Cholesky pattern, the descendant row
+  property of §2.1, the scatterRows worked example of §2.1.
+* ``factor.factor`` (exact): dense Cholesky of the permuted matrix (uniqueness).
+* ``factor.factor`` (compressed): full-rank sampling reproduces the exact factor;
+  exactly low-rank blocks are recovered; ``U^T U = I``, ``V = L^O U``; every
+  pivot positive (§3.2); approximation error against the SVD bound.
+* ``philox``: the published known-answer vectors of Philox4x32-10.
+* ``solve``: exact factor gives ``M^{-1} = A^{-1}``; symmetry and positivity of
+  the rank-structured preconditioner; manufactured solutions.
+* ``adjoint``: central finite differences of dense solves.
+* PCG iteration counts of the rank-structured preconditioner: parity unpinned by
+  the paper (checked only against this oracle's own count).
+"""

@@ -1,0 +1,184 @@
+"""Oracle: left-looking supernodal Cholesky, exact and rank-structured (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline``
+leg may import this module; the product path never does.  Plain FP64 NumPy /
+LAPACK, supernodes in ascending order, no blocking or fusion beyond what the
+paper states.
+
+Exact mode (``tol == 0``): Algorithm 1 (``factorSupernode``) for every
+supernode, with the Schur-complement assembly equations of §2.1: start from
+``A(C_j, C_j)`` and ``A(R_j, C_j)`` (the second assignment in Algorithm 1 is
+printed with the wrong left-hand side; it initialises the off-diagonal block),
+subtract ``scatter(X_D X_D^T)`` and ``scatter(X_O X_D^T)`` for every descendant,
+then ``L^D_j = chol(U^D_j)`` and ``L^O_j = U^O_j (L^D_j)^{-T}``.  Its result is
+the unique Cholesky factor of the permuted matrix.
+
+Rank-structured mode (``tol > 0``): after Algorithm 1, a separator supernode with
+``c_j >= tau_O`` columns and ``r_j > 0`` rows (§3.1, §3.3) is replaced by
+``L^O_j ~ V_j U_j^T`` from the randomized range finder of Algorithm 3, applied to
+the explicitly formed ``L^O_j``:
+
+1. ``l_j = min(k, ceil(alpha_O sqrt(k) log2 k) + p)``, ``k = min(r_j, c_j)``
+   (the rank function of §5.2, used as the number of samples);
+2. ``G = randomMatrix(r_j, l_j)``; ``Y = (L^O_j)^T G`` (the product Algorithm 3
+   labels ``offDiagonalMultiplyTrans``: a row-space sample);
+3. ``s_pow`` power iterations ``Y = (L^O_j)^T (L^O_j Y)``;
+4. ``U = makeOrthonormal(Y)`` (Householder QR);
+5. ``V = L^O_j U`` (the projection of Algorithm 3);
+6. truncation (the paper fixes ranks; this tolerance is an addition): with
+   ``V^T V = Z diag(lambda) Z^T`` (descending) and ``sigma_i = sqrt(lambda_i)``,
+   keep ``q_j = #{sigma_i > tol sigma_1}`` (``q_j = 0`` when ``sigma_1 = 0``),
+   ``U_j = U Z_q``, ``V_j = V Z_q``.
+
+``U_j`` stays orthonormal and ``V_j = L^O_j U_j``, which is the condition of §3.2
+under which every later Schur complement stays positive definite.  A compressed
+descendant updates its ancestors through ``V_k`` (§3.4, the low-rank product with
+``U_k^T U_k = I``).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .ordering import SEPARATOR, Symbolic, symbolic
+from .philox import gaussian_sample
+
+
+class NotSPDError(RuntimeError):
+    def __init__(self, supernode):
+        super().__init__(f"non-positive pivot in supernode {supernode}")
+        self.supernode = supernode
+
+
+@dataclass
+class Options:
+    leaf_max: int = 64
+    tau_O: int = 32
+    oversample: int = 10
+    power_iters: int = 0
+    alpha_O: float = 1.0
+    seed: int = 0
+
+
+def sample_count(r: int, c: int, alpha: float, p: int) -> int:
+    """Rank function of §5.2, ``alpha sqrt(k) log2(k) + p`` with ``k = min(r, c)``,
+    rounded up and capped at ``k``."""
+    k = min(r, c)
+    if k <= 0:
+        return 0
+    return int(min(k, math.ceil(alpha * math.sqrt(k) * math.log2(k)) + p))
+
+
+def compressible(sym: Symbolic, j: int, opts: Options, tol: float) -> bool:
+    return (tol > 0 and sym.kind[j] == SEPARATOR and sym.c(j) >= opts.tau_O and sym.r(j) > 0)
+
+
+@dataclass
+class Factor:
+    sym: Symbolic
+    tol: float
+    opts: Options
+    LD: list = field(default_factory=list)
+    LO: list = field(default_factory=list)     # dense L^O_j, or None when compressed
+    V: list = field(default_factory=list)
+    U: list = field(default_factory=list)
+    ell: list = field(default_factory=list)    # samples drawn (0 when not compressed)
+    q: list = field(default_factory=list)      # kept rank
+    flops: dict = field(default_factory=dict)
+
+    def offdiag(self, j):
+        """The stored off-diagonal operand ``X`` used by ancestors: ``L^O_j`` or ``V_j``."""
+        return self.LO[j] if self.LO[j] is not None else self.V[j]
+
+    def dense_L(self):
+        """The (approximate) factor as a dense lower-triangular matrix."""
+        n = self.sym.n
+        L = np.zeros((n, n))
+        for j in range(self.sym.M):
+            lo, hi = int(self.sym.first[j]), int(self.sym.first[j + 1])
+            L[lo:hi, lo:hi] = self.LD[j]
+            R = self.sym.rows[j]
+            if R.size:
+                L[np.ix_(R, np.arange(lo, hi))] = (self.LO[j] if self.LO[j] is not None
+                                                   else self.V[j] @ self.U[j].T)
+        return L
+
+
+def permuted_matrix(sym: Symbolic, n, rowptr, colind, values) -> sp.csr_matrix:
+    A = sp.csr_matrix((np.asarray(values, dtype=np.float64), colind, rowptr), shape=(n, n))
+    return A[sym.perm][:, sym.perm].tocsr()
+
+
+def compress(LO: np.ndarray, j: int, opts: Options, tol: float):
+    """Algorithm 3 on an explicit ``L^O_j`` followed by the truncation above."""
+    r, c = LO.shape
+    ell = sample_count(r, c, opts.alpha_O, opts.oversample)
+    G = gaussian_sample(opts.seed, j, r, ell)
+    Y = LO.T @ G
+    for _ in range(opts.power_iters):
+        Y = LO.T @ (LO @ Y)
+    U, _ = np.linalg.qr(Y)
+    V = LO @ U
+    lam, Z = np.linalg.eigh(V.T @ V)
+    order = np.argsort(lam)[::-1]
+    lam, Z = lam[order], Z[:, order]
+    sig = np.sqrt(np.maximum(lam, 0.0))
+    q = 0 if sig.size == 0 or sig[0] == 0.0 else int(np.count_nonzero(sig > tol * sig[0]))
+    return V @ Z[:, :q], U @ Z[:, :q], ell, q
+
+
+def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
+           opts: Options | None = None, stop_after: int | None = None) -> Factor:
+    """Factor supernodes ``0 .. M-1`` (or the first ``stop_after``) in order."""
+    opts = opts or Options()
+    Ap = permuted_matrix(sym, n, rowptr, colind, values)
+    F = Factor(sym=sym, tol=tol, opts=opts)
+    M = sym.M if stop_after is None else min(sym.M, stop_after)
+    fl = dict(potrf=0.0, trsm=0.0, update=0.0, sample=0.0, orth=0.0, trunc=0.0)
+    for j in range(M):
+        lo, hi = int(sym.first[j]), int(sym.first[j + 1])
+        c = hi - lo
+        R = sym.rows[j]
+        # Initialise the Schur complement blocks (Algorithm 1)
+        UD = Ap[lo:hi][:, lo:hi].toarray()
+        UO = Ap[R][:, lo:hi].toarray() if R.size else np.zeros((0, c))
+        for (k, p0, nD) in sym.pairs[j]:
+            X = F.offdiag(k)[p0:]
+            XD = X[:nD]
+            Rk = sym.rows[k]
+            cols = Rk[p0:p0 + nD] - lo                       # R^D_{k->j} within C_j
+            orow = np.searchsorted(R, Rk[p0 + nD:])          # R^O_{k->j} within R_j
+            UD[np.ix_(cols, cols)] -= XD @ XD.T
+            if orow.size:
+                UO[np.ix_(orow, cols)] -= X[nD:] @ XD.T
+            fl["update"] += 2.0 * X.shape[1] * (nD * (nD + 1) / 2.0 + float(X.shape[0] - nD) * nD)
+        try:
+            LD = np.linalg.cholesky(UD)
+        except np.linalg.LinAlgError:
+            raise NotSPDError(j) from None
+        if not np.all(np.isfinite(LD)):
+            raise NotSPDError(j)
+        LO = sla.solve_triangular(LD, UO.T, lower=True).T if R.size else np.zeros((0, c))
+        fl["potrf"] += c ** 3 / 3.0
+        fl["trsm"] += float(R.size) * c * c
+        F.LD.append(LD)
+        if compressible(sym, j, opts, tol):
+            V, U, ell, q = compress(LO, j, opts, tol)
+            F.LO.append(None); F.V.append(V); F.U.append(U); F.ell.append(ell); F.q.append(q)
+            fl["sample"] += 4.0 * R.size * c * ell * (1 + opts.power_iters)
+            fl["orth"] += 2.0 * c * ell * ell
+            fl["trunc"] += 2.0 * R.size * ell * ell
+        else:
+            F.LO.append(LO); F.V.append(None); F.U.append(None); F.ell.append(0); F.q.append(0)
+    F.flops = fl
+    return F
+
+
+def analyze_and_factor(n, rowptr, colind, values, tol=0.0, opts: Options | None = None):
+    opts = opts or Options()
+    sym = symbolic(n, rowptr, colind, opts.leaf_max)
+    return factor(sym, n, rowptr, colind, values, tol, opts)
