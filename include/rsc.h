@@ -1,0 +1,188 @@
+/*
+ * rsc.h -- C ABI of the rank-structured supernodal Cholesky solver for MI355X (gfx950).
+ *
+ * The method (Chadwick and Bindel, "An efficient solver for sparse linear systems
+ * based on rank-structured Cholesky factorization"): solve A x = b for a sparse
+ * symmetric positive definite A given only as a pre-assembled matrix (Sec. 1),
+ * with a symbolic phase on the host (nested-dissection ordering, elimination
+ * tree, supernodes; Sec. 2.1-2.2, 3.1) and a numeric phase on the device
+ * (Algorithm 1 per supernode, off-diagonal compression by Algorithm 3), the
+ * resulting factor preconditioning conjugate gradients (Sec. 5.2, 6.1.1).
+ *
+ * Conventions for every entry point:
+ *  - indices are 0-based; a function returns an rsc_status and never throws;
+ *    rsc_last_error() gives a message for the calling thread's last failure;
+ *  - "host" pointers are read during the call only and copied; "device" pointers
+ *    are HIP device memory owned by the caller, used in stream order on the
+ *    stream argument (a hipStream_t, NULL = the null stream) and must stay valid
+ *    until that stream reaches the end of the call's work;
+ *  - a handle owns all of its device memory (factor, plans, work space) and
+ *    releases it in rsc_destroy; a handle is not thread-safe, distinct handles are
+ *    independent;
+ *  - the symbolic phase needs no GPU; the first numeric call initialises the
+ *    current HIP device and binds the handle to it.
+ */
+#ifndef RSC_H
+#define RSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsc_handle_s* rsc_handle;
+
+typedef enum {
+  RSC_OK = 0,
+  RSC_ERR_INVALID_ARG = 1,   /* null pointer, negative size, option out of range */
+  RSC_ERR_PATTERN = 2,       /* pattern not symmetric / unsorted / duplicate / diagonal missing */
+  RSC_ERR_NOT_SPD = 3,       /* non-positive or non-finite pivot; supernode in rsc_stats */
+  RSC_ERR_NOT_CONVERGED = 4, /* PCG reached max_iter */
+  RSC_ERR_BREAKDOWN = 5,     /* PCG: p^T A p <= 0 or r^T z <= 0; or basis orthonormalisation failed */
+  RSC_ERR_OUT_OF_MEMORY = 6,
+  RSC_ERR_DEVICE = 7,        /* a HIP runtime call failed, or no gfx950 device */
+  RSC_ERR_STATE = 8          /* e.g. rsc_pcg before a successful rsc_factor */
+} rsc_status;
+
+enum {
+  RSC_FP64 = 0,        /* every product in FP64 on MFMA */
+  RSC_MIXED_BF16 = 1,  /* Schur-update and TRSM products as split BF16 (hi+lo, three BF16 MFMA
+                          products, FP32 accumulation), sampling products in plain BF16 with FP32
+                          accumulation; POTRF, orthonormalisation, projection and PCG in FP64 */
+  RSC_MIXED_FP32 = 2   /* Schur-update and TRSM products with FP32 operands and FP32 accumulation
+                          on MFMA, sampling in BF16; the rest FP64 */
+};
+
+typedef struct {
+  int32_t leaf_max;    /* dissection stops at subgraphs of at most this many vertices (64) */
+  int32_t tau_O;       /* separators with at least tau_O columns are compressed (Sec. 3.1; 32) */
+  int32_t oversample;  /* p of the rank function of Sec. 5.2 (10) */
+  int32_t power_iters; /* power iterations of Algorithm 3 (0) */
+  double alpha_O;      /* alpha of the rank function of Sec. 5.2, used as the sample cap (1.0) */
+  uint64_t seed;       /* key of the Philox4x32-10 sample streams (0) */
+  int32_t precision;   /* RSC_FP64 | RSC_MIXED_BF16 | RSC_MIXED_FP32 (RSC_FP64) */
+  int32_t use_graph;   /* replay the factor and PCG launch sequences as hipGraphs (1) */
+  int32_t retry;       /* mixed precision: on RSC_ERR_NOT_SPD refactor with FP32 products, then
+                          FP64 (the restart-with-more-accuracy policy of Sec. 5.3) (1) */
+  int32_t reserved;
+} rsc_options;
+
+typedef struct {
+  int32_t iters;          /* PCG iterations (one product with A each) */
+  int32_t converged;      /* 1 if ||r|| / ||b|| <= rtol was reached */
+  double rel_residual;    /* recursive residual ||r_k|| / ||b|| */
+  double true_residual;   /* ||b - A x|| / ||b|| recomputed after the loop */
+} rsc_pcg_result;
+
+typedef struct {
+  int64_t n, nnz, supernodes, levels, systems;
+  int64_t factor_entries;      /* stored FP64 entries of L (diagonal triangles + dense L^O + V,U) */
+  int64_t compressed;          /* supernodes stored as V U^T after the last factor */
+  int64_t rank_sum, sample_sum;/* sum of kept ranks q_j and of samples l_j */
+  int64_t rank_saturated;      /* supernodes with q_j == l_j < min(r_j, c_j) */
+  int32_t failed_supernode;    /* -1, or the supernode whose pivot failed */
+  int32_t precision_used;      /* precision of the last successful factor (after retries) */
+  int32_t retries;             /* refactorisations done by the retry policy */
+  int32_t reserved;
+  double flops_potrf, flops_trsm, flops_update, flops_sample, flops_orth, flops_trunc;
+  double bytes_factor;         /* bytes of the stored factor read by one preconditioner apply */
+  double t_analyze_ms;         /* host symbolic time */
+  double t_factor_ms;          /* device time of the last rsc_factor (hipEvents) */
+  double t_pcg_ms;             /* device time of the last rsc_pcg */
+  double device_bytes;         /* device memory owned by the handle */
+} rsc_stats;
+
+/* Kernel-class timing (hipEvents around every launch of a class while enabled). */
+enum { RSC_K_UPDATE = 0, RSC_K_POTRF = 1, RSC_K_TRSM = 2, RSC_K_GEMM = 3, RSC_K_EIG = 4,
+       RSC_K_PCG = 5, RSC_K_OTHER = 6, RSC_K_CLASSES = 7 };
+typedef struct {
+  int64_t launches[RSC_K_CLASSES];
+  double ms[RSC_K_CLASSES];
+  double flops[RSC_K_CLASSES];   /* algorithmic flops of the timed launches */
+} rsc_profile;
+
+/* Fill *opt with the defaults listed beside each field. */
+void rsc_default_options(rsc_options* opt);
+
+/* Symbolic phase (host only, no GPU needed; Sec. 2.1, 2.2, 3.1).
+ * n: order of A; rowptr: host int64[n+1]; colind: host int32[rowptr[n]] -- the full
+ * symmetric pattern (both triangles), rows sorted, no duplicates, every diagonal
+ * entry present.  opt may be NULL (defaults).  On success *out is a new handle.
+ * Errors: RSC_ERR_INVALID_ARG, RSC_ERR_PATTERN, RSC_ERR_OUT_OF_MEMORY. */
+rsc_status rsc_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                       const rsc_options* opt, rsc_handle* out);
+
+/* Symbolic phase for `count` independent systems factored together: the systems
+ * form one block-diagonal matrix (system i's unknowns follow system i-1's), so
+ * every elimination-tree level of every system is processed by the same launches;
+ * rsc_pcg then runs one independent CG per system.  n, rowptr, colind: host arrays
+ * of `count` entries, each as in rsc_analyze.  Values and vectors passed later are
+ * the systems' arrays concatenated in order. */
+rsc_status rsc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* rowptr,
+                             const int32_t* const* colind, const rsc_options* opt, rsc_handle* out);
+
+/* Numeric factorization on the device (Algorithm 1 for every supernode, level by
+ * level; with tol > 0, Algorithm 3 plus spectral truncation at tol for separators
+ * with at least tau_O columns).  values: device double[nnz] aligned with colind;
+ * only entries with col <= row are read (the values are taken as symmetric).
+ * tol: 0 for the exact factor, else the relative singular-value cut-off (0 < tol < 1).
+ * Returns RSC_ERR_NOT_SPD (with stats.failed_supernode) when a pivot is not positive.
+ * Synchronises the stream before returning (it reads the status word). */
+rsc_status rsc_factor(rsc_handle h, const double* values, double tol, void* stream);
+
+/* Preconditioned CG (Sec. 5.2, 6.1.1) with the factor as preconditioner: x0 = 0,
+ * stop when ||r_k|| / ||b|| <= rtol or after max_iter iterations.  b, x: device
+ * double[n].  out: host array of `systems` results (one per system of a batch).
+ * Returns RSC_ERR_NOT_CONVERGED if some system did not converge (x still holds the
+ * last iterate), RSC_ERR_BREAKDOWN on a non-positive curvature or r^T z. */
+rsc_status rsc_pcg(rsc_handle h, const double* b, double* x, double rtol, int32_t max_iter,
+                   void* stream, rsc_pcg_result* out);
+
+/* z = P^T L^{-T} L^{-1} P r: the two triangular solves of Sec. 1 with the stored
+ * (exact or rank-structured) factor.  r, z: device double[n], may not alias. */
+rsc_status rsc_apply_preconditioner(rsc_handle h, const double* r, double* z, void* stream);
+
+/* Adjoint of the solve with respect to the matrix values (not in the paper):
+ * g[p] = -lambda[row(p)] * x[col(p)] for every stored entry p (CSR order).
+ * lambda, x: device double[n]; g: device double[nnz]. */
+rsc_status rsc_grad_values(rsc_handle h, const double* lambda, const double* x, double* g,
+                           void* stream);
+
+/* Gradient with respect to face coefficients of a two-point-flux operator (not in
+ * the paper): g[f] = -(lambda[i]-lambda[j])(x[i]-x[j]) for a face between unknowns
+ * i = face_i[f] and j = face_j[f] >= 0, and -lambda[i] x[i] when face_j[f] < 0
+ * (a boundary face).  All arrays are device memory; nfaces >= 0. */
+rsc_status rsc_grad_faces(int64_t nfaces, const int32_t* face_i, const int32_t* face_j,
+                          const double* lambda, const double* x, double* g, void* stream);
+
+/* ---- inspection (host copies; valid after rsc_analyze unless noted) ---- */
+rsc_status rsc_get_sizes(rsc_handle h, int64_t* n, int64_t* nnz, int64_t* supernodes,
+                         int64_t* levels, int64_t* systems);
+/* perm: host int64[n], new index -> old index. */
+rsc_status rsc_get_permutation(rsc_handle h, int64_t* perm);
+/* first: int64[M+1] column boundaries; parent, level, kind (0 leaf, 1 separator): int32[M]. */
+rsc_status rsc_get_supernodes(rsc_handle h, int64_t* first, int32_t* parent, int32_t* level,
+                              int32_t* kind);
+/* rowptr: int64[M+1]; rows: int64[rowptr[M]]: the sorted off-diagonal rows R_j. */
+rsc_status rsc_get_rowsets(rsc_handle h, int64_t* rowptr, int64_t* rows);
+/* After rsc_factor: samples l_j and kept ranks q_j (0 for uncompressed), int32[M]. */
+rsc_status rsc_get_ranks(rsc_handle h, int32_t* ell, int32_t* q);
+/* After rsc_factor: copy one supernode's blocks to host, column-major:
+ * LD (c x c, lower triangle valid), LO (r x c; zeros when compressed),
+ * V (r x q), U (c x q).  Any pointer may be NULL. */
+rsc_status rsc_get_block(rsc_handle h, int64_t j, double* LD, double* LO, double* V, double* U);
+rsc_status rsc_get_stats(rsc_handle h, rsc_stats* out);
+rsc_status rsc_profile_enable(rsc_handle h, int32_t on);   /* also resets the counters */
+rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
+
+const char* rsc_status_string(rsc_status s);
+const char* rsc_last_error(void);
+/* Releases the handle and all its device memory (after synchronising its device). */
+void rsc_destroy(rsc_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSC_H */

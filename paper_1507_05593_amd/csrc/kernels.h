@@ -1,0 +1,62 @@
+// Host-side launchers of the gfx950 kernels (all asynchronous on the given stream).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "tasks.h"
+
+namespace rsc {
+
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, double* arena,
+                     hipStream_t s);
+void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s);
+void launch_gemm_f64(const GemmTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
+void launch_update_f64(const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
+                       double* arena, const int32_t* ilim, hipStream_t s);
+void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s);
+void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
+                   hipStream_t s);
+void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int64_t* out,
+                       int n, double* arena, hipStream_t s);
+void launch_jacobi_small(const EigTask* t, int n, double* arena, hipStream_t s);
+void launch_jacobi_round(const EigTask* t, int n, int max_pairs, int max_rowblocks, double* arena,
+                         int32_t* ints, int rnd, hipStream_t s);
+void launch_eig_init(const EigTask* t, int n, double* arena, hipStream_t s);
+void launch_eig_select(const EigTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
+
+void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
+void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
+                   const int32_t* ilim, hipStream_t s);
+void launch_trsv_bwd(const RowTask* t, int n, double* arena, hipStream_t s);
+void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
+                       int64_t nrows, const double* part, double* y, hipStream_t s);
+void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);
+void launch_scatter_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);
+void launch_spmv_dot(const Chunk* c, int nc, const int64_t* rowptr, const int32_t* colind,
+                     const double* vals, const double* p, double* Ap, double* partial, hipStream_t s);
+void launch_dot_partial(const Chunk* c, int nc, const double* a, const double* b, double* partial,
+                        hipStream_t s);
+void launch_resid_partial(const Chunk* c, int nc, const double* b, const double* ax,
+                          double* partial, hipStream_t s);
+void launch_seg_sum(const int32_t* seg_ptr, int32_t nseg, const double* partial, double* out,
+                    hipStream_t s);
+void launch_pcg_alpha(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s);
+void launch_pcg_xr(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
+                   double* partial, hipStream_t s);
+void launch_pcg_check(int32_t nseg, const PcgScalars& sc, double rtol, double* arena, int32_t* ints,
+                      hipStream_t s);
+void launch_pcg_beta(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s);
+void launch_pcg_p(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
+                  int first, hipStream_t s);
+void launch_pcg_start(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s);
+void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
+void launch_grad_values(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* lam,
+                        const double* x, double* g, hipStream_t s);
+void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const double* lam,
+                       const double* x, double* g, hipStream_t s);
+
+}  // namespace rsc

@@ -1,0 +1,384 @@
+// gfx950 kernels of the solve phase: the two supernodal triangular sweeps with the
+// stored factor (paper Sec. 1: two triangular solves), CSR SpMV, wavefront
+// reductions for the CG scalars (Sec. 5.2, 6.1.1), and the solve adjoint.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+#include "tasks.h"
+
+namespace rsc {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide deterministic sum (fixed reduction tree) of 256 threads.
+__device__ double block_sum(double v) {
+  __shared__ double red[4];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------- sweeps
+
+// out[t] = sum_{m < K} X(t, m) v[m], one thread per row t (coalesced column reads).
+__global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tasks,
+                                                double* __restrict__ arena,
+                                                const int32_t* __restrict__ ilim) {
+  const GemvTask T = tasks[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t >= T.rows) return;
+  const int K = T.kdim >= 0 ? T.kdim : ilim[-1 - T.kdim];
+  const double* X = arena + T.x + t;
+  const double* v = arena + T.v;
+  double acc = 0.0;
+  for (int m = 0; m < K; ++m) acc += X[(int64_t)m * T.ldx] * v[m];
+  arena[T.out + t] = acc;
+}
+
+// One wave per output column: lanes stride the rows, then a wave reduction.
+__global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ tasks,
+                                                double* __restrict__ arena,
+                                                const int64_t* __restrict__ gidx,
+                                                const int32_t* __restrict__ ilim) {
+  const ColDotTask T = tasks[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ncols = T.ncols >= 0 ? T.ncols : ilim[-1 - T.ncols];
+  const double* in = arena + T.in;
+  for (int u = 0; u < 4; ++u) {
+    const int col = T.col0 + w * 4 + u;
+    if (col >= ncols) continue;
+    const int rows = T.tri ? col + 1 : T.rows;
+    const double* X = arena + T.x + (int64_t)col * T.ldx;
+    double acc = 0.0;
+    if (T.idx >= 0) {
+      const int64_t* ix = gidx + T.idx;
+      for (int t = lane; t < rows; t += 64) acc += X[t] * in[ix[t]];
+    } else {
+      for (int t = lane; t < rows; t += 64) acc += X[t] * in[t];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) arena[T.out + col] = acc;
+  }
+}
+
+// out[i] = sum_{t >= i} M(i, t) (w[t] - s[t]): backward solve with L^{-T}.
+__global__ __launch_bounds__(256) void k_trsv_bwd(const RowTask* __restrict__ tasks,
+                                                  double* __restrict__ arena) {
+  const RowTask T = tasks[blockIdx.x];
+  const int i = T.i0 + threadIdx.x;
+  if (i >= T.c) return;
+  const double* M = arena + T.m + i;
+  const double* w = arena + T.w;
+  double acc = 0.0;
+  if (T.s >= 0) {
+    const double* s = arena + T.s;
+    for (int t = i; t < T.c; ++t) acc += M[(int64_t)t * T.ld] * (w[t] - s[t]);
+  } else {
+    for (int t = i; t < T.c; ++t) acc += M[(int64_t)t * T.ld] * w[t];
+  }
+  arena[T.out + i] = acc;
+}
+
+// y[rows[t]] -= sum of part[contrib[p]], p in [ptr[t], ptr[t+1]), in list order.
+__global__ void k_row_gather(const int64_t* __restrict__ rows, const int64_t* __restrict__ ptr,
+                             const int64_t* __restrict__ contrib, int64_t nrows,
+                             const double* __restrict__ part, double* __restrict__ y) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  double s = 0.0;
+  for (int64_t p = ptr[t]; p < ptr[t + 1]; ++p) s += part[contrib[p]];
+  y[rows[t]] -= s;
+}
+
+__global__ void k_gather_perm(int64_t n, const int64_t* __restrict__ perm,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ void k_scatter_perm(int64_t n, const int64_t* __restrict__ perm,
+                               const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[perm[i]] = src[i];
+}
+
+// ---------------------------------------------------------------- CG vectors
+
+// Ap = A p on one chunk of rows (one thread per row), partial = p . Ap for the chunk.
+__global__ __launch_bounds__(256) void k_spmv_dot(const Chunk* __restrict__ chunks,
+                                                  const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind,
+                                                  const double* __restrict__ vals,
+                                                  const double* __restrict__ p,
+                                                  double* __restrict__ Ap,
+                                                  double* __restrict__ partial) {
+  const Chunk C = chunks[blockIdx.x];
+  const int64_t i = C.begin + threadIdx.x;
+  double d = 0.0;
+  if (i < C.end) {
+    double s = 0.0;
+    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += vals[q] * p[colind[q]];
+    Ap[i] = s;
+    d = p[i] * s;
+  }
+  d = block_sum(d);
+  if (threadIdx.x == 0) partial[blockIdx.x] = d;
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(const Chunk* __restrict__ chunks,
+                                                     const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ partial) {
+  const Chunk C = chunks[blockIdx.x];
+  const int64_t i = C.begin + threadIdx.x;
+  double d = (i < C.end) ? a[i] * b[i] : 0.0;
+  d = block_sum(d);
+  if (threadIdx.x == 0) partial[blockIdx.x] = d;
+}
+
+// partial = sum over the chunk of (b - Ax)^2 (true residual).
+__global__ __launch_bounds__(256) void k_resid_partial(const Chunk* __restrict__ chunks,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ ax,
+                                                       double* __restrict__ partial) {
+  const Chunk C = chunks[blockIdx.x];
+  const int64_t i = C.begin + threadIdx.x;
+  double d = 0.0;
+  if (i < C.end) {
+    const double t = b[i] - ax[i];
+    d = t * t;
+  }
+  d = block_sum(d);
+  if (threadIdx.x == 0) partial[blockIdx.x] = d;
+}
+
+// out[s] = sum of the partials of segment s, in chunk order (deterministic).
+__global__ void k_seg_sum(const int32_t* __restrict__ seg_ptr, int32_t nseg,
+                          const double* __restrict__ partial, double* __restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  double acc = 0.0;
+  for (int c = seg_ptr[s]; c < seg_ptr[s + 1]; ++c) acc += partial[c];
+  out[s] = acc;
+}
+
+// Per-system CG scalars.  sc layout (doubles, per segment s): see PcgScalars.
+__global__ void k_pcg_alpha(int32_t nseg, PcgScalars sc, double* __restrict__ arena,
+                            int32_t* __restrict__ ints) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  double* pAp = arena + sc.pAp;
+  double* rz = arena + sc.rz;
+  double* alpha = arena + sc.alpha;
+  int32_t* active = ints + sc.active;
+  double a = 0.0;
+  if (active[s]) {
+    if (!(pAp[s] > 0.0) || !(rz[s] > 0.0)) {
+      ints[sc.breakdown] = 1;
+      active[s] = 0;
+    } else {
+      a = rz[s] / pAp[s];
+    }
+  }
+  alpha[s] = a;
+}
+
+__global__ __launch_bounds__(256) void k_pcg_xr(const Chunk* __restrict__ chunks, PcgScalars sc,
+                                                double* __restrict__ arena,
+                                                const int32_t* __restrict__ ints,
+                                                double* __restrict__ partial) {
+  const Chunk C = chunks[blockIdx.x];
+  const int64_t i = C.begin + threadIdx.x;
+  const double a = arena[sc.alpha + C.seg];
+  double d = 0.0;
+  if (i < C.end) {
+    double* x = arena + sc.x;
+    double* r = arena + sc.r;
+    const double* p = arena + sc.p;
+    const double* Ap = arena + sc.Ap;
+    if (ints[sc.active + C.seg]) {
+      x[i] += a * p[i];
+      r[i] -= a * Ap[i];
+    }
+    d = r[i] * r[i];
+  }
+  d = block_sum(d);
+  if (threadIdx.x == 0) partial[blockIdx.x] = d;
+}
+
+// Convergence test ||r|| / ||b|| <= rtol per system; counts the iteration.
+__global__ void k_pcg_check(int32_t nseg, PcgScalars sc, double rtol, double* __restrict__ arena,
+                            int32_t* __restrict__ ints) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
+    int32_t* active = ints + sc.active;
+    if (!active[s]) continue;
+    ints[sc.iters + s] += 1;
+    const double rel = sqrt(arena[sc.rr + s]) / arena[sc.bnorm + s];
+    arena[sc.rel + s] = rel;
+    if (rel <= rtol || !isfinite(rel)) active[s] = 0;
+    else atomicOr(&any, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ints[sc.any] = any;
+}
+
+__global__ void k_pcg_beta(int32_t nseg, PcgScalars sc, double* __restrict__ arena,
+                           int32_t* __restrict__ ints) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  if (!ints[sc.active + s]) { arena[sc.beta + s] = 0.0; return; }
+  const double rzn = arena[sc.rznew + s], rzo = arena[sc.rz + s];
+  if (!(rzn > 0.0) || !(rzo > 0.0)) {
+    ints[sc.breakdown] = 1;
+    ints[sc.active + s] = 0;
+    arena[sc.beta + s] = 0.0;
+    return;
+  }
+  arena[sc.beta + s] = rzn / rzo;
+  arena[sc.rz + s] = rzn;
+}
+
+__global__ __launch_bounds__(256) void k_pcg_p(const Chunk* __restrict__ chunks, PcgScalars sc,
+                                               double* __restrict__ arena,
+                                               const int32_t* __restrict__ ints, int first) {
+  const Chunk C = chunks[blockIdx.x];
+  const int64_t i = C.begin + threadIdx.x;
+  if (i >= C.end) return;
+  double* p = arena + sc.p;
+  if (first) {              // p = z (p holds no value yet: never read it)
+    p[i] = arena[sc.z + i];
+    return;
+  }
+  if (!ints[sc.active + C.seg]) return;
+  p[i] = arena[sc.z + i] + arena[sc.beta + C.seg] * p[i];
+}
+
+// Start of CG: x = 0, r = b, bnorm = ||b|| (set by the caller), iters = 0, active = bnorm > 0.
+__global__ void k_pcg_start(int32_t nseg, PcgScalars sc, double* __restrict__ arena,
+                            int32_t* __restrict__ ints) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) { ints[sc.breakdown] = 0; }
+  if (s >= nseg) return;
+  const double bb = arena[sc.bnorm + s];
+  arena[sc.bnorm + s] = sqrt(bb);
+  ints[sc.active + s] = bb > 0.0 ? 1 : 0;
+  ints[sc.iters + s] = 0;
+  arena[sc.rel + s] = bb > 0.0 ? 1.0 : 0.0;
+}
+
+__global__ void k_copy(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------- adjoint
+
+__global__ void k_grad_values(int64_t n, const int64_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ colind, const double* __restrict__ lam,
+                              const double* __restrict__ x, double* __restrict__ g) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double li = lam[i];
+  for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) g[q] = -li * x[colind[q]];
+}
+
+__global__ void k_grad_faces(int64_t nf, const int32_t* __restrict__ fi,
+                             const int32_t* __restrict__ fj, const double* __restrict__ lam,
+                             const double* __restrict__ x, double* __restrict__ g) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int i = fi[f], j = fj[f];
+  g[f] = (j >= 0) ? -(lam[i] - lam[j]) * (x[i] - x[j]) : -lam[i] * x[i];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gemv_n, dim3(n), dim3(256), 0, s, t, arena, ilim);
+}
+void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
+                   const int32_t* ilim, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_coldot, dim3(n), dim3(256), 0, s, t, arena, gidx, ilim);
+}
+void launch_trsv_bwd(const RowTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trsv_bwd, dim3(n), dim3(256), 0, s, t, arena);
+}
+void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
+                       int64_t nrows, const double* part, double* y, hipStream_t s) {
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_row_gather, dim3(blocks_for(nrows)), dim3(256), 0, s, rows, ptr, contrib,
+                       nrows, part, y);
+}
+void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n)), dim3(256), 0, s, n, perm, src, dst);
+}
+void launch_scatter_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_scatter_perm, dim3(blocks_for(n)), dim3(256), 0, s, n, perm, src, dst);
+}
+void launch_spmv_dot(const Chunk* c, int nc, const int64_t* rowptr, const int32_t* colind,
+                     const double* vals, const double* p, double* Ap, double* partial, hipStream_t s) {
+  if (nc > 0)
+    hipLaunchKernelGGL(k_spmv_dot, dim3(nc), dim3(256), 0, s, c, rowptr, colind, vals, p, Ap, partial);
+}
+void launch_dot_partial(const Chunk* c, int nc, const double* a, const double* b, double* partial,
+                        hipStream_t s) {
+  if (nc > 0) hipLaunchKernelGGL(k_dot_partial, dim3(nc), dim3(256), 0, s, c, a, b, partial);
+}
+void launch_resid_partial(const Chunk* c, int nc, const double* b, const double* ax,
+                          double* partial, hipStream_t s) {
+  if (nc > 0) hipLaunchKernelGGL(k_resid_partial, dim3(nc), dim3(256), 0, s, c, b, ax, partial);
+}
+void launch_seg_sum(const int32_t* seg_ptr, int32_t nseg, const double* partial, double* out,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_sum, dim3((nseg + 255) / 256), dim3(256), 0, s, seg_ptr, nseg, partial, out);
+}
+void launch_pcg_alpha(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_alpha, dim3((nseg + 255) / 256), dim3(256), 0, s, nseg, sc, arena, ints);
+}
+void launch_pcg_xr(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
+                   double* partial, hipStream_t s) {
+  if (nc > 0) hipLaunchKernelGGL(k_pcg_xr, dim3(nc), dim3(256), 0, s, c, sc, arena, ints, partial);
+}
+void launch_pcg_check(int32_t nseg, const PcgScalars& sc, double rtol, double* arena, int32_t* ints,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, nseg, sc, rtol, arena, ints);
+}
+void launch_pcg_beta(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_beta, dim3((nseg + 255) / 256), dim3(256), 0, s, nseg, sc, arena, ints);
+}
+void launch_pcg_p(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
+                  int first, hipStream_t s) {
+  if (nc > 0) hipLaunchKernelGGL(k_pcg_p, dim3(nc), dim3(256), 0, s, c, sc, arena, ints, first);
+}
+void launch_pcg_start(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_start, dim3((nseg + 255) / 256), dim3(256), 0, s, nseg, sc, arena, ints);
+}
+void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(256), 0, s, n, a, b);
+}
+void launch_grad_values(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* lam,
+                        const double* x, double* g, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_grad_values, dim3(blocks_for(n)), dim3(256), 0, s, n, rowptr, colind, lam, x, g);
+}
+void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const double* lam,
+                       const double* x, double* g, hipStream_t s) {
+  if (nf > 0) hipLaunchKernelGGL(k_grad_faces, dim3(blocks_for(nf)), dim3(256), 0, s, nf, fi, fj, lam, x, g);
+}
+
+}  // namespace rsc

@@ -1,0 +1,1110 @@
+// Device runtime: memory plan, launch plans (factor and solve), executor with
+// hipGraph replay, the factor driver and the PCG driver.
+//
+// Storage (one FP64 arena per handle):
+//   panel j: column-major (2 c_j + r_j) x c_j, ld = 2 c_j + r_j; rows [0, c) hold L^D_j,
+//   rows [c, c + r) hold L^O_j (rows R_j in order), rows [c + r, 2c + r) start as the
+//   identity and end as L^D_j^{-T} (the same blocked solve that forms L^O_j), which
+//   the preconditioner sweeps use as explicit inverses of the diagonal blocks.
+//   A compressed supernode additionally owns V_j (r x l_j) and U_j (c x l_j) and the
+//   work space of its range finder.
+#include "runtime.h"
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "kernels.h"
+
+namespace rsc {
+
+#define HIPCHK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
+      return Error{RSC_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};  \
+  } while (0)
+
+static const Error kOk{RSC_OK, ""};
+static constexpr int kSweepsBlockJacobi = 8;
+
+int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p) {
+  const int32_t k = std::min(r, c);
+  if (k <= 0) return 0;
+  const double v = std::ceil(alpha * std::sqrt((double)k) * std::log2((double)k)) + p;
+  return (int32_t)std::min<double>(k, v);
+}
+
+static int64_t align64(int64_t x) { return (x + 63) & ~int64_t(63); }
+
+// ------------------------------------------------------------------ layout
+
+void plan_layout(Handle& h) {
+  Symbolic& S = h.S;
+  const int64_t M = S.M();
+  h.panel_off.assign(M, 0);
+  h.panel_ld.assign(M, 0);
+  h.dinv_off.assign(M, 0);
+  h.compressible.assign(M, 0);
+  int64_t poff = 0, doff = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    const int64_t c = S.c(j), r = S.r(j);
+    h.panel_ld[j] = (int32_t)(2 * c + r);
+    h.panel_off[j] = poff;
+    poff += align64((2 * c + r) * c);
+    h.dinv_off[j] = doff;
+    doff += ((c + 63) / 64) * 4096;
+    h.compressible[j] = (S.kind[j] == kSeparator && c >= h.opt.tau_O && r > 0) ? 1 : 0;
+  }
+  const int64_t n = S.n, nnz = S.nnz;
+  const int32_t nseg = (int32_t)h.seg_first.size() - 1;
+  // arena regions
+  int64_t a = 0;
+  h.a_values = a; a += align64(nnz);
+  h.a_panels = a; a += poff;
+  h.a_dinv = a; a += doff;
+  h.a_x = a; a += align64(n);
+  h.a_r = a; a += align64(n);
+  h.a_z = a; a += align64(n);
+  h.a_p = a; a += align64(n);
+  h.a_Ap = a; a += align64(n);
+  h.a_y = a; a += align64(n);
+  h.a_w = a; a += align64(n);
+  h.a_s = a; a += align64(n);
+  h.a_zz = a; a += align64(n);
+  h.a_b = a; a += align64(n);
+  // forward-sweep partials: one per gathered diagonal row of every pair
+  h.part_off.assign(S.pairs.size(), 0);
+  int64_t pt = 0;
+  for (size_t q = 0; q < S.pairs.size(); ++q) { h.part_off[q] = pt; pt += S.pairs[q].nD; }
+  h.part_total = pt;
+  h.a_part = a; a += align64(std::max<int64_t>(pt, 1));
+  // chunks of <= 256 rows inside one system
+  int32_t nch = 0;
+  for (int32_t s = 0; s < nseg; ++s) nch += (int32_t)((h.seg_first[s + 1] - h.seg_first[s] + 255) / 256);
+  h.nchunks = nch;
+  h.a_partial = a; a += align64(std::max(nch, 1));
+  h.a_seg = a; a += align64(10 * (int64_t)nseg);
+  h.sc.x = h.a_x; h.sc.r = h.a_r; h.sc.z = h.a_z; h.sc.p = h.a_p; h.sc.Ap = h.a_Ap;
+  h.sc.rz = h.a_seg; h.sc.rznew = h.a_seg + nseg; h.sc.pAp = h.a_seg + 2 * nseg;
+  h.sc.alpha = h.a_seg + 3 * nseg; h.sc.beta = h.a_seg + 4 * nseg; h.sc.rr = h.a_seg + 5 * nseg;
+  h.sc.bnorm = h.a_seg + 6 * nseg; h.sc.rel = h.a_seg + 7 * nseg;
+  // compression work space, per compressible supernode (Gram blocks grouped together)
+  h.comp.assign(M, CompSlot());
+  int32_t islot = 0;
+  h.i_status = islot; islot += 4;
+  h.i_ranks = islot; islot += (int32_t)M;
+  int64_t gv_region = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    if (!h.compressible[j]) continue;
+    CompSlot& C = h.comp[j];
+    const int32_t c = S.c(j), r = S.r(j);
+    C.ell = sample_count(r, c, h.opt.alpha_O, h.opt.oversample);
+    C.npad = C.ell <= 64 ? 64 : (int32_t)(((C.ell + 63) / 64) * 64);
+    C.nbk = C.npad / 32;
+    const int64_t l = C.ell;
+    C.omega = a; a += align64(r * l);
+    C.ypanel = a; a += align64((l + c) * l);
+    C.ydinv = a; a += ((l + 63) / 64) * 4096;
+    C.V = a; a += align64(r * l);
+    C.Vj = a; a += align64(r * l);
+    C.Uj = a; a += align64(c * l);
+    C.zq = a; a += align64(l * l);
+    C.lam = a; a += align64(l);
+    C.rot = a; a += (int64_t)(C.nbk / 2) * 4096;
+    C.gscale = a; C.escale = a + 1; a += 64;
+    C.tvq = a; a += align64(l);
+    C.u = a; a += align64(l);
+    C.qslot = h.i_ranks + (int32_t)j;
+    C.flagslot = islot; islot += C.nbk / 2;
+    gv_region += 2 * (int64_t)C.npad * C.npad;
+  }
+  // Gram matrices and eigenvectors of every compressible supernode, contiguous so
+  // that one fill clears their padding
+  int64_t gv = a;
+  for (int64_t j = 0; j < M; ++j) {
+    if (!h.compressible[j]) continue;
+    CompSlot& C = h.comp[j];
+    C.Gv = gv; gv += (int64_t)C.npad * C.npad;
+    C.Z = gv; gv += (int64_t)C.npad * C.npad;
+  }
+  a = align64(gv);
+  h.arena_size = a;
+  // PCG int slots
+  h.sc.active = islot; islot += nseg;
+  h.sc.iters = islot; islot += nseg;
+  h.sc.any = islot++;
+  h.sc.breakdown = islot++;
+  h.ints_size = islot;
+  (void)gv_region;
+
+  // assembly map: entry (i, col) with col <= i goes to the lower position of the
+  // permuted pair in the panel of the supernode owning the column
+  h.asm_slot.assign(nnz, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = h.rowptr[i]; p < h.rowptr[i + 1]; ++p) {
+      const int64_t col = h.colind[p];
+      if (col > i) continue;
+      const int64_t ni = S.iperm[i], nc = S.iperm[col];
+      const int64_t lo = std::min(ni, nc), hi = std::max(ni, nc);
+      const int64_t j = S.owner[lo];
+      const int64_t t = lo - S.first[j];
+      int64_t rowpos;
+      if (hi < S.first[j + 1]) {
+        rowpos = hi - S.first[j];
+      } else {
+        const int64_t* b = S.rows.data() + S.rows_ptr[j];
+        const int64_t* e = S.rows.data() + S.rows_ptr[j + 1];
+        const int64_t* f = std::lower_bound(b, e, hi);
+        rowpos = S.c(j) + (f - b);
+      }
+      h.asm_slot[p] = h.a_panels + h.panel_off[j] + t * h.panel_ld[j] + rowpos;
+    }
+  }
+  h.ident_slot.clear();
+  for (int64_t j = 0; j < M; ++j) {
+    const int64_t c = S.c(j), r = S.r(j);
+    for (int64_t t = 0; t < c; ++t)
+      h.ident_slot.push_back(h.a_panels + h.panel_off[j] + t * h.panel_ld[j] + (c + r + t));
+  }
+}
+
+// ------------------------------------------------------------------ device set-up
+
+template <class T>
+static Error upload(DevArray<T>& d, const std::vector<T>& v) {
+  d.reset();
+  d.n = (int64_t)v.size();
+  if (v.empty()) return kOk;
+  HIPCHK(hipMalloc((void**)&d.p, sizeof(T) * v.size()));
+  HIPCHK(hipMemcpy(d.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+  return kOk;
+}
+
+Error ensure_device(Handle& h) {
+  if (h.dev_ready) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != h.device) return Error{RSC_ERR_STATE, "handle is bound to another device"};
+    return kOk;
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return Error{RSC_ERR_DEVICE, std::string("this library is built for gfx950, found ") + prop.gcnArchName};
+  h.device = dev;
+  size_t bytes = sizeof(double) * (size_t)h.arena_size;
+  hipError_t e = hipMalloc((void**)&h.arena.p, bytes);
+  if (e != hipSuccess) return Error{RSC_ERR_OUT_OF_MEMORY, "arena of " + std::to_string(bytes) + " bytes"};
+  h.arena.n = h.arena_size;
+  HIPCHK(hipMalloc((void**)&h.ints.p, sizeof(int32_t) * (size_t)h.ints_size));
+  h.ints.n = h.ints_size;
+  HIPCHK(hipMemset(h.ints.p, 0, sizeof(int32_t) * (size_t)h.ints_size));
+  Error r;
+  if ((r = upload(h.d_asm_slot, h.asm_slot)).code) return r;
+  if ((r = upload(h.d_ident_slot, h.ident_slot)).code) return r;
+  if ((r = upload(h.d_perm, h.S.perm)).code) return r;
+  if ((r = upload(h.d_rows, h.S.rows)).code) return r;
+  if ((r = upload(h.d_rowptr, h.rowptr)).code) return r;
+  if ((r = upload(h.d_colind, h.colind)).code) return r;
+  if ((r = upload(h.d_relmap, h.S.relmap)).code) return r;
+  std::vector<Chunk> ch;
+  std::vector<int32_t> segp(1, 0);
+  const int32_t nseg = (int32_t)h.seg_first.size() - 1;
+  for (int32_t s = 0; s < nseg; ++s) {
+    for (int64_t b = h.seg_first[s]; b < h.seg_first[s + 1]; b += 256)
+      ch.push_back(Chunk{b, std::min(b + 256, h.seg_first[s + 1]), s, 0});
+    segp.push_back((int32_t)ch.size());
+  }
+  if ((r = upload(h.d_chunks, ch)).code) return r;
+  if ((r = upload(h.d_seg_chunk_ptr, segp)).code) return r;
+  HIPCHK(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
+  h.dev_ready = true;
+  return kOk;
+}
+
+void release_device(Handle& h) {
+  if (h.dev_ready) (void)hipDeviceSynchronize();
+  if (h.fplan && h.fplan->graph) (void)hipGraphExecDestroy(h.fplan->graph);
+  if (h.splan) {
+    if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
+    if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
+    if (h.splan->graph_apply) (void)hipGraphExecDestroy(h.splan->graph_apply);
+  }
+  h.fplan.reset();
+  h.splan.reset();
+  if (h.cap_stream) (void)hipStreamDestroy(h.cap_stream);
+  h.cap_stream = nullptr;
+  h.dev_ready = false;
+}
+
+// ------------------------------------------------------------------ factor plan
+
+namespace {
+
+struct PanelDesc {
+  int64_t off;
+  int32_t ld, n, m_below;
+  bool ident;
+  int64_t dinv;
+  int32_t sn, mode;
+  int64_t scale_off;
+};
+
+struct Builder {
+  Handle& h;
+  FactorPlan& P;
+  Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {}
+
+  void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
+           int64_t b = 0, double v = 0) {
+    if (count <= 0 && type != kCmdJacobiRound) return;
+    Cmd c;
+    c.type = type; c.klass = klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
+    c.flops = flops;
+    P.cmds.push_back(c);
+  }
+
+  // Tiles of C(i, j) for i in [ib, m), j in [jb, n); lower: skip tiles with i0 < j0.
+  double tiles(GemmTask t, int32_t ib, int32_t jb, bool lower) {
+    double fl = 0;
+    for (int32_t j0 = jb; j0 < t.n; j0 += kTile)
+      for (int32_t i0 = ib; i0 < t.m; i0 += kTile) {
+        if (lower && i0 < j0) continue;
+        t.i0 = i0; t.j0 = j0;
+        P.gemm.push_back(t);
+        fl += 2.0 * std::min(kTile, t.m - i0) * std::min(kTile, t.n - j0) * (double)t.k;
+      }
+    return fl;
+  }
+
+  static GemmTask gt(int64_t a, int32_t ais, int32_t aks, int64_t b, int32_t bjs, int32_t bks,
+                     int64_t c, int32_t ldc, int32_t m, int32_t n, int32_t k, double alpha,
+                     double beta) {
+    GemmTask t{};
+    t.a = a; t.ais = ais; t.aks = aks; t.b = b; t.bjs = bjs; t.bks = bks; t.c = c; t.ldc = ldc;
+    t.m = m; t.n = n; t.k = k; t.alpha = alpha; t.beta = beta; t.nlim = -1; t.klim = -1;
+    return t;
+  }
+
+  // Blocked right-looking factorisation of tall panels [diag n x n; m_below rows;
+  // optional identity rows], 64 columns per step: diagonal Cholesky + inverse, the
+  // rows below times the inverse (in place), then the trailing update.
+  void panel_steps(const std::vector<PanelDesc>& pan) {
+    int32_t maxn = 0;
+    for (auto& p : pan) maxn = std::max(maxn, p.n);
+    for (int32_t d0 = 0; d0 < maxn; d0 += kTile) {
+      const int64_t p0 = (int64_t)P.potrf.size();
+      double fl = 0;
+      for (auto& p : pan) {
+        if (p.n <= d0) continue;
+        PotrfTask t{};
+        t.panel = p.off; t.inv = p.dinv + (int64_t)(d0 / kTile) * 4096; t.ld = p.ld;
+        t.nb = std::min(kTile, p.n - d0); t.d0 = d0; t.sn = p.sn; t.mode = p.mode;
+        t.scale_off = p.scale_off;
+        P.potrf.push_back(t);
+        fl += std::pow((double)t.nb, 3) / 3.0;
+      }
+      cmd(kCmdPotrf, RSC_K_POTRF, p0, (int64_t)P.potrf.size() - p0, fl);
+      int64_t g0 = (int64_t)P.gemm.size();
+      fl = 0;
+      for (auto& p : pan) {
+        if (p.n <= d0) continue;
+        const int32_t nb = std::min(kTile, p.n - d0);
+        const int32_t R1 = p.n + p.m_below + (p.ident ? std::min(p.n, d0 + nb) : 0);
+        const int64_t colb = p.off + (int64_t)d0 * p.ld;
+        GemmTask t = gt(colb, 1, p.ld, p.dinv + (int64_t)(d0 / kTile) * 4096, 1, kTile, colb, p.ld,
+                        R1, nb, nb, 1.0, 0.0);
+        fl += tiles(t, d0 + nb, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_TRSM, g0, (int64_t)P.gemm.size() - g0, fl);
+      g0 = (int64_t)P.gemm.size();
+      fl = 0;
+      for (auto& p : pan) {
+        const int32_t nb = std::min(kTile, p.n - d0);
+        if (p.n <= d0 + nb) continue;
+        const int32_t R1 = p.n + p.m_below + (p.ident ? std::min(p.n, d0 + nb) : 0);
+        const int64_t colb = p.off + (int64_t)d0 * p.ld;
+        GemmTask t = gt(colb, 1, p.ld, colb, 1, p.ld, p.off, p.ld, R1, p.n, nb, -1.0, 1.0);
+        fl += tiles(t, d0 + nb, d0 + nb, true);
+      }
+      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    }
+  }
+
+  // Schur-complement updates of every supernode of one level (Algorithm 1, the
+  // descendant loop), as target tiles with ordered contribution lists.
+  void updates(const std::vector<int32_t>& level) {
+    const Symbolic& S = h.S;
+    struct TileW { UpdTile t; double work; std::vector<UpdEntry> e; };
+    std::vector<TileW> all;
+    for (int32_t j : level) {
+      const int32_t c = S.c(j), r = S.r(j);
+      const int32_t nI = (c + r + kTile - 1) / kTile, nJ = (c + kTile - 1) / kTile;
+      std::vector<std::vector<UpdEntry>> ents((size_t)nI * nJ);
+      std::vector<double> work((size_t)nI * nJ, 0.0);
+      for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
+        const Pair& pr = S.pairs[q];
+        const int32_t k = pr.k;
+        UpdEntry base{};
+        double kest;
+        if (P.compressed && h.compressible[k]) {
+          const CompSlot& C = h.comp[k];
+          base.x = C.Vj + pr.p0;
+          base.ldx = S.r(k);
+          base.kdim = -(1 + C.qslot);
+          kest = C.ell;
+        } else {
+          base.x = h.a_panels + h.panel_off[k] + S.c(k) + pr.p0;
+          base.ldx = h.panel_ld[k];
+          base.kdim = S.c(k);
+          kest = S.c(k);
+        }
+        base.map = pr.map_off;
+        const int32_t* rm = S.relmap.data() + pr.map_off;
+        // runs of gathered rows per 64-row tile (relmap is increasing)
+        std::vector<std::array<int32_t, 3>> rr, cc;
+        for (int32_t t = 0; t < pr.nrows;) {
+          const int32_t I = rm[t] / kTile;
+          int32_t u = t;
+          while (u < pr.nrows && rm[u] / kTile == I) ++u;
+          rr.push_back({I, t, u});
+          t = u;
+        }
+        for (int32_t t = 0; t < pr.nD;) {
+          const int32_t J = rm[t] / kTile;
+          int32_t u = t;
+          while (u < pr.nD && rm[u] / kTile == J) ++u;
+          cc.push_back({J, t, u});
+          t = u;
+        }
+        for (auto& R : rr)
+          for (auto& Cc : cc) {
+            if (R[0] < Cc[0]) continue;   // tile strictly above the diagonal
+            UpdEntry e = base;
+            e.a = R[1]; e.b = R[2]; e.c = Cc[1]; e.d = Cc[2];
+            const size_t id = (size_t)R[0] * nJ + Cc[0];
+            ents[id].push_back(e);
+            work[id] += 2.0 * (e.b - e.a) * (e.d - e.c) * kest;
+          }
+      }
+      for (int32_t I = 0; I < nI; ++I)
+        for (int32_t J = 0; J < nJ; ++J) {
+          const size_t id = (size_t)I * nJ + J;
+          if (ents[id].empty()) continue;
+          TileW tw;
+          tw.t.panel = h.a_panels + h.panel_off[j];
+          tw.t.ld = h.panel_ld[j];
+          tw.t.row0 = I * kTile; tw.t.col0 = J * kTile;
+          tw.t.nrows = std::min(kTile, c + r - I * kTile);
+          tw.t.ncols = std::min(kTile, c - J * kTile);
+          tw.work = work[id];
+          tw.e = std::move(ents[id]);
+          all.push_back(std::move(tw));
+        }
+    }
+    if (all.empty()) return;
+    // heaviest tiles first: the long ones start early and the tail is short
+    std::stable_sort(all.begin(), all.end(), [](const TileW& x, const TileW& y) { return x.work > y.work; });
+    const int64_t t0 = (int64_t)P.tiles.size();
+    double fl = 0;
+    for (auto& tw : all) {
+      tw.t.e0 = (int32_t)P.ents.size();
+      for (auto& e : tw.e) P.ents.push_back(e);
+      tw.t.e1 = (int32_t)P.ents.size();
+      P.tiles.push_back(tw.t);
+      fl += tw.work;
+    }
+    cmd(kCmdUpdate, RSC_K_UPDATE, t0, (int64_t)P.tiles.size() - t0, fl);
+  }
+
+  // Algorithm 3 on the explicit L^O_j of every compressible supernode of a level,
+  // followed by the spectral truncation.
+  void compression(const std::vector<int32_t>& level, double tol) {
+    const Symbolic& S = h.S;
+    std::vector<int32_t> js;
+    for (int32_t j : level)
+      if (h.compressible[j]) js.push_back(j);
+    if (js.empty()) return;
+    // 1. Gaussian samples
+    const int64_t ph0 = (int64_t)P.philox.size();
+    int64_t maxw = 0;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      PhiloxTask t{};
+      t.out = C.omega; t.rows = S.r(j); t.cols = C.ell;
+      t.k0 = (uint32_t)(h.opt.seed & 0xFFFFFFFFull);
+      t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)j);
+      P.philox.push_back(t);
+      maxw = std::max<int64_t>(maxw, (int64_t)S.r(j) * ((C.ell + 3) / 4));
+    }
+    cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw);
+    // 2. Y = (L^O_j)^T Omega into rows [l, l + c) of the orthonormalisation panel
+    int64_t g0 = (int64_t)P.gemm.size();
+    double fl = 0;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
+      const int64_t LO = h.a_panels + h.panel_off[j] + c;
+      fl += tiles(gt(LO, h.panel_ld[j], 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    // 3. power iterations Y = (L^O)^T (L^O Y)
+    for (int it = 0; it < h.opt.power_iters; ++it) {
+      g0 = (int64_t)P.gemm.size(); fl = 0;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
+        const int64_t LO = h.a_panels + h.panel_off[j] + c;
+        fl += tiles(gt(LO, 1, h.panel_ld[j], C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      g0 = (int64_t)P.gemm.size(); fl = 0;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
+        const int64_t LO = h.a_panels + h.panel_off[j] + c;
+        fl += tiles(gt(LO, h.panel_ld[j], 1, C.V, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    }
+    // 4. orthonormalisation: three Cholesky-QR passes, dependent columns dropped
+    for (int pass = 0; pass < 3; ++pass) {
+      g0 = (int64_t)P.gemm.size(); fl = 0;
+      const int64_t s0 = (int64_t)P.gs_g.size();
+      std::vector<PanelDesc> pan;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t c = S.c(j), l = C.ell, ldy = l + c;
+        fl += tiles(gt(C.ypanel + l, ldy, 1, C.ypanel + l, ldy, 1, C.ypanel, ldy, l, l, c, 1.0, 0.0), 0, 0, true);
+        P.gs_g.push_back(C.ypanel); P.gs_ld.push_back(ldy); P.gs_n.push_back(l); P.gs_out.push_back(C.gscale);
+        pan.push_back(PanelDesc{C.ypanel, ldy, l, c, false, C.ydinv, j, 1, C.gscale});
+      }
+      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
+      panel_steps(pan);
+    }
+    // 5. V = L^O_j U
+    g0 = (int64_t)P.gemm.size(); fl = 0;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
+      const int64_t LO = h.a_panels + h.panel_off[j] + c;
+      fl += tiles(gt(LO, 1, h.panel_ld[j], C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    // 6. Gram V^T V (full) into the padded eigenproblem
+    g0 = (int64_t)P.gemm.size(); fl = 0;
+    const int64_t s0 = (int64_t)P.gs_g.size();
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      const int32_t r = S.r(j), l = C.ell;
+      fl += tiles(gt(C.V, r, 1, C.V, r, 1, C.Gv, C.npad, l, l, r, 1.0, 0.0), 0, 0, false);
+      P.gs_g.push_back(C.Gv); P.gs_ld.push_back(C.npad); P.gs_n.push_back(l); P.gs_out.push_back(C.escale);
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
+    // 7. Jacobi eigendecomposition and selection of the kept rank
+    const int64_t e_small = (int64_t)P.eig.size();
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      if (C.npad != 64) continue;
+      P.eig.push_back(eig_task(j, tol));
+    }
+    const int64_t e_big = (int64_t)P.eig.size();
+    int32_t maxnbk = 0, maxrb = 0;
+    double efl = 0;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      efl += 10.0 * std::pow((double)C.npad, 3);
+      if (C.npad == 64) continue;
+      P.eig.push_back(eig_task(j, tol));
+      maxnbk = std::max(maxnbk, C.nbk);
+      maxrb = std::max(maxrb, C.npad / 64);
+    }
+    const int64_t e_end = (int64_t)P.eig.size();
+    cmd(kCmdJacobiSmall, RSC_K_EIG, e_small, e_big - e_small, efl);
+    if (e_end > e_big) {
+      cmd(kCmdEigInit, RSC_K_EIG, e_big, e_end - e_big, 0);
+      const int32_t rounds = kSweepsBlockJacobi * (maxnbk - 1);
+      for (int32_t rnd = 0; rnd < rounds; ++rnd)
+        cmd(kCmdJacobiRound, RSC_K_EIG, e_big, e_end - e_big, 0, maxnbk / 2, maxrb, (double)rnd);
+    }
+    cmd(kCmdEigSelect, RSC_K_EIG, e_small, e_end - e_small, 0);
+    // 8. U_j = U Z_q, V_j = V Z_q (columns beyond the device rank q_j are skipped)
+    g0 = (int64_t)P.gemm.size(); fl = 0;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
+      GemmTask t = gt(C.ypanel + l, 1, ldy, C.zq, l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
+      t.nlim = C.qslot;
+      fl += tiles(t, 0, 0, false);
+      GemmTask t2 = gt(C.V, 1, r, C.zq, l, 1, C.Vj, r, r, l, l, 1.0, 0.0);
+      t2.nlim = C.qslot;
+      fl += tiles(t2, 0, 0, false);
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+  }
+
+  EigTask eig_task(int32_t j, double tol) {
+    const CompSlot& C = h.comp[j];
+    EigTask e{};
+    e.g = C.Gv; e.z = C.Z; e.rot = C.rot; e.zq = C.zq; e.lam = C.lam; e.scale = C.escale;
+    e.n = C.ell; e.npad = C.npad; e.nbk = C.nbk; e.qslot = C.qslot; e.tol = tol;
+    e.flagslot = C.flagslot;
+    return e;
+  }
+};
+
+template <class T>
+Error upload_plan(DevArray<T>& d, const std::vector<T>& v) { return upload(d, v); }
+
+}  // namespace
+
+static Error build_factor_plan(Handle& h, bool compressed, double tol) {
+  auto P = std::make_unique<FactorPlan>();
+  P->compressed = compressed;
+  P->precision = h.opt.precision;
+  Builder B(h, *P);
+  const Symbolic& S = h.S;
+  int64_t panels_total = h.a_dinv - h.a_panels;
+  B.cmd(kCmdFill, RSC_K_OTHER, h.a_panels, panels_total, 0, 0, 0, 0.0);
+  B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_status, 2, 0, 0, 0, (double)INT_MAX);
+  B.cmd(kCmdAssemble, RSC_K_OTHER, 0, S.nnz, 0);
+  B.cmd(kCmdIdent, RSC_K_OTHER, 0, (int64_t)h.ident_slot.size(), 0);
+  if (compressed) {
+    int64_t g0 = -1, g1 = -1;
+    for (int64_t j = 0; j < S.M(); ++j)
+      if (h.compressible[j]) {
+        if (g0 < 0) g0 = h.comp[j].Gv;
+        g1 = h.comp[j].Z + (int64_t)h.comp[j].npad * h.comp[j].npad;
+      }
+    if (g0 >= 0) B.cmd(kCmdFill, RSC_K_OTHER, g0, g1 - g0, 0, 0, 0, 0.0);
+    B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_ranks, S.M(), 0, 0, 0, 0.0);
+  }
+  for (int32_t L = 0; L < S.nlevels; ++L) {
+    const auto& lev = S.by_level[L];
+    B.updates(lev);
+    std::vector<PanelDesc> pan;
+    for (int32_t j : lev)
+      pan.push_back(PanelDesc{h.a_panels + h.panel_off[j], h.panel_ld[j], S.c(j), S.r(j), true,
+                              h.a_dinv + h.dinv_off[j], j, 0, 0});
+    B.panel_steps(pan);
+    if (compressed) B.compression(lev, tol);
+  }
+  // algorithmic flop counts of the method (per supernode, from the symbolic plan)
+  for (int64_t j = 0; j < S.M(); ++j) {
+    const double c = S.c(j), r = S.r(j);
+    P->flops[0] += c * c * c / 3.0;
+    P->flops[1] += r * c * c;
+    if (compressed && h.compressible[j]) {
+      const double l = h.comp[j].ell;
+      P->flops[3] += 4.0 * r * c * l * (1 + h.opt.power_iters);
+      P->flops[4] += 3.0 * (2.0 * c * l * l + l * l * l / 3.0);
+      P->flops[5] += 2.0 * r * l * l;
+    }
+  }
+  Error e;
+  if ((e = upload(P->d_gemm, P->gemm)).code) return e;
+  if ((e = upload(P->d_tiles, P->tiles)).code) return e;
+  if ((e = upload(P->d_ents, P->ents)).code) return e;
+  if ((e = upload(P->d_potrf, P->potrf)).code) return e;
+  if ((e = upload(P->d_philox, P->philox)).code) return e;
+  if ((e = upload(P->d_eig, P->eig)).code) return e;
+  if ((e = upload(P->d_gs_g, P->gs_g)).code) return e;
+  if ((e = upload(P->d_gs_out, P->gs_out)).code) return e;
+  if ((e = upload(P->d_gs_ld, P->gs_ld)).code) return e;
+  if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
+  if (h.fplan && h.fplan->graph) (void)hipGraphExecDestroy(h.fplan->graph);
+  h.fplan = std::move(P);
+  return kOk;
+}
+
+// ------------------------------------------------------------------ executor
+
+struct EventPair { hipEvent_t a, b; int32_t klass; double flops; };
+
+static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const SolvePlan* Q,
+                       hipStream_t s) {
+  double* A = h.arena.p;
+  int32_t* I = h.ints.p;
+  switch (c.type) {
+    case kCmdFill: launch_fill(A + c.off, c.count, c.v, s); break;
+    case kCmdFillInts: launch_fill_i32(I + c.off, c.count, (int32_t)c.v, s); break;
+    case kCmdAssemble: launch_assemble(A + h.a_values, h.d_asm_slot.p, c.count, A, s); break;
+    case kCmdIdent: launch_scatter_const(h.d_ident_slot.p, c.count, 1.0, A, s); break;
+    case kCmdUpdate:
+      launch_update_f64(P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A, I, s);
+      break;
+    case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
+    case kCmdGemm: launch_gemm_f64(P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, 0, s); break;
+    case kCmdGramScale:
+      launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,
+                        P->d_gs_out.p + c.off, (int)c.count, A, s);
+      break;
+    case kCmdEigInit: launch_eig_init(P->d_eig.p + c.off, (int)c.count, A, s); break;
+    case kCmdJacobiSmall: launch_jacobi_small(P->d_eig.p + c.off, (int)c.count, A, s); break;
+    case kCmdJacobiRound:
+      launch_jacobi_round(P->d_eig.p + c.off, (int)c.count, (int)c.a, (int)c.b, A, I, (int)c.v, s);
+      break;
+    case kCmdEigSelect: launch_eig_select(P->d_eig.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
+    case kCmdTrsvBwd: launch_trsv_bwd(Q->d_rows.p + c.off, (int)c.count, A, s); break;
+    case kCmdRowGather:
+      launch_row_gather(Q->d_rg_rows.p + c.off, Q->d_rg_ptr.p + c.a, Q->d_rg_contrib.p, c.count,
+                        A + h.a_part, A + h.a_y, s);
+      break;
+    case kCmdGatherPerm: launch_gather_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
+    case kCmdScatterPerm: launch_scatter_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
+    default: break;
+  }
+}
+
+// Runs a command list; with profiling on, brackets every launch with events.
+static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan* P,
+                      const SolvePlan* Q, hipStream_t s, std::vector<EventPair>* evs) {
+  for (const Cmd& c : cmds) {
+    if (evs) {
+      EventPair ep;
+      HIPCHK(hipEventCreate(&ep.a));
+      HIPCHK(hipEventCreate(&ep.b));
+      ep.klass = c.klass;
+      ep.flops = c.flops;
+      HIPCHK(hipEventRecord(ep.a, s));
+      launch_cmd(h, c, P, Q, s);
+      HIPCHK(hipEventRecord(ep.b, s));
+      evs->push_back(ep);
+    } else {
+      launch_cmd(h, c, P, Q, s);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  return kOk;
+}
+
+static Error collect_events(Handle& h, std::vector<EventPair>& evs) {
+  for (auto& ep : evs) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ep.a, ep.b));
+    h.prof.launches[ep.klass] += 1;
+    h.prof.ms[ep.klass] += ms;
+    h.prof.flops[ep.klass] += ep.flops;
+    (void)hipEventDestroy(ep.a);
+    (void)hipEventDestroy(ep.b);
+  }
+  evs.clear();
+  return kOk;
+}
+
+static Error capture(Handle& h, const std::function<Error(hipStream_t)>& body, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
+  Error e = body(h.cap_stream);
+  hipError_t ee = hipStreamEndCapture(h.cap_stream, &g);
+  if (e.code) { if (g) (void)hipGraphDestroy(g); return e; }
+  if (ee != hipSuccess) return Error{RSC_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee)};
+  hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return Error{RSC_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie)};
+  return kOk;
+}
+
+// ------------------------------------------------------------------ factor
+
+Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
+  Error e = ensure_device(h);
+  if (e.code) return e;
+  const bool compressed = tol > 0.0;
+  if (!h.fplan || h.fplan->compressed != compressed || (compressed && h.tol != tol) ||
+      h.fplan->precision != h.opt.precision) {
+    if ((e = build_factor_plan(h, compressed, tol)).code) return e;
+    if (h.splan) {
+      if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
+      if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
+      if (h.splan->graph_apply) (void)hipGraphExecDestroy(h.splan->graph_apply);
+      h.splan.reset();
+    }
+  }
+  h.factored = false;
+  h.tol = tol;
+  FactorPlan* P = h.fplan.get();
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipMemcpyAsync(h.arena.p + h.a_values, values, sizeof(double) * (size_t)h.S.nnz,
+                        hipMemcpyDeviceToDevice, stream));
+  HIPCHK(hipEventRecord(e0, stream));
+  if (h.profiling) {
+    std::vector<EventPair> evs;
+    if ((e = run_cmds(h, P->cmds, P, nullptr, stream, &evs)).code) return e;
+    HIPCHK(hipEventRecord(e1, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if ((e = collect_events(h, evs)).code) return e;
+  } else if (h.opt.use_graph) {
+    if (!P->graph) {
+      e = capture(h, [&](hipStream_t s) { return run_cmds(h, P->cmds, P, nullptr, s, nullptr); },
+                  &P->graph);
+      if (e.code) return e;
+    }
+    HIPCHK(hipGraphLaunch(P->graph, stream));
+    HIPCHK(hipEventRecord(e1, stream));
+  } else {
+    if ((e = run_cmds(h, P->cmds, P, nullptr, stream, nullptr)).code) return e;
+    HIPCHK(hipEventRecord(e1, stream));
+  }
+  int32_t st[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(st, h.ints.p + h.i_status, sizeof(st), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h.t_factor_ms = ms;
+  if (st[0] != INT_MAX) {
+    h.failed_supernode = st[0];
+    return Error{RSC_ERR_NOT_SPD, "non-positive pivot in supernode " + std::to_string(st[0])};
+  }
+  h.failed_supernode = -1;
+  h.precision_used = h.opt.precision;
+  h.factored = true;
+  return kOk;
+}
+
+// ------------------------------------------------------------------ solve plan
+
+static Error build_solve_plan(Handle& h) {
+  auto Q = std::make_unique<SolvePlan>();
+  const Symbolic& S = h.S;
+  const bool comp = h.fplan && h.fplan->compressed;
+  Q->compressed = comp;
+  auto cmd = [&](int32_t type, int64_t off, int64_t count, int64_t a = 0, int64_t b = 0) {
+    if (count <= 0) return;
+    Cmd c{};
+    c.type = type; c.klass = RSC_K_PCG; c.off = off; c.count = count; c.a = a; c.b = b;
+    Q->fwd_bwd.push_back(c);
+  };
+  auto iscomp = [&](int64_t j) { return comp && h.compressible[j]; };
+  double bytes = 0;
+  Q->rg_ptr.push_back(0);
+  // forward sweep, levels ascending
+  for (int32_t L = 0; L < S.nlevels; ++L) {
+    const auto& lev = S.by_level[L];
+    // f1: pair products of descendants restricted to their rows in C_j
+    int64_t g0 = (int64_t)Q->gemv.size();
+    for (int32_t j : lev)
+      for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
+        const Pair& pr = S.pairs[q];
+        const int32_t k = pr.k;
+        for (int32_t t0 = 0; t0 < pr.nD; t0 += 256) {
+          GemvTask t{};
+          if (iscomp(k)) {
+            t.x = h.comp[k].Vj + pr.p0 + t0; t.ldx = S.r(k); t.kdim = -(1 + h.comp[k].qslot);
+            t.v = h.comp[k].tvq;
+          } else {
+            t.x = h.a_panels + h.panel_off[k] + S.c(k) + pr.p0 + t0; t.ldx = h.panel_ld[k];
+            t.kdim = S.c(k); t.v = h.a_w + S.first[k];
+          }
+          t.rows = std::min(256, pr.nD - t0);
+          t.out = h.a_part + h.part_off[q] + t0;
+          Q->gemv.push_back(t);
+        }
+      }
+    cmd(kCmdGemvN, g0, (int64_t)Q->gemv.size() - g0);
+    // f2: subtract the partials from y on the rows of C_j (ascending descendant order)
+    const int64_t r0 = (int64_t)Q->rg_rows.size();
+    const int64_t p0 = (int64_t)Q->rg_ptr.size() - 1;
+    for (int32_t j : lev) {
+      const int32_t c = S.c(j);
+      std::vector<std::vector<int64_t>> per(c);
+      for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
+        const Pair& pr = S.pairs[q];
+        const int32_t* rm = S.relmap.data() + pr.map_off;
+        for (int32_t t = 0; t < pr.nD; ++t) per[rm[t]].push_back(h.part_off[q] + t);
+      }
+      for (int32_t t = 0; t < c; ++t) {
+        if (per[t].empty()) continue;
+        Q->rg_rows.push_back(S.first[j] + t);
+        for (int64_t v : per[t]) Q->rg_contrib.push_back(v);
+        Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
+      }
+    }
+    {
+      const int64_t nr = (int64_t)Q->rg_rows.size() - r0;
+      if (nr > 0) {
+        Cmd c{};
+        c.type = kCmdRowGather; c.klass = RSC_K_PCG; c.off = r0; c.count = nr; c.a = p0;
+        Q->fwd_bwd.push_back(c);
+      }
+    }
+    // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
+    int64_t c0 = (int64_t)Q->coldot.size();
+    for (int32_t j : lev) {
+      const int32_t c = S.c(j), r = S.r(j);
+      for (int32_t col0 = 0; col0 < c; col0 += 16) {
+        ColDotTask t{};
+        t.x = h.a_panels + h.panel_off[j] + c + r; t.ldx = h.panel_ld[j];
+        t.in = h.a_y + S.first[j]; t.idx = -1; t.out = h.a_w + S.first[j];
+        t.rows = c; t.ncols = c; t.col0 = col0; t.tri = 1;
+        Q->coldot.push_back(t);
+      }
+      bytes += 8.0 * c * (c + 1) / 2;
+    }
+    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+    // f4: t_j = U_j^T w_C for compressed supernodes
+    c0 = (int64_t)Q->coldot.size();
+    for (int32_t j : lev) {
+      if (!iscomp(j)) continue;
+      const CompSlot& C = h.comp[j];
+      for (int32_t col0 = 0; col0 < C.ell; col0 += 16) {
+        ColDotTask t{};
+        t.x = C.Uj; t.ldx = S.c(j); t.in = h.a_w + S.first[j]; t.idx = -1; t.out = C.tvq;
+        t.rows = S.c(j); t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
+        Q->coldot.push_back(t);
+      }
+    }
+    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+  }
+  // backward sweep, levels descending
+  for (int32_t L = S.nlevels - 1; L >= 0; --L) {
+    const auto& lev = S.by_level[L];
+    // b1: s_C = (L^O_j)^T z_R (dense) or u = V_j^T z_R (compressed)
+    int64_t c0 = (int64_t)Q->coldot.size();
+    for (int32_t j : lev) {
+      const int32_t c = S.c(j), r = S.r(j);
+      if (r == 0) continue;
+      if (iscomp(j)) {
+        const CompSlot& C = h.comp[j];
+        for (int32_t col0 = 0; col0 < C.ell; col0 += 16) {
+          ColDotTask t{};
+          t.x = C.Vj; t.ldx = r; t.in = h.a_zz; t.idx = S.rows_ptr[j]; t.out = C.u;
+          t.rows = r; t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
+          Q->coldot.push_back(t);
+        }
+      } else {
+        for (int32_t col0 = 0; col0 < c; col0 += 16) {
+          ColDotTask t{};
+          t.x = h.a_panels + h.panel_off[j] + c; t.ldx = h.panel_ld[j]; t.in = h.a_zz;
+          t.idx = S.rows_ptr[j]; t.out = h.a_s + S.first[j];
+          t.rows = r; t.ncols = c; t.col0 = col0; t.tri = 0;
+          Q->coldot.push_back(t);
+        }
+        bytes += 2.0 * 8.0 * (double)r * c;   // read by both sweeps
+      }
+    }
+    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+    // b1': s_C = U_j u for compressed supernodes
+    int64_t g0 = (int64_t)Q->gemv.size();
+    for (int32_t j : lev) {
+      if (!iscomp(j)) continue;
+      const CompSlot& C = h.comp[j];
+      for (int32_t t0 = 0; t0 < S.c(j); t0 += 256) {
+        GemvTask t{};
+        t.x = C.Uj + t0; t.ldx = S.c(j); t.kdim = -(1 + C.qslot); t.v = C.u;
+        t.rows = std::min(256, S.c(j) - t0); t.out = h.a_s + S.first[j] + t0;
+        Q->gemv.push_back(t);
+      }
+      bytes += 2.0 * 8.0 * (double)(S.c(j) + S.r(j)) * C.ell;
+    }
+    cmd(kCmdGemvN, g0, (int64_t)Q->gemv.size() - g0);
+    // b2: z_C = L_j^{-T} (w_C - s_C)
+    const int64_t w0 = (int64_t)Q->rows.size();
+    for (int32_t j : lev) {
+      const int32_t c = S.c(j), r = S.r(j);
+      for (int32_t i0 = 0; i0 < c; i0 += 256) {
+        RowTask t{};
+        t.m = h.a_panels + h.panel_off[j] + c + r; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
+        t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;
+        t.out = h.a_zz + S.first[j];
+        Q->rows.push_back(t);
+      }
+      bytes += 8.0 * c * (c + 1) / 2;
+    }
+    cmd(kCmdTrsvBwd, w0, (int64_t)Q->rows.size() - w0);
+  }
+  Q->bytes = bytes;
+  Error e;
+  if ((e = upload(Q->d_gemv, Q->gemv)).code) return e;
+  if ((e = upload(Q->d_coldot, Q->coldot)).code) return e;
+  if ((e = upload(Q->d_rows, Q->rows)).code) return e;
+  if ((e = upload(Q->d_rg_rows, Q->rg_rows)).code) return e;
+  if ((e = upload(Q->d_rg_ptr, Q->rg_ptr)).code) return e;
+  if ((e = upload(Q->d_rg_contrib, Q->rg_contrib)).code) return e;
+  h.splan = std::move(Q);
+  return kOk;
+}
+
+// One preconditioner apply: z (arena a_z) = M^{-1} r (arena a_r).
+static Error apply_cmds(Handle& h, hipStream_t s, std::vector<EventPair>* evs) {
+  Cmd g{}; g.type = kCmdGatherPerm; g.klass = RSC_K_PCG; g.count = 1; g.a = h.a_r; g.b = h.a_y;
+  Cmd z{}; z.type = kCmdScatterPerm; z.klass = RSC_K_PCG; z.count = 1; z.a = h.a_zz; z.b = h.a_z;
+  std::vector<Cmd> all;
+  all.push_back(g);
+  all.insert(all.end(), h.splan->fwd_bwd.begin(), h.splan->fwd_bwd.end());
+  all.push_back(z);
+  return run_cmds(h, all, nullptr, h.splan.get(), s, evs);
+}
+
+static Error ensure_solve(Handle& h) {
+  if (!h.factored) return Error{RSC_ERR_STATE, "no successful rsc_factor on this handle"};
+  if (!h.splan) return build_solve_plan(h);
+  return kOk;
+}
+
+Error apply_preconditioner(Handle& h, const double* r, double* z, hipStream_t stream) {
+  Error e = ensure_solve(h);
+  if (e.code) return e;
+  HIPCHK(hipMemcpyAsync(h.arena.p + h.a_r, r, sizeof(double) * (size_t)h.S.n, hipMemcpyDeviceToDevice, stream));
+  if (h.opt.use_graph && !h.profiling) {
+    if (!h.splan->graph_apply)
+      if ((e = capture(h, [&](hipStream_t s) { return apply_cmds(h, s, nullptr); }, &h.splan->graph_apply)).code)
+        return e;
+    HIPCHK(hipGraphLaunch(h.splan->graph_apply, stream));
+  } else {
+    if ((e = apply_cmds(h, stream, nullptr)).code) return e;
+  }
+  HIPCHK(hipMemcpyAsync(z, h.arena.p + h.a_z, sizeof(double) * (size_t)h.S.n, hipMemcpyDeviceToDevice, stream));
+  return kOk;
+}
+
+// ------------------------------------------------------------------ PCG
+
+Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, hipStream_t stream,
+          rsc_pcg_result* out) {
+  Error e = ensure_solve(h);
+  if (e.code) return e;
+  double* A = h.arena.p;
+  int32_t* I = h.ints.p;
+  const int64_t n = h.S.n;
+  const int32_t nseg = (int32_t)h.seg_first.size() - 1;
+  const int nc = h.nchunks;
+  const Chunk* ch = h.d_chunks.p;
+  const PcgScalars sc = h.sc;
+  double* partial = A + h.a_partial;
+  const double* vals = A + h.a_values;
+  std::vector<EventPair> evs;
+  std::vector<EventPair>* pe = h.profiling ? &evs : nullptr;
+
+  auto part_a = [&](hipStream_t s) -> Error {
+    launch_spmv_dot(ch, nc, h.d_rowptr.p, h.d_colind.p, vals, A + sc.p, A + sc.Ap, partial, s);
+    launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.pAp, s);
+    launch_pcg_alpha(nseg, sc, A, I, s);
+    launch_pcg_xr(ch, nc, sc, A, I, partial, s);
+    launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rr, s);
+    launch_pcg_check(nseg, sc, rtol, A, I, s);
+    HIPCHK(hipGetLastError());
+    return kOk;
+  };
+  auto part_b = [&](hipStream_t s) -> Error {
+    Error r = apply_cmds(h, s, nullptr);
+    if (r.code) return r;
+    launch_dot_partial(ch, nc, A + sc.r, A + sc.z, partial, s);
+    launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rznew, s);
+    launch_pcg_beta(nseg, sc, A, I, s);
+    launch_pcg_p(ch, nc, sc, A, I, 0, s);
+    HIPCHK(hipGetLastError());
+    return kOk;
+  };
+
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipMemcpyAsync(A + h.a_b, b, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+  HIPCHK(hipEventRecord(e0, stream));
+  // start: x = 0, r = b, bnorm, z = M r, rz = r.z, p = z
+  launch_fill(A + sc.x, n, 0.0, stream);
+  launch_copy(n, A + h.a_b, A + sc.r, stream);
+  launch_dot_partial(ch, nc, A + h.a_b, A + h.a_b, partial, stream);
+  launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.bnorm, stream);
+  launch_pcg_start(nseg, sc, A, I, stream);
+  if ((e = apply_cmds(h, stream, pe)).code) return e;
+  launch_dot_partial(ch, nc, A + sc.r, A + sc.z, partial, stream);
+  launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rz, stream);
+  launch_pcg_p(ch, nc, sc, A, I, 1, stream);
+  HIPCHK(hipGetLastError());
+
+  const bool graphs = h.opt.use_graph && !h.profiling;
+  SolvePlan* Q = h.splan.get();
+  if (graphs && Q->graph_a && Q->v_rtol != rtol) {
+    (void)hipGraphExecDestroy(Q->graph_a);
+    Q->graph_a = nullptr;
+  }
+  if (graphs && !Q->graph_a) {
+    if ((e = capture(h, part_a, &Q->graph_a)).code) return e;
+    Q->v_rtol = rtol;
+  }
+  if (graphs && !Q->graph_b)
+    if ((e = capture(h, part_b, &Q->graph_b)).code) return e;
+  int32_t flags[2] = {0, 0};
+  int32_t it = 0;
+  bool breakdown = false;
+  for (; it < max_iter; ++it) {
+    if (graphs) { HIPCHK(hipGraphLaunch(Q->graph_a, stream)); }
+    else if ((e = part_a(stream)).code) return e;
+    HIPCHK(hipMemcpyAsync(flags, I + sc.any, sizeof(flags), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (flags[1]) { breakdown = true; break; }
+    if (!flags[0]) break;
+    if (graphs) { HIPCHK(hipGraphLaunch(Q->graph_b, stream)); }
+    else {
+      if (pe) {
+        if ((e = apply_cmds(h, stream, pe)).code) return e;
+        launch_dot_partial(ch, nc, A + sc.r, A + sc.z, partial, stream);
+        launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rznew, stream);
+        launch_pcg_beta(nseg, sc, A, I, stream);
+        launch_pcg_p(ch, nc, sc, A, I, 0, stream);
+      } else if ((e = part_b(stream)).code) {
+        return e;
+      }
+    }
+  }
+  HIPCHK(hipEventRecord(e1, stream));
+  // true residual ||b - A x|| / ||b|| per system
+  launch_spmv_dot(ch, nc, h.d_rowptr.p, h.d_colind.p, vals, A + sc.x, A + sc.Ap, partial, stream);
+  launch_resid_partial(ch, nc, A + h.a_b, A + sc.Ap, partial, stream);
+  launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + h.a_seg + 8 * (int64_t)nseg, stream);
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> iters(nseg);
+  std::vector<double> rel(nseg), bn(nseg), tr(nseg);
+  HIPCHK(hipMemcpyAsync(iters.data(), I + sc.iters, sizeof(int32_t) * nseg, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(rel.data(), A + sc.rel, sizeof(double) * nseg, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(bn.data(), A + sc.bnorm, sizeof(double) * nseg, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(tr.data(), A + h.a_seg + 8 * (int64_t)nseg, sizeof(double) * nseg,
+                        hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(x, A + sc.x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (pe && (e = collect_events(h, evs)).code) return e;
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h.t_pcg_ms = ms;
+  bool all_conv = true;
+  for (int32_t s = 0; s < nseg; ++s) {
+    out[s].iters = iters[s];
+    out[s].rel_residual = rel[s];
+    out[s].true_residual = bn[s] > 0 ? std::sqrt(tr[s]) / bn[s] : 0.0;
+    out[s].converged = (bn[s] == 0.0 || rel[s] <= rtol) ? 1 : 0;
+    if (!out[s].converged) all_conv = false;
+  }
+  if (breakdown) return Error{RSC_ERR_BREAKDOWN, "non-positive curvature or r^T z in PCG"};
+  if (!all_conv) return Error{RSC_ERR_NOT_CONVERGED, "PCG did not reach rtol within max_iter"};
+  return kOk;
+}
+
+Error grad_values(Handle& h, const double* lam, const double* x, double* g, hipStream_t stream) {
+  Error e = ensure_device(h);
+  if (e.code) return e;
+  launch_grad_values(h.S.n, h.d_rowptr.p, h.d_colind.p, lam, x, g, stream);
+  HIPCHK(hipGetLastError());
+  return kOk;
+}
+
+}  // namespace rsc

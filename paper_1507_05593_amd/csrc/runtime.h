@@ -1,0 +1,169 @@
+// Device runtime of the solver: memory plan, launch plans, executor, factor and PCG drivers.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/rsc.h"
+#include "symbolic.h"
+#include "tasks.h"
+
+namespace rsc {
+
+struct Error {
+  rsc_status code;
+  std::string msg;
+};
+
+// One launch of the executor.
+enum CmdType : int32_t {
+  kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdUpdateLow, kCmdPotrf, kCmdGemm,
+  kCmdPhilox, kCmdGramScale, kCmdEigInit, kCmdJacobiSmall, kCmdJacobiRound, kCmdEigSelect,
+  kCmdGemvN, kCmdColDot, kCmdTrsvBwd, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
+  kCmdConvertLow,
+};
+
+struct Cmd {
+  int32_t type;
+  int32_t klass;        // RSC_K_* profiling class
+  int64_t off;          // offset into the task array of this type (or arena offset)
+  int64_t count;        // number of tasks (or elements)
+  int64_t a, b;         // command-specific
+  double v;             // command-specific
+  double flops;         // algorithmic flops of the launch (profiling)
+};
+
+template <class T>
+struct DevArray {
+  T* p = nullptr;
+  int64_t n = 0;
+  DevArray() = default;
+  DevArray(const DevArray&) = delete;
+  DevArray& operator=(const DevArray&) = delete;
+  ~DevArray() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// Per-supernode storage of the compressed form and its work space (arena offsets).
+struct CompSlot {
+  int32_t ell = 0, npad = 0, nbk = 0;
+  int64_t omega = -1, ypanel = -1, ydinv = -1, V = -1, Gv = -1, Z = -1, rot = -1, zq = -1,
+          lam = -1, Vj = -1, Uj = -1, gscale = -1, escale = -1, tvq = -1, u = -1;
+  int32_t qslot = -1, flagslot = -1;
+};
+
+// A launch plan (command list + task arrays) for one factor mode.
+struct FactorPlan {
+  bool compressed = false;
+  int32_t precision = RSC_FP64;
+  std::vector<Cmd> cmds;
+  std::vector<GemmTask> gemm;
+  std::vector<UpdTile> tiles;
+  std::vector<UpdEntry> ents;
+  std::vector<PotrfTask> potrf;
+  std::vector<PhiloxTask> philox;
+  std::vector<EigTask> eig;
+  std::vector<int64_t> gs_g, gs_out;
+  std::vector<int32_t> gs_ld, gs_n;
+  DevArray<GemmTask> d_gemm;
+  DevArray<UpdTile> d_tiles;
+  DevArray<UpdEntry> d_ents;
+  DevArray<PotrfTask> d_potrf;
+  DevArray<PhiloxTask> d_philox;
+  DevArray<EigTask> d_eig;
+  DevArray<int64_t> d_gs_g, d_gs_out;
+  DevArray<int32_t> d_gs_ld, d_gs_n;
+  hipGraphExec_t graph = nullptr;
+  double flops[6] = {0, 0, 0, 0, 0, 0};  // potrf, trsm, update, sample, orth, trunc
+};
+
+struct SolvePlan {
+  bool compressed = false;
+  std::vector<Cmd> fwd_bwd;           // commands of one preconditioner apply (y -> zz)
+  std::vector<GemvTask> gemv;
+  std::vector<ColDotTask> coldot;
+  std::vector<RowTask> rows;
+  std::vector<int64_t> rg_rows, rg_ptr, rg_contrib;  // row-gather CSR (all levels)
+  DevArray<GemvTask> d_gemv;
+  DevArray<ColDotTask> d_coldot;
+  DevArray<RowTask> d_rows;
+  DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib;
+  hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
+  double bytes = 0;                   // factor bytes read by one apply
+  double v_rtol = -1;                 // rtol baked into graph_a
+};
+
+struct Handle {
+  rsc_options opt;
+  Symbolic S;
+  std::vector<int64_t> rowptr;        // original CSR (systems concatenated)
+  std::vector<int32_t> colind;
+  std::vector<int64_t> seg_first;     // systems + 1
+  double t_analyze_ms = 0;
+
+  // layout (host, computed at analyze)
+  std::vector<int64_t> panel_off;
+  std::vector<int32_t> panel_ld;
+  std::vector<int64_t> dinv_off;
+  std::vector<int64_t> asm_slot;      // per stored entry: arena slot or -1
+  std::vector<int64_t> ident_slot;
+  std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
+  std::vector<int64_t> part_off;      // per pair: offset of its forward-sweep partial
+  int64_t part_total = 0;
+
+  // device
+  bool dev_ready = false;
+  int device = -1;
+  hipStream_t cap_stream = nullptr;   // private stream used for graph capture only
+  int64_t arena_size = 0, ints_size = 0;
+  DevArray<double> arena;
+  DevArray<int32_t> ints;
+  DevArray<int64_t> d_asm_slot, d_ident_slot, d_perm, d_rows, d_rowptr;
+  DevArray<int32_t> d_colind, d_relmap;
+  DevArray<Chunk> d_chunks;
+  DevArray<int32_t> d_seg_chunk_ptr;
+  int32_t nchunks = 0;
+  // arena regions
+  int64_t a_values = 0, a_panels = 0, a_dinv = 0;
+  int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_part, a_partial, a_seg;
+  PcgScalars sc{};
+  int32_t i_status = 0, i_ranks = 0;
+  std::vector<CompSlot> comp;         // per supernode (compressible ones only)
+  bool comp_ready = false;
+
+  std::unique_ptr<FactorPlan> fplan;
+  std::unique_ptr<SolvePlan> splan;
+  bool factored = false;
+  double tol = 0;
+  int32_t failed_supernode = -1;
+  int32_t precision_used = RSC_FP64;
+  int32_t retries = 0;
+  double t_factor_ms = 0, t_pcg_ms = 0;
+
+  // profiling
+  bool profiling = false;
+  rsc_profile prof{};
+};
+
+// analyze-phase layout (no device work)
+void plan_layout(Handle& h);
+// device set-up (first numeric call)
+Error ensure_device(Handle& h);
+Error factor(Handle& h, const double* values, double tol, hipStream_t stream);
+Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, hipStream_t stream,
+          rsc_pcg_result* out);
+Error apply_preconditioner(Handle& h, const double* r, double* z, hipStream_t stream);
+Error grad_values(Handle& h, const double* lam, const double* x, double* g, hipStream_t stream);
+void release_device(Handle& h);
+
+int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p);
+
+}  // namespace rsc

@@ -1,0 +1,130 @@
+// Task descriptors shared by the host planner and the gfx950 kernels.
+// All floating-point storage lives in one FP64 arena (offsets in elements);
+// all device-side integers (ranks, status words, limits) live in one int32 arena.
+#pragma once
+
+#include <cstdint>
+
+namespace rsc {
+
+constexpr int kTile = 64;      // output tile edge of the MFMA kernels and POTRF block size
+
+// C(i,j) = beta C(i,j) + alpha sum_k A(i,k) B(j,k) on one 64x64 output tile.
+// A(i,k) = arena[a + i*ais + k*aks], B(j,k) = arena[b + j*bjs + k*bks],
+// C(i,j) = arena[c + i + j*ldc].  nlim / klim >= 0 name int-arena slots holding a
+// device-side limit on n / k (ranks known only on the device).
+struct GemmTask {
+  int64_t a, b, c;
+  int32_t ais, aks, bjs, bks;
+  int32_t ldc;
+  int32_t m, n, k;
+  int32_t i0, j0;
+  int32_t nlim, klim;
+  double alpha, beta;
+};
+
+// One 64x64 target tile of a supernode panel that receives Schur-complement updates
+// (Sec. 2.1, Algorithm 1): entries [e0, e1) of the entry list, applied in order.
+struct UpdTile {
+  int64_t panel;               // arena offset of the target panel
+  int32_t ld;                  // its leading dimension
+  int32_t row0, col0;          // tile origin in panel-local rows / columns
+  int32_t nrows, ncols;        // valid extent (<= 64)
+  int32_t e0, e1;
+};
+
+// One descendant's contribution to one target tile: rows [a,b) and [c,d) of the
+// gathered operand X (X(t, m) = arena[x + t + m*ldx]); the target position of
+// gathered row t is relmap[map + t] (panel-local row; as a column index when t < nD).
+struct UpdEntry {
+  int64_t x;
+  int64_t map;
+  int32_t ldx;
+  int32_t kdim;                // inner dimension, or -(1 + int-arena slot) of a device rank
+  int32_t a, b, c, d;
+};
+
+// Cholesky of one diagonal block (<= 64) of a panel plus the explicit inverse of
+// that block (written column-major with ld 64 at `inv`).
+struct PotrfTask {
+  int64_t panel;
+  int64_t inv;
+  int32_t ld, nb, d0;
+  int32_t sn;                  // supernode for the status word
+  int32_t mode;                // 0: fail on a non-positive pivot; 1: drop dependent columns
+  int64_t scale_off;           // mode 1: arena offset of the column-drop scale (max Gram diagonal)
+};
+
+// Gaussian sample of one supernode: rows x cols column-major at `out` (ld = rows).
+struct PhiloxTask {
+  int64_t out;
+  int32_t rows, cols;
+  uint32_t k0, k1;
+};
+
+// Per-problem description of a symmetric eigenproblem (Jacobi) of order n <= npad.
+struct EigTask {
+  int64_t g;                   // npad x npad symmetric matrix (ld npad), destroyed
+  int64_t z;                   // npad x npad eigenvectors (ld npad)
+  int64_t rot;                 // scratch: (npad/64) ... rotation blocks (64x64 each, per pair)
+  int64_t zq;                  // output: n x n selected eigenvectors (ld n), descending
+  int64_t lam;                 // output: n eigenvalues, descending
+  int64_t scale;               // arena offset of the largest diagonal entry of the input
+  int32_t n, npad;
+  int32_t nbk;                 // number of 32-wide blocks (npad / 32)
+  int32_t qslot;               // int-arena slot receiving the kept rank
+  double tol;                  // relative singular-value cut-off
+  int32_t flagslot;            // int-arena slots [flagslot, flagslot + nbk/2): pair skip flags
+  int32_t pad_;
+};
+
+// Pair operand of the forward sweep: part[out + t] = sum_m X(t, m) v[m], t < rows.
+struct GemvTask {
+  int64_t x;                   // X(t, m) = arena[x + t + m*ldx]
+  int64_t v;                   // vector (arena offset)
+  int64_t out;                 // output (arena offset)
+  int32_t ldx, rows;
+  int32_t kdim;                // or -(1 + slot) of a device rank
+  int32_t pad_;
+};
+
+}  // namespace rsc
+
+namespace rsc {
+
+// out[col] = sum_{t < rows(col)} X(t, col) in[idx(t)] for 16 columns [col0, col0+16);
+// rows(col) = col + 1 when tri (the transposed upper-triangular inverse block),
+// else rows; idx = identity when idx < 0, else the int64 gather list at idx.
+// ncols < 0 names -(1 + int-arena slot) holding a device column count.
+struct ColDotTask {
+  int64_t x, in, idx, out;
+  int32_t ldx, rows, ncols, col0;
+  int32_t tri, pad_;
+};
+
+// out[i] = sum_{t >= i} M(i, t) (w[t] - s[t]) for rows [i0, i0 + 256) of a c x c
+// upper-triangular block (tri) -- the backward solve with the stored L^{-T}.
+struct RowTask {
+  int64_t m, w, s, out;        // s < 0: no subtraction
+  int32_t ld, c, i0, pad_;
+};
+
+// Contiguous row range inside one system (segment) for chunked vector kernels.
+struct Chunk {
+  int64_t begin, end;
+  int32_t seg, pad_;
+};
+
+}  // namespace rsc
+
+namespace rsc {
+
+// Arena offsets of the CG state: n-vectors and per-system scalars (doubles), and
+// int-arena slots of the per-system flags.
+struct PcgScalars {
+  int64_t x, r, z, p, Ap;
+  int64_t rz, rznew, pAp, alpha, beta, rr, bnorm, rel;
+  int32_t active, iters, any, breakdown;
+};
+
+}  // namespace rsc

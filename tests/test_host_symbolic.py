@@ -1,0 +1,105 @@
+"""Host side of the C library (no GPU): exported symbols, the symbolic phase bit for
+bit against the oracle, and argument/pattern validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle.factor import sample_count
+from oracle.ordering import symbolic
+from workloads import grid_problem
+from workloads.grids import batched_problems
+
+from paper_1507_05593_amd import RSCSolver, lib
+from paper_1507_05593_amd._lib import RSC_ERR_INVALID_ARG, RSC_ERR_PATTERN, Options, RSCError
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "rsc.h")).read()
+    names = set(re.findall(r"\b(rsc_[a-z_]+)\s*\(", hdr))
+    names -= {"rsc_handle"}
+    assert len(names) >= 20
+    L = lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def _compare(sol: RSCSolver, sym, n):
+    assert np.array_equal(sol.perm, sym.perm)
+    first, parent, level, kind = sol.supernode_info()
+    assert np.array_equal(first, sym.first)
+    assert np.array_equal(parent, sym.parent)
+    assert np.array_equal(level, sym.level)
+    assert np.array_equal(kind, sym.kind)
+    rp, rows = sol.rowsets()
+    for j in range(sym.M):
+        assert np.array_equal(rows[rp[j]:rp[j + 1]], sym.rows[j])
+
+
+@pytest.mark.parametrize("dims,sigma,leaf", [((64, 64), 0.0, 64), ((31, 17), 1.0, 16), ((12, 12, 12), 1.0, 64),
+                                             ((16, 16, 16), 1.0, 64), ((9, 10, 11), 1.5, 8),
+                                             ((24, 24, 24), 1.0, 64)])
+def test_symbolic_bit_exact_with_oracle(dims, sigma, leaf):
+    p = grid_problem(dims, sigma=sigma, seed=2, unit=(sigma == 0))
+    sym = symbolic(p.n, p.rowptr, p.colind, leaf)
+    sol = RSCSolver(p.n, p.rowptr, p.colind, leaf_max=leaf)
+    _compare(sol, sym, p.n)
+
+
+def test_batched_symbolic_is_per_system_dissection():
+    probs = batched_problems(5, 8, 40, 1.0, seed=4)
+    sol = RSCSolver.batch([q.n for q in probs], [q.rowptr for q in probs], [q.colind for q in probs])
+    assert sol.systems == 5
+    perm = sol.perm
+    first, parent, level, kind = sol.supernode_info()
+    off = 0
+    sn = 0
+    for q in probs:
+        sym = symbolic(q.n, q.rowptr, q.colind, 64)
+        assert np.array_equal(perm[off:off + q.n], sym.perm + off)
+        assert np.array_equal(first[sn:sn + sym.M + 1], sym.first + off)
+        assert np.array_equal(level[sn:sn + sym.M], sym.level)
+        off += q.n
+        sn += sym.M
+    assert sn == sol.supernodes
+
+
+def test_sample_count_matches_oracle():
+    # the device-side sample counts follow the same rank function as the oracle
+    from paper_1507_05593_amd._lib import lib as _l  # noqa: F401
+    for r, c in [(200, 64), (9216, 4600), (37, 33), (1, 1), (120, 5000), (812, 640)]:
+        assert sample_count(r, c, 1.0, 10) == min(min(r, c), int(np.ceil(np.sqrt(min(r, c)) * np.log2(min(r, c)))) + 10)
+
+
+def test_pattern_and_argument_errors():
+    p = grid_problem((5, 5), unit=True)
+    bad = p.colind.copy()
+    bad[1], bad[2] = bad[2], bad[1]            # unsorted row
+    with pytest.raises(RSCError) as e:
+        RSCSolver(p.n, p.rowptr, bad)
+    assert e.value.code == RSC_ERR_PATTERN
+    # asymmetric pattern: drop one off-diagonal entry of row 0 (and shift the row pointer)
+    rp = p.rowptr.copy(); ci = p.colind.copy()
+    ci2 = np.delete(ci, 1); rp2 = rp.copy(); rp2[1:] -= 1
+    with pytest.raises(RSCError) as e:
+        RSCSolver(p.n, rp2, ci2)
+    assert e.value.code == RSC_ERR_PATTERN
+    with pytest.raises(RSCError) as e:
+        RSCSolver(p.n, p.rowptr, p.colind, leaf_max=0)
+    assert e.value.code == RSC_ERR_INVALID_ARG
+    h = C.c_void_p()
+    assert lib().rsc_analyze(-1, None, None, None, C.byref(h)) == RSC_ERR_INVALID_ARG
+
+
+def test_stats_before_factor():
+    p = grid_problem((20, 20), unit=True)
+    sol = RSCSolver(p.n, p.rowptr, p.colind)
+    s = sol.stats()
+    assert s["n"] == p.n and s["nnz"] == p.nnz and s["supernodes"] == sol.supernodes
+    assert s["flops_potrf"] == 0.0 and s["t_analyze_ms"] > 0
+    o = Options()
+    lib().rsc_default_options(C.byref(o))
+    assert (o.leaf_max, o.tau_O, o.oversample, o.power_iters, o.alpha_O) == (64, 32, 10, 0, 1.0)
