@@ -22,11 +22,10 @@ void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, 
                    hipStream_t s);
 void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int64_t* out,
                        int n, double* arena, hipStream_t s);
-void launch_jacobi_small(const EigTask* t, int n, double* arena, hipStream_t s);
-void launch_jacobi_round(const EigTask* t, int n, int max_pairs, int max_rowblocks, double* arena,
-                         int32_t* ints, int rnd, hipStream_t s);
-void launch_eig_init(const EigTask* t, int n, double* arena, hipStream_t s);
-void launch_eig_select(const EigTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
+void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s);
+void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s);
+void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);
+void launch_trunc_p(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ t
         if (i < T.m && j < n) {
           double* cp = C + i + (int64_t)j * T.ldc;
           const double v = T.alpha * acc[x][y][e];
-          *cp = (T.beta == 0.0) ? v : v + T.beta * *cp;
+          const double* dp = (T.d >= 0) ? arena + T.d + i + (int64_t)j * T.ldc : cp;
+          *cp = (T.beta == 0.0) ? v : v + T.beta * *dp;
         }
       }
 }
@@ -348,7 +349,7 @@ __global__ void k_philox(const PhiloxTask* __restrict__ tasks, double* __restric
   for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total;
        id += (int64_t)gridDim.x * blockDim.x) {
     const int row = (int)(id / ngrp), g = (int)(id % ngrp);
-    uint32_t c[4] = {(uint32_t)row, (uint32_t)g, 0u, 0u};
+    uint32_t c[4] = {(uint32_t)row, (uint32_t)g, T.c2, 0u};
     philox4x32_10(c, T.k0, T.k1);
     double out[4];
     for (int h = 0; h < 2; ++h) {
@@ -393,289 +394,153 @@ __global__ void k_gram_scale(const int64_t* __restrict__ g, const int32_t* __res
   if (threadIdx.x == 0) arena[out[p]] = red[0];
 }
 
-// ---------------------------------------------------------------- Jacobi eigensolver
+// ---------------------------------------------------------------- spectral truncation
 
-// Cyclic Jacobi with the round-robin parallel ordering on a 64x64 symmetric matrix in
-// LDS (Golub and Van Loan, symmetric Schur decomposition); accumulates the rotations
-// into Q (initialised by the caller).  Runs sweeps until no rotation is applied.
-__device__ void jacobi64(double (*A)[65], double (*Q)[65], double scale) {
-  __shared__ double cs[32], sn[32];
-  __shared__ int pp[32], qq[32];
-  __shared__ int rotated;
-  const int tid = threadIdx.x;
-  const double tiny = 1e-300 + 1e-15 * scale;
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int rnd = 0; rnd < 63; ++rnd) {
-      if (tid < 32) {
-        // circle method: position 0 fixed, positions 1..63 rotate
-        auto at = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + rnd) % 63); };
-        int p = at(tid), q = at(63 - tid);
-        if (p > q) { int t = p; p = q; q = t; }
-        const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-16 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > tiny) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
-          rotated = 1;
-        }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int idx = tid; idx < 32 * 64; idx += 256) {
-        const int r = idx & 31, j = idx >> 5;
-        const double c = cs[r], s = sn[r];
-        if (s == 0.0) continue;
-        const int p = pp[r], q = qq[r];
-        const double ap = A[p][j], aq = A[q][j];
-        A[p][j] = c * ap - s * aq;
-        A[q][j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns: A <- A J, Q <- Q J
-      for (int idx = tid; idx < 32 * 64; idx += 256) {
-        const int r = idx & 31, i = idx >> 5;
-        const double c = cs[r], s = sn[r];
-        if (s == 0.0) continue;
-        const int p = pp[r], q = qq[r];
-        const double ap = A[i][p], aq = A[i][q];
-        A[i][p] = c * ap - s * aq;
-        A[i][q] = s * ap + c * aq;
-        const double qp = Q[i][p], qv = Q[i][q];
-        Q[i][p] = c * qp - s * qv;
-        Q[i][q] = s * qp + c * qv;
-      }
-      __syncthreads();
-    }
-    if (!rotated) break;
+// Truncation of V (r x l) at sigma_i > tol sigma_1 through the spectral projector of
+// its Gram matrix G = V^T V onto the eigenvalues lambda > theta = tol^2 lambda_max:
+// X0 = (G - theta I)(G + theta I)^{-1} maps lambda to (lambda - theta)/(lambda + theta)
+// in (-1, 1); Newton-Schulz iterations X <- X (3 I - X^2) / 2 drive it to sign(G - theta I);
+// P = (I + X) / 2.  Per-problem scalars (arena sc[0..7]): trace, lambda_max, theta,
+// scale (largest diagonal of G + theta I).
+
+__device__ double block_sum256(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-}
-
-__device__ __forceinline__ void pair_blocks(int rnd, int pair, int nbk, int& I, int& J) {
-  auto at = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + rnd) % (nbk - 1)); };
-  I = at(pair);
-  J = at(nbk - 1 - pair);
-  if (I > J) { int t = I; I = J; J = t; }
-}
-
-// Small problems (npad == 64): the whole matrix in LDS, solved to convergence.
-__global__ __launch_bounds__(256) void k_jacobi_small(const EigTask* __restrict__ tasks,
-                                                      double* __restrict__ arena) {
-  __shared__ double A[64][65];
-  __shared__ double Q[64][65];
-  const EigTask T = tasks[blockIdx.x];
-  if (T.npad != 64) return;
-  const int tid = threadIdx.x;
-  double* G = arena + T.g;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    A[r][c] = G[r + 64 * c];
-    Q[r][c] = (r == c) ? 1.0 : 0.0;
-  }
+  const double r = red[0];
   __syncthreads();
-  jacobi64(A, Q, arena[T.scale]);
-  double* Z = arena + T.z;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    Z[r + 64 * c] = Q[r][c];
-    G[r + 64 * c] = A[r][c];
-  }
+  return r;
 }
 
-// Block Jacobi round, phase 1: for each block pair (I, J) of this round solve the
-// 64x64 subproblem [[G_II, G_IJ], [G_JI, G_JJ]] and store its rotation (64x64).
-// A pair whose coupling block is already negligible stores nothing and is skipped.
-__global__ __launch_bounds__(256) void k_jacobi_pairs(const EigTask* __restrict__ tasks,
-                                                      double* __restrict__ arena,
-                                                      int32_t* __restrict__ ints, int rnd) {
-  __shared__ double A[64][65];
-  __shared__ double Q[64][65];
-  __shared__ int big;
-  const EigTask T = tasks[blockIdx.y];
-  const int pair = blockIdx.x;
-  if (T.npad <= 64 || pair >= T.nbk / 2) return;
-  int I, J;
-  pair_blocks(rnd % (T.nbk - 1), pair, T.nbk, I, J);
-  const int tid = threadIdx.x;
+// trace(G) and S = G / trace(G) (zero when the trace is not positive).
+__global__ __launch_bounds__(256) void k_trunc_prep(const TruncTask* __restrict__ tasks,
+                                                    double* __restrict__ arena) {
+  const TruncTask T = tasks[blockIdx.x];
+  const int l = T.l;
   const double* G = arena + T.g;
-  const int ld = T.npad;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    const int gr = (r < 32 ? I * 32 + r : J * 32 + r - 32);
-    const int gc = (c < 32 ? I * 32 + c : J * 32 + c - 32);
-    A[r][c] = G[gr + (int64_t)gc * ld];
-    Q[r][c] = (r == c) ? 1.0 : 0.0;
-  }
-  if (tid == 0) big = 0;
-  __syncthreads();
-  const double floor_abs = 1e-300 + 1e-15 * arena[T.scale];
-  for (int idx = tid; idx < 32 * 32; idx += 256) {
-    const int r = idx & 31, c = 32 + (idx >> 5);
-    const double a = A[r][c];
-    if (fabs(a) > 1e-16 * sqrt(fabs(A[r][r]) * fabs(A[c][c])) && fabs(a) > floor_abs) big = 1;
-  }
-  __syncthreads();
-  int32_t* flag = ints + T.flagslot + pair;
-  if (!big) {
-    if (tid == 0) *flag = 0;
-    return;
-  }
-  if (tid == 0) *flag = 1;
-  jacobi64(A, Q, arena[T.scale]);
-  double* R = arena + T.rot + (int64_t)pair * 64 * 64;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    R[r + 64 * c] = Q[r][c];
-  }
+  double t = 0.0;
+  for (int i = threadIdx.x; i < l; i += 256) t += G[i + (int64_t)i * l];
+  t = block_sum256(t);
+  if (threadIdx.x == 0) arena[T.sc] = t;
+  const double inv = (t > 0.0 && isfinite(t)) ? 1.0 / t : 0.0;
+  double* S = arena + T.sa;
+  const int64_t ll = (int64_t)l * l;
+  for (int64_t e = threadIdx.x; e < ll; e += 256) S[e] = G[e] * inv;
 }
 
-// Block Jacobi round, phase 2: G <- P^T G P for the block-diagonal rotation P of the
-// round, one (pair a, pair b) 64x64 block per workgroup; blockIdx.x = a * (nbk/2) + b.
-__global__ __launch_bounds__(256) void k_jacobi_apply_g(const EigTask* __restrict__ tasks,
-                                                        double* __restrict__ arena,
-                                                        const int32_t* __restrict__ ints, int rnd) {
-  __shared__ double X[64][65];
-  __shared__ double Y[64][65];
-  const EigTask T = tasks[blockIdx.y];
-  if (T.npad <= 64) return;
-  const int np = T.nbk / 2;
-  const int pa = blockIdx.x / np, pb = blockIdx.x % np;
-  if (pa >= np) return;
-  const int fa = ints[T.flagslot + pa], fb = ints[T.flagslot + pb];
-  if (!fa && !fb) return;
-  int Ia, Ja, Ib, Jb;
-  pair_blocks(rnd % (T.nbk - 1), pa, T.nbk, Ia, Ja);
-  pair_blocks(rnd % (T.nbk - 1), pb, T.nbk, Ib, Jb);
-  const int tid = threadIdx.x;
-  double* G = arena + T.g;
-  const int ld = T.npad;
-  const double* Ra = arena + T.rot + (int64_t)pa * 4096;
-  const double* Rb = arena + T.rot + (int64_t)pb * 4096;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    const int gr = (r < 32 ? Ia * 32 + r : Ja * 32 + r - 32);
-    const int gc = (c < 32 ? Ib * 32 + c : Jb * 32 + c - 32);
-    X[r][c] = G[gr + (int64_t)gc * ld];
-  }
-  __syncthreads();
-  // Y = Ra^T X (if pair a rotated), else Y = X
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    double s;
-    if (fa) {
-      s = 0.0;
-      for (int t = 0; t < 64; ++t) s += Ra[t + 64 * r] * X[t][c];
-    } else {
-      s = X[r][c];
-    }
-    Y[r][c] = s;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    double s;
-    if (fb) {
-      s = 0.0;
-      for (int t = 0; t < 64; ++t) s += Y[r][t] * Rb[t + 64 * c];
-    } else {
-      s = Y[r][c];
-    }
-    const int gr = (r < 32 ? Ia * 32 + r : Ja * 32 + r - 32);
-    const int gc = (c < 32 ? Ib * 32 + c : Jb * 32 + c - 32);
-    G[gr + (int64_t)gc * ld] = s;
-  }
-}
-
-// Block Jacobi round, phase 3: Z <- Z P on the columns of each rotated pair;
-// blockIdx.x = pair * (npad / 64) + row block.
-__global__ __launch_bounds__(256) void k_jacobi_apply_z(const EigTask* __restrict__ tasks,
-                                                        double* __restrict__ arena,
-                                                        const int32_t* __restrict__ ints, int rnd) {
-  __shared__ double X[64][65];
-  const EigTask T = tasks[blockIdx.y];
-  if (T.npad <= 64) return;
-  const int nrb = T.npad / 64;
-  const int pair = blockIdx.x / nrb, rb = blockIdx.x % nrb;
-  if (pair >= T.nbk / 2) return;
-  if (!ints[T.flagslot + pair]) return;
-  int I, J;
-  pair_blocks(rnd % (T.nbk - 1), pair, T.nbk, I, J);
-  const int tid = threadIdx.x;
-  double* Z = arena + T.z;
-  const int ld = T.npad;
-  const double* R = arena + T.rot + (int64_t)pair * 4096;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    const int gc = (c < 32 ? I * 32 + c : J * 32 + c - 32);
-    X[r][c] = Z[rb * 64 + r + (int64_t)gc * ld];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    double s = 0.0;
-    for (int t = 0; t < 64; ++t) s += X[r][t] * R[t + 64 * c];
-    const int gc = (c < 32 ? I * 32 + c : J * 32 + c - 32);
-    Z[rb * 64 + r + (int64_t)gc * ld] = s;
-  }
-}
-
-// Z = I (npad x npad) before the rounds of a block Jacobi solve.
-__global__ void k_eig_init(const EigTask* __restrict__ tasks, double* __restrict__ arena) {
-  const EigTask T = tasks[blockIdx.y];
-  const int64_t nn = (int64_t)T.npad * T.npad;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nn;
-       i += (int64_t)gridDim.x * blockDim.x)
-    arena[T.z + i] = (i % T.npad == i / T.npad) ? 1.0 : 0.0;
-}
-
-// Eigenvalues are the diagonal of the converged G.  Sort descending (rank by
-// counting, ties by index), keep q = #{sqrt(lambda_i) > tol * sqrt(lambda_max)}, and
-// write the kept eigenvectors, in order, as the first q columns of zq (n x n; the
-// rest zero).
-__global__ __launch_bounds__(256) void k_eig_select(const EigTask* __restrict__ tasks,
-                                                    double* __restrict__ arena,
-                                                    int32_t* __restrict__ ints) {
-  const EigTask T = tasks[blockIdx.x];
-  const int tid = threadIdx.x;
+// lambda_max by power iteration with S32 = (G / tr G)^32 (already in sb), Rayleigh
+// quotient with G; theta = tol^2 lambda_max; then the Cholesky panel
+// [G + theta I; I] (ld 2l) and its drop scale.
+__global__ __launch_bounds__(256) void k_trunc_power(const TruncTask* __restrict__ tasks,
+                                                     double* __restrict__ arena) {
+  __shared__ double v[2048], w[2048];   // l <= 2048 (checked by the planner)
+  const TruncTask T = tasks[blockIdx.x];
+  const int l = T.l;
+  const double* S = arena + T.sb;
   const double* G = arena + T.g;
-  const double* Z = arena + T.z;
-  double* zq = arena + T.zq;
-  double* lam = arena + T.lam;
-  const int n = T.n, ld = T.npad;
-  __shared__ double lmax;
-  __shared__ int q;
-  if (tid == 0) {
-    double m = 0.0;
-    bool bad = false;
-    for (int i = 0; i < n; ++i) {
-      const double d = G[i + (int64_t)i * ld];
-      if (!isfinite(d)) bad = true;
-      m = fmax(m, d);
-    }
-    lmax = bad ? 0.0 : m;
-    q = 0;
+  for (int i = threadIdx.x; i < l; i += 256) {
+    // fixed, non-structured start vector
+    uint32_t h = (uint32_t)i * 2654435761u + 0x9E3779B9u;
+    h ^= h >> 15; h *= 2246822519u; h ^= h >> 13;
+    v[i] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
   }
   __syncthreads();
-  const double smax = sqrt(fmax(lmax, 0.0));
-  for (int i = tid; i < n; i += 256) {
-    const double li = G[i + (int64_t)i * ld];
-    int rank = 0;
-    for (int t = 0; t < n; ++t) {
-      const double lt = G[t + (int64_t)t * ld];
-      rank += (lt > li) || (lt == li && t < i);
+  for (int it = 0; it < 12; ++it) {
+    for (int i = threadIdx.x; i < l; i += 256) {
+      double a = 0.0;
+      for (int k = 0; k < l; ++k) a += S[i + (int64_t)k * l] * v[k];
+      w[i] = a;
     }
-    lam[rank] = li;
-    const bool keep = smax > 0.0 && sqrt(fmax(li, 0.0)) > T.tol * smax;
-    if (keep) atomicAdd(&q, 1);
-    for (int r = 0; r < n; ++r) zq[r + (int64_t)rank * n] = keep ? Z[r + (int64_t)i * ld] : 0.0;
+    __syncthreads();
+    double nn = 0.0;
+    for (int i = threadIdx.x; i < l; i += 256) nn += w[i] * w[i];
+    nn = block_sum256(nn);
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = threadIdx.x; i < l; i += 256) v[i] = w[i] * inv;
+    __syncthreads();
   }
+  double num = 0.0, den = 0.0;
+  for (int i = threadIdx.x; i < l; i += 256) {
+    double a = 0.0;
+    for (int k = 0; k < l; ++k) a += G[i + (int64_t)k * l] * v[k];
+    num += v[i] * a;
+    den += v[i] * v[i];
+  }
+  num = block_sum256(num);
+  den = block_sum256(den);
+  double lam = (den > 0.0) ? num / den : 0.0;
+  if (!isfinite(lam) || lam < 0.0) lam = 0.0;
+  const double theta = T.tol * T.tol * lam;
+  if (threadIdx.x == 0) { arena[T.sc + 1] = lam; arena[T.sc + 2] = theta; }
+  double* M = arena + T.mpan;
+  const int ld = 2 * l;
+  double mx = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += 256) {
+    const int i = (int)(e % l), j = (int)(e / l);
+    const double gij = G[e] + (i == j ? theta : 0.0);
+    M[i + (int64_t)j * ld] = gij;
+    M[l + i + (int64_t)j * ld] = (i == j) ? 1.0 : 0.0;
+    if (i == j) mx = fmax(mx, gij);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = mx;
   __syncthreads();
-  if (tid == 0) ints[T.qslot] = q;
+  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) arena[T.sc + 3] = red[0];
+}
+
+// X0 = I - 2 theta H with H = (G + theta I)^{-1} (in sb), into sa.
+__global__ __launch_bounds__(256) void k_trunc_x0(const TruncTask* __restrict__ tasks,
+                                                  double* __restrict__ arena) {
+  const TruncTask T = tasks[blockIdx.y];
+  const int l = T.l;
+  const double theta = arena[T.sc + 2];
+  const double* H = arena + T.sb;
+  double* X = arena + T.sa;
+  const int64_t ll = (int64_t)l * l;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < ll; e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e % l), j = (int)(e / l);
+    X[e] = (i == j ? 1.0 : 0.0) - 2.0 * theta * H[e];
+  }
+}
+
+// P = (I + X) / 2 in place; q = round(trace P) (0 for a zero or non-finite Gram); the
+// sample block of the basis panel is cleared so that columns >= q stay zero.
+__global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ tasks,
+                                                 double* __restrict__ arena,
+                                                 int32_t* __restrict__ ints) {
+  const TruncTask T = tasks[blockIdx.x];
+  const int l = T.l;
+  double* X = arena + T.sa;
+  double tr = 0.0;
+  const int64_t ll = (int64_t)l * l;
+  for (int64_t e = threadIdx.x; e < ll; e += 256) {
+    const int i = (int)(e % l), j = (int)(e / l);
+    const double p = 0.5 * ((i == j ? 1.0 : 0.0) + X[e]);
+    X[e] = p;
+    if (i == j) tr += p;
+  }
+  tr = block_sum256(tr);
+  double* W = arena + T.wpan;
+  const int ld = 2 * l;
+  for (int64_t e = threadIdx.x; e < ll; e += 256) {
+    const int i = (int)(e % l), j = (int)(e / l);
+    W[l + i + (int64_t)j * ld] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    const double gt = arena[T.sc];
+    int q = (int)floor(tr + 0.5);
+    if (!(gt > 0.0) || !isfinite(gt) || !isfinite(tr)) q = 0;
+    q = max(0, min(q, l));
+    ints[T.qslot] = q;
+  }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -718,23 +583,17 @@ void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, c
                        int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gram_scale, dim3(n), dim3(256), 0, s, g, ld, nn, out, arena);
 }
-void launch_jacobi_small(const EigTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_jacobi_small, dim3(n), dim3(256), 0, s, t, arena);
+void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_prep, dim3(n), dim3(256), 0, s, t, arena);
 }
-void launch_jacobi_round(const EigTask* t, int n, int max_pairs, int max_rowblocks, double* arena,
-                         int32_t* ints, int rnd, hipStream_t s) {
-  if (n <= 0 || max_pairs <= 0) return;
-  hipLaunchKernelGGL(k_jacobi_pairs, dim3(max_pairs, n), dim3(256), 0, s, t, arena, ints, rnd);
-  hipLaunchKernelGGL(k_jacobi_apply_g, dim3(max_pairs * max_pairs, n), dim3(256), 0, s, t, arena,
-                     (const int32_t*)ints, rnd);
-  hipLaunchKernelGGL(k_jacobi_apply_z, dim3(max_pairs * max_rowblocks, n), dim3(256), 0, s, t,
-                     arena, (const int32_t*)ints, rnd);
+void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_power, dim3(n), dim3(256), 0, s, t, arena);
 }
-void launch_eig_init(const EigTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_eig_init, dim3(64, n), dim3(256), 0, s, t, arena);
+void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_x0, dim3(64, n), dim3(256), 0, s, t, arena);
 }
-void launch_eig_select(const EigTask* t, int n, double* arena, int32_t* ints, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_eig_select, dim3(n), dim3(256), 0, s, t, arena, ints);
+void launch_trunc_p(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_p, dim3(n), dim3(256), 0, s, t, arena, ints);
 }
 
 }  // namespace rsc

@@ -73,21 +73,35 @@ __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ t
 }
 
 // out[i] = sum_{t >= i} M(i, t) (w[t] - s[t]): backward solve with L^{-T}.
-__global__ __launch_bounds__(256) void k_trsv_bwd(const RowTask* __restrict__ tasks,
+// One 64-row block per workgroup of 512 threads: lane = row (coalesced column
+// reads of M), the 8 waves split the columns t >= i0 and their partial sums are
+// added in a fixed order.
+__global__ __launch_bounds__(512) void k_trsv_bwd(const RowTask* __restrict__ tasks,
                                                   double* __restrict__ arena) {
+  __shared__ double part[8][64];
   const RowTask T = tasks[blockIdx.x];
-  const int i = T.i0 + threadIdx.x;
-  if (i >= T.c) return;
-  const double* M = arena + T.m + i;
-  const double* w = arena + T.w;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = T.i0 + lane;
+  const double* w_ = arena + T.w;
+  const double* s_ = T.s >= 0 ? arena + T.s : nullptr;
   double acc = 0.0;
-  if (T.s >= 0) {
-    const double* s = arena + T.s;
-    for (int t = i; t < T.c; ++t) acc += M[(int64_t)t * T.ld] * (w[t] - s[t]);
-  } else {
-    for (int t = i; t < T.c; ++t) acc += M[(int64_t)t * T.ld] * w[t];
+  if (i < T.c) {
+    const double* M = arena + T.m + i;
+    const int ncol = T.c - T.i0;                 // columns t in [i0, c)
+    const int per = (ncol + 7) / 8;
+    const int t0 = T.i0 + w * per, t1 = min(T.c, t0 + per);
+    for (int t = max(t0, i); t < t1; ++t) {
+      const double v = s_ ? w_[t] - s_[t] : w_[t];
+      acc += M[(int64_t)t * T.ld] * v;
+    }
   }
-  arena[T.out + i] = acc;
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < T.c) {
+    double s = 0.0;
+    for (int q = 0; q < 8; ++q) s += part[q][lane];
+    arena[T.out + i] = s;
+  }
 }
 
 // y[rows[t]] -= sum of part[contrib[p]], p in [ptr[t], ptr[t+1]), in list order.
@@ -163,14 +177,16 @@ __global__ __launch_bounds__(256) void k_resid_partial(const Chunk* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = d;
 }
 
-// out[s] = sum of the partials of segment s, in chunk order (deterministic).
-__global__ void k_seg_sum(const int32_t* __restrict__ seg_ptr, int32_t nseg,
-                          const double* __restrict__ partial, double* __restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
+// out[s] = sum of the partials of segment s (one workgroup per segment, fixed
+// strided assignment and reduction tree: deterministic).
+__global__ __launch_bounds__(256) void k_seg_sum(const int32_t* __restrict__ seg_ptr, int32_t nseg,
+                                                 const double* __restrict__ partial,
+                                                 double* __restrict__ out) {
+  const int s = blockIdx.x;
   double acc = 0.0;
-  for (int c = seg_ptr[s]; c < seg_ptr[s + 1]; ++c) acc += partial[c];
-  out[s] = acc;
+  for (int c = seg_ptr[s] + threadIdx.x; c < seg_ptr[s + 1]; c += 256) acc += partial[c];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) out[s] = acc;
 }
 
 // Per-system CG scalars.  sc layout (doubles, per segment s): see PcgScalars.
@@ -317,7 +333,7 @@ void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gid
   if (n > 0) hipLaunchKernelGGL(k_coldot, dim3(n), dim3(256), 0, s, t, arena, gidx, ilim);
 }
 void launch_trsv_bwd(const RowTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_trsv_bwd, dim3(n), dim3(256), 0, s, t, arena);
+  if (n > 0) hipLaunchKernelGGL(k_trsv_bwd, dim3(n), dim3(512), 0, s, t, arena);
 }
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s) {
@@ -346,7 +362,7 @@ void launch_resid_partial(const Chunk* c, int nc, const double* b, const double*
 }
 void launch_seg_sum(const int32_t* seg_ptr, int32_t nseg, const double* partial, double* out,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_seg_sum, dim3((nseg + 255) / 256), dim3(256), 0, s, seg_ptr, nseg, partial, out);
+  if (nseg > 0) hipLaunchKernelGGL(k_seg_sum, dim3(nseg), dim3(256), 0, s, seg_ptr, nseg, partial, out);
 }
 void launch_pcg_alpha(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_alpha, dim3((nseg + 255) / 256), dim3(256), 0, s, nseg, sc, arena, ints);

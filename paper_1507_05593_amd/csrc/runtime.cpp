@@ -30,7 +30,7 @@ namespace rsc {
   } while (0)
 
 static const Error kOk{RSC_OK, ""};
-static constexpr int kSweepsBlockJacobi = 8;
+static constexpr int kNewtonSchulzSteps = 24;
 
 int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p) {
   const int32_t k = std::min(r, c);
@@ -98,14 +98,11 @@ void plan_layout(Handle& h) {
   int32_t islot = 0;
   h.i_status = islot; islot += 4;
   h.i_ranks = islot; islot += (int32_t)M;
-  int64_t gv_region = 0;
   for (int64_t j = 0; j < M; ++j) {
     if (!h.compressible[j]) continue;
     CompSlot& C = h.comp[j];
     const int32_t c = S.c(j), r = S.r(j);
-    C.ell = sample_count(r, c, h.opt.alpha_O, h.opt.oversample);
-    C.npad = C.ell <= 64 ? 64 : (int32_t)(((C.ell + 63) / 64) * 64);
-    C.nbk = C.npad / 32;
+    C.ell = std::min<int32_t>(sample_count(r, c, h.opt.alpha_O, h.opt.oversample), 2048);
     const int64_t l = C.ell;
     C.omega = a; a += align64(r * l);
     C.ypanel = a; a += align64((l + c) * l);
@@ -113,26 +110,21 @@ void plan_layout(Handle& h) {
     C.V = a; a += align64(r * l);
     C.Vj = a; a += align64(r * l);
     C.Uj = a; a += align64(c * l);
-    C.zq = a; a += align64(l * l);
-    C.lam = a; a += align64(l);
-    C.rot = a; a += (int64_t)(C.nbk / 2) * 4096;
-    C.gscale = a; C.escale = a + 1; a += 64;
+    C.gscale = a; a += 64;
     C.tvq = a; a += align64(l);
     C.u = a; a += align64(l);
+    C.G = a; a += align64(l * l);
+    C.Sa = a; a += align64(l * l);
+    C.Sb = a; a += align64(l * l);
+    C.Om2 = a; a += align64(l * l);
+    C.Mpan = a; a += align64(2 * l * l);
+    C.Mdinv = a; a += ((l + 63) / 64) * 4096;
+    C.Wpan = a; a += align64(2 * l * l);
+    C.Wdinv = a; a += ((l + 63) / 64) * 4096;
+    C.sc = a; a += 64;
     C.qslot = h.i_ranks + (int32_t)j;
-    C.flagslot = islot; islot += C.nbk / 2;
-    gv_region += 2 * (int64_t)C.npad * C.npad;
   }
-  // Gram matrices and eigenvectors of every compressible supernode, contiguous so
-  // that one fill clears their padding
-  int64_t gv = a;
-  for (int64_t j = 0; j < M; ++j) {
-    if (!h.compressible[j]) continue;
-    CompSlot& C = h.comp[j];
-    C.Gv = gv; gv += (int64_t)C.npad * C.npad;
-    C.Z = gv; gv += (int64_t)C.npad * C.npad;
-  }
-  a = align64(gv);
+  a = align64(a);
   h.arena_size = a;
   // PCG int slots
   h.sc.active = islot; islot += nseg;
@@ -140,7 +132,6 @@ void plan_layout(Handle& h) {
   h.sc.any = islot++;
   h.sc.breakdown = islot++;
   h.ints_size = islot;
-  (void)gv_region;
 
   // assembly map: entry (i, col) with col <= i goes to the lower position of the
   // permuted pair in the panel of the supernode owning the column
@@ -264,7 +255,7 @@ struct Builder {
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
            int64_t b = 0, double v = 0) {
-    if (count <= 0 && type != kCmdJacobiRound) return;
+    if (count <= 0) return;
     Cmd c;
     c.type = type; c.klass = klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
     c.flops = flops;
@@ -289,7 +280,7 @@ struct Builder {
                      double beta) {
     GemmTask t{};
     t.a = a; t.ais = ais; t.aks = aks; t.b = b; t.bjs = bjs; t.bks = bks; t.c = c; t.ldc = ldc;
-    t.m = m; t.n = n; t.k = k; t.alpha = alpha; t.beta = beta; t.nlim = -1; t.klim = -1;
+    t.m = m; t.n = n; t.k = k; t.alpha = alpha; t.beta = beta; t.nlim = -1; t.klim = -1; t.d = -1;
     return t;
   }
 
@@ -499,66 +490,134 @@ struct Builder {
       fl += tiles(gt(LO, 1, h.panel_ld[j], C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
-    // 6. Gram V^T V (full) into the padded eigenproblem
+    // 6. Gram G = V^T V (full)
     g0 = (int64_t)P.gemm.size(); fl = 0;
-    const int64_t s0 = (int64_t)P.gs_g.size();
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t r = S.r(j), l = C.ell;
-      fl += tiles(gt(C.V, r, 1, C.V, r, 1, C.Gv, C.npad, l, l, r, 1.0, 0.0), 0, 0, false);
-      P.gs_g.push_back(C.Gv); P.gs_ld.push_back(C.npad); P.gs_n.push_back(l); P.gs_out.push_back(C.escale);
+      fl += tiles(gt(C.V, r, 1, C.V, r, 1, C.G, l, l, l, r, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
-    cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
-    // 7. Jacobi eigendecomposition and selection of the kept rank
-    const int64_t e_small = (int64_t)P.eig.size();
+    // 7. spectral projector onto lambda > tol^2 lambda_max (see the truncation kernels)
+    const int64_t t0 = (int64_t)P.trunc.size();
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
-      if (C.npad != 64) continue;
-      P.eig.push_back(eig_task(j, tol));
+      TruncTask t{};
+      t.g = C.G; t.sa = C.Sa; t.sb = C.Sb; t.mpan = C.Mpan; t.wpan = C.Wpan; t.sc = C.sc;
+      t.l = C.ell; t.qslot = C.qslot; t.tol = tol;
+      P.trunc.push_back(t);
     }
-    const int64_t e_big = (int64_t)P.eig.size();
-    int32_t maxnbk = 0, maxrb = 0;
-    double efl = 0;
+    const int64_t nt = (int64_t)P.trunc.size() - t0;
+    auto sq_gemm = [&](bool a_to_b, double alpha, double beta, int64_t dsel) {
+      // C = alpha X Y^T (+ beta D) on every problem's l x l blocks; X = Y symmetric
+      const int64_t gg = (int64_t)P.gemm.size();
+      double f = 0;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t l = C.ell;
+        const int64_t src = a_to_b ? C.Sa : C.Sb, dst = a_to_b ? C.Sb : C.Sa;
+        GemmTask t = gt(src, 1, l, src, 1, l, dst, l, l, l, l, alpha, beta);
+        (void)dsel;
+        f += tiles(t, 0, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_EIG, gg, (int64_t)P.gemm.size() - gg, f);
+    };
+    cmd(kCmdTruncPrep, RSC_K_EIG, t0, nt, 0);          // sa = G / tr G
+    for (int k = 0; k < 5; ++k) sq_gemm(k % 2 == 0, 1.0, 0.0, -1);   // sb = (G / tr G)^32
+    cmd(kCmdTruncPower, RSC_K_EIG, t0, nt, 0);         // lambda_max, theta, [G + theta I; I]
+    {
+      std::vector<PanelDesc> pan;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        pan.push_back(PanelDesc{C.Mpan, 2 * C.ell, C.ell, 0, true, C.Mdinv, j, 1, C.sc + 3});
+      }
+      panel_steps(pan);                                 // rows [l, 2l) become L^{-T}
+    }
+    // H = (G + theta I)^{-1} = L^{-T} L^{-1} into sb
+    g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
-      efl += 10.0 * std::pow((double)C.npad, 3);
-      if (C.npad == 64) continue;
-      P.eig.push_back(eig_task(j, tol));
-      maxnbk = std::max(maxnbk, C.nbk);
-      maxrb = std::max(maxrb, C.npad / 64);
+      const int32_t l = C.ell;
+      fl += tiles(gt(C.Mpan + l, 1, 2 * l, C.Mpan + l, 1, 2 * l, C.Sb, l, l, l, l, 1.0, 0.0), 0, 0, false);
     }
-    const int64_t e_end = (int64_t)P.eig.size();
-    cmd(kCmdJacobiSmall, RSC_K_EIG, e_small, e_big - e_small, efl);
-    if (e_end > e_big) {
-      cmd(kCmdEigInit, RSC_K_EIG, e_big, e_end - e_big, 0);
-      const int32_t rounds = kSweepsBlockJacobi * (maxnbk - 1);
-      for (int32_t rnd = 0; rnd < rounds; ++rnd)
-        cmd(kCmdJacobiRound, RSC_K_EIG, e_big, e_end - e_big, 0, maxnbk / 2, maxrb, (double)rnd);
+    cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+    cmd(kCmdTruncX0, RSC_K_EIG, t0, nt, 0);            // sa = I - 2 theta H
+    for (int it = 0; it < kNewtonSchulzSteps; ++it) {
+      // sb = X X ; X_new = 1.5 X - 0.5 X sb (into sb via the D operand, then swap roles)
+      g0 = (int64_t)P.gemm.size(); fl = 0;
+      const bool even = (it % 2 == 0);
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t l = C.ell;
+        const int64_t X = even ? C.Sa : C.Sb;
+        fl += tiles(gt(X, 1, l, X, 1, l, C.Om2, l, l, l, l, 1.0, 0.0), 0, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+      g0 = (int64_t)P.gemm.size(); fl = 0;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t l = C.ell;
+        const int64_t X = even ? C.Sa : C.Sb, Xn = even ? C.Sb : C.Sa;
+        GemmTask t = gt(X, 1, l, C.Om2, 1, l, Xn, l, l, l, l, -0.5, 1.5);
+        t.d = X;
+        fl += tiles(t, 0, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
     }
-    cmd(kCmdEigSelect, RSC_K_EIG, e_small, e_end - e_small, 0);
-    // 8. U_j = U Z_q, V_j = V Z_q (columns beyond the device rank q_j are skipped)
+    static_assert(kNewtonSchulzSteps % 2 == 0, "the iterate must end in sa");
+    cmd(kCmdTruncP, RSC_K_EIG, t0, nt, 0);             // sa = P, q, clear the sample block
+    // 8. basis of range(P): W = orth(P Omega2) on the first q columns
+    {
+      const int64_t ph0 = (int64_t)P.philox.size();
+      int64_t maxw2 = 0;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        PhiloxTask t{};
+        t.out = C.Om2; t.rows = C.ell; t.cols = C.ell; t.c2 = 1;
+        t.k0 = (uint32_t)(h.opt.seed & 0xFFFFFFFFull);
+        t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)j);
+        P.philox.push_back(t);
+        maxw2 = std::max<int64_t>(maxw2, (int64_t)C.ell * ((C.ell + 3) / 4));
+      }
+      cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw2);
+      g0 = (int64_t)P.gemm.size(); fl = 0;
+      for (int32_t j : js) {
+        const CompSlot& C = h.comp[j];
+        const int32_t l = C.ell;
+        GemmTask t = gt(C.Sa, 1, l, C.Om2, l, 1, C.Wpan + l, 2 * l, l, l, l, 1.0, 0.0);
+        t.nlim = C.qslot;
+        fl += tiles(t, 0, 0, false);
+      }
+      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+      for (int pass = 0; pass < 3; ++pass) {
+        g0 = (int64_t)P.gemm.size(); fl = 0;
+        const int64_t s0 = (int64_t)P.gs_g.size();
+        std::vector<PanelDesc> pan;
+        for (int32_t j : js) {
+          const CompSlot& C = h.comp[j];
+          const int32_t l = C.ell;
+          fl += tiles(gt(C.Wpan + l, 2 * l, 1, C.Wpan + l, 2 * l, 1, C.Wpan, 2 * l, l, l, l, 1.0, 0.0), 0, 0, true);
+          P.gs_g.push_back(C.Wpan); P.gs_ld.push_back(2 * l); P.gs_n.push_back(l); P.gs_out.push_back(C.sc + 4);
+          pan.push_back(PanelDesc{C.Wpan, 2 * l, l, l, false, C.Wdinv, j, 1, C.sc + 4});
+        }
+        cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+        cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
+        panel_steps(pan);
+      }
+    }
+    // 9. U_j = U W, V_j = V W (columns beyond the device rank q_j are skipped)
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      GemmTask t = gt(C.ypanel + l, 1, ldy, C.zq, l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
+      GemmTask t = gt(C.ypanel + l, 1, ldy, C.Wpan + l, 2 * l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
       t.nlim = C.qslot;
       fl += tiles(t, 0, 0, false);
-      GemmTask t2 = gt(C.V, 1, r, C.zq, l, 1, C.Vj, r, r, l, l, 1.0, 0.0);
+      GemmTask t2 = gt(C.V, 1, r, C.Wpan + l, 2 * l, 1, C.Vj, r, r, l, l, 1.0, 0.0);
       t2.nlim = C.qslot;
       fl += tiles(t2, 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
-  }
-
-  EigTask eig_task(int32_t j, double tol) {
-    const CompSlot& C = h.comp[j];
-    EigTask e{};
-    e.g = C.Gv; e.z = C.Z; e.rot = C.rot; e.zq = C.zq; e.lam = C.lam; e.scale = C.escale;
-    e.n = C.ell; e.npad = C.npad; e.nbk = C.nbk; e.qslot = C.qslot; e.tol = tol;
-    e.flagslot = C.flagslot;
-    return e;
   }
 };
 
@@ -578,16 +637,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol) {
   B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_status, 2, 0, 0, 0, (double)INT_MAX);
   B.cmd(kCmdAssemble, RSC_K_OTHER, 0, S.nnz, 0);
   B.cmd(kCmdIdent, RSC_K_OTHER, 0, (int64_t)h.ident_slot.size(), 0);
-  if (compressed) {
-    int64_t g0 = -1, g1 = -1;
-    for (int64_t j = 0; j < S.M(); ++j)
-      if (h.compressible[j]) {
-        if (g0 < 0) g0 = h.comp[j].Gv;
-        g1 = h.comp[j].Z + (int64_t)h.comp[j].npad * h.comp[j].npad;
-      }
-    if (g0 >= 0) B.cmd(kCmdFill, RSC_K_OTHER, g0, g1 - g0, 0, 0, 0, 0.0);
-    B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_ranks, S.M(), 0, 0, 0, 0.0);
-  }
+  if (compressed) B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_ranks, S.M(), 0, 0, 0, 0.0);
   for (int32_t L = 0; L < S.nlevels; ++L) {
     const auto& lev = S.by_level[L];
     B.updates(lev);
@@ -607,7 +657,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol) {
       const double l = h.comp[j].ell;
       P->flops[3] += 4.0 * r * c * l * (1 + h.opt.power_iters);
       P->flops[4] += 3.0 * (2.0 * c * l * l + l * l * l / 3.0);
-      P->flops[5] += 2.0 * r * l * l;
+      P->flops[5] += 2.0 * r * l * l + (2.0 * 5 + 4.0 * kNewtonSchulzSteps + 2.0) * l * l * l;
     }
   }
   Error e;
@@ -616,7 +666,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol) {
   if ((e = upload(P->d_ents, P->ents)).code) return e;
   if ((e = upload(P->d_potrf, P->potrf)).code) return e;
   if ((e = upload(P->d_philox, P->philox)).code) return e;
-  if ((e = upload(P->d_eig, P->eig)).code) return e;
+  if ((e = upload(P->d_trunc, P->trunc)).code) return e;
   if ((e = upload(P->d_gs_g, P->gs_g)).code) return e;
   if ((e = upload(P->d_gs_out, P->gs_out)).code) return e;
   if ((e = upload(P->d_gs_ld, P->gs_ld)).code) return e;
@@ -649,12 +699,10 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,
                         P->d_gs_out.p + c.off, (int)c.count, A, s);
       break;
-    case kCmdEigInit: launch_eig_init(P->d_eig.p + c.off, (int)c.count, A, s); break;
-    case kCmdJacobiSmall: launch_jacobi_small(P->d_eig.p + c.off, (int)c.count, A, s); break;
-    case kCmdJacobiRound:
-      launch_jacobi_round(P->d_eig.p + c.off, (int)c.count, (int)c.a, (int)c.b, A, I, (int)c.v, s);
-      break;
-    case kCmdEigSelect: launch_eig_select(P->d_eig.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdTruncPrep: launch_trunc_prep(P->d_trunc.p + c.off, (int)c.count, A, s); break;
+    case kCmdTruncPower: launch_trunc_power(P->d_trunc.p + c.off, (int)c.count, A, s); break;
+    case kCmdTruncX0: launch_trunc_x0(P->d_trunc.p + c.off, (int)c.count, A, s); break;
+    case kCmdTruncP: launch_trunc_p(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
     case kCmdTrsvBwd: launch_trsv_bwd(Q->d_rows.p + c.off, (int)c.count, A, s); break;
@@ -918,7 +966,7 @@ static Error build_solve_plan(Handle& h) {
     const int64_t w0 = (int64_t)Q->rows.size();
     for (int32_t j : lev) {
       const int32_t c = S.c(j), r = S.r(j);
-      for (int32_t i0 = 0; i0 < c; i0 += 256) {
+      for (int32_t i0 = 0; i0 < c; i0 += 64) {
         RowTask t{};
         t.m = h.a_panels + h.panel_off[j] + c + r; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
         t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;

@@ -22,7 +22,7 @@ struct Error {
 // One launch of the executor.
 enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdUpdateLow, kCmdPotrf, kCmdGemm,
-  kCmdPhilox, kCmdGramScale, kCmdEigInit, kCmdJacobiSmall, kCmdJacobiRound, kCmdEigSelect,
+  kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP,
   kCmdGemvN, kCmdColDot, kCmdTrsvBwd, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdConvertLow,
 };
@@ -54,10 +54,13 @@ struct DevArray {
 
 // Per-supernode storage of the compressed form and its work space (arena offsets).
 struct CompSlot {
-  int32_t ell = 0, npad = 0, nbk = 0;
-  int64_t omega = -1, ypanel = -1, ydinv = -1, V = -1, Gv = -1, Z = -1, rot = -1, zq = -1,
-          lam = -1, Vj = -1, Uj = -1, gscale = -1, escale = -1, tvq = -1, u = -1;
-  int32_t qslot = -1, flagslot = -1;
+  int32_t ell = 0;
+  int64_t omega = -1, ypanel = -1, ydinv = -1, V = -1, Vj = -1, Uj = -1, gscale = -1, tvq = -1,
+          u = -1;
+  // truncation work space (l x l blocks, panels with ld 2l)
+  int64_t G = -1, Sa = -1, Sb = -1, Mpan = -1, Mdinv = -1, Wpan = -1, Wdinv = -1, Om2 = -1,
+          sc = -1;
+  int32_t qslot = -1;
 };
 
 // A launch plan (command list + task arrays) for one factor mode.
@@ -70,7 +73,7 @@ struct FactorPlan {
   std::vector<UpdEntry> ents;
   std::vector<PotrfTask> potrf;
   std::vector<PhiloxTask> philox;
-  std::vector<EigTask> eig;
+  std::vector<TruncTask> trunc;
   std::vector<int64_t> gs_g, gs_out;
   std::vector<int32_t> gs_ld, gs_n;
   DevArray<GemmTask> d_gemm;
@@ -78,7 +81,7 @@ struct FactorPlan {
   DevArray<UpdEntry> d_ents;
   DevArray<PotrfTask> d_potrf;
   DevArray<PhiloxTask> d_philox;
-  DevArray<EigTask> d_eig;
+  DevArray<TruncTask> d_trunc;
   DevArray<int64_t> d_gs_g, d_gs_out;
   DevArray<int32_t> d_gs_ld, d_gs_n;
   hipGraphExec_t graph = nullptr;

@@ -9,12 +9,13 @@ namespace rsc {
 
 constexpr int kTile = 64;      // output tile edge of the MFMA kernels and POTRF block size
 
-// C(i,j) = beta C(i,j) + alpha sum_k A(i,k) B(j,k) on one 64x64 output tile.
+// C(i,j) = beta D(i,j) + alpha sum_k A(i,k) B(j,k) on one 64x64 output tile.
 // A(i,k) = arena[a + i*ais + k*aks], B(j,k) = arena[b + j*bjs + k*bks],
 // C(i,j) = arena[c + i + j*ldc].  nlim / klim >= 0 name int-arena slots holding a
 // device-side limit on n / k (ranks known only on the device).
 struct GemmTask {
   int64_t a, b, c;
+  int64_t d;                   // beta term from D(i,j) = arena[d + i + j*ldc] (d < 0: from C)
   int32_t ais, aks, bjs, bks;
   int32_t ldc;
   int32_t m, n, k;
@@ -60,22 +61,16 @@ struct PhiloxTask {
   int64_t out;
   int32_t rows, cols;
   uint32_t k0, k1;
+  uint32_t c2, pad_;           // third counter word: 0 for the range-finder sample
 };
 
-// Per-problem description of a symmetric eigenproblem (Jacobi) of order n <= npad.
-struct EigTask {
-  int64_t g;                   // npad x npad symmetric matrix (ld npad), destroyed
-  int64_t z;                   // npad x npad eigenvectors (ld npad)
-  int64_t rot;                 // scratch: (npad/64) ... rotation blocks (64x64 each, per pair)
-  int64_t zq;                  // output: n x n selected eigenvectors (ld n), descending
-  int64_t lam;                 // output: n eigenvalues, descending
-  int64_t scale;               // arena offset of the largest diagonal entry of the input
-  int32_t n, npad;
-  int32_t nbk;                 // number of 32-wide blocks (npad / 32)
-  int32_t qslot;               // int-arena slot receiving the kept rank
-  double tol;                  // relative singular-value cut-off
-  int32_t flagslot;            // int-arena slots [flagslot, flagslot + nbk/2): pair skip flags
-  int32_t pad_;
+// One spectral truncation problem (order l): Gram g (l x l), two l x l work
+// matrices sa / sb, the Cholesky panel mpan ([G + theta I; I], ld 2l), the basis panel
+// wpan ([Gram; sample], ld 2l), scalars sc[0..7], kept rank into ints[qslot].
+struct TruncTask {
+  int64_t g, sa, sb, mpan, wpan, sc;
+  int32_t l, qslot;
+  double tol;
 };
 
 // Pair operand of the forward sweep: part[out + t] = sum_m X(t, m) v[m], t < rows.
