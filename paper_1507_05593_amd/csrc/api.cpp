@@ -229,7 +229,8 @@ rsc_status rsc_get_block(rsc_handle H, int64_t j, double* LD, double* LO, double
   if (LO && r > 0 && c > 0) {
     if (comp) {
       std::memset(LO, 0, sizeof(double) * r * c);
-    } else if (hipMemcpy2D(LO, r * 8, P + c, ld * 8, r * 8, c, hipMemcpyDeviceToHost) != hipSuccess) {
+    } else if (hipMemcpy(LO, h.arena.p + h.a_lo + h.lo_off[j], sizeof(double) * r * c,
+                         hipMemcpyDeviceToHost) != hipSuccess) {
       return fail(RSC_ERR_DEVICE, "copy LO");
     }
   }

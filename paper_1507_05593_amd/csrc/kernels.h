@@ -28,6 +28,8 @@ void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_p(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
+void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
+                        double* dst, hipStream_t s);
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
                    const int32_t* ilim, hipStream_t s);
 void launch_trsv_bwd(const RowTask* t, int n, double* arena, hipStream_t s);
@@ -58,4 +60,19 @@ void launch_grad_values(int64_t n, const int64_t* rowptr, const int32_t* colind,
 void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const double* lam,
                        const double* x, double* g, hipStream_t s);
 
+}  // namespace rsc
+
+namespace rsc {
+// mode: 1 = FP32 operands, 2 = BF16 hi/lo split (three products), 3 = plain BF16
+void launch_gemm_lp(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
+void launch_update_lp(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
+                      double* arena, const int32_t* ilim, hipStream_t s);
+}  // namespace rsc
+
+namespace rsc {
+// LDS-staged MFMA kernels; mode 0 = FP64, 1 = FP32 operands, 2 = BF16 hi/lo split, 3 = BF16
+void launch_gemm_staged(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
+                        hipStream_t s);
+void launch_update_staged(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
+                          double* arena, const int32_t* ilim, hipStream_t s);
 }  // namespace rsc

@@ -244,12 +244,16 @@ __global__ __launch_bounds__(256) void k_update_f64(const UpdTile* __restrict__ 
 // mode 0: a pivot that is not positive and finite records the supernode in
 //         status[0] (smallest id wins) and is replaced by 1 so the sweep stays finite.
 // mode 1 (orthonormalisation): a pivot <= 1e-14 * scale marks the column dependent:
-//         its L column and its row of the inverse become zero.
+//         its L column and its row and column of the inverse become zero.
+// Right-looking with 256 threads: every thread reads the pivot itself, a 16 x 16
+// thread grid updates the trailing lower triangle; the inverse is formed row by row
+// with four threads per column splitting each dot product.
 __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
   __shared__ double L[64][65];
   __shared__ double W[64][65];
+  __shared__ double part[4][64];
   __shared__ int32_t drop[64];
   const PotrfTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x;
@@ -259,61 +263,61 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int r = idx & 63, c = idx >> 6;
     L[r][c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
+    W[r][c] = 0.0;
   }
   if (tid < 64) drop[tid] = 0;
-  __shared__ double dscale;
-  if (tid == 0) dscale = (T.mode == 1) ? arena[T.scale_off] : 0.0;
+  const double dscale = (T.mode == 1) ? arena[T.scale_off] : 0.0;
+  const int tx = tid & 15, ty = tid >> 4;
   __syncthreads();
   for (int k = 0; k < nb; ++k) {
-    if (tid == 0) {
-      double d = L[k][k];
-      if (T.mode == 0) {
-        if (!(d > 0.0) || !isfinite(d)) {
-          atomicMin(&status[0], T.sn);
-          d = 1.0;
-        }
-        L[k][k] = sqrt(d);
-      } else {
-        if (!(d > 1e-14 * dscale) || !isfinite(d)) {
-          drop[k] = 1;
-          L[k][k] = 1.0;
-        } else {
-          L[k][k] = sqrt(d);
-        }
+    double d = L[k][k];
+    bool dk = false;
+    if (T.mode == 0) {
+      if (!(d > 0.0) || !isfinite(d)) {
+        if (tid == 0) atomicMin(&status[0], T.sn);
+        d = 1.0;
       }
+    } else if (!(d > 1e-14 * dscale) || !isfinite(d)) {
+      dk = true;
+      d = 1.0;
     }
-    __syncthreads();
-    const double piv = L[k][k];
-    const bool dk = drop[k] != 0;
+    const double piv = sqrt(d);
+    __syncthreads();                       // everyone has read L[k][k]
+    if (tid == 0) { L[k][k] = piv; drop[k] = dk ? 1 : 0; }
     for (int i = k + 1 + tid; i < nb; i += 256) L[i][k] = dk ? 0.0 : L[i][k] / piv;
     __syncthreads();
-    const int m = nb - k - 1;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i >= j) L[i][j] -= L[i][k] * L[j][k];
+    for (int i = k + 1 + ty; i < nb; i += 16) {
+      const double lik = L[i][k];
+      for (int j = k + 1 + tx; j <= i; j += 16) L[i][j] -= lik * L[j][k];
     }
     __syncthreads();
   }
-  // write L back (lower triangle incl. diagonal; dropped columns hold 0 below a unit diagonal)
-  for (int idx = tid; idx < nb * nb; idx += 256) {
-    const int r = idx % nb, c = idx / nb;
-    if (r >= c) P[base + r + (int64_t)c * T.ld] = L[r][c];
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = L[r][c];
   }
-  // explicit inverse, one column per thread (forward substitution)
-  if (tid < 64) {
-    const int t = tid;
-    for (int i = 0; i < 64; ++i) W[i][t] = 0.0;
-    if (t < nb && !drop[t]) {
-      W[t][t] = 1.0 / L[t][t];
-      for (int i = t + 1; i < nb; ++i) {
-        if (drop[i]) continue;
-        double s = 0.0;
-        for (int q = t; q < i; ++q) s += L[i][q] * W[q][t];
-        W[i][t] = -s / L[i][i];
-      }
+  // W = L^{-1}, row i from rows < i: W[i][t] = (delta_it - sum_{q=t}^{i-1} L[i][q] W[q][t]) / L[i][i];
+  // a dropped index has a zero row and a zero column
+  const int t = tid & 63, g = tid >> 6;
+  for (int i = 0; i < nb; ++i) {
+    double acc = 0.0;
+    if (t < i) {
+      const int span = i - t, per = (span + 3) >> 2;
+      const int q0 = t + g * per, q1 = min(i, q0 + per);
+      for (int q = q0; q < q1; ++q) acc += L[i][q] * W[q][t];
     }
+    part[g][t] = acc;
+    __syncthreads();
+    if (g == 0 && t <= i) {
+      const double sacc = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+      double v;
+      if (drop[i] || drop[t]) v = 0.0;
+      else if (t == i) v = 1.0 / L[i][i];
+      else v = -sacc / L[i][i];
+      W[i][t] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   double* inv = arena + T.inv;
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int r = idx & 63, c = idx >> 6;

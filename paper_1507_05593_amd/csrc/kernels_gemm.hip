@@ -1,0 +1,302 @@
+// LDS-staged MFMA tile GEMM for gfx950 (all precisions).
+//
+// One 64x64 output tile per 256-thread workgroup (wave w owns the 32x32 quarter
+// (w / 2, w % 2) as 2x2 MFMA blocks).  K advances in chunks of 32: the A and B chunks
+// (64 x 32 each) are read from the FP64 arena with coalesced loads whatever their
+// layout (the contiguous dimension is mapped to consecutive threads), converted once
+// to the matrix-core type and written to LDS; the next chunk's global loads are issued
+// into registers before the current chunk's MFMAs.
+//   kF64:    v_mfma_f64_16x16x4f64          (LDS tiles [k][i], FP64)
+//   kF32:    v_mfma_f32_16x16x4f32          (LDS tiles [k][i], FP32)
+//   kBF16x3: v_mfma_f32_16x16x32_bf16 x 3   (LDS tiles [i][k], hi and lo parts)
+//   kBF16:   v_mfma_f32_16x16x32_bf16       (LDS tiles [i][k], hi part)
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+#include "tasks.h"
+
+namespace rsc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+enum StMode { sF64 = 0, sF32 = 1, sBF16x3 = 2, sBF16 = 3 };
+
+constexpr int KC = 32;          // K chunk
+constexpr int PADF = 68;        // row pitch (elements) of [k][i] FP64/FP32 tiles
+constexpr int PADB = 40;        // row pitch (bf16) of [i][k] tiles: 80 bytes, 16-byte aligned
+
+template <int MODE> struct Stage;
+
+template <> struct Stage<sF64> {
+  double a[KC][PADF], b[KC][PADF];
+  __device__ void put_a(int i, int k, double v) { a[k][i] = v; }
+  __device__ void put_b(int j, int k, double v) { b[k][j] = v; }
+};
+template <> struct Stage<sF32> {
+  float a[KC][PADF], b[KC][PADF];
+  __device__ void put_a(int i, int k, double v) { a[k][i] = (float)v; }
+  __device__ void put_b(int j, int k, double v) { b[k][j] = (float)v; }
+};
+template <> struct Stage<sBF16x3> {
+  __bf16 ah[64][PADB], al[64][PADB], bh[64][PADB], bl[64][PADB];
+  __device__ void put_a(int i, int k, double v) {
+    const float f = (float)v; const __bf16 h = (__bf16)f;
+    ah[i][k] = h; al[i][k] = (__bf16)(f - (float)h);
+  }
+  __device__ void put_b(int j, int k, double v) {
+    const float f = (float)v; const __bf16 h = (__bf16)f;
+    bh[j][k] = h; bl[j][k] = (__bf16)(f - (float)h);
+  }
+};
+template <> struct Stage<sBF16> {
+  __bf16 ah[64][PADB], bh[64][PADB];
+  __device__ void put_a(int i, int k, double v) { ah[i][k] = (__bf16)(float)v; }
+  __device__ void put_b(int j, int k, double v) { bh[j][k] = (__bf16)(float)v; }
+};
+
+template <int MODE> struct Acc { typedef v4f T; };
+template <> struct Acc<sF64> { typedef v4d T; };
+
+// Global loads of one 64 x 32 operand chunk (8 values per thread), coalesced along the
+// operand's contiguous dimension.  Element (r, k) is at base + r * rs + k * ks, valid
+// for r < rmax, k < kmax.
+struct ChunkLoader {
+  double v[8];
+  __device__ void load(const double* base, int64_t rs, int64_t ks, int rmax, int kmax, int k0,
+                       bool rcont) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int r, k;
+      if (rcont) { r = t & 63; k = (t >> 6) + 4 * u; }
+      else       { k = t & 31; r = (t >> 5) + 8 * u; }
+      const int kk = k0 + k;
+      v[u] = (r < rmax && kk < kmax) ? base[r * rs + (int64_t)kk * ks] : 0.0;
+    }
+  }
+  template <class S>
+  __device__ void store_a(S& st, bool rcont) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int r, k;
+      if (rcont) { r = t & 63; k = (t >> 6) + 4 * u; }
+      else       { k = t & 31; r = (t >> 5) + 8 * u; }
+      st.put_a(r, k, v[u]);
+    }
+  }
+  template <class S>
+  __device__ void store_b(S& st, bool rcont) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int r, k;
+      if (rcont) { r = t & 63; k = (t >> 6) + 4 * u; }
+      else       { k = t & 31; r = (t >> 5) + 8 * u; }
+      st.put_b(r, k, v[u]);
+    }
+  }
+};
+
+template <int MODE>
+__device__ __forceinline__ void mma_chunk(Stage<MODE>& st, typename Acc<MODE>::T (&acc)[2][2],
+                                          int wr, int wc, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  if constexpr (MODE == sF64 || MODE == sF32) {
+#pragma unroll
+    for (int ks = 0; ks < KC; ks += 4) {
+      if constexpr (MODE == sF64) {
+        double av[2], bv[2];
+        for (int b = 0; b < 2; ++b) {
+          av[b] = st.a[ks + lk][wr * 32 + b * 16 + li];
+          bv[b] = st.b[ks + lk][wc * 32 + b * 16 + li];
+        }
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+      } else {
+        float av[2], bv[2];
+        for (int b = 0; b < 2; ++b) {
+          av[b] = st.a[ks + lk][wr * 32 + b * 16 + li];
+          bv[b] = st.b[ks + lk][wc * 32 + b * 16 + li];
+        }
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+      }
+    }
+  } else {
+    v8bf ah[2], bh[2];
+    for (int b = 0; b < 2; ++b) {
+      ah[b] = *reinterpret_cast<const v8bf*>(&st.ah[wr * 32 + b * 16 + li][8 * lk]);
+      bh[b] = *reinterpret_cast<const v8bf*>(&st.bh[wc * 32 + b * 16 + li][8 * lk]);
+    }
+    if constexpr (MODE == sBF16x3) {
+      v8bf al[2], bl[2];
+      for (int b = 0; b < 2; ++b) {
+        al[b] = *reinterpret_cast<const v8bf*>(&st.al[wr * 32 + b * 16 + li][8 * lk]);
+        bl[b] = *reinterpret_cast<const v8bf*>(&st.bl[wc * 32 + b * 16 + li][8 * lk]);
+      }
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+        }
+    } else {
+      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+    }
+  }
+}
+
+// Result element (i, j) of block (x, y) held by this lane as element e.
+template <int MODE>
+__device__ __forceinline__ void res_pos(int lane, int e, int& i, int& j) {
+  if constexpr (MODE == sF64) i = (lane >> 4) + 4 * e;    // f64: row lane/16 + 4e
+  else i = 4 * (lane >> 4) + e;                           // f32 accumulators: row 4 (lane/16) + e
+  j = lane & 15;
+}
+
+// Accumulates P = A(r0.., :) B(c0.., :)^T for the workgroup's 64x64 tile over k < K.
+template <int MODE>
+__device__ void tile_product(Stage<MODE>& st, typename Acc<MODE>::T (&acc)[2][2],
+                             const double* A, int64_t ars, int64_t aks, int amax,
+                             const double* B, int64_t brs, int64_t bks, int bmax, int K) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const bool acont = (ars == 1), bcont = (brs == 1);
+  ChunkLoader la, lb;
+  if (K > 0) {
+    la.load(A, ars, aks, amax, K, 0, acont);
+    lb.load(B, brs, bks, bmax, K, 0, bcont);
+  }
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();                       // previous chunk's MFMAs done with the LDS tiles
+    la.store_a(st, acont);
+    lb.store_b(st, bcont);
+    __syncthreads();
+    if (k0 + KC < K) {                     // next chunk in flight during the MFMAs
+      la.load(A, ars, aks, amax, K, k0 + KC, acont);
+      lb.load(B, brs, bks, bmax, K, k0 + KC, bcont);
+    }
+    mma_chunk<MODE>(st, acc, wr, wc, lane);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_staged(const GemmTask* __restrict__ tasks,
+                                                     double* __restrict__ arena,
+                                                     const int32_t* __restrict__ ilim) {
+  __shared__ Stage<MODE> st;
+  const GemmTask T = tasks[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int n = T.nlim >= 0 ? min(T.n, ilim[T.nlim]) : T.n;
+  const int K = T.klim >= 0 ? min(T.k, ilim[T.klim]) : T.k;
+  if (T.j0 >= n) return;
+  typename Acc<MODE>::T acc[2][2];
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      for (int e = 0; e < 4; ++e) acc[x][y][e] = 0;
+  const double* A = arena + T.a + (int64_t)T.i0 * T.ais;
+  const double* B = arena + T.b + (int64_t)T.j0 * T.bjs;
+  tile_product<MODE>(st, acc, A, T.ais, T.aks, T.m - T.i0, B, T.bjs, T.bks, n - T.j0, K);
+  __syncthreads();                         // A/B may alias C (in-place triangular solve)
+  double* C = arena + T.c;
+  for (int x = 0; x < 2; ++x)
+    for (int y = 0; y < 2; ++y)
+      for (int e = 0; e < 4; ++e) {
+        int ii, jj;
+        res_pos<MODE>(lane, e, ii, jj);
+        const int i = T.i0 + wr * 32 + x * 16 + ii;
+        const int j = T.j0 + wc * 32 + y * 16 + jj;
+        if (i < T.m && j < n) {
+          double* cp = C + i + (int64_t)j * T.ldc;
+          const double v = T.alpha * (double)acc[x][y][e];
+          const double* dp = (T.d >= 0) ? arena + T.d + i + (int64_t)j * T.ldc : cp;
+          *cp = (T.beta == 0.0) ? v : v + T.beta * *dp;
+        }
+      }
+}
+
+// Schur-complement update tile: the same staged product on gathered row runs of X,
+// scattered into the LDS-resident target tile (contract as in k_update_f64).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_update_staged(const UpdTile* __restrict__ tiles,
+                                                       const UpdEntry* __restrict__ ents,
+                                                       const int32_t* __restrict__ relmap,
+                                                       double* __restrict__ arena,
+                                                       const int32_t* __restrict__ ilim) {
+  __shared__ Stage<MODE> st;
+  __shared__ double tile[64][65];
+  __shared__ int32_t rmap[64], cmap[64];
+  const UpdTile T = tiles[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  double* P = arena + T.panel;
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    tile[r][c] = (r < T.nrows && c < T.ncols) ? P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] : 0.0;
+  }
+  for (int e = T.e0; e < T.e1; ++e) {
+    const UpdEntry E = ents[e];
+    const int nr = E.b - E.a, nc = E.d - E.c;
+    const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
+    if (tid < 64) {
+      rmap[tid] = tid < nr ? relmap[E.map + E.a + tid] - T.row0 : 0;
+    } else if (tid < 128) {
+      const int t = tid - 64;
+      cmap[t] = t < nc ? relmap[E.map + E.c + t] - T.col0 : 0;
+    }
+    typename Acc<MODE>::T acc[2][2];
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y)
+        for (int q = 0; q < 4; ++q) acc[x][y][q] = 0;
+    const double* X = arena + E.x;
+    tile_product<MODE>(st, acc, X + E.a, 1, E.ldx, nr, X + E.c, 1, E.ldx, nc, K);
+    __syncthreads();                       // maps visible; staged tiles no longer needed
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y)
+        for (int q = 0; q < 4; ++q) {
+          int ii, jj;
+          res_pos<MODE>(lane, q, ii, jj);
+          const int pr = wr * 32 + x * 16 + ii;
+          const int pc = wc * 32 + y * 16 + jj;
+          if (pr < nr && pc < nc) tile[rmap[pr]][cmap[pc]] -= (double)acc[x][y][q];
+        }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < 64 * 64; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    if (r < T.nrows && c < T.ncols) P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] = tile[r][c];
+  }
+}
+
+void launch_gemm_staged(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  switch (mode) {
+    case sF64: hipLaunchKernelGGL(k_gemm_staged<sF64>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
+    case sF32: hipLaunchKernelGGL(k_gemm_staged<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
+    case sBF16x3: hipLaunchKernelGGL(k_gemm_staged<sBF16x3>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
+    default: hipLaunchKernelGGL(k_gemm_staged<sBF16>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
+  }
+}
+
+void launch_update_staged(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
+                          double* arena, const int32_t* ilim, hipStream_t s) {
+  if (n <= 0) return;
+  switch (mode) {
+    case sF64: hipLaunchKernelGGL(k_update_staged<sF64>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim); break;
+    case sF32: hipLaunchKernelGGL(k_update_staged<sF32>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim); break;
+    default: hipLaunchKernelGGL(k_update_staged<sBF16x3>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim); break;
+  }
+}
+
+}  // namespace rsc

@@ -31,19 +31,36 @@ __device__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- sweeps
 
-// out[t] = sum_{m < K} X(t, m) v[m], one thread per row t (coalesced column reads).
+// out[t] = sum_{m < K} X(t, m) v[m] for up to 64 rows: lane = row (coalesced column
+// reads), the 4 waves split the inner dimension and their partial sums are added in
+// a fixed order.
 __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tasks,
                                                 double* __restrict__ arena,
                                                 const int32_t* __restrict__ ilim) {
+  __shared__ double part[4][64];
   const GemvTask T = tasks[blockIdx.x];
-  const int t = threadIdx.x;
-  if (t >= T.rows) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int K = T.kdim >= 0 ? T.kdim : ilim[-1 - T.kdim];
-  const double* X = arena + T.x + t;
-  const double* v = arena + T.v;
   double acc = 0.0;
-  for (int m = 0; m < K; ++m) acc += X[(int64_t)m * T.ldx] * v[m];
-  arena[T.out + t] = acc;
+  if (lane < T.rows) {
+    const int per = (K + 3) / 4;
+    const int m0 = w * per, m1 = min(K, m0 + per);
+    const double* X = arena + T.x + lane;
+    const double* v = arena + T.v;
+    for (int m = m0; m < m1; ++m) acc += X[(int64_t)m * T.ldx] * v[m];
+  }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && lane < T.rows)
+    arena[T.out + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// dst[begin + t] = src[idx[begin + t]] for t < count: the off-diagonal rows of one
+// supernode gathered once per sweep into a contiguous vector.
+__global__ void k_gather_rows(const int64_t* __restrict__ tasks, const int64_t* __restrict__ idx,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const int64_t b = tasks[2 * blockIdx.x], n = tasks[2 * blockIdx.x + 1];
+  for (int64_t t = threadIdx.x; t < n; t += 256) dst[b + t] = src[idx[b + t]];
 }
 
 // One wave per output column: lanes stride the rows, then a wave reduction.
@@ -327,6 +344,10 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gemv_n, dim3(n), dim3(256), 0, s, t, arena, ilim);
+}
+void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
+                        double* dst, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_rows, dim3(n), dim3(256), 0, s, tasks, idx, src, dst);
 }
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
                    const int32_t* ilim, hipStream_t s) {

@@ -67,6 +67,10 @@ void plan_layout(Handle& h) {
   h.a_values = a; a += align64(nnz);
   h.a_panels = a; a += poff;
   h.a_dinv = a; a += doff;
+  h.lo_off.assign(M, 0);
+  int64_t loff = 0;
+  for (int64_t j = 0; j < M; ++j) { h.lo_off[j] = loff; loff += align64((int64_t)S.c(j) * S.r(j)); }
+  h.a_lo = a; a += loff;
   h.a_x = a; a += align64(n);
   h.a_r = a; a += align64(n);
   h.a_z = a; a += align64(n);
@@ -77,6 +81,7 @@ void plan_layout(Handle& h) {
   h.a_s = a; a += align64(n);
   h.a_zz = a; a += align64(n);
   h.a_b = a; a += align64(n);
+  h.a_zr = a; a += align64(std::max<int64_t>((int64_t)S.rows.size(), 1));
   // forward-sweep partials: one per gathered diagonal row of every pair
   h.part_off.assign(S.pairs.size(), 0);
   int64_t pt = 0;
@@ -222,13 +227,15 @@ Error ensure_device(Handle& h) {
 
 void release_device(Handle& h) {
   if (h.dev_ready) (void)hipDeviceSynchronize();
-  if (h.fplan && h.fplan->graph) (void)hipGraphExecDestroy(h.fplan->graph);
+  for (auto& fp : h.fplans)
+    if (fp && fp->graph) (void)hipGraphExecDestroy(fp->graph);
   if (h.splan) {
     if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
     if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
     if (h.splan->graph_apply) (void)hipGraphExecDestroy(h.splan->graph_apply);
   }
-  h.fplan.reset();
+  for (auto& fp : h.fplans) fp.reset();
+  h.fplan = nullptr;
   h.splan.reset();
   if (h.cap_stream) (void)hipStreamDestroy(h.cap_stream);
   h.cap_stream = nullptr;
@@ -246,12 +253,19 @@ struct PanelDesc {
   int64_t dinv;
   int32_t sn, mode;
   int64_t scale_off;
+  int32_t lp_lo = 0, lp_hi = 0;   // rows [lp_lo, lp_hi) use the low-precision products
+  bool skip_mid = false;          // ... or are not touched at all
 };
 
 struct Builder {
   Handle& h;
   FactorPlan& P;
-  Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {}
+  int32_t lp_update = 0;   // 0: FP64 MFMA; else the low-precision mode of launch_gemm_lp
+  int32_t lp_sample = 0;
+  Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {
+    if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; }
+    if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; }
+  }
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
            int64_t b = 0, double v = 0) {
@@ -262,14 +276,16 @@ struct Builder {
     P.cmds.push_back(c);
   }
 
-  // Tiles of C(i, j) for i in [ib, m), j in [jb, n); lower: skip tiles with i0 < j0.
-  double tiles(GemmTask t, int32_t ib, int32_t jb, bool lower) {
+  // Tiles of C(i, j) for i in [ib, m), j in [jb, n); lower: skip tiles lying strictly
+  // above the diagonal.
+  double tiles(GemmTask t, int32_t ib, int32_t jb, bool lower, std::vector<GemmTask>* out = nullptr) {
     double fl = 0;
+    std::vector<GemmTask>& dst = out ? *out : P.gemm;
     for (int32_t j0 = jb; j0 < t.n; j0 += kTile)
       for (int32_t i0 = ib; i0 < t.m; i0 += kTile) {
-        if (lower && i0 < j0) continue;
+        if (lower && i0 + kTile - 1 < j0) continue;
         t.i0 = i0; t.j0 = j0;
-        P.gemm.push_back(t);
+        dst.push_back(t);
         fl += 2.0 * std::min(kTile, t.m - i0) * std::min(kTile, t.n - j0) * (double)t.k;
       }
     return fl;
@@ -303,30 +319,68 @@ struct Builder {
         fl += std::pow((double)t.nb, 3) / 3.0;
       }
       cmd(kCmdPotrf, RSC_K_POTRF, p0, (int64_t)P.potrf.size() - p0, fl);
-      int64_t g0 = (int64_t)P.gemm.size();
-      fl = 0;
-      for (auto& p : pan) {
-        if (p.n <= d0) continue;
-        const int32_t nb = std::min(kTile, p.n - d0);
-        const int32_t R1 = p.n + p.m_below + (p.ident ? std::min(p.n, d0 + nb) : 0);
-        const int64_t colb = p.off + (int64_t)d0 * p.ld;
-        GemmTask t = gt(colb, 1, p.ld, p.dinv + (int64_t)(d0 / kTile) * 4096, 1, kTile, colb, p.ld,
-                        R1, nb, nb, 1.0, 0.0);
-        fl += tiles(t, d0 + nb, 0, false);
+      // rows below the diagonal block times its inverse, then the trailing update;
+      // rows inside [lp_lo, lp_hi) go to the low-precision launch
+      for (int phase = 0; phase < 2; ++phase) {
+        std::vector<GemmTask> hi_t, lo_t;
+        double fh = 0, flo = 0;
+        for (auto& p : pan) {
+          if (p.n <= d0) continue;
+          const int32_t nb = std::min(kTile, p.n - d0);
+          if (phase == 1 && p.n <= d0 + nb) continue;
+          const int32_t R0 = d0 + nb;
+          const int32_t R1 = p.n + p.m_below + (p.ident ? std::min(p.n, d0 + nb) : 0);
+          const int64_t colb = p.off + (int64_t)d0 * p.ld;
+          GemmTask t = (phase == 0)
+              ? gt(colb, 1, p.ld, p.dinv + (int64_t)(d0 / kTile) * 4096, 1, kTile, colb, p.ld, R1, nb, nb, 1.0, 0.0)
+              : gt(colb, 1, p.ld, colb, 1, p.ld, p.off, p.ld, R1, p.n, nb, -1.0, 1.0);
+          const int32_t jb = (phase == 0) ? 0 : d0 + nb;
+          const bool lower = (phase == 1);
+          const bool use_lp = (lp_update || p.skip_mid) && p.lp_hi > p.lp_lo;
+          // segments [R0, lp_lo), [lp_lo, lp_hi), [lp_hi, R1)
+          int32_t cuts[4] = {R0, use_lp ? std::max(R0, p.lp_lo) : R1, use_lp ? std::max(R0, p.lp_hi) : R1, R1};
+          for (int sgm = 0; sgm < 3; ++sgm) {
+            const int32_t lo = cuts[sgm], hi = std::min(cuts[sgm + 1], R1);
+            if (hi <= lo) continue;
+            GemmTask ts = t;
+            ts.m = hi;
+            if (sgm == 1 && p.skip_mid) continue;
+            if (sgm == 1) flo += tiles(ts, lo, jb, lower, &lo_t);
+            else fh += tiles(ts, lo, jb, lower, &hi_t);
+          }
+        }
+        const int klass = phase == 0 ? RSC_K_TRSM : RSC_K_GEMM;
+        int64_t g0 = (int64_t)P.gemm.size();
+        P.gemm.insert(P.gemm.end(), hi_t.begin(), hi_t.end());
+        cmd(kCmdGemm, klass, g0, (int64_t)hi_t.size(), fh, 0);
+        g0 = (int64_t)P.gemm.size();
+        P.gemm.insert(P.gemm.end(), lo_t.begin(), lo_t.end());
+        cmd(kCmdGemm, klass, g0, (int64_t)lo_t.size(), flo, lp_update);
       }
-      cmd(kCmdGemm, RSC_K_TRSM, g0, (int64_t)P.gemm.size() - g0, fl);
-      g0 = (int64_t)P.gemm.size();
-      fl = 0;
-      for (auto& p : pan) {
-        const int32_t nb = std::min(kTile, p.n - d0);
-        if (p.n <= d0 + nb) continue;
-        const int32_t R1 = p.n + p.m_below + (p.ident ? std::min(p.n, d0 + nb) : 0);
-        const int64_t colb = p.off + (int64_t)d0 * p.ld;
-        GemmTask t = gt(colb, 1, p.ld, colb, 1, p.ld, p.off, p.ld, R1, p.n, nb, -1.0, 1.0);
-        fl += tiles(t, d0 + nb, d0 + nb, true);
-      }
-      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     }
+  }
+
+  // L^O_j = U^O_j (L^D_j)^{-T} = U^O_j M_j with the upper-triangular M_j = (L^D_j)^{-T}
+  // that the panel factorisation left in the panel's last c rows; column block j0 of
+  // the product only needs rows k < j0 + 64 of M.  Written to the L^O buffer.
+  void offdiag_solve(const std::vector<int32_t>& level) {
+    const Symbolic& S = h.S;
+    const int64_t g0 = (int64_t)P.gemm.size();
+    double fl = 0;
+    for (int32_t j : level) {
+      const int32_t c = S.c(j), r = S.r(j), ld = h.panel_ld[j];
+      if (r == 0) continue;
+      const int64_t pan = h.a_panels + h.panel_off[j];
+      GemmTask t = gt(pan + c, 1, ld, pan + c + r, ld, 1, h.a_lo + h.lo_off[j], r, r, c, c, 1.0, 0.0);
+      for (int32_t j0 = 0; j0 < c; j0 += kTile)
+        for (int32_t i0 = 0; i0 < r; i0 += kTile) {
+          GemmTask u = t;
+          u.i0 = i0; u.j0 = j0; u.k = std::min(c, j0 + kTile);
+          P.gemm.push_back(u);
+          fl += 2.0 * std::min(kTile, r - i0) * std::min(kTile, c - j0) * (double)u.k;
+        }
+    }
+    cmd(kCmdGemm, RSC_K_TRSM, g0, (int64_t)P.gemm.size() - g0, fl, lp_update);
   }
 
   // Schur-complement updates of every supernode of one level (Algorithm 1, the
@@ -352,8 +406,8 @@ struct Builder {
           base.kdim = -(1 + C.qslot);
           kest = C.ell;
         } else {
-          base.x = h.a_panels + h.panel_off[k] + S.c(k) + pr.p0;
-          base.ldx = h.panel_ld[k];
+          base.x = h.a_lo + h.lo_off[k] + pr.p0;
+          base.ldx = S.r(k);
           base.kdim = S.c(k);
           kest = S.c(k);
         }
@@ -412,7 +466,7 @@ struct Builder {
       P.tiles.push_back(tw.t);
       fl += tw.work;
     }
-    cmd(kCmdUpdate, RSC_K_UPDATE, t0, (int64_t)P.tiles.size() - t0, fl);
+    cmd(kCmdUpdate, RSC_K_UPDATE, t0, (int64_t)P.tiles.size() - t0, fl, lp_update);
   }
 
   // Algorithm 3 on the explicit L^O_j of every compressible supernode of a level,
@@ -442,26 +496,26 @@ struct Builder {
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      const int64_t LO = h.a_panels + h.panel_off[j] + c;
-      fl += tiles(gt(LO, h.panel_ld[j], 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
+      const int64_t LO = h.a_lo + h.lo_off[j];
+      fl += tiles(gt(LO, r, 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
     }
-    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_sample);
     // 3. power iterations Y = (L^O)^T (L^O Y)
     for (int it = 0; it < h.opt.power_iters; ++it) {
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-        const int64_t LO = h.a_panels + h.panel_off[j] + c;
-        fl += tiles(gt(LO, 1, h.panel_ld[j], C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
+        const int64_t LO = h.a_lo + h.lo_off[j];
+        fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-        const int64_t LO = h.a_panels + h.panel_off[j] + c;
-        fl += tiles(gt(LO, h.panel_ld[j], 1, C.V, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
+        const int64_t LO = h.a_lo + h.lo_off[j];
+        fl += tiles(gt(LO, r, 1, C.V, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     }
@@ -486,8 +540,8 @@ struct Builder {
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      const int64_t LO = h.a_panels + h.panel_off[j] + c;
-      fl += tiles(gt(LO, 1, h.panel_ld[j], C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
+      const int64_t LO = h.a_lo + h.lo_off[j];
+      fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     // 6. Gram G = V^T V (full)
@@ -626,10 +680,11 @@ Error upload_plan(DevArray<T>& d, const std::vector<T>& v) { return upload(d, v)
 
 }  // namespace
 
-static Error build_factor_plan(Handle& h, bool compressed, double tol) {
+static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t precision) {
   auto P = std::make_unique<FactorPlan>();
   P->compressed = compressed;
-  P->precision = h.opt.precision;
+  P->precision = precision;
+  P->tol = tol;
   Builder B(h, *P);
   const Symbolic& S = h.S;
   int64_t panels_total = h.a_dinv - h.a_panels;
@@ -642,10 +697,16 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol) {
     const auto& lev = S.by_level[L];
     B.updates(lev);
     std::vector<PanelDesc> pan;
-    for (int32_t j : lev)
-      pan.push_back(PanelDesc{h.a_panels + h.panel_off[j], h.panel_ld[j], S.c(j), S.r(j), true,
-                              h.a_dinv + h.dinv_off[j], j, 0, 0});
+    for (int32_t j : lev) {
+      PanelDesc pd{h.a_panels + h.panel_off[j], h.panel_ld[j], S.c(j), S.r(j), true,
+                   h.a_dinv + h.dinv_off[j], j, 0, 0};
+      pd.lp_lo = S.c(j);                 // rows U^O_j: solved below by one product
+      pd.lp_hi = S.c(j) + S.r(j);
+      pd.skip_mid = true;
+      pan.push_back(pd);
+    }
     B.panel_steps(pan);
+    B.offdiag_solve(lev);
     if (compressed) B.compression(lev, tol);
   }
   // algorithmic flop counts of the method (per supernode, from the symbolic plan)
@@ -671,8 +732,9 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol) {
   if ((e = upload(P->d_gs_out, P->gs_out)).code) return e;
   if ((e = upload(P->d_gs_ld, P->gs_ld)).code) return e;
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
-  if (h.fplan && h.fplan->graph) (void)hipGraphExecDestroy(h.fplan->graph);
-  h.fplan = std::move(P);
+  auto& slot = h.fplans[precision];
+  if (slot && slot->graph) (void)hipGraphExecDestroy(slot->graph);
+  slot = std::move(P);
   return kOk;
 }
 
@@ -690,10 +752,10 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdAssemble: launch_assemble(A + h.a_values, h.d_asm_slot.p, c.count, A, s); break;
     case kCmdIdent: launch_scatter_const(h.d_ident_slot.p, c.count, 1.0, A, s); break;
     case kCmdUpdate:
-      launch_update_f64(P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A, I, s);
+      launch_update_staged((int)c.a, P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A, I, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
-    case kCmdGemm: launch_gemm_f64(P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdGemm: launch_gemm_staged((int)c.a, P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
     case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, 0, s); break;
     case kCmdGramScale:
       launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,
@@ -706,6 +768,9 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
     case kCmdTrsvBwd: launch_trsv_bwd(Q->d_rows.p + c.off, (int)c.count, A, s); break;
+    case kCmdGatherRows:
+      launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);
+      break;
     case kCmdRowGather:
       launch_row_gather(Q->d_rg_rows.p + c.off, Q->d_rg_ptr.p + c.a, Q->d_rg_contrib.p, c.count,
                         A + h.a_part, A + h.a_y, s);
@@ -767,23 +832,23 @@ static Error capture(Handle& h, const std::function<Error(hipStream_t)>& body, h
 
 // ------------------------------------------------------------------ factor
 
-Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
-  Error e = ensure_device(h);
-  if (e.code) return e;
+static Error factor_once(Handle& h, const double* values, double tol, int32_t precision,
+                         hipStream_t stream) {
+  Error e;
   const bool compressed = tol > 0.0;
-  if (!h.fplan || h.fplan->compressed != compressed || (compressed && h.tol != tol) ||
-      h.fplan->precision != h.opt.precision) {
-    if ((e = build_factor_plan(h, compressed, tol)).code) return e;
-    if (h.splan) {
-      if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
-      if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
-      if (h.splan->graph_apply) (void)hipGraphExecDestroy(h.splan->graph_apply);
-      h.splan.reset();
-    }
+  auto& slot = h.fplans[precision];
+  if (!slot || slot->compressed != compressed || (compressed && slot->tol != tol))
+    if ((e = build_factor_plan(h, compressed, tol, precision)).code) return e;
+  if (h.splan && h.splan->compressed != compressed) {
+    if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
+    if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
+    if (h.splan->graph_apply) (void)hipGraphExecDestroy(h.splan->graph_apply);
+    h.splan.reset();
   }
+  h.fplan = slot.get();
   h.factored = false;
   h.tol = tol;
-  FactorPlan* P = h.fplan.get();
+  FactorPlan* P = h.fplan;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -821,9 +886,28 @@ Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
     return Error{RSC_ERR_NOT_SPD, "non-positive pivot in supernode " + std::to_string(st[0])};
   }
   h.failed_supernode = -1;
-  h.precision_used = h.opt.precision;
+  h.precision_used = precision;
   h.factored = true;
   return kOk;
+}
+
+// The restart policy of Sec. 5.3 (raise the accuracy and refactor after an indefinite
+// pivot) applied to precision: mixed BF16 -> FP32 products -> FP64.
+Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
+  Error e = ensure_device(h);
+  if (e.code) return e;
+  std::vector<int32_t> ladder{h.opt.precision};
+  if (h.opt.retry) {
+    if (h.opt.precision == RSC_MIXED_BF16) ladder.push_back(RSC_MIXED_FP32);
+    if (h.opt.precision != RSC_FP64) ladder.push_back(RSC_FP64);
+  }
+  h.retries = 0;
+  for (size_t k = 0; k < ladder.size(); ++k) {
+    e = factor_once(h, values, tol, ladder[k], stream);
+    if (e.code != RSC_ERR_NOT_SPD || k + 1 == ladder.size()) return e;
+    h.retries++;
+  }
+  return e;
 }
 
 // ------------------------------------------------------------------ solve plan
@@ -851,16 +935,16 @@ static Error build_solve_plan(Handle& h) {
       for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
         const Pair& pr = S.pairs[q];
         const int32_t k = pr.k;
-        for (int32_t t0 = 0; t0 < pr.nD; t0 += 256) {
+        for (int32_t t0 = 0; t0 < pr.nD; t0 += 64) {
           GemvTask t{};
           if (iscomp(k)) {
             t.x = h.comp[k].Vj + pr.p0 + t0; t.ldx = S.r(k); t.kdim = -(1 + h.comp[k].qslot);
             t.v = h.comp[k].tvq;
           } else {
-            t.x = h.a_panels + h.panel_off[k] + S.c(k) + pr.p0 + t0; t.ldx = h.panel_ld[k];
+            t.x = h.a_lo + h.lo_off[k] + pr.p0 + t0; t.ldx = S.r(k);
             t.kdim = S.c(k); t.v = h.a_w + S.first[k];
           }
-          t.rows = std::min(256, pr.nD - t0);
+          t.rows = std::min(64, pr.nD - t0);
           t.out = h.a_part + h.part_off[q] + t0;
           Q->gemv.push_back(t);
         }
@@ -923,6 +1007,18 @@ static Error build_solve_plan(Handle& h) {
   // backward sweep, levels descending
   for (int32_t L = S.nlevels - 1; L >= 0; --L) {
     const auto& lev = S.by_level[L];
+    // b0: z over R_j gathered once per supernode into the contiguous buffer zr
+    {
+      const int64_t g0q = (int64_t)Q->gath.size() / 2;
+      for (int32_t j : lev)
+        if (S.r(j) > 0) { Q->gath.push_back(S.rows_ptr[j]); Q->gath.push_back(S.r(j)); }
+      const int64_t ng = (int64_t)Q->gath.size() / 2 - g0q;
+      if (ng > 0) {
+        Cmd c{};
+        c.type = kCmdGatherRows; c.klass = RSC_K_PCG; c.off = g0q; c.count = ng;
+        Q->fwd_bwd.push_back(c);
+      }
+    }
     // b1: s_C = (L^O_j)^T z_R (dense) or u = V_j^T z_R (compressed)
     int64_t c0 = (int64_t)Q->coldot.size();
     for (int32_t j : lev) {
@@ -932,15 +1028,15 @@ static Error build_solve_plan(Handle& h) {
         const CompSlot& C = h.comp[j];
         for (int32_t col0 = 0; col0 < C.ell; col0 += 16) {
           ColDotTask t{};
-          t.x = C.Vj; t.ldx = r; t.in = h.a_zz; t.idx = S.rows_ptr[j]; t.out = C.u;
+          t.x = C.Vj; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j]; t.idx = -1; t.out = C.u;
           t.rows = r; t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
           Q->coldot.push_back(t);
         }
       } else {
         for (int32_t col0 = 0; col0 < c; col0 += 16) {
           ColDotTask t{};
-          t.x = h.a_panels + h.panel_off[j] + c; t.ldx = h.panel_ld[j]; t.in = h.a_zz;
-          t.idx = S.rows_ptr[j]; t.out = h.a_s + S.first[j];
+          t.x = h.a_lo + h.lo_off[j]; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j];
+          t.idx = -1; t.out = h.a_s + S.first[j];
           t.rows = r; t.ncols = c; t.col0 = col0; t.tri = 0;
           Q->coldot.push_back(t);
         }
@@ -953,10 +1049,10 @@ static Error build_solve_plan(Handle& h) {
     for (int32_t j : lev) {
       if (!iscomp(j)) continue;
       const CompSlot& C = h.comp[j];
-      for (int32_t t0 = 0; t0 < S.c(j); t0 += 256) {
+      for (int32_t t0 = 0; t0 < S.c(j); t0 += 64) {
         GemvTask t{};
         t.x = C.Uj + t0; t.ldx = S.c(j); t.kdim = -(1 + C.qslot); t.v = C.u;
-        t.rows = std::min(256, S.c(j) - t0); t.out = h.a_s + S.first[j] + t0;
+        t.rows = std::min(64, S.c(j) - t0); t.out = h.a_s + S.first[j] + t0;
         Q->gemv.push_back(t);
       }
       bytes += 2.0 * 8.0 * (double)(S.c(j) + S.r(j)) * C.ell;
@@ -982,6 +1078,7 @@ static Error build_solve_plan(Handle& h) {
   if ((e = upload(Q->d_gemv, Q->gemv)).code) return e;
   if ((e = upload(Q->d_coldot, Q->coldot)).code) return e;
   if ((e = upload(Q->d_rows, Q->rows)).code) return e;
+  if ((e = upload(Q->d_gath, Q->gath)).code) return e;
   if ((e = upload(Q->d_rg_rows, Q->rg_rows)).code) return e;
   if ((e = upload(Q->d_rg_ptr, Q->rg_ptr)).code) return e;
   if ((e = upload(Q->d_rg_contrib, Q->rg_contrib)).code) return e;

@@ -24,7 +24,7 @@ enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdUpdateLow, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP,
   kCmdGemvN, kCmdColDot, kCmdTrsvBwd, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdConvertLow,
+  kCmdConvertLow, kCmdGatherRows,
 };
 
 struct Cmd {
@@ -67,6 +67,7 @@ struct CompSlot {
 struct FactorPlan {
   bool compressed = false;
   int32_t precision = RSC_FP64;
+  double tol = 0;
   std::vector<Cmd> cmds;
   std::vector<GemmTask> gemm;
   std::vector<UpdTile> tiles;
@@ -95,10 +96,11 @@ struct SolvePlan {
   std::vector<ColDotTask> coldot;
   std::vector<RowTask> rows;
   std::vector<int64_t> rg_rows, rg_ptr, rg_contrib;  // row-gather CSR (all levels)
+  std::vector<int64_t> gath;          // (begin, count) pairs of z gathers over R_j
   DevArray<GemvTask> d_gemv;
   DevArray<ColDotTask> d_coldot;
   DevArray<RowTask> d_rows;
-  DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib;
+  DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib, d_gath;
   hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
   double bytes = 0;                   // factor bytes read by one apply
   double v_rtol = -1;                 // rtol baked into graph_a
@@ -116,6 +118,7 @@ struct Handle {
   std::vector<int64_t> panel_off;
   std::vector<int32_t> panel_ld;
   std::vector<int64_t> dinv_off;
+  std::vector<int64_t> lo_off;        // L^O_j (r x c, ld r) in the L^O buffer
   std::vector<int64_t> asm_slot;      // per stored entry: arena slot or -1
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
@@ -135,14 +138,15 @@ struct Handle {
   DevArray<int32_t> d_seg_chunk_ptr;
   int32_t nchunks = 0;
   // arena regions
-  int64_t a_values = 0, a_panels = 0, a_dinv = 0;
-  int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_part, a_partial, a_seg;
+  int64_t a_values = 0, a_panels = 0, a_dinv = 0, a_lo = 0;
+  int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_zr, a_part, a_partial, a_seg;
   PcgScalars sc{};
   int32_t i_status = 0, i_ranks = 0;
   std::vector<CompSlot> comp;         // per supernode (compressible ones only)
   bool comp_ready = false;
 
-  std::unique_ptr<FactorPlan> fplan;
+  std::unique_ptr<FactorPlan> fplans[3];  // per precision
+  FactorPlan* fplan = nullptr;          // plan of the last factor
   std::unique_ptr<SolvePlan> splan;
   bool factored = false;
   double tol = 0;
