@@ -28,6 +28,8 @@ void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_p(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
+void launch_fwd_block(const FwdTile* t, int n, const FwdEntry* e, const int32_t* relmap,
+                      double* arena, const int32_t* ilim, hipStream_t s);
 void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
                         double* dst, hipStream_t s);
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,

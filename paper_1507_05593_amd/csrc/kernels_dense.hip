@@ -240,32 +240,40 @@ __global__ __launch_bounds__(256) void k_update_f64(const UpdTile* __restrict__ 
 
 // ---------------------------------------------------------------- diagonal block Cholesky
 
-// Cholesky of one (<= 64) diagonal block in LDS, then its explicit inverse.
+// Cholesky of one (<= 64) diagonal block in LDS together with its explicit inverse.
 // mode 0: a pivot that is not positive and finite records the supernode in
 //         status[0] (smallest id wins) and is replaced by 1 so the sweep stays finite.
 // mode 1 (orthonormalisation): a pivot <= 1e-14 * scale marks the column dependent:
 //         its L column and its row and column of the inverse become zero.
-// Right-looking with 256 threads: every thread reads the pivot itself, a 16 x 16
-// thread grid updates the trailing lower triangle; the inverse is formed row by row
-// with four threads per column splitting each dot product.
+// Right-looking elimination with 256 threads on a 16 x 16 grid; the inverse rides on
+// the same steps (W starts as I; step k scales row k of W by 1 / l_kk and subtracts
+// l_ik times it from the rows below), so there is no separate substitution phase.
+// Inner loops have fixed trip counts (masked) so that their LDS loads issue ahead.
 __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
   __shared__ double L[64][65];
   __shared__ double W[64][65];
-  __shared__ double part[4][64];
-  __shared__ int32_t drop[64];
+  __shared__ int32_t dropk;
   const PotrfTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x;
   const int nb = T.nb;
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    L[r][c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
-    W[r][c] = 0.0;
+  {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      v[u] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      L[r][c] = v[u];
+      W[r][c] = (r == c && r < nb) ? 1.0 : 0.0;
+    }
   }
-  if (tid < 64) drop[tid] = 0;
   const double dscale = (T.mode == 1) ? arena[T.scale_off] : 0.0;
   const int tx = tid & 15, ty = tid >> 4;
   __syncthreads();
@@ -282,46 +290,43 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
       d = 1.0;
     }
     const double piv = sqrt(d);
+    const double rp = 1.0 / piv;
     __syncthreads();                       // everyone has read L[k][k]
-    if (tid == 0) { L[k][k] = piv; drop[k] = dk ? 1 : 0; }
-    for (int i = k + 1 + tid; i < nb; i += 256) L[i][k] = dk ? 0.0 : L[i][k] / piv;
+    // column k of L and row k of W (entries t <= k)
+    if (tid < 64) {
+      const int i = tid;
+      if (i == k) L[k][k] = piv;
+      else if (i > k && i < nb) L[i][k] = dk ? 0.0 : L[i][k] * rp;
+    } else if (tid < 128) {
+      const int t = tid - 64;
+      if (t <= k) W[k][t] = dk ? 0.0 : W[k][t] * rp;
+    }
     __syncthreads();
-    for (int i = k + 1 + ty; i < nb; i += 16) {
-      const double lik = L[i][k];
-      for (int j = k + 1 + tx; j <= i; j += 16) L[i][j] -= lik * L[j][k];
+    // trailing update L[i][j] -= l_ik l_jk (k < j <= i) and W[i][t] -= l_ik W[k][t] (t <= k)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = k + 1 + ty + 16 * a;
+      if (i < nb) {
+        const double lik = L[i][k];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          const int j = k + 1 + tx + 16 * bb;
+          if (j <= i) L[i][j] -= lik * L[j][k];
+          const int t = tx + 16 * bb;
+          if (t <= k) W[i][t] -= lik * W[k][t];
+        }
+      }
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = L[r][c];
-  }
-  // W = L^{-1}, row i from rows < i: W[i][t] = (delta_it - sum_{q=t}^{i-1} L[i][q] W[q][t]) / L[i][i];
-  // a dropped index has a zero row and a zero column
-  const int t = tid & 63, g = tid >> 6;
-  for (int i = 0; i < nb; ++i) {
-    double acc = 0.0;
-    if (t < i) {
-      const int span = i - t, per = (span + 3) >> 2;
-      const int q0 = t + g * per, q1 = min(i, q0 + per);
-      for (int q = q0; q < q1; ++q) acc += L[i][q] * W[q][t];
+  {
+    double* inv = arena + T.inv;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = L[r][c];
+      inv[r + 64 * c] = W[r][c];
     }
-    part[g][t] = acc;
-    __syncthreads();
-    if (g == 0 && t <= i) {
-      const double sacc = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
-      double v;
-      if (drop[i] || drop[t]) v = 0.0;
-      else if (t == i) v = 1.0 / L[i][i];
-      else v = -sacc / L[i][i];
-      W[i][t] = v;
-    }
-    __syncthreads();
-  }
-  double* inv = arena + T.inv;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    inv[r + 64 * c] = W[r][c];
   }
 }
 
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(256) void k_trunc_power(const TruncTask* __restrict
     v[i] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
   }
   __syncthreads();
-  for (int it = 0; it < 12; ++it) {
+  for (int it = 0; it < 4; ++it) {
     for (int i = threadIdx.x; i < l; i += 256) {
       double a = 0.0;
       for (int k = 0; k < l; ++k) a += S[i + (int64_t)k * l] * v[k];

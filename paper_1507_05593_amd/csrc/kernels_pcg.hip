@@ -47,12 +47,45 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
     const int m0 = w * per, m1 = min(K, m0 + per);
     const double* X = arena + T.x + lane;
     const double* v = arena + T.v;
+#pragma unroll 8
     for (int m = m0; m < m1; ++m) acc += X[(int64_t)m * T.ldx] * v[m];
   }
   part[w][lane] = acc;
   __syncthreads();
   if (w == 0 && lane < T.rows)
     arena[T.out + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// Forward-sweep target block: every descendant's X(a:b, :) v is accumulated into
+// LDS and subtracted from y once.  Entry e goes to wave (e - e0) mod 4 (lane = row,
+// unrolled inner loop); the four per-wave accumulators are added in a fixed order.
+__global__ __launch_bounds__(256) void k_fwd_block(const FwdTile* __restrict__ tiles,
+                                                   const FwdEntry* __restrict__ ents,
+                                                   const int32_t* __restrict__ relmap,
+                                                   double* __restrict__ arena,
+                                                   const int32_t* __restrict__ ilim) {
+  __shared__ double acc[4][64];
+  const FwdTile T = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  acc[w][lane] = 0.0;
+  for (int e = T.e0 + w; e < T.e1; e += 4) {
+    const FwdEntry E = ents[e];
+    const int nr = E.b - E.a;
+    const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
+    if (lane < nr) {
+      const double* X = arena + E.x + E.a + lane;
+      const double* v = arena + E.v;
+      double s = 0.0;
+#pragma unroll 8
+      for (int m = 0; m < K; ++m) s += X[(int64_t)m * E.ldx] * v[m];
+      acc[w][relmap[E.map + E.a + lane] - T.row0] += s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < T.nrows) {
+    const int r = threadIdx.x;
+    arena[T.y + r] -= (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+  }
 }
 
 // dst[begin + t] = src[idx[begin + t]] for t < count: the off-diagonal rows of one
@@ -63,7 +96,8 @@ __global__ void k_gather_rows(const int64_t* __restrict__ tasks, const int64_t* 
   for (int64_t t = threadIdx.x; t < n; t += 256) dst[b + t] = src[idx[b + t]];
 }
 
-// One wave per output column: lanes stride the rows, then a wave reduction.
+// One wave per output column (4 columns per wave, 16 per workgroup): lanes stride the
+// rows (unrolled so several loads are in flight), then a wave reduction.
 __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ tasks,
                                                 double* __restrict__ arena,
                                                 const int64_t* __restrict__ gidx,
@@ -80,8 +114,10 @@ __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ t
     double acc = 0.0;
     if (T.idx >= 0) {
       const int64_t* ix = gidx + T.idx;
+#pragma unroll 8
       for (int t = lane; t < rows; t += 64) acc += X[t] * in[ix[t]];
     } else {
+#pragma unroll 8
       for (int t = lane; t < rows; t += 64) acc += X[t] * in[t];
     }
     acc = wave_sum(acc);
@@ -107,6 +143,7 @@ __global__ __launch_bounds__(512) void k_trsv_bwd(const RowTask* __restrict__ ta
     const int ncol = T.c - T.i0;                 // columns t in [i0, c)
     const int per = (ncol + 7) / 8;
     const int t0 = T.i0 + w * per, t1 = min(T.c, t0 + per);
+#pragma unroll 8
     for (int t = max(t0, i); t < t1; ++t) {
       const double v = s_ ? w_[t] - s_[t] : w_[t];
       acc += M[(int64_t)t * T.ld] * v;
@@ -344,6 +381,10 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gemv_n, dim3(n), dim3(256), 0, s, t, arena, ilim);
+}
+void launch_fwd_block(const FwdTile* t, int n, const FwdEntry* e, const int32_t* relmap,
+                      double* arena, const int32_t* ilim, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fwd_block, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim);
 }
 void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
                         double* dst, hipStream_t s) {

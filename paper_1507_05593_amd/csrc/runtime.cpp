@@ -768,6 +768,9 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
     case kCmdTrsvBwd: launch_trsv_bwd(Q->d_rows.p + c.off, (int)c.count, A, s); break;
+    case kCmdFwdBlock:
+      launch_fwd_block(Q->d_ftiles.p + c.off, (int)c.count, Q->d_fents.p, h.d_relmap.p, A, I, s);
+      break;
     case kCmdGatherRows:
       launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);
       break;
@@ -929,52 +932,55 @@ static Error build_solve_plan(Handle& h) {
   // forward sweep, levels ascending
   for (int32_t L = 0; L < S.nlevels; ++L) {
     const auto& lev = S.by_level[L];
-    // f1: pair products of descendants restricted to their rows in C_j
-    int64_t g0 = (int64_t)Q->gemv.size();
-    for (int32_t j : lev)
-      for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
-        const Pair& pr = S.pairs[q];
-        const int32_t k = pr.k;
-        for (int32_t t0 = 0; t0 < pr.nD; t0 += 64) {
-          GemvTask t{};
+    // f1+f2: y_C -= sum over descendants of X_k(rows in C_j) t_k, per 64-row block of C_j
+    {
+      struct Blk { FwdTile t; std::vector<FwdEntry> e; };
+      std::vector<Blk> blks;
+      for (int32_t j : lev) {
+        const int32_t c = S.c(j);
+        const int32_t nB = (c + 63) / 64;
+        std::vector<std::vector<FwdEntry>> per(nB);
+        for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
+          const Pair& pr = S.pairs[q];
+          const int32_t k = pr.k;
+          const int32_t* rm = S.relmap.data() + pr.map_off;
+          FwdEntry base{};
           if (iscomp(k)) {
-            t.x = h.comp[k].Vj + pr.p0 + t0; t.ldx = S.r(k); t.kdim = -(1 + h.comp[k].qslot);
-            t.v = h.comp[k].tvq;
+            base.x = h.comp[k].Vj + pr.p0; base.ldx = S.r(k); base.kdim = -(1 + h.comp[k].qslot);
+            base.v = h.comp[k].tvq;
           } else {
-            t.x = h.a_lo + h.lo_off[k] + pr.p0 + t0; t.ldx = S.r(k);
-            t.kdim = S.c(k); t.v = h.a_w + S.first[k];
+            base.x = h.a_lo + h.lo_off[k] + pr.p0; base.ldx = S.r(k); base.kdim = S.c(k);
+            base.v = h.a_w + S.first[k];
           }
-          t.rows = std::min(64, pr.nD - t0);
-          t.out = h.a_part + h.part_off[q] + t0;
-          Q->gemv.push_back(t);
+          base.map = pr.map_off;
+          for (int32_t t = 0; t < pr.nD;) {
+            const int32_t B = rm[t] / 64;
+            int32_t u = t;
+            while (u < pr.nD && rm[u] / 64 == B) ++u;
+            FwdEntry e = base;
+            e.a = t; e.b = u;
+            per[B].push_back(e);
+            t = u;
+          }
+        }
+        for (int32_t B = 0; B < nB; ++B) {
+          if (per[B].empty()) continue;
+          Blk bk;
+          bk.t.y = h.a_y + S.first[j] + 64 * B;
+          bk.t.row0 = 64 * B;
+          bk.t.nrows = std::min(64, c - 64 * B);
+          bk.e = std::move(per[B]);
+          blks.push_back(std::move(bk));
         }
       }
-    cmd(kCmdGemvN, g0, (int64_t)Q->gemv.size() - g0);
-    // f2: subtract the partials from y on the rows of C_j (ascending descendant order)
-    const int64_t r0 = (int64_t)Q->rg_rows.size();
-    const int64_t p0 = (int64_t)Q->rg_ptr.size() - 1;
-    for (int32_t j : lev) {
-      const int32_t c = S.c(j);
-      std::vector<std::vector<int64_t>> per(c);
-      for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
-        const Pair& pr = S.pairs[q];
-        const int32_t* rm = S.relmap.data() + pr.map_off;
-        for (int32_t t = 0; t < pr.nD; ++t) per[rm[t]].push_back(h.part_off[q] + t);
+      const int64_t f0 = (int64_t)Q->ftiles.size();
+      for (auto& bk : blks) {
+        bk.t.e0 = (int32_t)Q->fents.size();
+        for (auto& e : bk.e) Q->fents.push_back(e);
+        bk.t.e1 = (int32_t)Q->fents.size();
+        Q->ftiles.push_back(bk.t);
       }
-      for (int32_t t = 0; t < c; ++t) {
-        if (per[t].empty()) continue;
-        Q->rg_rows.push_back(S.first[j] + t);
-        for (int64_t v : per[t]) Q->rg_contrib.push_back(v);
-        Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
-      }
-    }
-    {
-      const int64_t nr = (int64_t)Q->rg_rows.size() - r0;
-      if (nr > 0) {
-        Cmd c{};
-        c.type = kCmdRowGather; c.klass = RSC_K_PCG; c.off = r0; c.count = nr; c.a = p0;
-        Q->fwd_bwd.push_back(c);
-      }
+      cmd(kCmdFwdBlock, f0, (int64_t)Q->ftiles.size() - f0);
     }
     // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
     int64_t c0 = (int64_t)Q->coldot.size();
@@ -1076,6 +1082,8 @@ static Error build_solve_plan(Handle& h) {
   Q->bytes = bytes;
   Error e;
   if ((e = upload(Q->d_gemv, Q->gemv)).code) return e;
+  if ((e = upload(Q->d_ftiles, Q->ftiles)).code) return e;
+  if ((e = upload(Q->d_fents, Q->fents)).code) return e;
   if ((e = upload(Q->d_coldot, Q->coldot)).code) return e;
   if ((e = upload(Q->d_rows, Q->rows)).code) return e;
   if ((e = upload(Q->d_gath, Q->gath)).code) return e;

@@ -24,7 +24,7 @@ enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdUpdateLow, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP,
   kCmdGemvN, kCmdColDot, kCmdTrsvBwd, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdConvertLow, kCmdGatherRows,
+  kCmdConvertLow, kCmdGatherRows, kCmdFwdBlock,
 };
 
 struct Cmd {
@@ -93,11 +93,15 @@ struct SolvePlan {
   bool compressed = false;
   std::vector<Cmd> fwd_bwd;           // commands of one preconditioner apply (y -> zz)
   std::vector<GemvTask> gemv;
+  std::vector<FwdTile> ftiles;
+  std::vector<FwdEntry> fents;
   std::vector<ColDotTask> coldot;
   std::vector<RowTask> rows;
   std::vector<int64_t> rg_rows, rg_ptr, rg_contrib;  // row-gather CSR (all levels)
   std::vector<int64_t> gath;          // (begin, count) pairs of z gathers over R_j
   DevArray<GemvTask> d_gemv;
+  DevArray<FwdTile> d_ftiles;
+  DevArray<FwdEntry> d_fents;
   DevArray<ColDotTask> d_coldot;
   DevArray<RowTask> d_rows;
   DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib, d_gath;

@@ -123,3 +123,22 @@ struct PcgScalars {
 };
 
 }  // namespace rsc
+
+namespace rsc {
+
+// Forward sweep, one 64-row block of C_j: y[y0 + row] -= sum over entries of
+// X(a:b, :) v (rows scattered by relmap[map + t] - row0).
+struct FwdTile {
+  int64_t y;                   // arena offset of y on the first row of the block
+  int32_t nrows, row0;
+  int32_t e0, e1;
+};
+struct FwdEntry {
+  int64_t x;                   // X(t, m) = arena[x + t + m*ldx]
+  int64_t v;                   // multiplier vector (arena offset)
+  int64_t map;                 // relmap offset of gathered row 0
+  int32_t ldx, kdim;           // kdim < 0: -(1 + int-arena slot)
+  int32_t a, b;
+};
+
+}  // namespace rsc
