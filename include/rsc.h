@@ -170,8 +170,10 @@ rsc_status rsc_get_rowsets(rsc_handle h, int64_t* rowptr, int64_t* rows);
 /* After rsc_factor: samples l_j and kept ranks q_j (0 for uncompressed), int32[M]. */
 rsc_status rsc_get_ranks(rsc_handle h, int32_t* ell, int32_t* q);
 /* After rsc_factor: copy one supernode's blocks to host, column-major:
- * LD (c x c, lower triangle valid), LO (r x c; zeros when compressed),
- * V (r x q), U (c x q).  Any pointer may be NULL. */
+ * LD (c x c, lower triangle valid), LO (r x c: the dense off-diagonal block
+ * U^O_j (L^D_j)^{-T} as computed before compression; a compressed supernode keeps it
+ * in device memory but the factor itself uses V_j, U_j), V (r x q), U (c x q).
+ * Any pointer may be NULL. */
 rsc_status rsc_get_block(rsc_handle h, int64_t j, double* LD, double* LO, double* V, double* U);
 rsc_status rsc_get_stats(rsc_handle h, rsc_stats* out);
 rsc_status rsc_profile_enable(rsc_handle h, int32_t on);   /* also resets the counters */

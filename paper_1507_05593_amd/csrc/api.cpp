@@ -227,9 +227,7 @@ rsc_status rsc_get_block(rsc_handle H, int64_t j, double* LD, double* LO, double
       hipMemcpy2D(LD, c * 8, P, ld * 8, c * 8, c, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(RSC_ERR_DEVICE, "copy LD");
   if (LO && r > 0 && c > 0) {
-    if (comp) {
-      std::memset(LO, 0, sizeof(double) * r * c);
-    } else if (hipMemcpy(LO, h.arena.p + h.a_lo + h.lo_off[j], sizeof(double) * r * c,
+    if (hipMemcpy(LO, h.arena.p + h.a_lo + h.lo_off[j], sizeof(double) * r * c,
                          hipMemcpyDeviceToHost) != hipSuccess) {
       return fail(RSC_ERR_DEVICE, "copy LO");
     }

@@ -25,7 +25,8 @@ void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, c
 void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);
-void launch_trunc_p(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
+void launch_trunc_p(const TruncTask* t, int n, double* arena, hipStream_t s);
+void launch_trunc_compact(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
 void launch_fwd_block(const FwdTile* t, int n, const FwdEntry* e, const int32_t* relmap,

@@ -520,35 +520,78 @@ __global__ __launch_bounds__(256) void k_trunc_x0(const TruncTask* __restrict__ 
   }
 }
 
-// P = (I + X) / 2 in place; q = round(trace P) (0 for a zero or non-finite Gram); the
-// sample block of the basis panel is cleared so that columns >= q stay zero.
+// P = (I + X) / 2 in place.
 __global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ tasks,
-                                                 double* __restrict__ arena,
-                                                 int32_t* __restrict__ ints) {
+                                                 double* __restrict__ arena) {
   const TruncTask T = tasks[blockIdx.x];
   const int l = T.l;
   double* X = arena + T.sa;
-  double tr = 0.0;
   const int64_t ll = (int64_t)l * l;
   for (int64_t e = threadIdx.x; e < ll; e += 256) {
     const int i = (int)(e % l), j = (int)(e / l);
-    const double p = 0.5 * ((i == j ? 1.0 : 0.0) + X[e]);
-    X[e] = p;
-    if (i == j) tr += p;
+    X[e] = 0.5 * ((i == j ? 1.0 : 0.0) + X[e]);
   }
-  tr = block_sum256(tr);
-  double* W = arena + T.wpan;
-  const int ld = 2 * l;
-  for (int64_t e = threadIdx.x; e < ll; e += 256) {
-    const int i = (int)(e % l), j = (int)(e / l);
-    W[l + i + (int64_t)j * ld] = 0.0;
+}
+
+// Kept rank and basis.  The orthonormalisation of P Omega2 (all l columns, rows
+// [l, 2l) of the basis panel, ld 2l) zeroed every column that fell in the span of
+// the earlier ones, so the surviving columns span range(P): they are copied, in
+// order, to the front of the l x l block at wout (ld l) and their count is q.  An
+// eigenvalue that sits on the threshold leaves P with an intermediate eigenvalue;
+// its direction then survives whole instead of displacing a kept one.  q = 0 for a
+// zero or non-finite Gram matrix.
+__global__ __launch_bounds__(256) void k_trunc_compact(const TruncTask* __restrict__ tasks,
+                                                       double* __restrict__ arena,
+                                                       int32_t* __restrict__ ints) {
+  __shared__ int32_t pos[2048];          // l <= 2048 (checked by the planner)
+  __shared__ int32_t part[256];
+  const TruncTask T = tasks[blockIdx.x];
+  const int l = T.l;
+  const int64_t ld = 2 * (int64_t)l;
+  const double* W = arena + T.wpan + l;
+  double* out = arena + T.wout;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // 1. survivors: any non-zero (or non-finite) entry
+  for (int k = w; k < l; k += 4) {
+    const double* col = W + (int64_t)k * ld;
+    int nz = 0;
+    for (int i = lane; i < l; i += 64) nz |= (col[i] != 0.0);
+    const unsigned long long m = __ballot(nz);
+    if (lane == 0) pos[k] = m ? 1 : 0;
   }
-  if (threadIdx.x == 0) {
+  __syncthreads();
+  // 2. exclusive scan: thread t owns columns [t cs, (t + 1) cs)
+  const int cs = (l + 255) / 256;
+  const int k0 = min(l, tid * cs), k1 = min(l, k0 + cs);
+  int own = 0;
+  for (int k = k0; k < k1; ++k) own += pos[k];
+  part[tid] = own;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  const int q = part[255];
+  int dst = part[tid] - own;
+  for (int k = k0; k < k1; ++k) {
+    const int keep = pos[k];
+    pos[k] = keep ? dst : -1;
+    dst += keep;
+  }
+  __syncthreads();
+  // 3. copy the survivors
+  for (int k = w; k < l; k += 4) {
+    const int d = pos[k];
+    if (d < 0) continue;
+    const double* col = W + (int64_t)k * ld;
+    double* o = out + (int64_t)d * l;
+    for (int i = lane; i < l; i += 64) o[i] = col[i];
+  }
+  if (tid == 0) {
     const double gt = arena[T.sc];
-    int q = (int)floor(tr + 0.5);
-    if (!(gt > 0.0) || !isfinite(gt) || !isfinite(tr)) q = 0;
-    q = max(0, min(q, l));
-    ints[T.qslot] = q;
+    ints[T.qslot] = (gt > 0.0 && isfinite(gt)) ? q : 0;
   }
 }
 
@@ -601,8 +644,11 @@ void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s)
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_x0, dim3(64, n), dim3(256), 0, s, t, arena);
 }
-void launch_trunc_p(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_trunc_p, dim3(n), dim3(256), 0, s, t, arena, ints);
+void launch_trunc_p(const TruncTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_p, dim3(n), dim3(256), 0, s, t, arena);
+}
+void launch_trunc_compact(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_compact, dim3(n), dim3(256), 0, s, t, arena, ints);
 }
 
 }  // namespace rsc

@@ -558,6 +558,7 @@ struct Builder {
       const CompSlot& C = h.comp[j];
       TruncTask t{};
       t.g = C.G; t.sa = C.Sa; t.sb = C.Sb; t.mpan = C.Mpan; t.wpan = C.Wpan; t.sc = C.sc;
+      t.wout = C.Om2;
       t.l = C.ell; t.qslot = C.qslot; t.tol = tol;
       P.trunc.push_back(t);
     }
@@ -619,8 +620,9 @@ struct Builder {
       cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
     }
     static_assert(kNewtonSchulzSteps % 2 == 0, "the iterate must end in sa");
-    cmd(kCmdTruncP, RSC_K_EIG, t0, nt, 0);             // sa = P, q, clear the sample block
-    // 8. basis of range(P): W = orth(P Omega2) on the first q columns
+    cmd(kCmdTruncP, RSC_K_EIG, t0, nt, 0);             // sa = P
+    // 8. basis of range(P): W = orth(P Omega2) over all l columns; the columns the
+    //    orthonormalisation keeps are compacted to the front of Om2, their count is q_j
     {
       const int64_t ph0 = (int64_t)P.philox.size();
       int64_t maxw2 = 0;
@@ -638,9 +640,7 @@ struct Builder {
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t l = C.ell;
-        GemmTask t = gt(C.Sa, 1, l, C.Om2, l, 1, C.Wpan + l, 2 * l, l, l, l, 1.0, 0.0);
-        t.nlim = C.qslot;
-        fl += tiles(t, 0, 0, false);
+        fl += tiles(gt(C.Sa, 1, l, C.Om2, l, 1, C.Wpan + l, 2 * l, l, l, l, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
       for (int pass = 0; pass < 3; ++pass) {
@@ -658,16 +658,17 @@ struct Builder {
         cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
         panel_steps(pan);
       }
+      cmd(kCmdTruncCompact, RSC_K_EIG, t0, nt, 0);
     }
     // 9. U_j = U W, V_j = V W (columns beyond the device rank q_j are skipped)
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      GemmTask t = gt(C.ypanel + l, 1, ldy, C.Wpan + l, 2 * l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
+      GemmTask t = gt(C.ypanel + l, 1, ldy, C.Om2, l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
       t.nlim = C.qslot;
       fl += tiles(t, 0, 0, false);
-      GemmTask t2 = gt(C.V, 1, r, C.Wpan + l, 2 * l, 1, C.Vj, r, r, l, l, 1.0, 0.0);
+      GemmTask t2 = gt(C.V, 1, r, C.Om2, l, 1, C.Vj, r, r, l, l, 1.0, 0.0);
       t2.nlim = C.qslot;
       fl += tiles(t2, 0, 0, false);
     }
@@ -764,7 +765,8 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncPrep: launch_trunc_prep(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncPower: launch_trunc_power(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncX0: launch_trunc_x0(P->d_trunc.p + c.off, (int)c.count, A, s); break;
-    case kCmdTruncP: launch_trunc_p(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdTruncP: launch_trunc_p(P->d_trunc.p + c.off, (int)c.count, A, s); break;
+    case kCmdTruncCompact: launch_trunc_compact(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
     case kCmdTrsvBwd: launch_trsv_bwd(Q->d_rows.p + c.off, (int)c.count, A, s); break;

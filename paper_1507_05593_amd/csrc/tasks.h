@@ -69,6 +69,7 @@ struct PhiloxTask {
 // wpan ([Gram; sample], ld 2l), scalars sc[0..7], kept rank into ints[qslot].
 struct TruncTask {
   int64_t g, sa, sb, mpan, wpan, sc;
+  int64_t wout;                // compacted basis W (l x l, ld l)
   int32_t l, qslot;
   double tol;
 };
