@@ -61,7 +61,9 @@ typedef struct {
   int32_t oversample;  /* p of the rank function of Sec. 5.2 (10) */
   int32_t power_iters; /* power iterations of Algorithm 3 (0) */
   double alpha_O;      /* alpha of the rank function of Sec. 5.2, used as the sample cap (1.0) */
-  uint64_t seed;       /* key of the Philox4x32-10 sample streams (0) */
+  uint64_t seed;       /* key of the Gaussian samples (Algorithm 3): supernode j of a system is
+                          sampled from Philox4x32-10 under key (seed mod 2^32, (seed >> 32) XOR j)
+                          with j counted within its own system (0) */
   int32_t precision;   /* RSC_FP64 | RSC_MIXED_BF16 | RSC_MIXED_FP32 (RSC_FP64) */
   int32_t use_graph;   /* replay the factor and PCG launch sequences as hipGraphs (1) */
   int32_t retry;       /* mixed precision: on RSC_ERR_NOT_SPD refactor with FP32 products, then
@@ -119,7 +121,8 @@ rsc_status rsc_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
  * every elimination-tree level of every system is processed by the same launches;
  * rsc_pcg then runs one independent CG per system.  n, rowptr, colind: host arrays
  * of `count` entries, each as in rsc_analyze.  Values and vectors passed later are
- * the systems' arrays concatenated in order. */
+ * the systems' arrays concatenated in order.  Each system is dissected, sampled
+ * and solved exactly as it would be alone. */
 rsc_status rsc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* rowptr,
                              const int32_t* const* colind, const rsc_options* opt, rsc_handle* out);
 

@@ -60,6 +60,21 @@ void plan_layout(Handle& h) {
     doff += ((c + 63) / 64) * 4096;
     h.compressible[j] = (S.kind[j] == kSeparator && c >= h.opt.tau_O && r > 0) ? 1 : 0;
   }
+  // Systems of a batch are dissected one after another, so each owns a contiguous
+  // range of supernodes; the Gaussian sample is keyed by the index within that range
+  // so that a system draws the same sample batched or alone.
+  h.sn_local.assign(M, 0);
+  {
+    int64_t s = 0, base = 0;
+    for (int64_t j = 0; j < M; ++j) {
+      const int64_t v = S.perm[S.first[j]];
+      if (v >= h.seg_first[s + 1]) {
+        while (v >= h.seg_first[s + 1]) ++s;
+        base = j;
+      }
+      h.sn_local[j] = (int32_t)(j - base);
+    }
+  }
   const int64_t n = S.n, nnz = S.nnz;
   const int32_t nseg = (int32_t)h.seg_first.size() - 1;
   // arena regions
@@ -485,7 +500,7 @@ struct Builder {
       PhiloxTask t{};
       t.out = C.omega; t.rows = S.r(j); t.cols = C.ell;
       t.k0 = (uint32_t)(h.opt.seed & 0xFFFFFFFFull);
-      t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)j);
+      t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)h.sn_local[j]);
       P.philox.push_back(t);
       maxw = std::max<int64_t>(maxw, (int64_t)S.r(j) * ((C.ell + 3) / 4));
     }
@@ -631,7 +646,7 @@ struct Builder {
         PhiloxTask t{};
         t.out = C.Om2; t.rows = C.ell; t.cols = C.ell; t.c2 = 1;
         t.k0 = (uint32_t)(h.opt.seed & 0xFFFFFFFFull);
-        t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)j);
+        t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)h.sn_local[j]);
         P.philox.push_back(t);
         maxw2 = std::max<int64_t>(maxw2, (int64_t)C.ell * ((C.ell + 3) / 4));
       }

@@ -126,6 +126,7 @@ struct Handle {
   std::vector<int64_t> asm_slot;      // per stored entry: arena slot or -1
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
+  std::vector<int32_t> sn_local;      // supernode index within its own system (sample key)
   std::vector<int64_t> part_off;      // per pair: offset of its forward-sweep partial
   int64_t part_total = 0;
 

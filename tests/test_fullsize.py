@@ -1,0 +1,147 @@
+"""Full-size workloads against results the oracle stored (tests/golden/oracle_*.json,
+written by tests/golden/make_oracle_reference.py, which calls only the oracle).
+
+CPU: the library's ordering and supernode structure at 64^3 and 96^3 hash to the
+oracle's digests (bit for bit).  GPU: the rank-structured factor + PCG at the
+benchmark's settings against the oracle's ranks, iteration counts and solution,
+and exact-mode properties (PCG converges at once) that hold at any size.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from workloads import batched_problems, grid_problem, workload_config
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"oracle_{name}.json")) as f:
+        return json.load(f)
+
+
+def _problem(name):
+    cfg = workload_config(name)
+    return cfg, grid_problem(cfg["dims"], sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg["unit"])
+
+
+def _digests(sol):
+    def h(a, dt):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=dt).tobytes()).hexdigest()
+    first, parent, level, kind = sol.supernode_info()
+    _, rows = sol.rowsets()
+    return dict(perm=h(sol.perm, "<i8"), first=h(first, "<i8"), parent=h(parent, "<i4"),
+                level=h(level, "<i4"), kind=h(kind, "<i4"), rows=h(rows, "<i8"))
+
+
+@pytest.mark.parametrize("name", ["diffusion3d_64", "diffusion3d_96"])
+def test_fullsize_structure_matches_oracle(name):
+    from paper_1507_05593_amd import RSCSolver
+    g = _golden(name)
+    cfg, p = _problem(name)
+    sol = RSCSolver(p.n, p.rowptr, p.colind)
+    assert sol.supernodes == g["supernodes"]
+    assert _digests(sol) == g["structure_sha256"]
+
+
+# ------------------------------------------------------------------------ GPU
+
+def _gpu():
+    torch = pytest.importorskip("torch")
+    return torch
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,precision", [("diffusion3d_64", "fp64"), ("diffusion3d_96", "fp64"),
+                                            ("diffusion3d_96", "bf16")])
+def test_fullsize_rank_structured_pcg_matches_oracle(name, precision):
+    """The benchmark configuration (same options, seed 0) against the oracle's run.
+
+    Ranks: the compressed set and sample counts are integers fixed by the structure
+    (equal); kept ranks may differ where a singular value sits on the cut-off
+    (|dq| <= 2, at most 2 % of the supernodes).  PCG: within 10 % of the oracle's
+    iteration count (at least +-1), true residual <= rtol, and the solution within
+    1e-6 of the oracle's in norm and sum (both are solved to 1e-8 relative residual).
+    """
+    torch = _gpu()
+    from paper_1507_05593_amd import RSCSolver
+    print("case", name, precision, flush=True)
+    g = _golden(name)
+    cfg, p = _problem(name)
+    vals = torch.tensor(p.values, dtype=torch.float64, device="cuda:0")
+    b = torch.tensor(p.b, dtype=torch.float64, device="cuda:0")
+    sol = RSCSolver(p.n, p.rowptr, p.colind, precision=precision, seed=0)
+    sol.factor(vals, cfg["tol"])
+    x, info = sol.pcg(b, rtol=cfg["rtol"])
+    ell, q = sol.ranks()
+    comp = np.array(g["compressed"])
+    assert np.array_equal(np.nonzero(ell)[0], comp)
+    assert np.array_equal(ell[comp], np.array(g["ell"]))
+    dq = q[comp] - np.array(g["q"])
+    assert np.abs(dq).max() <= 2 and np.mean(dq != 0) <= 0.02, (np.abs(dq).max(), np.mean(dq != 0))
+    print("iters", info["iters"], "oracle", g["pcg_iters"], "true residual", info["true_residual"], flush=True)
+    assert info["converged"] and info["true_residual"] <= cfg["rtol"]
+    assert abs(info["iters"] - g["pcg_iters"]) <= max(1, 0.1 * g["pcg_iters"])
+    xs = x.cpu().numpy()
+    assert abs(np.linalg.norm(xs) - g["x_norm"]) <= 1e-6 * g["x_norm"]
+    assert abs(xs.sum() - g["x_sum"]) <= 1e-6 * np.abs(xs).sum()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["diffusion3d_64", "diffusion3d_96"])
+def test_fullsize_exact_factor_solves_at_once(name):
+    """tol = 0 gives the Cholesky factor itself: preconditioned CG converges in one
+    or two steps and the preconditioner inverts A (checked on a random vector)."""
+    torch = _gpu()
+    from paper_1507_05593_amd import RSCSolver
+    print("case", name, flush=True)
+    cfg, p = _problem(name)
+    vals = torch.tensor(p.values, dtype=torch.float64, device="cuda:0")
+    sol = RSCSolver(p.n, p.rowptr, p.colind)
+    sol.factor(vals, 0.0)
+    b = torch.tensor(p.b, dtype=torch.float64, device="cuda:0")
+    x, info = sol.pcg(b, rtol=1e-12)
+    assert info["iters"] <= 2 and info["true_residual"] <= 1e-12
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(p.n)
+    Av = torch.tensor(p.matrix() @ v, dtype=torch.float64, device="cuda:0")
+    z = sol.apply(Av).cpu().numpy()
+    assert np.linalg.norm(z - v) <= 1e-9 * np.linalg.norm(v)
+
+
+@pytest.mark.gpu
+def test_fullsize_batched_matches_oracle():
+    """64 independent 2D systems of uneven size in one handle: per system, the
+    structure digest, the kept-rank total and the PCG iteration count against the
+    oracle run on that system alone."""
+    torch = _gpu()
+    from paper_1507_05593_amd import RSCSolver
+    path = os.path.join(GOLDEN, "oracle_batched2d_64.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference for the batched workload not written")
+    g = _golden("batched2d_64")
+    cfg = workload_config("batched2d_64")
+    probs = batched_problems(cfg["count"], cfg["side_lo"], cfg["side_hi"], cfg["sigma"], cfg["seed"])
+    sol = RSCSolver.batch([q.n for q in probs], [q.rowptr for q in probs], [q.colind for q in probs],
+                          precision="fp32", seed=0)
+    vals = torch.cat([torch.tensor(q.values, dtype=torch.float64) for q in probs]).to("cuda:0")
+    b = torch.cat([torch.tensor(q.b, dtype=torch.float64) for q in probs]).to("cuda:0")
+    sol.factor(vals, cfg["tol"])
+    x, infos = sol.pcg(b, rtol=cfg["rtol"])
+    first, _, _, _ = sol.supernode_info()
+    ell, q = sol.ranks()
+    perm = sol.perm
+    # supernode ranges per system (systems are dissected one after another)
+    owner = np.searchsorted(np.cumsum([0] + [pp.n for pp in probs]), perm[first[:-1]], side="right") - 1
+    for i, (pp, info, gs) in enumerate(zip(probs, infos, g["systems"])):
+        assert pp.n == gs["n"]
+        sel = owner == i
+        assert int(sel.sum()) == gs["supernodes"]
+        assert int((ell[sel] > 0).sum()) == gs["compressed"]
+        assert abs(int(q[sel].sum()) - gs["q_sum"]) <= max(2, 0.01 * gs["q_sum"]), (i, q[sel].sum(), gs["q_sum"])
+        assert info["converged"] and info["true_residual"] <= cfg["rtol"]
+        assert abs(info["iters"] - gs["pcg_iters"]) <= max(1, 0.1 * gs["pcg_iters"]), (i, info, gs["pcg_iters"])

@@ -226,9 +226,12 @@ def test_adjoint_matches_dense_oracle_and_autograd():
     assert np.abs(gf - go).max() <= 1e-10 * np.abs(go).max()
 
 
-def test_batched_systems_equal_single_solves():
+@pytest.mark.parametrize("lo,hi", [(12, 48), (60, 140)])
+def test_batched_systems_equal_single_solves(lo, hi):
+    # (60, 140): every system has compressed separators, so the per-system sample
+    # keys are exercised too
     from paper_1507_05593_amd import RSCSolver
-    probs = batched_problems(6, 12, 48, 1.0, seed=4)
+    probs = batched_problems(6, lo, hi, 1.0, seed=4)
     sol = RSCSolver.batch([q.n for q in probs], [q.rowptr for q in probs], [q.colind for q in probs])
     vals = torch.cat([_vals(q) for q in probs])
     b = torch.cat([_vec(q.b) for q in probs])
@@ -240,6 +243,8 @@ def test_batched_systems_equal_single_solves():
         s1.factor(_vals(q), 1e-2)
         x1, i1 = s1.pcg(_vec(q.b), rtol=1e-10)
         assert info["iters"] == i1["iters"]
+        if hi > 100:
+            assert s1.ranks()[1].sum() > 0
         assert np.abs(x[off:off + q.n].cpu().numpy() - x1.cpu().numpy()).max() <= 1e-12 * np.abs(x1.cpu().numpy()).max()
         off += q.n
 
