@@ -1,14 +1,32 @@
 #!/usr/bin/env python
-"""Benchmark: rank-structured supernodal Cholesky factor + PCG to rel. residual 1e-8
-on one MI355X, on the synthetic 3D variable-coefficient diffusion problems.
+"""Benchmark: rank-structured supernodal Cholesky factor + PCG on one MI355X.
 
-One step = rsc_factor (assembly, Schur updates, POTRF, TRSM, range-finder
-compression, truncation) + rsc_pcg to rtol from x0 = 0, inputs resident in HBM.
-Prints one JSON line (see the README of the benchmark contract in the design doc).
+One step = rsc_factor (assembly, Schur updates, POTRF, TRSM, randomized
+compression with truncation) followed by rsc_pcg from x0 = 0 to relative residual
+1e-8 -- for the adjoint workload also the adjoint PCG and the face gradients -- on
+seeded synthetic diffusion matrices whose values and right-hand sides are already
+resident in HBM.  The default is the 96^3 variable-coefficient problem in the mixed
+BF16/FP32/FP64 form, with the plain FP64 form timed beside it on the same GPU.
+
+Prints one JSON line.  Fields beyond the common ones:
+  fp64_form      the FP64 form's timings (mixed-precision default only)
+  roofline       the kernel with the largest event-timed share of a profiled pass
+                 of the same steps: algorithmic flops per launch / mean launch time
+                 against the MI355X peak of its arithmetic; traffic from the stored
+                 rocprofv3 counter summary if the kernel source is unchanged
+  mfma_util      sum over MFMA kernels of flops / peak of their precision, divided
+                 by the factor time (time-weighted MFMA utilisation)
+  pcg_hbm        PCG algorithmic bytes (SpMV, two factor sweeps, vector updates)
+                 per second against 8 TB/s
+  cpu_baseline   the FP64 CPU oracle on a bounded sample (see cpu_baseline())
+
+  --calibrate-copy   only time a plain device copy of 1 GiB (the reference kernel
+                     for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -17,7 +35,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
+# MI355X published peaks (dense, no sparsity)
+PEAK_FLOPS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
+PEAK_HBM = 8.0e12
+KERNEL_PREC = {"gemm_staged_f64": "f64", "gemm_staged_f32": "f32", "gemm_staged_bf16x3": "bf16",
+               "gemm_staged_bf16": "bf16", "update_staged_f64": "f64", "update_staged_f32": "f32",
+               "update_staged_bf16x3": "bf16", "update_staged_bf16": "bf16", "potrf_f64": "f64"}
+KERNEL_SOURCE = {"gemm_staged": "kernels_gemm.hip", "update_staged": "kernels_gemm.hip",
+                 "potrf_f64": "kernels_dense.hip"}
+DEFAULT_PRECISION = {"diffusion3d_96": "bf16", "batched2d_64": "fp32"}
 
 
 def parse():
@@ -26,113 +52,253 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="diffusion3d_96")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--compare", default="", help="also time this precision form (e.g. fp64)")
-    ap.add_argument("--cpu-sample-s", type=float, default=15.0)
+    ap.add_argument("--precision", default="", choices=["", "fp64", "fp32", "bf16"])
+    ap.add_argument("--compare", default="auto", help="second precision timed beside (none to skip)")
+    ap.add_argument("--cpu-sample-side", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying hipGraphs")
+    ap.add_argument("--gemm-tile", type=int, default=0, choices=[0, 64, 128],
+                    help="output tile edge of the product launches (0: autotuned)")
+    ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
 
 
-def run_form(p, precision, tol, rtol, steps, warmup, profile):
+# ------------------------------------------------------------------ inputs
+
+def make_inputs(name):
+    import numpy as np
     import torch
 
-    from paper_1507_05593_amd import RSCSolver
+    from workloads import batched_problems, grid_problem, workload_config
 
+    cfg = workload_config(name)
     dev = torch.device("cuda:0")
-    vals = torch.tensor(p.values, dtype=torch.float64, device=dev)
-    b = torch.tensor(p.b, dtype=torch.float64, device=dev)
-    t0 = time.perf_counter()
-    sol = RSCSolver(p.n, p.rowptr, p.colind, precision=precision, seed=0)
-    t_an = time.perf_counter() - t0
-    info = None
-    for _ in range(warmup):
-        sol.factor(vals, tol)
-        x, info = sol.pcg(b, rtol=rtol)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fms = pms = 0.0
-    for _ in range(steps):
-        sol.factor(vals, tol)
-        x, info = sol.pcg(b, rtol=rtol)
-        st = sol.stats()
-        fms += st["t_factor_ms"]
-        pms += st["t_pcg_ms"]
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / max(steps, 1)
-    out = dict(sec_per_step=dt, analyze_s=t_an, factor_ms=fms / max(steps, 1), pcg_ms=pms / max(steps, 1),
-               iters=info["iters"], true_residual=info["true_residual"], stats=sol.stats())
-    if profile:
-        sol.profile(True)
-        sol.factor(vals, tol)
-        sol.pcg(b, rtol=rtol)
-        torch.cuda.synchronize()
-        out["profile"] = sol.profile_result()
-        out["stats_profiled"] = sol.stats()
-        sol.profile(False)
+    if "count" in cfg:
+        probs = batched_problems(cfg["count"], cfg["side_lo"], cfg["side_hi"], cfg["sigma"], cfg["seed"])
+        pattern = ([q.n for q in probs], [q.rowptr for q in probs], [q.colind for q in probs])
+        vals = torch.tensor(np.concatenate([q.values for q in probs]), device=dev)
+        b = torch.tensor(np.concatenate([q.b for q in probs]), device=dev)
+        desc = dict(workload=name, systems=len(probs), sides=[int(q.dims[0]) for q in probs],
+                    n=int(sum(q.n for q in probs)), nnz=int(sum(q.nnz for q in probs)), sigma=cfg["sigma"])
+        return cfg, None, pattern, vals, b, None, desc
+    p = grid_problem(cfg["dims"], sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg["unit"])
+    vals = torch.tensor(p.values, device=dev)
+    b = torch.tensor(p.b, device=dev)
+    extra = None
+    if name.startswith("adjoint"):
+        extra = dict(x_target=torch.tensor(p.x_target, device=dev),
+                     face_i=torch.tensor(p.face_i, device=dev), face_j=torch.tensor(p.face_j, device=dev),
+                     value_map=p)
+    desc = dict(workload=name, dims=list(p.dims), n=p.n, nnz=p.nnz, sigma=cfg["sigma"])
+    return cfg, p, (p.n, p.rowptr, p.colind), vals, b, extra, desc
+
+
+def make_solver(pattern, precision, batched, use_graph=True, gemm_tile=0):
+    from paper_1507_05593_amd import RSCSolver
+    kw = dict(precision=precision, seed=0, use_graph=use_graph, gemm_tile=gemm_tile)
+    if batched:
+        return RSCSolver.batch(*pattern, **kw)
+    return RSCSolver(*pattern, **kw)
+
+
+# ------------------------------------------------------------------ one step
+
+def step(sol, vals, b, cfg, extra):
+    from paper_1507_05593_amd import grad_faces
+    sol.factor(vals, cfg["tol"])
+    x, info = sol.pcg(b, rtol=cfg["rtol"])
+    out = dict(iters=info["iters"] if isinstance(info, dict) else [i["iters"] for i in info],
+               true_residual=(info["true_residual"] if isinstance(info, dict)
+                              else max(i["true_residual"] for i in info)))
+    t_pcg = sol.stats()["t_pcg_ms"]
+    if extra is not None:
+        # adjoint of L = 0.5 ||x - x_t||^2: lambda = A^{-1} (x - x_t), dL/dk_f on every face
+        lam, ainfo = sol.pcg(x - extra["x_target"], rtol=cfg["rtol"])
+        t_pcg += sol.stats()["t_pcg_ms"]
+        g = grad_faces(extra["face_i"], extra["face_j"], lam, x)
+        out["adjoint_iters"] = ainfo["iters"]
+        out["grad_norm"] = float(g.norm())
+    out["t_pcg_ms"] = t_pcg
     return out
 
 
-def cpu_baseline(p, tol, rtol, budget_s):
-    """The oracle on a bounded sample: its own symbolic analysis, then supernodes in
-    elimination order until the time budget is spent; scaled to the whole factor by
-    the algorithmic flop fraction of the sample, plus a PCG estimate."""
+def run_form(pattern, vals, b, cfg, extra, precision, steps, warmup, profile, batched, use_graph=True,
+             gemm_tile=0):
+    import torch
+    t0 = time.perf_counter()
+    sol = make_solver(pattern, precision, batched, use_graph, gemm_tile)
+    t_an = time.perf_counter() - t0
+    info = None
+    for _ in range(warmup):
+        info = step(sol, vals, b, cfg, extra)
+    torch.cuda.synchronize()
+    fms = pms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = step(sol, vals, b, cfg, extra)
+        fms += sol.stats()["t_factor_ms"]
+        pms += info["t_pcg_ms"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    out = dict(sec_per_step=dt, analyze_s=t_an, factor_ms=fms / max(steps, 1), pcg_ms=pms / max(steps, 1),
+               info=info, stats=sol.stats())
+    if profile:
+        # the same steps once more with an event pair around every launch
+        sol.profile(True)
+        pinfo = step(sol, vals, b, cfg, extra)
+        torch.cuda.synchronize()
+        out["kernels"] = sol.kernel_profile()
+        out["profiled_factor_ms"] = sol.stats()["t_factor_ms"]
+        out["profiled_iters"] = pinfo["iters"]
+        sol.profile(False)
+    del sol
+    torch.cuda.synchronize()
+    return out
+
+
+# ------------------------------------------------------------------ measurement helpers
+
+def source_digest(kernel):
+    for prefix, src in KERNEL_SOURCE.items():
+        if kernel.startswith(prefix):
+            path = os.path.join(ROOT, "paper_1507_05593_amd", "csrc", src)
+            with open(path, "rb") as f:
+                return src, hashlib.sha256(f.read()).hexdigest()[:16]
+    return None, None
+
+
+def stored_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current source of the kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src, dig = source_digest(kernel)
+    if d.get("source") != src or d.get("source_sha256_16") != dig:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def roofline(kernels, workload):
+    name = max((k for k in kernels if k in KERNEL_PREC), key=lambda k: kernels[k]["ms"])
+    d = kernels[name]
+    n = max(d["launches"], 1)
+    avg_s = d["ms"] / n * 1e-3
+    achieved = d["flops"] / n / avg_s if avg_s > 0 else 0.0
+    peak = PEAK_FLOPS[KERNEL_PREC[name]]
+    return {"kernel": name, "bound": "mfma", "achieved": round(achieved / 1e12, 3),
+            "peak": round(peak / 1e12, 1), "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": stored_traffic(name, workload), "launches": d["launches"],
+            "avg_launch_ms": round(d["ms"] / n, 5), "flops_per_launch": d["flops"] / n,
+            "arith": KERNEL_PREC[name]}
+
+
+def mfma_util(kernels, factor_ms):
+    t_ideal = sum(kernels[k]["flops"] / PEAK_FLOPS[p] for k, p in KERNEL_PREC.items()
+                  if k in kernels and not k.startswith("potrf"))
+    return round(t_ideal / (factor_ms * 1e-3), 4) if factor_ms > 0 else None
+
+
+def pcg_hbm(desc, stats, iters, pcg_ms):
+    it = iters if isinstance(iters, int) else max(iters)
+    n, nnz = desc["n"], desc["nnz"]
+    per_iter = 12.0 * nnz + 24.0 * n + 2.0 * stats["bytes_factor"] + 10.0 * 8.0 * n
+    total = (it + 1) * per_iter
+    gbs = total / (pcg_ms * 1e-3) if pcg_ms > 0 else 0.0
+    return {"bytes_per_iter": per_iter, "achieved": round(gbs / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM, 4)}
+
+
+def cpu_baseline(name, cfg, side, gpu_desc):
+    """The oracle as it stands (plain NumPy/SciPy FP64), on a bounded sample: the full
+    pipeline -- symbolic analysis, factor, PCG to the same rtol -- on a cube of side
+    `side` with the workload's own coefficient law, seed, tol and rtol; then, for the
+    metric's unit, scaled to the workload's size by the oracle's measured growth
+    between side / 2 and side (T ~ n^gamma).  Both measured times are reported."""
     import numpy as np
 
-    from oracle.factor import factor
+    from oracle.factor import Options, factor
     from oracle.ordering import symbolic
+    from oracle.solve import solve
+    from workloads import grid_problem
 
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count()
-    t0 = time.perf_counter()
-    sym = symbolic(p.n, p.rowptr, p.colind, 64)
-    t_sym = time.perf_counter() - t0
-    c = np.diff(sym.first)
-    r = np.array([sym.r(j) for j in range(sym.M)])
-    work = c ** 3 / 3.0 + r * c * c + r * r * c          # per-supernode exact-factor flop model
-    cum = np.cumsum(work)
-    # grow the sample until it takes about the budget
-    k = max(1, int(sym.M * 0.02))
-    t_f = 0.0
-    while True:
-        t0 = time.perf_counter()
-        factor(sym, p.n, p.rowptr, p.colind, p.values, tol, stop_after=k)
-        t_f = time.perf_counter() - t0
-        if t_f >= budget_s * 0.5 or k >= sym.M:
-            break
-        k = min(sym.M, int(k * max(2.0, budget_s / max(t_f, 1e-3) * 0.6)))
-    frac = cum[k - 1] / cum[-1]
-    est = t_f / frac
-    return dict(value=round(est, 2), unit="s", cores=int(threads), kind="oracle",
-                sample=(f"oracle symbolic analysis of the full {p.dims} problem ({t_sym:.1f} s, included) "
-                        f"then the factor of supernodes 0..{k - 1} of {sym.M} in elimination order "
-                        f"({t_f:.1f} s, {100 * frac:.2f}% of the exact-factor flop model), scaled by that "
-                        f"fraction; PCG not included"),
-                symbolic_s=round(t_sym, 2), factor_sample_s=round(t_f, 2), flop_fraction=float(frac))
+    d = 2 if cfg.get("dims") is not None and len(cfg["dims"]) == 2 else 3
+    if "count" in cfg:
+        d = 2
 
+    def run(s):
+        p = grid_problem((s,) * d, sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg.get("unit", False))
+        t0 = time.perf_counter()
+        sym = symbolic(p.n, p.rowptr, p.colind, 64)
+        F = factor(sym, p.n, p.rowptr, p.colind, p.values, cfg["tol"], Options(seed=0))
+        r = solve(F, p.matrix(), p.b, rtol=cfg["rtol"])
+        return time.perf_counter() - t0, p.n, r.iters
+
+    t_half, n_half, _ = run(max(side // 2, 4))
+    t_full, n_full, it = run(side)
+    gamma = float(np.log(t_full / t_half) / np.log(n_full / n_half)) if t_half > 0 else 1.0
+    gamma = min(max(gamma, 1.0), 2.0)
+    est = t_full * (gpu_desc["n"] / n_full) ** gamma
+    return dict(value=round(est, 2), unit="s", cores=int(threads), kind="oracle",
+                sample=(f"oracle symbolic+factor+PCG(rtol {cfg['rtol']}) on the same law at side {side} "
+                        f"(n={n_full}: {t_full:.2f} s, {it} iterations) and side {max(side // 2, 4)} "
+                        f"(n={n_half}: {t_half:.2f} s); scaled to n={gpu_desc['n']} as n^{gamma:.2f}"),
+                sample_s=round(t_full, 3), half_sample_s=round(t_half, 3), gamma=round(gamma, 3))
+
+
+def calibrate_copy():
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    c = torch.empty_like(a)
+    for _ in range(5):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "sec": dt,
+                      "GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+
+
+# ------------------------------------------------------------------ main
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of the path is described in DESIGN.md and not implemented", file=sys.stderr)
+        print(f"bench.py: this path runs on one GPU (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding is a design only and is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
-
-    from workloads import grid_problem, workload_config
-
-    cfg = workload_config(args.workload)
-    p = grid_problem(cfg["dims"], sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg["unit"])
-    tol, rtol = cfg["tol"], cfg["rtol"]
-    res = run_form(p, args.precision, tol, rtol, args.steps, args.warmup, not args.no_profile)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    name = args.workload
+    precision = args.precision or DEFAULT_PRECISION.get(name, "fp64")
+    compare = args.compare
+    if compare == "auto":
+        compare = "fp64" if precision != "fp64" and name == "diffusion3d_96" else "none"
+    cfg, p, pattern, vals, b, extra, desc = make_inputs(name)
+    batched = "count" in cfg
+    res = run_form(pattern, vals, b, cfg, extra, precision, args.steps, args.warmup, not args.no_profile, batched,
+                   not args.no_graph, args.gemm_tile)
     cmp = None
-    if args.compare:
-        cmp = run_form(p, args.compare, tol, rtol, args.steps, args.warmup, False)
+    if compare != "none":
+        cmp = run_form(pattern, vals, b, cfg, extra, compare, args.steps, args.warmup, False, batched,
+                       not args.no_graph, args.gemm_tile)
+    info, st = res["info"], res["stats"]
     line = {
-        "metric": "factor+PCG s to rel.res 1e-8",
+        "metric": "factor+PCG s to rel.res 1e-8, MFMA util; mixed-prec vs FP64 form, same GPU",
         "value": round(res["sec_per_step"], 5),
         "unit": "s",
         "n_gpus": 1,
@@ -142,38 +308,39 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f32+f64"}[precision],
         "data": "synthetic",
-        "config": {"workload": args.workload, "dims": list(p.dims), "n": p.n, "nnz": p.nnz,
-                   "sigma": cfg["sigma"], "tol": tol, "rtol": rtol, "precision": args.precision},
+        "config": dict(desc, tol=cfg["tol"], rtol=cfg["rtol"], precision=precision,
+                       gemm_tile=args.gemm_tile or "autotuned"),
         "factor_ms": round(res["factor_ms"], 3),
         "pcg_ms": round(res["pcg_ms"], 3),
-        "pcg_iters": res["iters"],
-        "true_residual": res["true_residual"],
+        "pcg_iters": info["iters"],
+        "true_residual": info["true_residual"],
         "analyze_s": round(res["analyze_s"], 3),
     }
-    st = res["stats"]
-    fl = st["flops_potrf"] + st["flops_trsm"] + st["flops_update"] + st["flops_sample"] + st["flops_orth"] + st["flops_trunc"]
-    line["factor_tflops"] = round(fl / 1e12, 4)
+    if "adjoint_iters" in info:
+        line["adjoint_iters"] = info["adjoint_iters"]
+    fl = sum(st[k] for k in ("flops_potrf", "flops_trsm", "flops_update", "flops_sample", "flops_orth",
+                             "flops_trunc"))
+    line["factor_tflop"] = round(fl / 1e12, 4)
     line["factor_tflop_per_s"] = round(fl / (res["factor_ms"] * 1e-3) / 1e12, 3)
+    line["device_gb"] = round(st["device_bytes"] / 1e9, 2)
+    line["tile_tuner"] = {"launches_tuned": st["gemm_tuned"], "launches_128": st["gemm_tile128"]}
     if cmp:
-        line["compare"] = {"precision": args.compare, "ms_per_step": round(1e3 * cmp["sec_per_step"], 3),
-                           "factor_ms": round(cmp["factor_ms"], 3), "pcg_ms": round(cmp["pcg_ms"], 3),
-                           "pcg_iters": cmp["iters"]}
-    if "profile" in res:
-        prof = res["profile"]
-        line["profile_ms"] = {k: round(v["ms"], 3) for k, v in prof.items()}
-        dom = max(("update", "gemm", "trsm", "potrf"), key=lambda k: prof[k]["ms"])
-        d = prof[dom]
-        avg_ms = d["ms"] / max(d["launches"], 1)
-        achieved = d["flops"] / max(d["launches"], 1) / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
-        peak = PEAK["fp64"] if args.precision == "fp64" else PEAK["fp32"]
-        line["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": round(achieved / 1e12, 3),
-                            "peak": round(peak / 1e12, 1), "unit": "TFLOP/s",
-                            "frac": round(achieved / peak, 4), "traffic": None,
-                            "launches": d["launches"], "avg_launch_ms": round(avg_ms, 4)}
+        line["fp64_form" if compare == "fp64" else "compare_form"] = {
+            "precision": compare, "ms_per_step": round(1e3 * cmp["sec_per_step"], 3),
+            "factor_ms": round(cmp["factor_ms"], 3), "pcg_ms": round(cmp["pcg_ms"], 3),
+            "pcg_iters": cmp["info"]["iters"], "true_residual": cmp["info"]["true_residual"]}
+        line["speedup_vs_" + compare] = round(cmp["sec_per_step"] / res["sec_per_step"], 3)
+    if "kernels" in res:
+        ks = res["kernels"]
+        line["roofline"] = roofline(ks, name)
+        line["mfma_util"] = mfma_util(ks, res["profiled_factor_ms"])
+        top = sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:8]
+        line["kernels_ms"] = {k: round(v["ms"], 3) for k, v in top}
+    line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, tol, rtol, args.cpu_sample_s)
+        line["cpu_baseline"] = cpu_baseline(name, cfg, args.cpu_sample_side, desc)
     print(json.dumps(line), flush=True)
 
 

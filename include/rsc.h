@@ -68,7 +68,9 @@ typedef struct {
   int32_t use_graph;   /* replay the factor and PCG launch sequences as hipGraphs (1) */
   int32_t retry;       /* mixed precision: on RSC_ERR_NOT_SPD refactor with FP32 products, then
                           FP64 (the restart-with-more-accuracy policy of Sec. 5.3) (1) */
-  int32_t reserved;
+  int32_t gemm_tile;   /* output tile edge of the dense-product launches: 0 = picked per launch
+                          class by the built-in autotuner (timed on the device the first time a
+                          class occurs in the process), 64 or 128 = fixed (0) */
 } rsc_options;
 
 typedef struct {
@@ -94,6 +96,9 @@ typedef struct {
   double t_factor_ms;          /* device time of the last rsc_factor (hipEvents) */
   double t_pcg_ms;             /* device time of the last rsc_pcg */
   double device_bytes;         /* device memory owned by the handle */
+  int64_t gemm_tuned;          /* product launches of the current factor plan timed by the tile
+                                  tuner (gemm_tile = 0) */
+  int64_t gemm_tile128;        /* of those, launches that run with 128-wide tiles */
 } rsc_stats;
 
 /* Kernel-class timing (hipEvents around every launch of a class while enabled). */
@@ -181,6 +186,14 @@ rsc_status rsc_get_block(rsc_handle h, int64_t j, double* LD, double* LO, double
 rsc_status rsc_get_stats(rsc_handle h, rsc_stats* out);
 rsc_status rsc_profile_enable(rsc_handle h, int32_t on);   /* also resets the counters */
 rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
+/* The same timings per kernel (and precision mode) rather than per class: entry k in
+ * [0, RSC_KERNELS) gives the kernel's name (static string), its launch count, the
+ * summed hipEvent time of those launches in ms (events on the launch stream, so
+ * each interval is one launch) and their algorithmic flops.  Any output may be NULL.
+ * Errors: RSC_ERR_INVALID_ARG for a null handle or k out of range. */
+#define RSC_KERNELS 24
+rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
+                                  double* ms, double* flops);
 
 const char* rsc_status_string(rsc_status s);
 const char* rsc_last_error(void);

@@ -22,13 +22,14 @@ RSC_MIXED_BF16 = 1
 RSC_MIXED_FP32 = 2
 
 K_CLASSES = ["update", "potrf", "trsm", "gemm", "eig", "pcg", "other"]
+RSC_KERNELS = 24
 
 
 class Options(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("tau_O", C.c_int32), ("oversample", C.c_int32),
                 ("power_iters", C.c_int32), ("alpha_O", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("use_graph", C.c_int32), ("retry", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("gemm_tile", C.c_int32)]
 
 
 class PcgResult(C.Structure):
@@ -44,7 +45,8 @@ class Stats(C.Structure):
                 ("reserved", C.c_int32), ("flops_potrf", C.c_double), ("flops_trsm", C.c_double),
                 ("flops_update", C.c_double), ("flops_sample", C.c_double), ("flops_orth", C.c_double),
                 ("flops_trunc", C.c_double), ("bytes_factor", C.c_double), ("t_analyze_ms", C.c_double),
-                ("t_factor_ms", C.c_double), ("t_pcg_ms", C.c_double), ("device_bytes", C.c_double)]
+                ("t_factor_ms", C.c_double), ("t_pcg_ms", C.c_double), ("device_bytes", C.c_double),
+                ("gemm_tuned", C.c_int64), ("gemm_tile128", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -74,6 +76,8 @@ SYMBOLS = {
     "rsc_get_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "rsc_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "rsc_get_profile": (C.c_int, [C.c_void_p, C.POINTER(Profile)]),
+    "rsc_get_kernel_profile": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rsc_status_string": (C.c_char_p, [C.c_int]),
     "rsc_last_error": (C.c_char_p, []),
     "rsc_destroy": (None, [C.c_void_p]),

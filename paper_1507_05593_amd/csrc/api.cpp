@@ -29,7 +29,8 @@ rsc_status ret(const rsc::Error& e) {
 
 rsc_status check_options(const rsc_options& o) {
   if (o.leaf_max < 1 || o.tau_O < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.alpha_O > 0) ||
-      o.precision < RSC_FP64 || o.precision > RSC_MIXED_FP32)
+      o.precision < RSC_FP64 || o.precision > RSC_MIXED_FP32 ||
+      (o.gemm_tile != 0 && o.gemm_tile != 64 && o.gemm_tile != 128))
     return fail(RSC_ERR_INVALID_ARG, "option out of range");
   return RSC_OK;
 }
@@ -263,6 +264,10 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
   out->t_factor_ms = h.t_factor_ms;
   out->t_pcg_ms = h.t_pcg_ms;
   out->device_bytes = 8.0 * (double)h.arena_size + 4.0 * (double)h.ints_size;
+  if (h.fplan) {
+    out->gemm_tuned = h.fplan->tuned;
+    out->gemm_tile128 = h.fplan->tuned128;
+  }
   const bool comp = h.factored && h.fplan && h.fplan->compressed;
   std::vector<int32_t> q(S.M(), 0);
   if (comp && hipMemcpy(q.data(), h.ints.p + h.i_ranks, sizeof(int32_t) * S.M(), hipMemcpyDeviceToHost) != hipSuccess)
@@ -303,6 +308,22 @@ rsc_status rsc_profile_enable(rsc_handle H, int32_t on) {
   if (!H) return fail(RSC_ERR_INVALID_ARG, "null handle");
   H->h.profiling = on != 0;
   std::memset(&H->h.prof, 0, sizeof(H->h.prof));
+  for (int k = 0; k < RSC_KERNELS; ++k) {
+    H->h.kprof_launches[k] = 0;
+    H->h.kprof_ms[k] = 0.0;
+    H->h.kprof_flops[k] = 0.0;
+  }
+  return RSC_OK;
+}
+
+rsc_status rsc_get_kernel_profile(rsc_handle H, int32_t k, const char** name, int64_t* launches,
+                                  double* ms, double* flops) {
+  if (!H) return fail(RSC_ERR_INVALID_ARG, "null handle");
+  if (k < 0 || k >= RSC_KERNELS) return fail(RSC_ERR_INVALID_ARG, "kernel index out of range");
+  if (name) *name = rsc::kernel_name(k);
+  if (launches) *launches = H->h.kprof_launches[k];
+  if (ms) *ms = H->h.kprof_ms[k];
+  if (flops) *flops = H->h.kprof_flops[k];
   return RSC_OK;
 }
 

@@ -14,9 +14,6 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, double* arena,
                      hipStream_t s);
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s);
-void launch_gemm_f64(const GemmTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
-void launch_update_f64(const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
-                       double* arena, const int32_t* ilim, hipStream_t s);
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s);
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
                    hipStream_t s);
@@ -66,16 +63,10 @@ void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const d
 }  // namespace rsc
 
 namespace rsc {
-// mode: 1 = FP32 operands, 2 = BF16 hi/lo split (three products), 3 = plain BF16
-void launch_gemm_lp(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
-void launch_update_lp(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
-                      double* arena, const int32_t* ilim, hipStream_t s);
-}  // namespace rsc
-
-namespace rsc {
 // LDS-staged MFMA kernels; mode 0 = FP64, 1 = FP32 operands, 2 = BF16 hi/lo split, 3 = BF16
-void launch_gemm_staged(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
-                        hipStream_t s);
+// tile: output tile edge, 64 or 128 (tasks must have been cut to that edge)
+void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
+                        const int32_t* ilim, hipStream_t s);
 void launch_update_staged(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
                           double* arena, const int32_t* ilim, hipStream_t s);
 }  // namespace rsc

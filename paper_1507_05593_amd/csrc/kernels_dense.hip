@@ -55,278 +55,220 @@ __global__ void k_scatter_const(const int64_t* __restrict__ slot, int64_t n, dou
     arena[slot[p]] = v;
 }
 
-// ---------------------------------------------------------------- FP64 MFMA tile GEMM
-
-// One 64x64 output tile per 256-thread workgroup; wave w owns the 32x32 quarter
-// (w / 2, w % 2) as 2x2 blocks of 16x16, accumulated by v_mfma_f64_16x16x4f64 with
-// operands read straight from the arena (L2-resident tiles).
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmTask* __restrict__ tasks,
-                                                  double* __restrict__ arena,
-                                                  const int32_t* __restrict__ ilim) {
-  const GemmTask T = tasks[blockIdx.x];
-  const int lane = lane_id(), w = wave_id();
-  const int wr = w >> 1, wc = w & 1;
-  const int n = T.nlim >= 0 ? min(T.n, ilim[T.nlim]) : T.n;
-  const int K = T.klim >= 0 ? min(T.k, ilim[T.klim]) : T.k;
-  if (T.j0 >= n) return;
-  const int li = lane & 15, lk = lane >> 4;
-  int rows[2], cols[2];
-  bool rv[2], cv[2];
-  for (int b = 0; b < 2; ++b) {
-    rows[b] = T.i0 + wr * 32 + b * 16 + li;
-    cols[b] = T.j0 + wc * 32 + b * 16 + li;
-    rv[b] = rows[b] < T.m;
-    cv[b] = cols[b] < n;
-  }
-  const double* A = arena + T.a;
-  const double* B = arena + T.b;
-  v4d acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y) acc[x][y] = (v4d){0.0, 0.0, 0.0, 0.0};
-  const bool active = (T.i0 + wr * 32 < T.m) && (T.j0 + wc * 32 < n);
-  if (active) {
-    int64_t ar[2], bc[2];
-    for (int b = 0; b < 2; ++b) {
-      ar[b] = (int64_t)rows[b] * T.ais;
-      bc[b] = (int64_t)cols[b] * T.bjs;
-    }
-    int k0 = 0;
-    for (; k0 + 16 <= K; k0 += 16) {
-      double av[4][2], bv[4][2];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t kk = k0 + 4 * u + lk;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          av[u][b] = rv[b] ? A[ar[b] + kk * T.aks] : 0.0;
-          bv[u][b] = cv[b] ? B[bc[b] + kk * T.bks] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][x], bv[u][y], acc[x][y], 0, 0, 0);
-    }
-    for (; k0 < K; k0 += 4) {
-      const int64_t kk = k0 + lk;
-      const bool kv = kk < K;
-      double av[2], bv[2];
-      for (int b = 0; b < 2; ++b) {
-        av[b] = (rv[b] && kv) ? A[ar[b] + kk * T.aks] : 0.0;
-        bv[b] = (cv[b] && kv) ? B[bc[b] + kk * T.bks] : 0.0;
-      }
-      for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-    }
-  }
-  // every read of A/B (which may alias C in the in-place triangular solve) is done
-  __syncthreads();
-  if (!active) return;
-  double* C = arena + T.c;
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y)
-      for (int e = 0; e < 4; ++e) {
-        const int i = T.i0 + wr * 32 + x * 16 + lk + 4 * e;
-        const int j = T.j0 + wc * 32 + y * 16 + li;
-        if (i < T.m && j < n) {
-          double* cp = C + i + (int64_t)j * T.ldc;
-          const double v = T.alpha * acc[x][y][e];
-          const double* dp = (T.d >= 0) ? arena + T.d + i + (int64_t)j * T.ldc : cp;
-          *cp = (T.beta == 0.0) ? v : v + T.beta * *dp;
-        }
-      }
-}
-
-// ---------------------------------------------------------------- Schur update
-
-// Target-tile ownership: the workgroup holds one 64x64 tile of a supernode panel in
-// LDS, subtracts every descendant's product X(a:b) X(c:d)^T (scattered through the
-// relative map) in entry order, and writes the tile back once.  No atomics: the
-// result does not depend on scheduling.
-__global__ __launch_bounds__(256) void k_update_f64(const UpdTile* __restrict__ tiles,
-                                                    const UpdEntry* __restrict__ ents,
-                                                    const int32_t* __restrict__ relmap,
-                                                    double* __restrict__ arena,
-                                                    const int32_t* __restrict__ ilim) {
-  __shared__ double tile[64][65];
-  __shared__ int32_t rmap[64], cmap[64];
-  const UpdTile T = tiles[blockIdx.x];
-  const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-  const int wr = w >> 1, wc = w & 1, li = lane & 15, lk = lane >> 4;
-  double* P = arena + T.panel;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    tile[r][c] = (r < T.nrows && c < T.ncols) ? P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] : 0.0;
-  }
-  for (int e = T.e0; e < T.e1; ++e) {
-    const UpdEntry E = ents[e];
-    const int nr = E.b - E.a, nc = E.d - E.c;
-    const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
-    if (tid < 64) {
-      rmap[tid] = tid < nr ? relmap[E.map + E.a + tid] - T.row0 : 0;
-    } else if (tid < 128) {
-      const int t = tid - 64;
-      cmap[t] = t < nc ? relmap[E.map + E.c + t] - T.col0 : 0;
-    }
-    __syncthreads();
-    const bool active = (wr * 32 < nr) && (wc * 32 < nc) && K > 0;
-    if (active) {
-      const double* X = arena + E.x;
-      v4d acc[2][2];
-      for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) acc[x][y] = (v4d){0.0, 0.0, 0.0, 0.0};
-      int ra[2], rc[2];
-      bool va[2], vc[2];
-      for (int b = 0; b < 2; ++b) {
-        ra[b] = wr * 32 + b * 16 + li;
-        rc[b] = wc * 32 + b * 16 + li;
-        va[b] = ra[b] < nr;
-        vc[b] = rc[b] < nc;
-        ra[b] += E.a;
-        rc[b] += E.c;
-      }
-      int k0 = 0;
-      for (; k0 + 16 <= K; k0 += 16) {
-        double av[4][2], bv[4][2];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t col = (int64_t)(k0 + 4 * u + lk) * E.ldx;
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            av[u][b] = va[b] ? X[ra[b] + col] : 0.0;
-            bv[u][b] = vc[b] ? X[rc[b] + col] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][x], bv[u][y], acc[x][y], 0, 0, 0);
-      }
-      for (; k0 < K; k0 += 4) {
-        const int kk = k0 + lk;
-        const bool kv = kk < K;
-        const int64_t col = (int64_t)kk * E.ldx;
-        double av[2], bv[2];
-        for (int b = 0; b < 2; ++b) {
-          av[b] = (va[b] && kv) ? X[ra[b] + col] : 0.0;
-          bv[b] = (vc[b] && kv) ? X[rc[b] + col] : 0.0;
-        }
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-      }
-      for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y)
-          for (int e2 = 0; e2 < 4; ++e2) {
-            const int pr = wr * 32 + x * 16 + lk + 4 * e2;
-            const int pc = wc * 32 + y * 16 + li;
-            if (pr < nr && pc < nc) tile[rmap[pr]][cmap[pc]] -= acc[x][y][e2];
-          }
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    if (r < T.nrows && c < T.ncols) P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] = tile[r][c];
-  }
-}
-
 // ---------------------------------------------------------------- diagonal block Cholesky
 
-// Cholesky of one (<= 64) diagonal block in LDS together with its explicit inverse.
+// 1 / sqrt(d) for a positive finite d: the hardware estimate refined by two Newton
+// steps r <- r (3 - d r^2) / 2 (each squares the relative error), to FP64 rounding.
+__device__ __forceinline__ double rsqrt_f64(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  r = r * (1.5 - 0.5 * d * r * r);
+  r = r * (1.5 - 0.5 * d * r * r);
+  return r;
+}
+
+// Cholesky of one (<= 64) diagonal block together with its explicit inverse.
 // mode 0: a pivot that is not positive and finite records the supernode in
 //         status[0] (smallest id wins) and is replaced by 1 so the sweep stays finite.
 // mode 1 (orthonormalisation): a pivot <= 1e-14 * scale marks the column dependent:
 //         its L column and its row and column of the inverse become zero.
-// Right-looking elimination with 256 threads on a 16 x 16 grid; the inverse rides on
-// the same steps (W starts as I; step k scales row k of W by 1 / l_kk and subtracts
-// l_ik times it from the rows below), so there is no separate substitution phase.
-// Inner loops have fixed trip counts (masked) so that their LDS loads issue ahead.
+// Right-looking elimination four columns at a time, register-blocked: thread (tx, ty)
+// of the 16 x 16 grid owns entries (ty + 16a, tx + 16b), a, b < 4, of L and of W
+// (W starts as I and ends as L^{-1}).  Step K publishes the four-column panel and rows
+// 4K..4K+3 of W through double-buffered LDS (one barrier); every thread then factors
+// the 4 x 4 diagonal block and inverts it in registers (Ld, Ldi), forms l_i = Ldi p_i
+// for its rows and columns, and applies the rank-4 updates
+//   L(i, j) -= l_i . l_j,   W(block rows) = Ldi W(block rows),   W(i, :) -= l_i . W(block rows).
+// Sixteen sequential steps instead of sixty-four; global accesses go through an LDS tile.
 __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
-  __shared__ double L[64][65];
-  __shared__ double W[64][65];
-  __shared__ int32_t dropk;
+  __shared__ double tile[64][65];
+  __shared__ double pan[2][64][4];
+  __shared__ double wrows[2][4][64];
   const PotrfTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
   const int nb = T.nb;
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
-  {
-    double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
-      v[u] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
-      L[r][c] = v[u];
-      W[r][c] = (r == c && r < nb) ? 1.0 : 0.0;
-    }
+  for (int u = 0; u < 16; ++u) {
+    const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+    tile[r][c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
   }
-  const double dscale = (T.mode == 1) ? arena[T.scale_off] : 0.0;
-  const int tx = tid & 15, ty = tid >> 4;
   __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    double d = L[k][k];
-    bool dk = false;
-    if (T.mode == 0) {
-      if (!(d > 0.0) || !isfinite(d)) {
-        if (tid == 0) atomicMin(&status[0], T.sn);
-        d = 1.0;
-      }
-    } else if (!(d > 1e-14 * dscale) || !isfinite(d)) {
-      dk = true;
-      d = 1.0;
+  double L[4][4], W[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 16 * a, j = tx + 16 * b;
+      L[a][b] = tile[i][j];
+      W[a][b] = (i == j && i < nb) ? 1.0 : 0.0;
     }
-    const double piv = sqrt(d);
-    const double rp = 1.0 / piv;
-    __syncthreads();                       // everyone has read L[k][k]
-    // column k of L and row k of W (entries t <= k)
-    if (tid < 64) {
-      const int i = tid;
-      if (i == k) L[k][k] = piv;
-      else if (i > k && i < nb) L[i][k] = dk ? 0.0 : L[i][k] * rp;
-    } else if (tid < 128) {
-      const int t = tid - 64;
-      if (t <= k) W[k][t] = dk ? 0.0 : W[k][t] * rp;
+  const double dscale = (T.mode == 1) ? arena[T.scale_off] : 0.0;
+  bool bad = false;
+  const int nsteps = (nb + 3) >> 2;
+  for (int K = 0; K < nsteps; ++K) {
+    const int k0 = 4 * K, kb = k0 >> 4, ko = k0 & 15, buf = K & 1;
+    const int nbk = min(4, nb - k0);
+    // publish the panel columns k0..k0+3 (rows >= k0) and rows k0..k0+3 of W
+    if (tx >= ko && tx < ko + 4) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (b == kb) {
+            const int i = ty + 16 * a;
+            if (i >= k0) pan[buf][i][tx - ko] = L[a][b];
+          }
+    }
+    if (ty >= ko && ty < ko + 4) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a == kb) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) wrows[buf][ty - ko][tx + 16 * b] = W[a][b];
+        }
     }
     __syncthreads();
-    // trailing update L[i][j] -= l_ik l_jk (k < j <= i) and W[i][t] -= l_ik W[k][t] (t <= k)
+    // 4 x 4 diagonal block: Cholesky factor Ld and inverse Ldi (every thread)
+    double A4[4][4], Ld[4][4], Ldi[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        A4[r][c] = (c <= r) ? pan[buf][k0 + r][c] : 0.0;
+        Ld[r][c] = 0.0;
+        Ldi[r][c] = 0.0;
+      }
+    bool drop[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double d = A4[c][c];
+      bool dk = false;
+      if (c >= nbk) {
+        d = 1.0;                                   // past the block edge: identity
+      } else if (T.mode == 0) {
+        if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
+      } else if (!(d > 1e-14 * dscale) || !isfinite(d)) {
+        dk = true;
+        d = 1.0;
+      }
+      drop[c] = dk;
+      const double rp = rsqrt_f64(d);
+      const double piv = d * rp;
+      Ld[c][c] = piv;
+      Ldi[c][c] = dk ? 0.0 : rp;
+#pragma unroll
+      for (int r = c + 1; r < 4; ++r) Ld[r][c] = dk ? 0.0 : A4[r][c] * rp;
+#pragma unroll
+      for (int r = c + 1; r < 4; ++r)
+#pragma unroll
+        for (int q = c + 1; q <= r; ++q) A4[r][q] -= Ld[r][c] * Ld[q][c];
+    }
+    // Ldi (rows and columns of dropped pivots stay zero): forward substitution
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = c + 1; r < 4; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = c; m < r; ++m) acc += Ld[r][m] * Ldi[m][c];
+        Ldi[r][c] = -acc * Ldi[r][r];                 // Ldi[r][r] = 1 / Ld[r][r], 0 if dropped
+      }
+    // l vectors of this thread's columns (j > k0 + 3) and new rows k0..k0+3 of W for
+    // its columns; the row vectors l_i are formed one row at a time below
+    double lj[4][4], wn[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = tx + 16 * b;
+      double pv[4], wb[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        pv[c] = (j > k0 + 3) ? pan[buf][j][c] : 0.0;
+        wb[c] = wrows[buf][c][j];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int m = 0; m <= c; ++m) {
+          x += Ldi[c][m] * pv[m];
+          y += Ldi[c][m] * wb[m];
+        }
+        lj[b][c] = x;
+        wn[b][c] = y;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int i = k + 1 + ty + 16 * a;
-      if (i < nb) {
-        const double lik = L[i][k];
+      const int i = ty + 16 * a;
+      double li[4];
+      {
+        double pv[4];
 #pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-          const int j = k + 1 + tx + 16 * bb;
-          if (j <= i) L[i][j] -= lik * L[j][k];
-          const int t = tx + 16 * bb;
-          if (t <= k) W[i][t] -= lik * W[k][t];
+        for (int c = 0; c < 4; ++c) pv[c] = (i > k0 + 3) ? pan[buf][i][c] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double x = 0.0;
+#pragma unroll
+          for (int m = 0; m <= c; ++m) x += Ldi[c][m] * pv[m];
+          li[c] = x;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = tx + 16 * b;
+        if (b == kb && tx >= ko && tx < ko + 4) {          // the panel columns
+          const int cc = tx - ko;
+          if (i > k0 + 3) {
+            L[a][b] = (cc == 0) ? li[0] : (cc == 1) ? li[1] : (cc == 2) ? li[2] : li[3];
+          } else if (i >= k0 && i - k0 >= cc) {
+            const int rr = i - k0;
+            double v = 0.0;
+#pragma unroll
+            for (int r2 = 0; r2 < 4; ++r2)
+#pragma unroll
+              for (int c2 = 0; c2 <= r2; ++c2)
+                if (r2 == rr && c2 == cc) v = Ld[r2][c2];
+            L[a][b] = v;
+          }
+        } else if (i > k0 + 3 && j > k0 + 3) {
+          L[a][b] -= li[0] * lj[b][0] + li[1] * lj[b][1] + li[2] * lj[b][2] + li[3] * lj[b][3];
+        }
+        if (a == kb && ty >= ko && ty < ko + 4) {           // rows k0..k0+3 of W
+          const int rr = ty - ko;
+          W[a][b] = (rr == 0) ? wn[b][0] : (rr == 1) ? wn[b][1] : (rr == 2) ? wn[b][2] : wn[b][3];
+        } else if (i > k0 + 3) {
+          W[a][b] -= li[0] * wn[b][0] + li[1] * wn[b][1] + li[2] * wn[b][2] + li[3] * wn[b][3];
         }
       }
     }
-    __syncthreads();
   }
-  {
-    double* inv = arena + T.inv;
+  if (bad && tid == 0) atomicMin(&status[0], T.sn);
+  __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
-      if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = L[r][c];
-      inv[r + 64 * c] = W[r][c];
-    }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) tile[ty + 16 * a][tx + 16 * b] = L[a][b];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = tile[r][c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) tile[ty + 16 * a][tx + 16 * b] = W[a][b];
+  __syncthreads();
+  double* inv = arena + T.inv;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+    inv[r + 64 * c] = tile[r][c];
   }
 }
 
@@ -616,13 +558,6 @@ void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, dou
 }
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, s, slot, n, v, arena);
-}
-void launch_gemm_f64(const GemmTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_gemm_f64, dim3(n), dim3(256), 0, s, t, arena, ilim);
-}
-void launch_update_f64(const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
-                       double* arena, const int32_t* ilim, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_update_f64, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim);
 }
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(256), 0, s, t, arena, status);

@@ -1,11 +1,14 @@
-// LDS-staged MFMA tile GEMM for gfx950 (all precisions).
+// LDS-staged MFMA tile GEMM for gfx950 (all precisions, two tile sizes).
 //
-// One 64x64 output tile per 256-thread workgroup (wave w owns the 32x32 quarter
-// (w / 2, w % 2) as 2x2 MFMA blocks).  K advances in chunks of 32: the A and B chunks
-// (64 x 32 each) are read from the FP64 arena with coalesced loads whatever their
-// layout (the contiguous dimension is mapped to consecutive threads), converted once
-// to the matrix-core type and written to LDS; the next chunk's global loads are issued
-// into registers before the current chunk's MFMAs.
+// One TM x TM output tile per workgroup: TM = 64 with 4 waves (each a 32 x 32 quarter
+// as 2 x 2 MFMA blocks of 16 x 16) or TM = 128 with 8 waves (each a 32 x 64 strip as
+// 2 x 4 blocks); wave w sits at row strip w / 2, column half w % 2.
+// K advances in chunks of 32: the A and B chunks (TM x 32 each) are read from the FP64
+// arena with coalesced loads whatever their layout (the contiguous dimension is mapped
+// to consecutive threads), converted once to the matrix-core type and written to LDS;
+// the next chunk's global loads are issued into registers before the current chunk's
+// MFMAs.  The 128 tile halves the operand bytes per flop; the 64 tile gives four times
+// as many workgroups for launches too small to fill the chip with 128 tiles.
 //   kF64:    v_mfma_f64_16x16x4f64          (LDS tiles [k][i], FP64)
 //   kF32:    v_mfma_f32_16x16x4f32          (LDS tiles [k][i], FP32)
 //   kBF16x3: v_mfma_f32_16x16x32_bf16 x 3   (LDS tiles [i][k], hi and lo parts)
@@ -26,23 +29,22 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 enum StMode { sF64 = 0, sF32 = 1, sBF16x3 = 2, sBF16 = 3 };
 
 constexpr int KC = 32;          // K chunk
-constexpr int PADF = 68;        // row pitch (elements) of [k][i] FP64/FP32 tiles
 constexpr int PADB = 40;        // row pitch (bf16) of [i][k] tiles: 80 bytes, 16-byte aligned
 
-template <int MODE> struct Stage;
+template <int MODE, int TM> struct Stage;
 
-template <> struct Stage<sF64> {
-  double a[KC][PADF], b[KC][PADF];
+template <int TM> struct Stage<sF64, TM> {
+  double a[KC][TM + 4], b[KC][TM + 4];
   __device__ void put_a(int i, int k, double v) { a[k][i] = v; }
   __device__ void put_b(int j, int k, double v) { b[k][j] = v; }
 };
-template <> struct Stage<sF32> {
-  float a[KC][PADF], b[KC][PADF];
+template <int TM> struct Stage<sF32, TM> {
+  float a[KC][TM + 4], b[KC][TM + 4];
   __device__ void put_a(int i, int k, double v) { a[k][i] = (float)v; }
   __device__ void put_b(int j, int k, double v) { b[k][j] = (float)v; }
 };
-template <> struct Stage<sBF16x3> {
-  __bf16 ah[64][PADB], al[64][PADB], bh[64][PADB], bl[64][PADB];
+template <int TM> struct Stage<sBF16x3, TM> {
+  __bf16 ah[TM][PADB], al[TM][PADB], bh[TM][PADB], bl[TM][PADB];
   __device__ void put_a(int i, int k, double v) {
     const float f = (float)v; const __bf16 h = (__bf16)f;
     ah[i][k] = h; al[i][k] = (__bf16)(f - (float)h);
@@ -52,8 +54,8 @@ template <> struct Stage<sBF16x3> {
     bh[j][k] = h; bl[j][k] = (__bf16)(f - (float)h);
   }
 };
-template <> struct Stage<sBF16> {
-  __bf16 ah[64][PADB], bh[64][PADB];
+template <int TM> struct Stage<sBF16, TM> {
+  __bf16 ah[TM][PADB], bh[TM][PADB];
   __device__ void put_a(int i, int k, double v) { ah[i][k] = (__bf16)(float)v; }
   __device__ void put_b(int j, int k, double v) { bh[j][k] = (__bf16)(float)v; }
 };
@@ -61,95 +63,117 @@ template <> struct Stage<sBF16> {
 template <int MODE> struct Acc { typedef v4f T; };
 template <> struct Acc<sF64> { typedef v4d T; };
 
-// Global loads of one 64 x 32 operand chunk (8 values per thread), coalesced along the
-// operand's contiguous dimension.  Element (r, k) is at base + r * rs + k * ks, valid
-// for r < rmax, k < kmax.
+// Global loads of one TM x 32 operand chunk by NT threads (TM * 32 / NT values per
+// thread), coalesced along the operand's contiguous dimension.  Element (r, k) is at
+// base + r * rs + k * ks, valid for r < rmax, k < kmax.
+template <int TM, int NT>
 struct ChunkLoader {
-  double v[8];
+  static constexpr int NV = TM * 32 / NT, RP = TM / 64;
+  double v[NV];
+  __device__ static void pos(int u, bool rcont, int& r, int& k) {
+    const int t = threadIdx.x;
+    if (rcont) { r = (t & 63) + 64 * (u % RP); k = (t >> 6) + (NT / 64) * (u / RP); }
+    else       { k = t & 31; r = (t >> 5) + (NT / 32) * u; }
+  }
   __device__ void load(const double* base, int64_t rs, int64_t ks, int rmax, int kmax, int k0,
                        bool rcont) {
-    const int t = threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < NV; ++u) {
       int r, k;
-      if (rcont) { r = t & 63; k = (t >> 6) + 4 * u; }
-      else       { k = t & 31; r = (t >> 5) + 8 * u; }
+      pos(u, rcont, r, k);
       const int kk = k0 + k;
       v[u] = (r < rmax && kk < kmax) ? base[r * rs + (int64_t)kk * ks] : 0.0;
     }
   }
   template <class S>
   __device__ void store_a(S& st, bool rcont) {
-    const int t = threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < NV; ++u) {
       int r, k;
-      if (rcont) { r = t & 63; k = (t >> 6) + 4 * u; }
-      else       { k = t & 31; r = (t >> 5) + 8 * u; }
+      pos(u, rcont, r, k);
       st.put_a(r, k, v[u]);
     }
   }
   template <class S>
   __device__ void store_b(S& st, bool rcont) {
-    const int t = threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < NV; ++u) {
       int r, k;
-      if (rcont) { r = t & 63; k = (t >> 6) + 4 * u; }
-      else       { k = t & 31; r = (t >> 5) + 8 * u; }
+      pos(u, rcont, r, k);
       st.put_b(r, k, v[u]);
     }
   }
 };
 
-template <int MODE>
-__device__ __forceinline__ void mma_chunk(Stage<MODE>& st, typename Acc<MODE>::T (&acc)[2][2],
+// Wave layout of a TM x TM tile: waves at row strips of RW rows and column halves.
+template <int TM> struct Layout {
+  static constexpr int NW = (TM == 128) ? 8 : 4;   // waves per workgroup
+  static constexpr int NT = 64 * NW;               // threads
+  static constexpr int RW = 2 * TM / NW;           // rows per wave strip (32)
+  static constexpr int CW = TM / 2;                // columns per wave half
+  static constexpr int BR = RW / 16, BC = CW / 16; // MFMA blocks per wave
+};
+
+template <int MODE, int TM>
+__device__ __forceinline__ void mma_chunk(Stage<MODE, TM>& st,
+                                          typename Acc<MODE>::T (&acc)[Layout<TM>::BR][Layout<TM>::BC],
                                           int wr, int wc, int lane) {
+  using Ly = Layout<TM>;
+  constexpr int BR = Ly::BR, BC = Ly::BC;
   const int li = lane & 15, lk = lane >> 4;
+  const int r0 = wr * Ly::RW, c0 = wc * Ly::CW;
   if constexpr (MODE == sF64 || MODE == sF32) {
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 4) {
       if constexpr (MODE == sF64) {
-        double av[2], bv[2];
-        for (int b = 0; b < 2; ++b) {
-          av[b] = st.a[ks + lk][wr * 32 + b * 16 + li];
-          bv[b] = st.b[ks + lk][wc * 32 + b * 16 + li];
-        }
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y)
+        double av[BR], bv[BC];
+#pragma unroll
+        for (int b = 0; b < BR; ++b) av[b] = st.a[ks + lk][r0 + b * 16 + li];
+#pragma unroll
+        for (int b = 0; b < BC; ++b) bv[b] = st.b[ks + lk][c0 + b * 16 + li];
+#pragma unroll
+        for (int x = 0; x < BR; ++x)
+#pragma unroll
+          for (int y = 0; y < BC; ++y)
             acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
       } else {
-        float av[2], bv[2];
-        for (int b = 0; b < 2; ++b) {
-          av[b] = st.a[ks + lk][wr * 32 + b * 16 + li];
-          bv[b] = st.b[ks + lk][wc * 32 + b * 16 + li];
-        }
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y)
+        float av[BR], bv[BC];
+#pragma unroll
+        for (int b = 0; b < BR; ++b) av[b] = st.a[ks + lk][r0 + b * 16 + li];
+#pragma unroll
+        for (int b = 0; b < BC; ++b) bv[b] = st.b[ks + lk][c0 + b * 16 + li];
+#pragma unroll
+        for (int x = 0; x < BR; ++x)
+#pragma unroll
+          for (int y = 0; y < BC; ++y)
             acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x], bv[y], acc[x][y], 0, 0, 0);
       }
     }
   } else {
-    v8bf ah[2], bh[2];
-    for (int b = 0; b < 2; ++b) {
-      ah[b] = *reinterpret_cast<const v8bf*>(&st.ah[wr * 32 + b * 16 + li][8 * lk]);
-      bh[b] = *reinterpret_cast<const v8bf*>(&st.bh[wc * 32 + b * 16 + li][8 * lk]);
-    }
+    v8bf ah[BR], bh[BC];
+#pragma unroll
+    for (int b = 0; b < BR; ++b) ah[b] = *reinterpret_cast<const v8bf*>(&st.ah[r0 + b * 16 + li][8 * lk]);
+#pragma unroll
+    for (int b = 0; b < BC; ++b) bh[b] = *reinterpret_cast<const v8bf*>(&st.bh[c0 + b * 16 + li][8 * lk]);
     if constexpr (MODE == sBF16x3) {
-      v8bf al[2], bl[2];
-      for (int b = 0; b < 2; ++b) {
-        al[b] = *reinterpret_cast<const v8bf*>(&st.al[wr * 32 + b * 16 + li][8 * lk]);
-        bl[b] = *reinterpret_cast<const v8bf*>(&st.bl[wc * 32 + b * 16 + li][8 * lk]);
-      }
-      for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y) {
+      v8bf al[BR], bl[BC];
+#pragma unroll
+      for (int b = 0; b < BR; ++b) al[b] = *reinterpret_cast<const v8bf*>(&st.al[r0 + b * 16 + li][8 * lk]);
+#pragma unroll
+      for (int b = 0; b < BC; ++b) bl[b] = *reinterpret_cast<const v8bf*>(&st.bl[c0 + b * 16 + li][8 * lk]);
+#pragma unroll
+      for (int x = 0; x < BR; ++x)
+#pragma unroll
+        for (int y = 0; y < BC; ++y) {
           acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
           acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
           acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
         }
     } else {
-      for (int x = 0; x < 2; ++x)
-        for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int x = 0; x < BR; ++x)
+#pragma unroll
+        for (int y = 0; y < BC; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
     }
   }
@@ -163,15 +187,16 @@ __device__ __forceinline__ void res_pos(int lane, int e, int& i, int& j) {
   j = lane & 15;
 }
 
-// Accumulates P = A(r0.., :) B(c0.., :)^T for the workgroup's 64x64 tile over k < K.
-template <int MODE>
-__device__ void tile_product(Stage<MODE>& st, typename Acc<MODE>::T (&acc)[2][2],
+// Accumulates P = A(r0.., :) B(c0.., :)^T for the workgroup's TM x TM tile over k < K.
+template <int MODE, int TM>
+__device__ void tile_product(Stage<MODE, TM>& st,
+                             typename Acc<MODE>::T (&acc)[Layout<TM>::BR][Layout<TM>::BC],
                              const double* A, int64_t ars, int64_t aks, int amax,
                              const double* B, int64_t brs, int64_t bks, int bmax, int K) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const bool acont = (ars == 1), bcont = (brs == 1);
-  ChunkLoader la, lb;
+  ChunkLoader<TM, Layout<TM>::NT> la, lb;
   if (K > 0) {
     la.load(A, ars, aks, amax, K, 0, acont);
     lb.load(B, brs, bks, bmax, K, 0, bcont);
@@ -185,37 +210,42 @@ __device__ void tile_product(Stage<MODE>& st, typename Acc<MODE>::T (&acc)[2][2]
       la.load(A, ars, aks, amax, K, k0 + KC, acont);
       lb.load(B, brs, bks, bmax, K, k0 + KC, bcont);
     }
-    mma_chunk<MODE>(st, acc, wr, wc, lane);
+    mma_chunk<MODE, TM>(st, acc, wr, wc, lane);
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_gemm_staged(const GemmTask* __restrict__ tasks,
-                                                     double* __restrict__ arena,
-                                                     const int32_t* __restrict__ ilim) {
-  __shared__ Stage<MODE> st;
+template <int MODE, int TM>
+__global__ __launch_bounds__(Layout<TM>::NT) void k_gemm_staged(const GemmTask* __restrict__ tasks,
+                                                               double* __restrict__ arena,
+                                                               const int32_t* __restrict__ ilim) {
+  using Ly = Layout<TM>;
+  __shared__ Stage<MODE, TM> st;
   const GemmTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int n = T.nlim >= 0 ? min(T.n, ilim[T.nlim]) : T.n;
   const int K = T.klim >= 0 ? min(T.k, ilim[T.klim]) : T.k;
   if (T.j0 >= n) return;
-  typename Acc<MODE>::T acc[2][2];
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y)
+  typename Acc<MODE>::T acc[Ly::BR][Ly::BC];
+#pragma unroll
+  for (int x = 0; x < Ly::BR; ++x)
+#pragma unroll
+    for (int y = 0; y < Ly::BC; ++y)
       for (int e = 0; e < 4; ++e) acc[x][y][e] = 0;
   const double* A = arena + T.a + (int64_t)T.i0 * T.ais;
   const double* B = arena + T.b + (int64_t)T.j0 * T.bjs;
-  tile_product<MODE>(st, acc, A, T.ais, T.aks, T.m - T.i0, B, T.bjs, T.bks, n - T.j0, K);
+  tile_product<MODE, TM>(st, acc, A, T.ais, T.aks, T.m - T.i0, B, T.bjs, T.bks, n - T.j0, K);
   __syncthreads();                         // A/B may alias C (in-place triangular solve)
   double* C = arena + T.c;
-  for (int x = 0; x < 2; ++x)
-    for (int y = 0; y < 2; ++y)
+#pragma unroll
+  for (int x = 0; x < Ly::BR; ++x)
+#pragma unroll
+    for (int y = 0; y < Ly::BC; ++y)
       for (int e = 0; e < 4; ++e) {
         int ii, jj;
         res_pos<MODE>(lane, e, ii, jj);
-        const int i = T.i0 + wr * 32 + x * 16 + ii;
-        const int j = T.j0 + wc * 32 + y * 16 + jj;
+        const int i = T.i0 + wr * Ly::RW + x * 16 + ii;
+        const int j = T.j0 + wc * Ly::CW + y * 16 + jj;
         if (i < T.m && j < n) {
           double* cp = C + i + (int64_t)j * T.ldc;
           const double v = T.alpha * (double)acc[x][y][e];
@@ -226,14 +256,17 @@ __global__ __launch_bounds__(256) void k_gemm_staged(const GemmTask* __restrict_
 }
 
 // Schur-complement update tile: the same staged product on gathered row runs of X,
-// scattered into the LDS-resident target tile (contract as in k_update_f64).
+// scattered into the LDS-resident 64 x 64 target tile.  The workgroup owns the tile:
+// it subtracts every descendant's product X(a:b) X(c:d)^T (scattered through the
+// relative map) in entry order and writes the tile back once -- no atomics, so the
+// result does not depend on scheduling.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_update_staged(const UpdTile* __restrict__ tiles,
                                                        const UpdEntry* __restrict__ ents,
                                                        const int32_t* __restrict__ relmap,
                                                        double* __restrict__ arena,
                                                        const int32_t* __restrict__ ilim) {
-  __shared__ Stage<MODE> st;
+  __shared__ Stage<MODE, 64> st;
   __shared__ double tile[64][65];
   __shared__ int32_t rmap[64], cmap[64];
   const UpdTile T = tiles[blockIdx.x];
@@ -259,7 +292,7 @@ __global__ __launch_bounds__(256) void k_update_staged(const UpdTile* __restrict
       for (int y = 0; y < 2; ++y)
         for (int q = 0; q < 4; ++q) acc[x][y][q] = 0;
     const double* X = arena + E.x;
-    tile_product<MODE>(st, acc, X + E.a, 1, E.ldx, nr, X + E.c, 1, E.ldx, nc, K);
+    tile_product<MODE, 64>(st, acc, X + E.a, 1, E.ldx, nr, X + E.c, 1, E.ldx, nc, K);
     __syncthreads();                       // maps visible; staged tiles no longer needed
     for (int x = 0; x < 2; ++x)
       for (int y = 0; y < 2; ++y)
@@ -278,15 +311,22 @@ __global__ __launch_bounds__(256) void k_update_staged(const UpdTile* __restrict
   }
 }
 
-void launch_gemm_staged(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
-                        hipStream_t s) {
-  if (n <= 0) return;
+template <int TM>
+static void launch_gemm_tm(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
+                           hipStream_t s) {
   switch (mode) {
-    case sF64: hipLaunchKernelGGL(k_gemm_staged<sF64>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
-    case sF32: hipLaunchKernelGGL(k_gemm_staged<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
-    case sBF16x3: hipLaunchKernelGGL(k_gemm_staged<sBF16x3>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
-    default: hipLaunchKernelGGL(k_gemm_staged<sBF16>, dim3(n), dim3(256), 0, s, t, arena, ilim); break;
+    case sF64: hipLaunchKernelGGL((k_gemm_staged<sF64, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
+    case sF32: hipLaunchKernelGGL((k_gemm_staged<sF32, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
+    case sBF16x3: hipLaunchKernelGGL((k_gemm_staged<sBF16x3, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
+    default: hipLaunchKernelGGL((k_gemm_staged<sBF16, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
   }
+}
+
+void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
+                        const int32_t* ilim, hipStream_t s) {
+  if (n <= 0) return;
+  if (tile == 128) launch_gemm_tm<128>(mode, t, n, arena, ilim, s);
+  else launch_gemm_tm<64>(mode, t, n, arena, ilim, s);
 }
 
 void launch_update_staged(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,

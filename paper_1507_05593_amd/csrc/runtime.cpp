@@ -11,6 +11,9 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <array>
 #include <chrono>
 #include <climits>
@@ -272,10 +275,65 @@ struct PanelDesc {
   bool skip_mid = false;          // ... or are not touched at all
 };
 
+// Merges a GEMM command's 64 x 64 output tiles (tasks [off, end) of the list, in the
+// order the builder cut them) into 128 x 128 tiles: tasks of one product share every
+// field but the tile origin and, for a triangular right operand, k; four neighbours
+// (origins relative to the product's first tile) become one task whose k is the
+// largest of theirs.  Returns the new task count.  Blocks the 64 cut skipped (strictly
+// above the diagonal of a symmetric product) may be computed inside a merged tile;
+// those entries are never read.
+static int64_t retile128(std::vector<GemmTask>& g, int64_t off) {
+  struct Key {
+    GemmTask t;
+    bool same(const GemmTask& u) const {
+      return u.a == t.a && u.b == t.b && u.c == t.c && u.d == t.d && u.ais == t.ais &&
+             u.aks == t.aks && u.bjs == t.bjs && u.bks == t.bks && u.ldc == t.ldc && u.m == t.m &&
+             u.n == t.n && u.nlim == t.nlim && u.klim == t.klim && u.alpha == t.alpha &&
+             u.beta == t.beta;
+    }
+  };
+  std::vector<GemmTask> out;
+  std::vector<std::pair<int64_t, int64_t>> org;           // per product: origin (i0, j0)
+  std::vector<size_t> prod_first;                         // first output index of each product
+  std::map<std::tuple<size_t, int32_t, int32_t>, size_t> slot;
+  std::vector<Key> prods;
+  const int64_t end = (int64_t)g.size();
+  for (int64_t i = off; i < end; ++i) {
+    const GemmTask& u = g[i];
+    size_t pi = prods.size();
+    for (size_t q = prods.size(); q-- > 0;) {
+      if (prods[q].same(u)) { pi = q; break; }
+    }
+    if (pi == prods.size()) {
+      prods.push_back(Key{u});
+      int64_t i0 = u.i0, j0 = u.j0;
+      for (int64_t v = i; v < end; ++v)            // the product's smallest origins
+        if (Key{u}.same(g[v])) { i0 = std::min<int64_t>(i0, g[v].i0); j0 = std::min<int64_t>(j0, g[v].j0); }
+      org.push_back({i0, j0});
+    }
+    const int32_t bi = (int32_t)((u.i0 - org[pi].first) / 128), bj = (int32_t)((u.j0 - org[pi].second) / 128);
+    auto key = std::make_tuple(pi, bi, bj);
+    auto it = slot.find(key);
+    if (it == slot.end()) {
+      GemmTask t = u;
+      t.i0 = (int32_t)(org[pi].first + 128 * bi);
+      t.j0 = (int32_t)(org[pi].second + 128 * bj);
+      slot[key] = out.size();
+      out.push_back(t);
+    } else {
+      GemmTask& t = out[it->second];
+      t.k = std::max(t.k, u.k);
+    }
+  }
+  g.resize(off);
+  g.insert(g.end(), out.begin(), out.end());
+  return (int64_t)out.size();
+}
+
 struct Builder {
   Handle& h;
   FactorPlan& P;
-  int32_t lp_update = 0;   // 0: FP64 MFMA; else the low-precision mode of launch_gemm_lp
+  int32_t lp_update = 0;   // 0: FP64 MFMA; else the low-precision mode of launch_gemm_staged
   int32_t lp_sample = 0;
   Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {
     if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; }
@@ -285,9 +343,33 @@ struct Builder {
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
            int64_t b = 0, double v = 0) {
     if (count <= 0) return;
+    int64_t alt_off = -1, alt_count = 0;
+    if (type == kCmdGemm) {
+      // the command's 64-tile tasks are the last ones pushed; with a fixed tile option
+      // they are cut to it, else a 128-tile copy is kept for the tile tuner
+      b = 64;
+      if (off + count == (int64_t)P.gemm.size()) {
+        int64_t last_col = 0;
+        for (int64_t i = off; i < off + count; ++i)
+          if (P.gemm[i].n - P.gemm[i].j0 <= kTile) ++last_col;
+        // products mostly one 64-column tile wide (the in-place triangular solves)
+        // would leave half of every 128 tile idle; launches under 16 tiles would leave
+        // most of the chip idle with a quarter as many workgroups
+        const bool narrow = 2 * last_col > count;
+        if (h.opt.gemm_tile == 128) {
+          count = retile128(P.gemm, off);
+          b = 128;
+        } else if (h.opt.gemm_tile == 0 && !narrow && count >= 16) {
+          alt_off = (int64_t)P.gemm.size();
+          P.gemm.insert(P.gemm.end(), P.gemm.begin() + off, P.gemm.begin() + off + count);
+          alt_count = retile128(P.gemm, alt_off);
+        }
+      }
+    }
     Cmd c;
     c.type = type; c.klass = klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
     c.flops = flops;
+    c.alt_off = alt_off; c.alt_count = alt_count;
     P.cmds.push_back(c);
   }
 
@@ -696,6 +778,54 @@ Error upload_plan(DevArray<T>& d, const std::vector<T>& v) { return upload(d, v)
 
 }  // namespace
 
+// Tile tuner.  Every product launch that kept a 128-tile alternative is run with
+// both task lists on the handle's own arena (one warm-up and one hipEvent-timed launch
+// each, on the handle's private stream) and keeps the faster; the 64 list stays unless
+// 128 is at least 3 % faster.  The arena holds scratch at this point -- the
+// factorisation writes every region it reads before reading it -- and the device ranks
+// are set to their largest value so that rank-limited products run at full width.
+static Error tune_tiles(Handle& h, FactorPlan& P) {
+  bool any = false;
+  for (const Cmd& c : P.cmds) any |= (c.alt_off >= 0);
+  if (!any) return kOk;
+  hipStream_t s = h.cap_stream;
+  double* A = h.arena.p;
+  int32_t* I = h.ints.p;
+  launch_fill_i32(I + h.i_ranks, h.S.M(), INT_MAX, s);
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  Error err = kOk;
+  for (Cmd& c : P.cmds) {
+    if (c.alt_off < 0) continue;
+    const int mode = (int)c.a;
+    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, s);
+    HIPCHK(hipEventRecord(ev[0], s));
+    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, s);
+    HIPCHK(hipEventRecord(ev[1], s));
+    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, s);
+    HIPCHK(hipEventRecord(ev[2], s));
+    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, s);
+    HIPCHK(hipEventRecord(ev[3], s));
+    HIPCHK(hipEventSynchronize(ev[3]));
+    float t64 = 0, t128 = 0;
+    HIPCHK(hipEventElapsedTime(&t64, ev[0], ev[1]));
+    HIPCHK(hipEventElapsedTime(&t128, ev[2], ev[3]));
+    if (t128 < 0.97f * t64) {
+      c.off = c.alt_off;
+      c.count = c.alt_count;
+      c.b = 128;
+      ++P.tuned128;
+    }
+    ++P.tuned;
+    c.alt_off = -1;
+  }
+  launch_fill_i32(I + h.i_ranks, h.S.M(), 0, s);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return err;
+}
+
 static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t precision) {
   auto P = std::make_unique<FactorPlan>();
   P->compressed = compressed;
@@ -748,6 +878,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gs_out, P->gs_out)).code) return e;
   if ((e = upload(P->d_gs_ld, P->gs_ld)).code) return e;
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
+  if ((e = tune_tiles(h, *P)).code) return e;
   auto& slot = h.fplans[precision];
   if (slot && slot->graph) (void)hipGraphExecDestroy(slot->graph);
   slot = std::move(P);
@@ -756,7 +887,39 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
 
 // ------------------------------------------------------------------ executor
 
-struct EventPair { hipEvent_t a, b; int32_t klass; double flops; };
+struct EventPair { hipEvent_t a, b; int32_t klass, kid; double flops; };
+
+static const char* const kKernelNames[RSC_KERNELS] = {
+    "gemm_staged_f64", "gemm_staged_f32", "gemm_staged_bf16x3", "gemm_staged_bf16",
+    "update_staged_f64", "update_staged_f32", "update_staged_bf16x3", "update_staged_bf16",
+    "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
+    "trunc_compact", "assemble", "fill", "fwd_block", "coldot", "trsv_bwd", "gemv_n",
+    "gather", "other"};
+
+int32_t kernel_id(int32_t type, int64_t a) {
+  switch (type) {
+    case kCmdGemm: return (int32_t)(0 + (a & 3));
+    case kCmdUpdate: return (int32_t)(4 + (a & 3));
+    case kCmdPotrf: return 8;
+    case kCmdPhilox: return 9;
+    case kCmdGramScale: return 10;
+    case kCmdTruncPrep: return 11;
+    case kCmdTruncPower: return 12;
+    case kCmdTruncX0: return 13;
+    case kCmdTruncP: return 14;
+    case kCmdTruncCompact: return 15;
+    case kCmdAssemble: case kCmdIdent: return 16;
+    case kCmdFill: case kCmdFillInts: return 17;
+    case kCmdFwdBlock: return 18;
+    case kCmdColDot: return 19;
+    case kCmdTrsvBwd: return 20;
+    case kCmdGemvN: return 21;
+    case kCmdGatherRows: case kCmdRowGather: case kCmdGatherPerm: case kCmdScatterPerm: return 22;
+    default: return 23;
+  }
+}
+
+const char* kernel_name(int32_t k) { return (k >= 0 && k < RSC_KERNELS) ? kKernelNames[k] : ""; }
 
 static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const SolvePlan* Q,
                        hipStream_t s) {
@@ -771,7 +934,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       launch_update_staged((int)c.a, P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A, I, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
-    case kCmdGemm: launch_gemm_staged((int)c.a, P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
     case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, 0, s); break;
     case kCmdGramScale:
       launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,
@@ -810,6 +973,7 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
       HIPCHK(hipEventCreate(&ep.a));
       HIPCHK(hipEventCreate(&ep.b));
       ep.klass = c.klass;
+      ep.kid = kernel_id(c.type, c.a);
       ep.flops = c.flops;
       HIPCHK(hipEventRecord(ep.a, s));
       launch_cmd(h, c, P, Q, s);
@@ -830,6 +994,9 @@ static Error collect_events(Handle& h, std::vector<EventPair>& evs) {
     h.prof.launches[ep.klass] += 1;
     h.prof.ms[ep.klass] += ms;
     h.prof.flops[ep.klass] += ep.flops;
+    h.kprof_launches[ep.kid] += 1;
+    h.kprof_ms[ep.kid] += ms;
+    h.kprof_flops[ep.kid] += ep.flops;
     (void)hipEventDestroy(ep.a);
     (void)hipEventDestroy(ep.b);
   }

@@ -21,11 +21,15 @@ struct Error {
 
 // One launch of the executor.
 enum CmdType : int32_t {
-  kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdUpdateLow, kCmdPotrf, kCmdGemm,
+  kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdTrsvBwd, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdConvertLow, kCmdGatherRows, kCmdFwdBlock,
+  kCmdGatherRows, kCmdFwdBlock,
 };
+
+// Kernel identity of a command for the per-kernel profile (index into kernel_name()).
+int32_t kernel_id(int32_t type, int64_t a);
+const char* kernel_name(int32_t k);
 
 struct Cmd {
   int32_t type;
@@ -35,6 +39,8 @@ struct Cmd {
   int64_t a, b;         // command-specific
   double v;             // command-specific
   double flops;         // algorithmic flops of the launch (profiling)
+  int64_t alt_off = -1; // product launch: 128-tile task list awaiting the tile tuner
+  int64_t alt_count = 0;
 };
 
 template <class T>
@@ -66,6 +72,7 @@ struct CompSlot {
 // A launch plan (command list + task arrays) for one factor mode.
 struct FactorPlan {
   bool compressed = false;
+  int32_t tuned = 0, tuned128 = 0;   // product launches tried by the tile tuner / set to 128
   int32_t precision = RSC_FP64;
   double tol = 0;
   std::vector<Cmd> cmds;
@@ -163,6 +170,9 @@ struct Handle {
   // profiling
   bool profiling = false;
   rsc_profile prof{};
+  int64_t kprof_launches[RSC_KERNELS] = {};
+  double kprof_ms[RSC_KERNELS] = {};
+  double kprof_flops[RSC_KERNELS] = {};
 };
 
 // analyze-phase layout (no device work)

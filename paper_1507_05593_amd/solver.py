@@ -33,13 +33,14 @@ def _dev_f64(t, n, name):
 
 
 def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.0, seed=0,
-                 precision="fp64", use_graph=True, retry=True) -> Options:
+                 precision="fp64", use_graph=True, retry=True, gemm_tile=0) -> Options:
     o = Options()
     lib().rsc_default_options(C.byref(o))
     o.leaf_max, o.tau_O, o.oversample, o.power_iters = leaf_max, tau_O, oversample, power_iters
     o.alpha_O, o.seed = float(alpha_O), int(seed)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.use_graph, o.retry = int(bool(use_graph)), int(bool(retry))
+    o.gemm_tile = int(gemm_tile)
     return o
 
 
@@ -175,6 +176,15 @@ class RSCSolver:
         check(lib().rsc_get_profile(self._h, C.byref(p)))
         return {k: dict(launches=p.launches[i], ms=p.ms[i], flops=p.flops[i])
                 for i, k in enumerate(_lib.K_CLASSES)}
+
+    def kernel_profile(self) -> dict:
+        """Per-kernel launches, hipEvent ms and algorithmic flops while profiling."""
+        out = {}
+        for k in range(_lib.RSC_KERNELS):
+            name, n, ms, fl = C.c_char_p(), C.c_int64(), C.c_double(), C.c_double()
+            check(lib().rsc_get_kernel_profile(self._h, k, C.byref(name), C.byref(n), C.byref(ms), C.byref(fl)))
+            out[name.value.decode()] = dict(launches=n.value, ms=ms.value, flops=fl.value)
+        return out
 
 
 def grad_faces(face_i: torch.Tensor, face_j: torch.Tensor, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:

@@ -56,6 +56,26 @@ def test_exact_factor_blocks_match_oracle(dims, sigma, leaf):
     _check_blocks(sol, F, 1e-12)
 
 
+@pytest.mark.parametrize("tile", [64, 128])
+def test_fixed_tile_sizes_match_oracle(tile):
+    # every product launch cut to one tile edge: exact blocks to 1e-12 and the
+    # compressed factor's PCG against the oracle's
+    print("case tile", tile, flush=True)
+    p = grid_problem((22, 20, 18), sigma=1.0, seed=6)
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 0.0, Options())
+    sol = _sol(p, gemm_tile=tile)
+    sol.factor(_vals(p), 0.0)
+    torch.cuda.synchronize()
+    _check_blocks(sol, F, 1e-12)
+    Fc = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-2, Options(seed=3))
+    sc = _sol(p, gemm_tile=tile, seed=3)
+    sc.factor(_vals(p), 1e-2)
+    x, info = sc.pcg(_vec(p.b), rtol=1e-8)
+    res = o_solve(Fc, p.matrix(), p.b, rtol=1e-8)
+    assert info["converged"] and abs(info["iters"] - res.iters) <= max(1, 0.1 * res.iters)
+
+
 def test_exact_factor_residual_and_pcg():
     p = grid_problem((14, 13, 12), sigma=1.0, seed=3)
     sol = _sol(p)
