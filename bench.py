@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--workload", default="diffusion3d_96")
     ap.add_argument("--precision", default="", choices=["", "fp64", "fp32", "bf16"])
     ap.add_argument("--compare", default="auto", help="second precision timed beside (none to skip)")
-    ap.add_argument("--cpu-sample-side", type=int, default=32)
+    ap.add_argument("--cpu-sample-side", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying hipGraphs")
@@ -205,7 +205,8 @@ def mfma_util(kernels, factor_ms):
 def pcg_hbm(desc, stats, iters, pcg_ms):
     it = iters if isinstance(iters, int) else max(iters)
     n, nnz = desc["n"], desc["nnz"]
-    per_iter = 12.0 * nnz + 24.0 * n + 2.0 * stats["bytes_factor"] + 10.0 * 8.0 * n
+    # SpMV, one preconditioner apply (both sweeps: bytes_factor), ten vector passes
+    per_iter = 12.0 * nnz + 24.0 * n + stats["bytes_factor"] + 10.0 * 8.0 * n
     total = (it + 1) * per_iter
     gbs = total / (pcg_ms * 1e-3) if pcg_ms > 0 else 0.0
     return {"bytes_per_iter": per_iter, "achieved": round(gbs / 1e9, 1), "peak": 8000.0, "unit": "GB/s",

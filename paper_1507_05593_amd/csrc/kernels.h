@@ -26,13 +26,15 @@ void launch_trunc_p(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_compact(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
-void launch_fwd_block(const FwdTile* t, int n, const FwdEntry* e, const int32_t* relmap,
-                      double* arena, const int32_t* ilim, hipStream_t s);
+void launch_fwd_part(const FwdChunk* c, int n, const FwdTile* t, const FwdEntry* e,
+                     const int32_t* relmap, const double* arena, const int32_t* ilim, double* part,
+                     hipStream_t s);
+void launch_row_part(const RowChunk* c, int n, const double* arena, double* part, hipStream_t s);
+void launch_part_apply(const PartApply* t, int n, const double* part, double* arena, hipStream_t s);
 void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
                         double* dst, hipStream_t s);
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
                    const int32_t* ilim, hipStream_t s);
-void launch_trsv_bwd(const RowTask* t, int n, double* arena, hipStream_t s);
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s);
 void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);

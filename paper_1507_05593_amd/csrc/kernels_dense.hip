@@ -70,7 +70,8 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 // mode 0: a pivot that is not positive and finite records the supernode in
 //         status[0] (smallest id wins) and is replaced by 1 so the sweep stays finite.
 // mode 1 (orthonormalisation): a pivot <= 1e-14 * scale marks the column dependent:
-//         its L column and its row and column of the inverse become zero.
+//         its L column and its row and column of the inverse become zero;
+// mode 2: the same with the threshold 1e-8 * scale.
 // Right-looking elimination four columns at a time, register-blocked: thread (tx, ty)
 // of the 16 x 16 grid owns entries (ty + 16a, tx + 16b), a, b < 4, of L and of W
 // (W starts as I and ends as L^{-1}).  Step K publishes the four-column panel and rows
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
       L[a][b] = tile[i][j];
       W[a][b] = (i == j && i < nb) ? 1.0 : 0.0;
     }
-  const double dscale = (T.mode == 1) ? arena[T.scale_off] : 0.0;
+  const double dscale = (T.mode >= 1) ? arena[T.scale_off] * (T.mode == 2 ? 1e-8 : 1e-14) : 0.0;
   bool bad = false;
   const int nsteps = (nb + 3) >> 2;
   for (int K = 0; K < nsteps; ++K) {
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
         d = 1.0;                                   // past the block edge: identity
       } else if (T.mode == 0) {
         if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
-      } else if (!(d > 1e-14 * dscale) || !isfinite(d)) {
+      } else if (!(d > dscale) || !isfinite(d)) {
         dk = true;
         d = 1.0;
       }

@@ -56,19 +56,23 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
     arena[T.out + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
-// Forward-sweep target block: every descendant's X(a:b, :) v is accumulated into
-// LDS and subtracted from y once.  Entry e goes to wave (e - e0) mod 4 (lane = row,
-// unrolled inner loop); the four per-wave accumulators are added in a fixed order.
-__global__ __launch_bounds__(256) void k_fwd_block(const FwdTile* __restrict__ tiles,
-                                                   const FwdEntry* __restrict__ ents,
-                                                   const int32_t* __restrict__ relmap,
-                                                   double* __restrict__ arena,
-                                                   const int32_t* __restrict__ ilim) {
+// Forward-sweep chunk: the products X(a:b, :) v of a run of descendant entries of one
+// target block, accumulated in LDS (entry e goes to wave (e - e0) mod 4, lane = row,
+// unrolled inner loop; the four per-wave sums are added in a fixed order) and written
+// as one 64-entry partial block.  k_part_apply subtracts the block's partials from y.
+__global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ chunks,
+                                                  const FwdTile* __restrict__ tiles,
+                                                  const FwdEntry* __restrict__ ents,
+                                                  const int32_t* __restrict__ relmap,
+                                                  const double* __restrict__ arena,
+                                                  const int32_t* __restrict__ ilim,
+                                                  double* __restrict__ part) {
   __shared__ double acc[4][64];
-  const FwdTile T = tiles[blockIdx.x];
+  const FwdChunk C = chunks[blockIdx.x];
+  const FwdTile T = tiles[C.tile];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   acc[w][lane] = 0.0;
-  for (int e = T.e0 + w; e < T.e1; e += 4) {
+  for (int e = C.e0 + w; e < C.e1; e += 4) {
     const FwdEntry E = ents[e];
     const int nr = E.b - E.a;
     const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
@@ -82,10 +86,53 @@ __global__ __launch_bounds__(256) void k_fwd_block(const FwdTile* __restrict__ t
     }
   }
   __syncthreads();
-  if (threadIdx.x < T.nrows) {
+  if (threadIdx.x < 64) {
     const int r = threadIdx.x;
-    arena[T.y + r] -= (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+    part[(int64_t)C.slot * 64 + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
   }
+}
+
+// Backward diagonal solve chunk: rows i in [i0, i0 + 64) (lanes) of M (w - s) over the
+// columns [t0, t1); v = w - s is staged in LDS, the four waves take consecutive column
+// quarters, and their sums are added in a fixed order into one partial block.
+__global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ chunks,
+                                                  const double* __restrict__ arena,
+                                                  double* __restrict__ part) {
+  __shared__ double v[kRowChunkMax];
+  __shared__ double red[4][64];
+  const RowChunk T = chunks[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = T.t1 - T.t0;
+  for (int t = threadIdx.x; t < n; t += 256) {
+    const double a = arena[T.w + T.t0 + t];
+    v[t] = T.s >= 0 ? a - arena[T.s + T.t0 + t] : a;
+  }
+  __syncthreads();
+  const int i = T.i0 + lane;
+  double acc = 0.0;
+  if (i < T.c) {
+    const int per = (n + 3) / 4;
+    const int ta = T.t0 + w * per, tb = min(T.t1, ta + per);
+    const double* M = arena + T.m + i;
+#pragma unroll 8
+    for (int t = max(ta, i); t < tb; ++t) acc += M[(int64_t)t * T.ld] * v[t - T.t0];
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0) part[(int64_t)T.slot * 64 + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// Applies the partial blocks of one vector block in slot order (see PartApply).
+__global__ __launch_bounds__(64) void k_part_apply(const PartApply* __restrict__ tasks,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ arena) {
+  const PartApply T = tasks[blockIdx.x];
+  const int r = threadIdx.x;
+  if (r >= T.nrows) return;
+  double s = 0.0;
+  for (int q = 0; q < T.ns; ++q) s += part[(int64_t)(T.s0 + q) * 64 + r];
+  if (T.mode == 0) arena[T.dst + r] -= s;
+  else arena[T.dst + r] = s;
 }
 
 // dst[begin + t] = src[idx[begin + t]] for t < count: the off-diagonal rows of one
@@ -122,39 +169,6 @@ __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ t
     }
     acc = wave_sum(acc);
     if (lane == 0) arena[T.out + col] = acc;
-  }
-}
-
-// out[i] = sum_{t >= i} M(i, t) (w[t] - s[t]): backward solve with L^{-T}.
-// One 64-row block per workgroup of 512 threads: lane = row (coalesced column
-// reads of M), the 8 waves split the columns t >= i0 and their partial sums are
-// added in a fixed order.
-__global__ __launch_bounds__(512) void k_trsv_bwd(const RowTask* __restrict__ tasks,
-                                                  double* __restrict__ arena) {
-  __shared__ double part[8][64];
-  const RowTask T = tasks[blockIdx.x];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = T.i0 + lane;
-  const double* w_ = arena + T.w;
-  const double* s_ = T.s >= 0 ? arena + T.s : nullptr;
-  double acc = 0.0;
-  if (i < T.c) {
-    const double* M = arena + T.m + i;
-    const int ncol = T.c - T.i0;                 // columns t in [i0, c)
-    const int per = (ncol + 7) / 8;
-    const int t0 = T.i0 + w * per, t1 = min(T.c, t0 + per);
-#pragma unroll 8
-    for (int t = max(t0, i); t < t1; ++t) {
-      const double v = s_ ? w_[t] - s_[t] : w_[t];
-      acc += M[(int64_t)t * T.ld] * v;
-    }
-  }
-  part[w][lane] = acc;
-  __syncthreads();
-  if (w == 0 && i < T.c) {
-    double s = 0.0;
-    for (int q = 0; q < 8; ++q) s += part[q][lane];
-    arena[T.out + i] = s;
   }
 }
 
@@ -382,9 +396,16 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gemv_n, dim3(n), dim3(256), 0, s, t, arena, ilim);
 }
-void launch_fwd_block(const FwdTile* t, int n, const FwdEntry* e, const int32_t* relmap,
-                      double* arena, const int32_t* ilim, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_fwd_block, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim);
+void launch_fwd_part(const FwdChunk* c, int n, const FwdTile* t, const FwdEntry* e,
+                     const int32_t* relmap, const double* arena, const int32_t* ilim, double* part,
+                     hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fwd_part, dim3(n), dim3(256), 0, s, c, t, e, relmap, arena, ilim, part);
+}
+void launch_row_part(const RowChunk* c, int n, const double* arena, double* part, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_row_part, dim3(n), dim3(256), 0, s, c, arena, part);
+}
+void launch_part_apply(const PartApply* t, int n, const double* part, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_part_apply, dim3(n), dim3(64), 0, s, t, part, arena);
 }
 void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
                         double* dst, hipStream_t s) {
@@ -393,9 +414,6 @@ void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const d
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
                    const int32_t* ilim, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_coldot, dim3(n), dim3(256), 0, s, t, arena, gidx, ilim);
-}
-void launch_trsv_bwd(const RowTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_trsv_bwd, dim3(n), dim3(512), 0, s, t, arena);
 }
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s) {

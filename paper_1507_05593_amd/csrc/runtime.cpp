@@ -335,9 +335,10 @@ struct Builder {
   FactorPlan& P;
   int32_t lp_update = 0;   // 0: FP64 MFMA; else the low-precision mode of launch_gemm_staged
   int32_t lp_sample = 0;
+  int32_t lp_eig = 0;      // products of the spectral truncation (projector iterations)
   Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {
-    if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; }
-    if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; }
+    if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; lp_eig = 1; }
+    if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; lp_eig = 1; }
   }
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
@@ -672,6 +673,7 @@ struct Builder {
         (void)dsel;
         f += tiles(t, 0, 0, false);
       }
+      // FP64: (G / tr G)^32 would underflow FP32 when lambda_max is a small share of tr G
       cmd(kCmdGemm, RSC_K_EIG, gg, (int64_t)P.gemm.size() - gg, f);
     };
     cmd(kCmdTruncPrep, RSC_K_EIG, t0, nt, 0);          // sa = G / tr G
@@ -695,26 +697,29 @@ struct Builder {
     cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
     cmd(kCmdTruncX0, RSC_K_EIG, t0, nt, 0);            // sa = I - 2 theta H
     for (int it = 0; it < kNewtonSchulzSteps; ++it) {
-      // sb = X X ; X_new = 1.5 X - 0.5 X sb (into sb via the D operand, then swap roles)
+      // sb = X X ; X_new = 1.5 X - 0.5 X sb (into sb via the D operand, then swap roles).
+      // The right operands are passed transposed (B(j, k) = Y(k, j)) so that the products
+      // are X X and X (X X): with X X^T in their place the iteration doubles the
+      // antisymmetric part of its rounding error on every step.
       g0 = (int64_t)P.gemm.size(); fl = 0;
       const bool even = (it % 2 == 0);
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t l = C.ell;
         const int64_t X = even ? C.Sa : C.Sb;
-        fl += tiles(gt(X, 1, l, X, 1, l, C.Om2, l, l, l, l, 1.0, 0.0), 0, 0, false);
+        fl += tiles(gt(X, 1, l, X, l, 1, C.Om2, l, l, l, l, 1.0, 0.0), 0, 0, false);
       }
-      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t l = C.ell;
         const int64_t X = even ? C.Sa : C.Sb, Xn = even ? C.Sb : C.Sa;
-        GemmTask t = gt(X, 1, l, C.Om2, 1, l, Xn, l, l, l, l, -0.5, 1.5);
+        GemmTask t = gt(X, 1, l, C.Om2, l, 1, Xn, l, l, l, l, -0.5, 1.5);
         t.d = X;
         fl += tiles(t, 0, 0, false);
       }
-      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
     }
     static_assert(kNewtonSchulzSteps % 2 == 0, "the iterate must end in sa");
     cmd(kCmdTruncP, RSC_K_EIG, t0, nt, 0);             // sa = P
@@ -749,7 +754,9 @@ struct Builder {
           const int32_t l = C.ell;
           fl += tiles(gt(C.Wpan + l, 2 * l, 1, C.Wpan + l, 2 * l, 1, C.Wpan, 2 * l, l, l, l, 1.0, 0.0), 0, 0, true);
           P.gs_g.push_back(C.Wpan); P.gs_ld.push_back(2 * l); P.gs_n.push_back(l); P.gs_out.push_back(C.sc + 4);
-          pan.push_back(PanelDesc{C.Wpan, 2 * l, l, l, false, C.Wdinv, j, 1, C.sc + 4});
+          // drop mode 2 (relative pivot 1e-8) when the projector came from FP32
+          // products: its rounding leaves ~1e-6 in the directions it annihilates
+          pan.push_back(PanelDesc{C.Wpan, 2 * l, l, l, false, C.Wdinv, j, lp_eig ? 2 : 1, C.sc + 4});
         }
         cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
         cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
@@ -889,12 +896,12 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
 
 struct EventPair { hipEvent_t a, b; int32_t klass, kid; double flops; };
 
-static const char* const kKernelNames[RSC_KERNELS] = {
+static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "gemm_staged_f64", "gemm_staged_f32", "gemm_staged_bf16x3", "gemm_staged_bf16",
     "update_staged_f64", "update_staged_f32", "update_staged_bf16x3", "update_staged_bf16",
     "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
-    "trunc_compact", "assemble", "fill", "fwd_block", "coldot", "trsv_bwd", "gemv_n",
-    "gather", "other"};
+    "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
+    "gather", "part_apply", "other"};
 
 int32_t kernel_id(int32_t type, int64_t a) {
   switch (type) {
@@ -910,12 +917,13 @@ int32_t kernel_id(int32_t type, int64_t a) {
     case kCmdTruncCompact: return 15;
     case kCmdAssemble: case kCmdIdent: return 16;
     case kCmdFill: case kCmdFillInts: return 17;
-    case kCmdFwdBlock: return 18;
+    case kCmdFwdPart: return 18;
     case kCmdColDot: return 19;
-    case kCmdTrsvBwd: return 20;
+    case kCmdRowPart: return 20;
     case kCmdGemvN: return 21;
     case kCmdGatherRows: case kCmdRowGather: case kCmdGatherPerm: case kCmdScatterPerm: return 22;
-    default: return 23;
+    case kCmdPartApply: return 23;
+    default: return 24;
   }
 }
 
@@ -947,10 +955,12 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncCompact: launch_trunc_compact(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
-    case kCmdTrsvBwd: launch_trsv_bwd(Q->d_rows.p + c.off, (int)c.count, A, s); break;
-    case kCmdFwdBlock:
-      launch_fwd_block(Q->d_ftiles.p + c.off, (int)c.count, Q->d_fents.p, h.d_relmap.p, A, I, s);
+    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, Q->d_part.p, s); break;
+    case kCmdFwdPart:
+      launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, I,
+                      Q->d_part.p, s);
       break;
+    case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, Q->d_part.p, A, s); break;
     case kCmdGatherRows:
       launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);
       break;
@@ -1157,14 +1167,42 @@ static Error build_solve_plan(Handle& h) {
           blks.push_back(std::move(bk));
         }
       }
-      const int64_t f0 = (int64_t)Q->ftiles.size();
+      // Each block's entries are cut into runs of about equal work (rows x depth; the
+      // sample count stands in for a compressed descendant's rank) so that the level
+      // has about 1024 chunks; one launch computes the chunks' partial blocks, a second
+      // subtracts them from y in a fixed order.
+      auto ework = [&](const FwdEntry& e) {
+        const double K = e.kdim >= 0 ? e.kdim : (double)h.comp[(-1 - e.kdim) - h.i_ranks].ell;
+        return (double)(e.b - e.a) * std::max(K, 1.0);
+      };
+      double wl = 0;
+      for (auto& bk : blks)
+        for (auto& e : bk.e) wl += ework(e);
+      const double target = std::max(wl / 1024.0, 64.0 * 64.0);
+      const int64_t c0f = (int64_t)Q->fchunks.size(), a0 = (int64_t)Q->papply.size();
+      int32_t slot = 0;
       for (auto& bk : blks) {
         bk.t.e0 = (int32_t)Q->fents.size();
         for (auto& e : bk.e) Q->fents.push_back(e);
         bk.t.e1 = (int32_t)Q->fents.size();
+        const int32_t ti = (int32_t)Q->ftiles.size();
         Q->ftiles.push_back(bk.t);
+        const int32_t s0 = slot;
+        double acc = 0;
+        int32_t cs = bk.t.e0;
+        for (int32_t e = bk.t.e0; e < bk.t.e1; ++e) {
+          acc += ework(Q->fents[e]);
+          if (acc >= target || e + 1 == bk.t.e1) {
+            Q->fchunks.push_back(FwdChunk{ti, cs, e + 1, slot++});
+            cs = e + 1;
+            acc = 0;
+          }
+        }
+        Q->papply.push_back(PartApply{bk.t.y, bk.t.nrows, s0, slot - s0, 0});
       }
-      cmd(kCmdFwdBlock, f0, (int64_t)Q->ftiles.size() - f0);
+      Q->part_slots = std::max<int64_t>(Q->part_slots, slot);
+      cmd(kCmdFwdPart, c0f, (int64_t)Q->fchunks.size() - c0f);
+      cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
     }
     // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
     int64_t c0 = (int64_t)Q->coldot.size();
@@ -1248,20 +1286,35 @@ static Error build_solve_plan(Handle& h) {
       bytes += 2.0 * 8.0 * (double)(S.c(j) + S.r(j)) * C.ell;
     }
     cmd(kCmdGemvN, g0, (int64_t)Q->gemv.size() - g0);
-    // b2: z_C = L_j^{-T} (w_C - s_C)
-    const int64_t w0 = (int64_t)Q->rows.size();
-    for (int32_t j : lev) {
-      const int32_t c = S.c(j), r = S.r(j);
-      for (int32_t i0 = 0; i0 < c; i0 += 64) {
-        RowTask t{};
-        t.m = h.a_panels + h.panel_off[j] + c + r; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
-        t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;
-        t.out = h.a_zz + S.first[j];
-        Q->rows.push_back(t);
+    // b2: z_C = L_j^{-T} (w_C - s_C) by 64-row blocks, the columns of each block cut
+    // into chunks (about 1024 per level) whose partial blocks are then stored in order
+    {
+      double cols = 0;
+      for (int32_t j : lev)
+        for (int32_t i0 = 0; i0 < S.c(j); i0 += 64) cols += S.c(j) - i0;
+      const int32_t width =
+          (int32_t)std::min<double>(kRowChunkMax, std::max(256.0, std::ceil(cols / 1024.0)));
+      const int64_t c0r = (int64_t)Q->rchunks.size(), a0 = (int64_t)Q->papply.size();
+      int32_t slot = 0;
+      for (int32_t j : lev) {
+        const int32_t c = S.c(j), r = S.r(j);
+        for (int32_t i0 = 0; i0 < c; i0 += 64) {
+          const int32_t s0 = slot;
+          for (int32_t t0 = i0; t0 < c; t0 += width) {
+            RowChunk t{};
+            t.m = h.a_panels + h.panel_off[j] + c + r; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
+            t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;
+            t.t0 = t0; t.t1 = std::min(c, t0 + width); t.slot = slot++;
+            Q->rchunks.push_back(t);
+          }
+          Q->papply.push_back(PartApply{h.a_zz + S.first[j] + i0, std::min(64, c - i0), s0, slot - s0, 1});
+        }
+        bytes += 8.0 * c * (c + 1) / 2;
       }
-      bytes += 8.0 * c * (c + 1) / 2;
+      Q->part_slots = std::max<int64_t>(Q->part_slots, slot);
+      cmd(kCmdRowPart, c0r, (int64_t)Q->rchunks.size() - c0r);
+      cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
     }
-    cmd(kCmdTrsvBwd, w0, (int64_t)Q->rows.size() - w0);
   }
   Q->bytes = bytes;
   Error e;
@@ -1269,7 +1322,13 @@ static Error build_solve_plan(Handle& h) {
   if ((e = upload(Q->d_ftiles, Q->ftiles)).code) return e;
   if ((e = upload(Q->d_fents, Q->fents)).code) return e;
   if ((e = upload(Q->d_coldot, Q->coldot)).code) return e;
-  if ((e = upload(Q->d_rows, Q->rows)).code) return e;
+  if ((e = upload(Q->d_fchunks, Q->fchunks)).code) return e;
+  if ((e = upload(Q->d_rchunks, Q->rchunks)).code) return e;
+  if ((e = upload(Q->d_papply, Q->papply)).code) return e;
+  {
+    std::vector<double> zero((size_t)std::max<int64_t>(Q->part_slots, 1) * 64, 0.0);
+    if ((e = upload(Q->d_part, zero)).code) return e;
+  }
   if ((e = upload(Q->d_gath, Q->gath)).code) return e;
   if ((e = upload(Q->d_rg_rows, Q->rg_rows)).code) return e;
   if ((e = upload(Q->d_rg_ptr, Q->rg_ptr)).code) return e;

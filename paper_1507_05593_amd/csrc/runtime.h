@@ -23,8 +23,8 @@ struct Error {
 enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
-  kCmdGemvN, kCmdColDot, kCmdTrsvBwd, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdGatherRows, kCmdFwdBlock,
+  kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
+  kCmdGatherRows,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -103,14 +103,20 @@ struct SolvePlan {
   std::vector<FwdTile> ftiles;
   std::vector<FwdEntry> fents;
   std::vector<ColDotTask> coldot;
-  std::vector<RowTask> rows;
+  std::vector<FwdChunk> fchunks;
+  std::vector<RowChunk> rchunks;
+  std::vector<PartApply> papply;
+  int64_t part_slots = 0;             // 64-entry partial blocks (reused level by level)
   std::vector<int64_t> rg_rows, rg_ptr, rg_contrib;  // row-gather CSR (all levels)
   std::vector<int64_t> gath;          // (begin, count) pairs of z gathers over R_j
   DevArray<GemvTask> d_gemv;
   DevArray<FwdTile> d_ftiles;
   DevArray<FwdEntry> d_fents;
   DevArray<ColDotTask> d_coldot;
-  DevArray<RowTask> d_rows;
+  DevArray<FwdChunk> d_fchunks;
+  DevArray<RowChunk> d_rchunks;
+  DevArray<PartApply> d_papply;
+  DevArray<double> d_part;
   DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib, d_gath;
   hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
   double bytes = 0;                   // factor bytes read by one apply

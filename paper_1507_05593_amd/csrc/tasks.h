@@ -8,6 +8,7 @@
 namespace rsc {
 
 constexpr int kTile = 64;      // output tile edge of the MFMA kernels and POTRF block size
+constexpr int kRowChunkMax = 2048;   // columns of one backward diagonal-solve chunk (LDS)
 
 // C(i,j) = beta D(i,j) + alpha sum_k A(i,k) B(j,k) on one 64x64 output tile.
 // A(i,k) = arena[a + i*ais + k*aks], B(j,k) = arena[b + j*bjs + k*bks],
@@ -52,8 +53,9 @@ struct PotrfTask {
   int64_t inv;
   int32_t ld, nb, d0;
   int32_t sn;                  // supernode for the status word
-  int32_t mode;                // 0: fail on a non-positive pivot; 1: drop dependent columns
-  int64_t scale_off;           // mode 1: arena offset of the column-drop scale (max Gram diagonal)
+  int32_t mode;                // 0: fail on a non-positive pivot; 1 / 2: drop dependent columns
+                               // (pivot <= 1e-14 / 1e-8 times the scale)
+  int64_t scale_off;           // modes 1, 2: arena offset of the scale (largest Gram diagonal)
 };
 
 // Gaussian sample of one supernode: rows x cols column-major at `out` (ld = rows).
@@ -98,12 +100,6 @@ struct ColDotTask {
   int32_t tri, pad_;
 };
 
-// out[i] = sum_{t >= i} M(i, t) (w[t] - s[t]) for rows [i0, i0 + 256) of a c x c
-// upper-triangular block (tri) -- the backward solve with the stored L^{-T}.
-struct RowTask {
-  int64_t m, w, s, out;        // s < 0: no subtraction
-  int32_t ld, c, i0, pad_;
-};
 
 // Contiguous row range inside one system (segment) for chunked vector kernels.
 struct Chunk {
@@ -133,6 +129,22 @@ struct FwdTile {
   int64_t y;                   // arena offset of y on the first row of the block
   int32_t nrows, row0;
   int32_t e0, e1;
+};
+// Forward-sweep chunk: entries [e0, e1) of target block `tile`, partial sums to slot.
+struct FwdChunk {
+  int32_t tile, e0, e1, slot;
+};
+// Backward diagonal solve chunk: rows [i0, i0 + 64) of z_C = M (w_C - s_C) over the
+// columns t in [t0, t1) (M = (L^D)^{-T}, upper triangular, M(i, t) = arena[m + i + t*ld]).
+struct RowChunk {
+  int64_t m, w, s;             // s < 0: no subtraction
+  int32_t ld, c, i0, t0, t1, slot;
+};
+// Sum of consecutive 64-entry partial blocks s0 .. s0+ns-1 applied to a vector block:
+// mode 0: dst[r] -= sum, mode 1: dst[r] = sum, for r < nrows.
+struct PartApply {
+  int64_t dst;
+  int32_t nrows, s0, ns, mode;
 };
 struct FwdEntry {
   int64_t x;                   // X(t, m) = arena[x + t + m*ldx]
