@@ -39,7 +39,9 @@ sys.path.insert(0, ROOT)
 PEAK_FLOPS = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
 PEAK_HBM = 8.0e12
 KERNEL_PREC = {"gemm_staged_f64": "f64", "gemm_staged_f32": "f32", "gemm_staged_bf16x3": "bf16",
-               "gemm_staged_bf16": "bf16", "update_staged_f64": "f64", "update_staged_f32": "f32",
+               "gemm_staged_bf16": "bf16", "gemm_staged128_f64": "f64", "gemm_staged128_f32": "f32",
+               "gemm_staged128_bf16x3": "bf16", "gemm_staged128_bf16": "bf16",
+               "update_staged_f64": "f64", "update_staged_f32": "f32",
                "update_staged_bf16x3": "bf16", "update_staged_bf16": "bf16", "potrf_f64": "f64"}
 KERNEL_SOURCE = {"gemm_staged": "kernels_gemm.hip", "update_staged": "kernels_gemm.hip",
                  "potrf_f64": "kernels_dense.hip"}
@@ -338,7 +340,7 @@ def main():
         line["roofline"] = roofline(ks, name)
         line["mfma_util"] = mfma_util(ks, res["profiled_factor_ms"])
         top = sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:8]
-        line["kernels_ms"] = {k: round(v["ms"], 3) for k, v in top}
+        line["kernels"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in top}
     line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name, cfg, args.cpu_sample_side, desc)

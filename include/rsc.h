@@ -191,7 +191,7 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
  * summed hipEvent time of those launches in ms (events on the launch stream, so
  * each interval is one launch) and their algorithmic flops.  Any output may be NULL.
  * Errors: RSC_ERR_INVALID_ARG for a null handle or k out of range. */
-#define RSC_KERNELS 25
+#define RSC_KERNELS 29
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops);
 

@@ -22,7 +22,7 @@ RSC_MIXED_BF16 = 1
 RSC_MIXED_FP32 = 2
 
 K_CLASSES = ["update", "potrf", "trsm", "gemm", "eig", "pcg", "other"]
-RSC_KERNELS = 25
+RSC_KERNELS = 29
 
 
 class Options(C.Structure):

@@ -34,7 +34,7 @@ void launch_part_apply(const PartApply* t, int n, const double* part, double* ar
 void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
                         double* dst, hipStream_t s);
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
-                   const int32_t* ilim, hipStream_t s);
+                   const int32_t* ilim, double* part, hipStream_t s);
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s);
 void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);

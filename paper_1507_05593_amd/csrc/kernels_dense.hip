@@ -73,14 +73,18 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 //         its L column and its row and column of the inverse become zero;
 // mode 2: the same with the threshold 1e-8 * scale.
 // Right-looking elimination four columns at a time, register-blocked: thread (tx, ty)
-// of the 16 x 16 grid owns entries (ty + 16a, tx + 16b), a, b < 4, of L and of W
-// (W starts as I and ends as L^{-1}).  Step K publishes the four-column panel and rows
-// 4K..4K+3 of W through double-buffered LDS (one barrier); every thread then factors
-// the 4 x 4 diagonal block and inverts it in registers (Ld, Ldi), forms l_i = Ldi p_i
-// for its rows and columns, and applies the rank-4 updates
+// of the TD x TD grid (TD = 32: 1024 threads) owns entries (ty + TD a, tx + TD b),
+// a, b < 64 / TD, of L and of W (W starts as I and ends as L^{-1}).  Step K publishes
+// the four-column panel and rows 4K..4K+3 of W through double-buffered LDS (one
+// barrier); every thread then factors the 4 x 4 diagonal block and inverts it in
+// registers (Ld, Ldi), forms l_i = Ldi p_i for its rows and columns, and applies the
+// rank-4 updates
 //   L(i, j) -= l_i . l_j,   W(block rows) = Ldi W(block rows),   W(i, :) -= l_i . W(block rows).
 // Sixteen sequential steps instead of sixty-four; global accesses go through an LDS tile.
-__global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
+constexpr int kPotrfTD = 32;                 // threads per dimension of the block grid
+constexpr int kPotrfNE = 64 / kPotrfTD;      // entries per thread and dimension
+
+__global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
   __shared__ double tile[64][65];
@@ -88,22 +92,23 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   __shared__ double wrows[2][4][64];
   const PotrfTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  constexpr int TD = kPotrfTD, NE = kPotrfNE, NT = TD * TD;
+  const int tx = tid % TD, ty = tid / TD;
   const int nb = T.nb;
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+  for (int u = 0; u < 4096 / NT; ++u) {
+    const int idx = tid + NT * u, r = idx & 63, c = idx >> 6;
     tile[r][c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
   }
   __syncthreads();
-  double L[4][4], W[4][4];
+  double L[NE][NE], W[NE][NE];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NE; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ty + 16 * a, j = tx + 16 * b;
+    for (int b = 0; b < NE; ++b) {
+      const int i = ty + TD * a, j = tx + TD * b;
       L[a][b] = tile[i][j];
       W[a][b] = (i == j && i < nb) ? 1.0 : 0.0;
     }
@@ -111,25 +116,25 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   bool bad = false;
   const int nsteps = (nb + 3) >> 2;
   for (int K = 0; K < nsteps; ++K) {
-    const int k0 = 4 * K, kb = k0 >> 4, ko = k0 & 15, buf = K & 1;
+    const int k0 = 4 * K, kb = k0 / TD, ko = k0 % TD, buf = K & 1;
     const int nbk = min(4, nb - k0);
     // publish the panel columns k0..k0+3 (rows >= k0) and rows k0..k0+3 of W
     if (tx >= ko && tx < ko + 4) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < NE; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < NE; ++b)
           if (b == kb) {
-            const int i = ty + 16 * a;
+            const int i = ty + TD * a;
             if (i >= k0) pan[buf][i][tx - ko] = L[a][b];
           }
     }
     if (ty >= ko && ty < ko + 4) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < NE; ++a)
         if (a == kb) {
 #pragma unroll
-          for (int b = 0; b < 4; ++b) wrows[buf][ty - ko][tx + 16 * b] = W[a][b];
+          for (int b = 0; b < NE; ++b) wrows[buf][ty - ko][tx + TD * b] = W[a][b];
         }
     }
     __syncthreads();
@@ -180,10 +185,10 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
       }
     // l vectors of this thread's columns (j > k0 + 3) and new rows k0..k0+3 of W for
     // its columns; the row vectors l_i are formed one row at a time below
-    double lj[4][4], wn[4][4];
+    double lj[NE][4], wn[NE][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = tx + 16 * b;
+    for (int b = 0; b < NE; ++b) {
+      const int j = tx + TD * b;
       double pv[4], wb[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -203,8 +208,8 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
       }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = ty + 16 * a;
+    for (int a = 0; a < NE; ++a) {
+      const int i = ty + TD * a;
       double li[4];
       {
         double pv[4];
@@ -219,8 +224,8 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
         }
       }
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = tx + 16 * b;
+      for (int b = 0; b < NE; ++b) {
+        const int j = tx + TD * b;
         if (b == kb && tx >= ko && tx < ko + 4) {          // the panel columns
           const int cc = tx - ko;
           if (i > k0 + 3) {
@@ -250,25 +255,25 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   if (bad && tid == 0) atomicMin(&status[0], T.sn);
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NE; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) tile[ty + 16 * a][tx + 16 * b] = L[a][b];
+    for (int b = 0; b < NE; ++b) tile[ty + TD * a][tx + TD * b] = L[a][b];
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+  for (int u = 0; u < 4096 / NT; ++u) {
+    const int idx = tid + NT * u, r = idx & 63, c = idx >> 6;
     if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = tile[r][c];
   }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NE; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) tile[ty + 16 * a][tx + 16 * b] = W[a][b];
+    for (int b = 0; b < NE; ++b) tile[ty + TD * a][tx + TD * b] = W[a][b];
   __syncthreads();
   double* inv = arena + T.inv;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+  for (int u = 0; u < 4096 / NT; ++u) {
+    const int idx = tid + NT * u, r = idx & 63, c = idx >> 6;
     inv[r + 64 * c] = tile[r][c];
   }
 }
@@ -561,7 +566,7 @@ void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* aren
   if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, s, slot, n, v, arena);
 }
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(256), 0, s, t, arena, status);
+  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(kPotrfTD * kPotrfTD), 0, s, t, arena, status);
 }
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
                    hipStream_t s) {

@@ -148,27 +148,32 @@ __global__ void k_gather_rows(const int64_t* __restrict__ tasks, const int64_t* 
 __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ tasks,
                                                 double* __restrict__ arena,
                                                 const int64_t* __restrict__ gidx,
-                                                const int32_t* __restrict__ ilim) {
+                                                const int32_t* __restrict__ ilim,
+                                                double* __restrict__ part) {
   const ColDotTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ncols = T.ncols >= 0 ? T.ncols : ilim[-1 - T.ncols];
   const double* in = arena + T.in;
   for (int u = 0; u < 4; ++u) {
     const int col = T.col0 + w * 4 + u;
-    if (col >= ncols) continue;
-    const int rows = T.tri ? col + 1 : T.rows;
-    const double* X = arena + T.x + (int64_t)col * T.ldx;
     double acc = 0.0;
-    if (T.idx >= 0) {
-      const int64_t* ix = gidx + T.idx;
+    if (col < ncols) {
+      const int rows = min(T.tri ? col + 1 : T.rows, T.r1);
+      const double* X = arena + T.x + (int64_t)col * T.ldx;
+      if (T.idx >= 0) {
+        const int64_t* ix = gidx + T.idx;
 #pragma unroll 8
-      for (int t = lane; t < rows; t += 64) acc += X[t] * in[ix[t]];
-    } else {
+        for (int t = T.r0 + lane; t < rows; t += 64) acc += X[t] * in[ix[t]];
+      } else {
 #pragma unroll 8
-      for (int t = lane; t < rows; t += 64) acc += X[t] * in[t];
+        for (int t = T.r0 + lane; t < rows; t += 64) acc += X[t] * in[t];
+      }
+      acc = wave_sum(acc);
     }
-    acc = wave_sum(acc);
-    if (lane == 0) arena[T.out + col] = acc;
+    if (lane == 0) {
+      if (T.slot >= 0) part[(int64_t)T.slot * 64 + (col - T.col0)] = acc;
+      else if (col < ncols) arena[T.out + col] = acc;
+    }
   }
 }
 
@@ -412,8 +417,8 @@ void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const d
   if (n > 0) hipLaunchKernelGGL(k_gather_rows, dim3(n), dim3(256), 0, s, tasks, idx, src, dst);
 }
 void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
-                   const int32_t* ilim, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_coldot, dim3(n), dim3(256), 0, s, t, arena, gidx, ilim);
+                   const int32_t* ilim, double* part, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_coldot, dim3(n), dim3(256), 0, s, t, arena, gidx, ilim, part);
 }
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s) {

@@ -273,6 +273,7 @@ struct PanelDesc {
   int64_t scale_off;
   int32_t lp_lo = 0, lp_hi = 0;   // rows [lp_lo, lp_hi) use the low-precision products
   bool skip_mid = false;          // ... or are not touched at all
+  bool tail_lp = false;           // rows from lp_hi on (the inverse being formed) use lp_tri
 };
 
 // Merges a GEMM command's 64 x 64 output tiles (tasks [off, end) of the list, in the
@@ -336,9 +337,10 @@ struct Builder {
   int32_t lp_update = 0;   // 0: FP64 MFMA; else the low-precision mode of launch_gemm_staged
   int32_t lp_sample = 0;
   int32_t lp_eig = 0;      // products of the spectral truncation (projector iterations)
+  int32_t lp_tri = 0;      // the rows of a panel that form the inverse of its diagonal block
   Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {
-    if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; lp_eig = 1; }
-    if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; lp_eig = 1; }
+    if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; lp_eig = 1; lp_tri = 1; }
+    if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; lp_eig = 1; lp_tri = 1; }
   }
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
@@ -420,8 +422,8 @@ struct Builder {
       // rows below the diagonal block times its inverse, then the trailing update;
       // rows inside [lp_lo, lp_hi) go to the low-precision launch
       for (int phase = 0; phase < 2; ++phase) {
-        std::vector<GemmTask> hi_t, lo_t;
-        double fh = 0, flo = 0;
+        std::vector<GemmTask> hi_t, lo_t, tl_t;
+        double fh = 0, flo = 0, ftl = 0;
         for (auto& p : pan) {
           if (p.n <= d0) continue;
           const int32_t nb = std::min(kTile, p.n - d0);
@@ -434,7 +436,7 @@ struct Builder {
               : gt(colb, 1, p.ld, colb, 1, p.ld, p.off, p.ld, R1, p.n, nb, -1.0, 1.0);
           const int32_t jb = (phase == 0) ? 0 : d0 + nb;
           const bool lower = (phase == 1);
-          const bool use_lp = (lp_update || p.skip_mid) && p.lp_hi > p.lp_lo;
+          const bool use_lp = ((lp_update || p.skip_mid) && p.lp_hi > p.lp_lo) || (p.tail_lp && lp_tri);
           // segments [R0, lp_lo), [lp_lo, lp_hi), [lp_hi, R1)
           int32_t cuts[4] = {R0, use_lp ? std::max(R0, p.lp_lo) : R1, use_lp ? std::max(R0, p.lp_hi) : R1, R1};
           for (int sgm = 0; sgm < 3; ++sgm) {
@@ -444,6 +446,7 @@ struct Builder {
             ts.m = hi;
             if (sgm == 1 && p.skip_mid) continue;
             if (sgm == 1) flo += tiles(ts, lo, jb, lower, &lo_t);
+            else if (sgm == 2 && p.tail_lp && lp_tri) ftl += tiles(ts, lo, jb, lower, &tl_t);
             else fh += tiles(ts, lo, jb, lower, &hi_t);
           }
         }
@@ -454,6 +457,9 @@ struct Builder {
         g0 = (int64_t)P.gemm.size();
         P.gemm.insert(P.gemm.end(), lo_t.begin(), lo_t.end());
         cmd(kCmdGemm, klass, g0, (int64_t)lo_t.size(), flo, lp_update);
+        g0 = (int64_t)P.gemm.size();
+        P.gemm.insert(P.gemm.end(), tl_t.begin(), tl_t.end());
+        cmd(kCmdGemm, klass, g0, (int64_t)tl_t.size(), ftl, lp_tri);
       }
     }
   }
@@ -901,11 +907,12 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "update_staged_f64", "update_staged_f32", "update_staged_bf16x3", "update_staged_bf16",
     "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
     "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
-    "gather", "part_apply", "other"};
+    "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
+    "gemm_staged128_bf16x3", "gemm_staged128_bf16"};
 
-int32_t kernel_id(int32_t type, int64_t a) {
+int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
-    case kCmdGemm: return (int32_t)(0 + (a & 3));
+    case kCmdGemm: return (int32_t)((b == 128 ? 25 : 0) + (a & 3));
     case kCmdUpdate: return (int32_t)(4 + (a & 3));
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
@@ -954,7 +961,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncP: launch_trunc_p(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncCompact: launch_trunc_compact(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
-    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, s); break;
+    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, Q->d_part.p, s); break;
     case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, Q->d_part.p, s); break;
     case kCmdFwdPart:
       launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, I,
@@ -983,7 +990,7 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
       HIPCHK(hipEventCreate(&ep.a));
       HIPCHK(hipEventCreate(&ep.b));
       ep.klass = c.klass;
-      ep.kid = kernel_id(c.type, c.a);
+      ep.kid = kernel_id(c.type, c.a, c.b);
       ep.flops = c.flops;
       HIPCHK(hipEventRecord(ep.a, s));
       launch_cmd(h, c, P, Q, s);
@@ -1120,6 +1127,40 @@ static Error build_solve_plan(Handle& h) {
     c.type = type; c.klass = RSC_K_PCG; c.off = off; c.count = count; c.a = a; c.b = b;
     Q->fwd_bwd.push_back(c);
   };
+  // Column-dot launch of one sweep stage.  When the stage has fewer than 1024 tasks,
+  // the rows of every task are cut into chunks (so that the stage has about 1024
+  // workgroups) whose 16 sums go to partial blocks, stored in order by a second launch.
+  auto coldot_stage = [&](std::vector<ColDotTask>& ts) {
+    if (ts.empty()) return;
+    const int64_t c0 = (int64_t)Q->coldot.size();
+    if (ts.size() >= 1024) {
+      for (auto& t : ts) { t.r0 = 0; t.r1 = INT_MAX; t.slot = -1; Q->coldot.push_back(t); }
+      cmd(kCmdColDot, c0, (int64_t)ts.size());
+      return;
+    }
+    double rows = 0;
+    for (auto& t : ts) rows += t.tri ? std::min(t.rows, t.col0 + 16) : t.rows;
+    const int32_t chunk = (int32_t)std::max(512.0, 64.0 * std::ceil(rows / 1024.0 / 64.0));
+    const int64_t a0 = (int64_t)Q->papply.size();
+    int32_t slot = 0;
+    for (auto& t : ts) {
+      const int32_t R = t.tri ? std::min(t.rows, t.col0 + 16) : t.rows;
+      if (R <= chunk) { t.r0 = 0; t.r1 = INT_MAX; t.slot = -1; Q->coldot.push_back(t); continue; }
+      const int32_t s0 = slot;
+      for (int32_t r0 = 0; r0 < R; r0 += chunk) {
+        ColDotTask u = t;
+        u.r0 = r0; u.r1 = std::min(R, r0 + chunk); u.slot = slot++;
+        Q->coldot.push_back(u);
+      }
+      // a static column count ends the block at the supernode's last column; a device
+      // rank may not, but those outputs are padded to a multiple of 64
+      const int32_t nout = t.ncols >= 0 ? std::min(16, t.ncols - t.col0) : 16;
+      Q->papply.push_back(PartApply{t.out + t.col0, nout, s0, slot - s0, 1});
+    }
+    Q->part_slots = std::max<int64_t>(Q->part_slots, slot);
+    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+    if ((int64_t)Q->papply.size() > a0) cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
+  };
   auto iscomp = [&](int64_t j) { return comp && h.compressible[j]; };
   double bytes = 0;
   Q->rg_ptr.push_back(0);
@@ -1205,7 +1246,7 @@ static Error build_solve_plan(Handle& h) {
       cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
     }
     // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
-    int64_t c0 = (int64_t)Q->coldot.size();
+    std::vector<ColDotTask> st;
     for (int32_t j : lev) {
       const int32_t c = S.c(j), r = S.r(j);
       for (int32_t col0 = 0; col0 < c; col0 += 16) {
@@ -1213,13 +1254,13 @@ static Error build_solve_plan(Handle& h) {
         t.x = h.a_panels + h.panel_off[j] + c + r; t.ldx = h.panel_ld[j];
         t.in = h.a_y + S.first[j]; t.idx = -1; t.out = h.a_w + S.first[j];
         t.rows = c; t.ncols = c; t.col0 = col0; t.tri = 1;
-        Q->coldot.push_back(t);
+        st.push_back(t);
       }
       bytes += 8.0 * c * (c + 1) / 2;
     }
-    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+    coldot_stage(st);
     // f4: t_j = U_j^T w_C for compressed supernodes
-    c0 = (int64_t)Q->coldot.size();
+    st.clear();
     for (int32_t j : lev) {
       if (!iscomp(j)) continue;
       const CompSlot& C = h.comp[j];
@@ -1227,10 +1268,10 @@ static Error build_solve_plan(Handle& h) {
         ColDotTask t{};
         t.x = C.Uj; t.ldx = S.c(j); t.in = h.a_w + S.first[j]; t.idx = -1; t.out = C.tvq;
         t.rows = S.c(j); t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
-        Q->coldot.push_back(t);
+        st.push_back(t);
       }
     }
-    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+    coldot_stage(st);
   }
   // backward sweep, levels descending
   for (int32_t L = S.nlevels - 1; L >= 0; --L) {
@@ -1248,7 +1289,7 @@ static Error build_solve_plan(Handle& h) {
       }
     }
     // b1: s_C = (L^O_j)^T z_R (dense) or u = V_j^T z_R (compressed)
-    int64_t c0 = (int64_t)Q->coldot.size();
+    std::vector<ColDotTask> st;
     for (int32_t j : lev) {
       const int32_t c = S.c(j), r = S.r(j);
       if (r == 0) continue;
@@ -1258,7 +1299,7 @@ static Error build_solve_plan(Handle& h) {
           ColDotTask t{};
           t.x = C.Vj; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j]; t.idx = -1; t.out = C.u;
           t.rows = r; t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
-          Q->coldot.push_back(t);
+          st.push_back(t);
         }
       } else {
         for (int32_t col0 = 0; col0 < c; col0 += 16) {
@@ -1266,12 +1307,12 @@ static Error build_solve_plan(Handle& h) {
           t.x = h.a_lo + h.lo_off[j]; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j];
           t.idx = -1; t.out = h.a_s + S.first[j];
           t.rows = r; t.ncols = c; t.col0 = col0; t.tri = 0;
-          Q->coldot.push_back(t);
+          st.push_back(t);
         }
         bytes += 2.0 * 8.0 * (double)r * c;   // read by both sweeps
       }
     }
-    cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
+    coldot_stage(st);
     // b1': s_C = U_j u for compressed supernodes
     int64_t g0 = (int64_t)Q->gemv.size();
     for (int32_t j : lev) {

@@ -97,7 +97,9 @@ namespace rsc {
 struct ColDotTask {
   int64_t x, in, idx, out;
   int32_t ldx, rows, ncols, col0;
-  int32_t tri, pad_;
+  int32_t tri;
+  int32_t r0, r1;              // rows of this task: [r0, min(r1, rows(col)))
+  int32_t slot;                // >= 0: write the 16 sums to partial block `slot` instead of out
 };
 
 
