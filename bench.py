@@ -151,6 +151,7 @@ def run_form(pattern, vals, b, cfg, extra, precision, steps, warmup, profile, ba
         pinfo = step(sol, vals, b, cfg, extra)
         torch.cuda.synchronize()
         out["kernels"] = sol.kernel_profile()
+        out["classes"] = sol.profile_result()
         out["profiled_factor_ms"] = sol.stats()["t_factor_ms"]
         out["profiled_iters"] = pinfo["iters"]
         sol.profile(False)
@@ -341,6 +342,7 @@ def main():
         line["mfma_util"] = mfma_util(ks, res["profiled_factor_ms"])
         top = sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:8]
         line["kernels"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in top}
+        line["classes_ms"] = {k: round(v["ms"], 3) for k, v in res["classes"].items() if v["launches"]}
     line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name, cfg, args.cpu_sample_side, desc)

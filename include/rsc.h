@@ -101,9 +101,15 @@ typedef struct {
   int64_t gemm_tile128;        /* of those, launches that run with 128-wide tiles */
 } rsc_stats;
 
-/* Kernel-class timing (hipEvents around every launch of a class while enabled). */
+/* Kernel-class timing (hipEvents around every launch of a class while enabled).  Classes
+ * follow the steps of the method: Schur updates; the supernode panels' diagonal blocks,
+ * in-place solves and trailing updates; the L^O product; sampling (Algorithm 3's random
+ * product and power iterations); orthonormalisation of the sample; projection and kept
+ * basis (V = L^O U, the basis of the projector, U_j, V_j); truncation (Gram matrix,
+ * projector iterations); PCG; other (assembly, fills). */
 enum { RSC_K_UPDATE = 0, RSC_K_POTRF = 1, RSC_K_TRSM = 2, RSC_K_GEMM = 3, RSC_K_EIG = 4,
-       RSC_K_PCG = 5, RSC_K_OTHER = 6, RSC_K_CLASSES = 7 };
+       RSC_K_PCG = 5, RSC_K_OTHER = 6, RSC_K_LO = 7, RSC_K_SAMPLE = 8, RSC_K_ORTH = 9,
+       RSC_K_BASIS = 10, RSC_K_CLASSES = 11 };
 typedef struct {
   int64_t launches[RSC_K_CLASSES];
   double ms[RSC_K_CLASSES];

@@ -21,7 +21,8 @@ RSC_FP64 = 0
 RSC_MIXED_BF16 = 1
 RSC_MIXED_FP32 = 2
 
-K_CLASSES = ["update", "potrf", "trsm", "gemm", "eig", "pcg", "other"]
+K_CLASSES = ["update", "panel_potrf", "panel_trsm", "panel_trailing", "truncation", "pcg", "other", "lo_product",
+             "sample", "orthonormalise", "basis"]
 RSC_KERNELS = 29
 
 
@@ -50,7 +51,8 @@ class Stats(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 7), ("ms", C.c_double * 7), ("flops", C.c_double * 7)]
+    _fields_ = [("launches", C.c_int64 * len(K_CLASSES)), ("ms", C.c_double * len(K_CLASSES)),
+                ("flops", C.c_double * len(K_CLASSES))]
 
 
 _lib = None

@@ -373,6 +373,19 @@ __device__ double block_sum256(double v) {
   return r;
 }
 
+__device__ double block_sum1024(double v) {
+  __shared__ double red[1024];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
 // trace(G) and S = G / trace(G) (zero when the trace is not positive).
 __global__ __launch_bounds__(256) void k_trunc_prep(const TruncTask* __restrict__ tasks,
                                                     double* __restrict__ arena) {
@@ -392,14 +405,14 @@ __global__ __launch_bounds__(256) void k_trunc_prep(const TruncTask* __restrict_
 // lambda_max by power iteration with S32 = (G / tr G)^32 (already in sb), Rayleigh
 // quotient with G; theta = tol^2 lambda_max; then the Cholesky panel
 // [G + theta I; I] (ld 2l) and its drop scale.
-__global__ __launch_bounds__(256) void k_trunc_power(const TruncTask* __restrict__ tasks,
+__global__ __launch_bounds__(1024) void k_trunc_power(const TruncTask* __restrict__ tasks,
                                                      double* __restrict__ arena) {
   __shared__ double v[2048], w[2048];   // l <= 2048 (checked by the planner)
   const TruncTask T = tasks[blockIdx.x];
   const int l = T.l;
   const double* S = arena + T.sb;
   const double* G = arena + T.g;
-  for (int i = threadIdx.x; i < l; i += 256) {
+  for (int i = threadIdx.x; i < l; i += 1024) {
     // fixed, non-structured start vector
     uint32_t h = (uint32_t)i * 2654435761u + 0x9E3779B9u;
     h ^= h >> 15; h *= 2246822519u; h ^= h >> 13;
@@ -407,28 +420,28 @@ __global__ __launch_bounds__(256) void k_trunc_power(const TruncTask* __restrict
   }
   __syncthreads();
   for (int it = 0; it < 4; ++it) {
-    for (int i = threadIdx.x; i < l; i += 256) {
+    for (int i = threadIdx.x; i < l; i += 1024) {
       double a = 0.0;
       for (int k = 0; k < l; ++k) a += S[i + (int64_t)k * l] * v[k];
       w[i] = a;
     }
     __syncthreads();
     double nn = 0.0;
-    for (int i = threadIdx.x; i < l; i += 256) nn += w[i] * w[i];
-    nn = block_sum256(nn);
+    for (int i = threadIdx.x; i < l; i += 1024) nn += w[i] * w[i];
+    nn = block_sum1024(nn);
     const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-    for (int i = threadIdx.x; i < l; i += 256) v[i] = w[i] * inv;
+    for (int i = threadIdx.x; i < l; i += 1024) v[i] = w[i] * inv;
     __syncthreads();
   }
   double num = 0.0, den = 0.0;
-  for (int i = threadIdx.x; i < l; i += 256) {
+  for (int i = threadIdx.x; i < l; i += 1024) {
     double a = 0.0;
     for (int k = 0; k < l; ++k) a += G[i + (int64_t)k * l] * v[k];
     num += v[i] * a;
     den += v[i] * v[i];
   }
-  num = block_sum256(num);
-  den = block_sum256(den);
+  num = block_sum1024(num);
+  den = block_sum1024(den);
   double lam = (den > 0.0) ? num / den : 0.0;
   if (!isfinite(lam) || lam < 0.0) lam = 0.0;
   const double theta = T.tol * T.tol * lam;
@@ -436,17 +449,17 @@ __global__ __launch_bounds__(256) void k_trunc_power(const TruncTask* __restrict
   double* M = arena + T.mpan;
   const int ld = 2 * l;
   double mx = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += 256) {
+  for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += 1024) {
     const int i = (int)(e % l), j = (int)(e / l);
     const double gij = G[e] + (i == j ? theta : 0.0);
     M[i + (int64_t)j * ld] = gij;
     M[l + i + (int64_t)j * ld] = (i == j) ? 1.0 : 0.0;
     if (i == j) mx = fmax(mx, gij);
   }
-  __shared__ double red[256];
+  __shared__ double red[1024];
   red[threadIdx.x] = mx;
   __syncthreads();
-  for (int s2 = 128; s2 > 0; s2 >>= 1) {
+  for (int s2 = 512; s2 > 0; s2 >>= 1) {
     if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
     __syncthreads();
   }
@@ -468,14 +481,14 @@ __global__ __launch_bounds__(256) void k_trunc_x0(const TruncTask* __restrict__ 
   }
 }
 
-// P = (I + X) / 2 in place.
+// P = (I + X) / 2 in place (a grid of workgroups per supernode).
 __global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ tasks,
                                                  double* __restrict__ arena) {
-  const TruncTask T = tasks[blockIdx.x];
+  const TruncTask T = tasks[blockIdx.y];
   const int l = T.l;
   double* X = arena + T.sa;
   const int64_t ll = (int64_t)l * l;
-  for (int64_t e = threadIdx.x; e < ll; e += 256) {
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < ll; e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e % l), j = (int)(e / l);
     X[e] = 0.5 * ((i == j ? 1.0 : 0.0) + X[e]);
   }
@@ -580,13 +593,13 @@ void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s) 
   if (n > 0) hipLaunchKernelGGL(k_trunc_prep, dim3(n), dim3(256), 0, s, t, arena);
 }
 void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_trunc_power, dim3(n), dim3(256), 0, s, t, arena);
+  if (n > 0) hipLaunchKernelGGL(k_trunc_power, dim3(n), dim3(1024), 0, s, t, arena);
 }
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_x0, dim3(64, n), dim3(256), 0, s, t, arena);
 }
 void launch_trunc_p(const TruncTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_trunc_p, dim3(n), dim3(256), 0, s, t, arena);
+  if (n > 0) hipLaunchKernelGGL(k_trunc_p, dim3(64, n), dim3(256), 0, s, t, arena);
 }
 void launch_trunc_compact(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_compact, dim3(n), dim3(256), 0, s, t, arena, ints);

@@ -331,6 +331,8 @@ static int64_t retile128(std::vector<GemmTask>& g, int64_t off) {
   return (int64_t)out.size();
 }
 
+constexpr int kCholQRPasses = 2;
+
 struct Builder {
   Handle& h;
   FactorPlan& P;
@@ -338,6 +340,7 @@ struct Builder {
   int32_t lp_sample = 0;
   int32_t lp_eig = 0;      // products of the spectral truncation (projector iterations)
   int32_t lp_tri = 0;      // the rows of a panel that form the inverse of its diagonal block
+  int32_t ctx = -1;        // >= 0: profiling class of every launch emitted (a compression stage)
   Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {
     if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; lp_eig = 1; lp_tri = 1; }
     if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; lp_eig = 1; lp_tri = 1; }
@@ -370,7 +373,7 @@ struct Builder {
       }
     }
     Cmd c;
-    c.type = type; c.klass = klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
+    c.type = type; c.klass = ctx >= 0 ? ctx : klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
     c.flops = flops;
     c.alt_off = alt_off; c.alt_count = alt_count;
     P.cmds.push_back(c);
@@ -484,7 +487,7 @@ struct Builder {
           fl += 2.0 * std::min(kTile, r - i0) * std::min(kTile, c - j0) * (double)u.k;
         }
     }
-    cmd(kCmdGemm, RSC_K_TRSM, g0, (int64_t)P.gemm.size() - g0, fl, lp_update);
+    cmd(kCmdGemm, RSC_K_LO, g0, (int64_t)P.gemm.size() - g0, fl, lp_update);
   }
 
   // Schur-complement updates of every supernode of one level (Algorithm 1, the
@@ -581,6 +584,7 @@ struct Builder {
     for (int32_t j : level)
       if (h.compressible[j]) js.push_back(j);
     if (js.empty()) return;
+    ctx = RSC_K_SAMPLE;
     // 1. Gaussian samples
     const int64_t ph0 = (int64_t)P.philox.size();
     int64_t maxw = 0;
@@ -623,8 +627,10 @@ struct Builder {
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     }
-    // 4. orthonormalisation: three Cholesky-QR passes, dependent columns dropped
-    for (int pass = 0; pass < 3; ++pass) {
+    ctx = RSC_K_ORTH;
+    // 4. orthonormalisation: Cholesky-QR passes, dependent columns dropped (the first
+    //    pass leaves a condition number below ~1e7, the second restores orthogonality)
+    for (int pass = 0; pass < kCholQRPasses; ++pass) {
       g0 = (int64_t)P.gemm.size(); fl = 0;
       const int64_t s0 = (int64_t)P.gs_g.size();
       std::vector<PanelDesc> pan;
@@ -639,6 +645,7 @@ struct Builder {
       cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
       panel_steps(pan);
     }
+    ctx = RSC_K_BASIS;
     // 5. V = L^O_j U
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
@@ -648,6 +655,7 @@ struct Builder {
       fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    ctx = RSC_K_EIG;
     // 6. Gram G = V^T V (full)
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
@@ -729,6 +737,7 @@ struct Builder {
     }
     static_assert(kNewtonSchulzSteps % 2 == 0, "the iterate must end in sa");
     cmd(kCmdTruncP, RSC_K_EIG, t0, nt, 0);             // sa = P
+    ctx = RSC_K_BASIS;
     // 8. basis of range(P): W = orth(P Omega2) over all l columns; the columns the
     //    orthonormalisation keeps are compacted to the front of Om2, their count is q_j
     {
@@ -751,7 +760,7 @@ struct Builder {
         fl += tiles(gt(C.Sa, 1, l, C.Om2, l, 1, C.Wpan + l, 2 * l, l, l, l, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
-      for (int pass = 0; pass < 3; ++pass) {
+      for (int pass = 0; pass < kCholQRPasses; ++pass) {
         g0 = (int64_t)P.gemm.size(); fl = 0;
         const int64_t s0 = (int64_t)P.gs_g.size();
         std::vector<PanelDesc> pan;
@@ -783,6 +792,7 @@ struct Builder {
       fl += tiles(t2, 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    ctx = -1;
   }
 };
 
