@@ -341,7 +341,9 @@ def main():
         line["roofline"] = roofline(ks, name)
         line["mfma_util"] = mfma_util(ks, res["profiled_factor_ms"])
         top = sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:8]
-        line["kernels"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in top}
+        line["kernels"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                               "tflop_s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0}
+                           for k, v in top}
         line["classes_ms"] = {k: round(v["ms"], 3) for k, v in res["classes"].items() if v["launches"]}
     line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])
     if not args.no_cpu_baseline:
