@@ -41,9 +41,9 @@ PEAK_HBM = 8.0e12
 KERNEL_PREC = {"gemm_staged_f64": "f64", "gemm_staged_f32": "f32", "gemm_staged_bf16x3": "bf16",
                "gemm_staged_bf16": "bf16", "gemm_staged128_f64": "f64", "gemm_staged128_f32": "f32",
                "gemm_staged128_bf16x3": "bf16", "gemm_staged128_bf16": "bf16",
-               "update_staged_f64": "f64", "update_staged_f32": "f32",
-               "update_staged_bf16x3": "bf16", "update_staged_bf16": "bf16", "potrf_f64": "f64"}
-KERNEL_SOURCE = {"gemm_staged": "kernels_gemm.hip", "update_staged": "kernels_gemm.hip",
+               "update_waves_f64": "f64", "update_waves_f32": "f32",
+               "update_waves_bf16x3": "bf16", "update_waves_bf16": "bf16", "potrf_f64": "f64"}
+KERNEL_SOURCE = {"gemm_staged": "kernels_gemm.hip", "update_waves": "kernels_gemm.hip",
                  "potrf_f64": "kernels_dense.hip"}
 DEFAULT_PRECISION = {"diffusion3d_96": "bf16", "batched2d_64": "fp32"}
 

@@ -195,9 +195,11 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
 /* The same timings per kernel (and precision mode) rather than per class: entry k in
  * [0, RSC_KERNELS) gives the kernel's name (static string), its launch count, the
  * summed hipEvent time of those launches in ms (events on the launch stream, so
- * each interval is one launch) and their algorithmic flops.  Any output may be NULL.
- * Errors: RSC_ERR_INVALID_ARG for a null handle or k out of range. */
-#define RSC_KERNELS 29
+ * each interval is one launch) and their algorithmic flops (launches whose extents
+ * depend on the kept ranks are counted at the ranks of the factorisation that ran).
+ * Any output may be NULL.  Errors: RSC_ERR_INVALID_ARG for a null handle or k out of
+ * range. */
+#define RSC_KERNELS 30
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops);
 

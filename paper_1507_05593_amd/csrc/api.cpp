@@ -265,6 +265,7 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
   out->t_pcg_ms = h.t_pcg_ms;
   out->device_bytes = 8.0 * (double)h.arena_size + 4.0 * (double)h.ints_size;
   if (h.fplan) {
+    out->device_bytes += 8.0 * (double)h.fplan->d_xc.n;
     out->gemm_tuned = h.fplan->tuned;
     out->gemm_tile128 = h.fplan->tuned128;
   }

@@ -69,6 +69,11 @@ namespace rsc {
 // tile: output tile edge, 64 or 128 (tasks must have been cut to that edge)
 void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
                         const int32_t* ilim, hipStream_t s);
-void launch_update_staged(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
-                          double* arena, const int32_t* ilim, hipStream_t s);
+// Schur update: one workgroup per target tile (entries in tile order, es = first entry of
+// at most 32 x 32); xbase = operand base (the arena in FP64 mode, else the compact copy).
+void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
+                         double* arena, const double* xbase, const int32_t* ilim, hipStream_t s);
+// Compact row-major copies (FP32 or BF16 hi/lo chunks) of Schur-update operands.
+void launch_compact_rows(int mode, const CompactTask* t, int n, const double* arena, const int32_t* ilim,
+                         double* xc, hipStream_t s);
 }  // namespace rsc

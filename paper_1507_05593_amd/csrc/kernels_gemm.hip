@@ -255,59 +255,245 @@ __global__ __launch_bounds__(Layout<TM>::NT) void k_gemm_staged(const GemmTask* 
       }
 }
 
-// Schur-complement update tile: the same staged product on gathered row runs of X,
-// scattered into the LDS-resident 64 x 64 target tile.  The workgroup owns the tile:
-// it subtracts every descendant's product X(a:b) X(c:d)^T (scattered through the
-// relative map) in entry order and writes the tile back once -- no atomics, so the
-// result does not depend on scheduling.
+// ------------------------------------------------------------------ Schur update
+//
+// Operands of the Schur update (L^O_k, or V_k of a compressed supernode) in the mixed
+// forms are read from a compact row-major copy written once when the operand is final:
+// row t holds the operand's K columns in chunks of 32, each chunk one 128-byte line --
+// FP32 values (kF32), or 32 BF16 high parts followed by the 32 low parts (kBF16x3) --
+// zero beyond the operand's kept columns.  A lane then takes its 8 consecutive k values
+// of a row with one or two 16-byte loads.  The FP64 form reads the column-major arena.
+
+// One 64-row block of one operand per workgroup: the 64 x 32 chunk is read column by
+// column (coalesced), transposed through LDS and written as rows.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_update_staged(const UpdTile* __restrict__ tiles,
-                                                       const UpdEntry* __restrict__ ents,
-                                                       const int32_t* __restrict__ relmap,
-                                                       double* __restrict__ arena,
-                                                       const int32_t* __restrict__ ilim) {
-  __shared__ Stage<MODE, 64> st;
-  __shared__ double tile[64][65];
-  __shared__ int32_t rmap[64], cmap[64];
+__global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restrict__ tasks,
+                                                      const double* __restrict__ arena,
+                                                      const int32_t* __restrict__ ilim,
+                                                      double* __restrict__ xc) {
+  __shared__ double t[KC][65];
+  const CompactTask T = tasks[blockIdx.x];
+  const int K = T.kdim >= 0 ? T.kdim : ilim[-1 - T.kdim];
+  const int tid = threadIdx.x;
+  const double* src = arena + T.src;
+  const int r = tid >> 2, kq = 8 * (tid & 3);     // writer: row r, values kq .. kq + 7
+  for (int c0 = 0; c0 < T.kp; c0 += KC) {
+    __syncthreads();
+    for (int idx = tid; idx < 64 * KC; idx += 256) {
+      const int rr = idx & 63, k = idx >> 6;
+      t[k][rr] = (rr < T.nrows && c0 + k < K) ? src[rr + (int64_t)(c0 + k) * T.ld] : 0.0;
+    }
+    __syncthreads();
+    if (r < T.nrows) {
+      if constexpr (MODE == sBF16x3) {
+        __bf16* row = reinterpret_cast<__bf16*>(xc + T.dst) + (int64_t)r * 2 * T.kp + 2 * c0;
+        v8bf hi, lo;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float f = (float)t[kq + u][r];
+          const __bf16 h = (__bf16)f;
+          hi[u] = h; lo[u] = (__bf16)(f - (float)h);
+        }
+        *reinterpret_cast<v8bf*>(row + kq) = hi;
+        *reinterpret_cast<v8bf*>(row + KC + kq) = lo;
+      } else {
+        float* row = reinterpret_cast<float*>(xc + T.dst) + (int64_t)r * T.kp + c0;
+        v4f a, b;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { a[u] = (float)t[kq + u][r]; b[u] = (float)t[kq + 4 + u][r]; }
+        *reinterpret_cast<v4f*>(row + kq) = a;
+        *reinterpret_cast<v4f*>(row + kq + 4) = b;
+      }
+    }
+  }
+}
+
+// A wave's product of rows [r0, r0 + nr) and [c0, c0 + nc) (each <= 32) of entry E over
+// k < K, as 2 x 2 MFMA blocks of 16 x 16.  Lane (li, lk) supplies k values 8 lk .. 8 lk + 7
+// of each 32-chunk (one bf16 MFMA; for the 16x16x4 FP32 / FP64 MFMAs, step u takes k =
+// 8 lk + u, the same permutation of k on both operands).
+template <int MODE>
+__device__ __forceinline__ void wave_entry(typename Acc<MODE>::T (&acc)[2][2], const UpdEntry& E,
+                                           const double* __restrict__ xbase, int r0, int nr, int c0,
+                                           int nc, int K, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  const int br = (nr + 15) >> 4, bc = (nc + 15) >> 4;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[x][y][e] = 0;
+  if constexpr (MODE == sF64) {
+    const double* XA = xbase + E.x + E.a + r0;
+    const double* XB = xbase + E.x + E.c + c0;
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      double va[2][8], vb[2][8];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int i = 16 * x + li;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + 8 * lk + u;
+          va[x][u] = (x < br && i < nr && k < K) ? XA[i + (int64_t)k * E.ldx] : 0.0;
+          vb[x][u] = (x < bc && i < nc && k < K) ? XB[i + (int64_t)k * E.ldx] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (x < br && y < bc) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[x][u], vb[y][u], acc[x][y], 0, 0, 0);
+    }
+  } else if constexpr (MODE == sF32) {
+    const float* X = reinterpret_cast<const float*>(xbase + E.x);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      v4f a[2][2], b[2][2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int i = 16 * x + li;
+        const float* pa = X + (int64_t)(E.a + r0 + i) * E.ldx + k0 + 8 * lk;
+        const float* pb = X + (int64_t)(E.c + c0 + i) * E.ldx + k0 + 8 * lk;
+        const bool oa = x < br && i < nr, ob = x < bc && i < nc;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          a[x][h] = oa ? *reinterpret_cast<const v4f*>(pa + 4 * h) : v4f{0, 0, 0, 0};
+          b[x][h] = ob ? *reinterpret_cast<const v4f*>(pb + 4 * h) : v4f{0, 0, 0, 0};
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            if (x < br && y < bc)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][u >> 2][u & 3], b[y][u >> 2][u & 3], acc[x][y], 0, 0, 0);
+    }
+  } else {
+    const __bf16* X = reinterpret_cast<const __bf16*>(xbase + E.x);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      v8bf ah[2], al[2], bh[2], bl[2];
+      const v8bf z = {};
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int i = 16 * x + li;
+        const __bf16* pa = X + (int64_t)(E.a + r0 + i) * E.ldx + 2 * k0 + 8 * lk;
+        const __bf16* pb = X + (int64_t)(E.c + c0 + i) * E.ldx + 2 * k0 + 8 * lk;
+        const bool oa = x < br && i < nr, ob = x < bc && i < nc;
+        ah[x] = oa ? *reinterpret_cast<const v8bf*>(pa) : z;
+        al[x] = oa ? *reinterpret_cast<const v8bf*>(pa + KC) : z;
+        bh[x] = ob ? *reinterpret_cast<const v8bf*>(pb) : z;
+        bl[x] = ob ? *reinterpret_cast<const v8bf*>(pb + KC) : z;
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          if (x < br && y < bc) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+          }
+    }
+  }
+}
+
+// Subtracts a wave's block (rows r0.., columns c0.. of entry E) from the LDS tile through
+// the relative map (target positions prm / pcm read before the product).
+template <int MODE>
+__device__ __forceinline__ void wave_scatter(double* tile, const typename Acc<MODE>::T (&acc)[2][2],
+                                             const int (&prm)[2][4], const int (&pcm)[2], int nr, int nc,
+                                             int lane) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int ii, jj;
+        res_pos<MODE>(lane, e, ii, jj);
+        if (16 * x + ii < nr && 16 * y + jj < nc) tile[prm[x][e] + 65 * pcm[y]] -= (double)acc[x][y][e];
+      }
+}
+
+template <int MODE>
+__device__ __forceinline__ void wave_maps(const int32_t* __restrict__ rm, const UpdTile& T, const UpdEntry& E,
+                                          int r0, int nr, int c0, int nc, int lane, int (&prm)[2][4],
+                                          int (&pcm)[2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int ii, jj;
+      res_pos<MODE>(lane, e, ii, jj);
+      const int i = 16 * x + ii;
+      prm[x][e] = i < nr ? rm[E.a + r0 + i] - T.row0 : 0;
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const int j = 16 * y + (lane & 15);
+    pcm[y] = j < nc ? rm[E.c + c0 + j] - T.col0 : 0;
+  }
+}
+
+// Schur-complement update of one 64 x 64 target tile per workgroup (the tile stays in
+// LDS): entries [e0, es) are wider than 32 in some direction -- the four waves take the
+// four 32 x 32 quadrants of one entry, whose target positions are disjoint; entries
+// [es, e1) are at most 32 x 32 -- the waves take four entries at a time and subtract
+// them in wave order, one barrier apart.  Each wave's product runs from registers with
+// no LDS staging, so four entries' loads are in flight per workgroup; the summation
+// order is fixed by the entry list, so the result does not depend on scheduling.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict__ tiles,
+                                                      const UpdEntry* __restrict__ ents,
+                                                      const int32_t* __restrict__ relmap,
+                                                      double* __restrict__ arena,
+                                                      const double* __restrict__ xbase,
+                                                      const int32_t* __restrict__ ilim) {
+  __shared__ double tile[64 * 65];
   const UpdTile T = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
   double* P = arena + T.panel;
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int r = idx & 63, c = idx >> 6;
-    tile[r][c] = (r < T.nrows && c < T.ncols) ? P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] : 0.0;
+    tile[r + 65 * c] = (r < T.nrows && c < T.ncols) ? P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] : 0.0;
   }
-  for (int e = T.e0; e < T.e1; ++e) {
+  __syncthreads();
+  typename Acc<MODE>::T acc[2][2];
+  int prm[2][4], pcm[2];
+  for (int e = T.e0; e < T.es; ++e) {
     const UpdEntry E = ents[e];
-    const int nr = E.b - E.a, nc = E.d - E.c;
-    const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
-    if (tid < 64) {
-      rmap[tid] = tid < nr ? relmap[E.map + E.a + tid] - T.row0 : 0;
-    } else if (tid < 128) {
-      const int t = tid - 64;
-      cmap[t] = t < nc ? relmap[E.map + E.c + t] - T.col0 : 0;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+    const int nr = min(32, E.b - E.a - r0), nc = min(32, E.d - E.c - c0);
+    if (nr > 0 && nc > 0) {
+      const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
+      wave_maps<MODE>(relmap + E.map, T, E, r0, nr, c0, nc, lane, prm, pcm);
+      wave_entry<MODE>(acc, E, xbase, r0, nr, c0, nc, K, lane);
+      wave_scatter<MODE>(tile, acc, prm, pcm, nr, nc, lane);
     }
-    typename Acc<MODE>::T acc[2][2];
-    for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 2; ++y)
-        for (int q = 0; q < 4; ++q) acc[x][y][q] = 0;
-    const double* X = arena + E.x;
-    tile_product<MODE, 64>(st, acc, X + E.a, 1, E.ldx, nr, X + E.c, 1, E.ldx, nc, K);
-    __syncthreads();                       // maps visible; staged tiles no longer needed
-    for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 2; ++y)
-        for (int q = 0; q < 4; ++q) {
-          int ii, jj;
-          res_pos<MODE>(lane, q, ii, jj);
-          const int pr = wr * 32 + x * 16 + ii;
-          const int pc = wc * 32 + y * 16 + jj;
-          if (pr < nr && pc < nc) tile[rmap[pr]][cmap[pc]] -= (double)acc[x][y][q];
-        }
     __syncthreads();
+  }
+  for (int e = T.es; e < T.e1; e += 4) {
+    const int my = e + w;
+    int nr = 0, nc = 0;
+    if (my < T.e1) {
+      const UpdEntry E = ents[my];
+      nr = E.b - E.a; nc = E.d - E.c;
+      const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
+      wave_maps<MODE>(relmap + E.map, T, E, 0, nr, 0, nc, lane, prm, pcm);
+      wave_entry<MODE>(acc, E, xbase, 0, nr, 0, nc, K, lane);
+    }
+    for (int t = 0; t < 4; ++t) {
+      if (w == t && my < T.e1) wave_scatter<MODE>(tile, acc, prm, pcm, nr, nc, lane);
+      __syncthreads();
+    }
   }
   for (int idx = tid; idx < 64 * 64; idx += 256) {
     const int r = idx & 63, c = idx >> 6;
-    if (r < T.nrows && c < T.ncols) P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] = tile[r][c];
+    if (r < T.nrows && c < T.ncols) P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] = tile[r + 65 * c];
   }
 }
 
@@ -329,14 +515,21 @@ void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* ar
   else launch_gemm_tm<64>(mode, t, n, arena, ilim, s);
 }
 
-void launch_update_staged(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
-                          double* arena, const int32_t* ilim, hipStream_t s) {
+void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
+                         double* arena, const double* xbase, const int32_t* ilim, hipStream_t s) {
   if (n <= 0) return;
   switch (mode) {
-    case sF64: hipLaunchKernelGGL(k_update_staged<sF64>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim); break;
-    case sF32: hipLaunchKernelGGL(k_update_staged<sF32>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim); break;
-    default: hipLaunchKernelGGL(k_update_staged<sBF16x3>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, ilim); break;
+    case sF64: hipLaunchKernelGGL(k_update_waves<sF64>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, xbase, ilim); break;
+    case sF32: hipLaunchKernelGGL(k_update_waves<sF32>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, xbase, ilim); break;
+    default: hipLaunchKernelGGL(k_update_waves<sBF16x3>, dim3(n), dim3(256), 0, s, t, e, relmap, arena, xbase, ilim); break;
   }
+}
+
+void launch_compact_rows(int mode, const CompactTask* t, int n, const double* arena, const int32_t* ilim,
+                         double* xc, hipStream_t s) {
+  if (n <= 0) return;
+  if (mode == sF32) hipLaunchKernelGGL(k_compact_rows<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
+  else hipLaunchKernelGGL(k_compact_rows<sBF16x3>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
 }
 
 }  // namespace rsc

@@ -341,9 +341,25 @@ struct Builder {
   int32_t lp_eig = 0;      // products of the spectral truncation (projector iterations)
   int32_t lp_tri = 0;      // the rows of a panel that form the inverse of its diagonal block
   int32_t ctx = -1;        // >= 0: profiling class of every launch emitted (a compression stage)
+  std::vector<int64_t> xc_off;   // compact copy of supernode j's update operand (doubles), or -1
+  std::vector<int32_t> xc_kp;    // its row length: kept columns rounded up to 32
   Builder(Handle& hh, FactorPlan& pp) : h(hh), P(pp) {
     if (P.precision == RSC_MIXED_BF16) { lp_update = 2; lp_sample = 3; lp_eig = 1; lp_tri = 1; }
     if (P.precision == RSC_MIXED_FP32) { lp_update = 1; lp_sample = 3; lp_eig = 1; lp_tri = 1; }
+    const Symbolic& S = h.S;
+    xc_off.assign(S.M(), -1);
+    xc_kp.assign(S.M(), 0);
+    if (lp_update == 0) return;
+    // r x kp FP32 values, or r x kp BF16 pairs: r * kp / 2 doubles either way
+    int64_t off = 0;
+    for (int64_t j = 0; j < S.M(); ++j) {
+      if (S.r(j) == 0) continue;
+      const int32_t kmax = (P.compressed && h.compressible[j]) ? h.comp[j].ell : S.c(j);
+      xc_kp[j] = (kmax + 31) / 32 * 32;
+      xc_off[j] = off;
+      off += ((int64_t)S.r(j) * xc_kp[j] / 2 + 31) / 32 * 32;
+    }
+    P.xc_size = off;
   }
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
@@ -376,6 +392,8 @@ struct Builder {
     c.type = type; c.klass = ctx >= 0 ? ctx : klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
     c.flops = flops;
     c.alt_off = alt_off; c.alt_count = alt_count;
+    if (type == kCmdGemm)
+      for (int64_t i = off; i < off + count && !c.dyn; ++i) c.dyn = (P.gemm[i].nlim >= 0 || P.gemm[i].klim >= 0);
     P.cmds.push_back(c);
   }
 
@@ -494,12 +512,13 @@ struct Builder {
   // descendant loop), as target tiles with ordered contribution lists.
   void updates(const std::vector<int32_t>& level) {
     const Symbolic& S = h.S;
-    struct TileW { UpdTile t; double work; std::vector<UpdEntry> e; };
+    struct TileW { UpdTile t; double work; std::vector<UpdEntry> e; std::vector<double> ke; };
     std::vector<TileW> all;
     for (int32_t j : level) {
       const int32_t c = S.c(j), r = S.r(j);
       const int32_t nI = (c + r + kTile - 1) / kTile, nJ = (c + kTile - 1) / kTile;
       std::vector<std::vector<UpdEntry>> ents((size_t)nI * nJ);
+      std::vector<std::vector<double>> kes((size_t)nI * nJ);   // planning inner dimension
       std::vector<double> work((size_t)nI * nJ, 0.0);
       for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
         const Pair& pr = S.pairs[q];
@@ -517,6 +536,10 @@ struct Builder {
           base.ldx = S.r(k);
           base.kdim = S.c(k);
           kest = S.c(k);
+        }
+        if (lp_update != 0) {            // the compact copy, shifted to the pair's rows
+          base.x = xc_off[k] + (int64_t)pr.p0 * xc_kp[k] / 2;
+          base.ldx = (lp_update == 2 ? 2 : 1) * xc_kp[k];
         }
         base.map = pr.map_off;
         const int32_t* rm = S.relmap.data() + pr.map_off;
@@ -543,6 +566,7 @@ struct Builder {
             e.a = R[1]; e.b = R[2]; e.c = Cc[1]; e.d = Cc[2];
             const size_t id = (size_t)R[0] * nJ + Cc[0];
             ents[id].push_back(e);
+            kes[id].push_back(kest);
             work[id] += 2.0 * (e.b - e.a) * (e.d - e.c) * kest;
           }
       }
@@ -558,22 +582,66 @@ struct Builder {
           tw.t.ncols = std::min(kTile, c - J * kTile);
           tw.work = work[id];
           tw.e = std::move(ents[id]);
+          tw.ke = std::move(kes[id]);
           all.push_back(std::move(tw));
         }
     }
     if (all.empty()) return;
     // heaviest tiles first: the long ones start early and the tail is short
     std::stable_sort(all.begin(), all.end(), [](const TileW& x, const TileW& y) { return x.work > y.work; });
+    // within a tile: entries wider than 32 first (list order), then the others by
+    // decreasing inner dimension, so that the four entries taken together are alike
     const int64_t t0 = (int64_t)P.tiles.size();
     double fl = 0;
+    bool dyn = false;
     for (auto& tw : all) {
+      std::vector<int32_t> idx(tw.e.size());
+      for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int32_t)q;
+      auto big = [&](int32_t q) { return tw.e[q].b - tw.e[q].a > 32 || tw.e[q].d - tw.e[q].c > 32; };
+      std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+        const bool bx = big(x), by = big(y);
+        if (bx != by) return bx;
+        return !bx && tw.ke[x] > tw.ke[y];
+      });
       tw.t.e0 = (int32_t)P.ents.size();
-      for (auto& e : tw.e) P.ents.push_back(e);
+      tw.t.es = tw.t.e0;
+      for (int32_t q : idx) {
+        const UpdEntry& e = tw.e[q];
+        if (big(q)) ++tw.t.es;
+        fl += 2.0 * (e.b - e.a) * (e.d - e.c) * tw.ke[q];
+        dyn |= (e.kdim < 0);
+        P.ents.push_back(e);
+      }
       tw.t.e1 = (int32_t)P.ents.size();
       P.tiles.push_back(tw.t);
-      fl += tw.work;
     }
     cmd(kCmdUpdate, RSC_K_UPDATE, t0, (int64_t)P.tiles.size() - t0, fl, lp_update);
+    P.cmds.back().dyn = dyn;
+  }
+
+  // Compact row-major copies of the Schur-update operands of a level once they are
+  // final (mixed forms): L^O_j of the supernodes kept explicit, V_j of the compressed.
+  void compact_operands(const std::vector<int32_t>& level, bool compressed_ones) {
+    if (lp_update == 0) return;
+    const Symbolic& S = h.S;
+    const int64_t c0 = (int64_t)P.compact.size();
+    for (int32_t j : level) {
+      const int32_t r = S.r(j);
+      if (r == 0 || xc_off[j] < 0) continue;
+      const bool comp = P.compressed && h.compressible[j];
+      if (comp != compressed_ones) continue;
+      for (int32_t r0 = 0; r0 < r; r0 += kTile) {
+        CompactTask t{};
+        t.src = (comp ? h.comp[j].Vj : h.a_lo + h.lo_off[j]) + r0;
+        t.dst = xc_off[j] + (int64_t)r0 * xc_kp[j] / 2;
+        t.ld = r;
+        t.nrows = std::min(kTile, r - r0);
+        t.kdim = comp ? -(1 + h.comp[j].qslot) : S.c(j);
+        t.kp = xc_kp[j];
+        P.compact.push_back(t);
+      }
+    }
+    cmd(kCmdCompact, RSC_K_UPDATE, c0, (int64_t)P.compact.size() - c0, 0.0, lp_update);
   }
 
   // Algorithm 3 on the explicit L^O_j of every compressible supernode of a level,
@@ -876,7 +944,11 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
     }
     B.panel_steps(pan);
     B.offdiag_solve(lev);
-    if (compressed) B.compression(lev, tol);
+    B.compact_operands(lev, false);
+    if (compressed) {
+      B.compression(lev, tol);
+      B.compact_operands(lev, true);
+    }
   }
   // algorithmic flop counts of the method (per supernode, from the symbolic plan)
   for (int64_t j = 0; j < S.M(); ++j) {
@@ -894,6 +966,11 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gemm, P->gemm)).code) return e;
   if ((e = upload(P->d_tiles, P->tiles)).code) return e;
   if ((e = upload(P->d_ents, P->ents)).code) return e;
+  if ((e = upload(P->d_compact, P->compact)).code) return e;
+  if (P->xc_size > 0) {
+    HIPCHK(hipMalloc((void**)&P->d_xc.p, sizeof(double) * P->xc_size));
+    P->d_xc.n = P->xc_size;
+  }
   if ((e = upload(P->d_potrf, P->potrf)).code) return e;
   if ((e = upload(P->d_philox, P->philox)).code) return e;
   if ((e = upload(P->d_trunc, P->trunc)).code) return e;
@@ -910,20 +987,44 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
 
 // ------------------------------------------------------------------ executor
 
-struct EventPair { hipEvent_t a, b; int32_t klass, kid; double flops; };
+struct EventPair { hipEvent_t a, b; int32_t klass, kid; double flops; const Cmd* cmd; const FactorPlan* plan; };
+
+// Flops of a launch whose extents come from device ranks, from its tasks and the
+// ranks as they stand (I: host copy of the int arena).
+static double recount_flops(const Cmd& c, const FactorPlan& P, const std::vector<int32_t>& I) {
+  double fl = 0;
+  if (c.type == kCmdUpdate) {
+    for (int64_t t = c.off; t < c.off + c.count; ++t)
+      for (int32_t i = P.tiles[t].e0; i < P.tiles[t].e1; ++i) {
+        const UpdEntry& e = P.ents[i];
+        const double K = e.kdim >= 0 ? e.kdim : I[-1 - e.kdim];
+        fl += 2.0 * (e.b - e.a) * (e.d - e.c) * K;
+      }
+  } else if (c.type == kCmdGemm) {
+    const int32_t T = (int32_t)c.b;
+    for (int64_t i = c.off; i < c.off + c.count; ++i) {
+      const GemmTask& t = P.gemm[i];
+      const int32_t n = t.nlim >= 0 ? std::min(t.n, I[t.nlim]) : t.n;
+      const int32_t K = t.klim >= 0 ? std::min(t.k, I[t.klim]) : t.k;
+      fl += 2.0 * std::min(T, t.m - t.i0) * std::max(0, std::min(T, n - t.j0)) * (double)K;
+    }
+  }
+  return fl;
+}
 
 static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "gemm_staged_f64", "gemm_staged_f32", "gemm_staged_bf16x3", "gemm_staged_bf16",
-    "update_staged_f64", "update_staged_f32", "update_staged_bf16x3", "update_staged_bf16",
+    "update_waves_f64", "update_waves_f32", "update_waves_bf16x3", "update_waves_bf16",
     "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
     "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
-    "gemm_staged128_bf16x3", "gemm_staged128_bf16"};
+    "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
     case kCmdGemm: return (int32_t)((b == 128 ? 25 : 0) + (a & 3));
     case kCmdUpdate: return (int32_t)(4 + (a & 3));
+    case kCmdCompact: return 29;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -956,7 +1057,11 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdAssemble: launch_assemble(A + h.a_values, h.d_asm_slot.p, c.count, A, s); break;
     case kCmdIdent: launch_scatter_const(h.d_ident_slot.p, c.count, 1.0, A, s); break;
     case kCmdUpdate:
-      launch_update_staged((int)c.a, P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A, I, s);
+      launch_update_waves((int)c.a, P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A,
+                          c.a ? P->d_xc.p : A, I, s);
+      break;
+    case kCmdCompact:
+      launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
     case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
@@ -1002,6 +1107,8 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
       ep.klass = c.klass;
       ep.kid = kernel_id(c.type, c.a, c.b);
       ep.flops = c.flops;
+      ep.cmd = c.dyn ? &c : nullptr;
+      ep.plan = P;
       HIPCHK(hipEventRecord(ep.a, s));
       launch_cmd(h, c, P, Q, s);
       HIPCHK(hipEventRecord(ep.b, s));
@@ -1015,9 +1122,17 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
 }
 
 static Error collect_events(Handle& h, std::vector<EventPair>& evs) {
+  std::vector<int32_t> ints;
   for (auto& ep : evs) {
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, ep.a, ep.b));
+    if (ep.cmd && ep.plan) {
+      if (ints.empty()) {
+        ints.resize((size_t)h.ints_size);
+        HIPCHK(hipMemcpy(ints.data(), h.ints.p, sizeof(int32_t) * ints.size(), hipMemcpyDeviceToHost));
+      }
+      ep.flops = recount_flops(*ep.cmd, *ep.plan, ints);
+    }
     h.prof.launches[ep.klass] += 1;
     h.prof.ms[ep.klass] += ms;
     h.prof.flops[ep.klass] += ep.flops;

@@ -24,7 +24,7 @@ enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdGatherRows,
+  kCmdGatherRows, kCmdCompact,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -41,6 +41,8 @@ struct Cmd {
   double flops;         // algorithmic flops of the launch (profiling)
   int64_t alt_off = -1; // product launch: 128-tile task list awaiting the tile tuner
   int64_t alt_count = 0;
+  bool dyn = false;     // inner or column extents read from device ranks: the profile
+                        // recounts the flops from the tasks once the ranks are known
 };
 
 template <class T>
@@ -79,6 +81,8 @@ struct FactorPlan {
   std::vector<GemmTask> gemm;
   std::vector<UpdTile> tiles;
   std::vector<UpdEntry> ents;
+  std::vector<CompactTask> compact;
+  int64_t xc_size = 0;                // compact operand copies (doubles; mixed forms)
   std::vector<PotrfTask> potrf;
   std::vector<PhiloxTask> philox;
   std::vector<TruncTask> trunc;
@@ -87,6 +91,8 @@ struct FactorPlan {
   DevArray<GemmTask> d_gemm;
   DevArray<UpdTile> d_tiles;
   DevArray<UpdEntry> d_ents;
+  DevArray<CompactTask> d_compact;
+  DevArray<double> d_xc;              // compact row-major Schur-update operands (mixed forms)
   DevArray<PotrfTask> d_potrf;
   DevArray<PhiloxTask> d_philox;
   DevArray<TruncTask> d_trunc;

@@ -33,17 +33,30 @@ struct UpdTile {
   int32_t row0, col0;          // tile origin in panel-local rows / columns
   int32_t nrows, ncols;        // valid extent (<= 64)
   int32_t e0, e1;
+  int32_t es;                  // entries [e0, es) exceed 32 rows or columns, [es, e1) do not
 };
 
 // One descendant's contribution to one target tile: rows [a,b) and [c,d) of the
 // gathered operand X (X(t, m) = arena[x + t + m*ldx]); the target position of
 // gathered row t is relmap[map + t] (panel-local row; as a column index when t < nD).
+//   Mixed forms: X is the compact row-major copy, X(t, m) at element t * ldx + m (FP32) or
+//   t * ldx + 2 * (m / 32) * 32 + m % 32 (BF16 high part; low part 32 further), counted
+//   from the double offset x of the operand's compact copy, shifted to the pair's rows.
 struct UpdEntry {
   int64_t x;
   int64_t map;
   int32_t ldx;
   int32_t kdim;                // inner dimension, or -(1 + int-arena slot) of a device rank
   int32_t a, b, c, d;
+};
+
+// One 64-row block of a Schur-update operand to copy into the compact row-major form:
+// rows [0, nrows) of the column-major block at arena offset src (column stride ld),
+// columns k < kdim (or the device rank at slot -(1 + kdim)); zero up to kp (a multiple
+// of 32), written at double offset dst of the compact buffer.
+struct CompactTask {
+  int64_t src, dst;
+  int32_t ld, nrows, kdim, kp;
 };
 
 // Cholesky of one diagonal block (<= 64) of a panel plus the explicit inverse of
