@@ -714,7 +714,8 @@ struct Builder {
       panel_steps(pan);
     }
     ctx = RSC_K_BASIS;
-    // 5. V = L^O_j U
+    // 5. V = L^O_j U (FP32 MFMA in the mixed forms, like the other basis products: its
+    //    rounding, ~1e-7 of |V|, is far below the truncation threshold tol^2 lambda_max)
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
@@ -722,7 +723,7 @@ struct Builder {
       const int64_t LO = h.a_lo + h.lo_off[j];
       fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
     }
-    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
     ctx = RSC_K_EIG;
     // 6. Gram G = V^T V (full)
     g0 = (int64_t)P.gemm.size(); fl = 0;
@@ -827,7 +828,7 @@ struct Builder {
         const int32_t l = C.ell;
         fl += tiles(gt(C.Sa, 1, l, C.Om2, l, 1, C.Wpan + l, 2 * l, l, l, l, 1.0, 0.0), 0, 0, false);
       }
-      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
+      cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
       for (int pass = 0; pass < kCholQRPasses; ++pass) {
         g0 = (int64_t)P.gemm.size(); fl = 0;
         const int64_t s0 = (int64_t)P.gs_g.size();
@@ -859,7 +860,7 @@ struct Builder {
       t2.nlim = C.qslot;
       fl += tiles(t2, 0, 0, false);
     }
-    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
     ctx = -1;
   }
 };
