@@ -73,18 +73,18 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 //         its L column and its row and column of the inverse become zero;
 // mode 2: the same with the threshold 1e-8 * scale.
 // Right-looking elimination four columns at a time, register-blocked: thread (tx, ty)
-// of the TD x TD grid (TD = 32: 1024 threads) owns entries (ty + TD a, tx + TD b),
-// a, b < 64 / TD, of L and of W (W starts as I and ends as L^{-1}).  Step K publishes
+// of the 16 x 32 grid (512 threads, so that the 16 entries of L and W per thread and the
+// step's temporaries stay in registers) owns entries (ty + 32 a, tx + 16 b), a < 2,
+// b < 4, of L and of W (W starts as I and ends as L^{-1}).  Step K publishes
 // the four-column panel and rows 4K..4K+3 of W through double-buffered LDS (one
 // barrier); every thread then factors the 4 x 4 diagonal block and inverts it in
 // registers (Ld, Ldi), forms l_i = Ldi p_i for its rows and columns, and applies the
 // rank-4 updates
 //   L(i, j) -= l_i . l_j,   W(block rows) = Ldi W(block rows),   W(i, :) -= l_i . W(block rows).
 // Sixteen sequential steps instead of sixty-four; global accesses go through an LDS tile.
-constexpr int kPotrfTD = 32;                 // threads per dimension of the block grid
-constexpr int kPotrfNE = 64 / kPotrfTD;      // entries per thread and dimension
+constexpr int kPotrfTX = 16, kPotrfTY = 32;  // thread grid: 16 columns x 32 rows (512 threads)
 
-__global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
+__global__ __launch_bounds__(kPotrfTX * kPotrfTY) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
   __shared__ double tile[64][65];
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
   __shared__ double wrows[2][4][64];
   const PotrfTask T = tasks[blockIdx.x];
   const int tid = threadIdx.x;
-  constexpr int TD = kPotrfTD, NE = kPotrfNE, NT = TD * TD;
-  const int tx = tid % TD, ty = tid / TD;
+  constexpr int TX = kPotrfTX, TY = kPotrfTY, NX = 64 / TX, NY = 64 / TY, NT = TX * TY;
+  const int tx = tid % TX, ty = tid / TX;
   const int nb = T.nb;
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
@@ -103,12 +103,12 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
     tile[r][c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
   }
   __syncthreads();
-  double L[NE][NE], W[NE][NE];
+  double L[NY][NX], W[NY][NX];
 #pragma unroll
-  for (int a = 0; a < NE; ++a)
+  for (int a = 0; a < NY; ++a)
 #pragma unroll
-    for (int b = 0; b < NE; ++b) {
-      const int i = ty + TD * a, j = tx + TD * b;
+    for (int b = 0; b < NX; ++b) {
+      const int i = ty + TY * a, j = tx + TX * b;
       L[a][b] = tile[i][j];
       W[a][b] = (i == j && i < nb) ? 1.0 : 0.0;
     }
@@ -116,25 +116,25 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
   bool bad = false;
   const int nsteps = (nb + 3) >> 2;
   for (int K = 0; K < nsteps; ++K) {
-    const int k0 = 4 * K, kb = k0 / TD, ko = k0 % TD, buf = K & 1;
+    const int k0 = 4 * K, kbx = k0 / TX, kox = k0 % TX, kby = k0 / TY, koy = k0 % TY, buf = K & 1;
     const int nbk = min(4, nb - k0);
     // publish the panel columns k0..k0+3 (rows >= k0) and rows k0..k0+3 of W
-    if (tx >= ko && tx < ko + 4) {
+    if (tx >= kox && tx < kox + 4) {
 #pragma unroll
-      for (int a = 0; a < NE; ++a)
+      for (int a = 0; a < NY; ++a)
 #pragma unroll
-        for (int b = 0; b < NE; ++b)
-          if (b == kb) {
-            const int i = ty + TD * a;
-            if (i >= k0) pan[buf][i][tx - ko] = L[a][b];
+        for (int b = 0; b < NX; ++b)
+          if (b == kbx) {
+            const int i = ty + TY * a;
+            if (i >= k0) pan[buf][i][tx - kox] = L[a][b];
           }
     }
-    if (ty >= ko && ty < ko + 4) {
+    if (ty >= koy && ty < koy + 4) {
 #pragma unroll
-      for (int a = 0; a < NE; ++a)
-        if (a == kb) {
+      for (int a = 0; a < NY; ++a)
+        if (a == kby) {
 #pragma unroll
-          for (int b = 0; b < NE; ++b) wrows[buf][ty - ko][tx + TD * b] = W[a][b];
+          for (int b = 0; b < NX; ++b) wrows[buf][ty - koy][tx + TX * b] = W[a][b];
         }
     }
     __syncthreads();
@@ -185,10 +185,10 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
       }
     // l vectors of this thread's columns (j > k0 + 3) and new rows k0..k0+3 of W for
     // its columns; the row vectors l_i are formed one row at a time below
-    double lj[NE][4], wn[NE][4];
+    double lj[NX][4], wn[NX][4];
 #pragma unroll
-    for (int b = 0; b < NE; ++b) {
-      const int j = tx + TD * b;
+    for (int b = 0; b < NX; ++b) {
+      const int j = tx + TX * b;
       double pv[4], wb[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -208,8 +208,8 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
       }
     }
 #pragma unroll
-    for (int a = 0; a < NE; ++a) {
-      const int i = ty + TD * a;
+    for (int a = 0; a < NY; ++a) {
+      const int i = ty + TY * a;
       double li[4];
       {
         double pv[4];
@@ -224,10 +224,10 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
         }
       }
 #pragma unroll
-      for (int b = 0; b < NE; ++b) {
-        const int j = tx + TD * b;
-        if (b == kb && tx >= ko && tx < ko + 4) {          // the panel columns
-          const int cc = tx - ko;
+      for (int b = 0; b < NX; ++b) {
+        const int j = tx + TX * b;
+        if (b == kbx && tx >= kox && tx < kox + 4) {        // the panel columns
+          const int cc = tx - kox;
           if (i > k0 + 3) {
             L[a][b] = (cc == 0) ? li[0] : (cc == 1) ? li[1] : (cc == 2) ? li[2] : li[3];
           } else if (i >= k0 && i - k0 >= cc) {
@@ -243,8 +243,8 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
         } else if (i > k0 + 3 && j > k0 + 3) {
           L[a][b] -= li[0] * lj[b][0] + li[1] * lj[b][1] + li[2] * lj[b][2] + li[3] * lj[b][3];
         }
-        if (a == kb && ty >= ko && ty < ko + 4) {           // rows k0..k0+3 of W
-          const int rr = ty - ko;
+        if (a == kby && ty >= koy && ty < koy + 4) {        // rows k0..k0+3 of W
+          const int rr = ty - koy;
           W[a][b] = (rr == 0) ? wn[b][0] : (rr == 1) ? wn[b][1] : (rr == 2) ? wn[b][2] : wn[b][3];
         } else if (i > k0 + 3) {
           W[a][b] -= li[0] * wn[b][0] + li[1] * wn[b][1] + li[2] * wn[b][2] + li[3] * wn[b][3];
@@ -255,9 +255,9 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
   if (bad && tid == 0) atomicMin(&status[0], T.sn);
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < NE; ++a)
+  for (int a = 0; a < NY; ++a)
 #pragma unroll
-    for (int b = 0; b < NE; ++b) tile[ty + TD * a][tx + TD * b] = L[a][b];
+    for (int b = 0; b < NX; ++b) tile[ty + TY * a][tx + TX * b] = L[a][b];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4096 / NT; ++u) {
@@ -266,9 +266,9 @@ __global__ __launch_bounds__(kPotrfTD * kPotrfTD) void k_potrf_f64(const PotrfTa
   }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < NE; ++a)
+  for (int a = 0; a < NY; ++a)
 #pragma unroll
-    for (int b = 0; b < NE; ++b) tile[ty + TD * a][tx + TD * b] = W[a][b];
+    for (int b = 0; b < NX; ++b) tile[ty + TY * a][tx + TX * b] = W[a][b];
   __syncthreads();
   double* inv = arena + T.inv;
 #pragma unroll
@@ -579,7 +579,7 @@ void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* aren
   if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, s, slot, n, v, arena);
 }
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(kPotrfTD * kPotrfTD), 0, s, t, arena, status);
+  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(kPotrfTX * kPotrfTY), 0, s, t, arena, status);
 }
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
                    hipStream_t s) {

@@ -57,9 +57,12 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
 }
 
 // Forward-sweep chunk: the products X(a:b, :) v of a run of descendant entries of one
-// target block, accumulated in LDS (entry e goes to wave (e - e0) mod 4, lane = row,
-// unrolled inner loop; the four per-wave sums are added in a fixed order) and written
-// as one 64-entry partial block.  k_part_apply subtracts the block's partials from y.
+// target block, accumulated in LDS (entry e goes to wave (e - e0) mod 4; the four
+// per-wave sums are added in a fixed order) and written as one 64-entry partial block.
+// Within a wave, an entry of nr rows takes lanes as P = max(8, nr rounded up to a
+// power of two) rows by G = 64 / P column groups, group g summing columns g, g + G, ...,
+// so that one load instruction reads G columns of the column-major X; the groups are
+// then added by a fixed butterfly.  k_part_apply subtracts the block's partials from y.
 __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ chunks,
                                                   const FwdTile* __restrict__ tiles,
                                                   const FwdEntry* __restrict__ ents,
@@ -76,14 +79,18 @@ __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ c
     const FwdEntry E = ents[e];
     const int nr = E.b - E.a;
     const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
-    if (lane < nr) {
-      const double* X = arena + E.x + E.a + lane;
+    const int P = nr <= 8 ? 8 : nr <= 16 ? 16 : nr <= 32 ? 32 : 64;   // wave-uniform
+    const int G = 64 / P;
+    const int row = lane & (P - 1), g = lane / P;
+    double s = 0.0;
+    if (row < nr) {
+      const double* X = arena + E.x + E.a + row;
       const double* v = arena + E.v;
-      double s = 0.0;
 #pragma unroll 8
-      for (int m = 0; m < K; ++m) s += X[(int64_t)m * E.ldx] * v[m];
-      acc[w][relmap[E.map + E.a + lane] - T.row0] += s;
+      for (int m = g; m < K; m += G) s += X[(int64_t)m * E.ldx] * v[m];
     }
+    for (int o = P; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (g == 0 && row < nr) acc[w][relmap[E.map + E.a + row] - T.row0] += s;
   }
   __syncthreads();
   if (threadIdx.x < 64) {

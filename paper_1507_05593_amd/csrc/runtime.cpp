@@ -1336,7 +1336,7 @@ static Error build_solve_plan(Handle& h) {
       }
       // Each block's entries are cut into runs of about equal work (rows x depth; the
       // sample count stands in for a compressed descendant's rank) so that the level
-      // has about 1024 chunks; one launch computes the chunks' partial blocks, a second
+      // has about 2048 chunks; one launch computes the chunks' partial blocks, a second
       // subtracts them from y in a fixed order.
       auto ework = [&](const FwdEntry& e) {
         const double K = e.kdim >= 0 ? e.kdim : (double)h.comp[(-1 - e.kdim) - h.i_ranks].ell;
@@ -1345,7 +1345,7 @@ static Error build_solve_plan(Handle& h) {
       double wl = 0;
       for (auto& bk : blks)
         for (auto& e : bk.e) wl += ework(e);
-      const double target = std::max(wl / 1024.0, 64.0 * 64.0);
+      const double target = std::max(wl / 2048.0, 64.0 * 64.0);
       const int64_t c0f = (int64_t)Q->fchunks.size(), a0 = (int64_t)Q->papply.size();
       int32_t slot = 0;
       for (auto& bk : blks) {
