@@ -214,12 +214,24 @@ __device__ void tile_product(Stage<MODE, TM>& st,
   }
 }
 
+// Epilogue slab: 64 columns of the tile as accumulator values, column-major with an
+// odd pitch; it reuses the operand stage's LDS.
+template <int MODE> struct AccElem { typedef float T; };
+template <> struct AccElem<sF64> { typedef double T; };
+template <int TM> constexpr int kSlabPitch = TM + 1;
 template <int MODE, int TM>
-__global__ __launch_bounds__(Layout<TM>::NT) void k_gemm_staged(const GemmTask* __restrict__ tasks,
+constexpr size_t kGemmSmem = sizeof(Stage<MODE, TM>) > 64 * kSlabPitch<TM> * sizeof(typename AccElem<MODE>::T)
+                                 ? sizeof(Stage<MODE, TM>)
+                                 : 64 * kSlabPitch<TM> * sizeof(typename AccElem<MODE>::T);
+
+template <int MODE, int TM>
+__global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1) void k_gemm_staged(const GemmTask* __restrict__ tasks,
                                                                double* __restrict__ arena,
                                                                const int32_t* __restrict__ ilim) {
   using Ly = Layout<TM>;
-  __shared__ Stage<MODE, TM> st;
+  using AE = typename AccElem<MODE>::T;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kGemmSmem<MODE, TM>];
+  Stage<MODE, TM>& st = *reinterpret_cast<Stage<MODE, TM>*>(smem);
   const GemmTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
@@ -235,24 +247,38 @@ __global__ __launch_bounds__(Layout<TM>::NT) void k_gemm_staged(const GemmTask* 
   const double* A = arena + T.a + (int64_t)T.i0 * T.ais;
   const double* B = arena + T.b + (int64_t)T.j0 * T.bjs;
   tile_product<MODE, TM>(st, acc, A, T.ais, T.aks, T.m - T.i0, B, T.bjs, T.bks, n - T.j0, K);
-  __syncthreads();                         // A/B may alias C (in-place triangular solve)
+  // C = alpha P (+ beta D), 64 columns at a time through LDS so that C and D are read
+  // and written one contiguous column (up to TM rows) per wave instruction
+  AE* slab = reinterpret_cast<AE*>(smem);
   double* C = arena + T.c;
+  const int mrows = min(TM, T.m - T.i0);
+  for (int s0 = 0; s0 < TM; s0 += 64) {
+    __syncthreads();                       // A/B may alias C; the stage (or the last slab) is free
+    if (wc * Ly::CW < s0 + 64 && wc * Ly::CW + Ly::CW > s0) {
 #pragma unroll
-  for (int x = 0; x < Ly::BR; ++x)
+      for (int x = 0; x < Ly::BR; ++x)
 #pragma unroll
-    for (int y = 0; y < Ly::BC; ++y)
-      for (int e = 0; e < 4; ++e) {
-        int ii, jj;
-        res_pos<MODE>(lane, e, ii, jj);
-        const int i = T.i0 + wr * Ly::RW + x * 16 + ii;
-        const int j = T.j0 + wc * Ly::CW + y * 16 + jj;
-        if (i < T.m && j < n) {
-          double* cp = C + i + (int64_t)j * T.ldc;
-          const double v = T.alpha * (double)acc[x][y][e];
-          const double* dp = (T.d >= 0) ? arena + T.d + i + (int64_t)j * T.ldc : cp;
-          *cp = (T.beta == 0.0) ? v : v + T.beta * *dp;
-        }
+        for (int y = 0; y < Ly::BC; ++y)
+          for (int e = 0; e < 4; ++e) {
+            int ii, jj;
+            res_pos<MODE>(lane, e, ii, jj);
+            const int i = wr * Ly::RW + x * 16 + ii;
+            const int j = wc * Ly::CW + y * 16 + jj - s0;
+            slab[j * kSlabPitch<TM> + i] = acc[x][y][e];
+          }
+    }
+    __syncthreads();
+    const int ncol = min(64, n - T.j0 - s0);
+    for (int idx = threadIdx.x; idx < TM * 64; idx += Ly::NT) {
+      const int i = idx % TM, j = idx / TM;
+      if (i < mrows && j < ncol) {
+        const int64_t o = (T.i0 + i) + (int64_t)(T.j0 + s0 + j) * T.ldc;
+        const double v = T.alpha * (double)slab[j * kSlabPitch<TM> + i];
+        if (T.beta == 0.0) C[o] = v;
+        else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + o] : C[o]);
       }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ Schur update
