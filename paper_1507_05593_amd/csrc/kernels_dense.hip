@@ -70,211 +70,168 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 // mode 0: a pivot that is not positive and finite records the supernode in
 //         status[0] (smallest id wins) and is replaced by 1 so the sweep stays finite.
 // mode 1 (orthonormalisation): a pivot <= 1e-14 * scale marks the column dependent:
-//         its L column and its row and column of the inverse become zero;
+//         its L column becomes the unit vector and its row and column of the inverse
+//         become zero;
 // mode 2: the same with the threshold 1e-8 * scale.
-// Right-looking elimination four columns at a time, register-blocked: thread (tx, ty)
-// of the 16 x 32 grid (512 threads, so that the 16 entries of L and W per thread and the
-// step's temporaries stay in registers) owns entries (ty + 32 a, tx + 16 b), a < 2,
-// b < 4, of L and of W (W starts as I and ends as L^{-1}).  Step K publishes
-// the four-column panel and rows 4K..4K+3 of W through double-buffered LDS (one
-// barrier); every thread then factors the 4 x 4 diagonal block and inverts it in
-// registers (Ld, Ldi), forms l_i = Ldi p_i for its rows and columns, and applies the
-// rank-4 updates
-//   L(i, j) -= l_i . l_j,   W(block rows) = Ldi W(block rows),   W(i, :) -= l_i . W(block rows).
-// Sixteen sequential steps instead of sixty-four; global accesses go through an LDS tile.
-constexpr int kPotrfTX = 16, kPotrfTY = 32;  // thread grid: 16 columns x 32 rows (512 threads)
+// Past the block edge (nb < 64) the tile is the identity.
+//
+// Blocked right-looking elimination over four 16-column block steps, the tile in LDS:
+//   1. wave 0 factors the 16 x 16 diagonal block and forms its inverse in registers
+//      (lane (j, g) holds column j, rows 4g..4g+3; one column at a time, the column
+//      and the rows it needs exchanged by lane shuffles);
+//   2. the rows below: P = A_below D^{-T}, one 16-row block per wave (FP64 MFMA);
+//   3. the trailing lower blocks: A -= P P^T, blocks dealt round robin to the waves.
+// The inverse's off-diagonal blocks then follow block row by block row:
+//   W_ij = -D_i^{-1} sum_{m = j}^{i-1} L_im W_mj.
+// MFMA v_mfma_f64_16x16x4f64: A operand (row lane % 16, k lane / 16), B operand
+// (column lane % 16, k lane / 16), result element e at (row lane / 16 + 4e, column lane % 16).
+constexpr int kPitch = 65;
 
-__global__ __launch_bounds__(kPotrfTX * kPotrfTY) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
+__device__ __forceinline__ v4d mma16(v4d acc, const double* X, int xr, int xc, const double* Y, int yr,
+                                     int yc, bool ytrans, int lane) {
+  // acc += X(xr.., xc..) Y^T over 16 k: Y element (col j, k) read at Y(yr + j, yc + k), or at
+  // Y(yr + k, yc + j) when ytrans
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 16; ks += 4) {
+    const double a = X[(xr + li) * kPitch + xc + ks + lk];
+    const double b = ytrans ? Y[(yr + ks + lk) * kPitch + yc + li] : Y[(yr + li) * kPitch + yc + ks + lk];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
-  __shared__ double tile[64][65];
-  __shared__ double pan[2][64][4];
-  __shared__ double wrows[2][4][64];
+  __shared__ double A[64 * kPitch];       // A(r, c) at r * kPitch + c
+  __shared__ double W[64 * kPitch];       // the inverse, same layout
   const PotrfTask T = tasks[blockIdx.x];
-  const int tid = threadIdx.x;
-  constexpr int TX = kPotrfTX, TY = kPotrfTY, NX = 64 / TX, NY = 64 / TY, NT = TX * TY;
-  const int tx = tid % TX, ty = tid / TX;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int nb = T.nb;
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
-#pragma unroll
-  for (int u = 0; u < 4096 / NT; ++u) {
-    const int idx = tid + NT * u, r = idx & 63, c = idx >> 6;
-    tile[r][c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld] : 0.0;
+  for (int idx = tid; idx < 4096; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    A[r * kPitch + c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld]
+                                                     : ((r == c) ? 1.0 : 0.0);
+    W[r * kPitch + c] = 0.0;
   }
-  __syncthreads();
-  double L[NY][NX], W[NY][NX];
-#pragma unroll
-  for (int a = 0; a < NY; ++a)
-#pragma unroll
-    for (int b = 0; b < NX; ++b) {
-      const int i = ty + TY * a, j = tx + TX * b;
-      L[a][b] = tile[i][j];
-      W[a][b] = (i == j && i < nb) ? 1.0 : 0.0;
-    }
   const double dscale = (T.mode >= 1) ? arena[T.scale_off] * (T.mode == 2 ? 1e-8 : 1e-14) : 0.0;
+  __syncthreads();
   bool bad = false;
-  const int nsteps = (nb + 3) >> 2;
-  for (int K = 0; K < nsteps; ++K) {
-    const int k0 = 4 * K, kbx = k0 / TX, kox = k0 % TX, kby = k0 / TY, koy = k0 % TY, buf = K & 1;
-    const int nbk = min(4, nb - k0);
-    // publish the panel columns k0..k0+3 (rows >= k0) and rows k0..k0+3 of W
-    if (tx >= kox && tx < kox + 4) {
+  for (int kb = 0; kb < 4; ++kb) {
+    const int kk = 16 * kb;
+    if (w == 0) {
+      const int j = li, g = lk;
+      double v[4], wv[4];
 #pragma unroll
-      for (int a = 0; a < NY; ++a)
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * g + e;
+        v[e] = (i >= j) ? A[(kk + i) * kPitch + kk + j] : 0.0;
+        wv[e] = (i == j) ? 1.0 : 0.0;
+      }
 #pragma unroll
-        for (int b = 0; b < NX; ++b)
-          if (b == kbx) {
-            const int i = ty + TY * a;
-            if (i >= k0) pan[buf][i][tx - kox] = L[a][b];
-          }
+      for (int c = 0; c < 16; ++c) {
+        const int gc = c >> 2, ec = c & 3;
+        double d = __shfl(v[ec], gc * 16 + c, 64);
+        bool dk = false;
+        if (kk + c >= nb) {
+          d = 1.0;                                   // past the block edge: identity
+        } else if (T.mode == 0) {
+          if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
+        } else if (!(d > dscale) || !isfinite(d)) {
+          dk = true;
+          d = 1.0;
+        }
+        const double rp = rsqrt_f64(d);
+        const double piv = d * rp;
+        // column c of L for this lane's rows, and L(j, c) for this lane's column
+        double lic[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double x = __shfl(v[e], g * 16 + c, 64);
+          const int i = 4 * g + e;
+          lic[e] = (i > c) ? (dk ? 0.0 : x * rp) : (i == c ? piv : 0.0);
+        }
+        double y[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[e] = __shfl(v[e], (j >> 2) * 16 + c, 64);
+        const double yj = ((j & 3) == 0) ? y[0] : ((j & 3) == 1) ? y[1] : ((j & 3) == 2) ? y[2] : y[3];
+        const double ljc = (j > c && !dk) ? yj * rp : 0.0;
+        // row c of the inverse, scaled by 1 / pivot (zero for a dropped column)
+        const double wcj = __shfl(wv[ec], gc * 16 + j, 64) * (dk ? 0.0 : rp);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = 4 * g + e;
+          if (j == c) v[e] = lic[e];
+          else if (i > c && j > c) v[e] -= lic[e] * ljc;
+          if (i == c) wv[e] = wcj;
+          else if (i > c) wv[e] -= lic[e] * wcj;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * g + e;
+        if (i >= j) A[(kk + i) * kPitch + kk + j] = v[e];
+        W[(kk + i) * kPitch + kk + j] = wv[e];
+      }
     }
-    if (ty >= koy && ty < koy + 4) {
+    __syncthreads();
+    if (kb == 3) break;
+    // rows below: P = A_below D^{-T} (block row rb by wave rb - kb - 1)
+    {
+      const int rb = kb + 1 + w;
+      if (rb < 4) {
+        v4d acc = {0, 0, 0, 0};
+        acc = mma16(acc, A, 16 * rb, kk, W, kk, kk, false, lane);
 #pragma unroll
-      for (int a = 0; a < NY; ++a)
-        if (a == kby) {
+        for (int e = 0; e < 4; ++e) A[(16 * rb + lk + 4 * e) * kPitch + kk + li] = acc[e];
+      }
+    }
+    __syncthreads();
+    // trailing lower blocks (ib, jb), kb < jb <= ib < 4
+    {
+      int t = 0;
+      for (int ib = kb + 1; ib < 4; ++ib)
+        for (int jb = kb + 1; jb <= ib; ++jb, ++t) {
+          if ((t & 3) != w) continue;
+          v4d acc = {0, 0, 0, 0};
+          acc = mma16(acc, A, 16 * ib, kk, A, 16 * jb, kk, false, lane);
 #pragma unroll
-          for (int b = 0; b < NX; ++b) wrows[buf][ty - koy][tx + TX * b] = W[a][b];
+          for (int e = 0; e < 4; ++e) A[(16 * ib + lk + 4 * e) * kPitch + 16 * jb + li] -= acc[e];
         }
     }
     __syncthreads();
-    // 4 x 4 diagonal block: Cholesky factor Ld and inverse Ldi (every thread)
-    double A4[4][4], Ld[4][4], Ldi[4][4];
+  }
+  // off-diagonal blocks of the inverse, block row by block row (block jb by wave jb)
+  for (int ib = 1; ib < 4; ++ib) {
+    if (w < ib) {
+      const int jb = w;
+      v4d t = {0, 0, 0, 0};
+      for (int mb = jb; mb < ib; ++mb) t = mma16(t, A, 16 * ib, 16 * mb, W, 16 * mb, 16 * jb, true, lane);
+      // W_ij = -D_i^{-1} T: the B operand (column li, k = 4e + lk) is t[e] of this lane
+      v4d acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        A4[r][c] = (c <= r) ? pan[buf][k0 + r][c] : 0.0;
-        Ld[r][c] = 0.0;
-        Ldi[r][c] = 0.0;
+      for (int e = 0; e < 4; ++e) {
+        const double a = W[(16 * ib + li) * kPitch + 16 * ib + 4 * e + lk];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, t[e], acc, 0, 0, 0);
       }
-    bool drop[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double d = A4[c][c];
-      bool dk = false;
-      if (c >= nbk) {
-        d = 1.0;                                   // past the block edge: identity
-      } else if (T.mode == 0) {
-        if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
-      } else if (!(d > dscale) || !isfinite(d)) {
-        dk = true;
-        d = 1.0;
-      }
-      drop[c] = dk;
-      const double rp = rsqrt_f64(d);
-      const double piv = d * rp;
-      Ld[c][c] = piv;
-      Ldi[c][c] = dk ? 0.0 : rp;
-#pragma unroll
-      for (int r = c + 1; r < 4; ++r) Ld[r][c] = dk ? 0.0 : A4[r][c] * rp;
-#pragma unroll
-      for (int r = c + 1; r < 4; ++r)
-#pragma unroll
-        for (int q = c + 1; q <= r; ++q) A4[r][q] -= Ld[r][c] * Ld[q][c];
+      for (int e = 0; e < 4; ++e) W[(16 * ib + lk + 4 * e) * kPitch + 16 * jb + li] = -acc[e];
     }
-    // Ldi (rows and columns of dropped pivots stay zero): forward substitution
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int r = c + 1; r < 4; ++r) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = c; m < r; ++m) acc += Ld[r][m] * Ldi[m][c];
-        Ldi[r][c] = -acc * Ldi[r][r];                 // Ldi[r][r] = 1 / Ld[r][r], 0 if dropped
-      }
-    // l vectors of this thread's columns (j > k0 + 3) and new rows k0..k0+3 of W for
-    // its columns; the row vectors l_i are formed one row at a time below
-    double lj[NX][4], wn[NX][4];
-#pragma unroll
-    for (int b = 0; b < NX; ++b) {
-      const int j = tx + TX * b;
-      double pv[4], wb[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        pv[c] = (j > k0 + 3) ? pan[buf][j][c] : 0.0;
-        wb[c] = wrows[buf][c][j];
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double x = 0.0, y = 0.0;
-#pragma unroll
-        for (int m = 0; m <= c; ++m) {
-          x += Ldi[c][m] * pv[m];
-          y += Ldi[c][m] * wb[m];
-        }
-        lj[b][c] = x;
-        wn[b][c] = y;
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < NY; ++a) {
-      const int i = ty + TY * a;
-      double li[4];
-      {
-        double pv[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) pv[c] = (i > k0 + 3) ? pan[buf][i][c] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          double x = 0.0;
-#pragma unroll
-          for (int m = 0; m <= c; ++m) x += Ldi[c][m] * pv[m];
-          li[c] = x;
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < NX; ++b) {
-        const int j = tx + TX * b;
-        if (b == kbx && tx >= kox && tx < kox + 4) {        // the panel columns
-          const int cc = tx - kox;
-          if (i > k0 + 3) {
-            L[a][b] = (cc == 0) ? li[0] : (cc == 1) ? li[1] : (cc == 2) ? li[2] : li[3];
-          } else if (i >= k0 && i - k0 >= cc) {
-            const int rr = i - k0;
-            double v = 0.0;
-#pragma unroll
-            for (int r2 = 0; r2 < 4; ++r2)
-#pragma unroll
-              for (int c2 = 0; c2 <= r2; ++c2)
-                if (r2 == rr && c2 == cc) v = Ld[r2][c2];
-            L[a][b] = v;
-          }
-        } else if (i > k0 + 3 && j > k0 + 3) {
-          L[a][b] -= li[0] * lj[b][0] + li[1] * lj[b][1] + li[2] * lj[b][2] + li[3] * lj[b][3];
-        }
-        if (a == kby && ty >= koy && ty < koy + 4) {        // rows k0..k0+3 of W
-          const int rr = ty - koy;
-          W[a][b] = (rr == 0) ? wn[b][0] : (rr == 1) ? wn[b][1] : (rr == 2) ? wn[b][2] : wn[b][3];
-        } else if (i > k0 + 3) {
-          W[a][b] -= li[0] * wn[b][0] + li[1] * wn[b][1] + li[2] * wn[b][2] + li[3] * wn[b][3];
-        }
-      }
-    }
+    __syncthreads();
   }
   if (bad && tid == 0) atomicMin(&status[0], T.sn);
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < NY; ++a)
-#pragma unroll
-    for (int b = 0; b < NX; ++b) tile[ty + TY * a][tx + TX * b] = L[a][b];
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < 4096 / NT; ++u) {
-    const int idx = tid + NT * u, r = idx & 63, c = idx >> 6;
-    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = tile[r][c];
+  for (int idx = tid; idx < 4096; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = A[r * kPitch + c];
   }
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < NY; ++a)
-#pragma unroll
-    for (int b = 0; b < NX; ++b) tile[ty + TY * a][tx + TX * b] = W[a][b];
-  __syncthreads();
   double* inv = arena + T.inv;
-#pragma unroll
-  for (int u = 0; u < 4096 / NT; ++u) {
-    const int idx = tid + NT * u, r = idx & 63, c = idx >> 6;
-    inv[r + 64 * c] = tile[r][c];
+  for (int idx = tid; idx < 4096; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    inv[r + 64 * c] = W[r * kPitch + c];
   }
 }
 
@@ -579,7 +536,7 @@ void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* aren
   if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, s, slot, n, v, arena);
 }
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(kPotrfTX * kPotrfTY), 0, s, t, arena, status);
+  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(256), 0, s, t, arena, status);
 }
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
                    hipStream_t s) {
