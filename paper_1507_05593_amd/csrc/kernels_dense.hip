@@ -59,6 +59,14 @@ __global__ void k_scatter_const(const int64_t* __restrict__ slot, int64_t n, dou
 
 // 1 / sqrt(d) for a positive finite d: the hardware estimate refined by two Newton
 // steps r <- r (3 - d r^2) / 2 (each squares the relative error), to FP64 rounding.
+// Lane l's value of x (l uniform), through two 32-bit readlanes.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double rsqrt_f64(double d) {
   double r = __builtin_amdgcn_rsq(d);
   r = r * (1.5 - 0.5 * d * r * r);
@@ -77,8 +85,8 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 //
 // Blocked right-looking elimination over four 16-column block steps, the tile in LDS:
 //   1. wave 0 factors the 16 x 16 diagonal block and forms its inverse in registers
-//      (lane (j, g) holds column j, rows 4g..4g+3; one column at a time, the column
-//      and the rows it needs exchanged by lane shuffles);
+//      (lane j holds column j of the symmetric block and of the inverse; one column at
+//      a time, the pivot and the column broadcast from their lane by readlane);
 //   2. the rows below: P = A_below D^{-T}, one 16-row block per wave (FP64 MFMA);
 //   3. the trailing lower blocks: A -= P P^T, blocks dealt round robin to the waves.
 // The inverse's off-diagonal blocks then follow block row by block row:
@@ -124,18 +132,20 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   for (int kb = 0; kb < 4; ++kb) {
     const int kk = 16 * kb;
     if (w == 0) {
-      const int j = li, g = lk;
-      double v[4], wv[4];
+      // lane j (lanes >= 16 repeat lanes 0..15) holds column j of the symmetric block
+      // (v[i] = A(i, j) for every i, read from the lower triangle) and column j of its
+      // inverse; the pivot and column c come from lane c by readlane, and this lane's own
+      // v[c] is A(j, c) by symmetry
+      const int j = li;
+      double v[16], wv[16];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = 4 * g + e;
-        v[e] = (i >= j) ? A[(kk + i) * kPitch + kk + j] : 0.0;
-        wv[e] = (i == j) ? 1.0 : 0.0;
+      for (int i = 0; i < 16; ++i) {
+        v[i] = A[(kk + (i > j ? i : j)) * kPitch + kk + (i > j ? j : i)];
+        wv[i] = (i == j) ? 1.0 : 0.0;
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        const int gc = c >> 2, ec = c & 3;
-        double d = __shfl(v[ec], gc * 16 + c, 64);
+        double d = readlane_f64(v[c], c);
         bool dk = false;
         if (kk + c >= nb) {
           d = 1.0;                                   // past the block edge: identity
@@ -147,35 +157,30 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
         }
         const double rp = rsqrt_f64(d);
         const double piv = d * rp;
-        // column c of L for this lane's rows, and L(j, c) for this lane's column
-        double lic[4];
+        const double sc = dk ? 0.0 : rp;
+        double s[16];                                // L(i, c), i > c
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double x = __shfl(v[e], g * 16 + c, 64);
-          const int i = 4 * g + e;
-          lic[e] = (i > c) ? (dk ? 0.0 : x * rp) : (i == c ? piv : 0.0);
+        for (int i = c + 1; i < 16; ++i) s[i] = readlane_f64(v[i], c) * sc;
+        const double ljc = (j > c) ? v[c] * sc : 0.0;
+        const double wcj = wv[c] * sc;               // row c of the inverse, scaled
+        wv[c] = wcj;
+#pragma unroll
+        for (int i = c + 1; i < 16; ++i) {
+          v[i] -= s[i] * ljc;
+          wv[i] -= s[i] * wcj;
         }
-        double y[4];
+        if (j == c) {
+          v[c] = piv;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) y[e] = __shfl(v[e], (j >> 2) * 16 + c, 64);
-        const double yj = ((j & 3) == 0) ? y[0] : ((j & 3) == 1) ? y[1] : ((j & 3) == 2) ? y[2] : y[3];
-        const double ljc = (j > c && !dk) ? yj * rp : 0.0;
-        // row c of the inverse, scaled by 1 / pivot (zero for a dropped column)
-        const double wcj = __shfl(wv[ec], gc * 16 + j, 64) * (dk ? 0.0 : rp);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int i = 4 * g + e;
-          if (j == c) v[e] = lic[e];
-          else if (i > c && j > c) v[e] -= lic[e] * ljc;
-          if (i == c) wv[e] = wcj;
-          else if (i > c) wv[e] -= lic[e] * wcj;
+          for (int i = c + 1; i < 16; ++i) v[i] = s[i];
         }
       }
+      if (lane < 16) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = 4 * g + e;
-        if (i >= j) A[(kk + i) * kPitch + kk + j] = v[e];
-        W[(kk + i) * kPitch + kk + j] = wv[e];
+        for (int i = 0; i < 16; ++i) {
+          if (i >= j) A[(kk + i) * kPitch + kk + j] = v[i];
+          W[(kk + i) * kPitch + kk + j] = wv[i];
+        }
       }
     }
     __syncthreads();
