@@ -118,18 +118,19 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nb = T.nb;
+  const int nbk = (nb + 15) >> 4, nbb16 = 16 * nbk;   // 16-column blocks that hold the block
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
   for (int idx = tid; idx < 4096; idx += 256) {
     const int r = idx & 63, c = idx >> 6;
     A[r * kPitch + c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld]
                                                      : ((r == c) ? 1.0 : 0.0);
-    W[r * kPitch + c] = 0.0;
+    W[r * kPitch + c] = (r == c && r >= nbb16) ? 1.0 : 0.0;   // blocks past nb: identity
   }
   const double dscale = (T.mode >= 1) ? arena[T.scale_off] * (T.mode == 2 ? 1e-8 : 1e-14) : 0.0;
   __syncthreads();
   bool bad = false;
-  for (int kb = 0; kb < 4; ++kb) {
+  for (int kb = 0; kb < nbk; ++kb) {
     const int kk = 16 * kb;
     if (w == 0) {
       // lane j (lanes >= 16 repeat lanes 0..15) holds column j of the symmetric block
@@ -158,21 +159,15 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
         const double rp = rsqrt_f64(d);
         const double piv = d * rp;
         const double sc = dk ? 0.0 : rp;
-        double s[16];                                // L(i, c), i > c
-#pragma unroll
-        for (int i = c + 1; i < 16; ++i) s[i] = readlane_f64(v[i], c) * sc;
         const double ljc = (j > c) ? v[c] * sc : 0.0;
         const double wcj = wv[c] * sc;               // row c of the inverse, scaled
         wv[c] = wcj;
+        if (j == c) v[c] = piv;
 #pragma unroll
         for (int i = c + 1; i < 16; ++i) {
-          v[i] -= s[i] * ljc;
-          wv[i] -= s[i] * wcj;
-        }
-        if (j == c) {
-          v[c] = piv;
-#pragma unroll
-          for (int i = c + 1; i < 16; ++i) v[i] = s[i];
+          const double si = readlane_f64(v[i], c) * sc;   // L(i, c)
+          v[i] = (j == c) ? si : v[i] - si * ljc;
+          wv[i] -= si * wcj;
         }
       }
       if (lane < 16) {
@@ -184,11 +179,11 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
       }
     }
     __syncthreads();
-    if (kb == 3) break;
+    if (kb == nbk - 1) break;
     // rows below: P = A_below D^{-T} (block row rb by wave rb - kb - 1)
     {
       const int rb = kb + 1 + w;
-      if (rb < 4) {
+      if (rb < nbk) {
         v4d acc = {0, 0, 0, 0};
         acc = mma16(acc, A, 16 * rb, kk, W, kk, kk, false, lane);
 #pragma unroll
@@ -199,7 +194,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
     // trailing lower blocks (ib, jb), kb < jb <= ib < 4
     {
       int t = 0;
-      for (int ib = kb + 1; ib < 4; ++ib)
+      for (int ib = kb + 1; ib < nbk; ++ib)
         for (int jb = kb + 1; jb <= ib; ++jb, ++t) {
           if ((t & 3) != w) continue;
           v4d acc = {0, 0, 0, 0};
@@ -211,7 +206,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
     __syncthreads();
   }
   // off-diagonal blocks of the inverse, block row by block row (block jb by wave jb)
-  for (int ib = 1; ib < 4; ++ib) {
+  for (int ib = 1; ib < nbk; ++ib) {
     if (w < ib) {
       const int jb = w;
       v4d t = {0, 0, 0, 0};
