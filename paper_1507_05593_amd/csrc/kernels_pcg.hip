@@ -150,8 +150,10 @@ __global__ void k_gather_rows(const int64_t* __restrict__ tasks, const int64_t* 
   for (int64_t t = threadIdx.x; t < n; t += 256) dst[b + t] = src[idx[b + t]];
 }
 
-// One wave per output column (4 columns per wave, 16 per workgroup): lanes stride the
-// rows (unrolled so several loads are in flight), then a wave reduction.
+// Column dots, 16 columns per workgroup: wave w takes columns col0 + 4w .. col0 + 4w + 3,
+// one per 16-lane group, the group's lanes striding the rows (one 128-byte line per
+// group and load, unrolled so several loads are in flight); then a fixed butterfly
+// within each group.  Short columns (the many small supernodes) keep most lanes busy.
 __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ tasks,
                                                 double* __restrict__ arena,
                                                 const int64_t* __restrict__ gidx,
@@ -159,28 +161,27 @@ __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ t
                                                 double* __restrict__ part) {
   const ColDotTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
   const int ncols = T.ncols >= 0 ? T.ncols : ilim[-1 - T.ncols];
   const double* in = arena + T.in;
-  for (int u = 0; u < 4; ++u) {
-    const int col = T.col0 + w * 4 + u;
-    double acc = 0.0;
-    if (col < ncols) {
-      const int rows = min(T.tri ? col + 1 : T.rows, T.r1);
-      const double* X = arena + T.x + (int64_t)col * T.ldx;
-      if (T.idx >= 0) {
-        const int64_t* ix = gidx + T.idx;
+  const int col = T.col0 + w * 4 + g;
+  double acc = 0.0;
+  if (col < ncols) {
+    const int rows = min(T.tri ? col + 1 : T.rows, T.r1);
+    const double* X = arena + T.x + (int64_t)col * T.ldx;
+    if (T.idx >= 0) {
+      const int64_t* ix = gidx + T.idx;
 #pragma unroll 8
-        for (int t = T.r0 + lane; t < rows; t += 64) acc += X[t] * in[ix[t]];
-      } else {
+      for (int t = T.r0 + r; t < rows; t += 16) acc += X[t] * in[ix[t]];
+    } else {
 #pragma unroll 8
-        for (int t = T.r0 + lane; t < rows; t += 64) acc += X[t] * in[t];
-      }
-      acc = wave_sum(acc);
+      for (int t = T.r0 + r; t < rows; t += 16) acc += X[t] * in[t];
     }
-    if (lane == 0) {
-      if (T.slot >= 0) part[(int64_t)T.slot * 64 + (col - T.col0)] = acc;
-      else if (col < ncols) arena[T.out + col] = acc;
-    }
+  }
+  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (r == 0) {
+    if (T.slot >= 0) part[(int64_t)T.slot * 64 + (col - T.col0)] = acc;
+    else if (col < ncols) arena[T.out + col] = acc;
   }
 }
 
