@@ -34,6 +34,7 @@ namespace rsc {
 
 static const Error kOk{RSC_OK, ""};
 static constexpr int kNewtonSchulzSteps = 24;
+static constexpr int32_t kOuter = 256;   // outer block width of the panel factorisation
 
 int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p) {
   const int32_t k = std::min(r, c);
@@ -440,23 +441,32 @@ struct Builder {
         fl += std::pow((double)t.nb, 3) / 3.0;
       }
       cmd(kCmdPotrf, RSC_K_POTRF, p0, (int64_t)P.potrf.size() - p0, fl);
-      // rows below the diagonal block times its inverse, then the trailing update;
+      // rows below the diagonal block times its inverse, then the trailing update in two
+      // levels: each 64-column step updates the columns of its kOuter-wide block, and the
+      // block's last step adds the whole block (K = kOuter) to the columns right of it,
+      // so the wide trailing matrix is read and written once per kOuter columns;
       // rows inside [lp_lo, lp_hi) go to the low-precision launch
-      for (int phase = 0; phase < 2; ++phase) {
+      const int32_t dend = (d0 / kOuter + 1) * kOuter;   // end of this step's outer block
+      for (int phase = 0; phase < 3; ++phase) {
+        if (phase == 2 && d0 + kTile != dend) continue;
         std::vector<GemmTask> hi_t, lo_t, tl_t;
         double fh = 0, flo = 0, ftl = 0;
         for (auto& p : pan) {
           if (p.n <= d0) continue;
           const int32_t nb = std::min(kTile, p.n - d0);
-          if (phase == 1 && p.n <= d0 + nb) continue;
-          const int32_t R0 = d0 + nb;
+          if (phase >= 1 && p.n <= d0 + nb) continue;
+          if (phase == 1 && d0 + nb >= dend) continue;      // no columns left in the block
+          const int32_t R0 = (phase == 2) ? dend : d0 + nb;
           const int32_t R1 = p.n + p.m_below + (p.ident ? std::min(p.n, d0 + nb) : 0);
           const int64_t colb = p.off + (int64_t)d0 * p.ld;
+          const int64_t colo = p.off + (int64_t)(dend - kOuter) * p.ld;
           GemmTask t = (phase == 0)
               ? gt(colb, 1, p.ld, p.dinv + (int64_t)(d0 / kTile) * 4096, 1, kTile, colb, p.ld, R1, nb, nb, 1.0, 0.0)
-              : gt(colb, 1, p.ld, colb, 1, p.ld, p.off, p.ld, R1, p.n, nb, -1.0, 1.0);
-          const int32_t jb = (phase == 0) ? 0 : d0 + nb;
-          const bool lower = (phase == 1);
+              : (phase == 1)
+              ? gt(colb, 1, p.ld, colb, 1, p.ld, p.off, p.ld, R1, std::min(p.n, dend), nb, -1.0, 1.0)
+              : gt(colo, 1, p.ld, colo, 1, p.ld, p.off, p.ld, R1, p.n, kOuter, -1.0, 1.0);
+          const int32_t jb = (phase == 0) ? 0 : (phase == 1) ? d0 + nb : dend;
+          const bool lower = (phase >= 1);
           const bool use_lp = ((lp_update || p.skip_mid) && p.lp_hi > p.lp_lo) || (p.tail_lp && lp_tri);
           // segments [R0, lp_lo), [lp_lo, lp_hi), [lp_hi, R1)
           int32_t cuts[4] = {R0, use_lp ? std::max(R0, p.lp_lo) : R1, use_lp ? std::max(R0, p.lp_hi) : R1, R1};
