@@ -269,13 +269,29 @@ __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1)
     }
     __syncthreads();
     const int ncol = min(64, n - T.j0 - s0);
+    // symmetric C: elements on or below the diagonal directly, their mirror images below
+    const int dj = T.j0 + s0 - T.i0;         // global column - row = j - i + dj
     for (int idx = threadIdx.x; idx < TM * 64; idx += Ly::NT) {
       const int i = idx % TM, j = idx / TM;
-      if (i < mrows && j < ncol) {
+      if (i < mrows && j < ncol && !(T.sym && j + dj > i)) {
         const int64_t o = (T.i0 + i) + (int64_t)(T.j0 + s0 + j) * T.ldc;
         const double v = T.alpha * (double)slab[j * kSlabPitch<TM> + i];
         if (T.beta == 0.0) C[o] = v;
         else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + o] : C[o]);
+      }
+    }
+    if (T.sym) {
+      // the transpose, rows of C along consecutive threads; D is symmetric too
+      __syncthreads();                     // the direct writes (which D may not alias) are done
+      for (int idx = threadIdx.x; idx < TM * 64; idx += Ly::NT) {
+        const int j = idx % 64, i = idx / 64;
+        if (i < mrows && j < ncol && j + dj < i) {
+          const int64_t o = (T.j0 + s0 + j) + (int64_t)(T.i0 + i) * T.ldc;
+          const int64_t od = (T.i0 + i) + (int64_t)(T.j0 + s0 + j) * T.ldc;
+          const double v = T.alpha * (double)slab[j * kSlabPitch<TM> + i];
+          if (T.beta == 0.0) C[o] = v;
+          else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + od] : C[od]);
+        }
       }
     }
   }

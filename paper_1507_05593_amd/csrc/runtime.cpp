@@ -419,7 +419,17 @@ struct Builder {
     GemmTask t{};
     t.a = a; t.ais = ais; t.aks = aks; t.b = b; t.bjs = bjs; t.bks = bks; t.c = c; t.ldc = ldc;
     t.m = m; t.n = n; t.k = k; t.alpha = alpha; t.beta = beta; t.nlim = -1; t.klim = -1; t.d = -1;
+    t.sym = 0;
     return t;
+  }
+
+  // Symmetric product: the tiles on or below the diagonal, each written with its mirror
+  // image.  The beta term must come from a separate D (the mirror writes would overwrite
+  // C before it is read); otherwise the full product is emitted.
+  double sym_tiles(GemmTask t) {
+    if (t.beta != 0.0 && t.d < 0) return tiles(t, 0, 0, false);
+    t.sym = 1;
+    return tiles(t, 0, 0, true);
   }
 
   // Blocked right-looking factorisation of tall panels [diag n x n; m_below rows;
@@ -740,7 +750,7 @@ struct Builder {
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t r = S.r(j), l = C.ell;
-      fl += tiles(gt(C.V, r, 1, C.V, r, 1, C.G, l, l, l, r, 1.0, 0.0), 0, 0, false);
+      fl += sym_tiles(gt(C.V, r, 1, C.V, r, 1, C.G, l, l, l, r, 1.0, 0.0));
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     // 7. spectral projector onto lambda > tol^2 lambda_max (see the truncation kernels)
@@ -764,7 +774,7 @@ struct Builder {
         const int64_t src = a_to_b ? C.Sa : C.Sb, dst = a_to_b ? C.Sb : C.Sa;
         GemmTask t = gt(src, 1, l, src, 1, l, dst, l, l, l, l, alpha, beta);
         (void)dsel;
-        f += tiles(t, 0, 0, false);
+        f += sym_tiles(t);
       }
       // FP64: (G / tr G)^32 would underflow FP32 when lambda_max is a small share of tr G
       cmd(kCmdGemm, RSC_K_EIG, gg, (int64_t)P.gemm.size() - gg, f);
@@ -785,7 +795,7 @@ struct Builder {
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t l = C.ell;
-      fl += tiles(gt(C.Mpan + l, 1, 2 * l, C.Mpan + l, 1, 2 * l, C.Sb, l, l, l, l, 1.0, 0.0), 0, 0, false);
+      fl += sym_tiles(gt(C.Mpan + l, 1, 2 * l, C.Mpan + l, 1, 2 * l, C.Sb, l, l, l, l, 1.0, 0.0));
     }
     cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
     cmd(kCmdTruncX0, RSC_K_EIG, t0, nt, 0);            // sa = I - 2 theta H
@@ -800,7 +810,7 @@ struct Builder {
         const CompSlot& C = h.comp[j];
         const int32_t l = C.ell;
         const int64_t X = even ? C.Sa : C.Sb;
-        fl += tiles(gt(X, 1, l, X, l, 1, C.Om2, l, l, l, l, 1.0, 0.0), 0, 0, false);
+        fl += sym_tiles(gt(X, 1, l, X, l, 1, C.Om2, l, l, l, l, 1.0, 0.0));
       }
       cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
       g0 = (int64_t)P.gemm.size(); fl = 0;
@@ -810,7 +820,7 @@ struct Builder {
         const int64_t X = even ? C.Sa : C.Sb, Xn = even ? C.Sb : C.Sa;
         GemmTask t = gt(X, 1, l, C.Om2, l, 1, Xn, l, l, l, l, -0.5, 1.5);
         t.d = X;
-        fl += tiles(t, 0, 0, false);
+        fl += sym_tiles(t);
       }
       cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
     }

@@ -22,6 +22,9 @@ struct GemmTask {
   int32_t m, n, k;
   int32_t i0, j0;
   int32_t nlim, klim;
+  int32_t sym;                 // 1: C is symmetric; tiles on or below the diagonal only, each
+                               // written with its transpose (diagonal tiles: lower half mirrored)
+  int32_t pad_;
   double alpha, beta;
 };
 
