@@ -68,7 +68,10 @@ namespace rsc {
 // LDS-staged MFMA kernels; mode 0 = FP64, 1 = FP32 operands, 2 = BF16 hi/lo split, 3 = BF16
 // tile: output tile edge, 64 or 128 (tasks must have been cut to that edge)
 void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
-                        const int32_t* ilim, hipStream_t s);
+                        const int32_t* ilim, double* part, hipStream_t s);
+// Adds the K-slice partial tiles of split products and stores C (one workgroup per tile).
+void launch_gemm_reduce(int tile, const GemmTask* t, int n, double* arena, const int32_t* ilim,
+                        const double* part, hipStream_t s);
 // Schur update: one workgroup per target tile (entries in tile order, es = first entry of
 // at most 32 x 32); xbase = operand base (the arena in FP64 mode, else the compact copy).
 void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,

@@ -227,7 +227,8 @@ constexpr size_t kGemmSmem = sizeof(Stage<MODE, TM>) > 64 * kSlabPitch<TM> * siz
 template <int MODE, int TM>
 __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1) void k_gemm_staged(const GemmTask* __restrict__ tasks,
                                                                double* __restrict__ arena,
-                                                               const int32_t* __restrict__ ilim) {
+                                                               const int32_t* __restrict__ ilim,
+                                                               double* __restrict__ part) {
   using Ly = Layout<TM>;
   using AE = typename AccElem<MODE>::T;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kGemmSmem<MODE, TM>];
@@ -244,9 +245,15 @@ __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1)
 #pragma unroll
     for (int y = 0; y < Ly::BC; ++y)
       for (int e = 0; e < 4; ++e) acc[x][y][e] = 0;
-  const double* A = arena + T.a + (int64_t)T.i0 * T.ais;
-  const double* B = arena + T.b + (int64_t)T.j0 * T.bjs;
-  tile_product<MODE, TM>(st, acc, A, T.ais, T.aks, T.m - T.i0, B, T.bjs, T.bks, n - T.j0, K);
+  int kb = 0, ke = K;
+  if (T.kz > 1) {                          // K slice ks of kz (chunk aligned)
+    const int per = ((K + T.kz - 1) / T.kz + KC - 1) / KC * KC;
+    kb = min(K, T.ks * per);
+    ke = min(K, kb + per);
+  }
+  const double* A = arena + T.a + (int64_t)T.i0 * T.ais + (int64_t)kb * T.aks;
+  const double* B = arena + T.b + (int64_t)T.j0 * T.bjs + (int64_t)kb * T.bks;
+  tile_product<MODE, TM>(st, acc, A, T.ais, T.aks, T.m - T.i0, B, T.bjs, T.bks, n - T.j0, ke - kb);
   // C = alpha P (+ beta D), 64 columns at a time through LDS so that C and D are read
   // and written one contiguous column (up to TM rows) per wave instruction
   AE* slab = reinterpret_cast<AE*>(smem);
@@ -268,6 +275,13 @@ __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1)
           }
     }
     __syncthreads();
+    if (T.kz > 1) {                        // a K slice: the raw partial tile (no alpha, beta)
+      for (int idx = threadIdx.x; idx < TM * 64; idx += Ly::NT) {
+        const int i = idx % TM, j = idx / TM;
+        part[T.part + i + (int64_t)(s0 + j) * TM] = (double)slab[j * kSlabPitch<TM> + i];
+      }
+      continue;
+    }
     const int ncol = min(64, n - T.j0 - s0);
     // symmetric C: elements on or below the diagonal directly, their mirror images below
     const int dj = T.j0 + s0 - T.i0;         // global column - row = j - i + dj
@@ -292,6 +306,55 @@ __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1)
           if (T.beta == 0.0) C[o] = v;
           else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + od] : C[od]);
         }
+      }
+    }
+  }
+}
+
+// Sum of the kz (<= 8) K-slice partial tiles of one output tile, then the same store as a
+// whole-K product: C = alpha S (+ beta D), mirrored for symmetric C.  1024 threads, four
+// elements each; every element's kz partials are loaded together and added in slice
+// order (the missing slices as exact zeros).
+template <int TM>
+__global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmTask* __restrict__ tasks,
+                                                      double* __restrict__ arena,
+                                                      const int32_t* __restrict__ ilim,
+                                                      const double* __restrict__ part) {
+  const GemmTask T = tasks[blockIdx.x];
+  const int n = T.nlim >= 0 ? min(T.n, ilim[T.nlim]) : T.n;
+  if (T.j0 >= n) return;
+  double* C = arena + T.c;
+  const int mrows = min(TM, T.m - T.i0), ncol = min(TM, n - T.j0);
+  const int dj = T.j0 - T.i0;
+  const int64_t tt = (int64_t)TM * TM;
+  auto sum = [&](int i, int j) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = q < T.kz ? part[T.part + q * tt + i + (int64_t)j * TM] : 0.0;
+    double acc = v[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) acc += v[q];
+    return acc;
+  };
+  for (int idx = threadIdx.x; idx < TM * TM; idx += 1024) {
+    const int i = idx % TM, j = idx / TM;
+    if (i < mrows && j < ncol && !(T.sym && j + dj > i)) {
+      const int64_t o = (T.i0 + i) + (int64_t)(T.j0 + j) * T.ldc;
+      const double v = T.alpha * sum(i, j);
+      if (T.beta == 0.0) C[o] = v;
+      else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + o] : C[o]);
+    }
+  }
+  if (T.sym) {
+    __syncthreads();                       // the direct writes are done
+    for (int idx = threadIdx.x; idx < TM * TM; idx += 1024) {
+      const int j = idx % TM, i = idx / TM;
+      if (i < mrows && j < ncol && j + dj < i) {
+        const int64_t o = (T.j0 + j) + (int64_t)(T.i0 + i) * T.ldc;
+        const int64_t od = (T.i0 + i) + (int64_t)(T.j0 + j) * T.ldc;
+        const double v = T.alpha * sum(i, j);
+        if (T.beta == 0.0) C[o] = v;
+        else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + od] : C[od]);
       }
     }
   }
@@ -541,20 +604,27 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
 
 template <int TM>
 static void launch_gemm_tm(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
-                           hipStream_t s) {
+                           double* part, hipStream_t s) {
   switch (mode) {
-    case sF64: hipLaunchKernelGGL((k_gemm_staged<sF64, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
-    case sF32: hipLaunchKernelGGL((k_gemm_staged<sF32, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
-    case sBF16x3: hipLaunchKernelGGL((k_gemm_staged<sBF16x3, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
-    default: hipLaunchKernelGGL((k_gemm_staged<sBF16, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim); break;
+    case sF64: hipLaunchKernelGGL((k_gemm_staged<sF64, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
+    case sF32: hipLaunchKernelGGL((k_gemm_staged<sF32, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
+    case sBF16x3: hipLaunchKernelGGL((k_gemm_staged<sBF16x3, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
+    default: hipLaunchKernelGGL((k_gemm_staged<sBF16, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
   }
 }
 
 void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
-                        const int32_t* ilim, hipStream_t s) {
+                        const int32_t* ilim, double* part, hipStream_t s) {
   if (n <= 0) return;
-  if (tile == 128) launch_gemm_tm<128>(mode, t, n, arena, ilim, s);
-  else launch_gemm_tm<64>(mode, t, n, arena, ilim, s);
+  if (tile == 128) launch_gemm_tm<128>(mode, t, n, arena, ilim, part, s);
+  else launch_gemm_tm<64>(mode, t, n, arena, ilim, part, s);
+}
+
+void launch_gemm_reduce(int tile, const GemmTask* t, int n, double* arena, const int32_t* ilim,
+                        const double* part, hipStream_t s) {
+  if (n <= 0) return;
+  if (tile == 128) hipLaunchKernelGGL(k_gemm_reduce<128>, dim3(n), dim3(1024), 0, s, t, arena, ilim, part);
+  else hipLaunchKernelGGL(k_gemm_reduce<64>, dim3(n), dim3(1024), 0, s, t, arena, ilim, part);
 }
 
 void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,

@@ -367,21 +367,50 @@ struct Builder {
            int64_t b = 0, double v = 0) {
     if (count <= 0) return;
     int64_t alt_off = -1, alt_count = 0;
+    // split K: a 64-tile product with fewer tiles than two per compute unit and a long
+    // K gets kz slices per tile (each at least 256 of K, at most 2048 workgroups in all)
+    // whose partial tiles a reduce launch adds
+    int32_t kz = 1;
+    int64_t red_off = -1;
     if (type == kCmdGemm) {
       // the command's 64-tile tasks are the last ones pushed; with a fixed tile option
       // they are cut to it, else a 128-tile copy is kept for the tile tuner
       b = 64;
       if (off + count == (int64_t)P.gemm.size()) {
         int64_t last_col = 0;
-        for (int64_t i = off; i < off + count; ++i)
+        int32_t kmax = 0;
+        for (int64_t i = off; i < off + count; ++i) {
           if (P.gemm[i].n - P.gemm[i].j0 <= kTile) ++last_col;
+          kmax = std::max(kmax, P.gemm[i].k);
+        }
         // products mostly one 64-column tile wide (the in-place triangular solves)
         // would leave half of every 128 tile idle; launches under 16 tiles would leave
         // most of the chip idle with a quarter as many workgroups
         const bool narrow = 2 * last_col > count;
+        if (h.opt.gemm_tile != 128 && count < 512)
+          kz = (int32_t)std::min<int64_t>({8, (2048 + count - 1) / count, std::max(1, kmax / 256)});
         if (h.opt.gemm_tile == 128) {
           count = retile128(P.gemm, off);
           b = 128;
+        } else if (kz > 1) {
+          red_off = off;
+          std::vector<GemmTask> sl;
+          sl.reserve((size_t)(count * kz));
+          for (int64_t i = 0; i < count; ++i) {
+            GemmTask& t = P.gemm[off + i];
+            t.kz = kz;
+            t.part = i * kz * 4096;
+            for (int32_t q = 0; q < kz; ++q) {
+              GemmTask u = t;
+              u.ks = q;
+              u.part = t.part + (int64_t)q * 4096;
+              sl.push_back(u);
+            }
+          }
+          off = (int64_t)P.gemm.size();
+          P.gemm.insert(P.gemm.end(), sl.begin(), sl.end());
+          count *= kz;
+          P.split_size = std::max(P.split_size, count * 4096);
         } else if (h.opt.gemm_tile == 0 && !narrow && count >= 16) {
           alt_off = (int64_t)P.gemm.size();
           P.gemm.insert(P.gemm.end(), P.gemm.begin() + off, P.gemm.begin() + off + count);
@@ -396,6 +425,11 @@ struct Builder {
     if (type == kCmdGemm)
       for (int64_t i = off; i < off + count && !c.dyn; ++i) c.dyn = (P.gemm[i].nlim >= 0 || P.gemm[i].klim >= 0);
     P.cmds.push_back(c);
+    if (red_off >= 0) {
+      Cmd r = c;
+      r.type = kCmdGemmReduce; r.off = red_off; r.count = count / kz; r.flops = 0; r.dyn = false;
+      P.cmds.push_back(r);
+    }
   }
 
   // Tiles of C(i, j) for i in [ib, m), j in [jb, n); lower: skip tiles lying strictly
@@ -419,7 +453,7 @@ struct Builder {
     GemmTask t{};
     t.a = a; t.ais = ais; t.aks = aks; t.b = b; t.bjs = bjs; t.bks = bks; t.c = c; t.ldc = ldc;
     t.m = m; t.n = n; t.k = k; t.alpha = alpha; t.beta = beta; t.nlim = -1; t.klim = -1; t.d = -1;
-    t.sym = 0;
+    t.sym = 0; t.kz = 1; t.ks = 0; t.part = 0;
     return t;
   }
 
@@ -910,13 +944,13 @@ static Error tune_tiles(Handle& h, FactorPlan& P) {
   for (Cmd& c : P.cmds) {
     if (c.alt_off < 0) continue;
     const int mode = (int)c.a;
-    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, s);
+    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, nullptr, s);
     HIPCHK(hipEventRecord(ev[0], s));
-    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, s);
+    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, nullptr, s);
     HIPCHK(hipEventRecord(ev[1], s));
-    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, s);
+    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, nullptr, s);
     HIPCHK(hipEventRecord(ev[2], s));
-    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, s);
+    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, nullptr, s);
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipEventSynchronize(ev[3]));
     float t64 = 0, t128 = 0;
@@ -992,6 +1026,10 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
     HIPCHK(hipMalloc((void**)&P->d_xc.p, sizeof(double) * P->xc_size));
     P->d_xc.n = P->xc_size;
   }
+  if (P->split_size > 0) {
+    HIPCHK(hipMalloc((void**)&P->d_split.p, sizeof(double) * P->split_size));
+    P->d_split.n = P->split_size;
+  }
   if ((e = upload(P->d_potrf, P->potrf)).code) return e;
   if ((e = upload(P->d_philox, P->philox)).code) return e;
   if ((e = upload(P->d_trunc, P->trunc)).code) return e;
@@ -1026,7 +1064,12 @@ static double recount_flops(const Cmd& c, const FactorPlan& P, const std::vector
     for (int64_t i = c.off; i < c.off + c.count; ++i) {
       const GemmTask& t = P.gemm[i];
       const int32_t n = t.nlim >= 0 ? std::min(t.n, I[t.nlim]) : t.n;
-      const int32_t K = t.klim >= 0 ? std::min(t.k, I[t.klim]) : t.k;
+      int32_t K = t.klim >= 0 ? std::min(t.k, I[t.klim]) : t.k;
+      if (t.kz > 1) {                    // this task's K slice
+        const int32_t per = ((K + t.kz - 1) / t.kz + 31) / 32 * 32;
+        const int32_t kb = std::min(K, t.ks * per);
+        K = std::min(K, kb + per) - kb;
+      }
       fl += 2.0 * std::min(T, t.m - t.i0) * std::max(0, std::min(T, n - t.j0)) * (double)K;
     }
   }
@@ -1039,13 +1082,14 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
     "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
-    "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows"};
+    "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
     case kCmdGemm: return (int32_t)((b == 128 ? 25 : 0) + (a & 3));
     case kCmdUpdate: return (int32_t)(4 + (a & 3));
     case kCmdCompact: return 29;
+    case kCmdGemmReduce: return 30;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -1085,7 +1129,8 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
-    case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
+    case kCmdGemmReduce: launch_gemm_reduce((int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
     case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, 0, s); break;
     case kCmdGramScale:
       launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,

@@ -24,7 +24,7 @@ enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdGatherRows, kCmdCompact,
+  kCmdGatherRows, kCmdCompact, kCmdGemmReduce,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -83,6 +83,7 @@ struct FactorPlan {
   std::vector<UpdEntry> ents;
   std::vector<CompactTask> compact;
   int64_t xc_size = 0;                // compact operand copies (doubles; mixed forms)
+  int64_t split_size = 0;             // partial tiles of the largest split-K product (doubles)
   std::vector<PotrfTask> potrf;
   std::vector<PhiloxTask> philox;
   std::vector<TruncTask> trunc;
@@ -93,6 +94,7 @@ struct FactorPlan {
   DevArray<UpdEntry> d_ents;
   DevArray<CompactTask> d_compact;
   DevArray<double> d_xc;              // compact row-major Schur-update operands (mixed forms)
+  DevArray<double> d_split;           // K-slice partial tiles (reused by every split product)
   DevArray<PotrfTask> d_potrf;
   DevArray<PhiloxTask> d_philox;
   DevArray<TruncTask> d_trunc;

@@ -24,7 +24,10 @@ struct GemmTask {
   int32_t nlim, klim;
   int32_t sym;                 // 1: C is symmetric; tiles on or below the diagonal only, each
                                // written with its transpose (diagonal tiles: lower half mirrored)
+  int32_t kz, ks;              // kz > 1: K cut into kz chunk-aligned slices, this task computes
+                               // slice ks into the partial tile at `part`; a reduce launch adds them
   int32_t pad_;
+  int64_t part;                // scratch offset (doubles) of the partial tile, column major TM x TM
   double alpha, beta;
 };
 
