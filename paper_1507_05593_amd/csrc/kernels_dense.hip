@@ -59,14 +59,6 @@ __global__ void k_scatter_const(const int64_t* __restrict__ slot, int64_t n, dou
 
 // 1 / sqrt(d) for a positive finite d: the hardware estimate refined by two Newton
 // steps r <- r (3 - d r^2) / 2 (each squares the relative error), to FP64 rounding.
-// Lane l's value of x (l uniform), through two 32-bit readlanes.
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  const long long b = __double_as_longlong(x);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 __device__ __forceinline__ double rsqrt_f64(double d) {
   double r = __builtin_amdgcn_rsq(d);
   r = r * (1.5 - 0.5 * d * r * r);
@@ -86,13 +78,58 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 // Blocked right-looking elimination over four 16-column block steps, the tile in LDS:
 //   1. wave 0 factors the 16 x 16 diagonal block and forms its inverse in registers
 //      (lane j holds column j of the symmetric block and of the inverse; one column at
-//      a time, the pivot and the column broadcast from their lane by readlane);
+//      a time, the pivot and the column broadcast from their lane by DPP row broadcast);
 //   2. the rows below: P = A_below D^{-T}, one 16-row block per wave (FP64 MFMA);
 //   3. the trailing lower blocks: A -= P P^T, blocks dealt round robin to the waves.
 // The inverse's off-diagonal blocks then follow block row by block row:
 //   W_ij = -D_i^{-1} sum_{m = j}^{i-1} L_im W_mj.
 // MFMA v_mfma_f64_16x16x4f64: A operand (row lane % 16, k lane / 16), B operand
 // (column lane % 16, k lane / 16), result element e at (row lane / 16 + 4e, column lane % 16).
+// Lane C of each 16-lane row, broadcast to the row (DPP row_newbcast, two 32-bit moves).
+template <int C>
+__device__ __forceinline__ double bcast16(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + C, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Column C of the 16 x 16 diagonal block (lane j holds column j of the symmetric block in
+// v and of the inverse in wv; lanes 16..63 repeat lanes 0..15): pivot, scaling, and the
+// rank-1 updates, with the pivot and column C broadcast from lane C.
+template <int C>
+__device__ __forceinline__ void diag_step(double (&v)[16], double (&wv)[16], int j, int kk, int nb, int mode,
+                                          double dscale, bool& bad) {
+  double d = bcast16<C>(v[C]);
+  bool dk = false;
+  if (kk + C >= nb) {
+    d = 1.0;                                       // past the block edge: identity
+  } else if (mode == 0) {
+    if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
+  } else if (!(d > dscale) || !isfinite(d)) {
+    dk = true;
+    d = 1.0;
+  }
+  const double rp = rsqrt_f64(d);
+  const double piv = d * rp;
+  const double sc = dk ? 0.0 : rp;
+  const double ljc = (j > C) ? v[C] * sc : 0.0;    // this lane's own A(j, C) (symmetry)
+  const double wcj = wv[C] * sc;                   // row C of the inverse, scaled
+  wv[C] = wcj;
+  // with x = A(i, C) from lane C, L(i, C) = x sc: lane C keeps v[i] sc (= L(i, C)),
+  // the others subtract L(i, C) L(j, C) and L(i, C) W(C, j)
+  const double al = (j == C) ? sc : 1.0;
+  const double ga = sc * ljc, de = sc * wcj;
+  if (j == C) v[C] = piv;
+#pragma unroll
+  for (int i = C + 1; i < 16; ++i) {
+    const double x = bcast16<C>(v[i]);
+    v[i] = fma(-x, ga, v[i] * al);
+    wv[i] = fma(-x, de, wv[i]);
+  }
+  if constexpr (C < 15) diag_step<C + 1>(v, wv, j, kk, nb, mode, dscale, bad);
+}
+
 constexpr int kPitch = 65;
 
 __device__ __forceinline__ v4d mma16(v4d acc, const double* X, int xr, int xc, const double* Y, int yr,
@@ -121,11 +158,20 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   const int nbk = (nb + 15) >> 4, nbb16 = 16 * nbk;   // 16-column blocks that hold the block
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
-  for (int idx = tid; idx < 4096; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    A[r * kPitch + c] = (r < nb && c < nb && r >= c) ? P[base + r + (int64_t)c * T.ld]
-                                                     : ((r == c) ? 1.0 : 0.0);
-    W[r * kPitch + c] = (r == c && r >= nbb16) ? 1.0 : 0.0;   // blocks past nb: identity
+  {
+    // all sixteen loads in flight together (addresses clamped into the block), then LDS
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      t[u] = P[base + min(r, nb - 1) + (int64_t)min(c, nb - 1) * T.ld];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      A[r * kPitch + c] = (r < nb && c < nb && r >= c) ? t[u] : ((r == c) ? 1.0 : 0.0);
+      W[r * kPitch + c] = (r == c && r >= nbb16) ? 1.0 : 0.0;   // blocks past nb: identity
+    }
   }
   const double dscale = (T.mode >= 1) ? arena[T.scale_off] * (T.mode == 2 ? 1e-8 : 1e-14) : 0.0;
   __syncthreads();
@@ -135,8 +181,8 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
     if (w == 0) {
       // lane j (lanes >= 16 repeat lanes 0..15) holds column j of the symmetric block
       // (v[i] = A(i, j) for every i, read from the lower triangle) and column j of its
-      // inverse; the pivot and column c come from lane c by readlane, and this lane's own
-      // v[c] is A(j, c) by symmetry
+      // inverse; the pivot and column c come from lane c by DPP row broadcast, and this
+      // lane's own v[c] is A(j, c) by symmetry
       const int j = li;
       double v[16], wv[16];
 #pragma unroll
@@ -144,32 +190,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
         v[i] = A[(kk + (i > j ? i : j)) * kPitch + kk + (i > j ? j : i)];
         wv[i] = (i == j) ? 1.0 : 0.0;
       }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double d = readlane_f64(v[c], c);
-        bool dk = false;
-        if (kk + c >= nb) {
-          d = 1.0;                                   // past the block edge: identity
-        } else if (T.mode == 0) {
-          if (!(d > 0.0) || !isfinite(d)) { bad = true; d = 1.0; }
-        } else if (!(d > dscale) || !isfinite(d)) {
-          dk = true;
-          d = 1.0;
-        }
-        const double rp = rsqrt_f64(d);
-        const double piv = d * rp;
-        const double sc = dk ? 0.0 : rp;
-        const double ljc = (j > c) ? v[c] * sc : 0.0;
-        const double wcj = wv[c] * sc;               // row c of the inverse, scaled
-        wv[c] = wcj;
-        if (j == c) v[c] = piv;
-#pragma unroll
-        for (int i = c + 1; i < 16; ++i) {
-          const double si = readlane_f64(v[i], c) * sc;   // L(i, c)
-          v[i] = (j == c) ? si : v[i] - si * ljc;
-          wv[i] -= si * wcj;
-        }
-      }
+      diag_step<0>(v, wv, j, kk, nb, T.mode, dscale, bad);
       if (lane < 16) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {

@@ -384,9 +384,20 @@ __global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restr
   const int r = tid >> 2, kq = 8 * (tid & 3);     // writer: row r, values kq .. kq + 7
   for (int c0 = 0; c0 < T.kp; c0 += KC) {
     __syncthreads();
-    for (int idx = tid; idx < 64 * KC; idx += 256) {
-      const int rr = idx & 63, k = idx >> 6;
-      t[k][rr] = (rr < T.nrows && c0 + k < K) ? src[rr + (int64_t)(c0 + k) * T.ld] : 0.0;
+    if (c0 < K) {                          // eight loads in flight together (clamped addresses)
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = tid + 256 * u, rr = idx & 63, k = idx >> 6;
+        v[u] = src[min(rr, T.nrows - 1) + (int64_t)min(c0 + k, K - 1) * T.ld];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = tid + 256 * u, rr = idx & 63, k = idx >> 6;
+        t[k][rr] = (rr < T.nrows && c0 + k < K) ? v[u] : 0.0;
+      }
+    } else {
+      for (int idx = tid; idx < 64 * KC; idx += 256) t[idx >> 6][idx & 63] = 0.0;
     }
     __syncthreads();
     if (r < T.nrows) {
@@ -562,9 +573,19 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
   const UpdTile T = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double* P = arena + T.panel;
-  for (int idx = tid; idx < 64 * 64; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    tile[r + 65 * c] = (r < T.nrows && c < T.ncols) ? P[(T.row0 + r) + (int64_t)(T.col0 + c) * T.ld] : 0.0;
+  {
+    // all sixteen loads in flight together (addresses clamped into the tile), then LDS
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      t[u] = P[(T.row0 + min(r, T.nrows - 1)) + (int64_t)(T.col0 + min(c, T.ncols - 1)) * T.ld];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+      tile[r + 65 * c] = (r < T.nrows && c < T.ncols) ? t[u] : 0.0;
+    }
   }
   __syncthreads();
   typename Acc<MODE>::T acc[2][2];
