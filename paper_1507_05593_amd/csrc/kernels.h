@@ -24,6 +24,9 @@ void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s)
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_p(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_compact(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);
+void launch_trunc_mfill(const TruncTask* t, int n, double* arena, hipStream_t s);
+void launch_trunc_flags(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s);
+void launch_trunc_copy(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s);
 
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
 void launch_fwd_part(const FwdChunk* c, int n, const FwdTile* t, const FwdEntry* e,

@@ -367,22 +367,24 @@ __device__ double block_sum1024(double v) {
 // trace(G) and S = G / trace(G) (zero when the trace is not positive).
 __global__ __launch_bounds__(256) void k_trunc_prep(const TruncTask* __restrict__ tasks,
                                                     double* __restrict__ arena) {
-  const TruncTask T = tasks[blockIdx.x];
+  // grid (blocks, tasks): every block forms tr G the same way, then scales its share
+  const TruncTask T = tasks[blockIdx.y];
   const int l = T.l;
   const double* G = arena + T.g;
   double t = 0.0;
   for (int i = threadIdx.x; i < l; i += 256) t += G[i + (int64_t)i * l];
   t = block_sum256(t);
-  if (threadIdx.x == 0) arena[T.sc] = t;
+  if (blockIdx.x == 0 && threadIdx.x == 0) arena[T.sc] = t;
   const double inv = (t > 0.0 && isfinite(t)) ? 1.0 / t : 0.0;
   double* S = arena + T.sa;
   const int64_t ll = (int64_t)l * l;
-  for (int64_t e = threadIdx.x; e < ll; e += 256) S[e] = G[e] * inv;
+#pragma unroll 4
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < ll; e += (int64_t)gridDim.x * 256) S[e] = G[e] * inv;
 }
 
 // lambda_max by power iteration with S32 = (G / tr G)^32 (already in sb), Rayleigh
-// quotient with G; theta = tol^2 lambda_max; then the Cholesky panel
-// [G + theta I; I] (ld 2l) and its drop scale.
+// quotient with G; theta = tol^2 lambda_max (the panel [G + theta I; I] is filled by
+// k_trunc_mfill).
 __global__ __launch_bounds__(1024) void k_trunc_power(const TruncTask* __restrict__ tasks,
                                                      double* __restrict__ arena) {
   __shared__ double v[2048], w[2048];   // l <= 2048 (checked by the planner)
@@ -400,6 +402,7 @@ __global__ __launch_bounds__(1024) void k_trunc_power(const TruncTask* __restric
   for (int it = 0; it < 4; ++it) {
     for (int i = threadIdx.x; i < l; i += 1024) {
       double a = 0.0;
+#pragma unroll 8
       for (int k = 0; k < l; ++k) a += S[i + (int64_t)k * l] * v[k];
       w[i] = a;
     }
@@ -414,6 +417,7 @@ __global__ __launch_bounds__(1024) void k_trunc_power(const TruncTask* __restric
   double num = 0.0, den = 0.0;
   for (int i = threadIdx.x; i < l; i += 1024) {
     double a = 0.0;
+#pragma unroll 8
     for (int k = 0; k < l; ++k) a += G[i + (int64_t)k * l] * v[k];
     num += v[i] * a;
     den += v[i] * v[i];
@@ -424,24 +428,35 @@ __global__ __launch_bounds__(1024) void k_trunc_power(const TruncTask* __restric
   if (!isfinite(lam) || lam < 0.0) lam = 0.0;
   const double theta = T.tol * T.tol * lam;
   if (threadIdx.x == 0) { arena[T.sc + 1] = lam; arena[T.sc + 2] = theta; }
+}
+
+// The Cholesky panel [G + theta I; I] (ld 2l) of the truncation and its drop scale (the
+// largest diagonal entry); grid (blocks, tasks).
+__global__ __launch_bounds__(256) void k_trunc_mfill(const TruncTask* __restrict__ tasks,
+                                                     double* __restrict__ arena) {
+  const TruncTask T = tasks[blockIdx.y];
+  const int l = T.l;
+  const double theta = arena[T.sc + 2];
+  const double* G = arena + T.g;
   double* M = arena + T.mpan;
-  const int ld = 2 * l;
-  double mx = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += 1024) {
+  const int64_t ld = 2 * (int64_t)l, ll = (int64_t)l * l;
+  for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < ll; e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e % l), j = (int)(e / l);
-    const double gij = G[e] + (i == j ? theta : 0.0);
-    M[i + (int64_t)j * ld] = gij;
-    M[l + i + (int64_t)j * ld] = (i == j) ? 1.0 : 0.0;
-    if (i == j) mx = fmax(mx, gij);
+    M[i + j * ld] = G[e] + (i == j ? theta : 0.0);
+    M[l + i + j * ld] = (i == j) ? 1.0 : 0.0;
   }
-  __shared__ double red[1024];
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s2 = 512; s2 > 0; s2 >>= 1) {
-    if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+  if (blockIdx.x == 0) {
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < l; i += 256) mx = fmax(mx, G[i + (int64_t)i * l] + theta);
+    __shared__ double red[256];
+    red[threadIdx.x] = mx;
     __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+      if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) arena[T.sc + 3] = red[0];
   }
-  if (threadIdx.x == 0) arena[T.sc + 3] = red[0];
 }
 
 // X0 = I - 2 theta H with H = (G + theta I)^{-1} (in sb), into sa.
@@ -472,6 +487,7 @@ __global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ t
   }
 }
 
+
 // Kept rank and basis.  The orthonormalisation of P Omega2 (all l columns, rows
 // [l, 2l) of the basis panel, ld 2l) zeroed every column that fell in the span of
 // the earlier ones, so the surviving columns span range(P): they are copied, in
@@ -479,31 +495,43 @@ __global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ t
 // eigenvalue that sits on the threshold leaves P with an intermediate eigenvalue;
 // its direction then survives whole instead of displacing a kept one.  q = 0 for a
 // zero or non-finite Gram matrix.
-__global__ __launch_bounds__(256) void k_trunc_compact(const TruncTask* __restrict__ tasks,
-                                                       double* __restrict__ arena,
-                                                       int32_t* __restrict__ ints) {
-  __shared__ int32_t pos[2048];          // l <= 2048 (checked by the planner)
-  __shared__ int32_t part[256];
-  const TruncTask T = tasks[blockIdx.x];
+// Basis compaction of the truncation, in three launches.  Flags (grid (columns / 16,
+// tasks)): column k of W survives if it has any non-zero (or non-finite) entry; the flag
+// goes to sb[k].  Scan (one workgroup per task): survivors are numbered in column order,
+// the destination (or -1) goes to sb[l + k] and their count q_j to the rank slot (0 when
+// tr G was zero or not finite).  Copy (grid (columns / 16, tasks)): surviving columns to
+// the front of wout (ld l).
+__global__ __launch_bounds__(256) void k_trunc_flags(const TruncTask* __restrict__ tasks,
+                                                     double* __restrict__ arena) {
+  const TruncTask T = tasks[blockIdx.y];
   const int l = T.l;
   const int64_t ld = 2 * (int64_t)l;
   const double* W = arena + T.wpan + l;
-  double* out = arena + T.wout;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // 1. survivors: any non-zero (or non-finite) entry
-  for (int k = w; k < l; k += 4) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int u = 0; u < 4; ++u) {
+    const int k = blockIdx.x * 16 + 4 * w + u;
+    if (k >= l) break;
     const double* col = W + (int64_t)k * ld;
     int nz = 0;
     for (int i = lane; i < l; i += 64) nz |= (col[i] != 0.0);
     const unsigned long long m = __ballot(nz);
-    if (lane == 0) pos[k] = m ? 1 : 0;
+    if (lane == 0) arena[T.sb + k] = m ? 1.0 : 0.0;
   }
-  __syncthreads();
-  // 2. exclusive scan: thread t owns columns [t cs, (t + 1) cs)
+}
+
+__global__ __launch_bounds__(256) void k_trunc_compact(const TruncTask* __restrict__ tasks,
+                                                       double* __restrict__ arena,
+                                                       int32_t* __restrict__ ints) {
+  __shared__ int32_t part[256];
+  const TruncTask T = tasks[blockIdx.x];
+  const int l = T.l;
+  const int tid = threadIdx.x;
+  double* flag = arena + T.sb;
+  // exclusive scan: thread t owns columns [t cs, (t + 1) cs)
   const int cs = (l + 255) / 256;
   const int k0 = min(l, tid * cs), k1 = min(l, k0 + cs);
   int own = 0;
-  for (int k = k0; k < k1; ++k) own += pos[k];
+  for (int k = k0; k < k1; ++k) own += (flag[k] != 0.0);
   part[tid] = own;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
@@ -515,22 +543,32 @@ __global__ __launch_bounds__(256) void k_trunc_compact(const TruncTask* __restri
   const int q = part[255];
   int dst = part[tid] - own;
   for (int k = k0; k < k1; ++k) {
-    const int keep = pos[k];
-    pos[k] = keep ? dst : -1;
+    const bool keep = flag[k] != 0.0;
+    flag[l + k] = keep ? (double)dst : -1.0;
     dst += keep;
-  }
-  __syncthreads();
-  // 3. copy the survivors
-  for (int k = w; k < l; k += 4) {
-    const int d = pos[k];
-    if (d < 0) continue;
-    const double* col = W + (int64_t)k * ld;
-    double* o = out + (int64_t)d * l;
-    for (int i = lane; i < l; i += 64) o[i] = col[i];
   }
   if (tid == 0) {
     const double gt = arena[T.sc];
     ints[T.qslot] = (gt > 0.0 && isfinite(gt)) ? q : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_trunc_copy(const TruncTask* __restrict__ tasks,
+                                                    double* __restrict__ arena) {
+  const TruncTask T = tasks[blockIdx.y];
+  const int l = T.l;
+  const int64_t ld = 2 * (int64_t)l;
+  const double* W = arena + T.wpan + l;
+  double* out = arena + T.wout;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int u = 0; u < 4; ++u) {
+    const int k = blockIdx.x * 16 + 4 * w + u;
+    if (k >= l) break;
+    const int d = (int)arena[T.sb + l + k];
+    if (d < 0) continue;
+    const double* col = W + (int64_t)k * ld;
+    double* o = out + (int64_t)d * l;
+    for (int i = lane; i < l; i += 64) o[i] = col[i];
   }
 }
 
@@ -568,7 +606,16 @@ void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, c
   if (n > 0) hipLaunchKernelGGL(k_gram_scale, dim3(n), dim3(256), 0, s, g, ld, nn, out, arena);
 }
 void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_trunc_prep, dim3(n), dim3(256), 0, s, t, arena);
+  if (n > 0) hipLaunchKernelGGL(k_trunc_prep, dim3(64, n), dim3(256), 0, s, t, arena);
+}
+void launch_trunc_mfill(const TruncTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_mfill, dim3(64, n), dim3(256), 0, s, t, arena);
+}
+void launch_trunc_flags(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_flags, dim3((lmax + 15) / 16, n), dim3(256), 0, s, t, arena);
+}
+void launch_trunc_copy(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_copy, dim3((lmax + 15) / 16, n), dim3(256), 0, s, t, arena);
 }
 void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_power, dim3(n), dim3(1024), 0, s, t, arena);

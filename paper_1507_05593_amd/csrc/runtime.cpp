@@ -815,7 +815,8 @@ struct Builder {
     };
     cmd(kCmdTruncPrep, RSC_K_EIG, t0, nt, 0);          // sa = G / tr G
     for (int k = 0; k < 5; ++k) sq_gemm(k % 2 == 0, 1.0, 0.0, -1);   // sb = (G / tr G)^32
-    cmd(kCmdTruncPower, RSC_K_EIG, t0, nt, 0);         // lambda_max, theta, [G + theta I; I]
+    cmd(kCmdTruncPower, RSC_K_EIG, t0, nt, 0);         // lambda_max, theta
+    cmd(kCmdTruncMfill, RSC_K_EIG, t0, nt, 0);         // [G + theta I; I]
     {
       std::vector<PanelDesc> pan;
       for (int32_t j : js) {
@@ -900,7 +901,11 @@ struct Builder {
         cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
         panel_steps(pan);
       }
+      int32_t lmax = 0;
+      for (int32_t j : js) lmax = std::max(lmax, h.comp[j].ell);
+      cmd(kCmdTruncFlags, RSC_K_EIG, t0, nt, 0, lmax);
       cmd(kCmdTruncCompact, RSC_K_EIG, t0, nt, 0);
+      cmd(kCmdTruncCopy, RSC_K_EIG, t0, nt, 0, lmax);
     }
     // 9. U_j = U W, V_j = V W (columns beyond the device rank q_j are skipped)
     g0 = (int64_t)P.gemm.size(); fl = 0;
@@ -1082,7 +1087,8 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
     "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
-    "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce"};
+    "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
+    "trunc_flags", "trunc_copy"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
@@ -1090,6 +1096,9 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
     case kCmdUpdate: return (int32_t)(4 + (a & 3));
     case kCmdCompact: return 29;
     case kCmdGemmReduce: return 30;
+    case kCmdTruncMfill: return 31;
+    case kCmdTruncFlags: return 32;
+    case kCmdTruncCopy: return 33;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -1141,6 +1150,9 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncX0: launch_trunc_x0(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncP: launch_trunc_p(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncCompact: launch_trunc_compact(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
+    case kCmdTruncMfill: launch_trunc_mfill(P->d_trunc.p + c.off, (int)c.count, A, s); break;
+    case kCmdTruncFlags: launch_trunc_flags(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
+    case kCmdTruncCopy: launch_trunc_copy(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, Q->d_part.p, s); break;
     case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, Q->d_part.p, s); break;

@@ -24,7 +24,7 @@ enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
-  kCmdGatherRows, kCmdCompact, kCmdGemmReduce,
+  kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
