@@ -77,8 +77,8 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 //
 // Blocked right-looking elimination over four 16-column block steps, the tile in LDS:
 //   1. wave 0 factors the 16 x 16 diagonal block and forms its inverse in registers
-//      (lane j holds column j of the symmetric block and of the inverse; one column at
-//      a time, the pivot and the column broadcast from their lane by DPP row broadcast);
+//      (each lane holds four rows of one column of the symmetric block and of the
+//      inverse; one column at a time, the pivot and the column broadcast across lanes);
 //   2. the rows below: P = A_below D^{-T}, one 16-row block per wave (FP64 MFMA);
 //   3. the trailing lower blocks: A -= P P^T, blocks dealt round robin to the waves.
 // The inverse's off-diagonal blocks then follow block row by block row:
@@ -94,13 +94,26 @@ __device__ __forceinline__ double bcast16(double x) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Column C of the 16 x 16 diagonal block (lane j holds column j of the symmetric block in
-// v and of the inverse in wv; lanes 16..63 repeat lanes 0..15): pivot, scaling, and the
-// rank-1 updates, with the pivot and column C broadcast from lane C.
+// Lane l's value of x (l uniform), through two 32-bit readlanes.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Column C of the 16 x 16 diagonal block.  Lane (j, g) = (lane % 16, lane / 16) holds rows
+// 4s + g (s < 4) of column j of the symmetric block (v[s]) and of the inverse (wv[s]).
+// The pivot comes from lane (C, C % 4) by readlane; A(j, C) = A(C, j) and W(C, j) from
+// lane (j, C % 4) by a shuffle; A(4s + g, C) from lane C of the lane's own 16-lane row by
+// DPP row broadcast, so each lane updates its four rows.
 template <int C>
-__device__ __forceinline__ void diag_step(double (&v)[16], double (&wv)[16], int j, int kk, int nb, int mode,
-                                          double dscale, bool& bad) {
-  double d = bcast16<C>(v[C]);
+__device__ __forceinline__ void diag_step(double (&v)[4], double (&wv)[4], int j, int g, int kk, int nb,
+                                          int mode, double dscale, bool& bad) {
+  constexpr int gC = C & 3, sC = C >> 2;
+  double d = readlane_f64(v[sC], 16 * gC + C);
+  const double ajc = __shfl(v[sC], 16 * gC + j, 64);
+  const double wcr = __shfl(wv[sC], 16 * gC + j, 64);
   bool dk = false;
   if (kk + C >= nb) {
     d = 1.0;                                       // past the block edge: identity
@@ -113,21 +126,22 @@ __device__ __forceinline__ void diag_step(double (&v)[16], double (&wv)[16], int
   const double rp = rsqrt_f64(d);
   const double piv = d * rp;
   const double sc = dk ? 0.0 : rp;
-  const double ljc = (j > C) ? v[C] * sc : 0.0;    // this lane's own A(j, C) (symmetry)
-  const double wcj = wv[C] * sc;                   // row C of the inverse, scaled
-  wv[C] = wcj;
-  // with x = A(i, C) from lane C, L(i, C) = x sc: lane C keeps v[i] sc (= L(i, C)),
-  // the others subtract L(i, C) L(j, C) and L(i, C) W(C, j)
+  const double ljc = (j > C) ? ajc * sc : 0.0;
+  const double wcj = wcr * sc;                     // row C of the inverse, scaled
+  if (g == gC) wv[sC] = wcj;
   const double al = (j == C) ? sc : 1.0;
   const double ga = sc * ljc, de = sc * wcj;
-  if (j == C) v[C] = piv;
+  if (j == C && g == gC) v[sC] = piv;
 #pragma unroll
-  for (int i = C + 1; i < 16; ++i) {
-    const double x = bcast16<C>(v[i]);
-    v[i] = fma(-x, ga, v[i] * al);
-    wv[i] = fma(-x, de, wv[i]);
+  for (int s = 0; s < 4; ++s) {
+    if (4 * s + 3 <= C) continue;                  // every row of the slot is done
+    const double x = bcast16<C>(v[s]);             // A(4s + g, C)
+    const bool below = 4 * s + g > C;
+    const double nv = fma(-x, ga, v[s] * al), nw = fma(-x, de, wv[s]);
+    v[s] = below ? nv : v[s];
+    wv[s] = below ? nw : wv[s];
   }
-  if constexpr (C < 15) diag_step<C + 1>(v, wv, j, kk, nb, mode, dscale, bad);
+  if constexpr (C < 15) diag_step<C + 1>(v, wv, j, g, kk, nb, mode, dscale, bad);
 }
 
 constexpr int kPitch = 65;
@@ -179,24 +193,22 @@ __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__
   for (int kb = 0; kb < nbk; ++kb) {
     const int kk = 16 * kb;
     if (w == 0) {
-      // lane j (lanes >= 16 repeat lanes 0..15) holds column j of the symmetric block
-      // (v[i] = A(i, j) for every i, read from the lower triangle) and column j of its
-      // inverse; the pivot and column c come from lane c by DPP row broadcast, and this
-      // lane's own v[c] is A(j, c) by symmetry
-      const int j = li;
-      double v[16], wv[16];
+      // lane (j, g) holds rows 4s + g of column j of the symmetric block (read from the
+      // lower triangle) and of the inverse (see diag_step)
+      const int j = li, g = lk;
+      double v[4], wv[4];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        v[i] = A[(kk + (i > j ? i : j)) * kPitch + kk + (i > j ? j : i)];
-        wv[i] = (i == j) ? 1.0 : 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * q + g;
+        v[q] = A[(kk + (i > j ? i : j)) * kPitch + kk + (i > j ? j : i)];
+        wv[q] = (i == j) ? 1.0 : 0.0;
       }
-      diag_step<0>(v, wv, j, kk, nb, T.mode, dscale, bad);
-      if (lane < 16) {
+      diag_step<0>(v, wv, j, g, kk, nb, T.mode, dscale, bad);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (i >= j) A[(kk + i) * kPitch + kk + j] = v[i];
-          W[(kk + i) * kPitch + kk + j] = wv[i];
-        }
+      for (int q = 0; q < 4; ++q) {
+        const int i = 4 * q + g;
+        if (i >= j) A[(kk + i) * kPitch + kk + j] = v[q];
+        W[(kk + i) * kPitch + kk + j] = wv[q];
       }
     }
     __syncthreads();
