@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--workload", default="diffusion3d_96")
     ap.add_argument("--precision", default="", choices=["", "fp64", "fp32", "bf16"])
     ap.add_argument("--compare", default="auto", help="second precision timed beside (none to skip)")
-    ap.add_argument("--cpu-sample-side", type=int, default=40)
+    ap.add_argument("--cpu-sample-side", type=int, default=46)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying hipGraphs")
