@@ -62,7 +62,9 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
 // Within a wave, an entry of nr rows takes lanes as P = max(8, nr rounded up to a
 // power of two) rows by G = 64 / P column groups, group g summing columns g, g + G, ...,
 // so that one load instruction reads G columns of the column-major X; the groups are
-// then added by a fixed butterfly.  k_part_apply subtracts the block's partials from y.
+// then added by a fixed butterfly.  A large entry is planned as several pieces over
+// column ranges, so that no chunk is much longer than the level's average.
+// k_part_apply subtracts the block's partials from y.
 __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ chunks,
                                                   const FwdTile* __restrict__ tiles,
                                                   const FwdEntry* __restrict__ ents,
@@ -83,11 +85,12 @@ __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ c
     const int G = 64 / P;
     const int row = lane & (P - 1), g = lane / P;
     double s = 0.0;
+    const int me = min(K, E.m0 + E.kspan);
     if (row < nr) {
       const double* X = arena + E.x + E.a + row;
       const double* v = arena + E.v;
 #pragma unroll 8
-      for (int m = g; m < K; m += G) s += X[(int64_t)m * E.ldx] * v[m];
+      for (int m = E.m0 + g; m < me; m += G) s += X[(int64_t)m * E.ldx] * v[m];
     }
     for (int o = P; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
     if (g == 0 && row < nr) acc[w][relmap[E.map + E.a + row] - T.row0] += s;

@@ -1391,6 +1391,7 @@ static Error build_solve_plan(Handle& h) {
             base.v = h.a_w + S.first[k];
           }
           base.map = pr.map_off;
+          base.m0 = 0; base.kspan = INT_MAX;
           for (int32_t t = 0; t < pr.nD;) {
             const int32_t B = rm[t] / 64;
             int32_t u = t;
@@ -1417,7 +1418,8 @@ static Error build_solve_plan(Handle& h) {
       // subtracts them from y in a fixed order.
       auto ework = [&](const FwdEntry& e) {
         const double K = e.kdim >= 0 ? e.kdim : (double)h.comp[(-1 - e.kdim) - h.i_ranks].ell;
-        return (double)(e.b - e.a) * std::max(K, 1.0);
+        const double Kp = std::min(K - e.m0, (double)e.kspan);   // this piece's columns
+        return (double)(e.b - e.a) * std::max(Kp, 1.0);
       };
       double wl = 0;
       for (auto& bk : blks)
@@ -1427,7 +1429,19 @@ static Error build_solve_plan(Handle& h) {
       int32_t slot = 0;
       for (auto& bk : blks) {
         bk.t.e0 = (int32_t)Q->fents.size();
-        for (auto& e : bk.e) Q->fents.push_back(e);
+        for (auto& e : bk.e) {
+          // an entry worth several chunks becomes pieces over column ranges
+          const double w = ework(e);
+          if (w <= 2.0 * target) { Q->fents.push_back(e); continue; }
+          const int32_t kst = e.kdim >= 0 ? e.kdim : h.comp[(-1 - e.kdim) - h.i_ranks].ell;
+          const int32_t np = (int32_t)std::ceil(w / target);
+          const int32_t span = ((kst + np - 1) / np + 7) / 8 * 8;
+          for (int32_t m0 = 0; m0 < kst; m0 += span) {
+            FwdEntry u = e;
+            u.m0 = m0; u.kspan = span;
+            Q->fents.push_back(u);
+          }
+        }
         bk.t.e1 = (int32_t)Q->fents.size();
         const int32_t ti = (int32_t)Q->ftiles.size();
         Q->ftiles.push_back(bk.t);

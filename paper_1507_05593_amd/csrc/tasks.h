@@ -173,6 +173,7 @@ struct FwdEntry {
   int64_t map;                 // relmap offset of gathered row 0
   int32_t ldx, kdim;           // kdim < 0: -(1 + int-arena slot)
   int32_t a, b;
+  int32_t m0, kspan;           // this piece sums columns [m0, min(kdim, m0 + kspan))
 };
 
 }  // namespace rsc
