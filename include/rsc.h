@@ -203,6 +203,18 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops);
 
+/* Device memory.  Every device allocation of the library (factor arena, task lists, work
+ * buffers) is made by alloc(bytes, stream, ctx) and returned by release(ptr, stream, ctx)
+ * (stream is always NULL: the memory outlives any one stream's work; it is released
+ * by rsc_destroy after the handle's work is complete).  For callers that manage device
+ * memory themselves, e.g. a caching allocator.  alloc returns NULL when it cannot
+ * satisfy the request (the calling function then fails with RSC_ERR_OUT_OF_MEMORY).
+ * Both NULL restores hipMalloc / hipFree.  Process wide; it may only change while no
+ * handle exists.  Errors: RSC_ERR_INVALID_ARG (one callback without the other),
+ * RSC_ERR_STATE (handles exist). */
+rsc_status rsc_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                             void (*release)(void* ptr, void* stream, void* ctx), void* ctx);
+
 const char* rsc_status_string(rsc_status s);
 const char* rsc_last_error(void);
 /* Releases the handle and all its device memory (after synchronising its device). */

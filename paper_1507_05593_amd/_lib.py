@@ -55,6 +55,14 @@ class Profile(C.Structure):
                 ("flops", C.c_double * len(K_CLASSES))]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+def fnptr(f):
+    """A ctypes callback as the plain pointer rsc_set_allocator takes (None: NULL)."""
+    return None if f is None else C.cast(f, C.c_void_p)
+
 _lib = None
 
 SYMBOLS = {
@@ -80,6 +88,7 @@ SYMBOLS = {
     "rsc_get_profile": (C.c_int, [C.c_void_p, C.POINTER(Profile)]),
     "rsc_get_kernel_profile": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "rsc_set_allocator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),   # ALLOC_FN, RELEASE_FN or NULL
     "rsc_status_string": (C.c_char_p, [C.c_int]),
     "rsc_last_error": (C.c_char_p, []),
     "rsc_destroy": (None, [C.c_void_p]),

@@ -9,7 +9,15 @@
 #include "kernels.h"
 #include "runtime.h"
 
+// Counts live handles; declared before the handle state so that it is destroyed after
+// the state has returned its device memory to the allocator that gave it.
+struct HandleCount {
+  HandleCount() { rsc::handle_count(+1); }
+  ~HandleCount() { rsc::handle_count(-1); }
+};
+
 struct rsc_handle_s {
+  HandleCount count;
   rsc::Handle h;
 };
 
@@ -350,6 +358,15 @@ const char* rsc_status_string(rsc_status s) {
 }
 
 const char* rsc_last_error(void) { return g_last_error.c_str(); }
+
+rsc_status rsc_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                             void (*release)(void* ptr, void* stream, void* ctx), void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(RSC_ERR_INVALID_ARG, "allocator and release must be given together");
+  if (!rsc::set_allocator(alloc, release, ctx))
+    return fail(RSC_ERR_STATE, "the allocator can only change while no handle exists");
+  return RSC_OK;
+}
 
 void rsc_destroy(rsc_handle H) {
   if (!H) return;

@@ -11,6 +11,7 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -190,12 +191,55 @@ void plan_layout(Handle& h) {
 
 // ------------------------------------------------------------------ device set-up
 
+namespace {
+void* (*g_alloc)(size_t, void*, void*) = nullptr;
+void (*g_release)(void*, void*, void*) = nullptr;
+void* g_alloc_ctx = nullptr;
+std::atomic<int> g_live_handles{0};
+std::mutex g_alloc_mu;
+}  // namespace
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (g_alloc) return g_alloc(bytes, nullptr, g_alloc_ctx);
+  void* p = nullptr;
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_release) {
+    // hipFree waits for the device; a caller's allocator may hand the block out at once
+    (void)hipDeviceSynchronize();
+    g_release(p, nullptr, g_alloc_ctx);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+bool set_allocator(void* (*alloc)(size_t, void*, void*), void (*release)(void*, void*, void*), void* ctx) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if (alloc == g_alloc && release == g_release && (alloc == nullptr || ctx == g_alloc_ctx))
+    return true;                                   // no change
+  if (g_live_handles.load() != 0) return false;
+  g_alloc = alloc;
+  g_release = release;
+  g_alloc_ctx = alloc ? ctx : nullptr;
+  return true;
+}
+
+void handle_count(int delta) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_live_handles += delta;
+}
+
 template <class T>
 static Error upload(DevArray<T>& d, const std::vector<T>& v) {
   d.reset();
   d.n = (int64_t)v.size();
   if (v.empty()) return kOk;
-  HIPCHK(hipMalloc((void**)&d.p, sizeof(T) * v.size()));
+  d.p = static_cast<T*>(dev_alloc(sizeof(T) * v.size()));
+  if (!d.p) return Error{RSC_ERR_OUT_OF_MEMORY, "device array of " + std::to_string(sizeof(T) * v.size()) + " bytes"};
   HIPCHK(hipMemcpy(d.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
   return kOk;
 }
@@ -215,10 +259,11 @@ Error ensure_device(Handle& h) {
     return Error{RSC_ERR_DEVICE, std::string("this library is built for gfx950, found ") + prop.gcnArchName};
   h.device = dev;
   size_t bytes = sizeof(double) * (size_t)h.arena_size;
-  hipError_t e = hipMalloc((void**)&h.arena.p, bytes);
-  if (e != hipSuccess) return Error{RSC_ERR_OUT_OF_MEMORY, "arena of " + std::to_string(bytes) + " bytes"};
+  h.arena.p = static_cast<double*>(dev_alloc(bytes));
+  if (!h.arena.p) return Error{RSC_ERR_OUT_OF_MEMORY, "arena of " + std::to_string(bytes) + " bytes"};
   h.arena.n = h.arena_size;
-  HIPCHK(hipMalloc((void**)&h.ints.p, sizeof(int32_t) * (size_t)h.ints_size));
+  h.ints.p = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (size_t)h.ints_size));
+  if (!h.ints.p) return Error{RSC_ERR_OUT_OF_MEMORY, "int arena"};
   h.ints.n = h.ints_size;
   HIPCHK(hipMemset(h.ints.p, 0, sizeof(int32_t) * (size_t)h.ints_size));
   Error r;
@@ -1028,11 +1073,13 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_ents, P->ents)).code) return e;
   if ((e = upload(P->d_compact, P->compact)).code) return e;
   if (P->xc_size > 0) {
-    HIPCHK(hipMalloc((void**)&P->d_xc.p, sizeof(double) * P->xc_size));
+    P->d_xc.p = static_cast<double*>(dev_alloc(sizeof(double) * P->xc_size));
+    if (!P->d_xc.p) return Error{RSC_ERR_OUT_OF_MEMORY, "compact operand copies"};
     P->d_xc.n = P->xc_size;
   }
   if (P->split_size > 0) {
-    HIPCHK(hipMalloc((void**)&P->d_split.p, sizeof(double) * P->split_size));
+    P->d_split.p = static_cast<double*>(dev_alloc(sizeof(double) * P->split_size));
+    if (!P->d_split.p) return Error{RSC_ERR_OUT_OF_MEMORY, "split-K scratch"};
     P->d_split.n = P->split_size;
   }
   if ((e = upload(P->d_potrf, P->potrf)).code) return e;

@@ -45,6 +45,15 @@ struct Cmd {
                         // recounts the flops from the tasks once the ranks are known
 };
 
+// Device memory of the library: the caller's allocator when one is set (rsc_set_allocator),
+// else hipMalloc / hipFree.  dev_alloc returns nullptr on failure.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+// Replaces the allocator; false while any handle holds device memory.
+bool set_allocator(void* (*alloc)(size_t, void*, void*), void (*release)(void*, void*, void*), void* ctx);
+// Live handles (an allocator may only change while there are none).
+void handle_count(int delta);
+
 template <class T>
 struct DevArray {
   T* p = nullptr;
@@ -54,7 +63,7 @@ struct DevArray {
   DevArray& operator=(const DevArray&) = delete;
   ~DevArray() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     n = 0;
   }

@@ -32,6 +32,33 @@ def _dev_f64(t, n, name):
     return t
 
 
+_allocator_refs = None   # the ctypes callbacks must outlive their use by the library
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Route the library's device memory (rsc_set_allocator) through torch's caching
+    allocator, or back to hipMalloc with on=False.  Only while no solver exists."""
+    global _allocator_refs
+    L = lib()
+    if not on:
+        check(L.rsc_set_allocator(None, None, None), "rsc_set_allocator")
+        _allocator_refs = None
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:        # out of memory: the library reports RSC_ERR_OUT_OF_MEMORY
+            return None
+
+    def _release(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    refs = (_lib.ALLOC_FN(_alloc), _lib.RELEASE_FN(_release))
+    check(L.rsc_set_allocator(_lib.fnptr(refs[0]), _lib.fnptr(refs[1]), None), "rsc_set_allocator")
+    _allocator_refs = refs
+
+
 def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.0, seed=0,
                  precision="fp64", use_graph=True, retry=True, gemm_tile=0) -> Options:
     o = Options()

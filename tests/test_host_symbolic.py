@@ -103,3 +103,25 @@ def test_stats_before_factor():
     o = Options()
     lib().rsc_default_options(C.byref(o))
     assert (o.leaf_max, o.tau_O, o.oversample, o.power_iters, o.alpha_O) == (64, 32, 10, 0, 1.0)
+
+
+def test_set_allocator_arguments_and_state():
+    """rsc_set_allocator: both callbacks or neither; no change while a handle exists
+    (analysis needs no device, so a handle can be made here)."""
+    import gc
+
+    from paper_1507_05593_amd import _lib
+    from paper_1507_05593_amd._lib import RSC_ERR_STATE, RSC_OK
+    L = lib()
+    assert L.rsc_set_allocator(None, None, None) == RSC_OK          # already the default
+    alloc_cb = _lib.ALLOC_FN(lambda n, s, c: None)
+    release_cb = _lib.RELEASE_FN(lambda p, s, c: None)
+    alloc, release = _lib.fnptr(alloc_cb), _lib.fnptr(release_cb)
+    assert L.rsc_set_allocator(alloc, None, None) == RSC_ERR_INVALID_ARG
+    assert L.rsc_set_allocator(None, release, None) == RSC_ERR_INVALID_ARG
+    p = grid_problem((6, 6), sigma=0.0, seed=1)
+    sol = RSCSolver(p.n, p.rowptr, p.colind)
+    assert L.rsc_set_allocator(alloc, release, None) == RSC_ERR_STATE
+    assert L.rsc_set_allocator(None, None, None) == RSC_OK          # no change: allowed
+    del sol
+    gc.collect()
