@@ -362,12 +362,12 @@ __global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmTask* __restrict
 
 // ------------------------------------------------------------------ Schur update
 //
-// Operands of the Schur update (L^O_k, or V_k of a compressed supernode) in the mixed
-// forms are read from a compact row-major copy written once when the operand is final:
-// row t holds the operand's K columns in chunks of 32, each chunk one 128-byte line --
-// FP32 values (kF32), or 32 BF16 high parts followed by the 32 low parts (kBF16x3) --
-// zero beyond the operand's kept columns.  A lane then takes its 8 consecutive k values
-// of a row with one or two 16-byte loads.  The FP64 form reads the column-major arena.
+// Operands of the Schur update (L^O_k, or V_k of a compressed supernode) are read from a
+// compact row-major copy written once when the operand is final: row t holds the
+// operand's K columns in chunks of 32 -- FP64 values (sF64, 256 bytes), FP32 values
+// (sF32, one 128-byte line), or 32 BF16 high parts followed by the 32 low parts
+// (sBF16x3, one line) -- zero beyond the operand's kept columns.  A lane then takes its
+// 8 consecutive k values of a row with one, two or four 16-byte loads.
 
 // One 64-row block of one operand per workgroup: the 64 x 32 chunk is read column by
 // column (coalesced), transposed through LDS and written as rows.
@@ -412,6 +412,15 @@ __global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restr
         }
         *reinterpret_cast<v8bf*>(row + kq) = hi;
         *reinterpret_cast<v8bf*>(row + KC + kq) = lo;
+      } else if constexpr (MODE == sF64) {
+        double* row = xc + T.dst + (int64_t)r * T.kp + c0 + kq;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          double2 d;
+          d.x = t[kq + 2 * u][r];
+          d.y = t[kq + 2 * u + 1][r];
+          *reinterpret_cast<double2*>(row + 2 * u) = d;
+        }
       } else {
         float* row = reinterpret_cast<float*>(xc + T.dst) + (int64_t)r * T.kp + c0;
         v4f a, b;
@@ -424,105 +433,145 @@ __global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restr
   }
 }
 
-// A wave's product of rows [r0, r0 + nr) and [c0, c0 + nc) (each <= 32) of entry E over
-// k < K, as 2 x 2 MFMA blocks of 16 x 16.  Lane (li, lk) supplies k values 8 lk .. 8 lk + 7
-// of each 32-chunk (one bf16 MFMA; for the 16x16x4 FP32 / FP64 MFMAs, step u takes k =
-// 8 lk + u, the same permutation of k on both operands).
+// A wave's share of one entry: rows [r0, r0 + nr) and [c0, c0 + nc) (each <= 32) of the
+// entry's operand, k < K.
+struct WaveWork {
+  UpdEntry E;
+  int r0, nr, c0, nc, K;
+};
+
+// Operand registers of one 32-column chunk of a wave's product.  Lane (li, lk) holds k
+// values 8 lk .. 8 lk + 7 of rows li and 16 + li (one bf16 MFMA takes them at once; for
+// the 16x16x4 FP32 / FP64 MFMAs, step u takes k = 8 lk + u, the same permutation of k on
+// both operands).
+template <int MODE> struct WaveOps;
+template <> struct WaveOps<sF64> { double a[2][8], b[2][8]; };
+template <> struct WaveOps<sF32> { v4f a[2][2], b[2][2]; };
+template <> struct WaveOps<sBF16x3> { v8bf ah[2], al[2], bh[2], bl[2]; };
+
+// Vector-memory instructions issued by one wave_load.
+template <int MODE> constexpr int kWaveLoads = MODE == sF64 ? 16 : 8;
+
+// Waits until at most N vector-memory loads of the wave are outstanding (expcnt and
+// lgkmcnt fields at their maxima, so only vmcnt is waited on).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N < 64, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// Relative-map entries (target positions) of a wave's result rows and columns.
+struct WaveMaps {
+  int r[2][4], c[2];
+};
+
+// Rows past nr (nc) are loaded from row nr - 1 (nc - 1): in-bounds, unconditional loads
+// that need no select before their use, and whose products land only in result rows or
+// columns that the scatter skips.  Columns past K within the chunk are zero in the copy.
+// Operand rows ia .. ia + na - 1 and ib .. ib + nb - 1 of the compact copy at double
+// offset xo (row length ldx elements), columns k0 .. k0 + 31.
 template <int MODE>
-__device__ __forceinline__ void wave_entry(typename Acc<MODE>::T (&acc)[2][2], const UpdEntry& E,
-                                           const double* __restrict__ xbase, int r0, int nr, int c0,
-                                           int nc, int K, int lane) {
+__device__ __forceinline__ void wave_load(WaveOps<MODE>& o, const double* __restrict__ xbase, int64_t xo, int ldx,
+                                          int ia, int na, int ib, int nb, int k0, int lane) {
   const int li = lane & 15, lk = lane >> 4;
-  const int br = (nr + 15) >> 4, bc = (nc + 15) >> 4;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 2; ++x) {
+    const int i = 16 * x + li;
+    const int64_t ra = (int64_t)(ia + min(i, na - 1)) * ldx;
+    const int64_t rb = (int64_t)(ib + min(i, nb - 1)) * ldx;
+    if constexpr (MODE == sF64) {
+      const double* pa = xbase + xo + ra + k0 + 8 * lk;
+      const double* pb = xbase + xo + rb + k0 + 8 * lk;
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[x][y][e] = 0;
-  if constexpr (MODE == sF64) {
-    const double* XA = xbase + E.x + E.a + r0;
-    const double* XB = xbase + E.x + E.c + c0;
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      double va[2][8], vb[2][8];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const int i = 16 * x + li;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int k = k0 + 8 * lk + u;
-          va[x][u] = (x < br && i < nr && k < K) ? XA[i + (int64_t)k * E.ldx] : 0.0;
-          vb[x][u] = (x < bc && i < nc && k < K) ? XB[i + (int64_t)k * E.ldx] : 0.0;
-        }
+      for (int h = 0; h < 4; ++h) {
+        const double2 za = *reinterpret_cast<const double2*>(pa + 2 * h);
+        const double2 zb = *reinterpret_cast<const double2*>(pb + 2 * h);
+        o.a[x][2 * h] = za.x; o.a[x][2 * h + 1] = za.y;
+        o.b[x][2 * h] = zb.x; o.b[x][2 * h + 1] = zb.y;
       }
+    } else if constexpr (MODE == sF32) {
+      const float* X = reinterpret_cast<const float*>(xbase + xo);
+      const float* pa = X + ra + k0 + 8 * lk;
+      const float* pb = X + rb + k0 + 8 * lk;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-            if (x < br && y < bc) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[x][u], vb[y][u], acc[x][y], 0, 0, 0);
-    }
-  } else if constexpr (MODE == sF32) {
-    const float* X = reinterpret_cast<const float*>(xbase + E.x);
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      v4f a[2][2], b[2][2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const int i = 16 * x + li;
-        const float* pa = X + (int64_t)(E.a + r0 + i) * E.ldx + k0 + 8 * lk;
-        const float* pb = X + (int64_t)(E.c + c0 + i) * E.ldx + k0 + 8 * lk;
-        const bool oa = x < br && i < nr, ob = x < bc && i < nc;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          a[x][h] = oa ? *reinterpret_cast<const v4f*>(pa + 4 * h) : v4f{0, 0, 0, 0};
-          b[x][h] = ob ? *reinterpret_cast<const v4f*>(pb + 4 * h) : v4f{0, 0, 0, 0};
-        }
+      for (int h = 0; h < 2; ++h) {
+        o.a[x][h] = *reinterpret_cast<const v4f*>(pa + 4 * h);
+        o.b[x][h] = *reinterpret_cast<const v4f*>(pb + 4 * h);
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-            if (x < br && y < bc)
-              acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][u >> 2][u & 3], b[y][u >> 2][u & 3], acc[x][y], 0, 0, 0);
-    }
-  } else {
-    const __bf16* X = reinterpret_cast<const __bf16*>(xbase + E.x);
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      v8bf ah[2], al[2], bh[2], bl[2];
-      const v8bf z = {};
-#pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const int i = 16 * x + li;
-        const __bf16* pa = X + (int64_t)(E.a + r0 + i) * E.ldx + 2 * k0 + 8 * lk;
-        const __bf16* pb = X + (int64_t)(E.c + c0 + i) * E.ldx + 2 * k0 + 8 * lk;
-        const bool oa = x < br && i < nr, ob = x < bc && i < nc;
-        ah[x] = oa ? *reinterpret_cast<const v8bf*>(pa) : z;
-        al[x] = oa ? *reinterpret_cast<const v8bf*>(pa + KC) : z;
-        bh[x] = ob ? *reinterpret_cast<const v8bf*>(pb) : z;
-        bl[x] = ob ? *reinterpret_cast<const v8bf*>(pb + KC) : z;
-      }
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-          if (x < br && y < bc) {
-            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
-            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
-            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
-          }
+    } else {
+      const __bf16* X = reinterpret_cast<const __bf16*>(xbase + xo);
+      const __bf16* pa = X + ra + 2 * k0 + 8 * lk;
+      const __bf16* pb = X + rb + 2 * k0 + 8 * lk;
+      o.ah[x] = *reinterpret_cast<const v8bf*>(pa);
+      o.al[x] = *reinterpret_cast<const v8bf*>(pa + KC);
+      o.bh[x] = *reinterpret_cast<const v8bf*>(pb);
+      o.bl[x] = *reinterpret_cast<const v8bf*>(pb + KC);
     }
   }
 }
 
-// Subtracts a wave's block (rows r0.., columns c0.. of entry E) from the LDS tile through
-// the relative map (target positions prm / pcm read before the product).
+template <int MODE>
+__device__ __forceinline__ void wave_mma(typename Acc<MODE>::T (&acc)[2][2], const WaveOps<MODE>& o, int br,
+                                         int bc) {
+  if constexpr (MODE == sF64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          if (x < br && y < bc) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[x][u], o.b[y][u], acc[x][y], 0, 0, 0);
+  } else if constexpr (MODE == sF32) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          if (x < br && y < bc)
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[x][u >> 2][u & 3], o.b[y][u >> 2][u & 3], acc[x][y], 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        if (x < br && y < bc) {
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.al[x], o.bh[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.ah[x], o.bl[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.ah[x], o.bh[y], acc[x][y], 0, 0, 0);
+        }
+  }
+}
+
+// Raw relative-map entries of a wave's result rows and columns (clamped like wave_load).
+template <int MODE>
+__device__ __forceinline__ void wave_maps(const int32_t* __restrict__ relmap, const WaveWork& W, int lane,
+                                          WaveMaps& m) {
+  const int32_t* rm = relmap + W.E.map;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int ii, jj;
+      res_pos<MODE>(lane, e, ii, jj);
+      m.r[x][e] = rm[W.E.a + W.r0 + min(16 * x + ii, W.nr - 1)];
+    }
+#pragma unroll
+  for (int y = 0; y < 2; ++y) m.c[y] = rm[W.E.c + W.c0 + min(16 * y + (lane & 15), W.nc - 1)];
+}
+
+// Subtracts a wave's block from the LDS tile at the target positions kept in the wave's
+// LDS slot (entry k of lane l at slot[64 k + l]).
 template <int MODE>
 __device__ __forceinline__ void wave_scatter(double* tile, const typename Acc<MODE>::T (&acc)[2][2],
-                                             const int (&prm)[2][4], const int (&pcm)[2], int nr, int nc,
-                                             int lane) {
+                                             const int* slot, const UpdTile& T, int nr, int nc, int lane) {
+  int pr[2][4], pc[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pr[x][e] = slot[64 * (4 * x + e) + lane] - T.row0;
+#pragma unroll
+  for (int y = 0; y < 2; ++y) pc[y] = slot[64 * (8 + y) + lane] - T.col0;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -531,37 +580,24 @@ __device__ __forceinline__ void wave_scatter(double* tile, const typename Acc<MO
       for (int e = 0; e < 4; ++e) {
         int ii, jj;
         res_pos<MODE>(lane, e, ii, jj);
-        if (16 * x + ii < nr && 16 * y + jj < nc) tile[prm[x][e] + 65 * pcm[y]] -= (double)acc[x][y][e];
+        if (16 * x + ii < nr && 16 * y + jj < nc) tile[pr[x][e] + 65 * pc[y]] -= (double)acc[x][y][e];
       }
 }
 
-template <int MODE>
-__device__ __forceinline__ void wave_maps(const int32_t* __restrict__ rm, const UpdTile& T, const UpdEntry& E,
-                                          int r0, int nr, int c0, int nc, int lane, int (&prm)[2][4],
-                                          int (&pcm)[2]) {
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int ii, jj;
-      res_pos<MODE>(lane, e, ii, jj);
-      const int i = 16 * x + ii;
-      prm[x][e] = i < nr ? rm[E.a + r0 + i] - T.row0 : 0;
-    }
-#pragma unroll
-  for (int y = 0; y < 2; ++y) {
-    const int j = 16 * y + (lane & 15);
-    pcm[y] = j < nc ? rm[E.c + c0 + j] - T.col0 : 0;
-  }
-}
-
 // Schur-complement update of one 64 x 64 target tile per workgroup (the tile stays in
-// LDS): entries [e0, es) are wider than 32 in some direction -- the four waves take the
-// four 32 x 32 quadrants of one entry, whose target positions are disjoint; entries
-// [es, e1) are at most 32 x 32 -- the waves take four entries at a time and subtract
-// them in wave order, one barrier apart.  Each wave's product runs from registers with
-// no LDS staging, so four entries' loads are in flight per workgroup; the summation
-// order is fixed by the entry list, so the result does not depend on scheduling.
+// LDS).  The tile's entries form groups: each entry of [e0, es) (wider than 32 in some
+// direction) is one group, whose four 32 x 32 quadrants go to the four waves (their
+// target positions are disjoint); the entries of [es, e1) (at most 32 x 32) form groups
+// of four, one per wave, subtracted in wave order one barrier apart.  Every wave passes
+// the barriers of all groups in order.  Between them each wave streams its own sequence
+// of (entry, 32-column chunk) steps from registers: a step issues the loads of the next
+// step -- the next chunk, or the first chunk and the target positions of the wave's next
+// entry -- before the MFMAs of its own chunk, so the loads overlap the products, the
+// scatters and the barriers.  The two operand register sets alternate by step (the loop
+// body holds two steps, so no set is copied while its loads are in flight), and the
+// target positions move to an LDS slot of the wave once they have arrived.  The
+// summation order is fixed by the entry list, so the result does not depend on
+// scheduling.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict__ tiles,
                                                       const UpdEntry* __restrict__ ents,
@@ -570,8 +606,11 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
                                                       const double* __restrict__ xbase,
                                                       const int32_t* __restrict__ ilim) {
   __shared__ double tile[64 * 65];
+  __shared__ int maps[4][10 * 64];
   const UpdTile T = tiles[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  int* const slot = maps[w];
   double* P = arena + T.panel;
   {
     // all sixteen loads in flight together (addresses clamped into the tile), then LDS
@@ -587,34 +626,103 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
       tile[r + 65 * c] = (r < T.nrows && c < T.ncols) ? t[u] : 0.0;
     }
   }
-  __syncthreads();
+  const int GL = T.es - T.e0;                     // groups of one large entry
+  const int G = GL + (T.e1 - T.es + 3) / 4;       // then groups of four small entries
+  // this wave's first group at or after g with a non-empty share (G if none), in W
+  auto next_work = [&](int g, WaveWork& W) __attribute__((always_inline)) -> int {
+    for (; g < G; ++g) {
+      int e;
+      if (g < GL) {
+        e = T.e0 + g; W.r0 = 32 * (w >> 1); W.c0 = 32 * (w & 1);
+      } else {
+        e = T.es + 4 * (g - GL) + w; W.r0 = 0; W.c0 = 0;
+        if (e >= T.e1) return G;
+      }
+      W.E = ents[e];
+      W.nr = min(32, W.E.b - W.E.a - W.r0);
+      W.nc = min(32, W.E.d - W.E.c - W.c0);
+      W.K = W.E.kdim >= 0 ? W.E.kdim : ilim[-1 - W.E.kdim];
+      if (((W.nr - 1) | (W.nc - 1) | (W.K - 1)) >= 0) return g;   // all three positive
+    }
+    return G;
+  };
   typename Acc<MODE>::T acc[2][2];
-  int prm[2][4], pcm[2];
-  for (int e = T.e0; e < T.es; ++e) {
-    const UpdEntry E = ents[e];
-    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
-    const int nr = min(32, E.b - E.a - r0), nc = min(32, E.d - E.c - c0);
-    if (nr > 0 && nc > 0) {
-      const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
-      wave_maps<MODE>(relmap + E.map, T, E, r0, nr, c0, nc, lane, prm, pcm);
-      wave_entry<MODE>(acc, E, xbase, r0, nr, c0, nc, K, lane);
-      wave_scatter<MODE>(tile, acc, prm, pcm, nr, nc, lane);
+  // the barriers of groups [g0, g1), scattering this wave's block in group `own`
+  auto groups = [&](int g0, int g1, int own, const WaveWork& W) __attribute__((always_inline)) {
+    for (int g = g0; g < g1; ++g) {
+      if (g < GL) {
+        if (g == own) wave_scatter<MODE>(tile, acc, slot, T, W.nr, W.nc, lane);
+        __syncthreads();
+      } else {
+        for (int t = 0; t < 4; ++t) {
+          if (w == t && g == own) wave_scatter<MODE>(tile, acc, slot, T, W.nr, W.nc, lane);
+          __syncthreads();
+        }
+      }
     }
-    __syncthreads();
+  };
+  WaveOps<MODE> o0, o1;
+  WaveMaps mn;                 // target positions of the next entry, in flight
+  WaveWork W, Wn;
+  int gn = next_work(0, Wn);
+  if (gn < G) {
+    wave_load<MODE>(o0, xbase, Wn.E.x, Wn.E.ldx, Wn.E.a + Wn.r0, Wn.nr, Wn.E.c + Wn.c0, Wn.nc, 0, lane);
+    wave_maps<MODE>(relmap, Wn, lane, mn);
   }
-  for (int e = T.es; e < T.e1; e += 4) {
-    const int my = e + w;
-    int nr = 0, nc = 0;
-    if (my < T.e1) {
-      const UpdEntry E = ents[my];
-      nr = E.b - E.a; nc = E.d - E.c;
-      const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
-      wave_maps<MODE>(relmap + E.map, T, E, 0, nr, 0, nc, lane, prm, pcm);
-      wave_entry<MODE>(acc, E, xbase, 0, nr, 0, nc, K, lane);
+  __syncthreads();             // the tile is in LDS
+  groups(0, gn, -1, Wn);
+  int gw = gn, k0 = 0;
+  W = Wn;
+  // one step on the chunk in `cur`; returns true when the wave has no further work
+  auto step = [&](WaveOps<MODE>& cur, WaveOps<MODE>& nxt) __attribute__((always_inline)) -> bool {
+    const bool last = k0 + KC >= W.K;
+    if (last) gn = next_work(gw + 1, Wn);
+    // the loads themselves are unconditional (with no work left, the current chunk is
+    // read again), so that every path issues the same loads and the waits before the
+    // MFMAs count only the older ones
+    {
+      const bool same = !last || gn >= G;
+      wave_load<MODE>(nxt, xbase, same ? W.E.x : Wn.E.x, same ? W.E.ldx : Wn.E.ldx,
+                      same ? W.E.a + W.r0 : Wn.E.a + Wn.r0, same ? W.nr : Wn.nr,
+                      same ? W.E.c + W.c0 : Wn.E.c + Wn.c0, same ? W.nc : Wn.nc,
+                      last ? (gn < G ? 0 : k0) : k0 + KC, lane);
     }
-    for (int t = 0; t < 4; ++t) {
-      if (w == t && my < T.e1) wave_scatter<MODE>(tile, acc, prm, pcm, nr, nc, lane);
-      __syncthreads();
+    if (k0 == 0) {             // this entry's target positions have arrived: park them
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) slot[64 * (4 * x + e) + lane] = mn.r[x][e];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) slot[64 * (8 + y) + lane] = mn.c[y];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[x][y][e] = 0;
+    }
+    const bool maps_now = last && gn < G;
+    if (maps_now) wave_maps<MODE>(relmap, Wn, lane, mn);
+    wave_mma<MODE>(acc, cur, (W.nr + 15) >> 4, (W.nc + 15) >> 4);
+    // every load older than this step's has arrived, including those of operand blocks
+    // the MFMAs skipped: stated here so that no later register reuse waits on them
+    if (maps_now) wait_vmcnt<kWaveLoads<MODE> + 10>(); else wait_vmcnt<kWaveLoads<MODE>>();
+    if (!last) {
+      k0 += KC;
+      return false;
+    }
+    groups(gw, gn, gw, W);
+    if (gn >= G) {             // the wave is done; its last (repeated) loads are drained
+      wait_vmcnt<0>();         // here, so no wait on them is merged into the loop
+      return true;
+    }
+    W = Wn; gw = gn; k0 = 0;
+    return false;
+  };
+  if (gn < G) {
+    while (true) {
+      if (step(o0, o1)) break;
+      if (step(o1, o0)) break;
     }
   }
   for (int idx = tid; idx < 64 * 64; idx += 256) {
@@ -661,7 +769,8 @@ void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, c
 void launch_compact_rows(int mode, const CompactTask* t, int n, const double* arena, const int32_t* ilim,
                          double* xc, hipStream_t s) {
   if (n <= 0) return;
-  if (mode == sF32) hipLaunchKernelGGL(k_compact_rows<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
+  if (mode == sF64) hipLaunchKernelGGL(k_compact_rows<sF64>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
+  else if (mode == sF32) hipLaunchKernelGGL(k_compact_rows<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
   else hipLaunchKernelGGL(k_compact_rows<sBF16x3>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
 }
 

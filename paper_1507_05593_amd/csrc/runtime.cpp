@@ -395,18 +395,20 @@ struct Builder {
     const Symbolic& S = h.S;
     xc_off.assign(S.M(), -1);
     xc_kp.assign(S.M(), 0);
-    if (lp_update == 0) return;
-    // r x kp FP32 values, or r x kp BF16 pairs: r * kp / 2 doubles either way
+    // r x kp FP64 values (r * kp doubles), or FP32 values or BF16 pairs (r * kp / 2)
     int64_t off = 0;
     for (int64_t j = 0; j < S.M(); ++j) {
       if (S.r(j) == 0) continue;
       const int32_t kmax = (P.compressed && h.compressible[j]) ? h.comp[j].ell : S.c(j);
       xc_kp[j] = (kmax + 31) / 32 * 32;
       xc_off[j] = off;
-      off += ((int64_t)S.r(j) * xc_kp[j] / 2 + 31) / 32 * 32;
+      off += ((int64_t)S.r(j) * xc_row(j) + 31) / 32 * 32;
     }
     P.xc_size = off;
   }
+
+  // doubles per row of supernode j's compact operand copy
+  int64_t xc_row(int64_t j) const { return lp_update == 0 ? xc_kp[j] : xc_kp[j] / 2; }
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
            int64_t b = 0, double v = 0) {
@@ -625,21 +627,16 @@ struct Builder {
         UpdEntry base{};
         double kest;
         if (P.compressed && h.compressible[k]) {
-          const CompSlot& C = h.comp[k];
-          base.x = C.Vj + pr.p0;
-          base.ldx = S.r(k);
-          base.kdim = -(1 + C.qslot);
-          kest = C.ell;
+          base.kdim = -(1 + h.comp[k].qslot);
+          kest = h.comp[k].ell;
         } else {
-          base.x = h.a_lo + h.lo_off[k] + pr.p0;
-          base.ldx = S.r(k);
           base.kdim = S.c(k);
           kest = S.c(k);
         }
-        if (lp_update != 0) {            // the compact copy, shifted to the pair's rows
-          base.x = xc_off[k] + (int64_t)pr.p0 * xc_kp[k] / 2;
-          base.ldx = (lp_update == 2 ? 2 : 1) * xc_kp[k];
-        }
+        // the compact copy of V_k or L^O_k, shifted to the pair's rows (ldx in the copy's
+        // element type)
+        base.x = xc_off[k] + (int64_t)pr.p0 * xc_row(k);
+        base.ldx = (lp_update == 2 ? 2 : 1) * xc_kp[k];
         base.map = pr.map_off;
         const int32_t* rm = S.relmap.data() + pr.map_off;
         // runs of gathered rows per 64-row tile (relmap is increasing)
@@ -719,9 +716,8 @@ struct Builder {
   }
 
   // Compact row-major copies of the Schur-update operands of a level once they are
-  // final (mixed forms): L^O_j of the supernodes kept explicit, V_j of the compressed.
+  // final: L^O_j of the supernodes kept explicit, V_j of the compressed.
   void compact_operands(const std::vector<int32_t>& level, bool compressed_ones) {
-    if (lp_update == 0) return;
     const Symbolic& S = h.S;
     const int64_t c0 = (int64_t)P.compact.size();
     for (int32_t j : level) {
@@ -732,7 +728,7 @@ struct Builder {
       for (int32_t r0 = 0; r0 < r; r0 += kTile) {
         CompactTask t{};
         t.src = (comp ? h.comp[j].Vj : h.a_lo + h.lo_off[j]) + r0;
-        t.dst = xc_off[j] + (int64_t)r0 * xc_kp[j] / 2;
+        t.dst = xc_off[j] + (int64_t)r0 * xc_row(j);
         t.ld = r;
         t.nrows = std::min(kTile, r - r0);
         t.kdim = comp ? -(1 + h.comp[j].qslot) : S.c(j);
@@ -1179,7 +1175,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdIdent: launch_scatter_const(h.d_ident_slot.p, c.count, 1.0, A, s); break;
     case kCmdUpdate:
       launch_update_waves((int)c.a, P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A,
-                          c.a ? P->d_xc.p : A, I, s);
+                          P->d_xc.p, I, s);
       break;
     case kCmdCompact:
       launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p, s);

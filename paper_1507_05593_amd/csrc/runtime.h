@@ -91,7 +91,7 @@ struct FactorPlan {
   std::vector<UpdTile> tiles;
   std::vector<UpdEntry> ents;
   std::vector<CompactTask> compact;
-  int64_t xc_size = 0;                // compact operand copies (doubles; mixed forms)
+  int64_t xc_size = 0;                // compact operand copies (doubles)
   int64_t split_size = 0;             // partial tiles of the largest split-K product (doubles)
   std::vector<PotrfTask> potrf;
   std::vector<PhiloxTask> philox;
@@ -102,7 +102,7 @@ struct FactorPlan {
   DevArray<UpdTile> d_tiles;
   DevArray<UpdEntry> d_ents;
   DevArray<CompactTask> d_compact;
-  DevArray<double> d_xc;              // compact row-major Schur-update operands (mixed forms)
+  DevArray<double> d_xc;              // compact row-major Schur-update operands
   DevArray<double> d_split;           // K-slice partial tiles (reused by every split product)
   DevArray<PotrfTask> d_potrf;
   DevArray<PhiloxTask> d_philox;

@@ -43,11 +43,11 @@ struct UpdTile {
 };
 
 // One descendant's contribution to one target tile: rows [a,b) and [c,d) of the
-// gathered operand X (X(t, m) = arena[x + t + m*ldx]); the target position of
-// gathered row t is relmap[map + t] (panel-local row; as a column index when t < nD).
-//   Mixed forms: X is the compact row-major copy, X(t, m) at element t * ldx + m (FP32) or
-//   t * ldx + 2 * (m / 32) * 32 + m % 32 (BF16 high part; low part 32 further), counted
-//   from the double offset x of the operand's compact copy, shifted to the pair's rows.
+// gathered operand X; the target position of gathered row t is relmap[map + t]
+// (panel-local row; as a column index when t < nD).  X is the compact row-major copy,
+// X(t, m) at element t * ldx + m (FP64 or FP32) or t * ldx + 2 * (m / 32) * 32 + m % 32
+// (BF16 high part; low part 32 further), counted from the double offset x of the
+// operand's compact copy, shifted to the pair's rows.
 struct UpdEntry {
   int64_t x;
   int64_t map;
