@@ -560,18 +560,24 @@ __device__ __forceinline__ void wave_maps(const int32_t* __restrict__ relmap, co
   for (int y = 0; y < 2; ++y) m.c[y] = rm[W.E.c + W.c0 + min(16 * y + (lane & 15), W.nc - 1)];
 }
 
-// Subtracts a wave's block from the LDS tile at the target positions kept in the wave's
-// LDS slot (entry k of lane l at slot[64 k + l]).
+// Subtracts a wave's block from the LDS tile at the tile-local target positions kept in
+// the wave's LDS slot: one byte each, rows r[x][0..3] in word x and columns c[0], c[1] in
+// word 2 of lane l (word k at slot[64 k + l]).
 template <int MODE>
 __device__ __forceinline__ void wave_scatter(double* tile, const typename Acc<MODE>::T (&acc)[2][2],
-                                             const int* slot, const UpdTile& T, int nr, int nc, int lane) {
+                                             const uint32_t* slot, int nr, int nc, int lane) {
   int pr[2][4], pc[2];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < 2; ++x) {
+    const uint32_t v = slot[64 * x + lane];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) pr[x][e] = slot[64 * (4 * x + e) + lane] - T.row0;
-#pragma unroll
-  for (int y = 0; y < 2; ++y) pc[y] = slot[64 * (8 + y) + lane] - T.col0;
+    for (int e = 0; e < 4; ++e) pr[x][e] = (v >> (8 * e)) & 255;
+  }
+  {
+    const uint32_t v = slot[128 + lane];
+    pc[0] = v & 255;
+    pc[1] = (v >> 8) & 255;
+  }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -595,9 +601,9 @@ __device__ __forceinline__ void wave_scatter(double* tile, const typename Acc<MO
 // entry -- before the MFMAs of its own chunk, so the loads overlap the products, the
 // scatters and the barriers.  The two operand register sets alternate by step (the loop
 // body holds two steps, so no set is copied while its loads are in flight), and the
-// target positions move to an LDS slot of the wave once they have arrived.  The
-// summation order is fixed by the entry list, so the result does not depend on
-// scheduling.
+// target positions move to an LDS slot of the wave once they have arrived (as bytes,
+// so that four workgroups fit in a compute unit's LDS).  The summation order is fixed
+// by the entry list, so the result does not depend on scheduling.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict__ tiles,
                                                       const UpdEntry* __restrict__ ents,
@@ -606,11 +612,11 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
                                                       const double* __restrict__ xbase,
                                                       const int32_t* __restrict__ ilim) {
   __shared__ double tile[64 * 65];
-  __shared__ int maps[4][10 * 64];
+  __shared__ uint32_t maps[4][3 * 64];
   const UpdTile T = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  int* const slot = maps[w];
+  uint32_t* const slot = maps[w];
   double* P = arena + T.panel;
   {
     // all sixteen loads in flight together (addresses clamped into the tile), then LDS
@@ -651,11 +657,11 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
   auto groups = [&](int g0, int g1, int own, const WaveWork& W) __attribute__((always_inline)) {
     for (int g = g0; g < g1; ++g) {
       if (g < GL) {
-        if (g == own) wave_scatter<MODE>(tile, acc, slot, T, W.nr, W.nc, lane);
+        if (g == own) wave_scatter<MODE>(tile, acc, slot, W.nr, W.nc, lane);
         __syncthreads();
       } else {
         for (int t = 0; t < 4; ++t) {
-          if (w == t && g == own) wave_scatter<MODE>(tile, acc, slot, T, W.nr, W.nc, lane);
+          if (w == t && g == own) wave_scatter<MODE>(tile, acc, slot, W.nr, W.nc, lane);
           __syncthreads();
         }
       }
@@ -688,12 +694,15 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
                       last ? (gn < G ? 0 : k0) : k0 + KC, lane);
     }
     if (k0 == 0) {             // this entry's target positions have arrived: park them
+      // tile-local positions lie in [0, 64): one byte each
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < 2; ++x) {
+        uint32_t v = 0;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) slot[64 * (4 * x + e) + lane] = mn.r[x][e];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) slot[64 * (8 + y) + lane] = mn.c[y];
+        for (int e = 0; e < 4; ++e) v |= (uint32_t)(mn.r[x][e] - T.row0) << (8 * e);
+        slot[64 * x + lane] = v;
+      }
+      slot[128 + lane] = (uint32_t)(mn.c[0] - T.col0) | ((uint32_t)(mn.c[1] - T.col0) << 8);
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
