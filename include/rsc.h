@@ -50,9 +50,11 @@ enum {
   RSC_FP64 = 0,        /* every product in FP64 on MFMA */
   RSC_MIXED_BF16 = 1,  /* Schur-update and TRSM products as split BF16 (hi+lo, three BF16 MFMA
                           products, FP32 accumulation), sampling products in plain BF16 with FP32
-                          accumulation; POTRF, orthonormalisation, projection and PCG in FP64 */
+                          accumulation; POTRF, orthonormalisation, projection and PCG in FP64;
+                          the preconditioner's sweeps read an FP32 copy of the factor (FP64
+                          vectors and sums) */
   RSC_MIXED_FP32 = 2   /* Schur-update and TRSM products with FP32 operands and FP32 accumulation
-                          on MFMA, sampling in BF16; the rest FP64 */
+                          on MFMA, sampling in BF16, sweeps as for RSC_MIXED_BF16; the rest FP64 */
 };
 
 typedef struct {
@@ -91,7 +93,8 @@ typedef struct {
   int32_t retries;             /* refactorisations done by the retry policy */
   int32_t reserved;
   double flops_potrf, flops_trsm, flops_update, flops_sample, flops_orth, flops_trunc;
-  double bytes_factor;         /* bytes of the stored factor read by one preconditioner apply */
+  double bytes_factor;         /* bytes of the stored factor read by one preconditioner apply
+                                  (FP32 entries after a mixed-precision factorization) */
   double t_analyze_ms;         /* host symbolic time */
   double t_factor_ms;          /* device time of the last rsc_factor (hipEvents) */
   double t_pcg_ms;             /* device time of the last rsc_pcg */
@@ -199,7 +202,7 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
  * depend on the kept ranks are counted at the ranks of the factorisation that ran).
  * Any output may be NULL.  Errors: RSC_ERR_INVALID_ARG for a null handle or k out of
  * range. */
-#define RSC_KERNELS 34
+#define RSC_KERNELS 35
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops);
 

@@ -272,6 +272,7 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
   out->t_factor_ms = h.t_factor_ms;
   out->t_pcg_ms = h.t_pcg_ms;
   out->device_bytes = 8.0 * (double)h.arena_size + 4.0 * (double)h.ints_size;
+  out->device_bytes += 4.0 * (double)h.arena32.n;
   if (h.fplan) {
     out->device_bytes += 8.0 * (double)h.fplan->d_xc.n;
     out->gemm_tuned = h.fplan->tuned;
@@ -309,7 +310,7 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
     out->flops_trunc = h.fplan->flops[5];
   }
   out->flops_update = fl_update;
-  out->bytes_factor = h.splan ? h.splan->bytes : 0.0;
+  out->bytes_factor = h.splan ? h.splan->bytes * (h.f32_valid ? 0.5 : 1.0) : 0.0;
   return RSC_OK;
 }
 

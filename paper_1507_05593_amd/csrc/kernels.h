@@ -28,15 +28,19 @@ void launch_trunc_mfill(const TruncTask* t, int n, double* arena, hipStream_t s)
 void launch_trunc_flags(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s);
 void launch_trunc_copy(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s);
 
-void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s);
+// sweep kernels: f32 = FP32 copy of the factor operands (mixed forms), or null (arena)
+void launch_gemv_n(const GemvTask* t, int n, double* arena, const float* f32, const int32_t* ilim,
+                   hipStream_t s);
 void launch_fwd_part(const FwdChunk* c, int n, const FwdTile* t, const FwdEntry* e,
-                     const int32_t* relmap, const double* arena, const int32_t* ilim, double* part,
+                     const int32_t* relmap, const double* arena, const float* f32, const int32_t* ilim,
+                     double* part, hipStream_t s);
+void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32, double* part,
                      hipStream_t s);
-void launch_row_part(const RowChunk* c, int n, const double* arena, double* part, hipStream_t s);
+void launch_to_f32(const ConvTask* t, int n, const double* arena, float* f32, hipStream_t s);
 void launch_part_apply(const PartApply* t, int n, const double* part, double* arena, hipStream_t s);
 void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const double* src,
                         double* dst, hipStream_t s);
-void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
+void launch_coldot(const ColDotTask* t, int n, double* arena, const float* f32, const int64_t* gidx,
                    const int32_t* ilim, double* part, hipStream_t s);
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s);

@@ -31,11 +31,17 @@ __device__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- sweeps
 
+// The factor operands of the sweeps (L^O_j, U_j, V_j, the inverse diagonal blocks) are
+// read through F: the arena itself (TF = double), or in the mixed forms its FP32 copy at
+// the same offsets (TF = float, written by k_to_f32 once the factorization is complete);
+// the vectors and every sum stay FP64.
+
 // out[t] = sum_{m < K} X(t, m) v[m] for up to 64 rows: lane = row (coalesced column
 // reads), the 4 waves split the inner dimension and their partial sums are added in
 // a fixed order.
+template <typename TF>
 __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tasks,
-                                                double* __restrict__ arena,
+                                                double* __restrict__ arena, const TF* __restrict__ F,
                                                 const int32_t* __restrict__ ilim) {
   __shared__ double part[4][64];
   const GemvTask T = tasks[blockIdx.x];
@@ -45,10 +51,10 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
   if (lane < T.rows) {
     const int per = (K + 3) / 4;
     const int m0 = w * per, m1 = min(K, m0 + per);
-    const double* X = arena + T.x + lane;
+    const TF* X = F + T.x + lane;
     const double* v = arena + T.v;
 #pragma unroll 8
-    for (int m = m0; m < m1; ++m) acc += X[(int64_t)m * T.ldx] * v[m];
+    for (int m = m0; m < m1; ++m) acc += (double)X[(int64_t)m * T.ldx] * v[m];
   }
   part[w][lane] = acc;
   __syncthreads();
@@ -65,11 +71,12 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
 // then added by a fixed butterfly.  A large entry is planned as several pieces over
 // column ranges, so that no chunk is much longer than the level's average.
 // k_part_apply subtracts the block's partials from y.
+template <typename TF>
 __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ chunks,
                                                   const FwdTile* __restrict__ tiles,
                                                   const FwdEntry* __restrict__ ents,
                                                   const int32_t* __restrict__ relmap,
-                                                  const double* __restrict__ arena,
+                                                  const double* __restrict__ arena, const TF* __restrict__ F,
                                                   const int32_t* __restrict__ ilim,
                                                   double* __restrict__ part) {
   __shared__ double acc[4][64];
@@ -87,10 +94,10 @@ __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ c
     double s = 0.0;
     const int me = min(K, E.m0 + E.kspan);
     if (row < nr) {
-      const double* X = arena + E.x + E.a + row;
+      const TF* X = F + E.x + E.a + row;
       const double* v = arena + E.v;
 #pragma unroll 8
-      for (int m = E.m0 + g; m < me; m += G) s += X[(int64_t)m * E.ldx] * v[m];
+      for (int m = E.m0 + g; m < me; m += G) s += (double)X[(int64_t)m * E.ldx] * v[m];
     }
     for (int o = P; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
     if (g == 0 && row < nr) acc[w][relmap[E.map + E.a + row] - T.row0] += s;
@@ -105,8 +112,9 @@ __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ c
 // Backward diagonal solve chunk: rows i in [i0, i0 + 64) (lanes) of M (w - s) over the
 // columns [t0, t1); v = w - s is staged in LDS, the four waves take consecutive column
 // quarters, and their sums are added in a fixed order into one partial block.
+template <typename TF>
 __global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ chunks,
-                                                  const double* __restrict__ arena,
+                                                  const double* __restrict__ arena, const TF* __restrict__ F,
                                                   double* __restrict__ part) {
   __shared__ double v[kRowChunkMax];
   __shared__ double red[4][64];
@@ -123,9 +131,9 @@ __global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ c
   if (i < T.c) {
     const int per = (n + 3) / 4;
     const int ta = T.t0 + w * per, tb = min(T.t1, ta + per);
-    const double* M = arena + T.m + i;
+    const TF* M = F + T.m + i;
 #pragma unroll 8
-    for (int t = max(ta, i); t < tb; ++t) acc += M[(int64_t)t * T.ld] * v[t - T.t0];
+    for (int t = max(ta, i); t < tb; ++t) acc += (double)M[(int64_t)t * T.ld] * v[t - T.t0];
   }
   red[w][lane] = acc;
   __syncthreads();
@@ -157,8 +165,9 @@ __global__ void k_gather_rows(const int64_t* __restrict__ tasks, const int64_t* 
 // one per 16-lane group, the group's lanes striding the rows (one 128-byte line per
 // group and load, unrolled so several loads are in flight); then a fixed butterfly
 // within each group.  Short columns (the many small supernodes) keep most lanes busy.
+template <typename TF>
 __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ tasks,
-                                                double* __restrict__ arena,
+                                                double* __restrict__ arena, const TF* __restrict__ F,
                                                 const int64_t* __restrict__ gidx,
                                                 const int32_t* __restrict__ ilim,
                                                 double* __restrict__ part) {
@@ -171,14 +180,14 @@ __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ t
   double acc = 0.0;
   if (col < ncols) {
     const int rows = min(T.tri ? col + 1 : T.rows, T.r1);
-    const double* X = arena + T.x + (int64_t)col * T.ldx;
+    const TF* X = F + T.x + (int64_t)col * T.ldx;
     if (T.idx >= 0) {
       const int64_t* ix = gidx + T.idx;
 #pragma unroll 8
-      for (int t = T.r0 + r; t < rows; t += 16) acc += X[t] * in[ix[t]];
+      for (int t = T.r0 + r; t < rows; t += 16) acc += (double)X[t] * in[ix[t]];
     } else {
 #pragma unroll 8
-      for (int t = T.r0 + r; t < rows; t += 16) acc += X[t] * in[t];
+      for (int t = T.r0 + r; t < rows; t += 16) acc += (double)X[t] * in[t];
     }
   }
   for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -409,16 +418,41 @@ __global__ void k_grad_faces(int64_t nf, const int32_t* __restrict__ fi,
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-void launch_gemv_n(const GemvTask* t, int n, double* arena, const int32_t* ilim, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_gemv_n, dim3(n), dim3(256), 0, s, t, arena, ilim);
+void launch_gemv_n(const GemvTask* t, int n, double* arena, const float* f32, const int32_t* ilim,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) hipLaunchKernelGGL(k_gemv_n<float>, dim3(n), dim3(256), 0, s, t, arena, f32, ilim);
+  else hipLaunchKernelGGL(k_gemv_n<double>, dim3(n), dim3(256), 0, s, t, arena, (const double*)arena, ilim);
 }
 void launch_fwd_part(const FwdChunk* c, int n, const FwdTile* t, const FwdEntry* e,
-                     const int32_t* relmap, const double* arena, const int32_t* ilim, double* part,
-                     hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_fwd_part, dim3(n), dim3(256), 0, s, c, t, e, relmap, arena, ilim, part);
+                     const int32_t* relmap, const double* arena, const float* f32, const int32_t* ilim,
+                     double* part, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) hipLaunchKernelGGL(k_fwd_part<float>, dim3(n), dim3(256), 0, s, c, t, e, relmap, arena, f32, ilim, part);
+  else hipLaunchKernelGGL(k_fwd_part<double>, dim3(n), dim3(256), 0, s, c, t, e, relmap, arena, arena, ilim, part);
 }
-void launch_row_part(const RowChunk* c, int n, const double* arena, double* part, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_row_part, dim3(n), dim3(256), 0, s, c, arena, part);
+void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32, double* part,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) hipLaunchKernelGGL(k_row_part<float>, dim3(n), dim3(256), 0, s, c, arena, f32, part);
+  else hipLaunchKernelGGL(k_row_part<double>, dim3(n), dim3(256), 0, s, c, arena, arena, part);
+}
+
+// FP32 copy of the factor operands the sweeps read, at the arena's offsets: one task per
+// block of at most 64 columns and kConvRows rows (see ConvTask).
+__global__ __launch_bounds__(256) void k_to_f32(const ConvTask* __restrict__ tasks,
+                                                const double* __restrict__ arena,
+                                                float* __restrict__ f32) {
+  const ConvTask T = tasks[blockIdx.x];
+  const int n = T.rows * T.cols;            // <= 64 * kConvRows: every thread busy on small blocks
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const int c = e / T.rows, t = e - c * T.rows;
+    const int64_t o = T.off + (int64_t)c * T.ld + t;
+    f32[o] = (float)arena[o];
+  }
+}
+void launch_to_f32(const ConvTask* t, int n, const double* arena, float* f32, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(n), dim3(256), 0, s, t, arena, f32);
 }
 void launch_part_apply(const PartApply* t, int n, const double* part, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_part_apply, dim3(n), dim3(64), 0, s, t, part, arena);
@@ -427,9 +461,11 @@ void launch_gather_rows(const int64_t* tasks, int n, const int64_t* idx, const d
                         double* dst, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gather_rows, dim3(n), dim3(256), 0, s, tasks, idx, src, dst);
 }
-void launch_coldot(const ColDotTask* t, int n, double* arena, const int64_t* gidx,
+void launch_coldot(const ColDotTask* t, int n, double* arena, const float* f32, const int64_t* gidx,
                    const int32_t* ilim, double* part, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_coldot, dim3(n), dim3(256), 0, s, t, arena, gidx, ilim, part);
+  if (n <= 0) return;
+  if (f32) hipLaunchKernelGGL(k_coldot<float>, dim3(n), dim3(256), 0, s, t, arena, f32, gidx, ilim, part);
+  else hipLaunchKernelGGL(k_coldot<double>, dim3(n), dim3(256), 0, s, t, arena, (const double*)arena, gidx, ilim, part);
 }
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s) {

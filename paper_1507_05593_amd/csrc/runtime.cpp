@@ -739,6 +739,33 @@ struct Builder {
     cmd(kCmdCompact, RSC_K_UPDATE, c0, (int64_t)P.compact.size() - c0, 0.0, lp_update);
   }
 
+  // FP32 copy (mixed forms) of every factor operand the two sweeps of the preconditioner
+  // read, at the arena's offsets: the inverse diagonal blocks M_j, and L^O_j or
+  // (U_j, V_j); blocks of at most 64 columns and kConvRows rows.
+  void f32_copy() {
+    const Symbolic& S = h.S;
+    const int64_t c0 = (int64_t)P.conv.size();
+    auto add = [&](int64_t off, int32_t rows, int32_t cols, int32_t ld) {
+      for (int32_t j0 = 0; j0 < cols; j0 += 64)
+        for (int32_t i0 = 0; i0 < rows; i0 += kConvRows)
+          P.conv.push_back(ConvTask{off + i0 + (int64_t)j0 * ld, std::min(kConvRows, rows - i0),
+                                    std::min(64, cols - j0), ld, 0});
+    };
+    for (int64_t j = 0; j < S.M(); ++j) {
+      const int32_t c = S.c(j), r = S.r(j);
+      add(h.a_panels + h.panel_off[j] + c + r, c, c, h.panel_ld[j]);
+      if (r == 0) continue;
+      if (P.compressed && h.compressible[j]) {
+        const CompSlot& C = h.comp[j];
+        add(C.Uj, c, C.ell, c);
+        add(C.Vj, r, C.ell, r);
+      } else {
+        add(h.a_lo + h.lo_off[j], r, c, r);
+      }
+    }
+    cmd(kCmdToF32, RSC_K_OTHER, c0, (int64_t)P.conv.size() - c0, 0.0, 0);
+  }
+
   // Algorithm 3 on the explicit L^O_j of every compressible supernode of a level,
   // followed by the spectral truncation.
   void compression(const std::vector<int32_t>& level, double tol) {
@@ -1051,6 +1078,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
       B.compact_operands(lev, true);
     }
   }
+  if (precision != RSC_FP64) B.f32_copy();
   // algorithmic flop counts of the method (per supernode, from the symbolic plan)
   for (int64_t j = 0; j < S.M(); ++j) {
     const double c = S.c(j), r = S.r(j);
@@ -1085,6 +1113,12 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gs_out, P->gs_out)).code) return e;
   if ((e = upload(P->d_gs_ld, P->gs_ld)).code) return e;
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
+  if ((e = upload(P->d_conv, P->conv)).code) return e;
+  if (!P->conv.empty() && !h.arena32.p) {
+    h.arena32.p = static_cast<float*>(dev_alloc(sizeof(float) * (size_t)h.arena_size));
+    if (!h.arena32.p) return Error{RSC_ERR_OUT_OF_MEMORY, "FP32 copy of the factor operands"};
+    h.arena32.n = h.arena_size;
+  }
   if ((e = tune_tiles(h, *P)).code) return e;
   auto& slot = h.fplans[precision];
   if (slot && slot->graph) (void)hipGraphExecDestroy(slot->graph);
@@ -1131,7 +1165,7 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
     "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
-    "trunc_flags", "trunc_copy"};
+    "trunc_flags", "trunc_copy", "to_f32"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
@@ -1142,6 +1176,7 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
     case kCmdTruncMfill: return 31;
     case kCmdTruncFlags: return 32;
     case kCmdTruncCopy: return 33;
+    case kCmdToF32: return 34;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -1168,6 +1203,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
                        hipStream_t s) {
   double* A = h.arena.p;
   int32_t* I = h.ints.p;
+  const float* F32 = h.f32_valid ? h.arena32.p : nullptr;   // factor operands of the sweeps
   switch (c.type) {
     case kCmdFill: launch_fill(A + c.off, c.count, c.v, s); break;
     case kCmdFillInts: launch_fill_i32(I + c.off, c.count, (int32_t)c.v, s); break;
@@ -1196,13 +1232,14 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncMfill: launch_trunc_mfill(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncFlags: launch_trunc_flags(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
     case kCmdTruncCopy: launch_trunc_copy(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
-    case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, I, s); break;
-    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, h.d_rows.p, I, Q->d_part.p, s); break;
-    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, Q->d_part.p, s); break;
+    case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, F32, I, s); break;
+    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, F32, h.d_rows.p, I, Q->d_part.p, s); break;
+    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, F32, Q->d_part.p, s); break;
     case kCmdFwdPart:
-      launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, I,
-                      Q->d_part.p, s);
+      launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, F32,
+                      I, Q->d_part.p, s);
       break;
+    case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, h.arena32.p, s); break;
     case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, Q->d_part.p, A, s); break;
     case kCmdGatherRows:
       launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);
@@ -1280,6 +1317,19 @@ static Error capture(Handle& h, const std::function<Error(hipStream_t)>& body, h
   return kOk;
 }
 
+// The solve graphs hold the sweep kernels of one factor operand copy (FP64 arena or
+// its FP32 copy): recaptured after a factorization of the other kind.
+static void solve_graph_mode(Handle& h) {
+  SolvePlan* Q = h.splan.get();
+  const int32_t m = h.f32_valid ? 1 : 0;
+  if (!Q || Q->f32_mode == m) return;
+  if (Q->graph_a) (void)hipGraphExecDestroy(Q->graph_a);
+  if (Q->graph_b) (void)hipGraphExecDestroy(Q->graph_b);
+  if (Q->graph_apply) (void)hipGraphExecDestroy(Q->graph_apply);
+  Q->graph_a = Q->graph_b = Q->graph_apply = nullptr;
+  Q->f32_mode = m;
+}
+
 // ------------------------------------------------------------------ factor
 
 static Error factor_once(Handle& h, const double* values, double tol, int32_t precision,
@@ -1297,6 +1347,7 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
   }
   h.fplan = slot.get();
   h.factored = false;
+  h.f32_valid = false;
   h.tol = tol;
   FactorPlan* P = h.fplan;
   hipEvent_t e0, e1;
@@ -1337,6 +1388,7 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
   }
   h.failed_supernode = -1;
   h.precision_used = precision;
+  h.f32_valid = precision != RSC_FP64;
   h.factored = true;
   return kOk;
 }
@@ -1659,6 +1711,7 @@ Error apply_preconditioner(Handle& h, const double* r, double* z, hipStream_t st
   Error e = ensure_solve(h);
   if (e.code) return e;
   HIPCHK(hipMemcpyAsync(h.arena.p + h.a_r, r, sizeof(double) * (size_t)h.S.n, hipMemcpyDeviceToDevice, stream));
+  solve_graph_mode(h);
   if (h.opt.use_graph && !h.profiling) {
     if (!h.splan->graph_apply)
       if ((e = capture(h, [&](hipStream_t s) { return apply_cmds(h, s, nullptr); }, &h.splan->graph_apply)).code)
@@ -1728,6 +1781,7 @@ Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, 
   HIPCHK(hipGetLastError());
 
   const bool graphs = h.opt.use_graph && !h.profiling;
+  solve_graph_mode(h);
   SolvePlan* Q = h.splan.get();
   if (graphs && Q->graph_a && Q->v_rtol != rtol) {
     (void)hipGraphExecDestroy(Q->graph_a);

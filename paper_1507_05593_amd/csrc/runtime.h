@@ -25,6 +25,7 @@ enum CmdType : int32_t {
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
+  kCmdToF32,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -98,6 +99,7 @@ struct FactorPlan {
   std::vector<TruncTask> trunc;
   std::vector<int64_t> gs_g, gs_out;
   std::vector<int32_t> gs_ld, gs_n;
+  std::vector<ConvTask> conv;         // FP32 copy of the sweeps' operands (mixed forms)
   DevArray<GemmTask> d_gemm;
   DevArray<UpdTile> d_tiles;
   DevArray<UpdEntry> d_ents;
@@ -109,6 +111,7 @@ struct FactorPlan {
   DevArray<TruncTask> d_trunc;
   DevArray<int64_t> d_gs_g, d_gs_out;
   DevArray<int32_t> d_gs_ld, d_gs_n;
+  DevArray<ConvTask> d_conv;
   hipGraphExec_t graph = nullptr;
   double flops[6] = {0, 0, 0, 0, 0, 0};  // potrf, trsm, update, sample, orth, trunc
 };
@@ -138,6 +141,7 @@ struct SolvePlan {
   hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
   double bytes = 0;                   // factor bytes read by one apply
   double v_rtol = -1;                 // rtol baked into graph_a
+  int32_t f32_mode = -1;              // factor operand copy the graphs were captured with
 };
 
 struct Handle {
@@ -166,6 +170,9 @@ struct Handle {
   hipStream_t cap_stream = nullptr;   // private stream used for graph capture only
   int64_t arena_size = 0, ints_size = 0;
   DevArray<double> arena;
+  DevArray<float> arena32;            // FP32 copy of the sweeps' factor operands (mixed forms),
+                                      // at the arena's offsets
+  bool f32_valid = false;             // the last factorization was mixed: the sweeps read arena32
   DevArray<int32_t> ints;
   DevArray<int64_t> d_asm_slot, d_ident_slot, d_perm, d_rows, d_rowptr;
   DevArray<int32_t> d_colind, d_relmap;

@@ -155,6 +155,14 @@ struct FwdTile {
 struct FwdChunk {
   int32_t tile, e0, e1, slot;
 };
+// One block of a factor operand to copy to FP32 (rows [0, rows) of columns [0, cols) of
+// the column-major block at arena offset off, column stride ld), at the same offsets.
+constexpr int32_t kConvRows = 4096;
+struct ConvTask {
+  int64_t off;
+  int32_t rows, cols, ld, pad_;
+};
+
 // Backward diagonal solve chunk: rows [i0, i0 + 64) of z_C = M (w_C - s_C) over the
 // columns t in [t0, t1) (M = (L^D)^{-T}, upper triangular, M(i, t) = arena[m + i + t*ld]).
 struct RowChunk {
