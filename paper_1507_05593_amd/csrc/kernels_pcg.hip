@@ -444,11 +444,19 @@ __global__ __launch_bounds__(256) void k_to_f32(const ConvTask* __restrict__ tas
                                                 const double* __restrict__ arena,
                                                 float* __restrict__ f32) {
   const ConvTask T = tasks[blockIdx.x];
-  const int n = T.rows * T.cols;            // <= 64 * kConvRows: every thread busy on small blocks
-  for (int e = threadIdx.x; e < n; e += 256) {
-    const int c = e / T.rows, t = e - c * T.rows;
-    const int64_t o = T.off + (int64_t)c * T.ld + t;
-    f32[o] = (float)arena[o];
+  if (T.rows >= 256) {
+    for (int c = 0; c < T.cols; ++c) {
+      const int64_t o = T.off + (int64_t)c * T.ld;
+#pragma unroll 4
+      for (int t = threadIdx.x; t < T.rows; t += 256) f32[o + t] = (float)arena[o + t];
+    }
+  } else {                                  // short columns: every thread busy
+    const int n = T.rows * T.cols;
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int c = e / T.rows, t = e - c * T.rows;
+      const int64_t o = T.off + (int64_t)c * T.ld + t;
+      f32[o] = (float)arena[o];
+    }
   }
 }
 void launch_to_f32(const ConvTask* t, int n, const double* arena, float* f32, hipStream_t s) {

@@ -745,22 +745,25 @@ struct Builder {
   void f32_copy() {
     const Symbolic& S = h.S;
     const int64_t c0 = (int64_t)P.conv.size();
-    auto add = [&](int64_t off, int32_t rows, int32_t cols, int32_t ld) {
-      for (int32_t j0 = 0; j0 < cols; j0 += 64)
-        for (int32_t i0 = 0; i0 < rows; i0 += kConvRows)
-          P.conv.push_back(ConvTask{off + i0 + (int64_t)j0 * ld, std::min(kConvRows, rows - i0),
+    // upper: only rows above the column block's end (M_j is upper triangular)
+    auto add = [&](int64_t off, int32_t rows, int32_t cols, int32_t ld, bool upper) {
+      for (int32_t j0 = 0; j0 < cols; j0 += 64) {
+        const int32_t rr = upper ? std::min(rows, j0 + 64) : rows;
+        for (int32_t i0 = 0; i0 < rr; i0 += kConvRows)
+          P.conv.push_back(ConvTask{off + i0 + (int64_t)j0 * ld, std::min(kConvRows, rr - i0),
                                     std::min(64, cols - j0), ld, 0});
+      }
     };
     for (int64_t j = 0; j < S.M(); ++j) {
       const int32_t c = S.c(j), r = S.r(j);
-      add(h.a_panels + h.panel_off[j] + c + r, c, c, h.panel_ld[j]);
+      add(h.a_panels + h.panel_off[j] + c + r, c, c, h.panel_ld[j], true);
       if (r == 0) continue;
       if (P.compressed && h.compressible[j]) {
         const CompSlot& C = h.comp[j];
-        add(C.Uj, c, C.ell, c);
-        add(C.Vj, r, C.ell, r);
+        add(C.Uj, c, C.ell, c, false);
+        add(C.Vj, r, C.ell, r, false);
       } else {
-        add(h.a_lo + h.lo_off[j], r, c, r);
+        add(h.a_lo + h.lo_off[j], r, c, r, false);
       }
     }
     cmd(kCmdToF32, RSC_K_OTHER, c0, (int64_t)P.conv.size() - c0, 0.0, 0);
@@ -902,7 +905,18 @@ struct Builder {
     }
     cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
     cmd(kCmdTruncX0, RSC_K_EIG, t0, nt, 0);            // sa = I - 2 theta H
-    for (int it = 0; it < kNewtonSchulzSteps; ++it) {
+    // supernodes with l up to nsmax: every step in one workgroup each (k_trunc_ns); the
+    // others by product launches
+    const int32_t nsmax = lp_eig ? kNsMaxF32 : kNsMaxF64;
+    {
+      double f = 0;
+      for (int32_t j : js)
+        if (h.comp[j].ell <= nsmax) f += 2.0 * kNewtonSchulzSteps * std::pow((double)h.comp[j].ell, 3);
+      if (f > 0) cmd(kCmdTruncNs, RSC_K_EIG, t0, nt, f, lp_eig ? 1 : 0);
+    }
+    bool big = false;
+    for (int32_t j : js) big |= h.comp[j].ell > nsmax;
+    for (int it = 0; big && it < kNewtonSchulzSteps; ++it) {
       // sb = X X ; X_new = 1.5 X - 0.5 X sb (into sb via the D operand, then swap roles).
       // The right operands are passed transposed (B(j, k) = Y(k, j)) so that the products
       // are X X and X (X X): with X X^T in their place the iteration doubles the
@@ -912,6 +926,7 @@ struct Builder {
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t l = C.ell;
+        if (l <= nsmax) continue;
         const int64_t X = even ? C.Sa : C.Sb;
         fl += sym_tiles(gt(X, 1, l, X, l, 1, C.Om2, l, l, l, l, 1.0, 0.0));
       }
@@ -920,6 +935,7 @@ struct Builder {
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t l = C.ell;
+        if (l <= nsmax) continue;
         const int64_t X = even ? C.Sa : C.Sb, Xn = even ? C.Sb : C.Sa;
         GemmTask t = gt(X, 1, l, C.Om2, l, 1, Xn, l, l, l, l, -0.5, 1.5);
         t.d = X;
@@ -1165,7 +1181,7 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
     "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
-    "trunc_flags", "trunc_copy", "to_f32"};
+    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
@@ -1177,6 +1193,7 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
     case kCmdTruncFlags: return 32;
     case kCmdTruncCopy: return 33;
     case kCmdToF32: return 34;
+    case kCmdTruncNs: return 35;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -1240,6 +1257,9 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
                       I, Q->d_part.p, s);
       break;
     case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, h.arena32.p, s); break;
+    case kCmdTruncNs:
+      launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNewtonSchulzSteps, s);
+      break;
     case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, Q->d_part.p, A, s); break;
     case kCmdGatherRows:
       launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);

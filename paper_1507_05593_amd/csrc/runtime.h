@@ -25,7 +25,7 @@ enum CmdType : int32_t {
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
-  kCmdToF32,
+  kCmdToF32, kCmdTruncNs,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
