@@ -321,3 +321,35 @@ def test_mixed_precision_exact_factor_error_is_small():
         res = np.linalg.norm(Ap - L @ L.T) / np.linalg.norm(Ap)
         print(precision, "factor residual", res)
         assert res <= bound
+
+
+def test_mixed_forms_sweeps_apply_the_fp32_rounded_factor():
+    # After a mixed factorization the sweeps read an FP32 copy of the factor operands
+    # with FP64 vectors and sums: the operator applied is F^T F for the rounded
+    # sweep operators F, so it is symmetric to FP64 summation, and it stays within FP32
+    # rounding (times the factor's conditioning) of the FP64 apply of the same factor.
+    print("case fp32 sweeps (12, 11, 10)", flush=True)
+    p = grid_problem((12, 11, 10), sigma=1.0, seed=4)
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    for precision in ("fp32", "bf16"):
+        sol = _sol(p, precision=precision, retry=False)
+        sol.factor(_vals(p), 0.0)
+        L = np.zeros((p.n, p.n))
+        for j in range(sym.M):
+            blk = sol.block(j)
+            lo, hi = sym.first[j], sym.first[j + 1]
+            L[lo:hi, lo:hi] = blk["LD"]
+            if sym.r(j):
+                L[np.ix_(sym.rows[j], np.arange(lo, hi))] = blk["LO"]
+        Mu = sol.apply(_vec(u)).cpu().numpy()
+        Mv = sol.apply(_vec(v)).cpu().numpy()
+        asym = abs(u @ Mv - v @ Mu) / (np.linalg.norm(u) * np.linalg.norm(Mv))
+        zp = np.linalg.solve(L.T, np.linalg.solve(L, u[sym.perm]))
+        z64 = np.empty(p.n)
+        z64[sym.perm] = zp
+        rel = np.linalg.norm(Mu - z64) / np.linalg.norm(z64)
+        print(precision, "asymmetry", asym, "vs FP64 apply", rel, flush=True)
+        assert asym <= 1e-12
+        assert rel <= 1e-6
