@@ -29,7 +29,7 @@ void launch_trunc_flags(const TruncTask* t, int n, int lmax, double* arena, hipS
 void launch_trunc_copy(const TruncTask* t, int n, int lmax, double* arena, hipStream_t s);
 // the projector's Newton-Schulz steps in one workgroup per supernode with l <= kNsMaxF32
 // (FP32) or kNsMaxF64 (FP64); larger supernodes are skipped
-constexpr int kNsMaxF32 = 64, kNsMaxF64 = 64;
+constexpr int kNsMaxF32 = 128, kNsMaxF64 = 64;
 void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, int steps, hipStream_t s);
 
 // sweep kernels: f32 = FP32 copy of the factor operands (mixed forms), or null (arena)

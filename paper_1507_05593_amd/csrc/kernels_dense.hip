@@ -501,54 +501,65 @@ __global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ t
 }
 
 // Newton-Schulz iteration of the spectral projector, X <- 1.5 X - 0.5 X (X X), all
-// `steps` steps in one workgroup per supernode for l <= LMAX: X and Y = X X live in LDS
-// (element type T, order L = l rounded up to 16, pitch L + 4 so that the sixteen lanes
-// of a fragment fall in distinct banks), each product over the blocks on and below the
-// diagonal (MFMA 16x16x4, blocks dealt to the four waves in turn) and mirrored, so both
-// iterates stay exactly symmetric -- which lets both operands be read column-wise:
-// A(i, k) = X(k, i).  Supernodes with l > LMAX are left to the product launches.  Reads
-// X0 from sa and leaves the last iterate there (FP64).
-template <typename T, int LMAX>
-__global__ __launch_bounds__(256) void k_trunc_ns(const TruncTask* __restrict__ tasks,
-                                                  double* __restrict__ arena, int steps) {
-  constexpr int NB = LMAX / 16, NBLK = NB * (NB + 1) / 2, MAXB = (NBLK + 3) / 4, PITCH = LMAX + 4;
+// `steps` steps in one workgroup (NW waves) per supernode with LMIN < l <= LMAX: X and
+// Y = X X live in LDS (element type T, order L = l rounded up to 16, pitch L + 4 so that
+// the sixteen lanes of a fragment fall in distinct banks), each product over the blocks
+// on and below the diagonal (MFMA 16x16x4, blocks dealt to the waves in turn; a wave
+// steps all its blocks together through k, so their MFMA chains interleave) and
+// mirrored, so both iterates stay exactly symmetric -- which lets both operands be read
+// column-wise: A(i, k) = X(k, i).  Other supernodes are left to the other launches.
+// Reads X0 from sa and leaves the last iterate there (FP64).
+template <typename T, int LMIN, int LMAX, int NW>
+__global__ __launch_bounds__(64 * NW) void k_trunc_ns(const TruncTask* __restrict__ tasks,
+                                                      double* __restrict__ arena, int steps) {
+  constexpr int NB = LMAX / 16, NBLK = NB * (NB + 1) / 2, MAXB = (NBLK + NW - 1) / NW, PITCH = LMAX + 4;
   typedef typename std::conditional<sizeof(T) == 8, v4d, v4f>::type AccT;
   __shared__ T X[LMAX * PITCH], Y[LMAX * PITCH];
   const TruncTask Tk = tasks[blockIdx.x];
   const int l = Tk.l;
-  if (l > LMAX) return;
+  if (l <= LMIN || l > LMAX) return;
   const int L = (l + 15) & ~15, nb = L >> 4, nblk = nb * (nb + 1) / 2;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   double* S = arena + Tk.sa;
-  for (int e = tid; e < L * L; e += 256) {
+  for (int e = tid; e < L * L; e += 64 * NW) {
     const int i = e % L, j = e / L;
     X[i + j * PITCH] = (i < l && j < l) ? (T)S[i + (int64_t)j * l] : (T)0;
   }
-  // this wave's blocks: q = w + 4u in row-major order of the lower block triangle
+  // this wave's blocks: q = w + NW u in row-major order of the lower block triangle
   int bi[MAXB], bj[MAXB];
+  int nmine = 0;
 #pragma unroll
   for (int u = 0; u < MAXB; ++u) {
-    const int q = w + 4 * u;
+    const int q = w + NW * u;
     int r = 0;
     while ((r + 1) * (r + 2) / 2 <= q) ++r;
     bi[u] = r; bj[u] = q - r * (r + 1) / 2;
+    if (q < nblk) nmine = u + 1;
   }
   AccT acc[MAXB];
   // acc[u] = (P Q)(block u) for symmetric P, Q: lane (li, lk) supplies P(16 bi + li, k)
   // = P[k + (16 bi + li) PITCH] and Q(k, 16 bj + li) = Q[k + (16 bj + li) PITCH]
   auto product = [&](const T* P, const T* Q) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < MAXB; ++u) {
+    for (int u = 0; u < MAXB; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[u][e] = 0;
-      if (w + 4 * u >= nblk) continue;
-      const T* pa = P + lk + (16 * bi[u] + li) * PITCH;
-      const T* pb = Q + lk + (16 * bj[u] + li) * PITCH;
-      for (int k0 = 0; k0 < L; k0 += 4) {
+    for (int k0 = 0; k0 < L; k0 += 4) {
+      T a[MAXB], b[MAXB];
+#pragma unroll
+      for (int u = 0; u < MAXB; ++u) {
+        if (u >= nmine) break;
+        a[u] = P[k0 + lk + (16 * bi[u] + li) * PITCH];
+        b[u] = Q[k0 + lk + (16 * bj[u] + li) * PITCH];
+      }
+#pragma unroll
+      for (int u = 0; u < MAXB; ++u) {
+        if (u >= nmine) break;
         if constexpr (sizeof(T) == 8)
-          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k0], pb[k0], acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u], 0, 0, 0);
         else
-          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[k0], pb[k0], acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc[u], 0, 0, 0);
       }
     }
   };
@@ -563,7 +574,7 @@ __global__ __launch_bounds__(256) void k_trunc_ns(const TruncTask* __restrict__ 
     product(X, X);                                   // Y = X X
 #pragma unroll
     for (int u = 0; u < MAXB; ++u) {
-      if (w + 4 * u >= nblk) continue;
+      if (u >= nmine) break;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int i, j;
@@ -577,7 +588,7 @@ __global__ __launch_bounds__(256) void k_trunc_ns(const TruncTask* __restrict__ 
     __syncthreads();                                 // every read of X is done
 #pragma unroll
     for (int u = 0; u < MAXB; ++u) {
-      if (w + 4 * u >= nblk) continue;
+      if (u >= nmine) break;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         int i, j;
@@ -589,7 +600,7 @@ __global__ __launch_bounds__(256) void k_trunc_ns(const TruncTask* __restrict__ 
     }
     __syncthreads();
   }
-  for (int e = tid; e < l * l; e += 256) {
+  for (int e = tid; e < l * l; e += 64 * NW) {
     const int i = e % l, j = e / l;
     S[e] = (double)X[i + j * PITCH];
   }
@@ -597,12 +608,11 @@ __global__ __launch_bounds__(256) void k_trunc_ns(const TruncTask* __restrict__ 
 
 void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, int steps, hipStream_t s) {
   if (n <= 0) return;
-  // one workgroup per supernode: beyond l = 64 the product launches, which spread a
-  // supernode's tiles over several compute units, finish sooner
   if (fp32) {
-    hipLaunchKernelGGL((k_trunc_ns<float, kNsMaxF32>), dim3(n), dim3(256), 0, s, t, arena, steps);
+    hipLaunchKernelGGL((k_trunc_ns<float, 0, 64, 4>), dim3(n), dim3(256), 0, s, t, arena, steps);
+    hipLaunchKernelGGL((k_trunc_ns<float, 64, kNsMaxF32, 8>), dim3(n), dim3(512), 0, s, t, arena, steps);
   } else {
-    hipLaunchKernelGGL((k_trunc_ns<double, kNsMaxF64>), dim3(n), dim3(256), 0, s, t, arena, steps);
+    hipLaunchKernelGGL((k_trunc_ns<double, 0, kNsMaxF64, 4>), dim3(n), dim3(256), 0, s, t, arena, steps);
   }
 }
 

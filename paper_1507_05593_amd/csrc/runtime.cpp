@@ -905,18 +905,22 @@ struct Builder {
     }
     cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl);
     cmd(kCmdTruncX0, RSC_K_EIG, t0, nt, 0);            // sa = I - 2 theta H
-    // supernodes with l up to nsmax: every step in one workgroup each (k_trunc_ns); the
-    // others by product launches
-    const int32_t nsmax = lp_eig ? kNsMaxF32 : kNsMaxF64;
+    // a level whose supernodes all have l <= nsmax runs every step in one workgroup per
+    // supernode (k_trunc_ns); any other level, all of it by product launches (whose count
+    // does not depend on how many supernodes they hold, so splitting a level would only
+    // add the in-LDS launch to them)
+    int32_t nsmax = lp_eig ? kNsMaxF32 : kNsMaxF64;
     {
+      int32_t lmax = 0;
       double f = 0;
-      for (int32_t j : js)
-        if (h.comp[j].ell <= nsmax) f += 2.0 * kNewtonSchulzSteps * std::pow((double)h.comp[j].ell, 3);
-      if (f > 0) cmd(kCmdTruncNs, RSC_K_EIG, t0, nt, f, lp_eig ? 1 : 0);
+      for (int32_t j : js) {
+        lmax = std::max(lmax, h.comp[j].ell);
+        f += 2.0 * kNewtonSchulzSteps * std::pow((double)h.comp[j].ell, 3);
+      }
+      if (lmax <= nsmax) cmd(kCmdTruncNs, RSC_K_EIG, t0, nt, f, lp_eig ? 1 : 0);
+      else nsmax = 0;
     }
-    bool big = false;
-    for (int32_t j : js) big |= h.comp[j].ell > nsmax;
-    for (int it = 0; big && it < kNewtonSchulzSteps; ++it) {
+    for (int it = 0; nsmax == 0 && it < kNewtonSchulzSteps; ++it) {
       // sb = X X ; X_new = 1.5 X - 0.5 X sb (into sb via the D operand, then swap roles).
       // The right operands are passed transposed (B(j, k) = Y(k, j)) so that the products
       // are X X and X (X X): with X X^T in their place the iteration doubles the
