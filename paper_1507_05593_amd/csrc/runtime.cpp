@@ -320,7 +320,6 @@ struct PanelDesc {
   int32_t lp_lo = 0, lp_hi = 0;   // rows [lp_lo, lp_hi) use the low-precision products
   bool skip_mid = false;          // ... or are not touched at all
   bool tail_lp = false;           // rows from lp_hi on (the inverse being formed) use lp_tri
-  bool head_lp = false;           // rows before lp_lo (the diagonal block) use lp_tri
 };
 
 // Merges a GEMM command's 64 x 64 output tiles (tasks [off, end) of the list, in the
@@ -559,7 +558,7 @@ struct Builder {
               : gt(colo, 1, p.ld, colo, 1, p.ld, p.off, p.ld, R1, p.n, kOuter, -1.0, 1.0);
           const int32_t jb = (phase == 0) ? 0 : (phase == 1) ? d0 + nb : dend;
           const bool lower = (phase >= 1);
-          const bool use_lp = ((lp_update || p.skip_mid) && p.lp_hi > p.lp_lo) || ((p.tail_lp || p.head_lp) && lp_tri);
+          const bool use_lp = ((lp_update || p.skip_mid) && p.lp_hi > p.lp_lo) || (p.tail_lp && lp_tri);
           // segments [R0, lp_lo), [lp_lo, lp_hi), [lp_hi, R1)
           int32_t cuts[4] = {R0, use_lp ? std::max(R0, p.lp_lo) : R1, use_lp ? std::max(R0, p.lp_hi) : R1, R1};
           for (int sgm = 0; sgm < 3; ++sgm) {
@@ -569,7 +568,7 @@ struct Builder {
             ts.m = hi;
             if (sgm == 1 && p.skip_mid) continue;
             if (sgm == 1) flo += tiles(ts, lo, jb, lower, &lo_t);
-            else if (((sgm == 2 && p.tail_lp) || (sgm == 0 && p.head_lp)) && lp_tri) ftl += tiles(ts, lo, jb, lower, &tl_t);
+            else if (sgm == 2 && p.tail_lp && lp_tri) ftl += tiles(ts, lo, jb, lower, &tl_t);
             else fh += tiles(ts, lo, jb, lower, &hi_t);
           }
         }
@@ -1089,7 +1088,6 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
       pd.lp_lo = S.c(j);                 // rows U^O_j: solved below by one product
       pd.lp_hi = S.c(j) + S.r(j);
       pd.skip_mid = true;
-      pd.head_lp = pd.tail_lp = true;    // mixed forms: the block and its inverse on FP32 products
       pan.push_back(pd);
     }
     B.panel_steps(pan);
