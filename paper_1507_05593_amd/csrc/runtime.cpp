@@ -1616,7 +1616,10 @@ static Error build_solve_plan(Handle& h) {
     {
       const int64_t g0q = (int64_t)Q->gath.size() / 2;
       for (int32_t j : lev)
-        if (S.r(j) > 0) { Q->gath.push_back(S.rows_ptr[j]); Q->gath.push_back(S.r(j)); }
+        for (int32_t t0 = 0; t0 < S.r(j); t0 += 1024) {   // pieces of <= 1024 rows, one workgroup each
+          Q->gath.push_back(S.rows_ptr[j] + t0);
+          Q->gath.push_back(std::min(1024, S.r(j) - t0));
+        }
       const int64_t ng = (int64_t)Q->gath.size() / 2 - g0q;
       if (ng > 0) {
         Cmd c{};
