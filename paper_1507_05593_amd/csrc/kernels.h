@@ -87,7 +87,8 @@ void launch_gemm_reduce(int tile, const GemmTask* t, int n, double* arena, const
 // at most 32 x 32); xbase = operand base (the arena in FP64 mode, else the compact copy).
 void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, const int32_t* relmap,
                          double* arena, const double* xbase, const int32_t* ilim, hipStream_t s);
-// Compact row-major copies (FP32 or BF16 hi/lo chunks) of Schur-update operands.
+// Compact row-major copies (FP64, FP32 or BF16 hi/lo chunks) of Schur-update operands;
+// f32 (or null): also the block's FP32 column-major copy at the arena's offsets.
 void launch_compact_rows(int mode, const CompactTask* t, int n, const double* arena, const int32_t* ilim,
-                         double* xc, hipStream_t s);
+                         double* xc, float* f32, hipStream_t s);
 }  // namespace rsc

@@ -375,7 +375,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restrict__ tasks,
                                                       const double* __restrict__ arena,
                                                       const int32_t* __restrict__ ilim,
-                                                      double* __restrict__ xc) {
+                                                      double* __restrict__ xc, float* __restrict__ f32) {
   __shared__ double t[KC][65];
   const CompactTask T = tasks[blockIdx.x];
   const int K = T.kdim >= 0 ? T.kdim : ilim[-1 - T.kdim];
@@ -394,7 +394,10 @@ __global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restr
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int idx = tid + 256 * u, rr = idx & 63, k = idx >> 6;
-        t[k][rr] = (rr < T.nrows && c0 + k < K) ? v[u] : 0.0;
+        const bool in = rr < T.nrows && c0 + k < K;
+        t[k][rr] = in ? v[u] : 0.0;
+        // the sweeps' FP32 copy of the same block, column-major at the arena's offsets
+        if (f32 && in) f32[T.src + rr + (int64_t)(c0 + k) * T.ld] = (float)v[u];
       }
     } else {
       for (int idx = tid; idx < 64 * KC; idx += 256) t[idx >> 6][idx & 63] = 0.0;
@@ -776,11 +779,11 @@ void launch_update_waves(int mode, const UpdTile* t, int n, const UpdEntry* e, c
 }
 
 void launch_compact_rows(int mode, const CompactTask* t, int n, const double* arena, const int32_t* ilim,
-                         double* xc, hipStream_t s) {
+                         double* xc, float* f32, hipStream_t s) {
   if (n <= 0) return;
-  if (mode == sF64) hipLaunchKernelGGL(k_compact_rows<sF64>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
-  else if (mode == sF32) hipLaunchKernelGGL(k_compact_rows<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
-  else hipLaunchKernelGGL(k_compact_rows<sBF16x3>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc);
+  if (mode == sF64) hipLaunchKernelGGL(k_compact_rows<sF64>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc, f32);
+  else if (mode == sF32) hipLaunchKernelGGL(k_compact_rows<sF32>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc, f32);
+  else hipLaunchKernelGGL(k_compact_rows<sBF16x3>, dim3(n), dim3(256), 0, s, t, arena, ilim, xc, f32);
 }
 
 }  // namespace rsc

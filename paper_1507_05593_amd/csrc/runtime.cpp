@@ -739,9 +739,10 @@ struct Builder {
     cmd(kCmdCompact, RSC_K_UPDATE, c0, (int64_t)P.compact.size() - c0, 0.0, lp_update);
   }
 
-  // FP32 copy (mixed forms) of every factor operand the two sweeps of the preconditioner
-  // read, at the arena's offsets: the inverse diagonal blocks M_j, and L^O_j or
-  // (U_j, V_j); blocks of at most 64 columns and kConvRows rows.
+  // FP32 copy (mixed forms) of the factor operands the two sweeps of the preconditioner
+  // read, at the arena's offsets: the inverse diagonal blocks M_j and U_j here (L^O_j
+  // and V_j are copied by k_compact_rows along with their compact copies); blocks of at
+  // most 64 columns and kConvRows rows.
   void f32_copy() {
     const Symbolic& S = h.S;
     const int64_t c0 = (int64_t)P.conv.size();
@@ -758,13 +759,7 @@ struct Builder {
       const int32_t c = S.c(j), r = S.r(j);
       add(h.a_panels + h.panel_off[j] + c + r, c, c, h.panel_ld[j], true);
       if (r == 0) continue;
-      if (P.compressed && h.compressible[j]) {
-        const CompSlot& C = h.comp[j];
-        add(C.Uj, c, C.ell, c, false);
-        add(C.Vj, r, C.ell, r, false);
-      } else {
-        add(h.a_lo + h.lo_off[j], r, c, r, false);
-      }
+      if (P.compressed && h.compressible[j]) add(h.comp[j].Uj, c, h.comp[j].ell, c, false);
     }
     cmd(kCmdToF32, RSC_K_OTHER, c0, (int64_t)P.conv.size() - c0, 0.0, 0);
   }
@@ -1235,7 +1230,8 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
                           P->d_xc.p, I, s);
       break;
     case kCmdCompact:
-      launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p, s);
+      launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p,
+                          P->precision != RSC_FP64 ? h.arena32.p : nullptr, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
     case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
