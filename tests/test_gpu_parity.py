@@ -353,3 +353,30 @@ def test_mixed_forms_sweeps_apply_the_fp32_rounded_factor():
         print(precision, "asymmetry", asym, "vs FP64 apply", rel, flush=True)
         assert asym <= 1e-12
         assert rel <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_projector_iteration_in_lds_ranks_and_pcg(precision):
+    # Levels whose supernodes all have small sample counts run the projector iteration in
+    # one workgroup per supernode (k_trunc_ns): check that it ran, that the ranks agree
+    # with the FP64 oracle's to the bar of the product-launch path, and that PCG
+    # converges within the stated iteration tolerance of the oracle's.
+    print("case projector in LDS", precision, flush=True)
+    p = grid_problem((18, 17, 16), sigma=1.0, seed=9)
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-2, Options(seed=2))
+    ref = o_solve(F, p.matrix(), p.b, rtol=1e-8)
+    sol = _sol(p, precision=precision, seed=2, retry=False)
+    sol.profile(True)
+    sol.factor(_vals(p), 1e-2)
+    kp = sol.kernel_profile()
+    sol.profile(False)
+    assert kp["trunc_ns"]["launches"] > 0, kp.get("trunc_ns")
+    ell, q = sol.ranks()
+    assert np.array_equal(ell, np.array(F.ell))
+    qo = np.array(F.q)
+    # the same bar as the product-launch path (upstream drift of near-threshold ranks)
+    assert np.abs(q - qo).max() <= 2 and np.mean(q != qo) <= 0.05, (q, qo)
+    x, info = sol.pcg(_vec(p.b), rtol=1e-8)
+    assert info["converged"] and info["true_residual"] <= 1.5e-8
+    assert info["iters"] <= 1.1 * ref.iters + 1, (info["iters"], ref.iters)
