@@ -1539,7 +1539,7 @@ static Error build_solve_plan(Handle& h) {
       double wl = 0;
       for (auto& bk : blks)
         for (auto& e : bk.e) wl += ework(e);
-      const double target = std::max(wl / 2048.0, 64.0 * 64.0);
+      const double target = std::max(wl / 4096.0, 64.0 * 64.0);
       const int64_t c0f = (int64_t)Q->fchunks.size(), a0 = (int64_t)Q->papply.size();
       int32_t slot = 0;
       for (auto& bk : blks) {
