@@ -1445,20 +1445,20 @@ static Error build_solve_plan(Handle& h) {
     c.type = type; c.klass = RSC_K_PCG; c.off = off; c.count = count; c.a = a; c.b = b;
     Q->fwd_bwd.push_back(c);
   };
-  // Column-dot launch of one sweep stage.  When the stage has fewer than 1024 tasks,
-  // the rows of every task are cut into chunks (so that the stage has about 1024
+  // Column-dot launch of one sweep stage.  When the stage has fewer than 2048 tasks,
+  // the rows of every task are cut into chunks (so that the stage has about 2048
   // workgroups) whose 16 sums go to partial blocks, stored in order by a second launch.
   auto coldot_stage = [&](std::vector<ColDotTask>& ts) {
     if (ts.empty()) return;
     const int64_t c0 = (int64_t)Q->coldot.size();
-    if (ts.size() >= 1024) {
+    if (ts.size() >= 2048) {
       for (auto& t : ts) { t.r0 = 0; t.r1 = INT_MAX; t.slot = -1; Q->coldot.push_back(t); }
       cmd(kCmdColDot, c0, (int64_t)ts.size());
       return;
     }
     double rows = 0;
     for (auto& t : ts) rows += t.tri ? std::min(t.rows, t.col0 + 16) : t.rows;
-    const int32_t chunk = (int32_t)std::max(512.0, 64.0 * std::ceil(rows / 1024.0 / 64.0));
+    const int32_t chunk = (int32_t)std::max(256.0, 64.0 * std::ceil(rows / 2048.0 / 64.0));
     const int64_t a0 = (int64_t)Q->papply.size();
     int32_t slot = 0;
     for (auto& t : ts) {
