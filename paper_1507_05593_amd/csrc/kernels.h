@@ -15,7 +15,7 @@ void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, dou
                      hipStream_t s);
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s);
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s);
-void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
+void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, bool f32,
                    hipStream_t s);
 void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int64_t* out,
                        int n, double* arena, hipStream_t s);

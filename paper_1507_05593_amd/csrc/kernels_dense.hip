@@ -286,14 +286,14 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 }
 
 // Entry (row, col) of supernode j's sample from counter (row, col / 4, 0, 0);
-// Box-Muller pairs (w0, w1) -> columns 4t, 4t+1 and (w2, w3) -> 4t+2, 4t+3.
-__global__ void k_philox(const PhiloxTask* __restrict__ tasks, double* __restrict__ arena,
-                         int round_bf16) {
+// Box-Muller pairs (w0, w1) -> columns 4t, 4t+1 and (w2, w3) -> 4t+2, 4t+3.  F32: the
+// transform in FP32 (the mixed forms, whose products round the sample to BF16 or FP32
+// anyway), else in FP64.
+template <bool F32>
+__global__ void k_philox(const PhiloxTask* __restrict__ tasks, double* __restrict__ arena) {
   const PhiloxTask T = tasks[blockIdx.y];
   const int ngrp = (T.cols + 3) / 4;
   const int64_t total = (int64_t)T.rows * ngrp;
-  const double two32 = 2.3283064365386963e-10;   // 2^-32
-  const double twopi = 2.0 * 3.141592653589793;
   for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total;
        id += (int64_t)gridDim.x * blockDim.x) {
     const int row = (int)(id / ngrp), g = (int)(id % ngrp);
@@ -301,20 +301,28 @@ __global__ void k_philox(const PhiloxTask* __restrict__ tasks, double* __restric
     philox4x32_10(c, T.k0, T.k1);
     double out[4];
     for (int h = 0; h < 2; ++h) {
-      const double u1 = ((double)c[2 * h] + 1.0) * two32;
-      const double u2 = (double)c[2 * h + 1] * two32;
-      const double rad = sqrt(-2.0 * log(u1));
-      const double th = twopi * u2;
-      out[2 * h] = rad * cos(th);
-      out[2 * h + 1] = rad * sin(th);
+      if constexpr (F32) {
+        const float two32 = 2.3283064365386963e-10f;   // 2^-32
+        const float u1 = ((float)c[2 * h] + 1.0f) * two32;
+        const float u2 = (float)c[2 * h + 1] * two32;
+        const float rad = sqrtf(-2.0f * logf(u1));
+        float sn, cs;
+        sincosf(6.283185307179586f * u2, &sn, &cs);
+        out[2 * h] = (double)(rad * cs);
+        out[2 * h + 1] = (double)(rad * sn);
+      } else {
+        const double two32 = 2.3283064365386963e-10;  // 2^-32
+        const double u1 = ((double)c[2 * h] + 1.0) * two32;
+        const double u2 = (double)c[2 * h + 1] * two32;
+        const double rad = sqrt(-2.0 * log(u1));
+        const double th = 2.0 * 3.141592653589793 * u2;
+        out[2 * h] = rad * cos(th);
+        out[2 * h + 1] = rad * sin(th);
+      }
     }
     for (int e = 0; e < 4; ++e) {
       const int col = 4 * g + e;
-      if (col < T.cols) {
-        double v = out[e];
-        if (round_bf16) v = (double)(float)(__bf16)(float)v;
-        arena[T.out + row + (int64_t)col * T.rows] = v;
-      }
+      if (col < T.cols) arena[T.out + row + (int64_t)col * T.rows] = out[e];
     }
   }
 }
@@ -726,9 +734,12 @@ void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* aren
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(256), 0, s, t, arena, status);
 }
-void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, int bf16,
+void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, bool f32,
                    hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_philox, dim3(grid_for(max_work, 256, 4096), n), dim3(256), 0, s, t, arena, bf16);
+  if (n <= 0) return;
+  const dim3 grid(grid_for(max_work, 256, 4096), n);
+  if (f32) hipLaunchKernelGGL(k_philox<true>, grid, dim3(256), 0, s, t, arena);
+  else hipLaunchKernelGGL(k_philox<false>, grid, dim3(256), 0, s, t, arena);
 }
 void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int64_t* out,
                        int n, double* arena, hipStream_t s) {

@@ -785,7 +785,8 @@ struct Builder {
       P.philox.push_back(t);
       maxw = std::max<int64_t>(maxw, (int64_t)S.r(j) * ((C.ell + 3) / 4));
     }
-    cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw);
+    // the mixed forms round the sample to BF16 in the product: the transform runs in FP32
+    cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw, lp_sample ? 1 : 0);
     // 2. Y = (L^O_j)^T Omega into rows [l, l + c) of the orthonormalisation panel
     int64_t g0 = (int64_t)P.gemm.size();
     double fl = 0;
@@ -959,7 +960,7 @@ struct Builder {
         P.philox.push_back(t);
         maxw2 = std::max<int64_t>(maxw2, (int64_t)C.ell * ((C.ell + 3) / 4));
       }
-      cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw2);
+      cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw2, lp_eig ? 1 : 0);
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
@@ -1236,7 +1237,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
     case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
     case kCmdGemmReduce: launch_gemm_reduce((int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
-    case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, 0, s); break;
+    case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, c.b != 0, s); break;
     case kCmdGramScale:
       launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,
                         P->d_gs_out.p + c.off, (int)c.count, A, s);
