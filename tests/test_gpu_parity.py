@@ -211,6 +211,40 @@ def test_not_spd_reports_supernode():
     assert info["converged"]
 
 
+def test_mixed_retry_policy_and_recovery():
+    # The restart policy: a mixed BF16 factorization that meets a non-positive pivot is
+    # redone with FP32 products, then in FP64; an indefinite matrix fails all three and
+    # reports the supernode.  The handle then factors valid values in BF16 again, twice
+    # (FP32 sweep copy, solve graphs recaptured for the new plan), PCG converges each time,
+    # and the solution agrees with an FP64 handle's.
+    print("case retry policy", flush=True)
+    p = grid_problem((10, 9, 8), sigma=1.0, seed=6)
+    vals = p.values.copy()
+    rows = np.repeat(np.arange(p.n), np.diff(p.rowptr))
+    d = np.nonzero(rows == p.colind)[0]
+    vals[d[150]] = -vals[d[150]]
+    from paper_1507_05593_amd import RSCError
+    sol = _sol(p, precision="bf16", seed=1)
+    with pytest.raises(RSCError) as eg:
+        sol.factor(_vec(vals), 1e-2)
+    assert eg.value.code == 3
+    st = sol.stats()
+    assert st["retries"] == 2 and st["failed_supernode"] >= 0
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-2, Options(seed=1))
+    ref = o_solve(F, p.matrix(), p.b, rtol=1e-8)
+    for _ in range(2):
+        sol.factor(_vals(p), 1e-2)
+        assert sol.stats()["precision_used"] == 1
+        x, info = sol.pcg(_vec(p.b), rtol=1e-8)
+        assert info["converged"] and info["true_residual"] <= 1.5e-8
+        assert info["iters"] <= 1.5 * ref.iters + 2
+    s64 = _sol(p, seed=1)
+    s64.factor(_vals(p), 1e-2)
+    x64, i64 = s64.pcg(_vec(p.b), rtol=1e-8)
+    assert np.linalg.norm(x.cpu().numpy() - x64.cpu().numpy()) <= 1e-6 * np.linalg.norm(x64.cpu().numpy())
+
+
 def test_determinism_and_graph_replay():
     p = grid_problem((18, 17, 16), sigma=1.0, seed=8)
     b = _vec(p.b)
