@@ -260,6 +260,32 @@ def test_determinism_and_graph_replay():
         assert np.array_equal(x, runs[0][0])
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 0.0), ("bf16", 1e-2)])
+def test_wide_separator_graph_equals_eager_launch_order(precision, tol):
+    # top separator of 867 columns, so its panel steps span several 256-column outer
+    # blocks with end-of-block trailing products; the captured graph must give bit for
+    # bit what the eager launches (one stream, list order) give
+    print("case wide separator graph vs eager", precision, tol, flush=True)
+    p = grid_problem((34, 34, 34), sigma=1.0, seed=5)
+    b = _vec(p.b)
+    out = []
+    for use_graph in (True, False):
+        sol = _sol(p, use_graph=use_graph, seed=3, precision=precision, gemm_tile=64)
+        assert np.diff(sol.supernode_info()[0]).max() > 768
+        sol.factor(_vals(p), tol)
+        x, info = sol.pcg(b, rtol=1e-9)
+        blocks = [sol.block(j)["LD"] for j in range(sol.supernodes)]
+        out.append((x.cpu().numpy().copy(), info["iters"], blocks))
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+    for u, v in zip(out[0][2], out[1][2]):
+        assert np.array_equal(u, v)
+    if tol == 0.0:
+        sym = symbolic(p.n, p.rowptr, p.colind, 64)
+        F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 0.0, Options(leaf_max=64))
+        _check_blocks(sol, F, 1e-12)
+
+
 def test_adjoint_matches_dense_oracle_and_autograd():
     from paper_1507_05593_amd import grad_faces, solve
     p = grid_problem((5, 4, 3), sigma=1.0, seed=9)
