@@ -87,6 +87,33 @@ def test_compress_error_within_range_finder_bound():
     assert abs(q - np.count_nonzero(s > tol * s[0])) <= 1
 
 
+def test_power_iterations_reach_best_rank_ell_error():
+    # Algorithm 3's power iterations are subspace iteration on B^T B: with a spectral
+    # gap after the l-th singular value the sampled subspace converges to the top-l
+    # right singular subspace, so ||B - V U^T||_2 falls to sigma_{l+1}, the smallest
+    # any rank-l approximation reaches (Eckart-Young-Mirsky).  Without the iterations
+    # the same sample stays about twice as far off, so a dropped or mis-transposed
+    # product fails one side or the other.
+    rng = np.random.default_rng(2)
+    m, n = 400, 120
+    ell = sample_count(m, n, 1.0, 10)
+    assert ell == 86
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.where(np.arange(n) < ell, 1.0, 0.5) * 0.999 ** np.arange(n)
+    B = (Q1 * s) @ Q2.T
+    err = {}
+    for q in (0, 6):
+        V, U, l, k = compress(B, 4, Options(seed=6, power_iters=q), 0.0)
+        assert l == ell and k == ell
+        assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-12
+        assert np.abs(V - B @ U).max() <= 1e-12 * s[0]
+        err[q] = np.linalg.norm(B - V @ U.T, 2)
+        assert err[q] >= s[ell] * (1 - 1e-12)
+    assert err[6] <= s[ell] * (1 + 1e-4)
+    assert err[0] >= 1.5 * s[ell]
+
+
 @pytest.mark.parametrize("dims,sigma", [((10, 10, 10), 1.0), ((40, 40), 1.0), ((12, 11, 10), 1.5)])
 def test_full_sampling_reproduces_exact_factor(dims, sigma):
     # With l_j = min(r_j, c_j) samples and nothing truncated, V_j U_j^T = L^O_j,
