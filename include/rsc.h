@@ -61,10 +61,9 @@ typedef struct {
   int32_t leaf_max;    /* dissection stops at subgraphs of at most this many vertices (64) */
   int32_t tau_O;       /* separators with at least tau_O columns are compressed (Sec. 3.1; 32) */
   int32_t oversample;  /* p of the rank function of Sec. 5.2 (10) */
-  int32_t power_iters; /* power iterations of Algorithm 3 (0). The sample is orthonormalised
-                          once, through its Gram matrix, after the last iteration, so a
-                          direction with sigma/sigma_1 below ~(1.5e-8)^(1/(2q+1)) of L^O_j is
-                          lost (q = 1: 0.0025, q = 2: 0.027); keep tol above that bound. */
+  int32_t power_iters; /* power iterations of Algorithm 3 (0): Y <- (L^O)^T (L^O Y), each product's
+                          operand first conditioned by one shifted Cholesky-QR pass (the span is
+                          unchanged) so that no direction kept by the truncation is lost */
   double alpha_O;      /* alpha of the rank function of Sec. 5.2, used as the sample cap (1.0) */
   uint64_t seed;       /* key of the Gaussian samples (Algorithm 3): supernode j of a system is
                           sampled from Philox4x32-10 under key (seed mod 2^32, (seed >> 32) XOR j)

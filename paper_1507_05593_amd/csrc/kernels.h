@@ -17,8 +17,10 @@ void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* aren
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s);
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, bool f32,
                    hipStream_t s);
-void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int64_t* out,
-                       int n, double* arena, hipStream_t s);
+// Largest Gram diagonal (the drop scale of the Cholesky step); mm[p] > 0: first add the
+// shift of shifted Cholesky-QR for a sampled block of mm[p] rows.
+void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int32_t* mm,
+                       const int64_t* out, int n, double* arena, hipStream_t s);
 void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);

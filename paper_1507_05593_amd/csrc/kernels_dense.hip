@@ -331,23 +331,39 @@ __global__ void k_philox(const PhiloxTask* __restrict__ tasks, double* __restric
 
 // Column-drop scale of an orthonormalisation panel: the largest diagonal entry of
 // its n x n Gram block (at arena[g], leading dimension ld), stored at arena[out].
+// m[p] > 0 (the rows of the sampled block Y whose Gram matrix this is): shifted
+// Cholesky-QR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020) -- the shift
+// s = 11 (m n + n (n + 1)) u ||Y||_F^2, u = 2^-53, ||Y||_F^2 = trace(G), is added to the
+// diagonal first, so that G + s I is positive definite despite the rounding of G and
+// the pass keeps every direction of Y (the scale then includes the shift).
 __global__ void k_gram_scale(const int64_t* __restrict__ g, const int32_t* __restrict__ ld,
-                             const int32_t* __restrict__ n, const int64_t* __restrict__ out,
-                             double* __restrict__ arena) {
-  __shared__ double red[256];
+                             const int32_t* __restrict__ n, const int32_t* __restrict__ m,
+                             const int64_t* __restrict__ out, double* __restrict__ arena) {
+  __shared__ double red[256], tr[256];
   const int p = blockIdx.x;
-  double m = 0.0;
+  double mx = 0.0, t = 0.0;
   for (int i = threadIdx.x; i < n[p]; i += 256) {
     const double d = arena[g[p] + i + (int64_t)i * ld[p]];
-    m = fmax(m, isfinite(d) ? d : 0.0);
+    mx = fmax(mx, isfinite(d) ? d : 0.0);
+    t += isfinite(d) ? d : 0.0;
   }
-  red[threadIdx.x] = m;
+  red[threadIdx.x] = mx;
+  tr[threadIdx.x] = t;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    if (threadIdx.x < s) {
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+      tr[threadIdx.x] += tr[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) arena[out[p]] = red[0];
+  double shift = 0.0;
+  if (m[p] > 0) {
+    const double nn = (double)n[p];
+    shift = 11.0 * ((double)m[p] * nn + nn * (nn + 1.0)) * 1.1102230246251565e-16 * tr[0];
+    for (int i = threadIdx.x; i < n[p]; i += 256) arena[g[p] + i + (int64_t)i * ld[p]] += shift;
+  }
+  if (threadIdx.x == 0) arena[out[p]] = red[0] + shift;
 }
 
 // ---------------------------------------------------------------- spectral truncation
@@ -741,9 +757,9 @@ void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, 
   if (f32) hipLaunchKernelGGL(k_philox<true>, grid, dim3(256), 0, s, t, arena);
   else hipLaunchKernelGGL(k_philox<false>, grid, dim3(256), 0, s, t, arena);
 }
-void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int64_t* out,
-                       int n, double* arena, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_gram_scale, dim3(n), dim3(256), 0, s, g, ld, nn, out, arena);
+void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, const int32_t* mm,
+                       const int64_t* out, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gram_scale, dim3(n), dim3(256), 0, s, g, ld, nn, mm, out, arena);
 }
 void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_prep, dim3(64, n), dim3(256), 0, s, t, arena);

@@ -147,6 +147,10 @@ void plan_layout(Handle& h) {
     C.Wpan = a; a += align64(2 * l * l);
     C.Wdinv = a; a += ((l + 63) / 64) * 4096;
     C.sc = a; a += 64;
+    if (h.opt.power_iters > 0) {
+      C.zpanel = a; a += align64((l + r) * l);
+      C.zdinv = a; a += ((l + 63) / 64) * 4096;
+    }
     C.qslot = h.i_ranks + (int32_t)j;
   }
   a = align64(a);
@@ -764,6 +768,30 @@ struct Builder {
     cmd(kCmdToF32, RSC_K_OTHER, c0, (int64_t)P.conv.size() - c0, 0.0, 0);
   }
 
+  // One Cholesky-QR pass over the sample panels of a level (Y: rows [l, l + c) of the
+  // panel [Gram; Y], or with zp the power iteration's Z = L^O Y, rows [l, l + r) of its
+  // panel): Gram = Y^T Y (lower tiles), the drop scale (and with shifted, the shift of
+  // shifted Cholesky-QR), then the blocked panel factorisation, which leaves Y R^{-1}.
+  void cholqr_pass(const std::vector<int32_t>& js, bool zp, bool shifted) {
+    const Symbolic& S = h.S;
+    const int64_t g0 = (int64_t)P.gemm.size();
+    double fl = 0;
+    const int64_t s0 = (int64_t)P.gs_g.size();
+    std::vector<PanelDesc> pan;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      const int32_t l = C.ell, m = zp ? S.r(j) : S.c(j), ld = l + m;
+      const int64_t pnl = zp ? C.zpanel : C.ypanel, sc = zp ? C.gscale + 1 : C.gscale;
+      fl += tiles(gt(pnl + l, ld, 1, pnl + l, ld, 1, pnl, ld, l, l, m, 1.0, 0.0), 0, 0, true);
+      P.gs_g.push_back(pnl); P.gs_ld.push_back(ld); P.gs_n.push_back(l); P.gs_out.push_back(sc);
+      P.gs_m.push_back(shifted ? m : 0);
+      pan.push_back(PanelDesc{pnl, ld, l, m, false, zp ? C.zdinv : C.ydinv, j, 1, sc});
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
+    panel_steps(pan);
+  }
+
   // Algorithm 3 on the explicit L^O_j of every compressible supernode of a level,
   // followed by the spectral truncation.
   void compression(const std::vector<int32_t>& level, double tol) {
@@ -797,43 +825,39 @@ struct Builder {
       fl += tiles(gt(LO, r, 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_sample);
-    // 3. power iterations Y = (L^O)^T (L^O Y)
+    // 3. power iterations Y = (L^O)^T (L^O Y).  Each product is preceded by one shifted
+    //    Cholesky-QR pass over its operand: the span is unchanged (a right factor), but the
+    //    operand's spread of singular values no longer compounds over the iterations, so
+    //    no direction that the final orthonormalisation would keep sinks below rounding.
     for (int it = 0; it < h.opt.power_iters; ++it) {
+      cholqr_pass(js, false, true);
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
         const int64_t LO = h.a_lo + h.lo_off[j];
-        fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
+        fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.zpanel + l, l + r, r, l, c, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      cholqr_pass(js, true, true);
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
         const int64_t LO = h.a_lo + h.lo_off[j];
-        fl += tiles(gt(LO, r, 1, C.V, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
+        fl += tiles(gt(LO, r, 1, C.zpanel + l, l + r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     }
     ctx = RSC_K_ORTH;
-    // 4. orthonormalisation: Cholesky-QR passes, dependent columns dropped (the first
-    //    pass leaves a condition number below ~1e7, the second restores orthogonality)
-    for (int pass = 0; pass < kCholQRPasses; ++pass) {
-      g0 = (int64_t)P.gemm.size(); fl = 0;
-      const int64_t s0 = (int64_t)P.gs_g.size();
-      std::vector<PanelDesc> pan;
-      for (int32_t j : js) {
-        const CompSlot& C = h.comp[j];
-        const int32_t c = S.c(j), l = C.ell, ldy = l + c;
-        fl += tiles(gt(C.ypanel + l, ldy, 1, C.ypanel + l, ldy, 1, C.ypanel, ldy, l, l, c, 1.0, 0.0), 0, 0, true);
-        P.gs_g.push_back(C.ypanel); P.gs_ld.push_back(ldy); P.gs_n.push_back(l); P.gs_out.push_back(C.gscale);
-        pan.push_back(PanelDesc{C.ypanel, ldy, l, c, false, C.ydinv, j, 1, C.gscale});
-      }
-      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
-      cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
-      panel_steps(pan);
-    }
+    // 4. orthonormalisation by Cholesky-QR passes, dependent columns dropped.  Two plain
+    //    passes (the first leaves a condition number below ~1e7, the second restores
+    //    orthogonality) lose the directions of Y below ~1e-7 of its largest, i.e. singular
+    //    values of L^O_j below ~1e-6 sigma_1: harmless for tol >= 1e-5.  Below that the first
+    //    pass is shifted (shifted Cholesky-QR3: three passes), which keeps every direction
+    //    above the rounding of Y.
+    const bool accurate = tol < 1e-5;
+    for (int pass = 0; pass < (accurate ? 3 : 2); ++pass) cholqr_pass(js, false, accurate && pass == 0);
     ctx = RSC_K_BASIS;
     // 5. V = L^O_j U (FP32 MFMA in the mixed forms, like the other basis products: its
     //    rounding, ~1e-7 of |V|, is far below the truncation threshold tol^2 lambda_max)
@@ -977,6 +1001,7 @@ struct Builder {
           const int32_t l = C.ell;
           fl += tiles(gt(C.Wpan + l, 2 * l, 1, C.Wpan + l, 2 * l, 1, C.Wpan, 2 * l, l, l, l, 1.0, 0.0), 0, 0, true);
           P.gs_g.push_back(C.Wpan); P.gs_ld.push_back(2 * l); P.gs_n.push_back(l); P.gs_out.push_back(C.sc + 4);
+          P.gs_m.push_back(0);
           // drop mode 2 (relative pivot 1e-8) when the projector came from FP32
           // products: its rounding leaves ~1e-6 in the directions it annihilates
           pan.push_back(PanelDesc{C.Wpan, 2 * l, l, l, false, C.Wdinv, j, lp_eig ? 2 : 1, C.sc + 4});
@@ -1129,6 +1154,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gs_out, P->gs_out)).code) return e;
   if ((e = upload(P->d_gs_ld, P->gs_ld)).code) return e;
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
+  if ((e = upload(P->d_gs_m, P->gs_m)).code) return e;
   if ((e = upload(P->d_conv, P->conv)).code) return e;
   if (!P->conv.empty() && !h.arena32.p) {
     h.arena32.p = static_cast<float*>(dev_alloc(sizeof(float) * (size_t)h.arena_size));
@@ -1240,7 +1266,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, c.b != 0, s); break;
     case kCmdGramScale:
       launch_gram_scale(P->d_gs_g.p + c.off, P->d_gs_ld.p + c.off, P->d_gs_n.p + c.off,
-                        P->d_gs_out.p + c.off, (int)c.count, A, s);
+                        P->d_gs_m.p + c.off, P->d_gs_out.p + c.off, (int)c.count, A, s);
       break;
     case kCmdTruncPrep: launch_trunc_prep(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncPower: launch_trunc_power(P->d_trunc.p + c.off, (int)c.count, A, s); break;

@@ -75,6 +75,7 @@ struct CompSlot {
   int32_t ell = 0;
   int64_t omega = -1, ypanel = -1, ydinv = -1, V = -1, Vj = -1, Uj = -1, gscale = -1, tvq = -1,
           u = -1;
+  int64_t zpanel = -1, zdinv = -1;   // power iterations: [Gram; L^O Y] panel ((l + r) x l) and its inverses
   // truncation work space (l x l blocks, panels with ld 2l)
   int64_t G = -1, Sa = -1, Sb = -1, Mpan = -1, Mdinv = -1, Wpan = -1, Wdinv = -1, Om2 = -1,
           sc = -1;
@@ -98,7 +99,7 @@ struct FactorPlan {
   std::vector<PhiloxTask> philox;
   std::vector<TruncTask> trunc;
   std::vector<int64_t> gs_g, gs_out;
-  std::vector<int32_t> gs_ld, gs_n;
+  std::vector<int32_t> gs_ld, gs_n, gs_m;   // gs_m > 0: shifted Cholesky-QR pass over gs_m rows
   std::vector<ConvTask> conv;         // FP32 copy of the sweeps' operands (mixed forms)
   DevArray<GemmTask> d_gemm;
   DevArray<UpdTile> d_tiles;
@@ -110,7 +111,7 @@ struct FactorPlan {
   DevArray<PhiloxTask> d_philox;
   DevArray<TruncTask> d_trunc;
   DevArray<int64_t> d_gs_g, d_gs_out;
-  DevArray<int32_t> d_gs_ld, d_gs_n;
+  DevArray<int32_t> d_gs_ld, d_gs_n, d_gs_m;
   DevArray<ConvTask> d_conv;
   hipGraphExec_t graph = nullptr;
   double flops[6] = {0, 0, 0, 0, 0, 0};  // potrf, trsm, update, sample, orth, trunc

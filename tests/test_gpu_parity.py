@@ -172,15 +172,7 @@ def test_compressed_ranks_and_pcg_match_oracle(dims, sigma, tol):
     assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-6 * np.linalg.norm(xs)
 
 
-_GRAM_LIMIT = pytest.mark.xfail(
-    strict=False,
-    reason="the device orthonormalises the sample through its Gram matrix once, after the "
-           "power iterations; directions of Y below ~sqrt(eps) of the largest are lost, i.e. "
-           "sigma/sigma_1 < ~(1.5e-8)^(1/(2q+1)) = 0.027 at q = 2, above this tolerance")
-
-
-@pytest.mark.parametrize("power_iters,tol", [(1, 1e-2), (2, 1e-1),
-                                             pytest.param(2, 1e-2, marks=_GRAM_LIMIT)])
+@pytest.mark.parametrize("power_iters,tol", [(1, 1e-2), (2, 1e-1), (2, 1e-2)])
 def test_power_iterations_ranks_compression_and_pcg(power_iters, tol):
     # Algorithm 3 with power iterations Y = (L^O)^T (L^O Y) on the device (FP64 form):
     # same sample counts as the oracle, ranks within the cut-off slack, each block's
@@ -219,21 +211,39 @@ def test_power_iterations_ranks_compression_and_pcg(power_iters, tol):
 
 
 def test_full_sampling_reproduces_exact_factor():
+    # Full sampling (l_j = min(r_j, c_j)) with a cut-off below rounding keeps every
+    # direction of L^O_j, so V_j U_j^T is the exact off-diagonal block: every block of
+    # the device's compressed factor against the oracle's exact factor (the unique
+    # Cholesky factor of the permuted matrix) to 1e-12, and the preconditioner against
+    # the oracle's exact one.
+    print("case full sampling (12, 12, 12)", flush=True)
     p = grid_problem((12, 12, 12), sigma=1.0, seed=4)
-    ex = _sol(p, tau_O=8, leaf_max=32)
-    ex.factor(_vals(p), 0.0)
+    sym = symbolic(p.n, p.rowptr, p.colind, 32)
+    F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 0.0, Options(leaf_max=32, tau_O=8))
     fc = _sol(p, tau_O=8, leaf_max=32, alpha_O=1e9)
     fc.factor(_vals(p), 1e-13)
     ell, q = fc.ranks()
-    assert ell.sum() > 0
+    comp = np.nonzero(ell)[0]
+    assert comp.size > 0
+    scale = max(np.abs(F.LD[j]).max() for j in range(sym.M))
+    worst = 0.0
+    for j in range(sym.M):
+        blk = fc.block(j)
+        worst = max(worst, np.abs(blk["LD"] - F.LD[j]).max())
+        if not sym.r(j):
+            continue
+        if ell[j]:
+            assert ell[j] == min(sym.r(j), sym.c(j)) and q[j] == ell[j], (j, ell[j], q[j])
+            LO = blk["V"] @ blk["U"].T
+        else:
+            LO = blk["LO"]
+        worst = max(worst, np.abs(LO - F.LO[j]).max())
+    print("full sampling: largest block difference / scale", worst / scale, flush=True)
+    assert worst <= 1e-12 * scale, worst / scale
     r = np.random.default_rng(1).standard_normal(p.n)
-    z1 = ex.apply(_vec(r)).cpu().numpy()
-    z2 = fc.apply(_vec(r)).cpu().numpy()
-    # The device orthonormalisation drops sample directions whose Cholesky-QR pivot
-    # is below 1e-14 of the largest Gram diagonal (singular values below 1e-7 of the
-    # sample's largest), so full sampling reproduces the exact factor to about that
-    # level rather than to rounding.
-    assert np.linalg.norm(z1 - z2) <= 1e-6 * np.linalg.norm(z1)
+    z = fc.apply(_vec(r)).cpu().numpy()
+    zo = o_apply(F, r)
+    assert np.linalg.norm(z - zo) <= 1e-11 * np.linalg.norm(zo)
 
 
 def test_not_spd_reports_supernode():
