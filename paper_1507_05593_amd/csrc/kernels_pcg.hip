@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
   __shared__ double part[4][64];
   const GemvTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int K = T.kdim >= 0 ? T.kdim : ilim[-1 - T.kdim];
+  const int K = T.kdim >= 0 ? T.kdim : min(ilim[-1 - T.kdim], T.kmax);
   double acc = 0.0;
   if (lane < T.rows) {
     const int per = (K + 3) / 4;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ c
   for (int e = C.e0 + w; e < C.e1; e += 4) {
     const FwdEntry E = ents[e];
     const int nr = E.b - E.a;
-    const int K = E.kdim >= 0 ? E.kdim : ilim[-1 - E.kdim];
+    const int K = E.kdim >= 0 ? E.kdim : min(ilim[-1 - E.kdim], E.kmax);
     const int P = nr <= 8 ? 8 : nr <= 16 ? 16 : nr <= 32 ? 32 : 64;   // wave-uniform
     const int G = 64 / P;
     const int row = lane & (P - 1), g = lane / P;
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_coldot(const ColDotTask* __restrict__ t
   const ColDotTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const int ncols = T.ncols >= 0 ? T.ncols : ilim[-1 - T.ncols];
+  const int ncols = T.ncols >= 0 ? T.ncols : min(ilim[-1 - T.ncols], T.kmax);
   const double* in = arena + T.in;
   const int col = T.col0 + w * 4 + g;
   double acc = 0.0;
@@ -536,5 +536,6 @@ void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const d
                        const double* x, double* g, hipStream_t s) {
   if (nf > 0) hipLaunchKernelGGL(k_grad_faces, dim3(blocks_for(nf)), dim3(256), 0, s, nf, fi, fj, lam, x, g);
 }
+
 
 }  // namespace rsc

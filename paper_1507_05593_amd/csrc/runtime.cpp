@@ -1044,11 +1044,20 @@ Error upload_plan(DevArray<T>& d, const std::vector<T>& v) { return upload(d, v)
 // 128 is at least 3 % faster.  The arena holds scratch at this point -- the
 // factorisation writes every region it reads before reading it -- and the device ranks
 // are set to their largest value so that rank-limited products run at full width.
-static Error tune_tiles(Handle& h, FactorPlan& P) {
+static Error tune_tiles(Handle& h, FactorPlan& P, hipStream_t caller) {
   bool any = false;
   for (const Cmd& c : P.cmds) any |= (c.alt_off >= 0);
   if (!any) return kOk;
   hipStream_t s = h.cap_stream;
+  {
+    // the tuner overwrites the arena and the device ranks: work the caller queued
+    // before this factorization (a preconditioner apply, a PCG) must be done first
+    hipEvent_t done;
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(done, caller));
+    HIPCHK(hipStreamWaitEvent(s, done, 0));
+    (void)hipEventDestroy(done);
+  }
   double* A = h.arena.p;
   int32_t* I = h.ints.p;
   launch_fill_i32(I + h.i_ranks, h.S.M(), INT_MAX, s);
@@ -1086,7 +1095,8 @@ static Error tune_tiles(Handle& h, FactorPlan& P) {
   return err;
 }
 
-static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t precision) {
+static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t precision,
+                               hipStream_t stream) {
   auto P = std::make_unique<FactorPlan>();
   P->compressed = compressed;
   P->precision = precision;
@@ -1161,7 +1171,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
     if (!h.arena32.p) return Error{RSC_ERR_OUT_OF_MEMORY, "FP32 copy of the factor operands"};
     h.arena32.n = h.arena_size;
   }
-  if ((e = tune_tiles(h, *P)).code) return e;
+  if ((e = tune_tiles(h, *P, stream)).code) return e;
   auto& slot = h.fplans[precision];
   if (slot && slot->graph) (void)hipGraphExecDestroy(slot->graph);
   slot = std::move(P);
@@ -1245,6 +1255,7 @@ const char* kernel_name(int32_t k) { return (k >= 0 && k < RSC_KERNELS) ? kKerne
 static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const SolvePlan* Q,
                        hipStream_t s) {
   double* A = h.arena.p;
+  double* QP = Q ? Q->d_part.p : nullptr;   // partial-sum blocks of the sweeps
   int32_t* I = h.ints.p;
   const float* F32 = h.f32_valid ? h.arena32.p : nullptr;   // factor operands of the sweeps
   switch (c.type) {
@@ -1277,17 +1288,17 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncFlags: launch_trunc_flags(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
     case kCmdTruncCopy: launch_trunc_copy(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, F32, I, s); break;
-    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, F32, h.d_rows.p, I, Q->d_part.p, s); break;
-    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, F32, Q->d_part.p, s); break;
+    case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, F32, h.d_rows.p, I, QP, s); break;
+    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, F32, QP, s); break;
     case kCmdFwdPart:
       launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, F32,
-                      I, Q->d_part.p, s);
+                      I, QP, s);
       break;
     case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, h.arena32.p, s); break;
     case kCmdTruncNs:
       launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNewtonSchulzSteps, s);
       break;
-    case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, Q->d_part.p, A, s); break;
+    case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, QP, A, s); break;
     case kCmdGatherRows:
       launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);
       break;
@@ -1385,7 +1396,7 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
   const bool compressed = tol > 0.0;
   auto& slot = h.fplans[precision];
   if (!slot || slot->compressed != compressed || (compressed && slot->tol != tol))
-    if ((e = build_factor_plan(h, compressed, tol, precision)).code) return e;
+    if ((e = build_factor_plan(h, compressed, tol, precision, stream)).code) return e;
   if (h.splan && h.splan->compressed != compressed) {
     if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
     if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
@@ -1453,7 +1464,7 @@ Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
   h.retries = 0;
   for (size_t k = 0; k < ladder.size(); ++k) {
     e = factor_once(h, values, tol, ladder[k], stream);
-    if (e.code != RSC_ERR_NOT_SPD || k + 1 == ladder.size()) return e;
+    if (e.code != RSC_ERR_NOT_SPD || k + 1 == ladder.size()) break;
     h.retries++;
   }
   return e;
@@ -1527,9 +1538,11 @@ static Error build_solve_plan(Handle& h) {
           FwdEntry base{};
           if (iscomp(k)) {
             base.x = h.comp[k].Vj + pr.p0; base.ldx = S.r(k); base.kdim = -(1 + h.comp[k].qslot);
+            base.kmax = h.comp[k].ell;
             base.v = h.comp[k].tvq;
           } else {
             base.x = h.a_lo + h.lo_off[k] + pr.p0; base.ldx = S.r(k); base.kdim = S.c(k);
+            base.kmax = S.c(k);
             base.v = h.a_w + S.first[k];
           }
           base.map = pr.map_off;
@@ -1626,7 +1639,7 @@ static Error build_solve_plan(Handle& h) {
       for (int32_t col0 = 0; col0 < C.ell; col0 += 16) {
         ColDotTask t{};
         t.x = C.Uj; t.ldx = S.c(j); t.in = h.a_w + S.first[j]; t.idx = -1; t.out = C.tvq;
-        t.rows = S.c(j); t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
+        t.rows = S.c(j); t.ncols = -(1 + C.qslot); t.kmax = C.ell; t.col0 = col0; t.tri = 0;
         st.push_back(t);
       }
     }
@@ -1660,7 +1673,7 @@ static Error build_solve_plan(Handle& h) {
         for (int32_t col0 = 0; col0 < C.ell; col0 += 16) {
           ColDotTask t{};
           t.x = C.Vj; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j]; t.idx = -1; t.out = C.u;
-          t.rows = r; t.ncols = -(1 + C.qslot); t.col0 = col0; t.tri = 0;
+          t.rows = r; t.ncols = -(1 + C.qslot); t.kmax = C.ell; t.col0 = col0; t.tri = 0;
           st.push_back(t);
         }
       } else {
@@ -1682,7 +1695,7 @@ static Error build_solve_plan(Handle& h) {
       const CompSlot& C = h.comp[j];
       for (int32_t t0 = 0; t0 < S.c(j); t0 += 64) {
         GemvTask t{};
-        t.x = C.Uj + t0; t.ldx = S.c(j); t.kdim = -(1 + C.qslot); t.v = C.u;
+        t.x = C.Uj + t0; t.ldx = S.c(j); t.kdim = -(1 + C.qslot); t.kmax = C.ell; t.v = C.u;
         t.rows = std::min(64, S.c(j) - t0); t.out = h.a_s + S.first[j] + t0;
         Q->gemv.push_back(t);
       }

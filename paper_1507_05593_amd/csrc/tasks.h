@@ -102,7 +102,7 @@ struct GemvTask {
   int64_t out;                 // output (arena offset)
   int32_t ldx, rows;
   int32_t kdim;                // or -(1 + slot) of a device rank
-  int32_t pad_;
+  int32_t kmax;                // bound of that device rank (the sample count)
 };
 
 }  // namespace rsc
@@ -119,6 +119,7 @@ struct ColDotTask {
   int32_t tri;
   int32_t r0, r1;              // rows of this task: [r0, min(r1, rows(col)))
   int32_t slot;                // >= 0: write the 16 sums to partial block `slot` instead of out
+  int32_t kmax;                // ncols < 0: bound of the device rank (the sample count)
 };
 
 
@@ -182,6 +183,7 @@ struct FwdEntry {
   int32_t ldx, kdim;           // kdim < 0: -(1 + int-arena slot)
   int32_t a, b;
   int32_t m0, kspan;           // this piece sums columns [m0, min(kdim, m0 + kspan))
+  int32_t kmax, pad_;          // kdim < 0: bound of the device rank (the sample count)
 };
 
 }  // namespace rsc

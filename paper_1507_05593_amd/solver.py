@@ -95,6 +95,8 @@ class RSCSolver:
         self.n, self.nnz, self.supernodes, self.levels, self.systems = (
             n_.value, nnz.value, M.value, lev.value, sysn.value)
         self._keep = []
+        self._struct = None   # (first, rowptr of R_j): fixed by the symbolic phase
+        self.generation = 0   # successful factorizations so far
 
     @classmethod
     def batch(cls, ns, rowptrs, colinds, **opts):
@@ -123,6 +125,7 @@ class RSCSolver:
     def factor(self, values: torch.Tensor, tol: float = 0.0):
         v = _dev_f64(values, self.nnz, "values")
         check(lib().rsc_factor(self._h, _ptr(v), float(tol), _stream()), "rsc_factor")
+        self.generation += 1
         return self
 
     def pcg(self, b: torch.Tensor, rtol: float = 1e-8, max_iter: int = 1000, x: torch.Tensor = None,
@@ -178,11 +181,16 @@ class RSCSolver:
         check(lib().rsc_get_ranks(self._h, ell.ctypes.data_as(C.c_void_p), q.ctypes.data_as(C.c_void_p)))
         return ell, q
 
-    def block(self, j):
-        first, _, _, _ = self.supernode_info()
-        rp, _ = self.rowsets()
+    def block(self, j, ranks=None):
+        """Host copies of supernode j's blocks (rsc_get_block).  ranks: the (ell, q)
+        pair of ranks() when the caller already holds it (they change with each factor)."""
+        if self._struct is None:
+            first, _, _, _ = self.supernode_info()
+            rp, _ = self.rowsets()
+            self._struct = (first, rp)
+        first, rp = self._struct
         c = int(first[j + 1] - first[j]); r = int(rp[j + 1] - rp[j])
-        ell, q = self.ranks()
+        ell, q = self.ranks() if ranks is None else ranks
         qj = int(q[j])
         LD = np.zeros((c, c), order="F"); LO = np.zeros((r, c), order="F")
         V = np.zeros((r, qj), order="F"); U = np.zeros((c, qj), order="F")
@@ -229,17 +237,25 @@ class RSCSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, values, b, solver: RSCSolver, tol: float, rtol: float, max_iter: int):
-        solver.factor(values.detach(), tol)
+        v = values.detach()
+        solver.factor(v, tol)
         x, info = solver.pcg(b.detach(), rtol=rtol, max_iter=max_iter)
-        ctx.solver, ctx.rtol, ctx.max_iter = solver, rtol, max_iter
-        ctx.save_for_backward(x)
+        ctx.solver, ctx.tol, ctx.rtol, ctx.max_iter = solver, tol, rtol, max_iter
+        ctx.generation = solver.generation
+        ctx.save_for_backward(x, v)
         ctx.info = info
         return x
 
     @staticmethod
     def backward(ctx, g):
-        (x,) = ctx.saved_tensors
+        x, v = ctx.saved_tensors
         solver = ctx.solver
+        # The adjoint solve must use this forward's matrix: the handle's SpMV and factor
+        # are those of its latest rsc_factor, so if the solver factored other values
+        # since, it is refactored from the values saved here first.
+        if solver.generation != ctx.generation:
+            solver.factor(v, ctx.tol)
+            ctx.generation = solver.generation
         lam, _ = solver.pcg(g.detach().contiguous(), rtol=ctx.rtol, max_iter=ctx.max_iter)
         gv = solver.grad_values(lam, x) if ctx.needs_input_grad[0] else None
         gb = lam if ctx.needs_input_grad[1] else None

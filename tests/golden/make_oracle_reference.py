@@ -4,7 +4,9 @@ Usage: python tests/golden/make_oracle_reference.py diffusion3d_96 [--symbolic-o
 Output: tests/golden/oracle_<workload>.json with the symbolic sizes and SHA-256
 digests of the ordering and supernode structure, the kept rank of every compressed
 supernode, and the PCG iteration count and residuals of the oracle's
-rank-structured factor (seed 0, the benchmark's settings).  The full run takes
+rank-structured factor (seed 0, the benchmark's settings), the oracle's solution at
+4096 indices drawn from numpy.random.default_rng(20151) (for element-wise comparison),
+and the host it ran on (cores, BLAS threads, per-phase seconds).  The full run takes
 minutes at full size; ``--symbolic-only`` refreshes the structure digests of an
 existing file.  The tests compare against the stored file.
 """
@@ -33,6 +35,28 @@ def structure_digests(sym):
     rows = np.concatenate([np.asarray(r, dtype=np.int64) for r in sym.rows]) if sym.M else np.zeros(0)
     return dict(perm=h(sym.perm, "<i8"), first=h(sym.first, "<i8"), parent=h(sym.parent, "<i4"),
                 level=h(sym.level, "<i4"), kind=h(sym.kind, "<i4"), rows=h(rows, "<i8"))
+
+
+def host_info():
+    """Cores and BLAS threads of the host the oracle ran on."""
+    info = dict(cpu_count=os.cpu_count())
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas"] = [dict(api=d.get("internal_api"), threads=d.get("num_threads")) for d in threadpool_info()]
+    except Exception:  # pragma: no cover - threadpoolctl is optional
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            info["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:  # pragma: no cover
+        pass
+    return info
+
+
+def solution_sample(x, k=4096):
+    """x at k distinct indices from a fixed generator, sorted."""
+    idx = np.sort(np.random.default_rng(20151).choice(x.size, size=min(k, x.size), replace=False))
+    return dict(idx=[int(i) for i in idx], x=[float(v) for v in x[idx]])
 
 
 def main_batched(name):
@@ -85,7 +109,8 @@ def main(name, symbolic_only=False):
                q=[int(F.q[j]) for j in comp],
                pcg_iters=int(res.iters), rel_residual=res.rel_residual, true_residual=res.true_residual,
                x_norm=float((res.x @ res.x) ** 0.5), x_sum=float(res.x.sum()),
-               seconds=dict(symbolic=t1 - t0, factor=t2 - t1, pcg=t3 - t2),
+               x_sample=solution_sample(res.x),
+               seconds=dict(symbolic=t1 - t0, factor=t2 - t1, pcg=t3 - t2), host=host_info(),
                structure_sha256=structure_digests(sym),
                written_by="tests/golden/make_oracle_reference.py (oracle only)")
     with open(path, "w") as f:

@@ -89,6 +89,80 @@ def test_fullsize_rank_structured_pcg_matches_oracle(name, precision):
     xs = x.cpu().numpy()
     assert abs(np.linalg.norm(xs) - g["x_norm"]) <= 1e-6 * g["x_norm"]
     assert abs(xs.sum() - g["x_sum"]) <= 1e-6 * np.abs(xs).sum()
+    # element by element at the oracle's stored sample of 4096 indices
+    idx, xo = np.array(g["x_sample"]["idx"]), np.array(g["x_sample"]["x"])
+    err = np.abs(xs[idx] - xo).max() / np.abs(xo).max()
+    print("max |x - x_oracle| / max |x_oracle| over the sample", err, flush=True)
+    assert err <= 1e-6
+
+
+def _factor_residual_fro(sol, p, torch, dev="cuda:0"):
+    """||P A P^T - L L^T||_F / ||A||_F for the exact factor held by sol, from its blocks
+    (rsc_get_block) on the GPU in FP64.  For every supernode i the residual block over
+    rows C_i u R_i and columns C_i starts as P A P^T there and loses L_i L_i(C_i)^T and,
+    for every descendant k whose rows reach C_i, L_k(rows >= C_i) L_k(rows in C_i)^T --
+    every nonzero of L L^T lies in one of these blocks (the row sets nest along the
+    elimination tree) and P A P^T has no entry outside them."""
+    first, _, _, _ = sol.supernode_info()
+    rp, rows = sol.rowsets()
+    M = sol.supernodes
+    ranks = sol.ranks()
+    perm = sol.perm
+    Ap = p.matrix()[perm][:, perm].tocsc()
+    owner = np.repeat(np.arange(M), np.diff(first))
+    Lk, res = [], []
+    for i in range(M):
+        lo, hi = int(first[i]), int(first[i + 1])
+        idx = np.concatenate([np.arange(lo, hi), rows[rp[i]:rp[i + 1]]])
+        blk = sol.block(i, ranks)
+        Lk.append(torch.tensor(np.vstack([blk["LD"], blk["LO"]]), dtype=torch.float64, device=dev))
+        res.append(torch.tensor(Ap[:, lo:hi].tocsr()[idx].toarray(), dtype=torch.float64, device=dev))
+    for k in range(M):
+        c = int(first[k + 1] - first[k])
+        X = Lk[k]
+        res[k] -= X @ X[:c].T
+        R = rows[rp[k]:rp[k + 1]]
+        if R.size == 0:
+            continue
+        o = owner[R]
+        starts = np.flatnonzero(np.r_[True, o[1:] != o[:-1]])
+        for s0 in starts:
+            i = int(o[s0])
+            s1 = s0 + int(np.searchsorted(o[s0:], i, side="right"))
+            lo, hi = int(first[i]), int(first[i + 1])
+            tail = R[s0:]
+            pos = np.where(tail < hi, tail - lo, (hi - lo) + np.searchsorted(rows[rp[i]:rp[i + 1]], tail))
+            prod = X[c + s0:] @ X[c + s0:c + s1].T
+            rr = torch.tensor(pos, device=dev)[:, None]
+            cc = torch.tensor(R[s0:s1] - lo, device=dev)[None, :]
+            res[i][rr, cc] -= prod
+    tot = 0.0
+    for i in range(M):
+        c = int(first[i + 1] - first[i])
+        D = torch.tril(res[i][:c])
+        tot += 2.0 * float((D ** 2).sum()) - float((torch.diagonal(D) ** 2).sum())
+        tot += 2.0 * float((res[i][c:] ** 2).sum())
+    return np.sqrt(tot) / sp_norm_fro(p.matrix())
+
+
+def sp_norm_fro(A):
+    return float(np.sqrt((A.data ** 2).sum()))
+
+
+@pytest.mark.gpu
+def test_fullsize_exact_factor_residual_64():
+    """tol = 0 at 64^3 (FP64): ||P A P^T - L L^T||_F / ||A||_F <= 1e-11 for the device
+    factor, every stored block included."""
+    torch = _gpu()
+    from paper_1507_05593_amd import RSCSolver
+    print("case exact residual diffusion3d_64", flush=True)
+    cfg, p = _problem("diffusion3d_64")
+    vals = torch.tensor(p.values, dtype=torch.float64, device="cuda:0")
+    sol = RSCSolver(p.n, p.rowptr, p.colind)
+    sol.factor(vals, 0.0)
+    rel = _factor_residual_fro(sol, p, torch)
+    print("64^3 exact factor residual", rel, flush=True)
+    assert rel <= 1e-11
 
 
 @pytest.mark.gpu

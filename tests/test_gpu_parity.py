@@ -294,7 +294,7 @@ def test_mixed_retry_policy_and_recovery():
         assert sol.stats()["precision_used"] == 1
         x, info = sol.pcg(_vec(p.b), rtol=1e-8)
         assert info["converged"] and info["true_residual"] <= 1.5e-8
-        assert info["iters"] <= 1.5 * ref.iters + 2
+        assert abs(info["iters"] - ref.iters) <= max(1, 0.1 * ref.iters), (info["iters"], ref.iters)
     s64 = _sol(p, seed=1)
     s64.factor(_vals(p), 1e-2)
     x64, i64 = s64.pcg(_vec(p.b), rtol=1e-8)
@@ -403,7 +403,7 @@ def test_empty_rhs_and_tiny_system():
 def test_mixed_precision_forms_reach_rtol(precision, dims, sigma):
     # Mixed forms: parity with the FP64 oracle is unpinned bitwise; the stated bar is
     # convergence to rtol with a true residual <= 1e-8 and an iteration count within
-    # 1.5x + 2 of the FP64 oracle's (FP64 PCG recovers the accuracy).
+    # 10 % of the FP64 oracle's (at least one; FP64 PCG recovers the accuracy).
     print("case", precision, dims, sigma, flush=True)
     p = grid_problem(dims, sigma=sigma, seed=12)
     sym = symbolic(p.n, p.rowptr, p.colind, 64)
@@ -414,7 +414,9 @@ def test_mixed_precision_forms_reach_rtol(precision, dims, sigma):
     st = sol.stats()
     x, info = sol.pcg(_vec(p.b), rtol=1e-8)
     assert info["converged"] and info["true_residual"] <= 1.5e-8
-    assert info["iters"] <= 1.5 * ref.iters + 2, (info["iters"], ref.iters, st["precision_used"])
+    print(precision, dims, "iters", info["iters"], "oracle", ref.iters, "precision used",
+          st["precision_used"], flush=True)
+    assert abs(info["iters"] - ref.iters) <= max(1, 0.1 * ref.iters), (info["iters"], ref.iters)
     assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
 
 
@@ -495,4 +497,77 @@ def test_projector_iteration_in_lds_ranks_and_pcg(precision):
     assert np.abs(q - qo).max() <= 2 and np.mean(q != qo) <= 0.05, (q, qo)
     x, info = sol.pcg(_vec(p.b), rtol=1e-8)
     assert info["converged"] and info["true_residual"] <= 1.5e-8
-    assert info["iters"] <= 1.1 * ref.iters + 1, (info["iters"], ref.iters)
+    assert abs(info["iters"] - ref.iters) <= max(1, 0.1 * ref.iters), (info["iters"], ref.iters)
+
+
+def test_poisson2d_64_exact_then_compressed_pcg():
+    # The 2D unit-coefficient 64 x 64 workload (4096 unknowns): the exact factor's
+    # blocks against the oracle's, then the rank-structured factor at tol 1e-2 with
+    # PCG to 1e-8 -- sample counts equal, kept ranks within one, iterations within
+    # 10 % of the oracle's (at least one), and the solution element by element.
+    from workloads import workload_config
+    print("case poisson2d_64", flush=True)
+    cfg = workload_config("poisson2d_64")
+    p = grid_problem(cfg["dims"], sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg["unit"])
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    F0 = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 0.0, Options())
+    sol = _sol(p, seed=0)
+    sol.factor(_vals(p), 0.0)
+    _check_blocks(sol, F0, 1e-12)
+    x0, i0 = sol.pcg(_vec(p.b), rtol=1e-12)
+    assert i0["iters"] <= 2 and i0["true_residual"] <= 1e-12
+    F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, cfg["tol"], Options(seed=0))
+    ref = o_solve(F, p.matrix(), p.b, rtol=cfg["rtol"])
+    sol.factor(_vals(p), cfg["tol"])
+    ell, q = sol.ranks()
+    assert np.array_equal(ell, np.array(F.ell)) and ell.sum() > 0
+    assert np.abs(q - np.array(F.q)).max() <= 1, (q, F.q)
+    x, info = sol.pcg(_vec(p.b), rtol=cfg["rtol"])
+    print("poisson2d_64 iters", info["iters"], "oracle", ref.iters, flush=True)
+    assert info["converged"] and info["true_residual"] <= cfg["rtol"]
+    assert abs(info["iters"] - ref.iters) <= max(1, 0.1 * ref.iters), (info["iters"], ref.iters)
+    err = np.abs(x.cpu().numpy() - ref.x).max() / np.abs(ref.x).max()
+    print("poisson2d_64 max |x - x_oracle| / max |x_oracle|", err, flush=True)
+    assert err <= 1e-6
+
+
+def test_pcg_not_converged_reports_status_and_first_iterate():
+    # max_iter = 1 with rtol out of reach: RSC_ERR_NOT_CONVERGED, and the iterate left
+    # in x is the oracle's first CG iterate (x1 = alpha_0 z_0) for the exact factor.
+    from paper_1507_05593_amd import RSCError
+    print("case not converged", flush=True)
+    p = grid_problem((12, 11, 10), sigma=1.0, seed=2)
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-1, Options(seed=4))
+    ref = o_solve(F, p.matrix(), p.b, rtol=1e-14, max_iter=1)
+    sol = _sol(p, seed=4)
+    sol.factor(_vals(p), 1e-1)
+    with pytest.raises(RSCError) as e:
+        sol.pcg(_vec(p.b), rtol=1e-14, max_iter=1)
+    assert e.value.code == 4
+    x, info = sol.pcg(_vec(p.b), rtol=1e-14, max_iter=1, raise_on_failure=False)
+    assert not info["converged"] and info["iters"] == 1 and not ref.converged
+    assert abs(info["rel_residual"] - ref.rel_residual) <= 1e-6 * ref.rel_residual
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_adjoint_after_the_solver_factored_other_values():
+    # Backward through a solve after the same solver factored another matrix (a second
+    # solve under no_grad): the adjoint must still be the first matrix's.
+    from paper_1507_05593_amd import solve
+    print("case stale factor adjoint", flush=True)
+    p = grid_problem((5, 4, 3), sigma=1.0, seed=9)
+    q = grid_problem((5, 4, 3), sigma=1.0, seed=10)
+    assert np.array_equal(p.colind, q.colind) and not np.allclose(p.values, q.values)
+    x_d, lam_d, _ = dense_adjoint(p.matrix().toarray(), p.b, p.x_target)
+    sol = _sol(p)
+    vals = _vals(p).requires_grad_(True)
+    b = _vec(p.b).requires_grad_(True)
+    x = solve(vals, b, sol, tol=0.0, rtol=1e-13)
+    with torch.no_grad():
+        solve(_vals(q), _vec(q.b), sol, tol=0.0, rtol=1e-13)
+    loss = 0.5 * ((x - _vec(p.x_target)) ** 2).sum()
+    loss.backward()
+    assert np.abs(b.grad.cpu().numpy() - lam_d).max() <= 1e-10 * np.abs(lam_d).max()
+    gv = o_grad_values(p.rowptr, p.colind, lam_d, x_d)
+    assert np.abs(vals.grad.cpu().numpy() - gv).max() <= 1e-10 * np.abs(gv).max()

@@ -1,14 +1,14 @@
 """Host side of the C library (no GPU): exported symbols, the symbolic phase bit for
 bit against the oracle, and argument/pattern validation."""
 import ctypes as C
+import json
 import os
 import re
 
 import numpy as np
 import pytest
 
-from conftest import ROOT
-from oracle.factor import sample_count
+from conftest import ROOT, golden_path
 from oracle.ordering import symbolic
 from workloads import grid_problem
 from workloads.grids import batched_problems
@@ -67,11 +67,26 @@ def test_batched_symbolic_is_per_system_dissection():
     assert sn == sol.supernodes
 
 
-def test_sample_count_matches_oracle():
-    # the device-side sample counts follow the same rank function as the oracle
-    from paper_1507_05593_amd._lib import lib as _l  # noqa: F401
-    for r, c in [(200, 64), (9216, 4600), (37, 33), (1, 1), (120, 5000), (812, 640)]:
-        assert sample_count(r, c, 1.0, 10) == min(min(r, c), int(np.ceil(np.sqrt(min(r, c)) * np.log2(min(r, c)))) + 10)
+def test_path_graph_structure_hand_worked():
+    # the library's dissection, row sets, parents and levels of the path graph 0-...-199
+    # against the structure worked by hand in the fixture (same as the oracle's test)
+    g = json.load(open(golden_path("nd_path200.json")))
+    n = g["n"]
+    rows_ = []
+    for i in range(n):
+        rows_.append([v for v in (i - 1, i, i + 1) if 0 <= v < n])
+    rp = np.cumsum([0] + [len(r) for r in rows_]).astype(np.int64)
+    ci = np.concatenate(rows_).astype(np.int32)
+    sol = RSCSolver(n, rp, ci, leaf_max=g["leaf_max"])
+    first, parent, level, kind = sol.supernode_info()
+    perm = sol.perm
+    got = [[int(perm[first[j]]), int(perm[first[j + 1] - 1]), "leaf" if kind[j] == 0 else "separator"]
+           for j in range(sol.supernodes)]
+    assert got == g["supernodes"]
+    rptr, rows = sol.rowsets()
+    assert [rows[rptr[j]:rptr[j + 1]].tolist() for j in range(sol.supernodes)] == g["rows"]
+    assert parent.tolist() == g["parent"]
+    assert level.tolist() == g["level"]
 
 
 def test_pattern_and_argument_errors():

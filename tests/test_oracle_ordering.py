@@ -39,6 +39,11 @@ def test_nd_path_graph_hand_worked():
         assert np.all(np.diff(seg) == 1)
         got.append([int(seg[0]), int(seg[-1]), "leaf" if kind[j] == LEAF else "separator"])
     assert got == g["supernodes"]
+    # row sets, elimination tree and levels of the same dissection, worked by hand
+    sym = symbolic(g["n"], rp, ci, g["leaf_max"])
+    assert [list(map(int, r)) for r in sym.rows] == g["rows"]
+    assert [int(v) for v in sym.parent] == g["parent"]
+    assert [int(v) for v in sym.level] == g["level"]
 
 
 def test_nd_square_grid_top_separator_is_antidiagonal():
