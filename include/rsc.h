@@ -163,6 +163,21 @@ rsc_status rsc_pcg(rsc_handle h, const double* b, double* x, double rtol, int32_
  * (exact or rank-structured) factor.  r, z: device double[n], may not alias. */
 rsc_status rsc_apply_preconditioner(rsc_handle h, const double* r, double* z, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same z as
+ * rsc_apply_preconditioner, with the same kernels, launched directly on `stream` (no
+ * graph of the library's own, so a caller may capture it) and with the partial sums of
+ * the sweeps in a static device buffer of RSC_APPLY_SCRATCH_BYTES per GPU instead of
+ * memory of the handle; it calls no allocator.  Needs a handle that rsc_factor factored
+ * (rsc_factor builds the sweep plan): RSC_ERR_STATE otherwise; RSC_ERR_INVALID_ARG when
+ * the plan's partial sums exceed the buffer (the message gives both sizes).  The buffer
+ * needs no clearing (every sweep stage writes each block it reads first) and keeps the
+ * last call's contents.  All calls on one GPU share it: calls that overlap in time on
+ * one GPU (other streams, other threads) race; calls in one stream's order do not.
+ * r, z: device double[n], may not alias. */
+#define RSC_APPLY_SCRATCH_BYTES (8u << 20)
+rsc_status rsc_apply_preconditioner_noalloc(rsc_handle h, const double* r, double* z, void* stream);
+
 /* Adjoint of the solve with respect to the matrix values (not in the paper):
  * g[p] = -lambda[row(p)] * x[col(p)] for every stored entry p (CSR order).
  * lambda, x: device double[n]; g: device double[nnz]. */

@@ -152,6 +152,12 @@ rsc_status rsc_apply_preconditioner(rsc_handle H, const double* r, double* z, vo
   return ret(rsc::apply_preconditioner(H->h, r, z, (hipStream_t)stream));
 }
 
+rsc_status rsc_apply_preconditioner_noalloc(rsc_handle H, const double* r, double* z, void* stream) {
+  if (!H || (H->h.S.n > 0 && (!r || !z))) return fail(RSC_ERR_INVALID_ARG, "null argument");
+  if (r == z && r) return fail(RSC_ERR_INVALID_ARG, "r and z may not alias");
+  return ret(rsc::apply_preconditioner_noalloc(H->h, r, z, (hipStream_t)stream));
+}
+
 rsc_status rsc_grad_values(rsc_handle H, const double* lambda, const double* x, double* g, void* stream) {
   if (!H || (H->h.S.n > 0 && (!lambda || !x || !g))) return fail(RSC_ERR_INVALID_ARG, "null argument");
   return ret(rsc::grad_values(H->h, lambda, x, g, (hipStream_t)stream));

@@ -74,6 +74,10 @@ void launch_grad_values(int64_t n, const int64_t* rowptr, const int32_t* colind,
                         const double* x, double* g, hipStream_t s);
 void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const double* lam,
                        const double* x, double* g, hipStream_t s);
+// Static device buffer for the partial sums of the allocation-free preconditioner apply
+// (kApplyScratchDoubles doubles per GPU): its address on the current device.
+constexpr int64_t kApplyScratchDoubles = 1 << 20;   // 8 MiB
+hipError_t apply_scratch(double** out);
 
 }  // namespace rsc
 

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 #include "tasks.h"
@@ -537,5 +538,33 @@ void launch_grad_faces(int64_t nf, const int32_t* fi, const int32_t* fj, const d
   if (nf > 0) hipLaunchKernelGGL(k_grad_faces, dim3(blocks_for(nf)), dim3(256), 0, s, nf, fi, fj, lam, x, g);
 }
 
+
+// Partial-sum blocks of the allocation-free preconditioner apply: a file-scope device
+// array, one copy on every GPU the library runs on, held until the process ends.  In
+// host code its name is not a device address; apply_scratch() looks the address up once
+// per device (with that device current) and every later use goes through that pointer.
+static __device__ __align__(256) double apply_scratch_buf[kApplyScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t apply_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(apply_scratch_buf));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 }  // namespace rsc

@@ -1253,9 +1253,10 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
 const char* kernel_name(int32_t k) { return (k >= 0 && k < RSC_KERNELS) ? kKernelNames[k] : ""; }
 
 static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const SolvePlan* Q,
-                       hipStream_t s) {
+                       hipStream_t s, double* part_buf = nullptr) {
   double* A = h.arena.p;
-  double* QP = Q ? Q->d_part.p : nullptr;   // partial-sum blocks of the sweeps
+  // partial-sum blocks of the sweeps: the solve plan's own, or a caller's buffer
+  double* QP = part_buf ? part_buf : (Q ? Q->d_part.p : nullptr);
   int32_t* I = h.ints.p;
   const float* F32 = h.f32_valid ? h.arena32.p : nullptr;   // factor operands of the sweeps
   switch (c.type) {
@@ -1314,7 +1315,8 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
 
 // Runs a command list; with profiling on, brackets every launch with events.
 static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan* P,
-                      const SolvePlan* Q, hipStream_t s, std::vector<EventPair>* evs) {
+                      const SolvePlan* Q, hipStream_t s, std::vector<EventPair>* evs,
+                      double* part_buf = nullptr) {
   for (const Cmd& c : cmds) {
     if (evs) {
       EventPair ep;
@@ -1326,11 +1328,11 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
       ep.cmd = c.dyn ? &c : nullptr;
       ep.plan = P;
       HIPCHK(hipEventRecord(ep.a, s));
-      launch_cmd(h, c, P, Q, s);
+      launch_cmd(h, c, P, Q, s, part_buf);
       HIPCHK(hipEventRecord(ep.b, s));
       evs->push_back(ep);
     } else {
-      launch_cmd(h, c, P, Q, s);
+      launch_cmd(h, c, P, Q, s, part_buf);
     }
   }
   HIPCHK(hipGetLastError());
@@ -1451,6 +1453,8 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
   return kOk;
 }
 
+static Error ensure_solve(Handle& h);
+
 // The restart policy of Sec. 5.3 (raise the accuracy and refactor after an indefinite
 // pivot) applied to precision: mixed BF16 -> FP32 products -> FP64.
 Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
@@ -1467,7 +1471,8 @@ Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
     if (e.code != RSC_ERR_NOT_SPD || k + 1 == ladder.size()) break;
     h.retries++;
   }
-  return e;
+  if (e.code) return e;
+  return ensure_solve(h);   // the sweep plan of this factor (rsc_apply_preconditioner_noalloc needs it)
 }
 
 // ------------------------------------------------------------------ solve plan
@@ -1754,14 +1759,15 @@ static Error build_solve_plan(Handle& h) {
 }
 
 // One preconditioner apply: z (arena a_z) = M^{-1} r (arena a_r).
-static Error apply_cmds(Handle& h, hipStream_t s, std::vector<EventPair>* evs) {
+static Error apply_cmds(Handle& h, hipStream_t s, std::vector<EventPair>* evs,
+                        double* part_buf = nullptr) {
   Cmd g{}; g.type = kCmdGatherPerm; g.klass = RSC_K_PCG; g.count = 1; g.a = h.a_r; g.b = h.a_y;
   Cmd z{}; z.type = kCmdScatterPerm; z.klass = RSC_K_PCG; z.count = 1; z.a = h.a_zz; z.b = h.a_z;
   std::vector<Cmd> all;
   all.push_back(g);
   all.insert(all.end(), h.splan->fwd_bwd.begin(), h.splan->fwd_bwd.end());
   all.push_back(z);
-  return run_cmds(h, all, nullptr, h.splan.get(), s, evs);
+  return run_cmds(h, all, nullptr, h.splan.get(), s, evs, part_buf);
 }
 
 static Error ensure_solve(Handle& h) {
@@ -1783,6 +1789,30 @@ Error apply_preconditioner(Handle& h, const double* r, double* z, hipStream_t st
   } else {
     if ((e = apply_cmds(h, stream, nullptr)).code) return e;
   }
+  HIPCHK(hipMemcpyAsync(z, h.arena.p + h.a_z, sizeof(double) * (size_t)h.S.n, hipMemcpyDeviceToDevice, stream));
+  return kOk;
+}
+
+// The same apply launched eagerly on the caller's stream with the sweeps' partial sums
+// in the static per-GPU buffer: allocates nothing (the sweep plan was built by
+// rsc_factor).  Every stage writes each partial block it reads before reading it, so
+// the buffer needs no clearing between calls.
+Error apply_preconditioner_noalloc(Handle& h, const double* r, double* z, hipStream_t stream) {
+  if (!h.factored || !h.dev_ready) return Error{RSC_ERR_STATE, "no successful rsc_factor on this handle"};
+  if (!h.splan) return Error{RSC_ERR_STATE, "no sweep plan (rsc_factor builds it)"};
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != h.device) return Error{RSC_ERR_STATE, "handle is bound to another device"};
+  const int64_t need = std::max<int64_t>(h.splan->part_slots, 1) * 64;
+  if (need > kApplyScratchDoubles)
+    return Error{RSC_ERR_INVALID_ARG, "the sweeps need " + std::to_string(8 * need) +
+                                          " bytes of partial sums; the static buffer holds " +
+                                          std::to_string(8 * kApplyScratchDoubles)};
+  double* part = nullptr;
+  HIPCHK(apply_scratch(&part));
+  HIPCHK(hipMemcpyAsync(h.arena.p + h.a_r, r, sizeof(double) * (size_t)h.S.n, hipMemcpyDeviceToDevice, stream));
+  Error e = apply_cmds(h, stream, nullptr, part);
+  if (e.code) return e;
   HIPCHK(hipMemcpyAsync(z, h.arena.p + h.a_z, sizeof(double) * (size_t)h.S.n, hipMemcpyDeviceToDevice, stream));
   return kOk;
 }

@@ -214,6 +214,7 @@ Error factor(Handle& h, const double* values, double tol, hipStream_t stream);
 Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, hipStream_t stream,
           rsc_pcg_result* out);
 Error apply_preconditioner(Handle& h, const double* r, double* z, hipStream_t stream);
+Error apply_preconditioner_noalloc(Handle& h, const double* r, double* z, hipStream_t stream);
 Error grad_values(Handle& h, const double* lam, const double* x, double* g, hipStream_t stream);
 void release_device(Handle& h);
 

@@ -147,6 +147,15 @@ class RSCSolver:
         check(lib().rsc_apply_preconditioner(self._h, _ptr(r), _ptr(z), _stream()), "rsc_apply_preconditioner")
         return z
 
+    def apply_noalloc(self, r: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
+        """z = M^{-1} r into the caller's z through rsc_apply_preconditioner_noalloc (no
+        device allocation by the library; see include/rsc.h for the shared buffer)."""
+        r = _dev_f64(r, self.n, "r")
+        z = _dev_f64(z, self.n, "z")
+        check(lib().rsc_apply_preconditioner_noalloc(self._h, _ptr(r), _ptr(z), _stream()),
+              "rsc_apply_preconditioner_noalloc")
+        return z
+
     def grad_values(self, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
         lam = _dev_f64(lam, self.n, "lambda")
         x = _dev_f64(x, self.n, "x")
