@@ -11,17 +11,28 @@ BF16/FP32/FP64 form, with the plain FP64 form timed beside it on the same GPU.
 Prints one JSON line.  Fields beyond the common ones:
   fp64_form      the FP64 form's timings (mixed-precision default only)
   roofline       the kernel with the largest event-timed share of a profiled pass
-                 of the same steps: algorithmic flops per launch / mean launch time
-                 against the MI355X peak of its arithmetic; traffic from the stored
-                 rocprofv3 counter summary if the kernel source is unchanged
-  mfma_util      sum over MFMA kernels of flops / peak of their precision, divided
-                 by the factor time (time-weighted MFMA utilisation)
+                 of the same steps: algorithmic flops per launch (the method's own
+                 work, counted per supernode from the symbolic plan and credited to the
+                 launches that carry it) / mean launch time, against the MI355X peak of
+                 its arithmetic; the executed tile flops beside them; the rocprofv3 mean
+                 launch time from the committed kernel-time summary of the same build;
+                 traffic from the stored rocprofv3 counter summary if the kernel source
+                 is unchanged
+  mfma_util      the time-weighted MFMA utilisation of the factorization:
+                 (F_bf16 / P_bf16 + F_f32 / P_f32 + F_f64 / P_f64) / T_factor over
+                 the algorithmic flops F of each arithmetic; also split into the
+                 diagonal factorizations (panel classes) and the rest of each supernode
+                 (updates, off-diagonal solve, compression), each over its own time
   pcg_hbm        PCG algorithmic bytes (SpMV, two factor sweeps, vector updates)
                  per second against 8 TB/s
   cpu_baseline   the FP64 CPU oracle on a bounded sample (see cpu_baseline())
 
   --calibrate-copy   only time a plain device copy of 1 GiB (the reference kernel
                      for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit
+  --summarize-trace DIR [--trace-last-from LINE.json]
+                     turn a rocprofv3 --kernel-trace --stats CSV directory into the
+                     kernel-time summary (JSON on stdout): per kernel over all
+                     dispatches, and over the last dispatches of the profiled pass
 """
 from __future__ import annotations
 
@@ -63,6 +74,10 @@ def parse():
     ap.add_argument("--gemm-tile", type=int, default=0, choices=[0, 64, 128],
                     help="output tile edge of the product launches (0: autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--summarize-trace", default="", help="rocprofv3 kernel-trace CSV directory")
+    ap.add_argument("--trace-last-from", default="", help="bench output whose profiled pass the trace ends with")
+    ap.add_argument("--cpu-record", action="store_true",
+                    help="time the oracle on the full workload and on the bench's sample (no GPU)")
     return ap.parse_args()
 
 
@@ -185,24 +200,59 @@ def stored_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def roofline(kernels, workload):
+def stored_kernel_time(kernel, workload, precision):
+    """Mean launch time (ms) of the kernel over the profiled pass in the committed
+    rocprofv3 kernel-time summary, if it was taken on the current source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src, dig = source_digest(kernel)
+    if src is None or d.get("sources", {}).get(src) != dig:
+        return None
+    k = d.get("pass", {}).get(kernel)
+    return k["avg_us"] * 1e-3 if k else None
+
+
+def roofline(kernels, workload, precision):
     name = max((k for k in kernels if k in KERNEL_PREC), key=lambda k: kernels[k]["ms"])
     d = kernels[name]
     n = max(d["launches"], 1)
     avg_s = d["ms"] / n * 1e-3
     achieved = d["flops"] / n / avg_s if avg_s > 0 else 0.0
+    tile = d["tile_flops"] / n / avg_s if avg_s > 0 else 0.0
     peak = PEAK_FLOPS[KERNEL_PREC[name]]
-    return {"kernel": name, "bound": "mfma", "achieved": round(achieved / 1e12, 3),
-            "peak": round(peak / 1e12, 1), "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": stored_traffic(name, workload), "launches": d["launches"],
-            "avg_launch_ms": round(d["ms"] / n, 5), "flops_per_launch": d["flops"] / n,
-            "arith": KERNEL_PREC[name]}
+    out = {"kernel": name, "bound": "mfma", "achieved": round(achieved / 1e12, 3),
+           "peak": round(peak / 1e12, 1), "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+           "traffic": stored_traffic(name, workload), "launches": d["launches"],
+           "avg_launch_ms": round(d["ms"] / n, 5), "flops_per_launch": d["flops"] / n,
+           "tile_flops_per_launch": d["tile_flops"] / n, "tile_achieved": round(tile / 1e12, 3),
+           "arith": KERNEL_PREC[name]}
+    rp = stored_kernel_time(name, workload, precision)
+    if rp:
+        out["rocprof_avg_launch_ms"] = round(rp, 5)
+        out["achieved_rocprof"] = round(d["flops"] / n / rp * 1e-3 / 1e9, 3) if rp > 0 else None
+    return out
 
 
-def mfma_util(kernels, factor_ms):
-    t_ideal = sum(kernels[k]["flops"] / PEAK_FLOPS[p] for k, p in KERNEL_PREC.items()
-                  if k in kernels and not k.startswith("potrf"))
-    return round(t_ideal / (factor_ms * 1e-3), 4) if factor_ms > 0 else None
+PANEL_CLASSES = ("panel_potrf", "panel_trsm", "panel_trailing")
+ARITH_PEAK = {"f64": PEAK_FLOPS["f64"], "f32": PEAK_FLOPS["f32"], "bf16": PEAK_FLOPS["bf16"]}
+
+
+def mfma_util(classes, factor_ms):
+    """Time-weighted MFMA utilisation of the factorization and of its two parts."""
+    def ideal(names):
+        return sum(classes[c]["flops_arith"][a] / ARITH_PEAK[a] for c in names for a in ARITH_PEAK)
+    fact = [c for c in classes if c != "pcg"]
+    rest = [c for c in fact if c not in PANEL_CLASSES]
+    t_diag = sum(classes[c]["ms"] for c in PANEL_CLASSES) * 1e-3
+    t_rest = sum(classes[c]["ms"] for c in rest) * 1e-3
+    out = {"factor": round(ideal(fact) / (factor_ms * 1e-3), 4) if factor_ms > 0 else None,
+           "diag_factor": round(ideal(PANEL_CLASSES) / t_diag, 4) if t_diag > 0 else None,
+           "supernode_rest": round(ideal(rest) / t_rest, 4) if t_rest > 0 else None,
+           "flops_by_arith": {a: sum(classes[c]["flops_arith"][a] for c in fact) for a in ARITH_PEAK}}
+    return out
 
 
 def pcg_hbm(desc, stats, iters, pcg_ms):
@@ -216,46 +266,105 @@ def pcg_hbm(desc, stats, iters, pcg_ms):
             "frac": round(gbs / PEAK_HBM, 4)}
 
 
-def cpu_baseline(name, cfg, side, gpu_desc):
-    """The oracle as it stands (plain NumPy/SciPy FP64), on a bounded sample: the full
-    pipeline -- symbolic analysis, factor, PCG to the same rtol -- on a cube of side
-    `side` with the workload's own coefficient law, seed, tol and rtol; then, for the
-    metric's unit, scaled to the workload's size by the oracle's measured growth
-    between side / 2 and side (T ~ n^gamma).  Both measured times are reported."""
-    import numpy as np
+def _host_info():
+    info = {"cpu_count": os.cpu_count()}
+    try:
+        from threadpoolctl import threadpool_info
+        import numpy  # noqa: F401  (loads the BLAS threadpoolctl reports)
+        info["blas"] = [{"api": d.get("internal_api"), "threads": d.get("num_threads")}
+                        for d in threadpool_info()]
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            info["cpu"] = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        pass
+    return info
 
+
+def _oracle_run(cfg, dims, report=False):
+    """The oracle's full pipeline (symbolic, factor, PCG to rtol) on a grid of the
+    workload's law: seconds per phase, iterations.  report: a line on stderr after each
+    phase and after each supernode that ends 30 s of factor work."""
     from oracle.factor import Options, factor
     from oracle.ordering import symbolic
     from oracle.solve import solve
     from workloads import grid_problem
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count()
-    d = 2 if cfg.get("dims") is not None and len(cfg["dims"]) == 2 else 3
-    if "count" in cfg:
-        d = 2
+    p = grid_problem(dims, sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg.get("unit", False))
+    last = [time.perf_counter()]
 
-    def run(s):
-        p = grid_problem((s,) * d, sigma=cfg["sigma"], seed=cfg["seed"], unit=cfg.get("unit", False))
-        t0 = time.perf_counter()
-        sym = symbolic(p.n, p.rowptr, p.colind, 64)
-        F = factor(sym, p.n, p.rowptr, p.colind, p.values, cfg["tol"], Options(seed=0))
-        r = solve(F, p.matrix(), p.b, rtol=cfg["rtol"])
-        return time.perf_counter() - t0, p.n, r.iters
+    def say(msg):
+        if report:
+            print(f"oracle {'x'.join(map(str, dims))}: {msg}", file=sys.stderr, flush=True)
 
-    t_half, n_half, _ = run(max(side // 2, 4))
-    t_full, n_full, it = run(side)
-    gamma = float(np.log(t_full / t_half) / np.log(n_full / n_half)) if t_half > 0 else 1.0
-    gamma = min(max(gamma, 1.0), 2.0)
-    est = t_full * (gpu_desc["n"] / n_full) ** gamma
-    return dict(value=round(est, 2), unit="s", cores=int(threads), kind="oracle",
-                sample=(f"oracle symbolic+factor+PCG(rtol {cfg['rtol']}) on the same law at side {side} "
-                        f"(n={n_full}: {t_full:.2f} s, {it} iterations) and side {max(side // 2, 4)} "
-                        f"(n={n_half}: {t_half:.2f} s); scaled to n={gpu_desc['n']} as n^{gamma:.2f}"),
-                sample_s=round(t_full, 3), half_sample_s=round(t_half, 3), gamma=round(gamma, 3))
+    def progress(j, M):
+        if report and time.perf_counter() - last[0] >= 30.0:
+            last[0] = time.perf_counter()
+            say(f"factor: supernode {j + 1} of {M}, {last[0] - t1:.0f} s")
+
+    t0 = time.perf_counter()
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    t1 = time.perf_counter()
+    say(f"symbolic {t1 - t0:.1f} s")
+    last[0] = t1
+    F = factor(sym, p.n, p.rowptr, p.colind, p.values, cfg["tol"], Options(seed=0), progress=progress)
+    t2 = time.perf_counter()
+    say(f"factor {t2 - t1:.1f} s")
+    r = solve(F, p.matrix(), p.b, rtol=cfg["rtol"])
+    t3 = time.perf_counter()
+    say(f"pcg {t3 - t2:.1f} s, {r.iters} iterations")
+    return {"dims": list(dims), "n": p.n, "seconds": t3 - t0, "symbolic_s": t1 - t0, "factor_s": t2 - t1,
+            "pcg_s": t3 - t2, "iters": int(r.iters), "true_residual": r.true_residual}
+
+
+def _sample_dims(cfg, side):
+    d = 2 if ("count" in cfg or len(cfg["dims"]) == 2) else 3
+    return (side,) * d
+
+
+def cpu_record(name, cfg, side):
+    """The oracle timed on this host on the whole workload and on the bench's bounded
+    sample (JSON on stdout; kept under profiles/ as cpu_oracle_<workload>.json)."""
+    full = _oracle_run(cfg, tuple(cfg["dims"]), report=True)
+    sample = _oracle_run(cfg, _sample_dims(cfg, side), report=True)
+    print(json.dumps({"workload": name, "host": _host_info(), "full": full, "sample": sample,
+                      "command": f"python bench.py --workload {name} --cpu-record --cpu-sample-side {side}"}),
+          flush=True)
+
+
+def cpu_baseline(name, cfg, side, gpu_desc):
+    """The oracle as it stands (plain NumPy/SciPy FP64) on a bounded sample: the full
+    pipeline -- symbolic analysis, factor, PCG to the same rtol -- on a grid of side
+    `side` with the workload's own coefficient law, seed, tol and rtol, timed here.
+    The value is the oracle's time on the whole workload as measured on a host of this
+    kind (profiles/cpu_oracle_<workload>.json, written by --cpu-record), corrected by how
+    this run's sample time compares with that record's; without the record, the sample
+    time alone, scaled by nothing, with value null."""
+    dims = _sample_dims(cfg, side)
+    live = _oracle_run(cfg, dims)
+    host = _host_info()
+    threads = max([b.get("threads") or 1 for b in host.get("blas", [])] or [os.cpu_count() or 1])
+    out = dict(value=None, unit="s", cores=int(threads), kind="oracle",
+               sample=(f"oracle symbolic+factor+PCG(rtol {cfg['rtol']}) on the workload's law at "
+                       f"{'x'.join(map(str, dims))} (n={live['n']}): {live['seconds']:.2f} s, "
+                       f"{live['iters']} iterations"),
+               sample_s=round(live["seconds"], 3))
+    path = os.path.join(ROOT, "profiles", f"cpu_oracle_{name}.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec["sample"]["dims"] == list(dims) and rec["sample"]["seconds"] > 0:
+            scale = live["seconds"] / rec["sample"]["seconds"]
+            out["value"] = round(rec["full"]["seconds"] * scale, 2)
+            out["measured_full_s"] = round(rec["full"]["seconds"], 2)
+            out["measured_full_phases_s"] = {k: round(rec["full"][k], 1) for k in ("symbolic_s", "factor_s", "pcg_s")}
+            out["host_speed_vs_record"] = round(scale, 3)
+            out["sample"] += (f"; value = the oracle's measured time on the whole workload "
+                              f"({rec['full']['seconds']:.1f} s, profiles/cpu_oracle_{name}.json) x this "
+                              f"run's sample time / the record's ({rec['sample']['seconds']:.2f} s)")
+    return out
 
 
 def calibrate_copy():
@@ -275,6 +384,60 @@ def calibrate_copy():
                       "GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
 
 
+_MODE_NAMES = {0: "f64", 1: "f32", 2: "bf16x3", 3: "bf16"}
+
+
+def profile_name(rocprof_name):
+    """Kernel name of the library's profile for a rocprofv3 kernel name (or None)."""
+    import re
+    m = re.search(r"k_gemm_staged<(\d), (\d+)>", rocprof_name)
+    if m:
+        return f"gemm_staged{'128' if m.group(2) == '128' else ''}_{_MODE_NAMES[int(m.group(1))]}"
+    m = re.search(r"k_update_waves<(\d)>", rocprof_name)
+    if m:
+        return f"update_waves_{_MODE_NAMES[int(m.group(1))]}"
+    m = re.search(r"rsc::k_(\w+)", rocprof_name)
+    return m.group(1) if m else None
+
+
+def summarize_trace(d, last_from):
+    """Per-kernel dispatch counts and durations of a rocprofv3 kernel trace: over all
+    dispatches, and over the last N dispatches of each kernel, N = its launch count in
+    the profiled pass of the bench line in `last_from` (that pass is the run's last)."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                             r["Kernel_Name"]))
+    rows.sort()
+    per = {}
+    for _, dur, nm in rows:
+        per.setdefault(nm, []).append(dur)
+    allk = {nm: {"calls": len(v), "total_ms": sum(v) * 1e-6, "avg_us": sum(v) / len(v) * 1e-3}
+            for nm, v in per.items()}
+    out = {"all": dict(sorted(allk.items(), key=lambda kv: -kv[1]["total_ms"])),
+           "sources": {src: source_digest(k)[1] for k, src in KERNEL_SOURCE.items()}}
+    if last_from:
+        with open(last_from) as fh:
+            line = json.loads(next(l for l in reversed(fh.read().splitlines()) if l.startswith('{"metric"')))
+        out["bench_line"] = line
+        pas = {}
+        for k, v in line.get("kernels", {}).items():
+            durs = [x for nm, xs in per.items() if profile_name(nm) == k for x in xs]
+            n = v["launches"]
+            if len(durs) < n:
+                continue
+            # last n dispatches of this kernel (trace order)
+            seq = sorted((t, dur) for t, dur, nm in rows if profile_name(nm) == k)[-n:]
+            pas[k] = {"launches": n, "avg_us": sum(x for _, x in seq) / n * 1e-3,
+                      "bench_event_avg_us": v["ms"] / n * 1e3}
+        out["pass"] = pas
+    print(json.dumps(out, indent=1), flush=True)
+
+
 # ------------------------------------------------------------------ main
 
 def main():
@@ -283,11 +446,18 @@ def main():
         print(f"bench.py: this path runs on one GPU (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design only and is not implemented", file=sys.stderr)
         sys.exit(2)
+    name = args.workload
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.trace_last_from)
+        return
+    if args.cpu_record:
+        from workloads import workload_config
+        cpu_record(name, workload_config(name), args.cpu_sample_side)
+        return
     import torch
     if args.calibrate_copy:
         calibrate_copy()
         return
-    name = args.workload
     precision = args.precision or DEFAULT_PRECISION.get(name, "fp64")
     compare = args.compare
     if compare == "auto":
@@ -338,11 +508,15 @@ def main():
         line["speedup_vs_" + compare] = round(cmp["sec_per_step"] / res["sec_per_step"], 3)
     if "kernels" in res:
         ks = res["kernels"]
-        line["roofline"] = roofline(ks, name)
-        line["mfma_util"] = mfma_util(ks, res["profiled_factor_ms"])
+        line["roofline"] = roofline(ks, name, precision)
+        mu = mfma_util(res["classes"], res["profiled_factor_ms"])
+        line["mfma_util"] = mu["factor"]
+        line["mfma_util_parts"] = {k: mu[k] for k in ("diag_factor", "supernode_rest")}
         top = sorted(ks.items(), key=lambda kv: -kv[1]["ms"])[:8]
         line["kernels"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                               "tflop_s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0}
+                               "tflop_s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 else 0.0,
+                               "tile_tflop_s": round(v["tile_flops"] / (v["ms"] * 1e-3) / 1e12, 2)
+                               if v["ms"] > 0 else 0.0}
                            for k, v in top}
         line["classes_ms"] = {k: round(v["ms"], 3) for k, v in res["classes"].items() if v["launches"]}
     line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])

@@ -115,10 +115,21 @@ typedef struct {
 enum { RSC_K_UPDATE = 0, RSC_K_POTRF = 1, RSC_K_TRSM = 2, RSC_K_GEMM = 3, RSC_K_EIG = 4,
        RSC_K_PCG = 5, RSC_K_OTHER = 6, RSC_K_LO = 7, RSC_K_SAMPLE = 8, RSC_K_ORTH = 9,
        RSC_K_BASIS = 10, RSC_K_CLASSES = 11 };
+/* Flops are counted two ways.  Algorithmic: the work of the method's own steps per
+ * supernode from the symbolic plan -- POTRF c^3/3, off-diagonal solve r c^2, Schur updates
+ * (SYRK lower half + GEMM) per descendant pair, sampling 2 r c l per product with L^O,
+ * orthonormalisation 2 c l^2, Gram matrix 2 r l^2, eigen-truncation 9 l^3 (a symmetric
+ * eigensolver's count), kept basis 2 (r + c) l q -- each step's total split over the
+ * launches that carry it in proportion to their tile work; explicit inverses, extra
+ * orthonormalisation passes and padding earn nothing.  Tile: what the launched tiles
+ * execute (2 m n k per tile, ragged edges exact). */
+enum { RSC_ARITH_F64 = 0, RSC_ARITH_F32 = 1, RSC_ARITH_BF16 = 2, RSC_ARITHS = 3 };
 typedef struct {
   int64_t launches[RSC_K_CLASSES];
   double ms[RSC_K_CLASSES];
-  double flops[RSC_K_CLASSES];   /* algorithmic flops of the timed launches */
+  double flops[RSC_K_CLASSES];        /* algorithmic flops of the timed launches */
+  double tile_flops[RSC_K_CLASSES];   /* executed tile flops of the timed launches */
+  double flops_arith[RSC_K_CLASSES][RSC_ARITHS];  /* algorithmic flops by MFMA arithmetic */
 } rsc_profile;
 
 /* Fill *opt with the defaults listed beside each field. */
@@ -215,13 +226,13 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
 /* The same timings per kernel (and precision mode) rather than per class: entry k in
  * [0, RSC_KERNELS) gives the kernel's name (static string), its launch count, the
  * summed hipEvent time of those launches in ms (events on the launch stream, so
- * each interval is one launch) and their algorithmic flops (launches whose extents
- * depend on the kept ranks are counted at the ranks of the factorisation that ran).
- * Any output may be NULL.  Errors: RSC_ERR_INVALID_ARG for a null handle or k out of
- * range. */
+ * each interval is one launch), their algorithmic flops and their executed tile flops
+ * (both as for rsc_profile; launches whose extents depend on the kept ranks are counted
+ * at the ranks of the factorisation that ran).  Any output may be NULL.  Errors:
+ * RSC_ERR_INVALID_ARG for a null handle or k out of range. */
 #define RSC_KERNELS 36
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
-                                  double* ms, double* flops);
+                                  double* ms, double* flops, double* tile_flops);
 
 /* Device memory.  Every device allocation of the library (factor arena, task lists, work
  * buffers) is made by alloc(bytes, stream, ctx) and returned by release(ptr, stream, ctx)

@@ -132,8 +132,9 @@ def compress(LO: np.ndarray, j: int, opts: Options, tol: float):
 
 
 def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
-           opts: Options | None = None, stop_after: int | None = None) -> Factor:
-    """Factor supernodes ``0 .. M-1`` (or the first ``stop_after``) in order."""
+           opts: Options | None = None, stop_after: int | None = None, progress=None) -> Factor:
+    """Factor supernodes ``0 .. M-1`` (or the first ``stop_after``) in order.
+    ``progress(j, M)``, if given, is called after each supernode (reporting only)."""
     opts = opts or Options()
     Ap = permuted_matrix(sym, n, rowptr, colind, values)
     F = Factor(sym=sym, tol=tol, opts=opts)
@@ -174,6 +175,8 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
             fl["trunc"] += 2.0 * R.size * ell * ell
         else:
             F.LO.append(LO); F.V.append(None); F.U.append(None); F.ell.append(0); F.q.append(0)
+        if progress is not None:
+            progress(j, M)
     F.flops = fl
     return F
 

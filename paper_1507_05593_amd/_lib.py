@@ -50,9 +50,13 @@ class Stats(C.Structure):
                 ("gemm_tuned", C.c_int64), ("gemm_tile128", C.c_int64)]
 
 
+ARITHS = ("f64", "f32", "bf16")
+
+
 class Profile(C.Structure):
     _fields_ = [("launches", C.c_int64 * len(K_CLASSES)), ("ms", C.c_double * len(K_CLASSES)),
-                ("flops", C.c_double * len(K_CLASSES))]
+                ("flops", C.c_double * len(K_CLASSES)), ("tile_flops", C.c_double * len(K_CLASSES)),
+                ("flops_arith", (C.c_double * len(ARITHS)) * len(K_CLASSES))]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -88,7 +92,7 @@ SYMBOLS = {
     "rsc_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "rsc_get_profile": (C.c_int, [C.c_void_p, C.POINTER(Profile)]),
     "rsc_get_kernel_profile": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
-                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rsc_set_allocator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),   # ALLOC_FN, RELEASE_FN or NULL
     "rsc_status_string": (C.c_char_p, [C.c_int]),
     "rsc_last_error": (C.c_char_p, []),

@@ -314,6 +314,9 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
     out->flops_sample = h.fplan->flops[3];
     out->flops_orth = h.fplan->flops[4];
     out->flops_trunc = h.fplan->flops[5];
+    if (comp)   // the kept basis U Z_q, V Z_q at the ranks
+      for (int64_t j = 0; j < S.M(); ++j)
+        if (h.compressible[j]) out->flops_trunc += 2.0 * (S.c(j) + S.r(j)) * (double)h.comp[j].ell * q[j];
   }
   out->flops_update = fl_update;
   out->bytes_factor = h.splan ? h.splan->bytes * (h.f32_valid ? 0.5 : 1.0) : 0.0;
@@ -328,18 +331,20 @@ rsc_status rsc_profile_enable(rsc_handle H, int32_t on) {
     H->h.kprof_launches[k] = 0;
     H->h.kprof_ms[k] = 0.0;
     H->h.kprof_flops[k] = 0.0;
+    H->h.kprof_tile_flops[k] = 0.0;
   }
   return RSC_OK;
 }
 
 rsc_status rsc_get_kernel_profile(rsc_handle H, int32_t k, const char** name, int64_t* launches,
-                                  double* ms, double* flops) {
+                                  double* ms, double* flops, double* tile_flops) {
   if (!H) return fail(RSC_ERR_INVALID_ARG, "null handle");
   if (k < 0 || k >= RSC_KERNELS) return fail(RSC_ERR_INVALID_ARG, "kernel index out of range");
   if (name) *name = rsc::kernel_name(k);
   if (launches) *launches = H->h.kprof_launches[k];
   if (ms) *ms = H->h.kprof_ms[k];
   if (flops) *flops = H->h.kprof_flops[k];
+  if (tile_flops) *tile_flops = H->h.kprof_tile_flops[k];
   return RSC_OK;
 }
 

@@ -1,5 +1,6 @@
-// gfx950 kernels of the numeric factorization: assembly, Schur-complement updates,
-// diagonal-block Cholesky, tile GEMMs, Gaussian sampling, Jacobi eigensolver.
+// gfx950 kernels of the numeric factorization: assembly, fills, identity scatter,
+// diagonal-block Cholesky, Gaussian sampling, Gram scale and the spectral-truncation
+// helpers (Newton-Schulz projector iteration in LDS, projector trace, basis compaction).
 //
 // Matrix-core layouts (CDNA4, 64-lane waves):
 //   v_mfma_f64_16x16x4f64: A(i,k) from lane i + 16k, B(k,j) from lane j + 16k,

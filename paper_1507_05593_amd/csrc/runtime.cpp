@@ -483,6 +483,15 @@ struct Builder {
     }
   }
 
+  // Algorithmic flops of one step of the method, `total`, split over the commands
+  // emitted since command index c0 in proportion to their tile work.
+  void credit(size_t c0, double total) {
+    double ex = 0;
+    for (size_t i = c0; i < P.cmds.size(); ++i) ex += P.cmds[i].flops;
+    if (ex <= 0) return;
+    for (size_t i = c0; i < P.cmds.size(); ++i) P.cmds[i].mflops += total * P.cmds[i].flops / ex;
+  }
+
   // Tiles of C(i, j) for i in [ib, m), j in [jb, n); lower: skip tiles lying strictly
   // above the diagonal.
   double tiles(GemmTask t, int32_t ib, int32_t jb, bool lower, std::vector<GemmTask>* out = nullptr) {
@@ -596,11 +605,13 @@ struct Builder {
   void offdiag_solve(const std::vector<int32_t>& level) {
     const Symbolic& S = h.S;
     const int64_t g0 = (int64_t)P.gemm.size();
-    double fl = 0;
+    const size_t c0 = P.cmds.size();
+    double fl = 0, mfl = 0;
     for (int32_t j : level) {
       const int32_t c = S.c(j), r = S.r(j), ld = h.panel_ld[j];
       if (r == 0) continue;
       const int64_t pan = h.a_panels + h.panel_off[j];
+      mfl += (double)r * c * c;
       GemmTask t = gt(pan + c, 1, ld, pan + c + r, ld, 1, h.a_lo + h.lo_off[j], r, r, c, c, 1.0, 0.0);
       for (int32_t j0 = 0; j0 < c; j0 += kTile)
         for (int32_t i0 = 0; i0 < r; i0 += kTile) {
@@ -611,19 +622,21 @@ struct Builder {
         }
     }
     cmd(kCmdGemm, RSC_K_LO, g0, (int64_t)P.gemm.size() - g0, fl, lp_update);
+    credit(c0, mfl);
   }
 
   // Schur-complement updates of every supernode of one level (Algorithm 1, the
   // descendant loop), as target tiles with ordered contribution lists.
   void updates(const std::vector<int32_t>& level) {
     const Symbolic& S = h.S;
-    struct TileW { UpdTile t; double work; std::vector<UpdEntry> e; std::vector<double> ke; };
+    struct TileW { UpdTile t; double work; std::vector<UpdEntry> e; std::vector<double> ke, lw; };
     std::vector<TileW> all;
     for (int32_t j : level) {
       const int32_t c = S.c(j), r = S.r(j);
       const int32_t nI = (c + r + kTile - 1) / kTile, nJ = (c + kTile - 1) / kTile;
       std::vector<std::vector<UpdEntry>> ents((size_t)nI * nJ);
       std::vector<std::vector<double>> kes((size_t)nI * nJ);   // planning inner dimension
+      std::vector<std::vector<double>> lws((size_t)nI * nJ);   // pairs on or below the diagonal
       std::vector<double> work((size_t)nI * nJ, 0.0);
       for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
         const Pair& pr = S.pairs[q];
@@ -665,8 +678,15 @@ struct Builder {
             UpdEntry e = base;
             e.a = R[1]; e.b = R[2]; e.c = Cc[1]; e.d = Cc[2];
             const size_t id = (size_t)R[0] * nJ + Cc[0];
+            // SYRK lower half in a diagonal tile (gathered row t >= column s), else all
+            double lw = (double)(e.b - e.a) * (e.d - e.c);
+            if (R[0] == Cc[0]) {
+              lw = 0;
+              for (int32_t s2 = e.c; s2 < e.d; ++s2) lw += std::max(0, e.b - std::max(e.a, s2));
+            }
             ents[id].push_back(e);
             kes[id].push_back(kest);
+            lws[id].push_back(lw);
             work[id] += 2.0 * (e.b - e.a) * (e.d - e.c) * kest;
           }
       }
@@ -683,6 +703,7 @@ struct Builder {
           tw.work = work[id];
           tw.e = std::move(ents[id]);
           tw.ke = std::move(kes[id]);
+          tw.lw = std::move(lws[id]);
           all.push_back(std::move(tw));
         }
     }
@@ -692,7 +713,7 @@ struct Builder {
     // within a tile: entries wider than 32 first (list order), then the others by
     // decreasing inner dimension, so that the four entries taken together are alike
     const int64_t t0 = (int64_t)P.tiles.size();
-    double fl = 0;
+    double fl = 0, mfl = 0;
     bool dyn = false;
     for (auto& tw : all) {
       std::vector<int32_t> idx(tw.e.size());
@@ -709,14 +730,18 @@ struct Builder {
         const UpdEntry& e = tw.e[q];
         if (big(q)) ++tw.t.es;
         fl += 2.0 * (e.b - e.a) * (e.d - e.c) * tw.ke[q];
+        mfl += 2.0 * tw.lw[q] * tw.ke[q];
         dyn |= (e.kdim < 0);
         P.ents.push_back(e);
+        P.ent_lower.push_back(tw.lw[q]);
       }
       tw.t.e1 = (int32_t)P.ents.size();
       P.tiles.push_back(tw.t);
     }
     cmd(kCmdUpdate, RSC_K_UPDATE, t0, (int64_t)P.tiles.size() - t0, fl, lp_update);
     P.cmds.back().dyn = dyn;
+    P.cmds.back().mflops = mfl;
+    P.cmds.back().mkind = 1;
   }
 
   // Compact row-major copies of the Schur-update operands of a level once they are
@@ -801,6 +826,16 @@ struct Builder {
       if (h.compressible[j]) js.push_back(j);
     if (js.empty()) return;
     ctx = RSC_K_SAMPLE;
+    // algorithmic work of the steps (summed over the level's compressible supernodes)
+    double m_prod = 0, m_orth = 0, m_gram = 0, m_eig = 0;
+    for (int32_t j : js) {
+      const double c = S.c(j), r = S.r(j), l = h.comp[j].ell;
+      m_prod += 2.0 * r * c * l;       // one product with L^O_j or its transpose
+      m_orth += 2.0 * c * l * l;       // orthonormalisation of the c x l sample
+      m_gram += 2.0 * r * l * l;       // Gram matrix of V
+      m_eig += 9.0 * l * l * l;        // symmetric eigen-decomposition of the l x l Gram matrix
+    }
+    size_t cs = P.cmds.size();
     // 1. Gaussian samples
     const int64_t ph0 = (int64_t)P.philox.size();
     int64_t maxw = 0;
@@ -825,12 +860,14 @@ struct Builder {
       fl += tiles(gt(LO, r, 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_sample);
+    credit(cs, m_prod);
     // 3. power iterations Y = (L^O)^T (L^O Y).  Each product is preceded by one shifted
     //    Cholesky-QR pass over its operand: the span is unchanged (a right factor), but the
     //    operand's spread of singular values no longer compounds over the iterations, so
     //    no direction that the final orthonormalisation would keep sinks below rounding.
     for (int it = 0; it < h.opt.power_iters; ++it) {
       cholqr_pass(js, false, true);
+      cs = P.cmds.size();
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
@@ -839,7 +876,9 @@ struct Builder {
         fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.zpanel + l, l + r, r, l, c, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      credit(cs, m_prod);
       cholqr_pass(js, true, true);
+      cs = P.cmds.size();
       g0 = (int64_t)P.gemm.size(); fl = 0;
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
@@ -848,6 +887,7 @@ struct Builder {
         fl += tiles(gt(LO, r, 1, C.zpanel + l, l + r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      credit(cs, m_prod);
     }
     ctx = RSC_K_ORTH;
     // 4. orthonormalisation by Cholesky-QR passes, dependent columns dropped.  Two plain
@@ -857,10 +897,13 @@ struct Builder {
     //    pass is shifted (shifted Cholesky-QR3: three passes), which keeps every direction
     //    above the rounding of Y.
     const bool accurate = tol < 1e-5;
+    cs = P.cmds.size();
     for (int pass = 0; pass < (accurate ? 3 : 2); ++pass) cholqr_pass(js, false, accurate && pass == 0);
+    credit(cs, m_orth);
     ctx = RSC_K_BASIS;
     // 5. V = L^O_j U (FP32 MFMA in the mixed forms, like the other basis products: its
     //    rounding, ~1e-7 of |V|, is far below the truncation threshold tol^2 lambda_max)
+    cs = P.cmds.size();
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
@@ -869,8 +912,10 @@ struct Builder {
       fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
+    credit(cs, m_prod);
     ctx = RSC_K_EIG;
     // 6. Gram G = V^T V (full)
+    cs = P.cmds.size();
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
@@ -878,6 +923,8 @@ struct Builder {
       fl += sym_tiles(gt(C.V, r, 1, C.V, r, 1, C.G, l, l, l, r, 1.0, 0.0));
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+    credit(cs, m_gram);
+    cs = P.cmds.size();   // the eigen-truncation's launches, up to the kept basis
     // 7. spectral projector onto lambda > tol^2 lambda_max (see the truncation kernels)
     const int64_t t0 = (int64_t)P.trunc.size();
     for (int32_t j : js) {
@@ -1016,6 +1063,7 @@ struct Builder {
       cmd(kCmdTruncCompact, RSC_K_EIG, t0, nt, 0);
       cmd(kCmdTruncCopy, RSC_K_EIG, t0, nt, 0, lmax);
     }
+    credit(cs, m_eig);
     // 9. U_j = U W, V_j = V W (columns beyond the device rank q_j are skipped)
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
@@ -1028,7 +1076,10 @@ struct Builder {
       t2.nlim = C.qslot;
       fl += tiles(t2, 0, 0, false);
     }
+    cs = P.cmds.size();
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
+    // the kept basis U Z_q, V Z_q: algorithmic = executed (exact extents, at the ranks)
+    for (size_t i = cs; i < P.cmds.size(); ++i) { P.cmds[i].mflops = P.cmds[i].flops; P.cmds[i].mkind = 2; }
     ctx = -1;
   }
 };
@@ -1121,7 +1172,11 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
       pd.skip_mid = true;
       pan.push_back(pd);
     }
+    const size_t cp = P->cmds.size();
+    double m_potrf = 0;
+    for (int32_t j : lev) m_potrf += std::pow((double)S.c(j), 3) / 3.0;
     B.panel_steps(pan);
+    B.credit(cp, m_potrf);
     B.offdiag_solve(lev);
     B.compact_operands(lev, false);
     if (compressed) {
@@ -1138,8 +1193,8 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
     if (compressed && h.compressible[j]) {
       const double l = h.comp[j].ell;
       P->flops[3] += 4.0 * r * c * l * (1 + h.opt.power_iters);
-      P->flops[4] += 3.0 * (2.0 * c * l * l + l * l * l / 3.0);
-      P->flops[5] += 2.0 * r * l * l + (2.0 * 5 + 4.0 * kNewtonSchulzSteps + 2.0) * l * l * l;
+      P->flops[4] += 2.0 * c * l * l;
+      P->flops[5] += 2.0 * r * l * l + 9.0 * l * l * l;   // + the kept basis, at the ranks (stats)
     }
   }
   Error e;
@@ -1180,18 +1235,41 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
 
 // ------------------------------------------------------------------ executor
 
-struct EventPair { hipEvent_t a, b; int32_t klass, kid; double flops; const Cmd* cmd; const FactorPlan* plan; };
+struct EventPair {
+  hipEvent_t a, b;
+  int32_t klass, kid, arith;   // arith: RSC_ARITH_* of the launch's MFMA work, -1 none
+  double flops, mflops;        // executed tile flops, algorithmic flops
+  const Cmd* cmd;
+  const FactorPlan* plan;
+};
+
+// MFMA arithmetic of a command (RSC_ARITH_*), or -1 when it has no MFMA work.
+static int32_t cmd_arith(const Cmd& c) {
+  switch (c.type) {
+    case kCmdGemm: case kCmdUpdate: {
+      const int m = (int)(c.a & 3);
+      return m == 0 ? RSC_ARITH_F64 : m == 1 ? RSC_ARITH_F32 : RSC_ARITH_BF16;
+    }
+    case kCmdPotrf: return RSC_ARITH_F64;
+    case kCmdTruncNs: return c.a != 0 ? RSC_ARITH_F32 : RSC_ARITH_F64;
+    default: return -1;
+  }
+}
 
 // Flops of a launch whose extents come from device ranks, from its tasks and the
-// ranks as they stand (I: host copy of the int arena).
-static double recount_flops(const Cmd& c, const FactorPlan& P, const std::vector<int32_t>& I) {
+// ranks as they stand (I: host copy of the int arena): executed tile flops, and in *mfl
+// the algorithmic flops of a Schur update (the entries' pairs on or below the diagonal).
+static double recount_flops(const Cmd& c, const FactorPlan& P, const std::vector<int32_t>& I,
+                            double* mfl) {
   double fl = 0;
+  *mfl = 0;
   if (c.type == kCmdUpdate) {
     for (int64_t t = c.off; t < c.off + c.count; ++t)
       for (int32_t i = P.tiles[t].e0; i < P.tiles[t].e1; ++i) {
         const UpdEntry& e = P.ents[i];
         const double K = e.kdim >= 0 ? e.kdim : I[-1 - e.kdim];
         fl += 2.0 * (e.b - e.a) * (e.d - e.c) * K;
+        *mfl += 2.0 * P.ent_lower[i] * K;
       }
   } else if (c.type == kCmdGemm) {
     const int32_t T = (int32_t)c.b;
@@ -1324,7 +1402,9 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
       HIPCHK(hipEventCreate(&ep.b));
       ep.klass = c.klass;
       ep.kid = kernel_id(c.type, c.a, c.b);
+      ep.arith = cmd_arith(c);
       ep.flops = c.flops;
+      ep.mflops = c.mflops;
       ep.cmd = c.dyn ? &c : nullptr;
       ep.plan = P;
       HIPCHK(hipEventRecord(ep.a, s));
@@ -1349,14 +1429,20 @@ static Error collect_events(Handle& h, std::vector<EventPair>& evs) {
         ints.resize((size_t)h.ints_size);
         HIPCHK(hipMemcpy(ints.data(), h.ints.p, sizeof(int32_t) * ints.size(), hipMemcpyDeviceToHost));
       }
-      ep.flops = recount_flops(*ep.cmd, *ep.plan, ints);
+      double mfl = 0;
+      ep.flops = recount_flops(*ep.cmd, *ep.plan, ints, &mfl);
+      if (ep.cmd->mkind == 1) ep.mflops = mfl;
+      else if (ep.cmd->mkind == 2) ep.mflops = ep.flops;
     }
     h.prof.launches[ep.klass] += 1;
     h.prof.ms[ep.klass] += ms;
-    h.prof.flops[ep.klass] += ep.flops;
+    h.prof.flops[ep.klass] += ep.mflops;
+    h.prof.tile_flops[ep.klass] += ep.flops;
+    if (ep.arith >= 0) h.prof.flops_arith[ep.klass][ep.arith] += ep.mflops;
     h.kprof_launches[ep.kid] += 1;
     h.kprof_ms[ep.kid] += ms;
-    h.kprof_flops[ep.kid] += ep.flops;
+    h.kprof_flops[ep.kid] += ep.mflops;
+    h.kprof_tile_flops[ep.kid] += ep.flops;
     (void)hipEventDestroy(ep.a);
     (void)hipEventDestroy(ep.b);
   }

@@ -39,7 +39,10 @@ struct Cmd {
   int64_t count;        // number of tasks (or elements)
   int64_t a, b;         // command-specific
   double v;             // command-specific
-  double flops;         // algorithmic flops of the launch (profiling)
+  double flops;         // executed tile flops of the launch (profiling)
+  double mflops = 0;    // algorithmic flops of the method credited to the launch
+  int32_t mkind = 0;    // with dyn: 1 = Schur update (recount from the pairs' ranks),
+                        // 2 = algorithmic = executed (recount), 0 = keep mflops
   int64_t alt_off = -1; // product launch: 128-tile task list awaiting the tile tuner
   int64_t alt_count = 0;
   bool dyn = false;     // inner or column extents read from device ranks: the profile
@@ -92,6 +95,7 @@ struct FactorPlan {
   std::vector<GemmTask> gemm;
   std::vector<UpdTile> tiles;
   std::vector<UpdEntry> ents;
+  std::vector<double> ent_lower;      // per entry: its (row, col) pairs on or below the diagonal
   std::vector<CompactTask> compact;
   int64_t xc_size = 0;                // compact operand copies (doubles)
   int64_t split_size = 0;             // partial tiles of the largest split-K product (doubles)
@@ -204,6 +208,7 @@ struct Handle {
   int64_t kprof_launches[RSC_KERNELS] = {};
   double kprof_ms[RSC_KERNELS] = {};
   double kprof_flops[RSC_KERNELS] = {};
+  double kprof_tile_flops[RSC_KERNELS] = {};
 };
 
 // analyze-phase layout (no device work)

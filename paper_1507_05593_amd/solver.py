@@ -218,16 +218,18 @@ class RSCSolver:
     def profile_result(self) -> dict:
         p = Profile()
         check(lib().rsc_get_profile(self._h, C.byref(p)))
-        return {k: dict(launches=p.launches[i], ms=p.ms[i], flops=p.flops[i])
+        return {k: dict(launches=p.launches[i], ms=p.ms[i], flops=p.flops[i], tile_flops=p.tile_flops[i],
+                        flops_arith={a: p.flops_arith[i][q] for q, a in enumerate(_lib.ARITHS)})
                 for i, k in enumerate(_lib.K_CLASSES)}
 
     def kernel_profile(self) -> dict:
-        """Per-kernel launches, hipEvent ms and algorithmic flops while profiling."""
+        """Per-kernel launches, hipEvent ms, algorithmic and executed tile flops while profiling."""
         out = {}
         for k in range(_lib.RSC_KERNELS):
-            name, n, ms, fl = C.c_char_p(), C.c_int64(), C.c_double(), C.c_double()
-            check(lib().rsc_get_kernel_profile(self._h, k, C.byref(name), C.byref(n), C.byref(ms), C.byref(fl)))
-            out[name.value.decode()] = dict(launches=n.value, ms=ms.value, flops=fl.value)
+            name, n, ms, fl, tf = C.c_char_p(), C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            check(lib().rsc_get_kernel_profile(self._h, k, C.byref(name), C.byref(n), C.byref(ms), C.byref(fl),
+                                               C.byref(tf)))
+            out[name.value.decode()] = dict(launches=n.value, ms=ms.value, flops=fl.value, tile_flops=tf.value)
         return out
 
 
