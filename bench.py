@@ -232,7 +232,7 @@ def roofline(kernels, workload, precision):
     rp = stored_kernel_time(name, workload, precision)
     if rp:
         out["rocprof_avg_launch_ms"] = round(rp, 5)
-        out["achieved_rocprof"] = round(d["flops"] / n / rp * 1e-3 / 1e9, 3) if rp > 0 else None
+        out["achieved_rocprof"] = round(d["flops"] / n / rp / 1e9, 3) if rp > 0 else None
     return out
 
 

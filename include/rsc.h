@@ -75,6 +75,9 @@ typedef struct {
   int32_t gemm_tile;   /* output tile edge of the dense-product launches: 0 = picked per launch
                           class by the built-in autotuner (timed on the device the first time a
                           class occurs in the process), 64 or 128 = fixed (0) */
+  int32_t keep_lo;     /* rank-structured factor: keep the dense L^O_j of every compressed
+                          supernode for rsc_get_block (1), or hold it only while its level is
+                          factored, in memory reused by the next level (0) */
 } rsc_options;
 
 typedef struct {
@@ -216,9 +219,9 @@ rsc_status rsc_get_rowsets(rsc_handle h, int64_t* rowptr, int64_t* rows);
 rsc_status rsc_get_ranks(rsc_handle h, int32_t* ell, int32_t* q);
 /* After rsc_factor: copy one supernode's blocks to host, column-major:
  * LD (c x c, lower triangle valid), LO (r x c: the dense off-diagonal block
- * U^O_j (L^D_j)^{-T} as computed before compression; a compressed supernode keeps it
- * in device memory but the factor itself uses V_j, U_j), V (r x q), U (c x q).
- * Any pointer may be NULL. */
+ * U^O_j (L^D_j)^{-T}; for a compressed supernode the block as computed before
+ * compression, available only with rsc_options.keep_lo -- RSC_ERR_STATE otherwise --
+ * the factor itself uses V_j, U_j), V (r x q), U (c x q).  Any pointer may be NULL. */
 rsc_status rsc_get_block(rsc_handle h, int64_t j, double* LD, double* LO, double* V, double* U);
 rsc_status rsc_get_stats(rsc_handle h, rsc_stats* out);
 rsc_status rsc_profile_enable(rsc_handle h, int32_t on);   /* also resets the counters */

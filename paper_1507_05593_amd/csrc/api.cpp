@@ -235,14 +235,16 @@ rsc_status rsc_get_block(rsc_handle H, int64_t j, double* LD, double* LO, double
   if (j < 0 || j >= h.S.M()) return fail(RSC_ERR_INVALID_ARG, "supernode out of range");
   if (!h.factored) return fail(RSC_ERR_STATE, "no factor");
   const int64_t c = h.S.c(j), r = h.S.r(j), ld = h.panel_ld[j];
-  const double* P = h.arena.p + h.a_panels + h.panel_off[j];
+  const double* P = h.arena.p + h.panel_off[j];
   if (hipDeviceSynchronize() != hipSuccess) return fail(RSC_ERR_DEVICE, "synchronize");
   const bool comp = h.fplan->compressed && h.compressible[j];
   if (LD && c > 0 &&
       hipMemcpy2D(LD, c * 8, P, ld * 8, c * 8, c, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(RSC_ERR_DEVICE, "copy LD");
+  if (LO && comp && !h.opt.keep_lo)
+    return fail(RSC_ERR_STATE, "L^O of a compressed supernode is not kept (rsc_options.keep_lo)");
   if (LO && r > 0 && c > 0) {
-    if (hipMemcpy(LO, h.arena.p + h.a_lo + h.lo_off[j], sizeof(double) * r * c,
+    if (hipMemcpy(LO, h.arena.p + h.lo_off[j], sizeof(double) * r * c,
                          hipMemcpyDeviceToHost) != hipSuccess) {
       return fail(RSC_ERR_DEVICE, "copy LO");
     }
@@ -277,7 +279,7 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
   out->t_analyze_ms = h.t_analyze_ms;
   out->t_factor_ms = h.t_factor_ms;
   out->t_pcg_ms = h.t_pcg_ms;
-  out->device_bytes = 8.0 * (double)h.arena_size + 4.0 * (double)h.ints_size;
+  out->device_bytes = 8.0 * (double)h.arena.n + 4.0 * (double)h.ints_size;
   out->device_bytes += 4.0 * (double)h.arena32.n;
   if (h.fplan) {
     out->device_bytes += 8.0 * (double)h.fplan->d_xc.n;

@@ -13,6 +13,8 @@ void launch_fill(double* p, int64_t n, double v, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, double* arena,
                      hipStream_t s);
+void launch_assemble_pairs(const double* values, const int64_t* idx, const int64_t* slot, int64_t n,
+                           double* arena, hipStream_t s);
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s);
 void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s);
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, bool f32,

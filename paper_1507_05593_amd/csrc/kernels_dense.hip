@@ -50,6 +50,13 @@ __global__ void k_assemble(const double* __restrict__ values, const int64_t* __r
   }
 }
 
+// arena[slot[t]] = values[idx[t]]: the entries of one level's off-diagonal blocks.
+__global__ void k_assemble_pairs(const double* __restrict__ values, const int64_t* __restrict__ idx,
+                                 const int64_t* __restrict__ slot, int64_t n, double* __restrict__ arena) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    arena[slot[t]] = values[idx[t]];
+}
+
 __global__ void k_scatter_const(const int64_t* __restrict__ slot, int64_t n, double v,
                                 double* __restrict__ arena) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
@@ -744,6 +751,10 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, double* arena,
                      hipStream_t s) {
   if (nnz > 0) hipLaunchKernelGGL(k_assemble, dim3(grid_for(nnz)), dim3(256), 0, s, values, slot, nnz, arena);
+}
+void launch_assemble_pairs(const double* values, const int64_t* idx, const int64_t* slot, int64_t n,
+                           double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_assemble_pairs, dim3(grid_for(n)), dim3(256), 0, s, values, idx, slot, n, arena);
 }
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, s, slot, n, v, arena);

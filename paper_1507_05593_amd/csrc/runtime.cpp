@@ -53,16 +53,13 @@ void plan_layout(Handle& h) {
   const int64_t M = S.M();
   h.panel_off.assign(M, 0);
   h.panel_ld.assign(M, 0);
-  h.dinv_off.assign(M, 0);
   h.compressible.assign(M, 0);
-  int64_t poff = 0, doff = 0;
+  int64_t poff = 0;
   for (int64_t j = 0; j < M; ++j) {
     const int64_t c = S.c(j), r = S.r(j);
-    h.panel_ld[j] = (int32_t)(2 * c + r);
+    h.panel_ld[j] = (int32_t)(2 * c);
     h.panel_off[j] = poff;
-    poff += align64((2 * c + r) * c);
-    h.dinv_off[j] = doff;
-    doff += ((c + 63) / 64) * 4096;
+    poff += align64(2 * c * c);
     h.compressible[j] = (S.kind[j] == kSeparator && c >= h.opt.tau_O && r > 0) ? 1 : 0;
   }
   // Systems of a batch are dissected one after another, so each owns a contiguous
@@ -82,15 +79,10 @@ void plan_layout(Handle& h) {
   }
   const int64_t n = S.n, nnz = S.nnz;
   const int32_t nseg = (int32_t)h.seg_first.size() - 1;
-  // arena regions
+  // arena regions: values, PCG vectors, then the factor's persistent blocks, then the
+  // level pool
   int64_t a = 0;
   h.a_values = a; a += align64(nnz);
-  h.a_panels = a; a += poff;
-  h.a_dinv = a; a += doff;
-  h.lo_off.assign(M, 0);
-  int64_t loff = 0;
-  for (int64_t j = 0; j < M; ++j) { h.lo_off[j] = loff; loff += align64((int64_t)S.c(j) * S.r(j)); }
-  h.a_lo = a; a += loff;
   h.a_x = a; a += align64(n);
   h.a_r = a; a += align64(n);
   h.a_z = a; a += align64(n);
@@ -118,43 +110,90 @@ void plan_layout(Handle& h) {
   h.sc.rz = h.a_seg; h.sc.rznew = h.a_seg + nseg; h.sc.pAp = h.a_seg + 2 * nseg;
   h.sc.alpha = h.a_seg + 3 * nseg; h.sc.beta = h.a_seg + 4 * nseg; h.sc.rr = h.a_seg + 5 * nseg;
   h.sc.bnorm = h.a_seg + 6 * nseg; h.sc.rel = h.a_seg + 7 * nseg;
-  // compression work space, per compressible supernode (Gram blocks grouped together)
+  // panels [L^D_j; M_j], 2c x c (ld 2c)
+  h.a_panels = a; a += poff;
+  h.panels_size = poff;
+  for (int64_t j = 0; j < M; ++j) h.panel_off[j] += h.a_panels;
+  // dense L^O_j of the supernodes never compressed
+  h.lo_off_exact.assign(M, -1);
+  h.lo_off_comp.assign(M, -1);
+  for (int64_t j = 0; j < M; ++j)
+    if (S.r(j) > 0 && !h.compressible[j]) {
+      h.lo_off_exact[j] = h.lo_off_comp[j] = a;
+      a += align64((int64_t)S.c(j) * S.r(j));
+    }
+  // Region X.  Exact factor: the dense L^O_j of the compressible supernodes.  Rank-
+  // structured factor: their V_j, U_j and the sweeps' two small vectors (and L^O_j when
+  // it is kept for inspection).
+  const int64_t aX = a;
+  int64_t ax = aX;
+  for (int64_t j = 0; j < M; ++j)
+    if (h.compressible[j]) { h.lo_off_exact[j] = ax; ax += align64((int64_t)S.c(j) * S.r(j)); }
   h.comp.assign(M, CompSlot());
   int32_t islot = 0;
   h.i_status = islot; islot += 4;
   h.i_ranks = islot; islot += (int32_t)M;
+  int64_t ac = aX;
   for (int64_t j = 0; j < M; ++j) {
     if (!h.compressible[j]) continue;
     CompSlot& C = h.comp[j];
     const int32_t c = S.c(j), r = S.r(j);
     C.ell = std::min<int32_t>(sample_count(r, c, h.opt.alpha_O, h.opt.oversample), 2048);
     const int64_t l = C.ell;
-    C.omega = a; a += align64(r * l);
-    C.ypanel = a; a += align64((l + c) * l);
-    C.ydinv = a; a += ((l + 63) / 64) * 4096;
-    C.V = a; a += align64(r * l);
-    C.Vj = a; a += align64(r * l);
-    C.Uj = a; a += align64(c * l);
-    C.gscale = a; a += 64;
-    C.tvq = a; a += align64(l);
-    C.u = a; a += align64(l);
-    C.G = a; a += align64(l * l);
-    C.Sa = a; a += align64(l * l);
-    C.Sb = a; a += align64(l * l);
-    C.Om2 = a; a += align64(l * l);
-    C.Mpan = a; a += align64(2 * l * l);
-    C.Mdinv = a; a += ((l + 63) / 64) * 4096;
-    C.Wpan = a; a += align64(2 * l * l);
-    C.Wdinv = a; a += ((l + 63) / 64) * 4096;
-    C.sc = a; a += 64;
-    if (h.opt.power_iters > 0) {
-      C.zpanel = a; a += align64((l + r) * l);
-      C.zdinv = a; a += ((l + 63) / 64) * 4096;
-    }
+    C.Vj = ac; ac += align64(r * l);
+    C.Uj = ac; ac += align64(c * l);
+    C.tvq = ac; ac += align64(l);
+    C.u = ac; ac += align64(l);
+    if (h.opt.keep_lo) { h.lo_off_comp[j] = ac; ac += align64((int64_t)c * r); }
     C.qslot = h.i_ranks + (int32_t)j;
   }
-  a = align64(a);
-  h.arena_size = a;
+  h.f32_end_exact = ax;
+  h.f32_end_comp = ac;
+  // Level pool: per elimination-tree level, U^O_j of its supernodes (assembled and
+  // updated there, dead once L^O_j is formed), the 64 x 64 inverse blocks of their panel
+  // steps, and with compression the dense L^O_j and the range finder's work space.  The
+  // levels run one after another, so each reuses the pool from its start.
+  h.a_pool = align64(std::max(ax, ac));
+  h.uo_off.assign(M, -1);
+  h.dinv_off.assign(M, 0);
+  h.lev_uo.assign(S.nlevels, {0, 0});
+  int64_t pool_exact = 0, pool_comp = 0;
+  for (int32_t L = 0; L < S.nlevels; ++L) {
+    int64_t p = h.a_pool;
+    for (int32_t j : S.by_level[L])
+      if (S.r(j) > 0) { h.uo_off[j] = p; p += align64((int64_t)S.c(j) * S.r(j)); }
+    h.lev_uo[L] = {h.a_pool, p};
+    for (int32_t j : S.by_level[L]) { h.dinv_off[j] = p; p += ((S.c(j) + 63) / 64) * 4096; }
+    pool_exact = std::max(pool_exact, p - h.a_pool);
+    for (int32_t j : S.by_level[L]) {
+      if (!h.compressible[j]) continue;
+      CompSlot& C = h.comp[j];
+      const int64_t c = S.c(j), r = S.r(j), l = C.ell;
+      if (!h.opt.keep_lo) { h.lo_off_comp[j] = p; p += align64(c * r); }
+      C.omega = p; p += align64(r * l);
+      C.ypanel = p; p += align64((l + c) * l);
+      C.ydinv = p; p += ((l + 63) / 64) * 4096;
+      C.V = p; p += align64(r * l);
+      C.gscale = p; p += 64;
+      C.G = p; p += align64(l * l);
+      C.Sa = p; p += align64(l * l);
+      C.Sb = p; p += align64(l * l);
+      C.Om2 = p; p += align64(l * l);
+      C.Mpan = p; p += align64(2 * l * l);
+      C.Mdinv = p; p += ((l + 63) / 64) * 4096;
+      C.Wpan = p; p += align64(2 * l * l);
+      C.Wdinv = p; p += ((l + 63) / 64) * 4096;
+      C.sc = p; p += 64;
+      if (h.opt.power_iters > 0) {
+        C.zpanel = p; p += align64((l + r) * l);
+        C.zdinv = p; p += ((l + 63) / 64) * 4096;
+      }
+    }
+    pool_comp = std::max(pool_comp, p - h.a_pool);
+  }
+  h.arena_size_exact = align64(h.a_pool + pool_exact);
+  h.arena_size_comp = align64(h.a_pool + pool_comp);
+  h.lo_off = h.lo_off_exact;
   // PCG int slots
   h.sc.active = islot; islot += nseg;
   h.sc.iters = islot; islot += nseg;
@@ -162,9 +201,11 @@ void plan_layout(Handle& h) {
   h.sc.breakdown = islot++;
   h.ints_size = islot;
 
-  // assembly map: entry (i, col) with col <= i goes to the lower position of the
-  // permuted pair in the panel of the supernode owning the column
+  // assembly: entry (i, col) with col <= i goes to the lower position of the permuted
+  // pair in the supernode owning the column -- its panel (rows in C_j, at the start of
+  // a factorization) or its U^O_j in the pool (rows in R_j, at the start of its level)
   h.asm_slot.assign(nnz, -1);
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> lev_ent(S.nlevels);
   for (int64_t i = 0; i < n; ++i) {
     for (int64_t p = h.rowptr[i]; p < h.rowptr[i + 1]; ++p) {
       const int64_t col = h.colind[p];
@@ -173,23 +214,27 @@ void plan_layout(Handle& h) {
       const int64_t lo = std::min(ni, nc), hi = std::max(ni, nc);
       const int64_t j = S.owner[lo];
       const int64_t t = lo - S.first[j];
-      int64_t rowpos;
       if (hi < S.first[j + 1]) {
-        rowpos = hi - S.first[j];
+        h.asm_slot[p] = h.panel_off[j] + t * h.panel_ld[j] + (hi - S.first[j]);
       } else {
         const int64_t* b = S.rows.data() + S.rows_ptr[j];
         const int64_t* e = S.rows.data() + S.rows_ptr[j + 1];
-        const int64_t* f = std::lower_bound(b, e, hi);
-        rowpos = S.c(j) + (f - b);
+        const int64_t f = std::lower_bound(b, e, hi) - b;
+        lev_ent[S.level[j]].push_back({p, h.uo_off[j] + t * S.r(j) + f});
       }
-      h.asm_slot[p] = h.a_panels + h.panel_off[j] + t * h.panel_ld[j] + rowpos;
     }
+  }
+  h.asmo_idx.clear();
+  h.asmo_slot.clear();
+  h.asmo_ptr.assign(1, 0);
+  for (int32_t L = 0; L < S.nlevels; ++L) {
+    for (auto& e : lev_ent[L]) { h.asmo_idx.push_back(e.first); h.asmo_slot.push_back(e.second); }
+    h.asmo_ptr.push_back((int64_t)h.asmo_idx.size());
   }
   h.ident_slot.clear();
   for (int64_t j = 0; j < M; ++j) {
-    const int64_t c = S.c(j), r = S.r(j);
-    for (int64_t t = 0; t < c; ++t)
-      h.ident_slot.push_back(h.a_panels + h.panel_off[j] + t * h.panel_ld[j] + (c + r + t));
+    const int64_t c = S.c(j);
+    for (int64_t t = 0; t < c; ++t) h.ident_slot.push_back(h.panel_off[j] + t * h.panel_ld[j] + (c + t));
   }
 }
 
@@ -262,16 +307,14 @@ Error ensure_device(Handle& h) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return Error{RSC_ERR_DEVICE, std::string("this library is built for gfx950, found ") + prop.gcnArchName};
   h.device = dev;
-  size_t bytes = sizeof(double) * (size_t)h.arena_size;
-  h.arena.p = static_cast<double*>(dev_alloc(bytes));
-  if (!h.arena.p) return Error{RSC_ERR_OUT_OF_MEMORY, "arena of " + std::to_string(bytes) + " bytes"};
-  h.arena.n = h.arena_size;
   h.ints.p = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (size_t)h.ints_size));
   if (!h.ints.p) return Error{RSC_ERR_OUT_OF_MEMORY, "int arena"};
   h.ints.n = h.ints_size;
   HIPCHK(hipMemset(h.ints.p, 0, sizeof(int32_t) * (size_t)h.ints_size));
   Error r;
   if ((r = upload(h.d_asm_slot, h.asm_slot)).code) return r;
+  if ((r = upload(h.d_asmo_idx, h.asmo_idx)).code) return r;
+  if ((r = upload(h.d_asmo_slot, h.asmo_slot)).code) return r;
   if ((r = upload(h.d_ident_slot, h.ident_slot)).code) return r;
   if ((r = upload(h.d_perm, h.S.perm)).code) return r;
   if ((r = upload(h.d_rows, h.S.rows)).code) return r;
@@ -290,6 +333,32 @@ Error ensure_device(Handle& h) {
   if ((r = upload(h.d_seg_chunk_ptr, segp)).code) return r;
   HIPCHK(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
   h.dev_ready = true;
+  return kOk;
+}
+
+// Destroys every captured graph of the handle (they hold device pointers of the arena
+// and its FP32 copy); plans keep their task lists and are captured again when next run.
+void drop_graphs(Handle& h) {
+  if (h.dev_ready) (void)hipDeviceSynchronize();
+  for (auto& fp : h.fplans)
+    if (fp && fp->graph) { (void)hipGraphExecDestroy(fp->graph); fp->graph = nullptr; }
+  if (h.splan) {
+    if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
+    if (h.splan->graph_b) (void)hipGraphExecDestroy(h.splan->graph_b);
+    if (h.splan->graph_apply) (void)hipGraphExecDestroy(h.splan->graph_apply);
+    h.splan->graph_a = h.splan->graph_b = h.splan->graph_apply = nullptr;
+  }
+}
+
+// The arena at least `len` doubles long (the layout of the factor about to run).
+Error ensure_arena(Handle& h, int64_t len) {
+  if (h.arena.p && h.arena.n >= len) return kOk;
+  drop_graphs(h);
+  h.arena.reset();
+  h.arena.p = static_cast<double*>(dev_alloc(sizeof(double) * (size_t)len));
+  h.arena.n = h.arena.p ? len : 0;
+  h.arena_size = h.arena.n;
+  if (!h.arena.p) return Error{RSC_ERR_OUT_OF_MEMORY, "arena of " + std::to_string(8 * len) + " bytes"};
   return kOk;
 }
 
@@ -601,7 +670,7 @@ struct Builder {
 
   // L^O_j = U^O_j (L^D_j)^{-T} = U^O_j M_j with the upper-triangular M_j = (L^D_j)^{-T}
   // that the panel factorisation left in the panel's last c rows; column block j0 of
-  // the product only needs rows k < j0 + 64 of M.  Written to the L^O buffer.
+  // the product only needs rows k < j0 + 64 of M.  U^O_j comes from the level pool.
   void offdiag_solve(const std::vector<int32_t>& level) {
     const Symbolic& S = h.S;
     const int64_t g0 = (int64_t)P.gemm.size();
@@ -610,9 +679,9 @@ struct Builder {
     for (int32_t j : level) {
       const int32_t c = S.c(j), r = S.r(j), ld = h.panel_ld[j];
       if (r == 0) continue;
-      const int64_t pan = h.a_panels + h.panel_off[j];
+      const int64_t pan = h.panel_off[j];
       mfl += (double)r * c * c;
-      GemmTask t = gt(pan + c, 1, ld, pan + c + r, ld, 1, h.a_lo + h.lo_off[j], r, r, c, c, 1.0, 0.0);
+      GemmTask t = gt(h.uo_off[j], 1, r, pan + c, ld, 1, h.lo_off[j], r, r, c, c, 1.0, 0.0);
       for (int32_t j0 = 0; j0 < c; j0 += kTile)
         for (int32_t i0 = 0; i0 < r; i0 += kTile) {
           GemmTask u = t;
@@ -633,7 +702,11 @@ struct Builder {
     std::vector<TileW> all;
     for (int32_t j : level) {
       const int32_t c = S.c(j), r = S.r(j);
-      const int32_t nI = (c + r + kTile - 1) / kTile, nJ = (c + kTile - 1) / kTile;
+      // row tiles: 64-row blocks of C_j (in the panel), then of R_j (U^O_j in the pool);
+      // no tile straddles the two
+      const int32_t nIc = (c + kTile - 1) / kTile, nJ = nIc;
+      const int32_t nI = nIc + (r + kTile - 1) / kTile;
+      auto tile_of = [&](int32_t x) { return x < c ? x / kTile : nIc + (x - c) / kTile; };
       std::vector<std::vector<UpdEntry>> ents((size_t)nI * nJ);
       std::vector<std::vector<double>> kes((size_t)nI * nJ);   // planning inner dimension
       std::vector<std::vector<double>> lws((size_t)nI * nJ);   // pairs on or below the diagonal
@@ -659,9 +732,9 @@ struct Builder {
         // runs of gathered rows per 64-row tile (relmap is increasing)
         std::vector<std::array<int32_t, 3>> rr, cc;
         for (int32_t t = 0; t < pr.nrows;) {
-          const int32_t I = rm[t] / kTile;
+          const int32_t I = tile_of(rm[t]);
           int32_t u = t;
-          while (u < pr.nrows && rm[u] / kTile == I) ++u;
+          while (u < pr.nrows && tile_of(rm[u]) == I) ++u;
           rr.push_back({I, t, u});
           t = u;
         }
@@ -695,10 +768,18 @@ struct Builder {
           const size_t id = (size_t)I * nJ + J;
           if (ents[id].empty()) continue;
           TileW tw;
-          tw.t.panel = h.a_panels + h.panel_off[j];
-          tw.t.ld = h.panel_ld[j];
-          tw.t.row0 = I * kTile; tw.t.col0 = J * kTile;
-          tw.t.nrows = std::min(kTile, c + r - I * kTile);
+          if (I < nIc) {       // target rows in C_j: the panel
+            tw.t.panel = h.panel_off[j];
+            tw.t.ld = h.panel_ld[j];
+            tw.t.row0 = I * kTile;
+            tw.t.nrows = std::min(kTile, c - I * kTile);
+          } else {             // rows of R_j: U^O_j, addressed so that row c is its first row
+            tw.t.panel = h.uo_off[j] - c;
+            tw.t.ld = r;
+            tw.t.row0 = c + (I - nIc) * kTile;
+            tw.t.nrows = std::min(kTile, c + r - tw.t.row0);
+          }
+          tw.t.col0 = J * kTile;
           tw.t.ncols = std::min(kTile, c - J * kTile);
           tw.work = work[id];
           tw.e = std::move(ents[id]);
@@ -756,7 +837,7 @@ struct Builder {
       if (comp != compressed_ones) continue;
       for (int32_t r0 = 0; r0 < r; r0 += kTile) {
         CompactTask t{};
-        t.src = (comp ? h.comp[j].Vj : h.a_lo + h.lo_off[j]) + r0;
+        t.src = (comp ? h.comp[j].Vj : h.lo_off[j]) + r0;
         t.dst = xc_off[j] + (int64_t)r0 * xc_row(j);
         t.ld = r;
         t.nrows = std::min(kTile, r - r0);
@@ -786,7 +867,7 @@ struct Builder {
     };
     for (int64_t j = 0; j < S.M(); ++j) {
       const int32_t c = S.c(j), r = S.r(j);
-      add(h.a_panels + h.panel_off[j] + c + r, c, c, h.panel_ld[j], true);
+      add(h.panel_off[j] + c, c, c, h.panel_ld[j], true);
       if (r == 0) continue;
       if (P.compressed && h.compressible[j]) add(h.comp[j].Uj, c, h.comp[j].ell, c, false);
     }
@@ -856,7 +937,7 @@ struct Builder {
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      const int64_t LO = h.a_lo + h.lo_off[j];
+      const int64_t LO = h.lo_off[j];
       fl += tiles(gt(LO, r, 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_sample);
@@ -872,7 +953,7 @@ struct Builder {
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-        const int64_t LO = h.a_lo + h.lo_off[j];
+        const int64_t LO = h.lo_off[j];
         fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.zpanel + l, l + r, r, l, c, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
@@ -883,7 +964,7 @@ struct Builder {
       for (int32_t j : js) {
         const CompSlot& C = h.comp[j];
         const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-        const int64_t LO = h.a_lo + h.lo_off[j];
+        const int64_t LO = h.lo_off[j];
         fl += tiles(gt(LO, r, 1, C.zpanel + l, l + r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
       }
       cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
@@ -908,7 +989,7 @@ struct Builder {
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
       const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      const int64_t LO = h.a_lo + h.lo_off[j];
+      const int64_t LO = h.lo_off[j];
       fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
@@ -1154,24 +1235,20 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   P->tol = tol;
   Builder B(h, *P);
   const Symbolic& S = h.S;
-  int64_t panels_total = h.a_dinv - h.a_panels;
-  B.cmd(kCmdFill, RSC_K_OTHER, h.a_panels, panels_total, 0, 0, 0, 0.0);
+  B.cmd(kCmdFill, RSC_K_OTHER, h.a_panels, h.panels_size, 0, 0, 0, 0.0);
   B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_status, 2, 0, 0, 0, (double)INT_MAX);
   B.cmd(kCmdAssemble, RSC_K_OTHER, 0, S.nnz, 0);
   B.cmd(kCmdIdent, RSC_K_OTHER, 0, (int64_t)h.ident_slot.size(), 0);
   if (compressed) B.cmd(kCmdFillInts, RSC_K_OTHER, h.i_ranks, S.M(), 0, 0, 0, 0.0);
   for (int32_t L = 0; L < S.nlevels; ++L) {
     const auto& lev = S.by_level[L];
+    // the level's U^O blocks in the pool: zero, then A(R_j, C_j)
+    B.cmd(kCmdFill, RSC_K_OTHER, h.lev_uo[L][0], h.lev_uo[L][1] - h.lev_uo[L][0], 0, 0, 0, 0.0);
+    B.cmd(kCmdAssembleLevel, RSC_K_OTHER, h.asmo_ptr[L], h.asmo_ptr[L + 1] - h.asmo_ptr[L], 0);
     B.updates(lev);
     std::vector<PanelDesc> pan;
-    for (int32_t j : lev) {
-      PanelDesc pd{h.a_panels + h.panel_off[j], h.panel_ld[j], S.c(j), S.r(j), true,
-                   h.a_dinv + h.dinv_off[j], j, 0, 0};
-      pd.lp_lo = S.c(j);                 // rows U^O_j: solved below by one product
-      pd.lp_hi = S.c(j) + S.r(j);
-      pd.skip_mid = true;
-      pan.push_back(pd);
-    }
+    for (int32_t j : lev)   // [L^D_j; I]: the Cholesky factor and, in the rows below, M_j
+      pan.push_back(PanelDesc{h.panel_off[j], h.panel_ld[j], S.c(j), 0, true, h.dinv_off[j], j, 0, 0});
     const size_t cp = P->cmds.size();
     double m_potrf = 0;
     for (int32_t j : lev) m_potrf += std::pow((double)S.c(j), 3) / 3.0;
@@ -1221,10 +1298,14 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
   if ((e = upload(P->d_gs_m, P->gs_m)).code) return e;
   if ((e = upload(P->d_conv, P->conv)).code) return e;
-  if (!P->conv.empty() && !h.arena32.p) {
-    h.arena32.p = static_cast<float*>(dev_alloc(sizeof(float) * (size_t)h.arena_size));
+  // FP32 copy of the sweeps' operands: panels, dense L^O and region X of this layout
+  const int64_t n32 = (compressed ? h.f32_end_comp : h.f32_end_exact) - h.a_panels;
+  if (!P->conv.empty() && h.arena32.n < n32) {
+    drop_graphs(h);
+    h.arena32.reset();
+    h.arena32.p = static_cast<float*>(dev_alloc(sizeof(float) * (size_t)n32));
+    h.arena32.n = h.arena32.p ? n32 : 0;
     if (!h.arena32.p) return Error{RSC_ERR_OUT_OF_MEMORY, "FP32 copy of the factor operands"};
-    h.arena32.n = h.arena_size;
   }
   if ((e = tune_tiles(h, *P, stream)).code) return e;
   auto& slot = h.fplans[precision];
@@ -1316,7 +1397,7 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
     case kCmdTruncX0: return 13;
     case kCmdTruncP: return 14;
     case kCmdTruncCompact: return 15;
-    case kCmdAssemble: case kCmdIdent: return 16;
+    case kCmdAssemble: case kCmdIdent: case kCmdAssembleLevel: return 16;
     case kCmdFill: case kCmdFillInts: return 17;
     case kCmdFwdPart: return 18;
     case kCmdColDot: return 19;
@@ -1330,17 +1411,27 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
 
 const char* kernel_name(int32_t k) { return (k >= 0 && k < RSC_KERNELS) ? kKernelNames[k] : ""; }
 
+// The FP32 copy addressed by arena offsets: element a_panels + k of the result is element
+// k of the copy (no offset below a_panels is ever used with it).
+static float* f32_base(Handle& h) {
+  return reinterpret_cast<float*>(reinterpret_cast<uintptr_t>(h.arena32.p) -
+                                  sizeof(float) * (uintptr_t)h.a_panels);
+}
+
 static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const SolvePlan* Q,
                        hipStream_t s, double* part_buf = nullptr) {
   double* A = h.arena.p;
   // partial-sum blocks of the sweeps: the solve plan's own, or a caller's buffer
   double* QP = part_buf ? part_buf : (Q ? Q->d_part.p : nullptr);
   int32_t* I = h.ints.p;
-  const float* F32 = h.f32_valid ? h.arena32.p : nullptr;   // factor operands of the sweeps
+  const float* F32 = h.f32_valid ? f32_base(h) : nullptr;   // factor operands of the sweeps
   switch (c.type) {
     case kCmdFill: launch_fill(A + c.off, c.count, c.v, s); break;
     case kCmdFillInts: launch_fill_i32(I + c.off, c.count, (int32_t)c.v, s); break;
     case kCmdAssemble: launch_assemble(A + h.a_values, h.d_asm_slot.p, c.count, A, s); break;
+    case kCmdAssembleLevel:
+      launch_assemble_pairs(A + h.a_values, h.d_asmo_idx.p + c.off, h.d_asmo_slot.p + c.off, c.count, A, s);
+      break;
     case kCmdIdent: launch_scatter_const(h.d_ident_slot.p, c.count, 1.0, A, s); break;
     case kCmdUpdate:
       launch_update_waves((int)c.a, P->d_tiles.p + c.off, (int)c.count, P->d_ents.p, h.d_relmap.p, A,
@@ -1348,7 +1439,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       break;
     case kCmdCompact:
       launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p,
-                          P->precision != RSC_FP64 ? h.arena32.p : nullptr, s);
+                          P->precision != RSC_FP64 ? f32_base(h) : nullptr, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
     case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
@@ -1373,7 +1464,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, F32,
                       I, QP, s);
       break;
-    case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, h.arena32.p, s); break;
+    case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, f32_base(h), s); break;
     case kCmdTruncNs:
       launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNewtonSchulzSteps, s);
       break;
@@ -1482,6 +1573,10 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
                          hipStream_t stream) {
   Error e;
   const bool compressed = tol > 0.0;
+  // the layout of this factor: where L^O_j of the compressible supernodes lives, and the
+  // arena length it needs
+  h.lo_off = compressed ? h.lo_off_comp : h.lo_off_exact;
+  if ((e = ensure_arena(h, compressed ? h.arena_size_comp : h.arena_size_exact)).code) return e;
   auto& slot = h.fplans[precision];
   if (!slot || slot->compressed != compressed || (compressed && slot->tol != tol))
     if ((e = build_factor_plan(h, compressed, tol, precision, stream)).code) return e;
@@ -1632,7 +1727,7 @@ static Error build_solve_plan(Handle& h) {
             base.kmax = h.comp[k].ell;
             base.v = h.comp[k].tvq;
           } else {
-            base.x = h.a_lo + h.lo_off[k] + pr.p0; base.ldx = S.r(k); base.kdim = S.c(k);
+            base.x = h.lo_off[k] + pr.p0; base.ldx = S.r(k); base.kdim = S.c(k);
             base.kmax = S.c(k);
             base.v = h.a_w + S.first[k];
           }
@@ -1714,7 +1809,7 @@ static Error build_solve_plan(Handle& h) {
       const int32_t c = S.c(j), r = S.r(j);
       for (int32_t col0 = 0; col0 < c; col0 += 16) {
         ColDotTask t{};
-        t.x = h.a_panels + h.panel_off[j] + c + r; t.ldx = h.panel_ld[j];
+        t.x = h.panel_off[j] + c; t.ldx = h.panel_ld[j];
         t.in = h.a_y + S.first[j]; t.idx = -1; t.out = h.a_w + S.first[j];
         t.rows = c; t.ncols = c; t.col0 = col0; t.tri = 1;
         st.push_back(t);
@@ -1770,7 +1865,7 @@ static Error build_solve_plan(Handle& h) {
       } else {
         for (int32_t col0 = 0; col0 < c; col0 += 16) {
           ColDotTask t{};
-          t.x = h.a_lo + h.lo_off[j]; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j];
+          t.x = h.lo_off[j]; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j];
           t.idx = -1; t.out = h.a_s + S.first[j];
           t.rows = r; t.ncols = c; t.col0 = col0; t.tri = 0;
           st.push_back(t);
@@ -1809,7 +1904,7 @@ static Error build_solve_plan(Handle& h) {
           const int32_t s0 = slot;
           for (int32_t t0 = i0; t0 < c; t0 += width) {
             RowChunk t{};
-            t.m = h.a_panels + h.panel_off[j] + c + r; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
+            t.m = h.panel_off[j] + c; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
             t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;
             t.t0 = t0; t.t1 = std::min(c, t0 + width); t.slot = slot++;
             Q->rchunks.push_back(t);

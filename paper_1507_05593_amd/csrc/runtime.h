@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <array>
 #include <memory>
 #include <string>
 #include <vector>
@@ -25,7 +26,7 @@ enum CmdType : int32_t {
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
-  kCmdToF32, kCmdTruncNs,
+  kCmdToF32, kCmdTruncNs, kCmdAssembleLevel,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -158,11 +159,17 @@ struct Handle {
   double t_analyze_ms = 0;
 
   // layout (host, computed at analyze)
-  std::vector<int64_t> panel_off;
-  std::vector<int32_t> panel_ld;
-  std::vector<int64_t> dinv_off;
-  std::vector<int64_t> lo_off;        // L^O_j (r x c, ld r) in the L^O buffer
-  std::vector<int64_t> asm_slot;      // per stored entry: arena slot or -1
+  // (all offsets are arena offsets)
+  std::vector<int64_t> panel_off;     // [L^D_j; M_j], 2c x c
+  std::vector<int32_t> panel_ld;      // 2c
+  std::vector<int64_t> dinv_off;      // 64 x 64 inverse blocks of the panel steps (level pool)
+  std::vector<int64_t> uo_off;        // U^O_j (r x c, ld r) in the level pool, or -1
+  std::vector<int64_t> lo_off;        // L^O_j (r x c, ld r) of the current factor's layout
+  std::vector<int64_t> lo_off_exact, lo_off_comp;   // ... of the exact / rank-structured layout
+  std::vector<std::array<int64_t, 2>> lev_uo;       // per level: its U^O range of the pool
+  std::vector<int64_t> asm_slot;      // per stored entry: panel slot (rows in C_j) or -1
+  std::vector<int64_t> asmo_idx, asmo_slot, asmo_ptr;   // entries of rows R_j: value index and
+                                                        // pool slot, by level (asmo_ptr)
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
   std::vector<int32_t> sn_local;      // supernode index within its own system (sample key)
@@ -173,19 +180,23 @@ struct Handle {
   bool dev_ready = false;
   int device = -1;
   hipStream_t cap_stream = nullptr;   // private stream used for graph capture only
-  int64_t arena_size = 0, ints_size = 0;
+  int64_t arena_size = 0, ints_size = 0;    // arena_size: the allocated arena's length
+  int64_t arena_size_exact = 0, arena_size_comp = 0;   // length each layout needs
+  int64_t panels_size = 0;
+  int64_t f32_end_exact = 0, f32_end_comp = 0;          // end of the sweeps' operands per layout
+  int64_t a_pool = 0;
   DevArray<double> arena;
-  DevArray<float> arena32;            // FP32 copy of the sweeps' factor operands (mixed forms),
-                                      // at the arena's offsets
+  DevArray<float> arena32;            // FP32 copy of the sweeps' factor operands (mixed forms):
+                                      // element k holds arena offset a_panels + k
   bool f32_valid = false;             // the last factorization was mixed: the sweeps read arena32
   DevArray<int32_t> ints;
-  DevArray<int64_t> d_asm_slot, d_ident_slot, d_perm, d_rows, d_rowptr;
+  DevArray<int64_t> d_asm_slot, d_ident_slot, d_perm, d_rows, d_rowptr, d_asmo_idx, d_asmo_slot;
   DevArray<int32_t> d_colind, d_relmap;
   DevArray<Chunk> d_chunks;
   DevArray<int32_t> d_seg_chunk_ptr;
   int32_t nchunks = 0;
   // arena regions
-  int64_t a_values = 0, a_panels = 0, a_dinv = 0, a_lo = 0;
+  int64_t a_values = 0, a_panels = 0;
   int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_zr, a_part, a_partial, a_seg;
   PcgScalars sc{};
   int32_t i_status = 0, i_ranks = 0;
@@ -215,6 +226,8 @@ struct Handle {
 void plan_layout(Handle& h);
 // device set-up (first numeric call)
 Error ensure_device(Handle& h);
+void drop_graphs(Handle& h);
+Error ensure_arena(Handle& h, int64_t len);
 Error factor(Handle& h, const double* values, double tol, hipStream_t stream);
 Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, hipStream_t stream,
           rsc_pcg_result* out);

@@ -60,7 +60,7 @@ def use_torch_allocator(on: bool = True) -> None:
 
 
 def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.0, seed=0,
-                 precision="fp64", use_graph=True, retry=True, gemm_tile=0) -> Options:
+                 precision="fp64", use_graph=True, retry=True, gemm_tile=0, keep_lo=False) -> Options:
     o = Options()
     lib().rsc_default_options(C.byref(o))
     o.leaf_max, o.tau_O, o.oversample, o.power_iters = leaf_max, tau_O, oversample, power_iters
@@ -68,6 +68,7 @@ def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.use_graph, o.retry = int(bool(use_graph)), int(bool(retry))
     o.gemm_tile = int(gemm_tile)
+    o.keep_lo = int(bool(keep_lo))
     return o
 
 
@@ -203,9 +204,12 @@ class RSCSolver:
         qj = int(q[j])
         LD = np.zeros((c, c), order="F"); LO = np.zeros((r, c), order="F")
         V = np.zeros((r, qj), order="F"); U = np.zeros((c, qj), order="F")
-        check(lib().rsc_get_block(self._h, int(j), LD.ctypes.data_as(C.c_void_p), LO.ctypes.data_as(C.c_void_p),
+        # the dense L^O_j of a compressed supernode exists only with keep_lo
+        want_lo = not (ell[j] > 0 and not self._opts.keep_lo)
+        check(lib().rsc_get_block(self._h, int(j), LD.ctypes.data_as(C.c_void_p),
+                                  LO.ctypes.data_as(C.c_void_p) if want_lo else None,
                                   V.ctypes.data_as(C.c_void_p), U.ctypes.data_as(C.c_void_p)), "rsc_get_block")
-        return dict(LD=np.tril(LD), LO=LO, V=V, U=U, compressed=bool(ell[j] > 0))
+        return dict(LD=np.tril(LD), LO=LO if want_lo else None, V=V, U=U, compressed=bool(ell[j] > 0))
 
     def stats(self) -> dict:
         s = Stats()

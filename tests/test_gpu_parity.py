@@ -119,7 +119,7 @@ def test_compressed_ranks_and_pcg_match_oracle(dims, sigma, tol):
     p = grid_problem(dims, sigma=sigma, seed=2)
     sym = symbolic(p.n, p.rowptr, p.colind, 64)
     F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, tol, Options(seed=11))
-    sol = _sol(p, seed=11)
+    sol = _sol(p, seed=11, keep_lo=True)   # the dense L^O_j kept for the block comparison
     sol.factor(_vals(p), tol)
     ell, q = sol.ranks()
     assert np.array_equal(ell, np.array(F.ell))
@@ -184,7 +184,7 @@ def test_power_iterations_ranks_compression_and_pcg(power_iters, tol):
     sym = symbolic(p.n, p.rowptr, p.colind, 64)
     opts = Options(seed=11, power_iters=power_iters)
     F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, tol, opts)
-    sol = _sol(p, seed=11, power_iters=power_iters)
+    sol = _sol(p, seed=11, power_iters=power_iters, keep_lo=True)
     sol.factor(_vals(p), tol)
     ell, q = sol.ranks()
     assert np.array_equal(ell, np.array(F.ell))
@@ -571,3 +571,28 @@ def test_adjoint_after_the_solver_factored_other_values():
     assert np.abs(b.grad.cpu().numpy() - lam_d).max() <= 1e-10 * np.abs(lam_d).max()
     gv = o_grad_values(p.rowptr, p.colind, lam_d, x_d)
     assert np.abs(vals.grad.cpu().numpy() - gv).max() <= 1e-10 * np.abs(gv).max()
+
+
+def test_compressed_lo_not_kept_by_default_and_same_factor():
+    # Without keep_lo the dense L^O_j of a compressed supernode lives in the level pool
+    # only while its level is factored: rsc_get_block refuses it, and the rank-structured
+    # factor (ranks, V_j, U_j, the preconditioner) is identical to the one kept with it.
+    from paper_1507_05593_amd import RSCError
+    print("case keep_lo", flush=True)
+    p = grid_problem((16, 15, 14), sigma=1.0, seed=5)
+    a = _sol(p, seed=2)
+    b = _sol(p, seed=2, keep_lo=True)
+    for s in (a, b):
+        s.factor(_vals(p), 1e-2)
+    ell, q = a.ranks()
+    assert np.array_equal((ell, q), b.ranks())
+    j = int(np.nonzero(ell)[0][-1])
+    from paper_1507_05593_amd import lib
+    import ctypes as C
+    lo = np.zeros(1 << 20)
+    assert lib().rsc_get_block(a._h, j, None, lo.ctypes.data_as(C.c_void_p), None, None) == 8
+    ba, bb = a.block(j), b.block(j)
+    assert ba["LO"] is None and bb["LO"] is not None
+    assert np.array_equal(ba["V"], bb["V"]) and np.array_equal(ba["U"], bb["U"])
+    r = _vec(np.random.default_rng(0).standard_normal(p.n))
+    assert np.array_equal(a.apply(r).cpu().numpy(), b.apply(r).cpu().numpy())
