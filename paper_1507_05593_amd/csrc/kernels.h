@@ -34,7 +34,8 @@ void launch_trunc_copy(const TruncTask* t, int n, int lmax, double* arena, hipSt
 // the projector's Newton-Schulz steps in one workgroup per supernode with l <= kNsMaxF32
 // (FP32) or kNsMaxF64 (FP64); larger supernodes are skipped
 constexpr int kNsMaxF32 = 128, kNsMaxF64 = 64;
-void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, int steps, hipStream_t s);
+void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, const NsSchedule& ns,
+                     hipStream_t s);
 
 // sweep kernels: f32 = FP32 copy of the factor operands (mixed forms), or null (arena)
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const float* f32, const int32_t* ilim,

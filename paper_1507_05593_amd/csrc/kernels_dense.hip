@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void k_trunc_p(const TruncTask* __restrict__ t
 // Reads X0 from sa and leaves the last iterate there (FP64).
 template <typename T, int LMIN, int LMAX, int NW>
 __global__ __launch_bounds__(64 * NW) void k_trunc_ns(const TruncTask* __restrict__ tasks,
-                                                      double* __restrict__ arena, int steps) {
+                                                      double* __restrict__ arena, NsSchedule ns) {
   constexpr int NB = LMAX / 16, NBLK = NB * (NB + 1) / 2, MAXB = (NBLK + NW - 1) / NW, PITCH = LMAX + 4;
   typedef typename std::conditional<sizeof(T) == 8, v4d, v4f>::type AccT;
   __shared__ T X[LMAX * PITCH], Y[LMAX * PITCH];
@@ -602,7 +602,9 @@ __global__ __launch_bounds__(64 * NW) void k_trunc_ns(const TruncTask* __restric
     j = 16 * bj[u] + li;
   };
   __syncthreads();
-  for (int it = 0; it < steps; ++it) {
+  for (int it = 0; it < ns.steps; ++it) {
+    const double a = ns.alpha[it];
+    const T ca = (T)(1.5 * a), cc = (T)(-0.5 * a * a * a);
     product(X, X);                                   // Y = X X
 #pragma unroll
     for (int u = 0; u < MAXB; ++u) {
@@ -625,7 +627,7 @@ __global__ __launch_bounds__(64 * NW) void k_trunc_ns(const TruncTask* __restric
       for (int e = 0; e < 4; ++e) {
         int i, j;
         pos(u, e, i, j);
-        const T v = (T)1.5 * X[i + j * PITCH] - (T)0.5 * acc[u][e];
+        const T v = ca * X[i + j * PITCH] + cc * acc[u][e];
         if (i >= j) X[i + j * PITCH] = v;
         if (i > j) X[j + i * PITCH] = v;
       }
@@ -638,13 +640,13 @@ __global__ __launch_bounds__(64 * NW) void k_trunc_ns(const TruncTask* __restric
   }
 }
 
-void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, int steps, hipStream_t s) {
+void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, const NsSchedule& ns, hipStream_t s) {
   if (n <= 0) return;
   if (fp32) {
-    hipLaunchKernelGGL((k_trunc_ns<float, 0, 64, 4>), dim3(n), dim3(256), 0, s, t, arena, steps);
-    hipLaunchKernelGGL((k_trunc_ns<float, 64, kNsMaxF32, 8>), dim3(n), dim3(512), 0, s, t, arena, steps);
+    hipLaunchKernelGGL((k_trunc_ns<float, 0, 64, 4>), dim3(n), dim3(256), 0, s, t, arena, ns);
+    hipLaunchKernelGGL((k_trunc_ns<float, 64, kNsMaxF32, 8>), dim3(n), dim3(512), 0, s, t, arena, ns);
   } else {
-    hipLaunchKernelGGL((k_trunc_ns<double, 0, kNsMaxF64, 4>), dim3(n), dim3(256), 0, s, t, arena, steps);
+    hipLaunchKernelGGL((k_trunc_ns<double, 0, kNsMaxF64, 4>), dim3(n), dim3(256), 0, s, t, arena, ns);
   }
 }
 

@@ -34,7 +34,35 @@ namespace rsc {
   } while (0)
 
 static const Error kOk{RSC_OK, ""};
-static constexpr int kNewtonSchulzSteps = 24;
+// Sign iteration of the spectral projector: the odd cubic f(y) = (3y - y^3)/2 applied to
+// a_k X.  On an eigenvalue interval [l, u] the scale a_k = sqrt(3 / (u^2 + u l + l^2)) makes
+// f(a_k l) = f(a_k u) (the equioscillating, minimax choice), so small eigenvalues grow
+// by about 2.6 per step instead of 1.5; u = 1 + 0.01 keeps an eigenvalue that rounding
+// lifts slightly above 1 from crossing the cubic's zero at sqrt(3).  From l >= 0.6 on the
+// plain step (a = 1) converges to +-1.  Starting from |x0| >= 1e-5 (an eigenvalue 2e-5
+// relative from the cut-off), 18 steps bring every eigenvalue to +-1 within FP64
+// rounding -- an eigenvalue left at 1 - 1e-7 would leave a direction of size 5e-8 in the
+// projector, which the basis step's relative pivot threshold 1e-14 could keep.
+static NsSchedule ns_schedule() {
+  NsSchedule s{};
+  double l = 1e-5;
+  const double u = 1.01;
+  auto f = [](double y) { return 0.5 * (3.0 * y - y * y * y); };
+  while (1.0 - l > 1e-12 && s.steps < 30) {
+    double a = 1.0, nl;
+    if (l < 0.6) {
+      a = std::sqrt(3.0 / (u * u + u * l + l * l));
+      nl = std::min(f(a * l), f(a * u));
+    } else {
+      nl = f(l);
+    }
+    s.alpha[s.steps++] = a;
+    l = nl;
+  }
+  if (s.steps % 2) s.alpha[s.steps++] = 1.0;   // the iterate ends in the buffer it started in
+  return s;
+}
+static const NsSchedule kNs = ns_schedule();
 static constexpr int32_t kOuter = 256;   // outer block width of the panel factorisation
 
 int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p) {
@@ -1063,12 +1091,13 @@ struct Builder {
       double f = 0;
       for (int32_t j : js) {
         lmax = std::max(lmax, h.comp[j].ell);
-        f += 2.0 * kNewtonSchulzSteps * std::pow((double)h.comp[j].ell, 3);
+        f += 2.0 * kNs.steps * std::pow((double)h.comp[j].ell, 3);
       }
       if (lmax <= nsmax) cmd(kCmdTruncNs, RSC_K_EIG, t0, nt, f, lp_eig ? 1 : 0);
       else nsmax = 0;
     }
-    for (int it = 0; nsmax == 0 && it < kNewtonSchulzSteps; ++it) {
+    for (int it = 0; nsmax == 0 && it < kNs.steps; ++it) {
+      const double a = kNs.alpha[it];
       // sb = X X ; X_new = 1.5 X - 0.5 X sb (into sb via the D operand, then swap roles).
       // The right operands are passed transposed (B(j, k) = Y(k, j)) so that the products
       // are X X and X (X X): with X X^T in their place the iteration doubles the
@@ -1089,13 +1118,13 @@ struct Builder {
         const int32_t l = C.ell;
         if (l <= nsmax) continue;
         const int64_t X = even ? C.Sa : C.Sb, Xn = even ? C.Sb : C.Sa;
-        GemmTask t = gt(X, 1, l, C.Om2, l, 1, Xn, l, l, l, l, -0.5, 1.5);
+        GemmTask t = gt(X, 1, l, C.Om2, l, 1, Xn, l, l, l, l, -0.5 * a * a * a, 1.5 * a);
         t.d = X;
         fl += sym_tiles(t);
       }
       cmd(kCmdGemm, RSC_K_EIG, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
     }
-    static_assert(kNewtonSchulzSteps % 2 == 0, "the iterate must end in sa");
+    // (kNs.steps is even: the iterate ends in sa)
     cmd(kCmdTruncP, RSC_K_EIG, t0, nt, 0);             // sa = P
     ctx = RSC_K_BASIS;
     // 8. basis of range(P): W = orth(P Omega2) over all l columns; the columns the
@@ -1466,7 +1495,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       break;
     case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, f32_base(h), s); break;
     case kCmdTruncNs:
-      launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNewtonSchulzSteps, s);
+      launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNs, s);
       break;
     case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, QP, A, s); break;
     case kCmdGatherRows:

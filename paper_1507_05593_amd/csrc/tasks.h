@@ -186,4 +186,11 @@ struct FwdEntry {
   int32_t kmax, pad_;          // kdim < 0: bound of the device rank (the sample count)
 };
 
+// Scaled Newton-Schulz steps X <- (3 a_k X - a_k^3 X^3) / 2 of the spectral projector.
+struct NsSchedule {
+  int32_t steps;
+  int32_t pad_;
+  double alpha[32];
+};
+
 }  // namespace rsc
