@@ -63,53 +63,6 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
     arena[T.out + lane] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
-// Forward-sweep chunk: the products X(a:b, :) v of a run of descendant entries of one
-// target block, accumulated in LDS (entry e goes to wave (e - e0) mod 4; the four
-// per-wave sums are added in a fixed order) and written as one 64-entry partial block.
-// Within a wave, an entry of nr rows takes lanes as P = max(8, nr rounded up to a
-// power of two) rows by G = 64 / P column groups, group g summing columns g, g + G, ...,
-// so that one load instruction reads G columns of the column-major X; the groups are
-// then added by a fixed butterfly.  A large entry is planned as several pieces over
-// column ranges, so that no chunk is much longer than the level's average.
-// k_part_apply subtracts the block's partials from y.
-template <typename TF>
-__global__ __launch_bounds__(256) void k_fwd_part(const FwdChunk* __restrict__ chunks,
-                                                  const FwdTile* __restrict__ tiles,
-                                                  const FwdEntry* __restrict__ ents,
-                                                  const int32_t* __restrict__ relmap,
-                                                  const double* __restrict__ arena, const TF* __restrict__ F,
-                                                  const int32_t* __restrict__ ilim,
-                                                  double* __restrict__ part) {
-  __shared__ double acc[4][64];
-  const FwdChunk C = chunks[blockIdx.x];
-  const FwdTile T = tiles[C.tile];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  acc[w][lane] = 0.0;
-  for (int e = C.e0 + w; e < C.e1; e += 4) {
-    const FwdEntry E = ents[e];
-    const int nr = E.b - E.a;
-    const int K = E.kdim >= 0 ? E.kdim : min(ilim[-1 - E.kdim], E.kmax);
-    const int P = nr <= 8 ? 8 : nr <= 16 ? 16 : nr <= 32 ? 32 : 64;   // wave-uniform
-    const int G = 64 / P;
-    const int row = lane & (P - 1), g = lane / P;
-    double s = 0.0;
-    const int me = min(K, E.m0 + E.kspan);
-    if (row < nr) {
-      const TF* X = F + E.x + E.a + row;
-      const double* v = arena + E.v;
-#pragma unroll 8
-      for (int m = E.m0 + g; m < me; m += G) s += (double)X[(int64_t)m * E.ldx] * v[m];
-    }
-    for (int o = P; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
-    if (g == 0 && row < nr) acc[w][relmap[E.map + E.a + row] - T.row0] += s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int r = threadIdx.x;
-    part[(int64_t)C.slot * 64 + r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
-  }
-}
-
 // Backward diagonal solve chunk: rows i in [i0, i0 + 64) (lanes) of M (w - s) over the
 // columns [t0, t1); v = w - s is staged in LDS, the four waves take consecutive column
 // quarters, and their sums are added in a fixed order into one partial block.
@@ -424,13 +377,6 @@ void launch_gemv_n(const GemvTask* t, int n, double* arena, const float* f32, co
   if (n <= 0) return;
   if (f32) hipLaunchKernelGGL(k_gemv_n<float>, dim3(n), dim3(256), 0, s, t, arena, f32, ilim);
   else hipLaunchKernelGGL(k_gemv_n<double>, dim3(n), dim3(256), 0, s, t, arena, (const double*)arena, ilim);
-}
-void launch_fwd_part(const FwdChunk* c, int n, const FwdTile* t, const FwdEntry* e,
-                     const int32_t* relmap, const double* arena, const float* f32, const int32_t* ilim,
-                     double* part, hipStream_t s) {
-  if (n <= 0) return;
-  if (f32) hipLaunchKernelGGL(k_fwd_part<float>, dim3(n), dim3(256), 0, s, c, t, e, relmap, arena, f32, ilim, part);
-  else hipLaunchKernelGGL(k_fwd_part<double>, dim3(n), dim3(256), 0, s, c, t, e, relmap, arena, arena, ilim, part);
 }
 void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32, double* part,
                      hipStream_t s) {

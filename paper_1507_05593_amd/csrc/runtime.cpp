@@ -122,12 +122,6 @@ void plan_layout(Handle& h) {
   h.a_zz = a; a += align64(n);
   h.a_b = a; a += align64(n);
   h.a_zr = a; a += align64(std::max<int64_t>((int64_t)S.rows.size(), 1));
-  // forward-sweep partials: one per gathered diagonal row of every pair
-  h.part_off.assign(S.pairs.size(), 0);
-  int64_t pt = 0;
-  for (size_t q = 0; q < S.pairs.size(); ++q) { h.part_off[q] = pt; pt += S.pairs[q].nD; }
-  h.part_total = pt;
-  h.a_part = a; a += align64(std::max<int64_t>(pt, 1));
   // chunks of <= 256 rows inside one system
   int32_t nch = 0;
   for (int32_t s = 0; s < nseg; ++s) nch += (int32_t)((h.seg_first[s + 1] - h.seg_first[s] + 255) / 256);
@@ -1402,7 +1396,7 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "gemm_staged_f64", "gemm_staged_f32", "gemm_staged_bf16x3", "gemm_staged_bf16",
     "update_waves_f64", "update_waves_f32", "update_waves_bf16x3", "update_waves_bf16",
     "potrf_f64", "philox", "gram_scale", "trunc_prep", "trunc_power", "trunc_x0", "trunc_p",
-    "trunc_compact", "assemble", "fill", "fwd_part", "coldot", "row_part", "gemv_n",
+    "trunc_compact", "assemble", "fill", "row_gather", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
     "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
     "trunc_flags", "trunc_copy", "to_f32", "trunc_ns"};
@@ -1428,11 +1422,11 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
     case kCmdTruncCompact: return 15;
     case kCmdAssemble: case kCmdIdent: case kCmdAssembleLevel: return 16;
     case kCmdFill: case kCmdFillInts: return 17;
-    case kCmdFwdPart: return 18;
     case kCmdColDot: return 19;
     case kCmdRowPart: return 20;
     case kCmdGemvN: return 21;
-    case kCmdGatherRows: case kCmdRowGather: case kCmdGatherPerm: case kCmdScatterPerm: return 22;
+    case kCmdRowGather: return 18;
+    case kCmdGatherRows: case kCmdGatherPerm: case kCmdScatterPerm: return 22;
     case kCmdPartApply: return 23;
     default: return 24;
   }
@@ -1489,10 +1483,6 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, F32, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, F32, h.d_rows.p, I, QP, s); break;
     case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, F32, QP, s); break;
-    case kCmdFwdPart:
-      launch_fwd_part(Q->d_fchunks.p + c.off, (int)c.count, Q->d_ftiles.p, Q->d_fents.p, h.d_relmap.p, A, F32,
-                      I, QP, s);
-      break;
     case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, f32_base(h), s); break;
     case kCmdTruncNs:
       launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNs, s);
@@ -1503,7 +1493,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       break;
     case kCmdRowGather:
       launch_row_gather(Q->d_rg_rows.p + c.off, Q->d_rg_ptr.p + c.a, Q->d_rg_contrib.p, c.count,
-                        A + h.a_part, A + h.a_y, s);
+                        A + h.a_zr, A + h.a_y, s);
       break;
     case kCmdGatherPerm: launch_gather_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
     case kCmdScatterPerm: launch_scatter_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
@@ -1734,104 +1724,9 @@ static Error build_solve_plan(Handle& h) {
   };
   auto iscomp = [&](int64_t j) { return comp && h.compressible[j]; };
   double bytes = 0;
-  Q->rg_ptr.push_back(0);
   // forward sweep, levels ascending
   for (int32_t L = 0; L < S.nlevels; ++L) {
     const auto& lev = S.by_level[L];
-    // f1+f2: y_C -= sum over descendants of X_k(rows in C_j) t_k, per 64-row block of C_j
-    {
-      struct Blk { FwdTile t; std::vector<FwdEntry> e; };
-      std::vector<Blk> blks;
-      for (int32_t j : lev) {
-        const int32_t c = S.c(j);
-        const int32_t nB = (c + 63) / 64;
-        std::vector<std::vector<FwdEntry>> per(nB);
-        for (int64_t q = S.pair_ptr[j]; q < S.pair_ptr[j + 1]; ++q) {
-          const Pair& pr = S.pairs[q];
-          const int32_t k = pr.k;
-          const int32_t* rm = S.relmap.data() + pr.map_off;
-          FwdEntry base{};
-          if (iscomp(k)) {
-            base.x = h.comp[k].Vj + pr.p0; base.ldx = S.r(k); base.kdim = -(1 + h.comp[k].qslot);
-            base.kmax = h.comp[k].ell;
-            base.v = h.comp[k].tvq;
-          } else {
-            base.x = h.lo_off[k] + pr.p0; base.ldx = S.r(k); base.kdim = S.c(k);
-            base.kmax = S.c(k);
-            base.v = h.a_w + S.first[k];
-          }
-          base.map = pr.map_off;
-          base.m0 = 0; base.kspan = INT_MAX;
-          for (int32_t t = 0; t < pr.nD;) {
-            const int32_t B = rm[t] / 64;
-            int32_t u = t;
-            while (u < pr.nD && rm[u] / 64 == B) ++u;
-            FwdEntry e = base;
-            e.a = t; e.b = u;
-            per[B].push_back(e);
-            t = u;
-          }
-        }
-        for (int32_t B = 0; B < nB; ++B) {
-          if (per[B].empty()) continue;
-          Blk bk;
-          bk.t.y = h.a_y + S.first[j] + 64 * B;
-          bk.t.row0 = 64 * B;
-          bk.t.nrows = std::min(64, c - 64 * B);
-          bk.e = std::move(per[B]);
-          blks.push_back(std::move(bk));
-        }
-      }
-      // Each block's entries are cut into runs of about equal work (rows x depth; the
-      // sample count stands in for a compressed descendant's rank) so that the level
-      // has about 2048 chunks; one launch computes the chunks' partial blocks, a second
-      // subtracts them from y in a fixed order.
-      auto ework = [&](const FwdEntry& e) {
-        const double K = e.kdim >= 0 ? e.kdim : (double)h.comp[(-1 - e.kdim) - h.i_ranks].ell;
-        const double Kp = std::min(K - e.m0, (double)e.kspan);   // this piece's columns
-        return (double)(e.b - e.a) * std::max(Kp, 1.0);
-      };
-      double wl = 0;
-      for (auto& bk : blks)
-        for (auto& e : bk.e) wl += ework(e);
-      const double target = std::max(wl / 4096.0, 64.0 * 64.0);
-      const int64_t c0f = (int64_t)Q->fchunks.size(), a0 = (int64_t)Q->papply.size();
-      int32_t slot = 0;
-      for (auto& bk : blks) {
-        bk.t.e0 = (int32_t)Q->fents.size();
-        for (auto& e : bk.e) {
-          // an entry worth several chunks becomes pieces over column ranges
-          const double w = ework(e);
-          if (w <= 2.0 * target) { Q->fents.push_back(e); continue; }
-          const int32_t kst = e.kdim >= 0 ? e.kdim : h.comp[(-1 - e.kdim) - h.i_ranks].ell;
-          const int32_t np = (int32_t)std::ceil(w / target);
-          const int32_t span = ((kst + np - 1) / np + 7) / 8 * 8;
-          for (int32_t m0 = 0; m0 < kst; m0 += span) {
-            FwdEntry u = e;
-            u.m0 = m0; u.kspan = span;
-            Q->fents.push_back(u);
-          }
-        }
-        bk.t.e1 = (int32_t)Q->fents.size();
-        const int32_t ti = (int32_t)Q->ftiles.size();
-        Q->ftiles.push_back(bk.t);
-        const int32_t s0 = slot;
-        double acc = 0;
-        int32_t cs = bk.t.e0;
-        for (int32_t e = bk.t.e0; e < bk.t.e1; ++e) {
-          acc += ework(Q->fents[e]);
-          if (acc >= target || e + 1 == bk.t.e1) {
-            Q->fchunks.push_back(FwdChunk{ti, cs, e + 1, slot++});
-            cs = e + 1;
-            acc = 0;
-          }
-        }
-        Q->papply.push_back(PartApply{bk.t.y, bk.t.nrows, s0, slot - s0, 0});
-      }
-      Q->part_slots = std::max<int64_t>(Q->part_slots, slot);
-      cmd(kCmdFwdPart, c0f, (int64_t)Q->fchunks.size() - c0f);
-      cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
-    }
     // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
     std::vector<ColDotTask> st;
     for (int32_t j : lev) {
@@ -1859,7 +1754,47 @@ static Error build_solve_plan(Handle& h) {
       }
     }
     coldot_stage(st);
+    // f5: t_j = L^O_j w_C (explicit) or V_j t (compressed), column-major products in
+    //     64-row pieces (coalesced over the rows), into the R_j rows of the zr buffer
+    {
+      const int64_t g0 = (int64_t)Q->gemv.size();
+      for (int32_t j : lev) {
+        const int32_t c = S.c(j), r = S.r(j);
+        for (int32_t t0 = 0; t0 < r; t0 += 64) {
+          GemvTask t{};
+          if (iscomp(j)) {
+            const CompSlot& C = h.comp[j];
+            t.x = C.Vj + t0; t.kdim = -(1 + C.qslot); t.kmax = C.ell; t.v = C.tvq;
+          } else {
+            t.x = h.lo_off[j] + t0; t.kdim = c; t.kmax = c; t.v = h.a_w + S.first[j];
+          }
+          t.ldx = r; t.rows = std::min(64, r - t0);
+          t.out = h.a_zr + S.rows_ptr[j] + t0;
+          Q->gemv.push_back(t);
+        }
+      }
+      cmd(kCmdGemvN, g0, (int64_t)Q->gemv.size() - g0);
+    }
+    // f6: y_i -= the level's t entries of row i, in supernode order (each row once per launch)
+    {
+      std::vector<std::pair<int64_t, int64_t>> tc;   // (target row, zr index)
+      for (int32_t j : lev)
+        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j + 1]; ++p) tc.push_back({S.rows[p], p});
+      std::stable_sort(tc.begin(), tc.end(), [](const std::pair<int64_t, int64_t>& x,
+                                                const std::pair<int64_t, int64_t>& y) { return x.first < y.first; });
+      const int64_t r0 = (int64_t)Q->rg_rows.size();
+      for (size_t u = 0; u < tc.size(); ++u) {
+        if (u == 0 || tc[u].first != tc[u - 1].first) {
+          Q->rg_rows.push_back(tc[u].first);
+          Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
+        }
+        Q->rg_contrib.push_back(tc[u].second);
+      }
+      const int64_t nr = (int64_t)Q->rg_rows.size() - r0;
+      if (nr > 0) cmd(kCmdRowGather, r0, nr, r0);
+    }
   }
+  Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
   // backward sweep, levels descending
   for (int32_t L = S.nlevels - 1; L >= 0; --L) {
     const auto& lev = S.by_level[L];
@@ -1950,10 +1885,7 @@ static Error build_solve_plan(Handle& h) {
   Q->bytes = bytes;
   Error e;
   if ((e = upload(Q->d_gemv, Q->gemv)).code) return e;
-  if ((e = upload(Q->d_ftiles, Q->ftiles)).code) return e;
-  if ((e = upload(Q->d_fents, Q->fents)).code) return e;
   if ((e = upload(Q->d_coldot, Q->coldot)).code) return e;
-  if ((e = upload(Q->d_fchunks, Q->fchunks)).code) return e;
   if ((e = upload(Q->d_rchunks, Q->rchunks)).code) return e;
   if ((e = upload(Q->d_papply, Q->papply)).code) return e;
   {

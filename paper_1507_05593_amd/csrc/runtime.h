@@ -24,7 +24,7 @@ struct Error {
 enum CmdType : int32_t {
   kCmdFill, kCmdFillInts, kCmdAssemble, kCmdIdent, kCmdUpdate, kCmdPotrf, kCmdGemm,
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
-  kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdFwdPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
+  kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
   kCmdToF32, kCmdTruncNs, kCmdAssembleLevel,
 };
@@ -126,20 +126,14 @@ struct SolvePlan {
   bool compressed = false;
   std::vector<Cmd> fwd_bwd;           // commands of one preconditioner apply (y -> zz)
   std::vector<GemvTask> gemv;
-  std::vector<FwdTile> ftiles;
-  std::vector<FwdEntry> fents;
   std::vector<ColDotTask> coldot;
-  std::vector<FwdChunk> fchunks;
   std::vector<RowChunk> rchunks;
   std::vector<PartApply> papply;
   int64_t part_slots = 0;             // 64-entry partial blocks (reused level by level)
   std::vector<int64_t> rg_rows, rg_ptr, rg_contrib;  // row-gather CSR (all levels)
   std::vector<int64_t> gath;          // (begin, count) pairs of z gathers over R_j
   DevArray<GemvTask> d_gemv;
-  DevArray<FwdTile> d_ftiles;
-  DevArray<FwdEntry> d_fents;
   DevArray<ColDotTask> d_coldot;
-  DevArray<FwdChunk> d_fchunks;
   DevArray<RowChunk> d_rchunks;
   DevArray<PartApply> d_papply;
   DevArray<double> d_part;
@@ -173,8 +167,6 @@ struct Handle {
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
   std::vector<int32_t> sn_local;      // supernode index within its own system (sample key)
-  std::vector<int64_t> part_off;      // per pair: offset of its forward-sweep partial
-  int64_t part_total = 0;
 
   // device
   bool dev_ready = false;
@@ -197,7 +189,7 @@ struct Handle {
   int32_t nchunks = 0;
   // arena regions
   int64_t a_values = 0, a_panels = 0;
-  int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_zr, a_part, a_partial, a_seg;
+  int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_zr, a_partial, a_seg;
   PcgScalars sc{};
   int32_t i_status = 0, i_ranks = 0;
   std::vector<CompSlot> comp;         // per supernode (compressible ones only)

@@ -95,7 +95,7 @@ struct TruncTask {
   double tol;
 };
 
-// Pair operand of the forward sweep: part[out + t] = sum_m X(t, m) v[m], t < rows.
+// One 64-row piece of a column-major product: arena[out + t] = sum_m X(t, m) v[m], t < rows.
 struct GemvTask {
   int64_t x;                   // X(t, m) = arena[x + t + m*ldx]
   int64_t v;                   // vector (arena offset)
@@ -145,17 +145,6 @@ struct PcgScalars {
 
 namespace rsc {
 
-// Forward sweep, one 64-row block of C_j: y[y0 + row] -= sum over entries of
-// X(a:b, :) v (rows scattered by relmap[map + t] - row0).
-struct FwdTile {
-  int64_t y;                   // arena offset of y on the first row of the block
-  int32_t nrows, row0;
-  int32_t e0, e1;
-};
-// Forward-sweep chunk: entries [e0, e1) of target block `tile`, partial sums to slot.
-struct FwdChunk {
-  int32_t tile, e0, e1, slot;
-};
 // One block of a factor operand to copy to FP32 (rows [0, rows) of columns [0, cols) of
 // the column-major block at arena offset off, column stride ld), at the same offsets.
 constexpr int32_t kConvRows = 4096;
@@ -175,15 +164,6 @@ struct RowChunk {
 struct PartApply {
   int64_t dst;
   int32_t nrows, s0, ns, mode;
-};
-struct FwdEntry {
-  int64_t x;                   // X(t, m) = arena[x + t + m*ldx]
-  int64_t v;                   // multiplier vector (arena offset)
-  int64_t map;                 // relmap offset of gathered row 0
-  int32_t ldx, kdim;           // kdim < 0: -(1 + int-arena slot)
-  int32_t a, b;
-  int32_t m0, kspan;           // this piece sums columns [m0, min(kdim, m0 + kspan))
-  int32_t kmax, pad_;          // kdim < 0: bound of the device rank (the sample count)
 };
 
 // Scaled Newton-Schulz steps X <- (3 a_k X - a_k^3 X^3) / 2 of the spectral projector.
