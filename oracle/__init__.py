@@ -15,6 +15,10 @@ Parity status per function (what pins it, see the tests named ``test_oracle_*``)
 * ``factor.factor`` (compressed): full-rank sampling reproduces the exact factor;
   exactly low-rank blocks are recovered; ``U^T U = I``, ``V = L^O U``; every
   pivot positive (§3.2); approximation error against the SVD bound.
+* ``factor.offdiag_multiply`` / ``offdiag_multiply_transpose`` (Algorithm 2 and its
+  transpose): the explicit block product ``L^O_j G`` with ``L^O_j`` formed by the
+  triangular solve of Algorithm 1, with explicit and with compressed descendants;
+  ``compress_implicit`` reproduces the explicit compression (ranks, ``V_j U_j^T``).
 * ``philox``: the published known-answer vectors of Philox4x32-10.
 * ``solve``: exact factor gives ``M^{-1} = A^{-1}``; symmetry and positivity of
   the rank-structured preconditioner; manufactured solutions.

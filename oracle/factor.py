@@ -34,6 +34,13 @@ the explicitly formed ``L^O_j``:
 under which every later Schur complement stays positive definite.  A compressed
 descendant updates its ancestors through ``V_k`` (§3.4, the low-rank product with
 ``U_k^T U_k = I``).
+
+Implicit products (``Options.implicit``): the same steps 2-5 without forming
+``L^O_j`` -- Algorithm 2 (``offdiag_multiply``: ``L^O_j G`` from ``(L^D_j)^{-T} G``,
+the block ``A(R_j, C_j)`` and every descendant's two products, a compressed
+descendant through ``V_k`` with ``U_prod = U_k^T U_k``, eq. lowRankMult) and its
+transpose (``offdiag_multiply_transpose``, the same terms in reverse order), as
+Algorithm 3 calls them.
 """
 from __future__ import annotations
 
@@ -62,6 +69,8 @@ class Options:
     power_iters: int = 0
     alpha_O: float = 1.0
     seed: int = 0
+    implicit: bool = False   # Algorithm 3 through Algorithm 2 (L^O_j of compressed supernodes never formed)
+    keep_lo: bool = False    # explicit path: also keep the dense L^O_j of compressed supernodes (LO_dense)
 
 
 def sample_count(r: int, c: int, alpha: float, p: int) -> int:
@@ -89,6 +98,8 @@ class Factor:
     ell: list = field(default_factory=list)    # samples drawn (0 when not compressed)
     q: list = field(default_factory=list)      # kept rank
     flops: dict = field(default_factory=dict)
+    LO_dense: dict = field(default_factory=dict)   # with Options.keep_lo: L^O_j before compression
+    Ap: object = None                          # the permuted matrix P A P^T (CSR)
 
     def offdiag(self, j):
         """The stored off-diagonal operand ``X`` used by ancestors: ``L^O_j`` or ``V_j``."""
@@ -113,6 +124,17 @@ def permuted_matrix(sym: Symbolic, n, rowptr, colind, values) -> sp.csr_matrix:
     return A[sym.perm][:, sym.perm].tocsr()
 
 
+def _truncate(V: np.ndarray, U: np.ndarray, tol: float):
+    """Keep the directions of ``V`` with singular value ``> tol sigma_1``: eigen-
+    decomposition of ``V^T V`` (descending); returns ``V Z_q, U Z_q, q``."""
+    lam, Z = np.linalg.eigh(V.T @ V)
+    order = np.argsort(lam)[::-1]
+    lam, Z = lam[order], Z[:, order]
+    sig = np.sqrt(np.maximum(lam, 0.0))
+    q = 0 if sig.size == 0 or sig[0] == 0.0 else int(np.count_nonzero(sig > tol * sig[0]))
+    return V @ Z[:, :q], U @ Z[:, :q], q
+
+
 def compress(LO: np.ndarray, j: int, opts: Options, tol: float):
     """Algorithm 3 on an explicit ``L^O_j`` followed by the truncation above."""
     r, c = LO.shape
@@ -123,12 +145,77 @@ def compress(LO: np.ndarray, j: int, opts: Options, tol: float):
         Y = LO.T @ (LO @ Y)
     U, _ = np.linalg.qr(Y)
     V = LO @ U
-    lam, Z = np.linalg.eigh(V.T @ V)
-    order = np.argsort(lam)[::-1]
-    lam, Z = lam[order], Z[:, order]
-    sig = np.sqrt(np.maximum(lam, 0.0))
-    q = 0 if sig.size == 0 or sig[0] == 0.0 else int(np.count_nonzero(sig > tol * sig[0]))
-    return V @ Z[:, :q], U @ Z[:, :q], ell, q
+    Vq, Uq, q = _truncate(V, U, tol)
+    return Vq, Uq, ell, q
+
+
+def _pair_rows(sym: Symbolic, j: int, k: int, p0: int, nD: int):
+    """Rows of descendant ``k``'s operand that meet supernode ``j``: ``C_j``-local
+    positions of ``R^D_{k->j}`` and ``R_j``-local positions of ``R^O_{k->j}`` (§2.1)."""
+    lo = int(sym.first[j])
+    Rk = sym.rows[k]
+    return Rk[p0:p0 + nD] - lo, np.searchsorted(sym.rows[j], Rk[p0 + nD:])
+
+
+def _descendant_term(F: Factor, k: int, p0: int, nD: int, G: np.ndarray, transpose: bool):
+    """One descendant's product of Algorithm 2 (lines 10-11, or eq. lowRankMult for a
+    compressed ``k``): ``L^O_k(r^O) [L^O_k(r^D)]^T G`` (``G`` on the ``r^D`` rows), or
+    with ``transpose`` ``L^O_k(r^D) [L^O_k(r^O)]^T G`` (``G`` on the ``r^O`` rows)."""
+    if F.LO[k] is not None:
+        X = F.LO[k][p0:]
+        XD, XO = X[:nD], X[nD:]
+        return XD @ (XO.T @ G) if transpose else XO @ (XD.T @ G)
+    Vk = F.V[k][p0:]
+    VD, VO = Vk[:nD], Vk[nD:]
+    Uprod = F.U[k].T @ F.U[k]
+    return VD @ (Uprod @ (VO.T @ G)) if transpose else VO @ (Uprod @ (VD.T @ G))
+
+
+def offdiag_multiply(F: Factor, j: int, G: np.ndarray) -> np.ndarray:
+    """Algorithm 2 (offDiagonalMultiply): ``L^O_j G`` for ``G`` of ``c_j`` rows, from
+    ``(L^D_j)^{-T} G``, the block ``A(R_j, C_j)`` and the descendants of ``j``; needs
+    ``L^D_j`` and the factored descendants, never ``L^O_j`` itself."""
+    sym, Ap = F.sym, F.Ap
+    lo, hi = int(sym.first[j]), int(sym.first[j + 1])
+    R = sym.rows[j]
+    G = sla.solve_triangular(F.LD[j], G, lower=True, trans="T")
+    W = Ap[R][:, lo:hi] @ G
+    for (k, p0, nD) in sym.pairs[j]:
+        cols, orow = _pair_rows(sym, j, k, p0, nD)
+        if orow.size:
+            W[orow] -= _descendant_term(F, k, p0, nD, G[cols], transpose=False)
+    return W
+
+
+def offdiag_multiply_transpose(F: Factor, j: int, G: np.ndarray) -> np.ndarray:
+    """The transpose product ``(L^O_j)^T G`` for ``G`` of ``r_j`` rows (the function
+    the paper names offDiagonalMultiplyTranspose): ``A(R_j, C_j)^T G`` minus every
+    descendant's term gathered from the ``r^O`` rows and scattered to the ``r^D``
+    columns, then ``(L^D_j)^{-1}`` applied."""
+    sym, Ap = F.sym, F.Ap
+    lo, hi = int(sym.first[j]), int(sym.first[j + 1])
+    R = sym.rows[j]
+    S = Ap[R][:, lo:hi].T @ G
+    for (k, p0, nD) in sym.pairs[j]:
+        cols, orow = _pair_rows(sym, j, k, p0, nD)
+        if orow.size:
+            S[cols] -= _descendant_term(F, k, p0, nD, G[orow], transpose=True)
+    return sla.solve_triangular(F.LD[j], S, lower=True)
+
+
+def compress_implicit(F: Factor, j: int, opts: Options, tol: float):
+    """Algorithm 3 through Algorithm 2 and its transpose, then the truncation."""
+    sym = F.sym
+    r, c = sym.r(j), sym.c(j)
+    ell = sample_count(r, c, opts.alpha_O, opts.oversample)
+    G = gaussian_sample(opts.seed, j, r, ell)
+    Y = offdiag_multiply_transpose(F, j, G)
+    for _ in range(opts.power_iters):
+        Y = offdiag_multiply_transpose(F, j, offdiag_multiply(F, j, Y))
+    U, _ = np.linalg.qr(Y)
+    V = offdiag_multiply(F, j, U)
+    Vq, Uq, q = _truncate(V, U, tol)
+    return Vq, Uq, ell, q
 
 
 def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
@@ -137,16 +224,18 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
     ``progress(j, M)``, if given, is called after each supernode (reporting only)."""
     opts = opts or Options()
     Ap = permuted_matrix(sym, n, rowptr, colind, values)
-    F = Factor(sym=sym, tol=tol, opts=opts)
+    F = Factor(sym=sym, tol=tol, opts=opts, Ap=Ap)
     M = sym.M if stop_after is None else min(sym.M, stop_after)
     fl = dict(potrf=0.0, trsm=0.0, update=0.0, sample=0.0, orth=0.0, trunc=0.0)
     for j in range(M):
         lo, hi = int(sym.first[j]), int(sym.first[j + 1])
         c = hi - lo
         R = sym.rows[j]
+        comp = compressible(sym, j, opts, tol)
+        implicit = comp and opts.implicit   # the off-diagonal block is only used through Algorithm 2
         # Initialise the Schur complement blocks (Algorithm 1)
         UD = Ap[lo:hi][:, lo:hi].toarray()
-        UO = Ap[R][:, lo:hi].toarray() if R.size else np.zeros((0, c))
+        UO = Ap[R][:, lo:hi].toarray() if (R.size and not implicit) else np.zeros((0, c))
         for (k, p0, nD) in sym.pairs[j]:
             X = F.offdiag(k)[p0:]
             XD = X[:nD]
@@ -154,7 +243,7 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
             cols = Rk[p0:p0 + nD] - lo                       # R^D_{k->j} within C_j
             orow = np.searchsorted(R, Rk[p0 + nD:])          # R^O_{k->j} within R_j
             UD[np.ix_(cols, cols)] -= XD @ XD.T
-            if orow.size:
+            if orow.size and not implicit:
                 UO[np.ix_(orow, cols)] -= X[nD:] @ XD.T
             fl["update"] += 2.0 * X.shape[1] * (nD * (nD + 1) / 2.0 + float(X.shape[0] - nD) * nD)
         try:
@@ -163,12 +252,19 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
             raise NotSPDError(j) from None
         if not np.all(np.isfinite(LD)):
             raise NotSPDError(j)
-        LO = sla.solve_triangular(LD, UO.T, lower=True).T if R.size else np.zeros((0, c))
+        LO = (sla.solve_triangular(LD, UO.T, lower=True).T if (R.size and not implicit)
+              else np.zeros((0, c)))
         fl["potrf"] += c ** 3 / 3.0
-        fl["trsm"] += float(R.size) * c * c
+        if not implicit:
+            fl["trsm"] += float(R.size) * c * c
         F.LD.append(LD)
-        if compressible(sym, j, opts, tol):
-            V, U, ell, q = compress(LO, j, opts, tol)
+        if comp:
+            if implicit:
+                V, U, ell, q = compress_implicit(F, j, opts, tol)
+            else:
+                if opts.keep_lo:
+                    F.LO_dense[j] = LO
+                V, U, ell, q = compress(LO, j, opts, tol)
             F.LO.append(None); F.V.append(V); F.U.append(U); F.ell.append(ell); F.q.append(q)
             fl["sample"] += 4.0 * R.size * c * ell * (1 + opts.power_iters)
             fl["orth"] += 2.0 * c * ell * ell

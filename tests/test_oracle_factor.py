@@ -249,3 +249,62 @@ def test_adjoint_matches_finite_differences():
     Lp = dense_adjoint(p.matrix().toarray(), p.b + h * e, p.x_target)[2]
     Lm = dense_adjoint(p.matrix().toarray(), p.b - h * e, p.x_target)[2]
     assert abs((Lp - Lm) / (2 * h) - lam[5]) <= 1e-6 * max(1.0, abs(lam[5]))
+
+
+# ---------------------------------------------------------------- Algorithm 2
+
+def _offdiag_worst(F, blocks, rng, k=6):
+    from oracle.factor import offdiag_multiply, offdiag_multiply_transpose
+    worst = 0.0
+    for j, LO in blocks:
+        G = rng.standard_normal((LO.shape[1], k))
+        H = rng.standard_normal((LO.shape[0], k))
+        a, b = offdiag_multiply(F, j, G), LO @ G
+        at, bt = offdiag_multiply_transpose(F, j, H), LO.T @ H
+        worst = max(worst, np.abs(a - b).max() / np.abs(b).max(), np.abs(at - bt).max() / np.abs(bt).max())
+    return worst
+
+
+def test_offdiag_multiply_is_the_explicit_block_product():
+    # Algorithm 2 and its transpose against L^O_j = U^O_j (L^D_j)^{-T} formed by the
+    # triangular solve of Algorithm 1 (the exact factor): the same block applied two
+    # ways, equal to rounding for every supernode with off-diagonal rows.
+    p = grid_problem((14, 13, 12), sigma=1.0, seed=3)
+    sym = symbolic(p.n, p.rowptr, p.colind, 32)
+    F = factor(sym, p.n, p.rowptr, p.colind, p.values, 0.0, Options(leaf_max=32))
+    blocks = [(j, F.LO[j]) for j in range(sym.M) if sym.r(j)]
+    assert _offdiag_worst(F, blocks, np.random.default_rng(0)) <= 1e-12
+
+
+def test_offdiag_multiply_with_compressed_descendants_matches_dense_block():
+    # With compressed descendants (eq. lowRankMult, U_prod = U_k^T U_k): Algorithm 2's
+    # product equals the dense L^O_j that the explicit path forms from the same
+    # low-rank updates, for every compressed supernode that has compressed descendants.
+    p = grid_problem((16, 15, 14), sigma=1.0, seed=4)
+    sym = symbolic(p.n, p.rowptr, p.colind, 32)
+    F = factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-2, Options(leaf_max=32, tau_O=16, keep_lo=True))
+    comp = {j for j in range(sym.M) if F.V[j] is not None}
+    blocks = [(j, F.LO_dense[j]) for j in sorted(comp) if any(k in comp for (k, _, _) in sym.pairs[j])]
+    assert len(blocks) >= 3
+    assert _offdiag_worst(F, blocks, np.random.default_rng(1)) <= 1e-12
+
+
+@pytest.mark.parametrize("power_iters", [0, 1])
+def test_implicit_compression_reproduces_explicit_factor(power_iters):
+    # Algorithm 3 through Algorithm 2 (L^O_j of compressed supernodes never formed)
+    # against Algorithm 3 on the explicit block, same samples: identical ranks, V_j U_j^T
+    # and preconditioner to rounding.
+    p = grid_problem((16, 15, 14), sigma=1.0, seed=5)
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    opts = dict(seed=7, power_iters=power_iters)
+    Fe = factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-2, Options(**opts))
+    Fi = factor(sym, p.n, p.rowptr, p.colind, p.values, 1e-2, Options(implicit=True, **opts))
+    assert Fe.ell == Fi.ell and Fe.q == Fi.q and sum(Fe.q) > 0
+    for j in range(sym.M):
+        if Fe.V[j] is not None:
+            a, b = Fe.V[j] @ Fe.U[j].T, Fi.V[j] @ Fi.U[j].T
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+            assert Fi.LO[j] is None
+    r = np.random.default_rng(2).standard_normal(p.n)
+    ze, zi = apply_preconditioner(Fe, r), apply_preconditioner(Fi, r)
+    assert np.linalg.norm(ze - zi) <= 1e-12 * np.linalg.norm(ze)
