@@ -191,8 +191,8 @@ void plan_layout(Handle& h) {
       if (!h.compressible[j]) continue;
       CompSlot& C = h.comp[j];
       const int64_t c = S.c(j), r = S.r(j), l = C.ell;
-      if (!h.opt.keep_lo) { h.lo_off_comp[j] = p; p += align64(c * r); }
       C.omega = p; p += align64(r * l);
+      C.tmp = p; p += align64(c * l);
       C.ypanel = p; p += align64((l + c) * l);
       C.ydinv = p; p += ((l + 63) / 64) * 4096;
       C.V = p; p += align64(r * l);
@@ -701,8 +701,12 @@ struct Builder {
     for (int32_t j : level) {
       const int32_t c = S.c(j), r = S.r(j), ld = h.panel_ld[j];
       if (r == 0) continue;
+      // a compressed supernode's L^O_j is only reached through the implicit products
+      // of Algorithm 2 (formed here only when kept for inspection, and not credited)
+      const bool implicit = P.compressed && h.compressible[j];
+      if (implicit && !h.opt.keep_lo) continue;
       const int64_t pan = h.panel_off[j];
-      mfl += (double)r * c * c;
+      if (!implicit) mfl += (double)r * c * c;
       GemmTask t = gt(h.uo_off[j], 1, r, pan + c, ld, 1, h.lo_off[j], r, r, c, c, 1.0, 0.0);
       for (int32_t j0 = 0; j0 < c; j0 += kTile)
         for (int32_t i0 = 0; i0 < r; i0 += kTile) {
@@ -920,8 +924,75 @@ struct Builder {
     panel_steps(pan);
   }
 
-  // Algorithm 3 on the explicit L^O_j of every compressible supernode of a level,
-  // followed by the spectral truncation.
+  // Algorithm 2 on the device.  Its descendant terms, summed over k, are the rows R_j of
+  // the Schur update: the update launch accumulates them once per supernode into U^O_j
+  // (level pool) instead of re-forming them for every product, so
+  //   L^O_j G = U^O_j ((L^D_j)^{-T} G) = U^O_j (M_j G)   and   (L^O_j)^T G = M_j^T (U^O_j^T G),
+  // with M_j = (L^D_j)^{-T} the inverse the panel factorisation leaves in rows [c, 2c) of
+  // the panel.  L^O_j (r x c) and the r c^2 solve that forms it are never needed.
+  // A product's operands: src (rows x l, column-major, ld) -> dst; the launch mode `mode`.
+  struct Blk { int64_t off; int32_t ld; };
+  // dst = M_j src (c x l): M_j upper triangular, row tile i0 needs k >= i0 (operands shifted)
+  double emit_M(const std::vector<int32_t>& js, const std::function<Blk(int32_t)>& src,
+                const std::function<Blk(int32_t)>& dst, int mode) {
+    const Symbolic& S = h.S;
+    const int64_t g0 = (int64_t)P.gemm.size();
+    double fl = 0;
+    for (int32_t j : js) {
+      const int32_t c = S.c(j), l = h.comp[j].ell, ldp = h.panel_ld[j];
+      const Blk s = src(j), d = dst(j);
+      const int64_t Mp = h.panel_off[j] + c;      // M(i, k) at Mp + i + k ldp
+      for (int32_t j0 = 0; j0 < l; j0 += kTile)
+        for (int32_t i0 = 0; i0 < c; i0 += kTile) {
+          GemmTask t = gt(Mp + (int64_t)i0 * ldp, 1, ldp, s.off + i0, s.ld, 1, d.off, d.ld, c, l, c - i0, 1.0, 0.0);
+          t.i0 = i0; t.j0 = j0;
+          P.gemm.push_back(t);
+          fl += 2.0 * std::min(kTile, c - i0) * std::min(kTile, l - j0) * (double)(c - i0);
+        }
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, mode);
+    return fl;
+  }
+  // dst = M_j^T src (c x l): M_j^T lower triangular, row tile i0 needs k < i0 + 64
+  double emit_MT(const std::vector<int32_t>& js, const std::function<Blk(int32_t)>& src,
+                 const std::function<Blk(int32_t)>& dst, int mode) {
+    const Symbolic& S = h.S;
+    const int64_t g0 = (int64_t)P.gemm.size();
+    double fl = 0;
+    for (int32_t j : js) {
+      const int32_t c = S.c(j), l = h.comp[j].ell, ldp = h.panel_ld[j];
+      const Blk s = src(j), d = dst(j);
+      const int64_t Mp = h.panel_off[j] + c;      // M^T(i, k) = M(k, i) at Mp + k + i ldp
+      for (int32_t j0 = 0; j0 < l; j0 += kTile)
+        for (int32_t i0 = 0; i0 < c; i0 += kTile) {
+          GemmTask t = gt(Mp, ldp, 1, s.off, s.ld, 1, d.off, d.ld, c, l, std::min(c, i0 + kTile), 1.0, 0.0);
+          t.i0 = i0; t.j0 = j0;
+          P.gemm.push_back(t);
+          fl += 2.0 * std::min(kTile, c - i0) * std::min(kTile, l - j0) * (double)t.k;
+        }
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, mode);
+    return fl;
+  }
+  // dst = U^O_j src (r x l, src c x l) or, with trans, dst = (U^O_j)^T src (c x l, src r x l)
+  double emit_UO(const std::vector<int32_t>& js, bool trans, const std::function<Blk(int32_t)>& src,
+                 const std::function<Blk(int32_t)>& dst, int mode) {
+    const Symbolic& S = h.S;
+    const int64_t g0 = (int64_t)P.gemm.size();
+    double fl = 0;
+    for (int32_t j : js) {
+      const int32_t c = S.c(j), r = S.r(j), l = h.comp[j].ell;
+      const Blk s = src(j), d = dst(j);
+      const int64_t uo = h.uo_off[j];             // U^O(i, k) at uo + i + k r
+      fl += trans ? tiles(gt(uo, r, 1, s.off, s.ld, 1, d.off, d.ld, c, l, r, 1.0, 0.0), 0, 0, false)
+                  : tiles(gt(uo, 1, r, s.off, s.ld, 1, d.off, d.ld, r, l, c, 1.0, 0.0), 0, 0, false);
+    }
+    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, mode);
+    return fl;
+  }
+
+  // Algorithm 3 for every compressible supernode of a level, its products with L^O_j
+  // formed implicitly (Algorithm 2, above), followed by the spectral truncation.
   void compression(const std::vector<int32_t>& level, double tol) {
     const Symbolic& S = h.S;
     std::vector<int32_t> js;
@@ -930,10 +1001,11 @@ struct Builder {
     if (js.empty()) return;
     ctx = RSC_K_SAMPLE;
     // algorithmic work of the steps (summed over the level's compressible supernodes)
-    double m_prod = 0, m_orth = 0, m_gram = 0, m_eig = 0;
+    double m_prod = 0, m_orth = 0, m_gram = 0, m_eig = 0, m_diag = 0;
     for (int32_t j : js) {
       const double c = S.c(j), r = S.r(j), l = h.comp[j].ell;
       m_prod += 2.0 * r * c * l;       // one product with L^O_j or its transpose
+      m_diag += c * c * l;             // Algorithm 2's diagonal solve of a c x l operand
       m_orth += 2.0 * c * l * l;       // orthonormalisation of the c x l sample
       m_gram += 2.0 * r * l * l;       // Gram matrix of V
       m_eig += 9.0 * l * l * l;        // symmetric eigen-decomposition of the l x l Gram matrix
@@ -953,17 +1025,20 @@ struct Builder {
     }
     // the mixed forms round the sample to BF16 in the product: the transform runs in FP32
     cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw, lp_sample ? 1 : 0);
-    // 2. Y = (L^O_j)^T Omega into rows [l, l + c) of the orthonormalisation panel
-    int64_t g0 = (int64_t)P.gemm.size();
-    double fl = 0;
-    for (int32_t j : js) {
-      const CompSlot& C = h.comp[j];
-      const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      const int64_t LO = h.lo_off[j];
-      fl += tiles(gt(LO, r, 1, C.omega, r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
-    }
-    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_sample);
+    // 2. Y = (L^O_j)^T Omega = M_j^T (U^O_j^T Omega) into rows [l, l + c) of the
+    //    orthonormalisation panel (the intermediate in the c x l work block `tmp`)
+    auto omega = [&](int32_t j) { return Blk{h.comp[j].omega, S.r(j)}; };
+    auto tmpb = [&](int32_t j) { return Blk{h.comp[j].tmp, S.c(j)}; };
+    auto ybl = [&](int32_t j) { return Blk{h.comp[j].ypanel + h.comp[j].ell, h.comp[j].ell + S.c(j)}; };
+    auto zbl = [&](int32_t j) { return Blk{h.comp[j].zpanel + h.comp[j].ell, h.comp[j].ell + S.r(j)}; };
+    auto vbl = [&](int32_t j) { return Blk{h.comp[j].V, S.r(j)}; };
+    emit_UO(js, true, omega, tmpb, lp_sample);
     credit(cs, m_prod);
+    cs = P.cmds.size();
+    emit_MT(js, tmpb, ybl, lp_update);
+    credit(cs, m_diag);
+    int64_t g0;
+    double fl;
     // 3. power iterations Y = (L^O)^T (L^O Y).  Each product is preceded by one shifted
     //    Cholesky-QR pass over its operand: the span is unchanged (a right factor), but the
     //    operand's spread of singular values no longer compounds over the iterations, so
@@ -971,26 +1046,18 @@ struct Builder {
     for (int it = 0; it < h.opt.power_iters; ++it) {
       cholqr_pass(js, false, true);
       cs = P.cmds.size();
-      g0 = (int64_t)P.gemm.size(); fl = 0;
-      for (int32_t j : js) {
-        const CompSlot& C = h.comp[j];
-        const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-        const int64_t LO = h.lo_off[j];
-        fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.zpanel + l, l + r, r, l, c, 1.0, 0.0), 0, 0, false);
-      }
-      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      emit_M(js, ybl, tmpb, 0);                // Z = L^O Y = U^O (M Y)
+      credit(cs, m_diag);
+      cs = P.cmds.size();
+      emit_UO(js, false, tmpb, zbl, 0);
       credit(cs, m_prod);
       cholqr_pass(js, true, true);
       cs = P.cmds.size();
-      g0 = (int64_t)P.gemm.size(); fl = 0;
-      for (int32_t j : js) {
-        const CompSlot& C = h.comp[j];
-        const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-        const int64_t LO = h.lo_off[j];
-        fl += tiles(gt(LO, r, 1, C.zpanel + l, l + r, 1, C.ypanel + l, ldy, c, l, r, 1.0, 0.0), 0, 0, false);
-      }
-      cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
+      emit_UO(js, true, zbl, tmpb, 0);         // Y = (L^O)^T Z = M^T (U^O^T Z)
       credit(cs, m_prod);
+      cs = P.cmds.size();
+      emit_MT(js, tmpb, ybl, 0);
+      credit(cs, m_diag);
     }
     ctx = RSC_K_ORTH;
     // 4. orthonormalisation by Cholesky-QR passes, dependent columns dropped.  Two plain
@@ -1007,14 +1074,10 @@ struct Builder {
     // 5. V = L^O_j U (FP32 MFMA in the mixed forms, like the other basis products: its
     //    rounding, ~1e-7 of |V|, is far below the truncation threshold tol^2 lambda_max)
     cs = P.cmds.size();
-    g0 = (int64_t)P.gemm.size(); fl = 0;
-    for (int32_t j : js) {
-      const CompSlot& C = h.comp[j];
-      const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      const int64_t LO = h.lo_off[j];
-      fl += tiles(gt(LO, 1, r, C.ypanel + l, ldy, 1, C.V, r, r, l, c, 1.0, 0.0), 0, 0, false);
-    }
-    cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl, lp_eig);
+    emit_M(js, ybl, tmpb, lp_eig);             // V = L^O U = U^O (M U)
+    credit(cs, m_diag);
+    cs = P.cmds.size();
+    emit_UO(js, false, tmpb, vbl, lp_eig);
     credit(cs, m_prod);
     ctx = RSC_K_EIG;
     // 6. Gram G = V^T V (full)
@@ -1289,10 +1352,11 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   for (int64_t j = 0; j < S.M(); ++j) {
     const double c = S.c(j), r = S.r(j);
     P->flops[0] += c * c * c / 3.0;
-    P->flops[1] += r * c * c;
+    if (!(compressed && h.compressible[j])) P->flops[1] += r * c * c;
     if (compressed && h.compressible[j]) {
       const double l = h.comp[j].ell;
-      P->flops[3] += 4.0 * r * c * l * (1 + h.opt.power_iters);
+      // the products with U^O_j and Algorithm 2's diagonal solves (c^2 l each)
+      P->flops[3] += (4.0 * r * c * l + 2.0 * c * c * l) * (1 + h.opt.power_iters);
       P->flops[4] += 2.0 * c * l * l;
       P->flops[5] += 2.0 * r * l * l + 9.0 * l * l * l;   // + the kept basis, at the ranks (stats)
     }

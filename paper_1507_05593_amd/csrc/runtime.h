@@ -79,6 +79,7 @@ struct CompSlot {
   int32_t ell = 0;
   int64_t omega = -1, ypanel = -1, ydinv = -1, V = -1, Vj = -1, Uj = -1, gscale = -1, tvq = -1,
           u = -1;
+  int64_t tmp = -1;                  // c x l work block of the implicit products
   int64_t zpanel = -1, zdinv = -1;   // power iterations: [Gram; L^O Y] panel ((l + r) x l) and its inverses
   // truncation work space (l x l blocks, panels with ld 2l)
   int64_t G = -1, Sa = -1, Sb = -1, Mpan = -1, Mdinv = -1, Wpan = -1, Wdinv = -1, Om2 = -1,

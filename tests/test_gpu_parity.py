@@ -105,7 +105,9 @@ def test_preconditioner_apply_matches_oracle_exact_and_compressed():
         sol = _sol(p, seed=7)
         sol.factor(_vals(p), tol)
         z = sol.apply(_vec(r)).cpu().numpy()
-        F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, tol, Options(seed=7))
+        # compressed: the oracle also through Algorithm 2 (L^O_j of compressed supernodes
+        # never formed on either side)
+        F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, tol, Options(seed=7, implicit=tol > 0))
         zo = o_apply(F, r)
         # the compressed factors agree to the conditioning of the truncation only
         bound = 1e-11 if tol == 0 else 1e-6
