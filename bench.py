@@ -29,6 +29,11 @@ Prints one JSON line.  Fields beyond the common ones:
 
   --calibrate-copy   only time a plain device copy of 1 GiB (the reference kernel
                      for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit
+  --summarize-pmc FETCH WRITE COPYFETCH COPYWRITE --pmc-kernel NAME --pmc-last N
+                     turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the
+                     bench, then of --calibrate-copy) into the kernel's HBM bytes per
+                     launch over its last N dispatches (one factorization), each counter
+                     scaled by what it reads for the plain copy of known size (JSON)
   --summarize-trace DIR [--trace-last-from LINE.json]
                      turn a rocprofv3 --kernel-trace --stats CSV directory into the
                      kernel-time summary (JSON on stdout): per kernel over all
@@ -76,6 +81,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-trace", default="", help="rocprofv3 kernel-trace CSV directory")
     ap.add_argument("--trace-last-from", default="", help="bench output whose profiled pass the trace ends with")
+    ap.add_argument("--summarize-pmc", nargs=4, default=None)
+    ap.add_argument("--pmc-kernel", default="gemm_staged_f64")
+    ap.add_argument("--pmc-last", type=int, default=0)
     ap.add_argument("--cpu-record", action="store_true",
                     help="time the oracle on the full workload and on the bench's sample (no GPU)")
     return ap.parse_args()
@@ -438,6 +446,53 @@ def summarize_trace(d, last_from):
     print(json.dumps(out, indent=1), flush=True)
 
 
+def _pmc_rows(d, counter):
+    """(dispatch id, kernel name, value) of one counter in a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    return sorted(out)
+
+
+def summarize_pmc(dirs, kernel, last, workload):
+    fetch_d, write_d, cfetch_d, cwrite_d = dirs
+    def per_dispatch(d, counter, pick):
+        rows = [x for x in _pmc_rows(d, counter) if pick(x[1])]
+        return rows
+    mine = lambda nm: profile_name(nm) == kernel
+    fr = per_dispatch(fetch_d, "FETCH_SIZE", mine)[-last:]
+    wr = per_dispatch(write_d, "WRITE_SIZE", mine)[-last:]
+    copy = lambda nm: "copy" in nm.lower() or "elementwise" in nm.lower() or "direct_copy" in nm.lower()
+    cf = per_dispatch(cfetch_d, "FETCH_SIZE", copy)
+    cw = per_dispatch(cwrite_d, "WRITE_SIZE", copy)
+    nbytes = 1 << 30
+    # the copy's last dispatch moves exactly nbytes each way
+    fkib, wkib = cf[-1][2], cw[-1][2]
+    ff, wf = nbytes / 1024.0 / fkib, nbytes / 1024.0 / wkib
+    f_avg = sum(x[2] for x in fr) / len(fr)
+    w_avg = sum(x[2] for x in wr) / len(wr)
+    src, dig = source_digest(kernel)
+    out = {"kernel": kernel, "workload": workload, "source": src, "source_sha256_16": dig,
+           "dispatches_used": len(fr), "fetch_kib_per_dispatch": f_avg, "write_kib_per_dispatch": w_avg,
+           "copy_calibration": {"bytes": nbytes, "fetch_kib": fkib, "write_kib": wkib, "fetch_factor": ff,
+                                "write_factor": wf},
+           "hbm_bytes_per_launch": 1024.0 * (f_avg * ff + w_avg * wf),
+           "commands": [
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-profile --compare none --no-graph",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-profile --compare none --no-graph",
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/copyfetch -o run -- python3 bench.py --calibrate-copy",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/copywrite -o run -- python3 bench.py --calibrate-copy",
+               f"python bench.py --summarize-pmc OUT/fetch OUT/write OUT/copyfetch OUT/copywrite --pmc-kernel {kernel} --pmc-last {last}"],
+           "note": "last N dispatches of the kernel in each counter run = one factorization; FETCH_SIZE and "
+                   "WRITE_SIZE scaled by what they read for a plain 1 GiB device copy"}
+    print(json.dumps(out, indent=1), flush=True)
+
+
 # ------------------------------------------------------------------ main
 
 def main():
@@ -449,6 +504,9 @@ def main():
     name = args.workload
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.trace_last_from)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.pmc_kernel, args.pmc_last, name)
         return
     if args.cpu_record:
         from workloads import workload_config
