@@ -78,6 +78,11 @@ typedef struct {
   int32_t keep_lo;     /* rank-structured factor: keep the dense L^O_j of every compressed
                           supernode for rsc_get_block (1), or hold it only while its level is
                           factored, in memory reused by the next level (0) */
+  int32_t sweep_small_c; /* the preconditioner's sweeps run each elimination-tree level whose
+                          supernodes all have at most this many columns (and at most 2048 rows
+                          R_j) as one launch per sweep, one workgroup per supernode; the lowest
+                          such levels only, up to the first level that exceeds the bound; at
+                          most 1024, 0 = every level by the per-operation launches (64) */
 } rsc_options;
 
 typedef struct {
@@ -233,7 +238,7 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
  * (both as for rsc_profile; launches whose extents depend on the kept ranks are counted
  * at the ranks of the factorisation that ran).  Any output may be NULL.  Errors:
  * RSC_ERR_INVALID_ARG for a null handle or k out of range. */
-#define RSC_KERNELS 36
+#define RSC_KERNELS 38
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops, double* tile_flops);
 

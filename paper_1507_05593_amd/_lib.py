@@ -23,14 +23,15 @@ RSC_MIXED_FP32 = 2
 
 K_CLASSES = ["update", "panel_potrf", "panel_trsm", "panel_trailing", "truncation", "pcg", "other", "lo_product",
              "sample", "orthonormalise", "basis"]
-RSC_KERNELS = 36
+RSC_KERNELS = 38
 
 
 class Options(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("tau_O", C.c_int32), ("oversample", C.c_int32),
                 ("power_iters", C.c_int32), ("alpha_O", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("use_graph", C.c_int32), ("retry", C.c_int32),
-                ("gemm_tile", C.c_int32), ("keep_lo", C.c_int32)]
+                ("gemm_tile", C.c_int32), ("keep_lo", C.c_int32),
+                ("sweep_small_c", C.c_int32)]
 
 
 class PcgResult(C.Structure):

@@ -38,7 +38,8 @@ rsc_status ret(const rsc::Error& e) {
 rsc_status check_options(const rsc_options& o) {
   if (o.leaf_max < 1 || o.tau_O < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.alpha_O > 0) ||
       o.precision < RSC_FP64 || o.precision > RSC_MIXED_FP32 ||
-      (o.gemm_tile != 0 && o.gemm_tile != 64 && o.gemm_tile != 128))
+      (o.gemm_tile != 0 && o.gemm_tile != 64 && o.gemm_tile != 128) || o.sweep_small_c < 0 ||
+      o.sweep_small_c > 1024)
     return fail(RSC_ERR_INVALID_ARG, "option out of range");
   return RSC_OK;
 }
@@ -121,6 +122,7 @@ void rsc_default_options(rsc_options* o) {
   o->precision = RSC_FP64;
   o->use_graph = 1;
   o->retry = 1;
+  o->sweep_small_c = 64;
 }
 
 rsc_status rsc_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,

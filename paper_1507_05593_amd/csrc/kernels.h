@@ -50,6 +50,14 @@ void launch_coldot(const ColDotTask* t, int n, double* arena, const float* f32, 
                    const int32_t* ilim, double* part, hipStream_t s);
 void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* contrib,
                        int64_t nrows, const double* part, double* y, hipStream_t s);
+// small-supernode sweep levels: nt threads per supernode (64 or 256), LDS vectors of
+// cpad (columns), lpad (ranks) and rmax (rows) doubles
+void launch_sweep_fwd(const SweepTask* t, int n, int nt, int cpad, int lpad, double* arena,
+                      const float* f32, int64_t a_y, int64_t a_w, int64_t a_zr, const int32_t* ilim,
+                      const int64_t* pull_ptr, const int64_t* pull_idx, hipStream_t s);
+void launch_sweep_bwd(const SweepTask* t, int n, int nt, int cpad, int lpad, int rmax, double* arena,
+                      const float* f32, int64_t a_w, int64_t a_zz, const int32_t* ilim,
+                      const int64_t* rows_idx, hipStream_t s);
 void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);
 void launch_scatter_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);
 void launch_spmv_dot(const Chunk* c, int nc, const int64_t* rowptr, const int32_t* colind,

@@ -162,6 +162,128 @@ __global__ void k_row_gather(const int64_t* __restrict__ rows, const int64_t* __
   y[rows[t]] -= s;
 }
 
+// Small-supernode sweep levels (SweepTask): one workgroup of 64 or 256 threads per
+// supernode runs the whole level step of a sweep, its vectors in LDS.  Column dots use
+// 16 lanes per column (a fixed butterfly at the end), row products one thread per row
+// (column-major operands: the threads of a column read consecutive entries).
+__device__ __forceinline__ double sum16(double acc) {
+  for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  return acc;
+}
+
+// Forward step:  y_C minus the descendants' contributions (pulled from zr in list order),
+// w_C = (L^D_j)^{-1} y_C = M_j^T y_C, and t = L^O_j w_C or V_j (U_j^T w_C) stored in the
+// supernode's zr slots, from which its ancestors pull.  LDS: y_C, w_C (cpad each), U^T w.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_sweep_fwd(const SweepTask* __restrict__ tasks,
+                                                   const double* __restrict__ y, double* __restrict__ w,
+                                                   double* __restrict__ zr, const TF* __restrict__ F,
+                                                   const int32_t* __restrict__ ilim,
+                                                   const int64_t* __restrict__ pull_ptr,
+                                                   const int64_t* __restrict__ pull_idx, int32_t cpad) {
+  extern __shared__ double sm[];
+  const SweepTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int g = tid >> 4, gl = tid & 15, ng = nt >> 4;
+  double* yc = sm;
+  double* wc = sm + cpad;
+  double* tq = sm + 2 * cpad;
+  for (int i = tid; i < T.c; i += nt) {
+    const int64_t row = T.first + i;
+    double s = y[row];
+    for (int64_t p = pull_ptr[row]; p < pull_ptr[row + 1]; ++p) s -= zr[pull_idx[p]];
+    yc[i] = s;
+  }
+  __syncthreads();
+  for (int col = g; col < T.c; col += ng) {
+    const TF* X = F + T.m + (int64_t)col * T.ld;
+    double acc = 0.0;
+    for (int t = gl; t <= col; t += 16) acc += (double)X[t] * yc[t];
+    acc = sum16(acc);
+    if (gl == 0) {
+      wc[col] = acc;
+      w[T.first + col] = acc;
+    }
+  }
+  __syncthreads();
+  const double* v = wc;
+  int K = T.c;
+  if (T.u >= 0) {
+    K = min(ilim[T.qslot], T.kmax);
+    for (int k = g; k < K; k += ng) {
+      const TF* U = F + T.u + (int64_t)k * T.c;
+      double acc = 0.0;
+      for (int i = gl; i < T.c; i += 16) acc += (double)U[i] * wc[i];
+      acc = sum16(acc);
+      if (gl == 0) tq[k] = acc;
+    }
+    __syncthreads();
+    v = tq;
+  }
+  for (int i = tid; i < T.r; i += nt) {
+    const TF* X = F + T.x + i;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < K; ++k) acc += (double)X[(int64_t)k * T.r] * v[k];
+    zr[T.rows + i] = acc;
+  }
+}
+
+// Backward step:  z_R gathered from zz, s = (L^O_j)^T z_R or U_j (V_j^T z_R), and
+// z_C = (L^D_j)^{-T} (w_C - s) = M_j (w_C - s) into zz.  LDS: w_C - s (cpad), V^T z_R
+// (lpad), z_R.
+template <typename TF>
+__global__ __launch_bounds__(256) void k_sweep_bwd(const SweepTask* __restrict__ tasks,
+                                                   const double* __restrict__ w, double* __restrict__ zz,
+                                                   const TF* __restrict__ F,
+                                                   const int32_t* __restrict__ ilim,
+                                                   const int64_t* __restrict__ rows_idx, int32_t cpad,
+                                                   int32_t lpad) {
+  extern __shared__ double sm[];
+  const SweepTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int g = tid >> 4, gl = tid & 15, ng = nt >> 4;
+  double* v = sm;
+  double* uq = sm + cpad;
+  double* zR = sm + cpad + lpad;
+  for (int i = tid; i < T.r; i += nt) zR[i] = zz[rows_idx[T.rows + i]];
+  __syncthreads();
+  if (T.u < 0) {
+    for (int col = g; col < T.c; col += ng) {
+      const TF* X = F + T.x + (int64_t)col * T.r;
+      double acc = 0.0;
+      for (int i = gl; i < T.r; i += 16) acc += (double)X[i] * zR[i];
+      acc = sum16(acc);
+      if (gl == 0) v[col] = w[T.first + col] - acc;
+    }
+  } else {
+    const int K = min(ilim[T.qslot], T.kmax);
+    for (int k = g; k < K; k += ng) {
+      const TF* V = F + T.x + (int64_t)k * T.r;
+      double acc = 0.0;
+      for (int i = gl; i < T.r; i += 16) acc += (double)V[i] * zR[i];
+      acc = sum16(acc);
+      if (gl == 0) uq[k] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < T.c; i += nt) {
+      const TF* U = F + T.u + i;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < K; ++k) acc += (double)U[(int64_t)k * T.c] * uq[k];
+      v[i] = w[T.first + i] - acc;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < T.c; i += nt) {
+    const TF* M = F + T.m + i;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int t = i; t < T.c; ++t) acc += (double)M[(int64_t)t * T.ld] * v[t];
+    zz[T.first + i] = acc;
+  }
+}
+
 __global__ void k_gather_perm(int64_t n, const int64_t* __restrict__ perm,
                               const double* __restrict__ src, double* __restrict__ dst) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -427,6 +549,30 @@ void launch_row_gather(const int64_t* rows, const int64_t* ptr, const int64_t* c
   if (nrows > 0)
     hipLaunchKernelGGL(k_row_gather, dim3(blocks_for(nrows)), dim3(256), 0, s, rows, ptr, contrib,
                        nrows, part, y);
+}
+void launch_sweep_fwd(const SweepTask* t, int n, int nt, int cpad, int lpad, double* arena,
+                      const float* f32, int64_t a_y, int64_t a_w, int64_t a_zr, const int32_t* ilim,
+                      const int64_t* pull_ptr, const int64_t* pull_idx, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = sizeof(double) * (size_t)(2 * cpad + lpad);
+  if (f32)
+    hipLaunchKernelGGL(k_sweep_fwd<float>, dim3(n), dim3(nt), lds, s, t, arena + a_y, arena + a_w,
+                       arena + a_zr, f32, ilim, pull_ptr, pull_idx, cpad);
+  else
+    hipLaunchKernelGGL(k_sweep_fwd<double>, dim3(n), dim3(nt), lds, s, t, arena + a_y, arena + a_w,
+                       arena + a_zr, (const double*)arena, ilim, pull_ptr, pull_idx, cpad);
+}
+void launch_sweep_bwd(const SweepTask* t, int n, int nt, int cpad, int lpad, int rmax, double* arena,
+                      const float* f32, int64_t a_w, int64_t a_zz, const int32_t* ilim,
+                      const int64_t* rows_idx, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = sizeof(double) * (size_t)(cpad + lpad + rmax);
+  if (f32)
+    hipLaunchKernelGGL(k_sweep_bwd<float>, dim3(n), dim3(nt), lds, s, t, arena + a_w, arena + a_zz,
+                       f32, ilim, rows_idx, cpad, lpad);
+  else
+    hipLaunchKernelGGL(k_sweep_bwd<double>, dim3(n), dim3(nt), lds, s, t, arena + a_w, arena + a_zz,
+                       (const double*)arena, ilim, rows_idx, cpad, lpad);
 }
 void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n)), dim3(256), 0, s, n, perm, src, dst);

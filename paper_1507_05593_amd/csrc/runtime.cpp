@@ -2,12 +2,13 @@
 // hipGraph replay, the factor driver and the PCG driver.
 //
 // Storage (one FP64 arena per handle):
-//   panel j: column-major (2 c_j + r_j) x c_j, ld = 2 c_j + r_j; rows [0, c) hold L^D_j,
-//   rows [c, c + r) hold L^O_j (rows R_j in order), rows [c + r, 2c + r) start as the
-//   identity and end as L^D_j^{-T} (the same blocked solve that forms L^O_j), which
-//   the preconditioner sweeps use as explicit inverses of the diagonal blocks.
-//   A compressed supernode additionally owns V_j (r x l_j) and U_j (c x l_j) and the
-//   work space of its range finder.
+//   panel j: column-major 2 c_j x c_j, ld = 2 c_j; rows [0, c) hold L^D_j, rows [c, 2c)
+//   start as the identity and end as M_j = (L^D_j)^{-T} (the same blocked factorisation
+//   step), the explicit inverse that the sweeps and the implicit products use.
+//   L^O_j (r_j x c_j, ld r_j, rows R_j in order) has a block of its own; a compressed
+//   supernode holds V_j (r x l_j) and U_j (c x l_j) instead (the first q_j columns are
+//   the kept basis).  The Schur update U^O_j and the range finder's work space live in a
+//   level pool that every elimination-tree level reuses.
 #include "runtime.h"
 
 #include <algorithm>
@@ -1463,7 +1464,7 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "trunc_compact", "assemble", "fill", "row_gather", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
     "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
-    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns"};
+    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns", "sweep_fwd", "sweep_bwd"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
   switch (type) {
@@ -1476,6 +1477,8 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
     case kCmdTruncCopy: return 33;
     case kCmdToF32: return 34;
     case kCmdTruncNs: return 35;
+    case kCmdSweepFwd: return 36;
+    case kCmdSweepBwd: return 37;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -1552,6 +1555,14 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNs, s);
       break;
     case kCmdPartApply: launch_part_apply(Q->d_papply.p + c.off, (int)c.count, QP, A, s); break;
+    case kCmdSweepFwd:
+      launch_sweep_fwd(Q->d_sweep.p + c.off, (int)c.count, (int)c.a, (int)c.b, c.lds_l, A, F32, h.a_y,
+                       h.a_w, h.a_zr, I, Q->d_pull_ptr.p, Q->d_pull_idx.p, s);
+      break;
+    case kCmdSweepBwd:
+      launch_sweep_bwd(Q->d_sweep.p + c.off, (int)c.count, (int)c.a, (int)c.b, c.lds_l, c.lds_r, A, F32,
+                       h.a_w, h.a_zz, I, h.d_rows.p, s);
+      break;
     case kCmdGatherRows:
       launch_gather_rows(Q->d_gath.p + 2 * c.off, (int)c.count, h.d_rows.p, A + h.a_zz, A + h.a_zr, s);
       break;
@@ -1788,8 +1799,96 @@ static Error build_solve_plan(Handle& h) {
   };
   auto iscomp = [&](int64_t j) { return comp && h.compressible[j]; };
   double bytes = 0;
+  // Small-supernode levels: the lowest levels whose supernodes all fit one workgroup
+  // (at most sweep_small_c columns and kSweepMaxR rows) run each sweep step as one launch
+  // (k_sweep_fwd / k_sweep_bwd).  Inside them a row pulls its descendants' contributions
+  // when its own supernode is solved; the contributions to rows above them are applied
+  // by one row gather before the first larger level.
+  struct SmallLevel {
+    int64_t t0 = 0, nt = 0;
+    int32_t threads = 64, cpad = 1, lpad = 0, rmax = 0;
+  };
+  int32_t nsmall = 0;
+  while (h.opt.sweep_small_c > 0 && nsmall < S.nlevels) {
+    bool ok = true;
+    for (int32_t j : S.by_level[nsmall]) ok = ok && S.c(j) <= h.opt.sweep_small_c && S.r(j) <= kSweepMaxR;
+    if (!ok) break;
+    ++nsmall;
+  }
+  Q->small_levels = nsmall;
+  std::vector<SmallLevel> small(nsmall);
+  std::vector<std::pair<int64_t, int64_t>> outside;   // (row, zr slot) of rows above them
+  if (nsmall > 0) {
+    auto small_row = [&](int64_t row) { return S.level[S.owner[row]] < nsmall; };
+    std::vector<int64_t> ptr((size_t)S.n + 1, 0);
+    for (int32_t L = 0; L < nsmall; ++L) {
+      SmallLevel& sl = small[L];
+      sl.t0 = (int64_t)Q->sweep.size();
+      int32_t cmax = 1, rmax = 0, lmax = 0;
+      for (int32_t j : S.by_level[L]) {
+        const int32_t c = S.c(j), r = S.r(j);
+        SweepTask t{};
+        t.m = h.panel_off[j] + c; t.ld = h.panel_ld[j];
+        t.first = S.first[j]; t.rows = S.rows_ptr[j]; t.c = c; t.r = r;
+        t.x = 0; t.u = -1; t.qslot = -1; t.kmax = 0;
+        if (iscomp(j)) {
+          const CompSlot& C = h.comp[j];
+          t.x = C.Vj; t.u = C.Uj; t.qslot = C.qslot; t.kmax = C.ell;
+          lmax = std::max(lmax, C.ell);
+          bytes += 2.0 * 8.0 * (double)(c + r) * C.ell;
+        } else if (r > 0) {
+          t.x = h.lo_off[j];
+          bytes += 2.0 * 8.0 * (double)r * c;
+        }
+        bytes += 2.0 * 8.0 * c * (c + 1) / 2;
+        Q->sweep.push_back(t);
+        cmax = std::max(cmax, c);
+        rmax = std::max(rmax, r);
+        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j + 1]; ++p) {
+          const int64_t row = S.rows[p];
+          if (small_row(row)) ++ptr[row + 1];
+          else outside.push_back({row, p});
+        }
+      }
+      sl.nt = (int64_t)Q->sweep.size() - sl.t0;
+      sl.threads = (cmax <= 64 && rmax <= 256) ? 64 : 256;
+      sl.cpad = cmax; sl.lpad = lmax; sl.rmax = rmax;
+    }
+    for (int64_t i = 0; i < S.n; ++i) ptr[i + 1] += ptr[i];
+    Q->pull_idx.assign((size_t)ptr[S.n], 0);
+    std::vector<int64_t> next(ptr.begin(), ptr.end() - 1);
+    for (int32_t L = 0; L < nsmall; ++L)
+      for (int32_t j : S.by_level[L])
+        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j + 1]; ++p)
+          if (small_row(S.rows[p])) Q->pull_idx[(size_t)next[S.rows[p]]++] = p;
+    Q->pull_ptr = std::move(ptr);
+    std::stable_sort(outside.begin(), outside.end(), [](const std::pair<int64_t, int64_t>& x,
+                                                        const std::pair<int64_t, int64_t>& y) { return x.first < y.first; });
+  }
+  auto small_cmd = [&](int32_t type, const SmallLevel& sl) {
+    if (sl.nt <= 0) return;
+    Cmd c{};
+    c.type = type; c.klass = RSC_K_PCG; c.off = sl.t0; c.count = sl.nt;
+    c.a = sl.threads; c.b = sl.cpad; c.lds_l = sl.lpad; c.lds_r = sl.rmax;
+    Q->fwd_bwd.push_back(c);
+  };
   // forward sweep, levels ascending
   for (int32_t L = 0; L < S.nlevels; ++L) {
+    if (L < nsmall) {
+      small_cmd(kCmdSweepFwd, small[L]);
+      continue;
+    }
+    if (L == nsmall && !outside.empty()) {
+      const int64_t r0 = (int64_t)Q->rg_rows.size();
+      for (size_t u = 0; u < outside.size(); ++u) {
+        if (u == 0 || outside[u].first != outside[u - 1].first) {
+          Q->rg_rows.push_back(outside[u].first);
+          Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
+        }
+        Q->rg_contrib.push_back(outside[u].second);
+      }
+      cmd(kCmdRowGather, r0, (int64_t)Q->rg_rows.size() - r0, r0);
+    }
     const auto& lev = S.by_level[L];
     // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
     std::vector<ColDotTask> st;
@@ -1861,6 +1960,10 @@ static Error build_solve_plan(Handle& h) {
   Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
   // backward sweep, levels descending
   for (int32_t L = S.nlevels - 1; L >= 0; --L) {
+    if (L < nsmall) {
+      small_cmd(kCmdSweepBwd, small[L]);
+      continue;
+    }
     const auto& lev = S.by_level[L];
     // b0: z over R_j gathered once per supernode into the contiguous buffer zr
     {
@@ -1960,6 +2063,9 @@ static Error build_solve_plan(Handle& h) {
   if ((e = upload(Q->d_rg_rows, Q->rg_rows)).code) return e;
   if ((e = upload(Q->d_rg_ptr, Q->rg_ptr)).code) return e;
   if ((e = upload(Q->d_rg_contrib, Q->rg_contrib)).code) return e;
+  if ((e = upload(Q->d_sweep, Q->sweep)).code) return e;
+  if ((e = upload(Q->d_pull_ptr, Q->pull_ptr)).code) return e;
+  if ((e = upload(Q->d_pull_idx, Q->pull_idx)).code) return e;
   h.splan = std::move(Q);
   return kOk;
 }

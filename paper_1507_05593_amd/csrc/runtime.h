@@ -26,7 +26,7 @@ enum CmdType : int32_t {
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
-  kCmdToF32, kCmdTruncNs, kCmdAssembleLevel,
+  kCmdToF32, kCmdTruncNs, kCmdAssembleLevel, kCmdSweepFwd, kCmdSweepBwd,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -48,6 +48,7 @@ struct Cmd {
   int64_t alt_count = 0;
   bool dyn = false;     // inner or column extents read from device ranks: the profile
                         // recounts the flops from the tasks once the ranks are known
+  int32_t lds_l = 0, lds_r = 0;   // small-supernode sweep launch: LDS doubles for ranks, rows
 };
 
 // Device memory of the library: the caller's allocator when one is set (rsc_set_allocator),
@@ -133,12 +134,18 @@ struct SolvePlan {
   int64_t part_slots = 0;             // 64-entry partial blocks (reused level by level)
   std::vector<int64_t> rg_rows, rg_ptr, rg_contrib;  // row-gather CSR (all levels)
   std::vector<int64_t> gath;          // (begin, count) pairs of z gathers over R_j
+  int32_t small_levels = 0;           // levels 0 .. small_levels-1 run as small-supernode steps
+  std::vector<SweepTask> sweep;       // their supernodes, level by level
+  std::vector<int64_t> pull_ptr, pull_idx;   // per row (n + 1): zr slots of the contributions
+                                             // it pulls inside those levels
   DevArray<GemvTask> d_gemv;
   DevArray<ColDotTask> d_coldot;
   DevArray<RowChunk> d_rchunks;
   DevArray<PartApply> d_papply;
   DevArray<double> d_part;
   DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib, d_gath;
+  DevArray<SweepTask> d_sweep;
+  DevArray<int64_t> d_pull_ptr, d_pull_idx;
   hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
   double bytes = 0;                   // factor bytes read by one apply
   double v_rtol = -1;                 // rtol baked into graph_a

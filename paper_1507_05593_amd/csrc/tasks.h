@@ -159,6 +159,20 @@ struct RowChunk {
   int64_t m, w, s;             // s < 0: no subtraction
   int32_t ld, c, i0, t0, t1, slot;
 };
+// One supernode of a small-supernode sweep level: both sweeps of the level run in one
+// launch each, one workgroup per supernode.  M_j = (L^D_j)^{-T} (upper triangular,
+// M(i, t) = F[m + i + t*ld]); the off-diagonal operand X is L^O_j (r x c) or, compressed,
+// V_j (r x l) with U_j (c x l, ld c) and the rank in the int arena; both column major.
+constexpr int32_t kSweepMaxR = 2048;   // rows R_j of a small-sweep supernode (LDS)
+struct SweepTask {
+  int64_t m, x, u;             // u < 0: explicit L^O_j
+  int64_t first;               // first column of the supernode (permuted index)
+  int64_t rows;                // offset of its rows R_j in the row list and in zr
+  int32_t c, r, ld;
+  int32_t qslot, kmax;         // compressed: int-arena slot of the rank and its bound
+  int32_t pad_;
+};
+
 // Sum of consecutive 64-entry partial blocks s0 .. s0+ns-1 applied to a vector block:
 // mode 0: dst[r] -= sum, mode 1: dst[r] = sum, for r < nrows.
 struct PartApply {

@@ -60,7 +60,8 @@ def use_torch_allocator(on: bool = True) -> None:
 
 
 def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.0, seed=0,
-                 precision="fp64", use_graph=True, retry=True, gemm_tile=0, keep_lo=False) -> Options:
+                 precision="fp64", use_graph=True, retry=True, gemm_tile=0, keep_lo=False,
+                 sweep_small_c=64) -> Options:
     o = Options()
     lib().rsc_default_options(C.byref(o))
     o.leaf_max, o.tau_O, o.oversample, o.power_iters = leaf_max, tau_O, oversample, power_iters
@@ -69,6 +70,7 @@ def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.
     o.use_graph, o.retry = int(bool(use_graph)), int(bool(retry))
     o.gemm_tile = int(gemm_tile)
     o.keep_lo = int(bool(keep_lo))
+    o.sweep_small_c = int(sweep_small_c)
     return o
 
 

@@ -475,6 +475,57 @@ def test_mixed_forms_sweeps_apply_the_fp32_rounded_factor():
         assert rel <= 1e-6
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 0.0), ("fp64", 1e-2), ("bf16", 1e-2)])
+def test_small_level_sweeps_equal_per_operation_sweeps(precision, tol):
+    # The lowest elimination-tree levels run each sweep step as one launch (one workgroup
+    # per supernode, descendants' contributions pulled by the rows); the per-operation
+    # launches compute the same products in another summation order.  Bounds on this grid
+    # (level column maxima 63, 25, 40, 56, 96, 126, 216): none, four levels (64 threads per
+    # supernode), five (the fifth with 256), and every level, the root's included.
+    print("case small sweeps", precision, tol, flush=True)
+    p = grid_problem((18, 17, 16), sigma=1.5, seed=8)
+    sym = symbolic(p.n, p.rowptr, p.colind, 64)
+    rng = np.random.default_rng(4)
+    r = _vec(rng.standard_normal(p.n))
+    nlev = max(sym.level) + 1
+    b = _vec(p.b)
+    zs = {}
+    for bound in (0, 64, 100, 1024):
+        sol = _sol(p, seed=3, precision=precision, retry=False, sweep_small_c=bound)
+        sol.factor(_vals(p), tol)
+        zs[bound] = sol.apply(r).cpu().numpy()
+        # launches per preconditioner apply, from a profiled PCG run
+        sol.profile(True)
+        _, res = sol.pcg(b, rtol=1e-6)
+        prof = sol.kernel_profile()
+        sol.profile(False)
+        nfwd, nbwd = prof["sweep_fwd"]["launches"], prof["sweep_bwd"]["launches"]
+        iters = res["iters"]
+        small = 0
+        while small < nlev and all(sym.c(j) <= bound and sym.r(j) <= 2048
+                                   for j in range(sym.M) if sym.level[j] == small):
+            small += 1
+        assert small == {0: 0, 64: 4, 100: 5, 1024: nlev}[bound], (bound, small)
+        print(bound, "small levels", small, "of", nlev, flush=True)
+        # one apply before the loop and one per iteration that did not stop it
+        assert nfwd == nbwd, (nfwd, nbwd)
+        if small == 0:
+            assert nfwd == 0
+        else:
+            assert nfwd % small == 0 and nfwd // small in (iters, iters + 1), (bound, nfwd, small, iters)
+    ref = zs[0]
+    for bound in (64, 100, 1024):
+        rel = np.linalg.norm(zs[bound] - ref) / np.linalg.norm(ref)
+        print(bound, "vs per-operation sweeps", rel, flush=True)
+        assert rel <= 1e-13, (bound, rel)
+    # and the default against the oracle
+    if precision == "fp64":
+        F = o_factor(sym, p.n, p.rowptr, p.colind, p.values, tol, Options(seed=3, implicit=tol > 0))
+        zo = o_apply(F, r.cpu().numpy())
+        bound = 1e-11 if tol == 0 else 1e-6
+        assert np.linalg.norm(zs[100] - zo) <= bound * np.linalg.norm(zo)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_projector_iteration_in_lds_ranks_and_pcg(precision):
     # Levels whose supernodes all have small sample counts run the projector iteration in

@@ -102,9 +102,10 @@ def test_pattern_and_argument_errors():
     with pytest.raises(RSCError) as e:
         RSCSolver(p.n, rp2, ci2)
     assert e.value.code == RSC_ERR_PATTERN
-    with pytest.raises(RSCError) as e:
-        RSCSolver(p.n, p.rowptr, p.colind, leaf_max=0)
-    assert e.value.code == RSC_ERR_INVALID_ARG
+    for bad_opt in (dict(leaf_max=0), dict(sweep_small_c=-1), dict(sweep_small_c=1025), dict(gemm_tile=32)):
+        with pytest.raises(RSCError) as e:
+            RSCSolver(p.n, p.rowptr, p.colind, **bad_opt)
+        assert e.value.code == RSC_ERR_INVALID_ARG, bad_opt
     h = C.c_void_p()
     assert lib().rsc_analyze(-1, None, None, None, C.byref(h)) == RSC_ERR_INVALID_ARG
 
