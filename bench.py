@@ -398,7 +398,7 @@ _MODE_NAMES = {0: "f64", 1: "f32", 2: "bf16x3", 3: "bf16"}
 def profile_name(rocprof_name):
     """Kernel name of the library's profile for a rocprofv3 kernel name (or None)."""
     import re
-    m = re.search(r"k_gemm_staged<(\d), (\d+)>", rocprof_name)
+    m = re.search(r"k_gemm_staged<(\d), (\d+)", rocprof_name)
     if m:
         return f"gemm_staged{'128' if m.group(2) == '128' else ''}_{_MODE_NAMES[int(m.group(1))]}"
     m = re.search(r"k_update_waves<(\d)>", rocprof_name)

@@ -91,9 +91,12 @@ hipError_t apply_scratch(double** out);
 
 namespace rsc {
 // LDS-staged MFMA kernels; mode 0 = FP64, 1 = FP32 operands, 2 = BF16 hi/lo split, 3 = BF16
-// tile: output tile edge, 64 or 128 (tasks must have been cut to that edge)
+// tile: output tile edge, 64 or 128 (tasks must have been cut to that edge).  ptasks (FP64,
+// 64 tiles only): the launch holds tasks with potrf1 > 0, whose workgroups then factor
+// their tile as the diagonal block described by ptasks[potrf1 - 1] (status as for POTRF)
 void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
-                        const int32_t* ilim, double* part, hipStream_t s);
+                        const int32_t* ilim, double* part, const PotrfTask* ptasks, int32_t* status,
+                        hipStream_t s);
 // Adds the K-slice partial tiles of split products and stores C (one workgroup per tile).
 void launch_gemm_reduce(int tile, const GemmTask* t, int n, double* arena, const int32_t* ilim,
                         const double* part, hipStream_t s);

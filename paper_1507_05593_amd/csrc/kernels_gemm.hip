@@ -18,11 +18,11 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "potrf_block.h"
 #include "tasks.h"
 
 namespace rsc {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
@@ -224,14 +224,22 @@ constexpr size_t kGemmSmem = sizeof(Stage<MODE, TM>) > 64 * kSlabPitch<TM> * siz
                                  ? sizeof(Stage<MODE, TM>)
                                  : 64 * kSlabPitch<TM> * sizeof(typename AccElem<MODE>::T);
 
-template <int MODE, int TM>
-__global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1) void k_gemm_staged(const GemmTask* __restrict__ tasks,
+// POST (FP64, 64 tiles): a task with potrf1 > 0 holds a panel's next diagonal block; its
+// workgroup factors the block (potrf_block) once the tile is stored, so the POTRF of the
+// next panel step runs inside this launch instead of after it.
+template <int MODE, int TM, bool POST>
+constexpr size_t kStagedSmem = (POST && kPotrfSmem > kGemmSmem<MODE, TM>) ? kPotrfSmem : kGemmSmem<MODE, TM>;
+
+template <int MODE, int TM, bool POST>
+__global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? (POST ? 2 : 3) : 1) void k_gemm_staged(const GemmTask* __restrict__ tasks,
                                                                double* __restrict__ arena,
                                                                const int32_t* __restrict__ ilim,
-                                                               double* __restrict__ part) {
+                                                               double* __restrict__ part,
+                                                               const PotrfTask* __restrict__ ptasks,
+                                                               int32_t* __restrict__ status) {
   using Ly = Layout<TM>;
   using AE = typename AccElem<MODE>::T;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kGemmSmem<MODE, TM>];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kStagedSmem<MODE, TM, POST>];
   Stage<MODE, TM>& st = *reinterpret_cast<Stage<MODE, TM>*>(smem);
   const GemmTask T = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -307,6 +315,13 @@ __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? 3 : 1)
           else C[o] = v + T.beta * ((T.d >= 0) ? arena[T.d + od] : C[od]);
         }
       }
+    }
+  }
+  if constexpr (POST) {
+    if (T.potrf1 > 0) {
+      __syncthreads();                     // the tile's stores, then its factorization
+      double* blk = reinterpret_cast<double*>(smem);
+      potrf_block(ptasks[T.potrf1 - 1], arena, status, blk, blk + 64 * kPitch);
     }
   }
 }
@@ -746,18 +761,24 @@ __global__ __launch_bounds__(256) void k_update_waves(const UpdTile* __restrict_
 template <int TM>
 static void launch_gemm_tm(int mode, const GemmTask* t, int n, double* arena, const int32_t* ilim,
                            double* part, hipStream_t s) {
+  const PotrfTask* np = nullptr;
+  int32_t* ns = nullptr;
   switch (mode) {
-    case sF64: hipLaunchKernelGGL((k_gemm_staged<sF64, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
-    case sF32: hipLaunchKernelGGL((k_gemm_staged<sF32, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
-    case sBF16x3: hipLaunchKernelGGL((k_gemm_staged<sBF16x3, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
-    default: hipLaunchKernelGGL((k_gemm_staged<sBF16, TM>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part); break;
+    case sF64: hipLaunchKernelGGL((k_gemm_staged<sF64, TM, false>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part, np, ns); break;
+    case sF32: hipLaunchKernelGGL((k_gemm_staged<sF32, TM, false>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part, np, ns); break;
+    case sBF16x3: hipLaunchKernelGGL((k_gemm_staged<sBF16x3, TM, false>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part, np, ns); break;
+    default: hipLaunchKernelGGL((k_gemm_staged<sBF16, TM, false>), dim3(n), dim3(Layout<TM>::NT), 0, s, t, arena, ilim, part, np, ns); break;
   }
 }
 
 void launch_gemm_staged(int mode, int tile, const GemmTask* t, int n, double* arena,
-                        const int32_t* ilim, double* part, hipStream_t s) {
+                        const int32_t* ilim, double* part, const PotrfTask* ptasks, int32_t* status,
+                        hipStream_t s) {
   if (n <= 0) return;
-  if (tile == 128) launch_gemm_tm<128>(mode, t, n, arena, ilim, part, s);
+  if (ptasks && mode == sF64 && tile == 64)
+    hipLaunchKernelGGL((k_gemm_staged<sF64, 64, true>), dim3(n), dim3(Layout<64>::NT), 0, s, t, arena, ilim,
+                       part, ptasks, status);
+  else if (tile == 128) launch_gemm_tm<128>(mode, t, n, arena, ilim, part, s);
   else launch_gemm_tm<64>(mode, t, n, arena, ilim, part, s);
 }
 

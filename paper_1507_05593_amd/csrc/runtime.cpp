@@ -482,6 +482,7 @@ struct Builder {
   int32_t lp_sample = 0;
   int32_t lp_eig = 0;      // products of the spectral truncation (projector iterations)
   int32_t lp_tri = 0;      // the rows of a panel that form the inverse of its diagonal block
+  bool next_post = false;  // the next cmd() is a product launch carrying diagonal blocks
   int32_t ctx = -1;        // >= 0: profiling class of every launch emitted (a compression stage)
   std::vector<int64_t> xc_off;   // compact copy of supernode j's update operand (doubles), or -1
   std::vector<int32_t> xc_kp;    // its row length: kept columns rounded up to 32
@@ -508,6 +509,8 @@ struct Builder {
 
   void cmd(int32_t type, int32_t klass, int64_t off, int64_t count, double flops, int64_t a = 0,
            int64_t b = 0, double v = 0) {
+    const bool post = next_post;          // tasks with next diagonal blocks: no split, no 128 copy
+    next_post = false;
     if (count <= 0) return;
     int64_t alt_off = -1, alt_count = 0;
     // split K: a 64-tile product with fewer tiles than two per compute unit and a long
@@ -530,7 +533,7 @@ struct Builder {
         // would leave half of every 128 tile idle; launches under 16 tiles would leave
         // most of the chip idle with a quarter as many workgroups
         const bool narrow = 2 * last_col > count;
-        if (h.opt.gemm_tile != 128 && count < 512)
+        if (!post && h.opt.gemm_tile != 128 && count < 512)
           kz = (int32_t)std::min<int64_t>({8, (2048 + count - 1) / count, std::max(1, kmax / 256)});
         if (h.opt.gemm_tile == 128) {
           count = retile128(P.gemm, off);
@@ -554,7 +557,7 @@ struct Builder {
           P.gemm.insert(P.gemm.end(), sl.begin(), sl.end());
           count *= kz;
           P.split_size = std::max(P.split_size, count * 4096);
-        } else if (h.opt.gemm_tile == 0 && !narrow && count >= 16) {
+        } else if (!post && h.opt.gemm_tile == 0 && !narrow && count >= 16) {
           alt_off = (int64_t)P.gemm.size();
           P.gemm.insert(P.gemm.end(), P.gemm.begin() + off, P.gemm.begin() + off + count);
           alt_count = retile128(P.gemm, alt_off);
@@ -565,6 +568,7 @@ struct Builder {
     c.type = type; c.klass = ctx >= 0 ? ctx : klass; c.off = off; c.count = count; c.a = a; c.b = b; c.v = v;
     c.flops = flops;
     c.alt_off = alt_off; c.alt_count = alt_count;
+    c.post = post;
     if (type == kCmdGemm)
       for (int64_t i = off; i < off + count && !c.dyn; ++i) c.dyn = (P.gemm[i].nlim >= 0 || P.gemm[i].klim >= 0);
     P.cmds.push_back(c);
@@ -621,21 +625,34 @@ struct Builder {
   // Blocked right-looking factorisation of tall panels [diag n x n; m_below rows;
   // optional identity rows], 64 columns per step: diagonal Cholesky + inverse, the
   // rows below times the inverse (in place), then the trailing update.
+  static PotrfTask potrf_task(const PanelDesc& p, int32_t d0) {
+    PotrfTask t{};
+    t.panel = p.off; t.inv = p.dinv + (int64_t)(d0 / kTile) * 4096; t.ld = p.ld;
+    t.nb = std::min(kTile, p.n - d0); t.d0 = d0; t.sn = p.sn; t.mode = p.mode;
+    t.scale_off = p.scale_off;
+    return t;
+  }
+
+  // Inside an outer block the next step's diagonal block is last updated by one tile of
+  // this step's in-block trailing launch; that tile's workgroup factors it right after
+  // storing it (GemmTask::potrf1), so only the first step of each outer block has a POTRF
+  // launch of its own.  (The wide outer launches keep the plain kernel: the fused one
+  // holds twice the LDS, which would cost them a third of their workgroups per CU.)
   void panel_steps(const std::vector<PanelDesc>& pan) {
     int32_t maxn = 0;
     for (auto& p : pan) maxn = std::max(maxn, p.n);
+    const bool fuse = h.opt.gemm_tile != 128;   // (a fixed 128 edge merges the tiles)
+    std::vector<char> fused(pan.size(), 0);     // panel's POTRF of this step already placed
     for (int32_t d0 = 0; d0 < maxn; d0 += kTile) {
       const int64_t p0 = (int64_t)P.potrf.size();
       double fl = 0;
-      for (auto& p : pan) {
-        if (p.n <= d0) continue;
-        PotrfTask t{};
-        t.panel = p.off; t.inv = p.dinv + (int64_t)(d0 / kTile) * 4096; t.ld = p.ld;
-        t.nb = std::min(kTile, p.n - d0); t.d0 = d0; t.sn = p.sn; t.mode = p.mode;
-        t.scale_off = p.scale_off;
-        P.potrf.push_back(t);
-        fl += std::pow((double)t.nb, 3) / 3.0;
+      for (size_t pi = 0; pi < pan.size(); ++pi) {
+        const PanelDesc& p = pan[pi];
+        if (p.n <= d0 || fused[pi]) continue;
+        P.potrf.push_back(potrf_task(p, d0));
+        fl += std::pow((double)P.potrf.back().nb, 3) / 3.0;
       }
+      std::fill(fused.begin(), fused.end(), 0);
       cmd(kCmdPotrf, RSC_K_POTRF, p0, (int64_t)P.potrf.size() - p0, fl);
       // rows below the diagonal block times its inverse, then the trailing update in two
       // levels: each 64-column step updates the columns of its kOuter-wide block, and the
@@ -647,8 +664,10 @@ struct Builder {
         if (phase == 2 && d0 + kTile != dend) continue;
         std::vector<GemmTask> hi_t, lo_t, tl_t;
         double fh = 0, flo = 0, ftl = 0;
-        for (auto& p : pan) {
+        for (size_t pi = 0; pi < pan.size(); ++pi) {
+          const PanelDesc& p = pan[pi];
           if (p.n <= d0) continue;
+          const size_t h0 = hi_t.size();
           const int32_t nb = std::min(kTile, p.n - d0);
           if (phase >= 1 && p.n <= d0 + nb) continue;
           if (phase == 1 && d0 + nb >= dend) continue;      // no columns left in the block
@@ -676,10 +695,24 @@ struct Builder {
             else if (sgm == 2 && p.tail_lp && lp_tri) ftl += tiles(ts, lo, jb, lower, &tl_t);
             else fh += tiles(ts, lo, jb, lower, &hi_t);
           }
+          const int32_t nd = d0 + kTile;   // the next step's diagonal block
+          if (fuse && phase == 1 && p.n > nd && nd < dend)
+            for (size_t q = h0; q < hi_t.size(); ++q)
+              if (hi_t[q].i0 == nd && hi_t[q].j0 == nd) {
+                hi_t[q].potrf1 = (int32_t)P.potrf.size() + 1;
+                P.potrf.push_back(potrf_task(p, nd));
+                fh += std::pow((double)P.potrf.back().nb, 3) / 3.0;
+                fused[pi] = 1;
+                break;
+              }
         }
+        // the diagonal blocks' workgroups first: they have the factorization still to do
+        std::stable_partition(hi_t.begin(), hi_t.end(), [](const GemmTask& t) { return t.potrf1 > 0; });
+        const bool post = !hi_t.empty() && hi_t.front().potrf1 > 0;
         const int klass = phase == 0 ? RSC_K_TRSM : RSC_K_GEMM;
         int64_t g0 = (int64_t)P.gemm.size();
         P.gemm.insert(P.gemm.end(), hi_t.begin(), hi_t.end());
+        next_post = post;
         cmd(kCmdGemm, klass, g0, (int64_t)hi_t.size(), fh, 0);
         g0 = (int64_t)P.gemm.size();
         P.gemm.insert(P.gemm.end(), lo_t.begin(), lo_t.end());
@@ -1286,13 +1319,13 @@ static Error tune_tiles(Handle& h, FactorPlan& P, hipStream_t caller) {
   for (Cmd& c : P.cmds) {
     if (c.alt_off < 0) continue;
     const int mode = (int)c.a;
-    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, nullptr, s);
+    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, nullptr, nullptr, nullptr, s);
     HIPCHK(hipEventRecord(ev[0], s));
-    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, nullptr, s);
+    launch_gemm_staged(mode, 64, P.d_gemm.p + c.off, (int)c.count, A, I, nullptr, nullptr, nullptr, s);
     HIPCHK(hipEventRecord(ev[1], s));
-    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, nullptr, s);
+    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, nullptr, nullptr, nullptr, s);
     HIPCHK(hipEventRecord(ev[2], s));
-    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, nullptr, s);
+    launch_gemm_staged(mode, 128, P.d_gemm.p + c.alt_off, (int)c.alt_count, A, I, nullptr, nullptr, nullptr, s);
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipEventSynchronize(ev[3]));
     float t64 = 0, t128 = 0;
@@ -1532,7 +1565,10 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
                           P->precision != RSC_FP64 ? f32_base(h) : nullptr, s);
       break;
     case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
-    case kCmdGemm: launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
+    case kCmdGemm:
+      launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p,
+                         c.post ? P->d_potrf.p : nullptr, I + h.i_status, s);
+      break;
     case kCmdGemmReduce: launch_gemm_reduce((int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p, s); break;
     case kCmdPhilox: launch_philox(P->d_philox.p + c.off, (int)c.count, c.a, A, c.b != 0, s); break;
     case kCmdGramScale:

@@ -49,6 +49,7 @@ struct Cmd {
   bool dyn = false;     // inner or column extents read from device ranks: the profile
                         // recounts the flops from the tasks once the ranks are known
   int32_t lds_l = 0, lds_r = 0;   // small-supernode sweep launch: LDS doubles for ranks, rows
+  bool post = false;    // product launch whose tasks include next diagonal blocks to factor
 };
 
 // Device memory of the library: the caller's allocator when one is set (rsc_set_allocator),

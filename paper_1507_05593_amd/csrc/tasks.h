@@ -26,7 +26,8 @@ struct GemmTask {
                                // written with its transpose (diagonal tiles: lower half mirrored)
   int32_t kz, ks;              // kz > 1: K cut into kz chunk-aligned slices, this task computes
                                // slice ks into the partial tile at `part`; a reduce launch adds them
-  int32_t pad_;
+  int32_t potrf1;              // > 0: the tile is a panel's next diagonal block, which this
+                               // workgroup then factors (POTRF task potrf1 - 1)
   int64_t part;                // scratch offset (doubles) of the partial tile, column major TM x TM
   double alpha, beta;
 };
