@@ -221,6 +221,14 @@ __device__ inline void potrf_block(const PotrfTask& T, double* __restrict__ aren
     const int r = idx & 63, c = idx >> 6;
     inv[r + 64 * c] = W[r * kPitch + c];
   }
+  if (T.mrow > 0) {
+    // a one-block panel: its identity rows become M = W^T at once (no solve launch)
+    double* M = P + T.mrow;
+    for (int idx = tid; idx < 4096; idx += 256) {
+      const int r = idx & 63, c = idx >> 6;
+      if (r < nb && c < nb) M[r + (int64_t)c * T.ld] = W[c * kPitch + r];
+    }
+  }
 }
 
 // LDS bytes of potrf_block's two blocks

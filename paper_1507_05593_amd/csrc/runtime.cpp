@@ -630,8 +630,11 @@ struct Builder {
     t.panel = p.off; t.inv = p.dinv + (int64_t)(d0 / kTile) * 4096; t.ld = p.ld;
     t.nb = std::min(kTile, p.n - d0); t.d0 = d0; t.sn = p.sn; t.mode = p.mode;
     t.scale_off = p.scale_off;
+    t.mrow = one_block(p) ? p.n : 0;
     return t;
   }
+  // a panel of one 64-column block over identity rows only: POTRF stores M itself
+  static bool one_block(const PanelDesc& p) { return p.ident && p.m_below == 0 && p.n <= kTile; }
 
   // Inside an outer block the next step's diagonal block is last updated by one tile of
   // this step's in-block trailing launch; that tile's workgroup factors it right after
@@ -669,6 +672,7 @@ struct Builder {
           if (p.n <= d0) continue;
           const size_t h0 = hi_t.size();
           const int32_t nb = std::min(kTile, p.n - d0);
+          if (phase == 0 && one_block(p)) continue;
           if (phase >= 1 && p.n <= d0 + nb) continue;
           if (phase == 1 && d0 + nb >= dend) continue;      // no columns left in the block
           const int32_t R0 = (phase == 2) ? dend : d0 + nb;

@@ -75,6 +75,8 @@ struct PotrfTask {
   int32_t sn;                  // supernode for the status word
   int32_t mode;                // 0: fail on a non-positive pivot; 1 / 2: drop dependent columns
                                // (pivot <= 1e-14 / 1e-8 times the scale)
+  int32_t mrow;                // > 0: the panel is this one block over identity rows starting at
+                               // row mrow, which receive M = L^{-T} (the inverse transposed)
   int64_t scale_off;           // modes 1, 2: arena offset of the scale (largest Gram diagonal)
 };
 
