@@ -16,7 +16,7 @@ void launch_assemble(const double* values, const int64_t* slot, int64_t nnz, dou
 void launch_assemble_pairs(const double* values, const int64_t* idx, const int64_t* slot, int64_t n,
                            double* arena, hipStream_t s);
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s);
-void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s);
+void launch_potrf_f64(const PotrfTask* t, int n, int nbmax, double* arena, int32_t* status, hipStream_t s);
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, bool f32,
                    hipStream_t s);
 // Largest Gram diagonal (the drop scale of the Cholesky step); mm[p] > 0: first add the

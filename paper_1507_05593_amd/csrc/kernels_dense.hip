@@ -66,12 +66,15 @@ __global__ void k_scatter_const(const int64_t* __restrict__ slot, int64_t n, dou
 
 // ---------------------------------------------------------------- diagonal block Cholesky
 
+// NB = 32 for launches whose blocks all have at most 32 columns (a quarter of the LDS,
+// so several times as many workgroups per compute unit), else 64.
+template <int NB>
 __global__ __launch_bounds__(256) void k_potrf_f64(const PotrfTask* __restrict__ tasks,
                                                    double* __restrict__ arena,
                                                    int32_t* __restrict__ status) {
-  __shared__ double A[64 * kPitch];
-  __shared__ double W[64 * kPitch];
-  potrf_block(tasks[blockIdx.x], arena, status, A, W);
+  __shared__ double A[NB * (NB + 1)];
+  __shared__ double W[NB * (NB + 1)];
+  potrf_block<NB>(tasks[blockIdx.x], arena, status, A, W);
 }
 
 // ---------------------------------------------------------------- Gaussian sample
@@ -558,8 +561,10 @@ void launch_assemble_pairs(const double* values, const int64_t* idx, const int64
 void launch_scatter_const(const int64_t* slot, int64_t n, double v, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_scatter_const, dim3(grid_for(n)), dim3(256), 0, s, slot, n, v, arena);
 }
-void launch_potrf_f64(const PotrfTask* t, int n, double* arena, int32_t* status, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_potrf_f64, dim3(n), dim3(256), 0, s, t, arena, status);
+void launch_potrf_f64(const PotrfTask* t, int n, int nbmax, double* arena, int32_t* status, hipStream_t s) {
+  if (n <= 0) return;
+  if (nbmax <= 32) hipLaunchKernelGGL(k_potrf_f64<32>, dim3(n), dim3(256), 0, s, t, arena, status);
+  else hipLaunchKernelGGL(k_potrf_f64<64>, dim3(n), dim3(256), 0, s, t, arena, status);
 }
 void launch_philox(const PhiloxTask* t, int n, int64_t max_work, double* arena, bool f32,
                    hipStream_t s) {

@@ -321,7 +321,7 @@ __global__ __launch_bounds__(Layout<TM>::NT, (TM == 64 && MODE == sF64) ? (POST 
     if (T.potrf1 > 0) {
       __syncthreads();                     // the tile's stores, then its factorization
       double* blk = reinterpret_cast<double*>(smem);
-      potrf_block(ptasks[T.potrf1 - 1], arena, status, blk, blk + 64 * kPitch);
+      potrf_block<64>(ptasks[T.potrf1 - 1], arena, status, blk, blk + 64 * kPitch);
     }
   }
 }

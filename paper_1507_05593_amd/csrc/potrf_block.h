@@ -101,8 +101,9 @@ __device__ __forceinline__ void diag_step(double (&v)[4], double (&wv)[4], int j
   if constexpr (C < 15) diag_step<C + 1>(v, wv, j, g, kk, nb, mode, dscale, bad);
 }
 
-constexpr int kPitch = 65;
+constexpr int kPitch = 65;   // LDS row pitch of a 64-edge block (NB + 1 in general)
 
+template <int PITCH>
 __device__ __forceinline__ v4d mma16(v4d acc, const double* X, int xr, int xc, const double* Y, int yr,
                                      int yc, bool ytrans, int lane) {
   // acc += X(xr.., xc..) Y^T over 16 k: Y element (col j, k) read at Y(yr + j, yc + k), or at
@@ -110,17 +111,20 @@ __device__ __forceinline__ v4d mma16(v4d acc, const double* X, int xr, int xc, c
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < 16; ks += 4) {
-    const double a = X[(xr + li) * kPitch + xc + ks + lk];
-    const double b = ytrans ? Y[(yr + ks + lk) * kPitch + yc + li] : Y[(yr + li) * kPitch + yc + ks + lk];
+    const double a = X[(xr + li) * PITCH + xc + ks + lk];
+    const double b = ytrans ? Y[(yr + ks + lk) * PITCH + yc + li] : Y[(yr + li) * PITCH + yc + ks + lk];
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
   return acc;
 }
 
-// One diagonal block for a 256-thread workgroup; A and W are its LDS blocks (64 x kPitch
-// doubles each; A(r, c) at r * kPitch + c, the inverse W in the same layout).
+// One diagonal block (nb <= NB, NB = 32 or 64) for a 256-thread workgroup; A and W are its
+// LDS blocks (NB x (NB + 1) doubles each; A(r, c) at r * (NB + 1) + c, the inverse W in
+// the same layout).  The inverse is stored as a 64 x 64 block whatever NB.
+template <int NB>
 __device__ inline void potrf_block(const PotrfTask& T, double* __restrict__ arena, int32_t* __restrict__ status,
-                            double* __restrict__ A, double* __restrict__ W) {
+                                   double* __restrict__ A, double* __restrict__ W) {
+  constexpr int PI = NB + 1, NL = NB * NB / 256;      // pitch, loads per thread
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nb = T.nb;
@@ -128,18 +132,18 @@ __device__ inline void potrf_block(const PotrfTask& T, double* __restrict__ aren
   double* P = arena + T.panel;
   const int64_t base = T.d0 + (int64_t)T.d0 * T.ld;
   {
-    // all sixteen loads in flight together (addresses clamped into the block), then LDS
-    double t[16];
+    // all loads in flight together (addresses clamped into the block), then LDS
+    double t[NL];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
+    for (int u = 0; u < NL; ++u) {
+      const int idx = tid + 256 * u, r = idx % NB, c = idx / NB;
       t[u] = P[base + min(r, nb - 1) + (int64_t)min(c, nb - 1) * T.ld];
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * u, r = idx & 63, c = idx >> 6;
-      A[r * kPitch + c] = (r < nb && c < nb && r >= c) ? t[u] : ((r == c) ? 1.0 : 0.0);
-      W[r * kPitch + c] = (r == c && r >= nbb16) ? 1.0 : 0.0;   // blocks past nb: identity
+    for (int u = 0; u < NL; ++u) {
+      const int idx = tid + 256 * u, r = idx % NB, c = idx / NB;
+      A[r * PI + c] = (r < nb && c < nb && r >= c) ? t[u] : ((r == c) ? 1.0 : 0.0);
+      W[r * PI + c] = (r == c && r >= nbb16) ? 1.0 : 0.0;   // blocks past nb: identity
     }
   }
   const double dscale = (T.mode >= 1) ? arena[T.scale_off] * (T.mode == 2 ? 1e-8 : 1e-14) : 0.0;
@@ -155,15 +159,15 @@ __device__ inline void potrf_block(const PotrfTask& T, double* __restrict__ aren
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * q + g;
-        v[q] = A[(kk + (i > j ? i : j)) * kPitch + kk + (i > j ? j : i)];
+        v[q] = A[(kk + (i > j ? i : j)) * PI + kk + (i > j ? j : i)];
         wv[q] = (i == j) ? 1.0 : 0.0;
       }
       diag_step<0>(v, wv, j, g, kk, nb, T.mode, dscale, bad);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * q + g;
-        if (i >= j) A[(kk + i) * kPitch + kk + j] = v[q];
-        W[(kk + i) * kPitch + kk + j] = wv[q];
+        if (i >= j) A[(kk + i) * PI + kk + j] = v[q];
+        W[(kk + i) * PI + kk + j] = wv[q];
       }
     }
     __syncthreads();
@@ -173,22 +177,22 @@ __device__ inline void potrf_block(const PotrfTask& T, double* __restrict__ aren
       const int rb = kb + 1 + w;
       if (rb < nbk) {
         v4d acc = {0, 0, 0, 0};
-        acc = mma16(acc, A, 16 * rb, kk, W, kk, kk, false, lane);
+        acc = mma16<PI>(acc, A, 16 * rb, kk, W, kk, kk, false, lane);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) A[(16 * rb + lk + 4 * e) * kPitch + kk + li] = acc[e];
+        for (int e = 0; e < 4; ++e) A[(16 * rb + lk + 4 * e) * PI + kk + li] = acc[e];
       }
     }
     __syncthreads();
-    // trailing lower blocks (ib, jb), kb < jb <= ib < 4
+    // trailing lower blocks (ib, jb), kb < jb <= ib < nbk
     {
       int t = 0;
       for (int ib = kb + 1; ib < nbk; ++ib)
         for (int jb = kb + 1; jb <= ib; ++jb, ++t) {
           if ((t & 3) != w) continue;
           v4d acc = {0, 0, 0, 0};
-          acc = mma16(acc, A, 16 * ib, kk, A, 16 * jb, kk, false, lane);
+          acc = mma16<PI>(acc, A, 16 * ib, kk, A, 16 * jb, kk, false, lane);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) A[(16 * ib + lk + 4 * e) * kPitch + 16 * jb + li] -= acc[e];
+          for (int e = 0; e < 4; ++e) A[(16 * ib + lk + 4 * e) * PI + 16 * jb + li] -= acc[e];
         }
     }
     __syncthreads();
@@ -198,40 +202,40 @@ __device__ inline void potrf_block(const PotrfTask& T, double* __restrict__ aren
     if (w < ib) {
       const int jb = w;
       v4d t = {0, 0, 0, 0};
-      for (int mb = jb; mb < ib; ++mb) t = mma16(t, A, 16 * ib, 16 * mb, W, 16 * mb, 16 * jb, true, lane);
+      for (int mb = jb; mb < ib; ++mb) t = mma16<PI>(t, A, 16 * ib, 16 * mb, W, 16 * mb, 16 * jb, true, lane);
       // W_ij = -D_i^{-1} T: the B operand (column li, k = 4e + lk) is t[e] of this lane
       v4d acc = {0, 0, 0, 0};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const double a = W[(16 * ib + li) * kPitch + 16 * ib + 4 * e + lk];
+        const double a = W[(16 * ib + li) * PI + 16 * ib + 4 * e + lk];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, t[e], acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) W[(16 * ib + lk + 4 * e) * kPitch + 16 * jb + li] = -acc[e];
+      for (int e = 0; e < 4; ++e) W[(16 * ib + lk + 4 * e) * PI + 16 * jb + li] = -acc[e];
     }
     __syncthreads();
   }
   if (bad && tid == 0) atomicMin(&status[0], T.sn);
-  for (int idx = tid; idx < 4096; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = A[r * kPitch + c];
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx % NB, c = idx / NB;
+    if (r < nb && c <= r) P[base + r + (int64_t)c * T.ld] = A[r * PI + c];
   }
   double* inv = arena + T.inv;
-  for (int idx = tid; idx < 4096; idx += 256) {
-    const int r = idx & 63, c = idx >> 6;
-    inv[r + 64 * c] = W[r * kPitch + c];
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx % NB, c = idx / NB;
+    inv[r + 64 * c] = W[r * PI + c];
   }
   if (T.mrow > 0) {
     // a one-block panel: its identity rows become M = W^T at once (no solve launch)
     double* M = P + T.mrow;
-    for (int idx = tid; idx < 4096; idx += 256) {
-      const int r = idx & 63, c = idx >> 6;
-      if (r < nb && c < nb) M[r + (int64_t)c * T.ld] = W[c * kPitch + r];
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+      const int r = idx % NB, c = idx / NB;
+      if (r < nb && c < nb) M[r + (int64_t)c * T.ld] = W[c * PI + r];
     }
   }
 }
 
-// LDS bytes of potrf_block's two blocks
+// LDS bytes of potrf_block<64>'s two blocks
 constexpr size_t kPotrfSmem = 2 * 64 * kPitch * sizeof(double);
 
 }  // namespace rsc

@@ -647,16 +647,21 @@ struct Builder {
     const bool fuse = h.opt.gemm_tile != 128;   // (a fixed 128 edge merges the tiles)
     std::vector<char> fused(pan.size(), 0);     // panel's POTRF of this step already placed
     for (int32_t d0 = 0; d0 < maxn; d0 += kTile) {
-      const int64_t p0 = (int64_t)P.potrf.size();
-      double fl = 0;
-      for (size_t pi = 0; pi < pan.size(); ++pi) {
-        const PanelDesc& p = pan[pi];
-        if (p.n <= d0 || fused[pi]) continue;
-        P.potrf.push_back(potrf_task(p, d0));
-        fl += std::pow((double)P.potrf.back().nb, 3) / 3.0;
+      // blocks of at most 32 columns in a launch of the 32-edge kernel, the rest after
+      for (int edge : {32, 64}) {
+        const int64_t q0 = (int64_t)P.potrf.size();
+        double fl = 0;
+        for (size_t pi = 0; pi < pan.size(); ++pi) {
+          const PanelDesc& p = pan[pi];
+          if (p.n <= d0 || fused[pi]) continue;
+          const int32_t nb = std::min(kTile, p.n - d0);
+          if ((nb <= 32) != (edge == 32)) continue;
+          P.potrf.push_back(potrf_task(p, d0));
+          fl += std::pow((double)nb, 3) / 3.0;
+        }
+        cmd(kCmdPotrf, RSC_K_POTRF, q0, (int64_t)P.potrf.size() - q0, fl, edge);
       }
       std::fill(fused.begin(), fused.end(), 0);
-      cmd(kCmdPotrf, RSC_K_POTRF, p0, (int64_t)P.potrf.size() - p0, fl);
       // rows below the diagonal block times its inverse, then the trailing update in two
       // levels: each 64-column step updates the columns of its kOuter-wide block, and the
       // block's last step adds the whole block (K = kOuter) to the columns right of it,
@@ -1568,7 +1573,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
       launch_compact_rows((int)c.a, P->d_compact.p + c.off, (int)c.count, A, I, P->d_xc.p,
                           P->precision != RSC_FP64 ? f32_base(h) : nullptr, s);
       break;
-    case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, A, I + h.i_status, s); break;
+    case kCmdPotrf: launch_potrf_f64(P->d_potrf.p + c.off, (int)c.count, (int)c.a, A, I + h.i_status, s); break;
     case kCmdGemm:
       launch_gemm_staged((int)c.a, (int)c.b, P->d_gemm.p + c.off, (int)c.count, A, I, P->d_split.p,
                          c.post ? P->d_potrf.p : nullptr, I + h.i_status, s);
