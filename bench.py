@@ -58,9 +58,12 @@ KERNEL_PREC = {"gemm_staged_f64": "f64", "gemm_staged_f32": "f32", "gemm_staged_
                "gemm_staged_bf16": "bf16", "gemm_staged128_f64": "f64", "gemm_staged128_f32": "f32",
                "gemm_staged128_bf16x3": "bf16", "gemm_staged128_bf16": "bf16",
                "update_waves_f64": "f64", "update_waves_f32": "f32",
-               "update_waves_bf16x3": "bf16", "update_waves_bf16": "bf16", "potrf_f64": "f64"}
-KERNEL_SOURCE = {"gemm_staged": "kernels_gemm.hip", "update_waves": "kernels_gemm.hip",
-                 "potrf_f64": "kernels_dense.hip"}
+               "update_waves_bf16x3": "bf16", "update_waves_bf16": "bf16", "potrf_f64": "f64",
+               "gemm_potrf_f64": "f64"}
+# kernel name prefix -> the source files its code lives in (digest of their concatenation)
+KERNEL_SOURCE = {"gemm_staged": ("kernels_gemm.hip",), "update_waves": ("kernels_gemm.hip",),
+                 "gemm_potrf": ("kernels_gemm.hip", "potrf_block.h"),
+                 "potrf_f64": ("kernels_dense.hip", "potrf_block.h")}
 DEFAULT_PRECISION = {"diffusion3d_96": "bf16", "batched2d_64": "fp32"}
 
 
@@ -186,11 +189,13 @@ def run_form(pattern, vals, b, cfg, extra, precision, steps, warmup, profile, ba
 # ------------------------------------------------------------------ measurement helpers
 
 def source_digest(kernel):
-    for prefix, src in KERNEL_SOURCE.items():
+    for prefix, srcs in KERNEL_SOURCE.items():
         if kernel.startswith(prefix):
-            path = os.path.join(ROOT, "paper_1507_05593_amd", "csrc", src)
-            with open(path, "rb") as f:
-                return src, hashlib.sha256(f.read()).hexdigest()[:16]
+            h = hashlib.sha256()
+            for src in srcs:
+                with open(os.path.join(ROOT, "paper_1507_05593_amd", "csrc", src), "rb") as f:
+                    h.update(f.read())
+            return "+".join(srcs), h.hexdigest()[:16]
     return None, None
 
 
@@ -398,6 +403,8 @@ _MODE_NAMES = {0: "f64", 1: "f32", 2: "bf16x3", 3: "bf16"}
 def profile_name(rocprof_name):
     """Kernel name of the library's profile for a rocprofv3 kernel name (or None)."""
     import re
+    if re.search(r"k_gemm_staged<0, 64, true>", rocprof_name):
+        return "gemm_potrf_f64"
     m = re.search(r"k_gemm_staged<(\d), (\d+)", rocprof_name)
     if m:
         return f"gemm_staged{'128' if m.group(2) == '128' else ''}_{_MODE_NAMES[int(m.group(1))]}"
@@ -427,7 +434,7 @@ def summarize_trace(d, last_from):
     allk = {nm: {"calls": len(v), "total_ms": sum(v) * 1e-6, "avg_us": sum(v) / len(v) * 1e-3}
             for nm, v in per.items()}
     out = {"all": dict(sorted(allk.items(), key=lambda kv: -kv[1]["total_ms"])),
-           "sources": {src: source_digest(k)[1] for k, src in KERNEL_SOURCE.items()}}
+           "sources": {"+".join(src): source_digest(k)[1] for k, src in KERNEL_SOURCE.items()}}
     if last_from:
         with open(last_from) as fh:
             line = json.loads(next(l for l in reversed(fh.read().splitlines()) if l.startswith('{"metric"')))

@@ -238,7 +238,7 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
  * (both as for rsc_profile; launches whose extents depend on the kept ranks are counted
  * at the ranks of the factorisation that ran).  Any output may be NULL.  Errors:
  * RSC_ERR_INVALID_ARG for a null handle or k out of range. */
-#define RSC_KERNELS 38
+#define RSC_KERNELS 39
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops, double* tile_flops);
 

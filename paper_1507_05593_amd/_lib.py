@@ -23,7 +23,7 @@ RSC_MIXED_FP32 = 2
 
 K_CLASSES = ["update", "panel_potrf", "panel_trsm", "panel_trailing", "truncation", "pcg", "other", "lo_product",
              "sample", "orthonormalise", "basis"]
-RSC_KERNELS = 38
+RSC_KERNELS = 39
 
 
 class Options(C.Structure):

@@ -1506,11 +1506,11 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "trunc_compact", "assemble", "fill", "row_gather", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
     "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
-    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns", "sweep_fwd", "sweep_bwd"};
+    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns", "sweep_fwd", "sweep_bwd", "gemm_potrf_f64"};
 
-int32_t kernel_id(int32_t type, int64_t a, int64_t b) {
+int32_t kernel_id(int32_t type, int64_t a, int64_t b, bool post) {
   switch (type) {
-    case kCmdGemm: return (int32_t)((b == 128 ? 25 : 0) + (a & 3));
+    case kCmdGemm: return post ? 38 : (int32_t)((b == 128 ? 25 : 0) + (a & 3));
     case kCmdUpdate: return (int32_t)(4 + (a & 3));
     case kCmdCompact: return 29;
     case kCmdGemmReduce: return 30;
@@ -1631,7 +1631,7 @@ static Error run_cmds(Handle& h, const std::vector<Cmd>& cmds, const FactorPlan*
       HIPCHK(hipEventCreate(&ep.a));
       HIPCHK(hipEventCreate(&ep.b));
       ep.klass = c.klass;
-      ep.kid = kernel_id(c.type, c.a, c.b);
+      ep.kid = kernel_id(c.type, c.a, c.b, c.post);
       ep.arith = cmd_arith(c);
       ep.flops = c.flops;
       ep.mflops = c.mflops;

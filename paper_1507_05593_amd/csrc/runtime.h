@@ -30,7 +30,7 @@ enum CmdType : int32_t {
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
-int32_t kernel_id(int32_t type, int64_t a, int64_t b);
+int32_t kernel_id(int32_t type, int64_t a, int64_t b, bool post = false);
 const char* kernel_name(int32_t k);
 
 struct Cmd {
