@@ -174,23 +174,27 @@ void plan_layout(Handle& h) {
   h.f32_end_comp = ac;
   // Level pool: per elimination-tree level, U^O_j of its supernodes (assembled and
   // updated there, dead once L^O_j is formed), the 64 x 64 inverse blocks of their panel
-  // steps, and with compression the dense L^O_j and the range finder's work space.  The
-  // levels run one after another, so each reuses the pool from its start.
-  h.a_pool = align64(std::max(ax, ac));
-  h.uo_off.assign(M, -1);
-  h.dinv_off.assign(M, 0);
-  h.lev_uo.assign(S.nlevels, {0, 0});
+  // steps, and with compression the range finder's work space.  The levels run one after
+  // another, so each reuses the pool from its start.  The pool follows region X of the
+  // factor's own layout (the exact layout's dense L^O_j or the compressed one's V_j, U_j),
+  // so its offsets are kept relative to its start and made absolute by set_layout.
+  h.pool_base_exact = align64(ax);
+  h.pool_base_comp = align64(ac);
+  h.uo_rel.assign(M, -1);
+  h.dinv_rel.assign(M, 0);
+  h.lev_uo_rel.assign(S.nlevels, {0, 0});
+  h.comp_rel = h.comp;
   int64_t pool_exact = 0, pool_comp = 0;
   for (int32_t L = 0; L < S.nlevels; ++L) {
-    int64_t p = h.a_pool;
+    int64_t p = 0;
     for (int32_t j : S.by_level[L])
-      if (S.r(j) > 0) { h.uo_off[j] = p; p += align64((int64_t)S.c(j) * S.r(j)); }
-    h.lev_uo[L] = {h.a_pool, p};
-    for (int32_t j : S.by_level[L]) { h.dinv_off[j] = p; p += ((S.c(j) + 63) / 64) * 4096; }
-    pool_exact = std::max(pool_exact, p - h.a_pool);
+      if (S.r(j) > 0) { h.uo_rel[j] = p; p += align64((int64_t)S.c(j) * S.r(j)); }
+    h.lev_uo_rel[L] = {0, p};
+    for (int32_t j : S.by_level[L]) { h.dinv_rel[j] = p; p += ((S.c(j) + 63) / 64) * 4096; }
+    pool_exact = std::max(pool_exact, p);
     for (int32_t j : S.by_level[L]) {
       if (!h.compressible[j]) continue;
-      CompSlot& C = h.comp[j];
+      CompSlot& C = h.comp_rel[j];
       const int64_t c = S.c(j), r = S.r(j), l = C.ell;
       C.omega = p; p += align64(r * l);
       C.tmp = p; p += align64(c * l);
@@ -212,11 +216,13 @@ void plan_layout(Handle& h) {
         C.zdinv = p; p += ((l + 63) / 64) * 4096;
       }
     }
-    pool_comp = std::max(pool_comp, p - h.a_pool);
+    pool_comp = std::max(pool_comp, p);
   }
-  h.arena_size_exact = align64(h.a_pool + pool_exact);
-  h.arena_size_comp = align64(h.a_pool + pool_comp);
+  h.arena_size_exact = align64(h.pool_base_exact + pool_exact);
+  h.arena_size_comp = align64(h.pool_base_comp + pool_comp);
   h.lo_off = h.lo_off_exact;
+  h.a_pool = -1;
+  set_layout(h, false);
   // PCG int slots
   h.sc.active = islot; islot += nseg;
   h.sc.iters = islot; islot += nseg;
@@ -226,7 +232,8 @@ void plan_layout(Handle& h) {
 
   // assembly: entry (i, col) with col <= i goes to the lower position of the permuted
   // pair in the supernode owning the column -- its panel (rows in C_j, at the start of
-  // a factorization) or its U^O_j in the pool (rows in R_j, at the start of its level)
+  // a factorization) or its U^O_j in the pool (rows in R_j, at the start of its level;
+  // offsets relative to the pool)
   h.asm_slot.assign(nnz, -1);
   std::vector<std::vector<std::pair<int64_t, int64_t>>> lev_ent(S.nlevels);
   for (int64_t i = 0; i < n; ++i) {
@@ -243,7 +250,7 @@ void plan_layout(Handle& h) {
         const int64_t* b = S.rows.data() + S.rows_ptr[j];
         const int64_t* e = S.rows.data() + S.rows_ptr[j + 1];
         const int64_t f = std::lower_bound(b, e, hi) - b;
-        lev_ent[S.level[j]].push_back({p, h.uo_off[j] + t * S.r(j) + f});
+        lev_ent[S.level[j]].push_back({p, h.uo_rel[j] + t * S.r(j) + f});
       }
     }
   }
@@ -258,6 +265,35 @@ void plan_layout(Handle& h) {
   for (int64_t j = 0; j < M; ++j) {
     const int64_t c = S.c(j);
     for (int64_t t = 0; t < c; ++t) h.ident_slot.push_back(h.panel_off[j] + t * h.panel_ld[j] + (c + t));
+  }
+}
+
+// Pool offsets of one layout (exact or compressed factor): the pool-relative tables plus
+// that layout's pool start.
+void set_layout(Handle& h, bool compressed) {
+  const int64_t base = compressed ? h.pool_base_comp : h.pool_base_exact;
+  h.lo_off = compressed ? h.lo_off_comp : h.lo_off_exact;
+  if (h.a_pool == base) return;
+  h.a_pool = base;
+  const int64_t M = h.S.M();
+  h.uo_off.assign(M, -1);
+  h.dinv_off.assign(M, 0);
+  for (int64_t j = 0; j < M; ++j) {
+    if (h.uo_rel[j] >= 0) h.uo_off[j] = base + h.uo_rel[j];
+    h.dinv_off[j] = base + h.dinv_rel[j];
+  }
+  h.lev_uo.assign(h.lev_uo_rel.size(), {0, 0});
+  for (size_t L = 0; L < h.lev_uo_rel.size(); ++L)
+    h.lev_uo[L] = {base + h.lev_uo_rel[L][0], base + h.lev_uo_rel[L][1]};
+  for (int64_t j = 0; j < M; ++j) {
+    if (!h.compressible[j]) continue;
+    const CompSlot& R = h.comp_rel[j];
+    CompSlot& C = h.comp[j];
+    auto abs = [&](int64_t x) { return x >= 0 ? base + x : x; };
+    C.omega = abs(R.omega); C.tmp = abs(R.tmp); C.ypanel = abs(R.ypanel); C.ydinv = abs(R.ydinv);
+    C.V = abs(R.V); C.gscale = abs(R.gscale); C.G = abs(R.G); C.Sa = abs(R.Sa); C.Sb = abs(R.Sb);
+    C.Om2 = abs(R.Om2); C.Mpan = abs(R.Mpan); C.Mdinv = abs(R.Mdinv); C.Wpan = abs(R.Wpan);
+    C.Wdinv = abs(R.Wdinv); C.sc = abs(R.sc); C.zpanel = abs(R.zpanel); C.zdinv = abs(R.zdinv);
   }
 }
 
@@ -1562,7 +1598,8 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdFillInts: launch_fill_i32(I + c.off, c.count, (int32_t)c.v, s); break;
     case kCmdAssemble: launch_assemble(A + h.a_values, h.d_asm_slot.p, c.count, A, s); break;
     case kCmdAssembleLevel:
-      launch_assemble_pairs(A + h.a_values, h.d_asmo_idx.p + c.off, h.d_asmo_slot.p + c.off, c.count, A, s);
+      launch_assemble_pairs(A + h.a_values, h.d_asmo_idx.p + c.off, h.d_asmo_slot.p + c.off, c.count,
+                            A + h.a_pool, s);
       break;
     case kCmdIdent: launch_scatter_const(h.d_ident_slot.p, c.count, 1.0, A, s); break;
     case kCmdUpdate:
@@ -1712,9 +1749,9 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
                          hipStream_t stream) {
   Error e;
   const bool compressed = tol > 0.0;
-  // the layout of this factor: where L^O_j of the compressible supernodes lives, and the
-  // arena length it needs
-  h.lo_off = compressed ? h.lo_off_comp : h.lo_off_exact;
+  // the layout of this factor: where L^O_j of the compressible supernodes (or V_j, U_j)
+  // live, where the level pool starts, and the arena length it needs
+  set_layout(h, compressed);
   if ((e = ensure_arena(h, compressed ? h.arena_size_comp : h.arena_size_exact)).code) return e;
   auto& slot = h.fplans[precision];
   if (!slot || slot->compressed != compressed || (compressed && slot->tol != tol))

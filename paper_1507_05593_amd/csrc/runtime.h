@@ -172,7 +172,12 @@ struct Handle {
   std::vector<std::array<int64_t, 2>> lev_uo;       // per level: its U^O range of the pool
   std::vector<int64_t> asm_slot;      // per stored entry: panel slot (rows in C_j) or -1
   std::vector<int64_t> asmo_idx, asmo_slot, asmo_ptr;   // entries of rows R_j: value index and
-                                                        // pool slot, by level (asmo_ptr)
+                                                        // pool-relative slot, by level (asmo_ptr)
+  // level pool: offsets relative to its start (set_layout adds the layout's start)
+  int64_t pool_base_exact = 0, pool_base_comp = 0;
+  std::vector<int64_t> uo_rel, dinv_rel;
+  std::vector<std::array<int64_t, 2>> lev_uo_rel;
+  std::vector<CompSlot> comp_rel;     // the work-space fields of comp, pool-relative
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
   std::vector<int32_t> sn_local;      // supernode index within its own system (sample key)
@@ -225,6 +230,8 @@ struct Handle {
 
 // analyze-phase layout (no device work)
 void plan_layout(Handle& h);
+// the pool offsets (and L^O offsets) of the exact (false) or rank-structured layout
+void set_layout(Handle& h, bool compressed);
 // device set-up (first numeric call)
 Error ensure_device(Handle& h);
 void drop_graphs(Handle& h);
