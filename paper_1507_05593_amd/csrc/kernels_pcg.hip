@@ -33,9 +33,9 @@ __device__ double block_sum(double v) {
 // ---------------------------------------------------------------- sweeps
 
 // The factor operands of the sweeps (L^O_j, U_j, V_j, the inverse diagonal blocks) are
-// read through F: the arena itself (TF = double), or in the mixed forms its FP32 copy at
-// the same offsets (TF = float, written by k_to_f32 once the factorization is complete);
-// the vectors and every sum stay FP64.
+// read through F: the arena itself (TF = double), or in the mixed forms its FP32 copy
+// (TF = float: L^O_j, U_j and V_j at their arena offsets, the inverse blocks M_j compact,
+// written once the factorization is complete); the vectors and every sum stay FP64.
 
 // out[t] = sum_{m < K} X(t, m) v[m] for up to 64 rows: lane = row (coalesced column
 // reads), the 4 waves split the inner dimension and their partial sums are added in
@@ -515,16 +515,15 @@ __global__ __launch_bounds__(256) void k_to_f32(const ConvTask* __restrict__ tas
   const ConvTask T = tasks[blockIdx.x];
   if (T.rows >= 256) {
     for (int c = 0; c < T.cols; ++c) {
-      const int64_t o = T.off + (int64_t)c * T.ld;
+      const int64_t o = T.off + (int64_t)c * T.ld, d = T.dst + (int64_t)c * T.dld;
 #pragma unroll 4
-      for (int t = threadIdx.x; t < T.rows; t += 256) f32[o + t] = (float)arena[o + t];
+      for (int t = threadIdx.x; t < T.rows; t += 256) f32[d + t] = (float)arena[o + t];
     }
   } else {                                  // short columns: every thread busy
     const int n = T.rows * T.cols;
     for (int e = threadIdx.x; e < n; e += 256) {
       const int c = e / T.rows, t = e - c * T.rows;
-      const int64_t o = T.off + (int64_t)c * T.ld + t;
-      f32[o] = (float)arena[o];
+      f32[T.dst + (int64_t)c * T.dld + t] = (float)arena[T.off + (int64_t)c * T.ld + t];
     }
   }
 }

@@ -137,6 +137,15 @@ void plan_layout(Handle& h) {
   h.a_panels = a; a += poff;
   h.panels_size = poff;
   for (int64_t j = 0; j < M; ++j) h.panel_off[j] += h.a_panels;
+  // the FP32 copy's compact M_j blocks sit just below a_lo in its own offsets
+  h.a_lo = a;
+  h.m32_off.assign(M, 0);
+  {
+    int64_t m32 = 0;
+    for (int64_t j = 0; j < M; ++j) { h.m32_off[j] = m32; m32 += align64((int64_t)S.c(j) * S.c(j)); }
+    h.m32_size = m32;
+    for (int64_t j = 0; j < M; ++j) h.m32_off[j] += h.a_lo - m32;
+  }
   // dense L^O_j of the supernodes never compressed
   h.lo_off_exact.assign(M, -1);
   h.lo_off_comp.assign(M, -1);
@@ -955,26 +964,26 @@ struct Builder {
   }
 
   // FP32 copy (mixed forms) of the factor operands the two sweeps of the preconditioner
-  // read, at the arena's offsets: the inverse diagonal blocks M_j and U_j here (L^O_j
-  // and V_j are copied by k_compact_rows along with their compact copies); blocks of at
-  // most 64 columns and kConvRows rows.
+  // read: the inverse diagonal blocks M_j as compact c x c blocks, U_j at its arena
+  // offsets (L^O_j and V_j are copied by k_compact_rows along with their compact copies);
+  // blocks of at most 64 columns and kConvRows rows.
   void f32_copy() {
     const Symbolic& S = h.S;
     const int64_t c0 = (int64_t)P.conv.size();
     // upper: only rows above the column block's end (M_j is upper triangular)
-    auto add = [&](int64_t off, int32_t rows, int32_t cols, int32_t ld, bool upper) {
+    auto add = [&](int64_t off, int32_t ld, int64_t dst, int32_t dld, int32_t rows, int32_t cols, bool upper) {
       for (int32_t j0 = 0; j0 < cols; j0 += 64) {
         const int32_t rr = upper ? std::min(rows, j0 + 64) : rows;
         for (int32_t i0 = 0; i0 < rr; i0 += kConvRows)
-          P.conv.push_back(ConvTask{off + i0 + (int64_t)j0 * ld, std::min(kConvRows, rr - i0),
-                                    std::min(64, cols - j0), ld, 0});
+          P.conv.push_back(ConvTask{off + i0 + (int64_t)j0 * ld, dst + i0 + (int64_t)j0 * dld,
+                                    std::min(kConvRows, rr - i0), std::min(64, cols - j0), ld, dld});
       }
     };
     for (int64_t j = 0; j < S.M(); ++j) {
       const int32_t c = S.c(j), r = S.r(j);
-      add(h.panel_off[j] + c, c, c, h.panel_ld[j], true);
+      add(h.panel_off[j] + c, h.panel_ld[j], h.m32_off[j], c, c, c, true);
       if (r == 0) continue;
-      if (P.compressed && h.compressible[j]) add(h.comp[j].Uj, c, h.comp[j].ell, c, false);
+      if (P.compressed && h.compressible[j]) add(h.comp[j].Uj, c, h.comp[j].Uj, c, c, h.comp[j].ell, false);
     }
     cmd(kCmdToF32, RSC_K_OTHER, c0, (int64_t)P.conv.size() - c0, 0.0, 0);
   }
@@ -1464,8 +1473,8 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
   if ((e = upload(P->d_gs_m, P->gs_m)).code) return e;
   if ((e = upload(P->d_conv, P->conv)).code) return e;
-  // FP32 copy of the sweeps' operands: panels, dense L^O and region X of this layout
-  const int64_t n32 = (compressed ? h.f32_end_comp : h.f32_end_exact) - h.a_panels;
+  // FP32 copy of the sweeps' operands: the compact M_j, dense L^O and region X of this layout
+  const int64_t n32 = h.m32_size + (compressed ? h.f32_end_comp : h.f32_end_exact) - h.a_lo;
   if (!P->conv.empty() && h.arena32.n < n32) {
     drop_graphs(h);
     h.arena32.reset();
@@ -1579,11 +1588,11 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b, bool post) {
 
 const char* kernel_name(int32_t k) { return (k >= 0 && k < RSC_KERNELS) ? kKernelNames[k] : ""; }
 
-// The FP32 copy addressed by arena offsets: element a_panels + k of the result is element
-// k of the copy (no offset below a_panels is ever used with it).
+// The FP32 copy addressed by FP32 offsets: element a_lo - m32_size + k of the result is
+// element k of the copy (no offset below that is ever used with it).
 static float* f32_base(Handle& h) {
   return reinterpret_cast<float*>(reinterpret_cast<uintptr_t>(h.arena32.p) -
-                                  sizeof(float) * (uintptr_t)h.a_panels);
+                                  sizeof(float) * (uintptr_t)(h.a_lo - h.m32_size));
 }
 
 static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const SolvePlan* Q,
@@ -1880,6 +1889,12 @@ static Error build_solve_plan(Handle& h) {
     if ((int64_t)Q->papply.size() > a0) cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
   };
   auto iscomp = [&](int64_t j) { return comp && h.compressible[j]; };
+  // the inverse diagonal blocks M_j: in the panels (FP64 sweeps), or the FP32 copy's
+  // compact blocks after a mixed factorization
+  const bool f32 = h.f32_valid;
+  Q->f32_tasks = f32;
+  auto m_off = [&](int64_t j) { return f32 ? h.m32_off[j] : h.panel_off[j] + S.c(j); };
+  auto m_ld = [&](int64_t j) { return f32 ? S.c(j) : h.panel_ld[j]; };
   double bytes = 0;
   // Small-supernode levels: the lowest levels whose supernodes all fit one workgroup
   // (at most sweep_small_c columns and kSweepMaxR rows) run each sweep step as one launch
@@ -1910,7 +1925,7 @@ static Error build_solve_plan(Handle& h) {
       for (int32_t j : S.by_level[L]) {
         const int32_t c = S.c(j), r = S.r(j);
         SweepTask t{};
-        t.m = h.panel_off[j] + c; t.ld = h.panel_ld[j];
+        t.m = m_off(j); t.ld = m_ld(j);
         t.first = S.first[j]; t.rows = S.rows_ptr[j]; t.c = c; t.r = r;
         t.x = 0; t.u = -1; t.qslot = -1; t.kmax = 0;
         if (iscomp(j)) {
@@ -1978,7 +1993,7 @@ static Error build_solve_plan(Handle& h) {
       const int32_t c = S.c(j), r = S.r(j);
       for (int32_t col0 = 0; col0 < c; col0 += 16) {
         ColDotTask t{};
-        t.x = h.panel_off[j] + c; t.ldx = h.panel_ld[j];
+        t.x = m_off(j); t.ldx = m_ld(j);
         t.in = h.a_y + S.first[j]; t.idx = -1; t.out = h.a_w + S.first[j];
         t.rows = c; t.ncols = c; t.col0 = col0; t.tri = 1;
         st.push_back(t);
@@ -2117,7 +2132,7 @@ static Error build_solve_plan(Handle& h) {
           const int32_t s0 = slot;
           for (int32_t t0 = i0; t0 < c; t0 += width) {
             RowChunk t{};
-            t.m = h.panel_off[j] + c; t.ld = h.panel_ld[j]; t.c = c; t.i0 = i0;
+            t.m = m_off(j); t.ld = m_ld(j); t.c = c; t.i0 = i0;
             t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;
             t.t0 = t0; t.t1 = std::min(c, t0 + width); t.slot = slot++;
             Q->rchunks.push_back(t);
@@ -2166,6 +2181,13 @@ static Error apply_cmds(Handle& h, hipStream_t s, std::vector<EventPair>* evs,
 
 static Error ensure_solve(Handle& h) {
   if (!h.factored) return Error{RSC_ERR_STATE, "no successful rsc_factor on this handle"};
+  if (h.splan && h.splan->f32_tasks != h.f32_valid) {   // M_j read from the other copy
+    SolvePlan& Q = *h.splan;
+    if (Q.graph_a) (void)hipGraphExecDestroy(Q.graph_a);
+    if (Q.graph_b) (void)hipGraphExecDestroy(Q.graph_b);
+    if (Q.graph_apply) (void)hipGraphExecDestroy(Q.graph_apply);
+    h.splan.reset();
+  }
   if (!h.splan) return build_solve_plan(h);
   return kOk;
 }

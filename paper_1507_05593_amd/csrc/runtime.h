@@ -151,6 +151,7 @@ struct SolvePlan {
   double bytes = 0;                   // factor bytes read by one apply
   double v_rtol = -1;                 // rtol baked into graph_a
   int32_t f32_mode = -1;              // factor operand copy the graphs were captured with
+  bool f32_tasks = false;             // the tasks address M_j in the FP32 copy's compact blocks
 };
 
 struct Handle {
@@ -190,10 +191,14 @@ struct Handle {
   int64_t arena_size_exact = 0, arena_size_comp = 0;   // length each layout needs
   int64_t panels_size = 0;
   int64_t f32_end_exact = 0, f32_end_comp = 0;          // end of the sweeps' operands per layout
+  // FP32 copy (mixed forms): offsets [a_lo, f32_end) mirror the arena (L^O_j, V_j, U_j);
+  // below a_lo, m32_size floats hold each M_j compact (c x c, ld c) at m32_off[j]
+  int64_t a_lo = 0, m32_size = 0;
+  std::vector<int64_t> m32_off;
   int64_t a_pool = 0;
   DevArray<double> arena;
   DevArray<float> arena32;            // FP32 copy of the sweeps' factor operands (mixed forms):
-                                      // element k holds arena offset a_panels + k
+                                      // element k holds FP32 offset a_lo - m32_size + k
   bool f32_valid = false;             // the last factorization was mixed: the sweeps read arena32
   DevArray<int32_t> ints;
   DevArray<int64_t> d_asm_slot, d_ident_slot, d_perm, d_rows, d_rowptr, d_asmo_idx, d_asmo_slot;

@@ -148,12 +148,13 @@ struct PcgScalars {
 
 namespace rsc {
 
-// One block of a factor operand to copy to FP32 (rows [0, rows) of columns [0, cols) of
-// the column-major block at arena offset off, column stride ld), at the same offsets.
+// One block of a factor operand to copy to FP32: rows [0, rows) of columns [0, cols) of
+// the column-major block at arena offset off (column stride ld) to FP32 offset dst
+// (column stride dld).
 constexpr int32_t kConvRows = 4096;
 struct ConvTask {
-  int64_t off;
-  int32_t rows, cols, ld, pad_;
+  int64_t off, dst;
+  int32_t rows, cols, ld, dld;
 };
 
 // Backward diagonal solve chunk: rows [i0, i0 + 64) of z_C = M (w_C - s_C) over the
