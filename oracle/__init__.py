@@ -20,6 +20,10 @@ Parity status per function (what pins it, see the tests named ``test_oracle_*``)
   triangular solve of Algorithm 1, with explicit and with compressed descendants;
   ``compress_implicit`` reproduces the explicit compression (ranks, ``V_j U_j^T``).
 * ``philox``: the published known-answer vectors of Philox4x32-10.
+* ``spectral.spectral_coordinates`` (§4.3, block Lanczos on the graph Laplacian): the
+  closed-form spectrum and cosine eigenvectors of grid graphs (distinct modes, and the
+  threefold axis mode of a cube), a dense eigen-decomposition when the Krylov space is the
+  whole space, and a hand-built Laplacian.
 * ``solve``: exact factor gives ``M^{-1} = A^{-1}``; symmetry and positivity of
   the rank-structured preconditioner; manufactured solutions.
 * ``adjoint``: central finite differences of dense solves.

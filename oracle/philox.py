@@ -46,8 +46,9 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
     return c0, c1, c2, c3
 
 
-def gaussian_sample(seed: int, j: int, rows: int, cols: int) -> np.ndarray:
-    """The ``rows x cols`` FP64 Gaussian sample of supernode ``j``."""
+def gaussian_sample(seed: int, j: int, rows: int, cols: int, c2: int = 0) -> np.ndarray:
+    """The ``rows x cols`` FP64 Gaussian sample of supernode ``j`` (third counter word
+    ``c2``: 0 for the range finder's sample, 2 for the spectral start block)."""
     seed = int(seed)
     k0 = np.uint32(seed & 0xFFFFFFFF)
     k1 = np.uint32(((seed >> 32) & 0xFFFFFFFF) ^ (j & 0xFFFFFFFF))
@@ -55,7 +56,7 @@ def gaussian_sample(seed: int, j: int, rows: int, cols: int) -> np.ndarray:
     r = np.repeat(np.arange(rows, dtype=np.uint32), ngrp)
     t = np.tile(np.arange(ngrp, dtype=np.uint32), rows)
     z = np.zeros_like(r)
-    w0, w1, w2, w3 = philox4x32_10(r, t, z, z, np.full_like(r, k0), np.full_like(r, k1))
+    w0, w1, w2, w3 = philox4x32_10(r, t, np.full_like(r, c2), z, np.full_like(r, k0), np.full_like(r, k1))
     two32 = 2.0 ** -32
     out = np.empty((rows, ngrp, 4))
     for a, b, i in ((w0, w1, 0), (w2, w3, 2)):
