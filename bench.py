@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--cpu-sample-side", type=int, default=46)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-coordinates timing")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying hipGraphs")
     ap.add_argument("--gemm-tile", type=int, default=0, choices=[0, 64, 128],
                     help="output tile edge of the product launches (0: autotuned)")
@@ -128,6 +129,45 @@ def make_solver(pattern, precision, batched, use_graph=True, gemm_tile=0):
     if batched:
         return RSCSolver.batch(*pattern, **kw)
     return RSCSolver(*pattern, **kw)
+
+
+def spectral_bytes(n, nnz, m):
+    """Algorithmic HBM bytes of one rsc_spectral_coordinates call (FP64, m blocks of three):
+    per block the Laplacian product (pattern and 3 vectors in, 3 out), the diagonal block's
+    inner products, the copy of L X, two orthogonalisation passes against the c0 earlier
+    basis vectors (inner products: c0 + 3 columns read; update: c0 + 3 read, 3 written)
+    and two Cholesky-QR passes (Gram: 3 columns; scaling: 3 read, 3 written); then the Ritz
+    vectors (3 m columns read, 3 written) and the sign (3 read, 3 + 3 read/written)."""
+    col = 8.0 * n
+    total = 2 * (2 * (1 + 3) + 3) * col + 2 * 9 * col          # start block
+    for k in range(m):
+        c0 = 1 + 3 * (k + 1)
+        total += 12.0 * nnz + 8.0 * n + 6 * col + 6 * col      # Laplacian product, A_k
+        if k + 1 == m:
+            break
+        total += 6 * col + 2 * ((c0 + 3) + (c0 + 6)) * col + 2 * 9 * col
+    return total + (3 * m + 3) * col + 9 * col
+
+
+def spectral_line(pattern, m=20, reps=3):
+    """Timed spectral coordinates (paper Sec. 4.3) on the workload's pattern."""
+    import torch
+    from paper_1507_05593_amd import RSCSolver
+    sol = RSCSolver(*pattern)
+    sol.spectral_coordinates(steps=m, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, ritz = sol.spectral_coordinates(steps=m, seed=0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    n, nnz = sol.n, sol.nnz
+    byt = spectral_bytes(n, nnz, m)
+    del sol
+    gbs = byt / (ms * 1e-3) / 1e9
+    return {"steps": m, "ms": round(ms, 3), "ritz": [float(x) for x in ritz],
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(gbs / 8000.0, 4), "bytes": byt}}
 
 
 # ------------------------------------------------------------------ one step
@@ -585,6 +625,8 @@ def main():
                            for k, v in top}
         line["classes_ms"] = {k: round(v["ms"], 3) for k, v in res["classes"].items() if v["launches"]}
     line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])
+    if not batched and not args.no_spectral:
+        line["spectral_coordinates"] = spectral_line(pattern)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name, cfg, args.cpu_sample_side, desc)
     print(json.dumps(line), flush=True)

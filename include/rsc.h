@@ -197,6 +197,25 @@ rsc_status rsc_apply_preconditioner(rsc_handle h, const double* r, double* z, vo
 #define RSC_APPLY_SCRATCH_BYTES (8u << 20)
 rsc_status rsc_apply_preconditioner_noalloc(rsc_handle h, const double* r, double* z, void* stream);
 
+/* Spectral coordinates (Sec. 4.3): a position in three dimensions for every index of the
+ * handle's matrix (one system only), for reordering when the problem supplies none: the
+ * three lowest eigenvectors orthogonal to the constant vector of the graph Laplacian of
+ * the pattern (-1 per stored off-diagonal entry, the row's count of them on the
+ * diagonal), approximated by block Lanczos iteration (the symmetric form of Arnoldi) with
+ * blocks of three vectors over `steps` blocks, every block orthogonalised against all
+ * earlier ones; the Ritz vectors of the three smallest Ritz values, each signed so that
+ * sum_i (i + 1) y_i >= 0.  The start block is entry (i, c) of the Philox4x32-10 Gaussian
+ * stream under key (seed mod 2^32, (seed >> 32) XOR 0xFFFFFFFF) with third counter word 2.
+ * xyz: device double[3 n], coordinate c of index i (caller's order) at xyz[i + c n].
+ * ritz: optional host double[3], the Ritz values (ascending).  steps in [1, 30] with
+ * 1 + 3 steps <= n.  Allocates its work space (n x (1 + 3 steps) doubles and small blocks)
+ * for the call and synchronises the stream before returning.
+ * Errors: RSC_ERR_INVALID_ARG (null xyz, a batch handle, steps out of range),
+ * RSC_ERR_BREAKDOWN (the Krylov space was exhausted: fewer steps), RSC_ERR_OUT_OF_MEMORY,
+ * RSC_ERR_DEVICE. */
+rsc_status rsc_spectral_coordinates(rsc_handle h, int32_t steps, uint64_t seed, double* xyz, double* ritz,
+                                    void* stream);
+
 /* Adjoint of the solve with respect to the matrix values (not in the paper):
  * g[p] = -lambda[row(p)] * x[col(p)] for every stored entry p (CSR order).
  * lambda, x: device double[n]; g: device double[nnz]. */

@@ -81,6 +81,8 @@ SYMBOLS = {
     "rsc_apply_preconditioner": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rsc_apply_preconditioner_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rsc_grad_values": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rsc_spectral_coordinates": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint64, C.c_void_p, C.c_void_p,
+                                           C.c_void_p]),
     "rsc_grad_faces": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p]),
     "rsc_get_sizes": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int64)] * 5),

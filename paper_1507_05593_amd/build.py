@@ -17,8 +17,8 @@ LIB = os.path.join(PKG, "librsc.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SOURCES = ["symbolic.cpp", "runtime.cpp", "api.cpp"]
-HIP_SOURCES = ["kernels_dense.hip", "kernels_pcg.hip", "kernels_gemm.hip"]
+HOST_SOURCES = ["symbolic.cpp", "runtime.cpp", "spectral.cpp", "api.cpp"]
+HIP_SOURCES = ["kernels_dense.hip", "kernels_pcg.hip", "kernels_gemm.hip", "kernels_spectral.hip"]
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result"]

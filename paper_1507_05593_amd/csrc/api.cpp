@@ -160,6 +160,12 @@ rsc_status rsc_apply_preconditioner_noalloc(rsc_handle H, const double* r, doubl
   return ret(rsc::apply_preconditioner_noalloc(H->h, r, z, (hipStream_t)stream));
 }
 
+rsc_status rsc_spectral_coordinates(rsc_handle H, int32_t steps, uint64_t seed, double* xyz, double* ritz,
+                                    void* stream) {
+  if (!H || !xyz) return fail(RSC_ERR_INVALID_ARG, "null argument");
+  return ret(rsc::spectral_coordinates(H->h, steps, seed, xyz, ritz, (hipStream_t)stream));
+}
+
 rsc_status rsc_grad_values(rsc_handle H, const double* lambda, const double* x, double* g, void* stream) {
   if (!H || (H->h.S.n > 0 && (!lambda || !x || !g))) return fail(RSC_ERR_INVALID_ARG, "null argument");
   return ret(rsc::grad_values(H->h, lambda, x, g, (hipStream_t)stream));

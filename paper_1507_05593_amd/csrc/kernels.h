@@ -58,6 +58,25 @@ void launch_sweep_fwd(const SweepTask* t, int n, int nt, int cpad, int lpad, dou
 void launch_sweep_bwd(const SweepTask* t, int n, int nt, int cpad, int lpad, int rmax, double* arena,
                       const float* f32, int64_t a_w, int64_t a_zz, const int32_t* ilim,
                       const int64_t* rows_idx, hipStream_t s);
+// spectral coordinates: blocks of three vectors (column-major, ld n)
+constexpr int kSpChunk = 4096;               // rows per workgroup of the block inner products
+constexpr int kSpMaxSteps = 30;              // block Lanczos steps (projected order 3 steps)
+constexpr int kSpMaxN = 3 * kSpMaxSteps;
+constexpr int kSpMaxCols = 1 + kSpMaxN;      // basis vectors, the constant one included
+void launch_lap3(const int64_t* rowptr, const int32_t* colind, int64_t n, const double* X, double* Y,
+                 hipStream_t s);
+void launch_bdots(const double* Q, int64_t ldq, int ncols, const double* W, int64_t n, double* part,
+                  hipStream_t s);
+void launch_bsum(const double* part, int nchunks, int nout, double* out, int ld, int r0, int c0, hipStream_t s);
+void launch_bupd(const double* Q, int64_t ldq, int ncols, const double* C, double* W, int64_t n, hipStream_t s);
+void launch_chol3(const double* G, double* rinv, double* racc, int pass, double* T, int ldt, int r0, int c0,
+                  int32_t* flag, hipStream_t s);
+void launch_bscale(double* W, int64_t n, const double* rinv, hipStream_t s);
+void launch_bcopy(const double* src, double* dst, int64_t len, double v, bool fill, hipStream_t s);
+void launch_jacobi(const double* T, int N, int ldt, double* V, double* evals, int32_t* sel, hipStream_t s);
+void launch_ritz(const double* Q, int64_t ldq, int nc, const double* V, int ldv, const int32_t* sel, double* Y,
+                 int64_t n, hipStream_t s);
+void launch_bsign(double* Y, int64_t n, const double* sums, hipStream_t s);
 void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);
 void launch_scatter_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s);
 void launch_spmv_dot(const Chunk* c, int nc, const int64_t* rowptr, const int32_t* colind,

@@ -247,6 +247,7 @@ Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, 
 Error apply_preconditioner(Handle& h, const double* r, double* z, hipStream_t stream);
 Error apply_preconditioner_noalloc(Handle& h, const double* r, double* z, hipStream_t stream);
 Error grad_values(Handle& h, const double* lam, const double* x, double* g, hipStream_t stream);
+Error spectral_coordinates(Handle& h, int32_t steps, uint64_t seed, double* xyz, double* ritz, hipStream_t s);
 void release_device(Handle& h);
 
 int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p);

@@ -167,6 +167,14 @@ class RSCSolver:
         return g
 
     # ---------------------------------------------------------------- inspection
+    def spectral_coordinates(self, steps: int = 20, seed: int = 0):
+        """Positions (n, 3) of the indices from the graph Laplacian of the pattern (§4.3)
+        and the three Ritz values (rsc_spectral_coordinates)."""
+        xyz = torch.empty(3 * self.n, dtype=torch.float64, device="cuda")
+        ritz = (C.c_double * 3)()
+        check(lib().rsc_spectral_coordinates(self._h, int(steps), int(seed), _ptr(xyz), ritz, _stream()))
+        return xyz.view(3, self.n).t(), np.array(ritz[:])
+
     @property
     def perm(self) -> np.ndarray:
         p = np.empty(self.n, dtype=np.int64)

@@ -258,3 +258,24 @@ def test_fullsize_adjoint_matches_central_difference():
     err = abs(fd - ad) / abs(ad)
     print("adjoint", ad, "central difference", fd, "relative difference", err, flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.gpu
+def test_fullsize_spectral_coordinates_64():
+    """Spectral coordinates (§4.3) of the 64^3 workload, 20 block steps: the device's
+    Ritz values and three-dimensional coordinate subspace against the oracle's block
+    Lanczos from the same start block."""
+    torch = _gpu()
+    from oracle.spectral import spectral_coordinates as o_spectral
+    from paper_1507_05593_amd import RSCSolver
+    print("case spectral diffusion3d_64", flush=True)
+    cfg, p = _problem("diffusion3d_64")
+    sol = RSCSolver(p.n, p.rowptr, p.colind)
+    xyz, ritz = sol.spectral_coordinates(steps=20, seed=7)
+    Y = xyz.cpu().numpy()
+    Yo, to = o_spectral(p.n, p.rowptr, p.colind, steps=20, seed=7)
+    print("ritz", ritz, "oracle", to, flush=True)
+    assert np.allclose(ritz, to, rtol=1e-9), (ritz, to)
+    qa, _ = np.linalg.qr(Y)
+    qb, _ = np.linalg.qr(Yo)
+    assert np.linalg.svd(qa.T @ qb, compute_uv=False).min() > 1 - 1e-7
