@@ -60,6 +60,7 @@ void launch_sweep_bwd(const SweepTask* t, int n, int nt, int cpad, int lpad, int
                       const int64_t* rows_idx, hipStream_t s);
 // spectral coordinates: blocks of three vectors (column-major, ld n)
 constexpr int kSpChunk = 4096;               // rows per workgroup of the block inner products
+constexpr int kSpGroup = 8;                  // basis columns per workgroup of the block inner products
 constexpr int kSpMaxSteps = 30;              // block Lanczos steps (projected order 3 steps)
 constexpr int kSpMaxN = 3 * kSpMaxSteps;
 constexpr int kSpMaxCols = 1 + kSpMaxN;      // basis vectors, the constant one included

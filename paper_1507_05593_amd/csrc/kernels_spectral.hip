@@ -44,16 +44,20 @@ __global__ __launch_bounds__(256) void k_lap3(const int64_t* __restrict__ rowptr
   Y[i + 2 * n] = deg * X[i + 2 * n] - s2;
 }
 
-// Partial inner products of one chunk of kSpChunk rows: part[(chunk * ncols + c) * 3 + k]
-// = sum over the chunk's rows of Q(i, c) W(i, k), c < ncols, k < 3.  ncols < 0: one
-// column, the weights i + 1.  Lane sums by a fixed butterfly, then the four waves in order.
+// Partial inner products of one chunk of kSpChunk rows and one group of kSpGroup
+// columns (grid: chunks x groups): part[(chunk * ncols + c) * 3 + k] = sum over the chunk's
+// rows of Q(i, c) W(i, k), c < ncols, k < 3.  ncols < 0: one column, the weights i + 1.
+// Each thread keeps its rows' W in registers and the group's 3 kSpGroup sums; lanes are
+// summed by a fixed butterfly, then the four waves in order.
 __global__ __launch_bounds__(256) void k_bdots(const double* __restrict__ Q, int64_t ldq, int ncols,
                                                const double* __restrict__ W, int64_t n,
                                                double* __restrict__ part) {
-  __shared__ double red[3][4];
+  __shared__ double red[3 * kSpGroup][4];
   constexpr int R = kSpChunk / 256;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t r0 = blockIdx.x * (int64_t)kSpChunk;
+  const int nc = ncols < 0 ? 1 : ncols;
+  const int g0 = blockIdx.y * kSpGroup, g1 = min(nc, g0 + kSpGroup);
   double w0[R], w1[R], w2[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -63,41 +67,43 @@ __global__ __launch_bounds__(256) void k_bdots(const double* __restrict__ Q, int
     w1[u] = in ? W[i + n] : 0.0;
     w2[u] = in ? W[i + 2 * n] : 0.0;
   }
-  const int nc = ncols < 0 ? 1 : ncols;
-  for (int c = 0; c < nc; ++c) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double acc[3 * kSpGroup];
+#pragma unroll
+  for (int t = 0; t < 3 * kSpGroup; ++t) acc[t] = 0.0;
+#pragma unroll
+  for (int g = 0; g < kSpGroup; ++g) {
+    const int c = g0 + g;
+    if (c >= g1) break;
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int64_t i = r0 + tid + 256 * u;
       const double q = (i < n) ? (ncols < 0 ? (double)(i + 1) : Q[i + c * ldq]) : 0.0;
-      a0 = fma(q, w0[u], a0);
-      a1 = fma(q, w1[u], a1);
-      a2 = fma(q, w2[u], a2);
+      acc[3 * g] = fma(q, w0[u], acc[3 * g]);
+      acc[3 * g + 1] = fma(q, w1[u], acc[3 * g + 1]);
+      acc[3 * g + 2] = fma(q, w2[u], acc[3 * g + 2]);
     }
-    a0 = wsum64(a0);
-    a1 = wsum64(a1);
-    a2 = wsum64(a2);
-    if (lane == 0) {
-      red[0][w] = a0;
-      red[1][w] = a1;
-      red[2][w] = a2;
-    }
-    __syncthreads();
-    if (tid < 3)
-      part[((int64_t)blockIdx.x * nc + c) * 3 + tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
-    __syncthreads();
   }
+#pragma unroll
+  for (int t = 0; t < 3 * kSpGroup; ++t) {
+    const double v = wsum64(acc[t]);
+    if (lane == 0) red[t][w] = v;
+  }
+  __syncthreads();
+  const int nout = 3 * (g1 - g0);
+  if (tid < nout)
+    part[((int64_t)blockIdx.x * nc + g0) * 3 + tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
 }
 
-// out[(r0 + o / 3) + (c0 + o % 3) ld] = sum over the chunks, in chunk order, of part[.. o],
-// o < nout.
-__global__ void k_bsum(const double* __restrict__ part, int nchunks, int nout, double* __restrict__ out,
-                       int ld, int r0, int c0) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+// out[(r0 + o / 3) + (c0 + o % 3) ld] = the sum over the chunks of part[.. o], o < nout:
+// one wave per output, lane l adding chunks l, l + 64, ... in order, then a fixed butterfly.
+__global__ __launch_bounds__(256) void k_bsum(const double* __restrict__ part, int nchunks, int nout,
+                                              double* __restrict__ out, int ld, int r0, int c0) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (o >= nout) return;
   double s = 0.0;
-  for (int b = 0; b < nchunks; ++b) s += part[(int64_t)b * nout + o];
-  out[(r0 + o / 3) + (int64_t)(c0 + o % 3) * ld] = s;
+  for (int b = lane; b < nchunks; b += 64) s += part[(int64_t)b * nout + o];
+  s = wsum64(s);
+  if (lane == 0) out[(r0 + o / 3) + (int64_t)(c0 + o % 3) * ld] = s;
 }
 
 // W -= Q(:, 0:ncols) C, C ncols x 3 (ld ncols).
@@ -200,56 +206,53 @@ __global__ __launch_bounds__(256) void k_bcopy(const double* __restrict__ src, d
 // Np - 1 rounds per sweep, Np = N rounded up to even, the extra index an inert diagonal
 // entry larger than any eigenvalue); the pair (p, q) is rotated by J = [c s; -s c] with
 // t = s / c the smaller root of t^2 + 2 theta t - 1 = 0, theta = (T_qq - T_pp) / (2 T_pq),
-// which zeroes T_pq.  Sweeps stop when the off-diagonal mass falls below 1e-32 of the
-// whole.  Output: the eigenvectors as the columns of V (Np x Np, ld Np), the eigenvalues in
-// evals, and in sel the indices of the three smallest (ascending).
-__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ T, int N, int ldt,
-                                                 double* __restrict__ V, double* __restrict__ evals,
-                                                 int32_t* __restrict__ sel) {
-  extern __shared__ double A[];   // Np x Np, A(p, q) at p + q Np
+// which zeroes T_pq.  A' = J^T A J acts on the 2 x 2 blocks (pair k rows, pair k' columns)
+// one at a time, so a round is one pass over those blocks.  Sweeps stop when the
+// off-diagonal mass falls below 1e-32 of the whole.  Output: the eigenvectors as the
+// columns of V (Np x Np, ld Np), the eigenvalues in evals, and in sel the indices of the
+// three smallest (ascending).
+__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ T, int N, int ldt,
+                                                double* __restrict__ V, double* __restrict__ evals,
+                                                int32_t* __restrict__ sel) {
+  extern __shared__ double A[];   // Np x (Np + 1), A(p, q) at p + q (Np + 1)
   __shared__ double cs[kSpMaxN / 2 + 1], sn[kSpMaxN / 2 + 1];
   __shared__ int pp[kSpMaxN / 2 + 1], qq[kSpMaxN / 2 + 1];
-  __shared__ double red[32];
+  __shared__ double red[8];
   __shared__ int go;
-  const int Np = N + (N & 1);
+  const int Np = N + (N & 1), L = Np + 1, half = Np / 2;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < Np * Np; e += nt) {
     const int p = e % Np, q = e / Np;
-    A[e] = (p < N && q < N) ? T[p + (int64_t)q * ldt] : ((p == q) ? DBL_MAX / 4 : 0.0);
+    A[p + q * L] = (p < N && q < N) ? T[p + (int64_t)q * ldt] : ((p == q) ? DBL_MAX / 4 : 0.0);
     V[e] = (p == q) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
-    // off-diagonal and total squared mass
     double off = 0.0, all = 0.0;
     for (int e = tid; e < N * N; e += nt) {
       const int p = e % N, q = e / N;
-      const double a = A[p + q * Np];
+      const double a = A[p + q * L];
       all += a * a;
       if (p != q) off += a * a;
     }
     off = wsum64(off);
     all = wsum64(all);
-    if ((tid & 63) == 0) { red[tid >> 6] = off; red[16 + (tid >> 6)] = all; }
+    if ((tid & 63) == 0) { red[tid >> 6] = off; red[4 + (tid >> 6)] = all; }
     __syncthreads();
-    if (tid == 0) {
-      double o = 0.0, t = 0.0;
-      for (int w = 0; w < nt / 64; ++w) { o += red[w]; t += red[16 + w]; }
-      go = (o > 1e-32 * t) ? 1 : 0;
-    }
+    if (tid == 0) go = ((red[0] + red[1]) + (red[2] + red[3]) > 1e-32 * ((red[4] + red[5]) + (red[6] + red[7]))) ? 1 : 0;
     __syncthreads();
     if (!go) break;
     for (int rd = 0; rd < Np - 1; ++rd) {
-      const int half = Np / 2;
       if (tid < half) {
         // round-robin pairs: index 0 fixed, the others rotated by rd
-        auto pos = [&](int k) { return k == 0 ? 0 : ((k - 1 + rd) % (Np - 1)) + 1; };
-        int p = pos(tid), q = pos(Np - 1 - tid);
+        const int a = tid, b = Np - 1 - tid;
+        int p = a == 0 ? 0 : ((a - 1 + rd) % (Np - 1)) + 1;
+        int q = ((b - 1 + rd) % (Np - 1)) + 1;
         if (p > q) { const int x = p; p = q; q = x; }
-        const double apq = A[p + q * Np];
+        const double apq = A[p + q * L];
         double c = 1.0, s = 0.0;
         if (fabs(apq) > 1e-300) {
-          const double th = (A[q + q * Np] - A[p + p * Np]) / (2.0 * apq);
+          const double th = (A[q + q * L] - A[p + p * L]) / (2.0 * apq);
           const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
@@ -257,24 +260,25 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ T, i
         cs[tid] = c; sn[tid] = s; pp[tid] = p; qq[tid] = q;
       }
       __syncthreads();
-      // rows p, q of A: J^T A
-      for (int e = tid; e < half * Np; e += nt) {
-        const int k = e / Np, j = e % Np;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double a = A[p + j * Np], b = A[q + j * Np];
-        A[p + j * Np] = c * a - s * b;
-        A[q + j * Np] = s * a + c * b;
+      // 2 x 2 blocks (rows of pair k, columns of pair kk): J_k^T A J_kk
+      for (int e = tid; e < half * half; e += nt) {
+        const int k = e % half, kk = e / half;
+        const int p = pp[k], q = qq[k], p2 = pp[kk], q2 = qq[kk];
+        const double c = cs[k], s = sn[k], c2 = cs[kk], s2 = sn[kk];
+        const double a = A[p + p2 * L], b = A[p + q2 * L], d = A[q + p2 * L], f = A[q + q2 * L];
+        // rows: [c -s; s c] applied to (row p, row q)
+        const double ra = c * a - s * d, rb = c * b - s * f, rd2 = s * a + c * d, rf = s * b + c * f;
+        // columns: (col p2, col q2) [c2 s2; -s2 c2]
+        A[p + p2 * L] = c2 * ra - s2 * rb;
+        A[p + q2 * L] = s2 * ra + c2 * rb;
+        A[q + p2 * L] = c2 * rd2 - s2 * rf;
+        A[q + q2 * L] = s2 * rd2 + c2 * rf;
       }
-      __syncthreads();
-      // columns p, q of A and V: A J, V J
+      // V J: rows j, columns of pair k
       for (int e = tid; e < half * Np; e += nt) {
-        const int k = e / Np, j = e % Np;
+        const int j = e % Np, k = e / Np;
         const int p = pp[k], q = qq[k];
         const double c = cs[k], s = sn[k];
-        const double a = A[j + p * Np], b = A[j + q * Np];
-        A[j + p * Np] = c * a - s * b;
-        A[j + q * Np] = s * a + c * b;
         const double u = V[j + p * Np], v = V[j + q * Np];
         V[j + p * Np] = c * u - s * v;
         V[j + q * Np] = s * u + c * v;
@@ -282,14 +286,14 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ T, i
       __syncthreads();
     }
   }
-  for (int p = tid; p < N; p += nt) evals[p] = A[p + p * Np];
+  for (int p = tid; p < N; p += nt) evals[p] = A[p + p * L];
   if (tid == 0) {
     int s0 = -1, s1 = -1, s2 = -1;
     for (int p = 0; p < N; ++p) {
-      const double d = A[p + p * Np];
-      if (s0 < 0 || d < A[s0 + s0 * Np]) { s2 = s1; s1 = s0; s0 = p; }
-      else if (s1 < 0 || d < A[s1 + s1 * Np]) { s2 = s1; s1 = p; }
-      else if (s2 < 0 || d < A[s2 + s2 * Np]) { s2 = p; }
+      const double d = A[p + p * L];
+      if (s0 < 0 || d < A[s0 + s0 * L]) { s2 = s1; s1 = s0; s0 = p; }
+      else if (s1 < 0 || d < A[s1 + s1 * L]) { s2 = s1; s1 = p; }
+      else if (s2 < 0 || d < A[s2 + s2 * L]) { s2 = p; }
     }
     sel[0] = s0; sel[1] = s1; sel[2] = s2;
   }
@@ -334,10 +338,12 @@ void launch_lap3(const int64_t* rowptr, const int32_t* colind, int64_t n, const 
 void launch_bdots(const double* Q, int64_t ldq, int ncols, const double* W, int64_t n, double* part,
                   hipStream_t s) {
   const int nchunks = (int)((n + kSpChunk - 1) / kSpChunk);
-  if (nchunks > 0) hipLaunchKernelGGL(k_bdots, dim3(nchunks), dim3(256), 0, s, Q, ldq, ncols, W, n, part);
+  const int ngroups = ((ncols < 0 ? 1 : ncols) + kSpGroup - 1) / kSpGroup;
+  if (nchunks > 0 && ngroups > 0)
+    hipLaunchKernelGGL(k_bdots, dim3(nchunks, ngroups), dim3(256), 0, s, Q, ldq, ncols, W, n, part);
 }
 void launch_bsum(const double* part, int nchunks, int nout, double* out, int ld, int r0, int c0, hipStream_t s) {
-  if (nout > 0) hipLaunchKernelGGL(k_bsum, dim3((nout + 255) / 256), dim3(256), 0, s, part, nchunks, nout, out, ld, r0, c0);
+  if (nout > 0) hipLaunchKernelGGL(k_bsum, dim3((nout + 3) / 4), dim3(256), 0, s, part, nchunks, nout, out, ld, r0, c0);
 }
 void launch_bupd(const double* Q, int64_t ldq, int ncols, const double* C, double* W, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_bupd, dim3(sp_blocks(n)), dim3(256), 0, s, Q, ldq, ncols, C, W, n);
@@ -354,8 +360,8 @@ void launch_bcopy(const double* src, double* dst, int64_t len, double v, bool fi
 }
 void launch_jacobi(const double* T, int N, int ldt, double* V, double* evals, int32_t* sel, hipStream_t s) {
   const int Np = N + (N & 1);
-  const size_t lds = sizeof(double) * (size_t)Np * Np;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), lds, s, T, N, ldt, V, evals, sel);
+  const size_t lds = sizeof(double) * (size_t)Np * (Np + 1);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), lds, s, T, N, ldt, V, evals, sel);
 }
 void launch_ritz(const double* Q, int64_t ldq, int nc, const double* V, int ldv, const int32_t* sel, double* Y,
                  int64_t n, hipStream_t s) {
