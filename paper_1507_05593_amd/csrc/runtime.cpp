@@ -692,19 +692,27 @@ struct Builder {
     const bool fuse = h.opt.gemm_tile != 128;   // (a fixed 128 edge merges the tiles)
     std::vector<char> fused(pan.size(), 0);     // panel's POTRF of this step already placed
     for (int32_t d0 = 0; d0 < maxn; d0 += kTile) {
-      // blocks of at most 32 columns in a launch of the 32-edge kernel, the rest after
+      // blocks of at most 32 columns in a launch of the 32-edge kernel (when there are
+      // enough of them to fill the chip several times), the rest after
+      int64_t nsmall = 0;
+      for (size_t pi = 0; pi < pan.size(); ++pi)
+        if (pan[pi].n > d0 && !fused[pi] && std::min(kTile, pan[pi].n - d0) <= 32) ++nsmall;
+      const bool split = nsmall >= 1024;
       for (int edge : {32, 64}) {
+        if (edge == 32 && !split) continue;
         const int64_t q0 = (int64_t)P.potrf.size();
         double fl = 0;
         for (size_t pi = 0; pi < pan.size(); ++pi) {
           const PanelDesc& p = pan[pi];
           if (p.n <= d0 || fused[pi]) continue;
           const int32_t nb = std::min(kTile, p.n - d0);
-          if ((nb <= 32) != (edge == 32)) continue;
+          if (split && (nb <= 32) != (edge == 32)) continue;
           P.potrf.push_back(potrf_task(p, d0));
           fl += std::pow((double)nb, 3) / 3.0;
         }
-        cmd(kCmdPotrf, RSC_K_POTRF, q0, (int64_t)P.potrf.size() - q0, fl, edge);
+        int32_t nbmax = 0;
+        for (int64_t q = q0; q < (int64_t)P.potrf.size(); ++q) nbmax = std::max(nbmax, P.potrf[q].nb);
+        cmd(kCmdPotrf, RSC_K_POTRF, q0, (int64_t)P.potrf.size() - q0, fl, nbmax <= 32 ? 32 : 64);
       }
       std::fill(fused.begin(), fused.end(), 0);
       // rows below the diagonal block times its inverse, then the trailing update in two
