@@ -19,6 +19,12 @@ Parity status per function (what pins it, see the tests named ``test_oracle_*``)
   transpose): the explicit block product ``L^O_j G`` with ``L^O_j`` formed by the
   triangular solve of Algorithm 1, with explicit and with compressed descendants;
   ``compress_implicit`` reproduces the explicit compression (ranks, ``V_j U_j^T``).
+* ``diagonal`` (§4.1-4.2, §5.3: coordinate split, block tree, Algorithms 4-6): hand-worked
+  splits and tree labels; Algorithm 4 against a dense triangular solve of the written-out
+  tree; full-rank sampling reproduces the dense Cholesky factor; every leaf and low-rank
+  block satisfies the block-Cholesky recurrences of the written-out factor (Schur
+  complement, ``V_s = L(R_s, C_s) U_s``, ``U_s`` orthonormal and spanning the sample);
+  the restart policy on a planted failure.
 * ``philox``: the published known-answer vectors of Philox4x32-10.
 * ``spectral.spectral_coordinates`` (§4.3, block Lanczos on the graph Laplacian): the
   closed-form spectrum and cosine eigenvectors of grid graphs (distinct modes, and the

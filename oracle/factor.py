@@ -51,6 +51,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from .diagonal import HierDiag, diagonal_solve, factor_hierarchical, height, leaf_bounds
 from .ordering import SEPARATOR, Symbolic, symbolic
 from .philox import gaussian_sample
 
@@ -71,6 +72,8 @@ class Options:
     seed: int = 0
     implicit: bool = False   # Algorithm 3 through Algorithm 2 (L^O_j of compressed supernodes never formed)
     keep_lo: bool = False    # explicit path: also keep the dense L^O_j of compressed supernodes (LO_dense)
+    tau_D: int = 0           # largest dense diagonal block (0: no diagonal compression)
+    alpha_D: float = 0.5     # rank constant of the diagonal blocks, raised by 1.25 on failure (§5.3)
 
 
 def sample_count(r: int, c: int, alpha: float, p: int) -> int:
@@ -86,12 +89,26 @@ def compressible(sym: Symbolic, j: int, opts: Options, tol: float) -> bool:
     return (tol > 0 and sym.kind[j] == SEPARATOR and sym.c(j) >= opts.tau_O and sym.r(j) > 0)
 
 
+def hierarchical(sym: Symbolic, j: int, tol: float) -> bool:
+    """Whether ``L^D_j`` is stored as a block tree (§4): rank-structured factor and a
+    diagonal block tree from the symbolic phase."""
+    return tol > 0 and sym.depth is not None and int(sym.depth[j]) > 0
+
+
+def diag_solve(LD, G: np.ndarray, transpose: bool) -> np.ndarray:
+    """``(L^D_j)^{-1} G``, or ``(L^D_j)^{-T} G``: a dense triangular solve, or
+    Algorithm 4 for a block tree."""
+    if isinstance(LD, HierDiag):
+        return diagonal_solve(LD, G, transpose)
+    return sla.solve_triangular(LD, G, lower=True, trans="T" if transpose else "N")
+
+
 @dataclass
 class Factor:
     sym: Symbolic
     tol: float
     opts: Options
-    LD: list = field(default_factory=list)
+    LD: list = field(default_factory=list)     # dense L^D_j, or a HierDiag block tree
     LO: list = field(default_factory=list)     # dense L^O_j, or None when compressed
     V: list = field(default_factory=list)
     U: list = field(default_factory=list)
@@ -100,6 +117,8 @@ class Factor:
     flops: dict = field(default_factory=dict)
     LO_dense: dict = field(default_factory=dict)   # with Options.keep_lo: L^O_j before compression
     Ap: object = None                          # the permuted matrix P A P^T (CSR)
+    alpha_D: float = 0.0                       # the diagonal rank constant that succeeded
+    restarts: int = 0                          # factorizations restarted with a larger alpha_D
 
     def offdiag(self, j):
         """The stored off-diagonal operand ``X`` used by ancestors: ``L^O_j`` or ``V_j``."""
@@ -111,7 +130,7 @@ class Factor:
         L = np.zeros((n, n))
         for j in range(self.sym.M):
             lo, hi = int(self.sym.first[j]), int(self.sym.first[j + 1])
-            L[lo:hi, lo:hi] = self.LD[j]
+            L[lo:hi, lo:hi] = self.LD[j].dense() if isinstance(self.LD[j], HierDiag) else self.LD[j]
             R = self.sym.rows[j]
             if R.size:
                 L[np.ix_(R, np.arange(lo, hi))] = (self.LO[j] if self.LO[j] is not None
@@ -178,7 +197,7 @@ def offdiag_multiply(F: Factor, j: int, G: np.ndarray) -> np.ndarray:
     sym, Ap = F.sym, F.Ap
     lo, hi = int(sym.first[j]), int(sym.first[j + 1])
     R = sym.rows[j]
-    G = sla.solve_triangular(F.LD[j], G, lower=True, trans="T")
+    G = diag_solve(F.LD[j], G, transpose=True)
     W = Ap[R][:, lo:hi] @ G
     for (k, p0, nD) in sym.pairs[j]:
         cols, orow = _pair_rows(sym, j, k, p0, nD)
@@ -200,7 +219,7 @@ def offdiag_multiply_transpose(F: Factor, j: int, G: np.ndarray) -> np.ndarray:
         cols, orow = _pair_rows(sym, j, k, p0, nD)
         if orow.size:
             S[cols] -= _descendant_term(F, k, p0, nD, G[orow], transpose=True)
-    return sla.solve_triangular(F.LD[j], S, lower=True)
+    return diag_solve(F.LD[j], S, transpose=False)
 
 
 def compress_implicit(F: Factor, j: int, opts: Options, tol: float):
@@ -218,11 +237,50 @@ def compress_implicit(F: Factor, j: int, opts: Options, tol: float):
     return Vq, Uq, ell, q
 
 
+def _all_blocks_exact(sym: Symbolic, alpha_D: float, opts: Options) -> bool:
+    """Whether every block of every diagonal block tree is sampled at full rank."""
+    for j in range(sym.M):
+        d = int(sym.depth[j]) if sym.depth is not None else 0
+        if d == 0:
+            continue
+        b = leaf_bounds(sym.c(j), d)
+        H = HierDiag(c=sym.c(j), d=d, bounds=b)
+        for s in range(2, H.nblocks + 1, 2):
+            (ca, cb), (ra, rb) = H.cols(s), H.rows(s)
+            if sample_count(rb - ra, cb - ca, alpha_D, opts.oversample) < min(rb - ra, cb - ca):
+                return False
+    return True
+
+
 def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
            opts: Options | None = None, stop_after: int | None = None, progress=None) -> Factor:
     """Factor supernodes ``0 .. M-1`` (or the first ``stop_after``) in order.
-    ``progress(j, M)``, if given, is called after each supernode (reporting only)."""
+    ``progress(j, M)``, if given, is called after each supernode (reporting only).
+
+    With diagonal block trees the factorization may meet a Schur complement that is
+    not positive definite; it then restarts with ``alpha_D`` multiplied by 1.25
+    (§5.3), until it succeeds or every diagonal block is already sampled at full rank
+    (then the factor is exact in those blocks and the failure is the matrix's)."""
     opts = opts or Options()
+    use_tree = any(hierarchical(sym, j, tol) for j in range(sym.M))
+    alpha = opts.alpha_D
+    restarts = 0
+    while True:
+        try:
+            F = _factor_once(sym, n, rowptr, colind, values, tol, opts, alpha, stop_after, progress)
+        except NotSPDError:
+            if not use_tree or _all_blocks_exact(sym, alpha, opts):
+                raise
+            alpha *= 1.25
+            restarts += 1
+            continue
+        F.alpha_D = alpha if use_tree else 0.0
+        F.restarts = restarts
+        return F
+
+
+def _factor_once(sym: Symbolic, n, rowptr, colind, values, tol, opts, alpha_D, stop_after,
+                 progress) -> Factor:
     Ap = permuted_matrix(sym, n, rowptr, colind, values)
     F = Factor(sym=sym, tol=tol, opts=opts, Ap=Ap)
     M = sym.M if stop_after is None else min(sym.M, stop_after)
@@ -233,8 +291,9 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
         R = sym.rows[j]
         comp = compressible(sym, j, opts, tol)
         implicit = comp and opts.implicit   # the off-diagonal block is only used through Algorithm 2
+        tree = hierarchical(sym, j, tol)    # L^D_j by Algorithms 4-6 (its leaves form their own Schur blocks)
         # Initialise the Schur complement blocks (Algorithm 1)
-        UD = Ap[lo:hi][:, lo:hi].toarray()
+        UD = Ap[lo:hi][:, lo:hi].toarray() if not tree else None
         UO = Ap[R][:, lo:hi].toarray() if (R.size and not implicit) else np.zeros((0, c))
         for (k, p0, nD) in sym.pairs[j]:
             X = F.offdiag(k)[p0:]
@@ -242,17 +301,25 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
             Rk = sym.rows[k]
             cols = Rk[p0:p0 + nD] - lo                       # R^D_{k->j} within C_j
             orow = np.searchsorted(R, Rk[p0 + nD:])          # R^O_{k->j} within R_j
-            UD[np.ix_(cols, cols)] -= XD @ XD.T
+            if not tree:
+                UD[np.ix_(cols, cols)] -= XD @ XD.T
             if orow.size and not implicit:
                 UO[np.ix_(orow, cols)] -= X[nD:] @ XD.T
             fl["update"] += 2.0 * X.shape[1] * (nD * (nD + 1) / 2.0 + float(X.shape[0] - nD) * nD)
-        try:
-            LD = np.linalg.cholesky(UD)
-        except np.linalg.LinAlgError:
-            raise NotSPDError(j) from None
-        if not np.all(np.isfinite(LD)):
-            raise NotSPDError(j)
-        LO = (sla.solve_triangular(LD, UO.T, lower=True).T if (R.size and not implicit)
+        if tree:
+            d = int(sym.depth[j])
+            try:
+                LD = factor_hierarchical(F, j, leaf_bounds(c, d), d, alpha_D, opts, j)
+            except np.linalg.LinAlgError:
+                raise NotSPDError(j) from None
+        else:
+            try:
+                LD = np.linalg.cholesky(UD)
+            except np.linalg.LinAlgError:
+                raise NotSPDError(j) from None
+            if not np.all(np.isfinite(LD)):
+                raise NotSPDError(j)
+        LO = (diag_solve(LD, UO.T, transpose=False).T if (R.size and not implicit)
               else np.zeros((0, c)))
         fl["potrf"] += c ** 3 / 3.0
         if not implicit:
@@ -277,7 +344,7 @@ def factor(sym: Symbolic, n, rowptr, colind, values, tol: float = 0.0,
     return F
 
 
-def analyze_and_factor(n, rowptr, colind, values, tol=0.0, opts: Options | None = None):
+def analyze_and_factor(n, rowptr, colind, values, tol=0.0, opts: Options | None = None, coords=None):
     opts = opts or Options()
-    sym = symbolic(n, rowptr, colind, opts.leaf_max)
+    sym = symbolic(n, rowptr, colind, opts.leaf_max, opts.tau_D, coords)
     return factor(sym, n, rowptr, colind, values, tol, opts)

@@ -35,6 +35,11 @@ What is computed
   ``min R_j``; ``level = 0`` for a supernode without children, else
   ``1 + max(child levels)``.
 
+* Diagonal block trees (§4.1, ``oracle.diagonal``): with ``tau_D > 0`` a separator
+  of more than ``tau_D`` columns gets the depth of its complete block tree and, when
+  positions are given, its columns are reordered by the recursive coordinate split.
+  Reordering inside a supernode leaves its pattern unchanged.
+
 * Descendant pairs (paper §2.1, descendant set and the row lists ``R^D_{k->j}``,
   ``R^O_{k->j}``): for each ``k`` the rows of ``R_k`` fall into runs owned by
   ancestors ``j``; for each run, ``p0`` is its first position in ``R_k`` and
@@ -188,6 +193,7 @@ class Symbolic:
     level: np.ndarray
     owner: np.ndarray       # new index -> supernode
     pairs: list             # per target j: list of (k, p0, nD) in ascending k
+    depth: np.ndarray = None   # per supernode: depth of its diagonal block tree (0: dense)
 
     @property
     def M(self):
@@ -200,9 +206,22 @@ class Symbolic:
         return int(self.rows[j].size)
 
 
-def symbolic(n, rowptr, colind, leaf_max: int = 64) -> Symbolic:
+def symbolic(n, rowptr, colind, leaf_max: int = 64, tau_D: int = 0, coords=None) -> Symbolic:
+    """Ordering and symbolic analysis.  With ``tau_D > 0`` every separator of more than
+    ``tau_D`` columns gets a diagonal block tree (§4.1); with ``coords`` (``n x 3``
+    positions of the original indices) its columns are first reordered by the
+    recursive coordinate split of that tree."""
+    from .diagonal import coordinate_order, split_depth
     check_pattern(n, rowptr, colind)
     perm, first, kind = nested_dissection(n, rowptr, colind, leaf_max)
+    depth = np.zeros(first.size - 1, dtype=np.int64)
+    for j in range(first.size - 1):
+        lo, hi = int(first[j]), int(first[j + 1])
+        if kind[j] == SEPARATOR and tau_D > 0 and hi - lo > tau_D:
+            depth[j] = split_depth(hi - lo, tau_D)
+            if coords is not None:
+                xyz = np.asarray(coords, dtype=np.float64)[perm[lo:hi]]
+                perm[lo:hi] = perm[lo:hi][coordinate_order(xyz, int(depth[j]))]
     iperm = np.empty(n, dtype=np.int64)
     iperm[perm] = np.arange(n)
     M = first.size - 1
@@ -237,7 +256,7 @@ def symbolic(n, rowptr, colind, leaf_max: int = 64) -> Symbolic:
         for s, e in zip(starts, ends):
             pairs[int(own[s])].append((k, int(s), int(e - s)))
     return Symbolic(n=n, perm=perm, iperm=iperm, first=first, kind=kind, rows=rows,
-                    parent=parent, level=level, owner=owner, pairs=pairs)
+                    parent=parent, level=level, owner=owner, pairs=pairs, depth=depth)
 
 
 def scatter_rows(B, R1, R2):

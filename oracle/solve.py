@@ -22,7 +22,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .factor import Factor
+from .factor import Factor, diag_solve
 
 
 def apply_preconditioner(F: Factor, r: np.ndarray) -> np.ndarray:
@@ -30,7 +30,7 @@ def apply_preconditioner(F: Factor, r: np.ndarray) -> np.ndarray:
     y = np.asarray(r, dtype=np.float64)[sym.perm].copy()
     for j in range(sym.M):
         lo, hi = int(sym.first[j]), int(sym.first[j + 1])
-        y[lo:hi] = sla.solve_triangular(F.LD[j], y[lo:hi], lower=True)
+        y[lo:hi] = diag_solve(F.LD[j], y[lo:hi], transpose=False)
         R = sym.rows[j]
         if R.size:
             if F.LO[j] is not None:
@@ -46,7 +46,7 @@ def apply_preconditioner(F: Factor, r: np.ndarray) -> np.ndarray:
                 w -= F.LO[j].T @ y[R]
             else:
                 w -= F.U[j] @ (F.V[j].T @ y[R])
-        y[lo:hi] = sla.solve_triangular(F.LD[j], w, lower=True, trans="T")
+        y[lo:hi] = diag_solve(F.LD[j], w, transpose=True)
     z = np.empty_like(y)
     z[sym.perm] = y
     return z

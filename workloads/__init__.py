@@ -9,6 +9,7 @@ the solver's arithmetic: no ordering, no factorization, no Krylov iteration.
 from .grids import (  # noqa: F401
     GridProblem,
     grid_problem,
+    grid_coordinates,
     batched_problems,
     workload_config,
     WORKLOADS,

@@ -121,6 +121,19 @@ def _build_pattern(dims):
     return N, rowptr, colind, value_map, value_const, face_i, face_j
 
 
+def grid_coordinates(dims) -> np.ndarray:
+    """Positions of the unknowns (``N x 3`` FP64, the cell's integer grid coordinates,
+    zero beyond the grid's dimension), in the unknowns' lexicographic numbering."""
+    dims = tuple(int(x) for x in dims)
+    N = int(np.prod(dims))
+    strides = _strides(dims)
+    cells = np.arange(N, dtype=np.int64)
+    xyz = np.zeros((N, 3))
+    for d in range(len(dims)):
+        xyz[:, d] = (cells // strides[d]) % dims[d]
+    return xyz
+
+
 def grid_problem(dims, sigma: float = 0.0, seed: int = 0, unit: bool = False) -> GridProblem:
     """One seeded diffusion problem; ``unit=True`` sets every coefficient to 1."""
     dims = tuple(int(x) for x in dims)
