@@ -83,6 +83,17 @@ typedef struct {
                           R_j) as one launch per sweep, one workgroup per supernode; the lowest
                           such levels only, up to the first level that exceeds the bound; at
                           most 1024, 0 = every level by the per-operation launches (64) */
+  int32_t tau_D;       /* largest dense diagonal block (Sec. 4.1): in the rank-structured factor a
+                          separator of more than tau_D columns stores L^D_j as a complete block
+                          tree of depth ceil(log2(c / tau_D)) -- dense leaves of at most tau_D
+                          columns, the blocks between them low rank (Sec. 4.2, Algorithms 4-6);
+                          0 = every L^D_j dense; 1 is refused (0) */
+  int32_t reserved0;
+  double alpha_D;      /* alpha of the rank function of Sec. 5.2 for the blocks of a block tree:
+                          each is sampled at min(k, ceil(alpha_D sqrt(k) log2 k) + oversample),
+                          k = min(rows, cols), and kept at that rank; an indefinite pivot makes
+                          rsc_factor restart with alpha_D x 1.25 (Sec. 5.3) until it succeeds or
+                          every block is sampled at full rank (0.5) */
 } rsc_options;
 
 typedef struct {
@@ -112,6 +123,13 @@ typedef struct {
   int64_t gemm_tuned;          /* product launches of the current factor plan timed by the tile
                                   tuner (gemm_tile = 0) */
   int64_t gemm_tile128;        /* of those, launches that run with 128-wide tiles */
+  int64_t tree_supernodes;     /* supernodes whose L^D_j is a block tree (Sec. 4), last factor */
+  int64_t tree_blocks;         /* their low-rank blocks */
+  int64_t tree_rank_sum;       /* the sum of those blocks' ranks */
+  int64_t tree_entries;        /* stored entries of the trees: leaf triangles and V_s, U_s */
+  double alpha_D_used;         /* the diagonal rank constant of the last factor */
+  int32_t diag_restarts;       /* restarts of the last rsc_factor with a larger alpha_D */
+  int32_t reserved1;
 } rsc_stats;
 
 /* Kernel-class timing (hipEvents around every launch of a class while enabled).  Classes
@@ -150,6 +168,18 @@ void rsc_default_options(rsc_options* opt);
  * Errors: RSC_ERR_INVALID_ARG, RSC_ERR_PATTERN, RSC_ERR_OUT_OF_MEMORY. */
 rsc_status rsc_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
                        const rsc_options* opt, rsc_handle* out);
+
+/* rsc_analyze with positions of the indices (Sec. 4.1, 4.3): xyz is host memory,
+ * double[3 n] (x, y, z of original index i at 3i .. 3i+2; a two-dimensional problem
+ * passes z = 0), borrowed for the call.  With opt->tau_D > 0 the columns of every
+ * separator of more than tau_D columns are reordered by the recursive split of their
+ * positions along the longest side of each piece's bounding box (a stable sort, the
+ * first of equal sides, first half m / 2) into the leaves of its block tree; the
+ * supernode's pattern is unchanged.  Positions may come from the mesh or from
+ * rsc_spectral_coordinates.  Errors as rsc_analyze, and RSC_ERR_INVALID_ARG for a
+ * null xyz or a non-finite position. */
+rsc_status rsc_analyze_coords(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                              const double* xyz, const rsc_options* opt, rsc_handle* out);
 
 /* Symbolic phase for `count` independent systems factored together: the systems
  * form one block-diagonal matrix (system i's unknowns follow system i-1's), so
@@ -237,6 +267,10 @@ rsc_status rsc_get_permutation(rsc_handle h, int64_t* perm);
 /* first: int64[M+1] column boundaries; parent, level, kind (0 leaf, 1 separator): int32[M]. */
 rsc_status rsc_get_supernodes(rsc_handle h, int64_t* first, int32_t* parent, int32_t* level,
                               int32_t* kind);
+/* depth: int32[M], the depth d of each supernode's diagonal block tree (Sec. 4.1; 0 for a
+ * dense L^D_j): 2^d leaves from halving its c columns (first half m / 2), used by the
+ * rank-structured factor. */
+rsc_status rsc_get_tree_depths(rsc_handle h, int32_t* depth);
 /* rowptr: int64[M+1]; rows: int64[rowptr[M]]: the sorted off-diagonal rows R_j. */
 rsc_status rsc_get_rowsets(rsc_handle h, int64_t* rowptr, int64_t* rows);
 /* After rsc_factor: samples l_j and kept ranks q_j (0 for uncompressed), int32[M]. */

@@ -31,7 +31,8 @@ class Options(C.Structure):
                 ("power_iters", C.c_int32), ("alpha_O", C.c_double), ("seed", C.c_uint64),
                 ("precision", C.c_int32), ("use_graph", C.c_int32), ("retry", C.c_int32),
                 ("gemm_tile", C.c_int32), ("keep_lo", C.c_int32),
-                ("sweep_small_c", C.c_int32)]
+                ("sweep_small_c", C.c_int32), ("tau_D", C.c_int32), ("reserved0", C.c_int32),
+                ("alpha_D", C.c_double)]
 
 
 class PcgResult(C.Structure):
@@ -48,7 +49,9 @@ class Stats(C.Structure):
                 ("flops_update", C.c_double), ("flops_sample", C.c_double), ("flops_orth", C.c_double),
                 ("flops_trunc", C.c_double), ("bytes_factor", C.c_double), ("t_analyze_ms", C.c_double),
                 ("t_factor_ms", C.c_double), ("t_pcg_ms", C.c_double), ("device_bytes", C.c_double),
-                ("gemm_tuned", C.c_int64), ("gemm_tile128", C.c_int64)]
+                ("gemm_tuned", C.c_int64), ("gemm_tile128", C.c_int64), ("tree_supernodes", C.c_int64),
+                ("tree_blocks", C.c_int64), ("tree_rank_sum", C.c_int64), ("tree_entries", C.c_int64),
+                ("alpha_D_used", C.c_double), ("diag_restarts", C.c_int32), ("reserved1", C.c_int32)]
 
 
 ARITHS = ("f64", "f32", "bf16")
@@ -73,6 +76,9 @@ _lib = None
 SYMBOLS = {
     "rsc_default_options": (None, [C.POINTER(Options)]),
     "rsc_analyze": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "rsc_get_tree_depths": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "rsc_analyze_coords": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Options),
+                                     C.POINTER(C.c_void_p)]),
     "rsc_analyze_batch": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Options),
                                     C.POINTER(C.c_void_p)]),
     "rsc_factor": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),

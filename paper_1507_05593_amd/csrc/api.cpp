@@ -39,13 +39,14 @@ rsc_status check_options(const rsc_options& o) {
   if (o.leaf_max < 1 || o.tau_O < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.alpha_O > 0) ||
       o.precision < RSC_FP64 || o.precision > RSC_MIXED_FP32 ||
       (o.gemm_tile != 0 && o.gemm_tile != 64 && o.gemm_tile != 128) || o.sweep_small_c < 0 ||
-      o.sweep_small_c > 1024)
+      o.sweep_small_c > 1024 || o.tau_D < 0 || o.tau_D == 1 || !(o.alpha_D > 0) || !(o.alpha_D < 1e6))
     return fail(RSC_ERR_INVALID_ARG, "option out of range");
   return RSC_OK;
 }
 
 rsc_status analyze_impl(int32_t count, const int64_t* n, const int64_t* const* rowptr,
-                        const int32_t* const* colind, const rsc_options* opt, rsc_handle* out) {
+                        const int32_t* const* colind, const double* xyz, const rsc_options* opt,
+                        rsc_handle* out) {
   if (!out || count < 1 || !n || !rowptr || !colind) return fail(RSC_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
   rsc_options o;
@@ -89,7 +90,13 @@ rsc_status analyze_impl(int32_t count, const int64_t* n, const int64_t* const* r
       base += n[s];
       h.seg_first.push_back(base);
     }
-    rsc::build_symbolic(total, h.rowptr.data(), h.colind.data(), o.leaf_max, h.S);
+    if (xyz)
+      for (int64_t i = 0; i < 3 * total; ++i)
+        if (!std::isfinite(xyz[i])) {
+          delete H;
+          return fail(RSC_ERR_INVALID_ARG, "non-finite position of index " + std::to_string(i / 3));
+        }
+    rsc::build_symbolic(total, h.rowptr.data(), h.colind.data(), o.leaf_max, o.tau_D, xyz, h.S);
     h.S.systems = count;
     h.S.sys_first = h.seg_first;
     rsc::plan_layout(h);
@@ -123,16 +130,27 @@ void rsc_default_options(rsc_options* o) {
   o->use_graph = 1;
   o->retry = 1;
   o->sweep_small_c = 64;
+  o->tau_D = 0;
+  o->alpha_D = 0.5;
 }
 
 rsc_status rsc_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
                        const rsc_options* opt, rsc_handle* out) {
-  return analyze_impl(1, &n, &rowptr, &colind, opt, out);
+  return analyze_impl(1, &n, &rowptr, &colind, nullptr, opt, out);
+}
+
+rsc_status rsc_analyze_coords(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                              const double* xyz, const rsc_options* opt, rsc_handle* out) {
+  if (!xyz && n > 0) {
+    if (out) *out = nullptr;
+    return fail(RSC_ERR_INVALID_ARG, "null positions");
+  }
+  return analyze_impl(1, &n, &rowptr, &colind, xyz, opt, out);
 }
 
 rsc_status rsc_analyze_batch(int32_t count, const int64_t* n, const int64_t* const* rowptr,
                              const int32_t* const* colind, const rsc_options* opt, rsc_handle* out) {
-  return analyze_impl(count, n, rowptr, colind, opt, out);
+  return analyze_impl(count, n, rowptr, colind, nullptr, opt, out);
 }
 
 rsc_status rsc_factor(rsc_handle H, const double* values, double tol, void* stream) {
@@ -271,6 +289,13 @@ rsc_status rsc_get_block(rsc_handle H, int64_t j, double* LD, double* LO, double
   return RSC_OK;
 }
 
+rsc_status rsc_get_tree_depths(rsc_handle H, int32_t* depth) {
+  if (!H || !depth) return fail(RSC_ERR_INVALID_ARG, "null argument");
+  const rsc::Symbolic& S = H->h.S;
+  for (int64_t j = 0; j < S.M(); ++j) depth[j] = S.depth[j];
+  return RSC_OK;
+}
+
 rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
   if (!H || !out) return fail(RSC_ERR_INVALID_ARG, "null argument");
   rsc::Handle& h = H->h;
@@ -300,9 +325,25 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
     return fail(RSC_ERR_DEVICE, "copy of ranks");
   int64_t entries = 0;
   double fl_update = 0;
+  const bool tree = comp && h.fplan->alpha_D > 0;
   for (int64_t j = 0; j < S.M(); ++j) {
     const int64_t c = S.c(j), r = S.r(j);
-    entries += c * (c + 1) / 2;
+    if (tree && !h.tree[j].empty()) {
+      // the block tree's storage: leaf triangles and every block's V_s, U_s
+      int64_t te = 0;
+      out->tree_supernodes++;
+      for (const rsc::TreeNode& t : h.tree[j]) {
+        const int64_t nc = t.cb - t.ca, nr = t.rb - t.ra;
+        if (t.ht == 0) { te += nc * (nc + 1) / 2; continue; }
+        out->tree_blocks++;
+        out->tree_rank_sum += t.ell;
+        te += (nr + nc) * t.ell;
+      }
+      out->tree_entries += te;
+      entries += te;
+    } else {
+      entries += c * (c + 1) / 2;
+    }
     if (comp && h.compressible[j]) {
       out->compressed++;
       out->rank_sum += q[j];
@@ -328,7 +369,9 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
       for (int64_t j = 0; j < S.M(); ++j)
         if (h.compressible[j]) out->flops_trunc += 2.0 * (S.c(j) + S.r(j)) * (double)h.comp[j].ell * q[j];
   }
-  out->flops_update = fl_update;
+  out->flops_update = fl_update + (h.fplan ? h.fplan->flops[2] : 0.0);
+  out->alpha_D_used = tree ? h.fplan->alpha_D : 0.0;
+  out->diag_restarts = h.diag_restarts;
   out->bytes_factor = h.splan ? h.splan->bytes * (h.f32_valid ? 0.5 : 1.0) : 0.0;
   return RSC_OK;
 }

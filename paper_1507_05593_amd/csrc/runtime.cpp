@@ -194,6 +194,7 @@ void plan_layout(Handle& h) {
   h.lev_uo_rel.assign(S.nlevels, {0, 0});
   h.comp_rel = h.comp;
   int64_t pool_exact = 0, pool_comp = 0;
+  h.lev_pool_comp.assign(S.nlevels, 0);
   for (int32_t L = 0; L < S.nlevels; ++L) {
     int64_t p = 0;
     for (int32_t j : S.by_level[L])
@@ -225,10 +226,12 @@ void plan_layout(Handle& h) {
         C.zdinv = p; p += ((l + 63) / 64) * 4096;
       }
     }
+    h.lev_pool_comp[L] = p;
     pool_comp = std::max(pool_comp, p);
   }
   h.arena_size_exact = align64(h.pool_base_exact + pool_exact);
-  h.arena_size_comp = align64(h.pool_base_comp + pool_comp);
+  h.pool_comp_plain = pool_comp;
+  plan_trees(h, h.opt.alpha_D);
   h.lo_off = h.lo_off_exact;
   h.a_pool = -1;
   set_layout(h, false);
@@ -275,6 +278,79 @@ void plan_layout(Handle& h) {
     const int64_t c = S.c(j);
     for (int64_t t = 0; t < c; ++t) h.ident_slot.push_back(h.panel_off[j] + t * h.panel_ld[j] + (c + t));
   }
+}
+
+// Diagonal block trees (Sec. 4.1-4.2): a supernode with tree depth d > 0 splits its c
+// columns into 2^d leaves by halving (first half m / 2); the blocks are numbered in order
+// (leaves odd, the root 2^d).  Each level's trees take work space after that level's
+// rank-structured pool: a leaf its panel steps' inverse blocks; an internal block its
+// sample, the intermediate of its products, the orthonormalisation panel [Gram; Y], the
+// kept W = M_{s1} U_s, V_s and X = M_{s2}^T V_s.
+void plan_trees(Handle& h, double alpha_D) {
+  const Symbolic& S = h.S;
+  h.tree.assign(S.M(), {});
+  h.tree_alpha = alpha_D;
+  const int64_t base = h.pool_base_comp;
+  int64_t pool = h.pool_comp_plain;
+  for (int32_t L = 0; L < S.nlevels; ++L) {
+    int64_t p = h.lev_pool_comp[L];
+    for (int32_t j : S.by_level[L]) {
+      const int32_t d = S.depth[j];
+      if (d == 0) continue;
+      const int32_t c = S.c(j), nleaf = 1 << d;
+      std::vector<int32_t> bnd;
+      std::function<void(int32_t, int32_t, int32_t)> split = [&](int32_t lo, int32_t m, int32_t dep) {
+        if (dep == 0) { bnd.push_back(lo); return; }
+        split(lo, m / 2, dep - 1);
+        split(lo + m / 2, m - m / 2, dep - 1);
+      };
+      split(0, c, d);
+      bnd.push_back(c);
+      std::vector<TreeNode>& T = h.tree[j];
+      T.resize(2 * nleaf - 1);
+      for (int32_t s = 1; s < 2 * nleaf; ++s) {
+        TreeNode& t = T[s - 1];
+        t.s = s;
+        t.ht = __builtin_ctz(s);
+        auto span = [&](int32_t u, int32_t hu, int32_t& a, int32_t& b) {
+          const int32_t f = (u - ((1 << hu) - 1)) / 2;
+          a = bnd[f]; b = bnd[f + (1 << hu)];
+        };
+        if (t.ht == 0) {
+          span(s, 0, t.ca, t.cb);
+          t.ra = t.ca; t.rb = t.cb;
+          t.dinv = base + p; p += ((t.cb - t.ca + 63) / 64) * 4096;
+          continue;
+        }
+        span(s - (1 << (t.ht - 1)), t.ht - 1, t.ca, t.cb);
+        span(s + (1 << (t.ht - 1)), t.ht - 1, t.ra, t.rb);
+        const int64_t nc = t.cb - t.ca, nr = t.rb - t.ra;
+        t.ell = std::min<int32_t>(sample_count((int32_t)nr, (int32_t)nc, alpha_D, h.opt.oversample), 2048);
+        const int64_t l = t.ell;
+        t.omega = base + p; p += align64(nr * l);
+        t.tmp = base + p; p += align64(std::max(nc, nr) * l);
+        t.ypanel = base + p; p += align64((l + nc) * l);
+        t.dinv = base + p; p += ((l + 63) / 64) * 4096;
+        t.W = base + p; p += align64(nc * l);
+        t.V = base + p; p += align64(nr * l);
+        t.X = base + p; p += align64(nr * l);
+        t.gscale = base + p; p += 64;
+        if (h.opt.power_iters > 0) {
+          t.zpanel = base + p; p += align64((l + nr) * l);
+          t.zdinv = base + p; p += ((l + 63) / 64) * 4096;
+        }
+      }
+    }
+    pool = std::max(pool, p);
+  }
+  h.arena_size_comp = align64(h.pool_base_comp + pool);
+}
+
+bool trees_exact(const Handle& h) {
+  for (const auto& T : h.tree)
+    for (const TreeNode& t : T)
+      if (t.ht > 0 && t.ell < std::min(t.cb - t.ca, t.rb - t.ra)) return false;
+  return true;
 }
 
 // Pool offsets of one layout (exact or compressed factor): the pool-relative tables plus
@@ -1000,24 +1076,35 @@ struct Builder {
   // panel [Gram; Y], or with zp the power iteration's Z = L^O Y, rows [l, l + r) of its
   // panel): Gram = Y^T Y (lower tiles), the drop scale (and with shifted, the shift of
   // shifted Cholesky-QR), then the blocked panel factorisation, which leaves Y R^{-1}.
-  void cholqr_pass(const std::vector<int32_t>& js, bool zp, bool shifted) {
-    const Symbolic& S = h.S;
+  // One Cholesky-QR pass over panels [Gram (l x l); Y (m x l)] (ld l + m): the Gram
+  // matrix Y^T Y, its diagonal scaling (and shift), then the panel factorisation whose
+  // rows below turn Y into Y R^{-1} (dependent columns dropped).
+  struct QRPanel { int64_t pnl; int32_t l, m; int64_t dinv; int32_t sn; int64_t sc; };
+  void cholqr(const std::vector<QRPanel>& qs, bool shifted) {
     const int64_t g0 = (int64_t)P.gemm.size();
     double fl = 0;
     const int64_t s0 = (int64_t)P.gs_g.size();
     std::vector<PanelDesc> pan;
-    for (int32_t j : js) {
-      const CompSlot& C = h.comp[j];
-      const int32_t l = C.ell, m = zp ? S.r(j) : S.c(j), ld = l + m;
-      const int64_t pnl = zp ? C.zpanel : C.ypanel, sc = zp ? C.gscale + 1 : C.gscale;
-      fl += tiles(gt(pnl + l, ld, 1, pnl + l, ld, 1, pnl, ld, l, l, m, 1.0, 0.0), 0, 0, true);
-      P.gs_g.push_back(pnl); P.gs_ld.push_back(ld); P.gs_n.push_back(l); P.gs_out.push_back(sc);
+    for (const QRPanel& q : qs) {
+      const int32_t l = q.l, m = q.m, ld = l + m;
+      fl += tiles(gt(q.pnl + l, ld, 1, q.pnl + l, ld, 1, q.pnl, ld, l, l, m, 1.0, 0.0), 0, 0, true);
+      P.gs_g.push_back(q.pnl); P.gs_ld.push_back(ld); P.gs_n.push_back(l); P.gs_out.push_back(q.sc);
       P.gs_m.push_back(shifted ? m : 0);
-      pan.push_back(PanelDesc{pnl, ld, l, m, false, zp ? C.zdinv : C.ydinv, j, 1, sc});
+      pan.push_back(PanelDesc{q.pnl, ld, l, m, false, q.dinv, q.sn, 1, q.sc});
     }
     cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, fl);
     cmd(kCmdGramScale, RSC_K_OTHER, s0, (int64_t)P.gs_g.size() - s0, 0);
     panel_steps(pan);
+  }
+  void cholqr_pass(const std::vector<int32_t>& js, bool zp, bool shifted) {
+    const Symbolic& S = h.S;
+    std::vector<QRPanel> qs;
+    for (int32_t j : js) {
+      const CompSlot& C = h.comp[j];
+      qs.push_back(QRPanel{zp ? C.zpanel : C.ypanel, C.ell, zp ? S.r(j) : S.c(j), zp ? C.zdinv : C.ydinv,
+                           j, zp ? C.gscale + 1 : C.gscale});
+    }
+    cholqr(qs, shifted);
   }
 
   // Algorithm 2 on the device.  Its descendant terms, summed over k, are the rows R_j of
@@ -1345,6 +1432,188 @@ struct Builder {
     for (size_t i = cs; i < P.cmds.size(); ++i) { P.cmds[i].mflops = P.cmds[i].flops; P.cmds[i].mkind = 2; }
     ctx = -1;
   }
+
+  // Sec. 4.2 for the block-tree supernodes of one level: every block of each tree in
+  // order, right-looking on the dense Schur block that the level's Schur update left in
+  // the panel (A(C_j, C_j) minus every descendant's term: the first terms of Algorithms
+  // 5 and 6, subtracted once for all blocks):
+  //  * leaf (Algorithm 6): the panel factorisation of its diagonal block alone, the rows
+  //    below it untouched, its inverse into its rows of M_j (which start as I);
+  //  * internal block s: Algorithm 3 on L(R_s, C_s) = S(R_s, C_s) M_{s1}, M_{s1} the left
+  //    subtree's (finished) part of M_j = (L^D_j)^{-T} -- Algorithm 4 as a product with
+  //    that explicit inverse -- at the fixed rank l_s (shifted Cholesky-QR3, no
+  //    truncation); then S(R_s, R_s) -= V_s V_s^T (every later block's term from block s,
+  //    Algorithms 5 and 6's loop over earlier blocks) and V_s U_s^T written over
+  //    S(R_s, C_s), so that the panel holds the block tree's L^D_j;
+  //  * once both subtrees of block t are done, M_j's coupling block
+  //    M(C_t, R_t) = -(M_{t1} U_t) (M_{t2}^T V_t)^T (the inverse of the 2 x 2 block
+  //    triangle), bottom-up, so that M_{s1} is whole before block s needs it.
+  // The supernodes of one tree depth run in the same launches.
+  void diag_trees(const std::vector<int32_t>& js) {
+    const Symbolic& S = h.S;
+    std::map<int32_t, std::vector<int32_t>> by_d;
+    for (int32_t j : js) by_d[S.depth[j]].push_back(j);
+    const size_t c_first = P.cmds.size();
+    for (auto& kv : by_d) {
+      const int32_t d = kv.first;
+      const std::vector<int32_t>& g = kv.second;
+      auto node = [&](int32_t j, int32_t s) -> const TreeNode& { return h.tree[j][s - 1]; };
+      // tasks of dst = M(a:a+n, a:a+n) src or its transpose times src (n x l operands)
+      auto tri = [&](int32_t j, bool trans, int32_t a, int32_t n, int32_t l, int64_t src, int32_t sld,
+                     int64_t dst, int32_t dld) {
+        const int32_t ldp = h.panel_ld[j];
+        const int64_t M0 = h.panel_off[j] + S.c(j) + a + (int64_t)a * ldp;
+        double f = 0;
+        for (int32_t j0 = 0; j0 < l; j0 += kTile)
+          for (int32_t i0 = 0; i0 < n; i0 += kTile) {
+            GemmTask t = trans ? gt(M0, ldp, 1, src, sld, 1, dst, dld, n, l, std::min(n, i0 + kTile), 1.0, 0.0)
+                               : gt(M0 + (int64_t)i0 * ldp, 1, ldp, src + i0, sld, 1, dst, dld, n, l, n - i0, 1.0, 0.0);
+            t.i0 = i0; t.j0 = j0;
+            P.gemm.push_back(t);
+            f += 2.0 * std::min(kTile, n - i0) * std::min(kTile, l - j0) * (double)t.k;
+          }
+        return f;
+      };
+      auto launch = [&](int mode, const std::function<double(int32_t)>& push) {
+        const int64_t g0 = (int64_t)P.gemm.size();
+        double f = 0;
+        for (int32_t j : g) f += push(j);
+        cmd(kCmdGemm, RSC_K_GEMM, g0, (int64_t)P.gemm.size() - g0, f, mode);
+      };
+      auto SRC = [&](int32_t j, const TreeNode& n) {   // S(R_s, C_s) in the panel (ld 2c)
+        return h.panel_off[j] + n.ra + (int64_t)n.ca * h.panel_ld[j];
+      };
+      auto assemble = [&](int32_t t) {
+        ctx = RSC_K_TRSM;
+        launch(lp_eig, [&](int32_t j) {          // X = M(R, R)^T V
+          const TreeNode& n = node(j, t);
+          const int32_t nr = n.rb - n.ra;
+          return tri(j, true, n.ra, nr, n.ell, n.V, nr, n.X, nr);
+        });
+        launch(lp_eig, [&](int32_t j) {          // M(C, R) = -W X^T
+          const TreeNode& n = node(j, t);
+          const int32_t nc = n.cb - n.ca, nr = n.rb - n.ra, ldp = h.panel_ld[j];
+          return tiles(gt(n.W, 1, nc, n.X, 1, nr, h.panel_off[j] + S.c(j) + n.ca + (int64_t)n.ra * ldp,
+                          ldp, nc, nr, n.ell, -1.0, 0.0), 0, 0, false);
+        });
+        ctx = -1;
+      };
+      auto qr = [&](bool z, bool shifted) {
+        std::vector<QRPanel> qs;
+        for (int32_t j : g) {
+          // (one tree's blocks run one after another, so they share the scale slot)
+          const TreeNode& n = node(j, cur_s);
+          qs.push_back(z ? QRPanel{n.zpanel, n.ell, n.rb - n.ra, n.zdinv, j, n.gscale + 1}
+                         : QRPanel{n.ypanel, n.ell, n.cb - n.ca, n.dinv, j, n.gscale});
+        }
+        cholqr(qs, shifted);
+      };
+      const int32_t nb = (2 << d) - 1;
+      for (int32_t s = 1; s <= nb; ++s) {
+        cur_s = s;
+        const int32_t ht = __builtin_ctz(s);
+        if (ht == 0) {
+          std::vector<PanelDesc> pan;
+          for (int32_t j : g) {
+            const TreeNode& n = node(j, s);
+            const int32_t nn = n.cb - n.ca, c = S.c(j), ld = h.panel_ld[j];
+            PanelDesc p{h.panel_off[j] + n.ca + (int64_t)n.ca * ld, ld, nn, c - nn, true, n.dinv, j, 0, 0};
+            p.lp_lo = nn; p.lp_hi = c; p.skip_mid = true;   // [diagonal block; rows below (untouched); I]
+            pan.push_back(p);
+          }
+          panel_steps(pan);
+          continue;
+        }
+        for (int32_t hh = 1; hh < ht; ++hh) assemble(s - (1 << hh));
+        // sample Omega (|R_s| x l), key of supernode j, third counter word 4 + s
+        ctx = RSC_K_SAMPLE;
+        const int64_t ph0 = (int64_t)P.philox.size();
+        int64_t maxw = 0;
+        for (int32_t j : g) {
+          const TreeNode& n = node(j, s);
+          PhiloxTask t{};
+          t.out = n.omega; t.rows = n.rb - n.ra; t.cols = n.ell; t.c2 = 4 + (uint32_t)s;
+          t.k0 = (uint32_t)(h.opt.seed & 0xFFFFFFFFull);
+          t.k1 = (uint32_t)(((h.opt.seed >> 32) & 0xFFFFFFFFull) ^ (uint64_t)(uint32_t)h.sn_local[j]);
+          P.philox.push_back(t);
+          maxw = std::max<int64_t>(maxw, (int64_t)t.rows * ((t.cols + 3) / 4));
+        }
+        cmd(kCmdPhilox, RSC_K_OTHER, ph0, (int64_t)P.philox.size() - ph0, 0, maxw, lp_sample ? 1 : 0);
+        // Y = L(R, C)^T Omega = M_{s1}^T (S(R, C)^T Omega) into rows [l, l + |C|) of the panel
+        launch(lp_sample, [&](int32_t j) {
+          const TreeNode& n = node(j, s);
+          const int32_t nc = n.cb - n.ca, nr = n.rb - n.ra, ld = h.panel_ld[j];
+          return tiles(gt(SRC(j, n), ld, 1, n.omega, nr, 1, n.tmp, nc, nc, n.ell, nr, 1.0, 0.0), 0, 0, false);
+        });
+        launch(lp_update, [&](int32_t j) {
+          const TreeNode& n = node(j, s);
+          const int32_t nc = n.cb - n.ca;
+          return tri(j, true, n.ca, nc, n.ell, n.tmp, nc, n.ypanel + n.ell, n.ell + nc);
+        });
+        for (int it = 0; it < h.opt.power_iters; ++it) {
+          qr(false, true);
+          launch(0, [&](int32_t j) {             // Z = L(R, C) Y = S(R, C) (M_{s1} Y)
+            const TreeNode& n = node(j, s);
+            const int32_t nc = n.cb - n.ca;
+            return tri(j, false, n.ca, nc, n.ell, n.ypanel + n.ell, n.ell + nc, n.tmp, nc);
+          });
+          launch(0, [&](int32_t j) {
+            const TreeNode& n = node(j, s);
+            const int32_t nc = n.cb - n.ca, nr = n.rb - n.ra, ld = h.panel_ld[j];
+            return tiles(gt(SRC(j, n), 1, ld, n.tmp, nc, 1, n.zpanel + n.ell, n.ell + nr, nr, n.ell, nc, 1.0, 0.0),
+                         0, 0, false);
+          });
+          qr(true, true);
+          launch(0, [&](int32_t j) {             // Y = M_{s1}^T (S(R, C)^T Z)
+            const TreeNode& n = node(j, s);
+            const int32_t nc = n.cb - n.ca, nr = n.rb - n.ra, ld = h.panel_ld[j];
+            return tiles(gt(SRC(j, n), ld, 1, n.zpanel + n.ell, n.ell + nr, 1, n.tmp, nc, nc, n.ell, nr, 1.0, 0.0),
+                         0, 0, false);
+          });
+          launch(0, [&](int32_t j) {
+            const TreeNode& n = node(j, s);
+            const int32_t nc = n.cb - n.ca;
+            return tri(j, true, n.ca, nc, n.ell, n.tmp, nc, n.ypanel + n.ell, n.ell + nc);
+          });
+        }
+        // U = orth(Y): shifted Cholesky-QR3 (keeps every direction above Y's rounding)
+        ctx = RSC_K_ORTH;
+        for (int pass = 0; pass < 3; ++pass) qr(false, pass == 0);
+        // W = M_{s1} U, V = S(R, C) W = L(R, C) U
+        ctx = RSC_K_BASIS;
+        launch(lp_eig, [&](int32_t j) {
+          const TreeNode& n = node(j, s);
+          const int32_t nc = n.cb - n.ca;
+          return tri(j, false, n.ca, nc, n.ell, n.ypanel + n.ell, n.ell + nc, n.W, nc);
+        });
+        launch(lp_eig, [&](int32_t j) {
+          const TreeNode& n = node(j, s);
+          const int32_t nc = n.cb - n.ca, nr = n.rb - n.ra, ld = h.panel_ld[j];
+          return tiles(gt(SRC(j, n), 1, ld, n.W, nc, 1, n.V, nr, nr, n.ell, nc, 1.0, 0.0), 0, 0, false);
+        });
+        // S(R, R) -= V V^T (tiles on or below the diagonal); L(R, C) = V U^T over S(R, C)
+        ctx = RSC_K_UPDATE;
+        launch(lp_update, [&](int32_t j) {
+          const TreeNode& n = node(j, s);
+          const int32_t nr = n.rb - n.ra, ld = h.panel_ld[j];
+          return tiles(gt(n.V, 1, nr, n.V, 1, nr, h.panel_off[j] + n.ra + (int64_t)n.ra * ld, ld, nr, nr,
+                          n.ell, -1.0, 1.0), 0, 0, true);
+        });
+        ctx = RSC_K_BASIS;
+        launch(lp_eig, [&](int32_t j) {
+          const TreeNode& n = node(j, s);
+          const int32_t nc = n.cb - n.ca, nr = n.rb - n.ra, ld = h.panel_ld[j];
+          return tiles(gt(n.V, 1, nr, n.ypanel + n.ell, 1, n.ell + nc, SRC(j, n), ld, nr, nc, n.ell, 1.0, 0.0),
+                       0, 0, false);
+        });
+        ctx = -1;
+      }
+      for (int32_t hh = 1; hh <= d; ++hh) assemble((2 << d) - (1 << hh));
+    }
+    // algorithmic = executed for the trees' launches (exact extents, fixed ranks)
+    for (size_t i = c_first; i < P.cmds.size(); ++i) P.cmds[i].mflops = P.cmds[i].flops;
+  }
+  int32_t cur_s = 0;   // the tree block being emitted
 };
 
 template <class T>
@@ -1429,13 +1698,18 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
     B.cmd(kCmdAssembleLevel, RSC_K_OTHER, h.asmo_ptr[L], h.asmo_ptr[L + 1] - h.asmo_ptr[L], 0);
     B.updates(lev);
     std::vector<PanelDesc> pan;
-    for (int32_t j : lev)   // [L^D_j; I]: the Cholesky factor and, in the rows below, M_j
-      pan.push_back(PanelDesc{h.panel_off[j], h.panel_ld[j], S.c(j), 0, true, h.dinv_off[j], j, 0, 0});
-    const size_t cp = P->cmds.size();
+    std::vector<int32_t> trees;   // rank-structured factor: L^D_j as a block tree (Sec. 4)
     double m_potrf = 0;
-    for (int32_t j : lev) m_potrf += std::pow((double)S.c(j), 3) / 3.0;
+    for (int32_t j : lev) {
+      if (compressed && S.depth[j] > 0) { trees.push_back(j); continue; }
+      // [L^D_j; I]: the Cholesky factor and, in the rows below, M_j
+      pan.push_back(PanelDesc{h.panel_off[j], h.panel_ld[j], S.c(j), 0, true, h.dinv_off[j], j, 0, 0});
+      m_potrf += std::pow((double)S.c(j), 3) / 3.0;
+    }
+    const size_t cp = P->cmds.size();
     B.panel_steps(pan);
     B.credit(cp, m_potrf);
+    if (!trees.empty()) B.diag_trees(trees);
     B.offdiag_solve(lev);
     B.compact_operands(lev, false);
     if (compressed) {
@@ -1445,9 +1719,22 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   }
   if (precision != RSC_FP64) B.f32_copy();
   // algorithmic flop counts of the method (per supernode, from the symbolic plan)
+  P->alpha_D = h.tree_alpha;
   for (int64_t j = 0; j < S.M(); ++j) {
     const double c = S.c(j), r = S.r(j);
-    P->flops[0] += c * c * c / 3.0;
+    if (compressed && S.depth[j] > 0) {
+      // block tree: leaves' Cholesky, and per internal block its two products with
+      // S(R, C), the products with M_{s1}, Cholesky-QR, the Schur update and M's coupling
+      for (const TreeNode& t : h.tree[j]) {
+        const double nc = t.cb - t.ca, nr = t.rb - t.ra, l = t.ell;
+        if (t.ht == 0) { P->flops[0] += nc * nc * nc / 3.0; continue; }
+        P->flops[3] += 4.0 * nr * nc * l + 2.0 * nc * nc * l;
+        P->flops[4] += 2.0 * nc * l * l;
+        P->flops[2] += nr * nr * l + nr * nr * l + 2.0 * nc * nr * l;
+      }
+    } else {
+      P->flops[0] += c * c * c / 3.0;
+    }
     if (!(compressed && h.compressible[j])) P->flops[1] += r * c * c;
     if (compressed && h.compressible[j]) {
       const double l = h.comp[j].ell;
@@ -1771,7 +2058,8 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
   set_layout(h, compressed);
   if ((e = ensure_arena(h, compressed ? h.arena_size_comp : h.arena_size_exact)).code) return e;
   auto& slot = h.fplans[precision];
-  if (!slot || slot->compressed != compressed || (compressed && slot->tol != tol))
+  if (!slot || slot->compressed != compressed ||
+      (compressed && (slot->tol != tol || slot->alpha_D != h.tree_alpha)))
     if ((e = build_factor_plan(h, compressed, tol, precision, stream)).code) return e;
   if (h.splan && h.splan->compressed != compressed) {
     if (h.splan->graph_a) (void)hipGraphExecDestroy(h.splan->graph_a);
@@ -1830,7 +2118,8 @@ static Error factor_once(Handle& h, const double* values, double tol, int32_t pr
 static Error ensure_solve(Handle& h);
 
 // The restart policy of Sec. 5.3 (raise the accuracy and refactor after an indefinite
-// pivot) applied to precision: mixed BF16 -> FP32 products -> FP64.
+// pivot): for block trees the diagonal rank constant alpha_D, by 1.25 per restart; then
+// the precision of the products: mixed BF16 -> FP32 products -> FP64.
 Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
   Error e = ensure_device(h);
   if (e.code) return e;
@@ -1840,8 +2129,20 @@ Error factor(Handle& h, const double* values, double tol, hipStream_t stream) {
     if (h.opt.precision != RSC_FP64) ladder.push_back(RSC_FP64);
   }
   h.retries = 0;
+  h.diag_restarts = 0;
+  // block trees (Sec. 5.3): a factorization that meets an indefinite pivot restarts with
+  // alpha_D raised by a quarter, until it succeeds or every block is sampled at full rank
+  bool trees = false;
+  if (tol > 0.0)
+    for (int32_t d : h.S.depth) trees = trees || d > 0;
+  if (trees && h.tree_alpha != h.opt.alpha_D) plan_trees(h, h.opt.alpha_D);
   for (size_t k = 0; k < ladder.size(); ++k) {
-    e = factor_once(h, values, tol, ladder[k], stream);
+    for (;;) {
+      e = factor_once(h, values, tol, ladder[k], stream);
+      if (e.code != RSC_ERR_NOT_SPD || !trees || trees_exact(h) || h.diag_restarts >= 64) break;
+      plan_trees(h, h.tree_alpha * 1.25);
+      h.diag_restarts++;
+    }
     if (e.code != RSC_ERR_NOT_SPD || k + 1 == ladder.size()) break;
     h.retries++;
   }

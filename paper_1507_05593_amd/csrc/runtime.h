@@ -89,9 +89,25 @@ struct CompSlot {
   int32_t qslot = -1;
 };
 
+// One block of a supernode's diagonal block tree (Sec. 4.1-4.2), in-order label s.  A leaf
+// (height 0) is the dense diagonal block on columns [ca, cb) (= [ra, rb)) of C_j; an
+// internal block is L(R_s, C_s) ~ V_s U_s^T with C_s = [ca, cb) its left subtree's
+// columns and R_s = [ra, rb) its right subtree's (offsets relative to C_j).  Arena
+// offsets of its work space in the level pool of the rank-structured layout.
+struct TreeNode {
+  int32_t s = 0, ht = 0;
+  int32_t ca = 0, cb = 0, ra = 0, rb = 0;
+  int32_t ell = 0;                   // samples (= kept rank) of an internal block
+  int64_t dinv = -1;                 // 64 x 64 inverse blocks: the leaf's panel steps, or
+                                     // the orthonormalisation panel's
+  int64_t omega = -1, tmp = -1, ypanel = -1, W = -1, V = -1, X = -1, gscale = -1;
+  int64_t zpanel = -1, zdinv = -1;   // power iterations
+};
+
 // A launch plan (command list + task arrays) for one factor mode.
 struct FactorPlan {
   bool compressed = false;
+  double alpha_D = 0;                // the diagonal rank constant the block trees were planned with
   int32_t tuned = 0, tuned128 = 0;   // product launches tried by the tile tuner / set to 128
   int32_t precision = RSC_FP64;
   double tol = 0;
@@ -179,6 +195,13 @@ struct Handle {
   std::vector<int64_t> uo_rel, dinv_rel;
   std::vector<std::array<int64_t, 2>> lev_uo_rel;
   std::vector<CompSlot> comp_rel;     // the work-space fields of comp, pool-relative
+  // diagonal block trees (rank-structured layout): per supernode its blocks in order
+  // (empty: dense L^D_j), planned for the rank constant tree_alpha
+  std::vector<std::vector<TreeNode>> tree;
+  double tree_alpha = 0;
+  std::vector<int64_t> lev_pool_comp;  // per level: its rank-structured pool end before the trees
+  int64_t pool_comp_plain = 0;         // the largest of those
+  int32_t diag_restarts = 0;           // refactorizations with a larger alpha_D (Sec. 5.3)
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
   std::vector<int32_t> sn_local;      // supernode index within its own system (sample key)
@@ -237,6 +260,10 @@ struct Handle {
 void plan_layout(Handle& h);
 // the pool offsets (and L^O offsets) of the exact (false) or rank-structured layout
 void set_layout(Handle& h, bool compressed);
+// the diagonal block trees' work space for the rank constant alpha_D (sets
+// arena_size_comp); whether every internal block is then sampled at full rank
+void plan_trees(Handle& h, double alpha_D);
+bool trees_exact(const Handle& h);
 // device set-up (first numeric call)
 Error ensure_device(Handle& h);
 void drop_graphs(Handle& h);

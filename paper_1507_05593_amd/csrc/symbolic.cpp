@@ -11,6 +11,10 @@
 //   L_{m+1}; recurse on the lower part, then the upper part, then emit the separator.
 // Supernodes: one per emitted set.  Row sets are the union pattern (neighbours of
 // C_j after C_j plus the children's row sets), parent = owner of min R_j.
+// Large separators (Sec. 4.1): more than tau_D columns -> a complete block tree of
+// depth ceil(log2(c / tau_D)); given positions, the columns are first reordered by the
+// recursive split along the longest side of each piece's bounding box (stable sort,
+// first of equal sides, first half m / 2), which leaves the supernode's pattern as is.
 #include "symbolic.h"
 
 #include <algorithm>
@@ -213,12 +217,56 @@ void nested_dissection(int64_t n, const int64_t* rowptr, const int32_t* colind, 
   d.run(perm, first, kind);
 }
 
+int32_t split_depth(int64_t c, int32_t tau_D) {
+  if (tau_D <= 0) return 0;
+  int32_t d = 0;
+  while (((c + (int64_t(1) << d) - 1) >> d) > tau_D) ++d;
+  return d;
+}
+
+void coordinate_order(const double* xyz, std::vector<int64_t>& idx, int32_t d) {
+  std::function<void(int64_t, int64_t, int32_t)> rec = [&](int64_t lo, int64_t hi, int32_t depth) {
+    if (depth == 0 || hi - lo < 2) return;
+    double mn[3], mx[3];
+    for (int a = 0; a < 3; ++a) { mn[a] = xyz[3 * idx[lo] + a]; mx[a] = mn[a]; }
+    for (int64_t i = lo; i < hi; ++i)
+      for (int a = 0; a < 3; ++a) {
+        const double v = xyz[3 * idx[i] + a];
+        mn[a] = std::min(mn[a], v);
+        mx[a] = std::max(mx[a], v);
+      }
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+      if (mx[a] - mn[a] > mx[axis] - mn[axis]) axis = a;
+    std::stable_sort(idx.begin() + lo, idx.begin() + hi,
+                     [&](int64_t u, int64_t v) { return xyz[3 * u + axis] < xyz[3 * v + axis]; });
+    const int64_t h = (hi - lo) / 2;
+    rec(lo, lo + h, depth - 1);
+    rec(lo + h, hi, depth - 1);
+  };
+  rec(0, (int64_t)idx.size(), d);
+}
+
 void build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* colind, int32_t leaf_max,
-                    Symbolic& S) {
+                    int32_t tau_D, const double* coords, Symbolic& S) {
   S.n = n;
   S.nnz = rowptr[n];
   nested_dissection(n, rowptr, colind, leaf_max, S.perm, S.first, S.kind);
   const int64_t M = S.M();
+  S.depth.assign(M, 0);
+  for (int64_t j = 0; j < M; ++j) {
+    const int64_t c = S.first[j + 1] - S.first[j];
+    if (S.kind[j] != kSeparator || tau_D <= 0 || c <= tau_D) continue;
+    S.depth[j] = split_depth(c, tau_D);
+    if (!coords) continue;
+    std::vector<int64_t> pos(c), old(S.perm.begin() + S.first[j], S.perm.begin() + S.first[j + 1]);
+    std::iota(pos.begin(), pos.end(), 0);
+    std::vector<double> xyz(3 * c);
+    for (int64_t i = 0; i < c; ++i)
+      for (int a = 0; a < 3; ++a) xyz[3 * i + a] = coords[3 * old[i] + a];
+    coordinate_order(xyz.data(), pos, S.depth[j]);
+    for (int64_t i = 0; i < c; ++i) S.perm[S.first[j] + i] = old[pos[i]];
+  }
   S.iperm.assign(n, 0);
   for (int64_t i = 0; i < n; ++i) S.iperm[S.perm[i]] = i;
   S.owner.assign(n, 0);

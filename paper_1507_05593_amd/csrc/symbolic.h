@@ -31,6 +31,7 @@ struct Symbolic {
   std::vector<int64_t> rows;         // R_j concatenated (new indices, ascending)
   std::vector<int32_t> owner;        // new index -> supernode
   std::vector<int32_t> sys_of_sn;    // supernode -> system
+  std::vector<int32_t> depth;        // depth of the diagonal block tree (Sec. 4.1), 0: dense
   int32_t nlevels = 0;
   std::vector<std::vector<int32_t>> by_level;
 
@@ -54,8 +55,19 @@ void nested_dissection(int64_t n, const int64_t* rowptr, const int32_t* colind, 
                        std::vector<int64_t>& perm, std::vector<int64_t>& first,
                        std::vector<int32_t>& kind);
 
-// Full symbolic analysis.
+// Depth d of the complete block tree over c columns: the smallest d with
+// ceil(c / 2^d) <= tau_D (0 when tau_D <= 0 or c <= tau_D).
+int32_t split_depth(int64_t c, int32_t tau_D);
+
+// Reorders idx (positions into xyz, n x 3 row-major) by d rounds of the coordinate
+// split of Sec. 4.1: each piece is sorted stably along the longest side of its bounding
+// box (the first of equal sides) and cut into its first m / 2 entries and the rest.
+void coordinate_order(const double* xyz, std::vector<int64_t>& idx, int32_t d);
+
+// Full symbolic analysis.  With tau_D > 0 every separator of more than tau_D columns
+// gets a block tree of depth split_depth(c, tau_D); with coords (n x 3, original
+// numbering, row-major) its columns are reordered by coordinate_order first.
 void build_symbolic(int64_t n, const int64_t* rowptr, const int32_t* colind, int32_t leaf_max,
-                    Symbolic& S);
+                    int32_t tau_D, const double* coords, Symbolic& S);
 
 }  // namespace rsc

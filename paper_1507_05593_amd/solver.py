@@ -61,7 +61,7 @@ def use_torch_allocator(on: bool = True) -> None:
 
 def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.0, seed=0,
                  precision="fp64", use_graph=True, retry=True, gemm_tile=0, keep_lo=False,
-                 sweep_small_c=64) -> Options:
+                 sweep_small_c=64, tau_D=0, alpha_D=0.5) -> Options:
     o = Options()
     lib().rsc_default_options(C.byref(o))
     o.leaf_max, o.tau_O, o.oversample, o.power_iters = leaf_max, tau_O, oversample, power_iters
@@ -71,6 +71,7 @@ def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.
     o.gemm_tile = int(gemm_tile)
     o.keep_lo = int(bool(keep_lo))
     o.sweep_small_c = int(sweep_small_c)
+    o.tau_D, o.alpha_D = int(tau_D), float(alpha_D)
     return o
 
 
@@ -82,15 +83,33 @@ class RSCSolver:
     For several independent systems pass lists to ``RSCSolver.batch``.
     """
 
-    def __init__(self, n=None, rowptr=None, colind=None, _handle=None, _systems=1, **opts):
+    def __init__(self, n=None, rowptr=None, colind=None, _handle=None, _systems=1, coords=None, **opts):
+        """``coords``: positions of the indices (``n x 3`` host array, or ``"spectral"``
+        for the three spectral coordinates computed on the device first); with
+        ``tau_D > 0`` they order the columns of the block-tree separators."""
         L = lib()
         self._opts = make_options(**opts)
         if _handle is None:
             rp = np.ascontiguousarray(rowptr, dtype=np.int64)
             ci = np.ascontiguousarray(colind, dtype=np.int32)
+            if isinstance(coords, str):
+                if coords != "spectral":
+                    raise ValueError("coords must be an n x 3 array or 'spectral'")
+                pre = RSCSolver(n, rowptr, colind, **{k: v for k, v in opts.items() if k != "tau_D"})
+                xyz, _ = pre.spectral_coordinates()
+                coords = xyz.cpu().numpy()
+                del pre
             h = C.c_void_p()
-            check(L.rsc_analyze(int(n), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
-                                C.byref(self._opts), C.byref(h)), "rsc_analyze")
+            if coords is None:
+                check(L.rsc_analyze(int(n), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                                    C.byref(self._opts), C.byref(h)), "rsc_analyze")
+            else:
+                xyz = np.ascontiguousarray(coords, dtype=np.float64)
+                if xyz.shape != (int(n), 3):
+                    raise ValueError("coords must have shape (n, 3)")
+                check(L.rsc_analyze_coords(int(n), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                                           xyz.ctypes.data_as(C.c_void_p), C.byref(self._opts), C.byref(h)),
+                      "rsc_analyze_coords")
             _handle = h
         self._h = _handle
         n_, nnz, M, lev, sysn = (C.c_int64() for _ in range(5))
@@ -174,6 +193,13 @@ class RSCSolver:
         ritz = (C.c_double * 3)()
         check(lib().rsc_spectral_coordinates(self._h, int(steps), int(seed), _ptr(xyz), ritz, _stream()))
         return xyz.view(3, self.n).t(), np.array(ritz[:])
+
+    @property
+    def tree_depths(self) -> np.ndarray:
+        """Depth of each supernode's diagonal block tree (0: dense L^D_j)."""
+        d = np.empty(self.supernodes, dtype=np.int32)
+        check(lib().rsc_get_tree_depths(self._h, d.ctypes.data_as(C.c_void_p)))
+        return d
 
     @property
     def perm(self) -> np.ndarray:

@@ -10,7 +10,7 @@ import pytest
 
 from conftest import ROOT, golden_path
 from oracle.ordering import symbolic
-from workloads import grid_problem
+from workloads import grid_coordinates, grid_problem
 from workloads.grids import batched_problems
 
 from paper_1507_05593_amd import RSCSolver, lib
@@ -47,6 +47,29 @@ def test_symbolic_bit_exact_with_oracle(dims, sigma, leaf):
     sym = symbolic(p.n, p.rowptr, p.colind, leaf)
     sol = RSCSolver(p.n, p.rowptr, p.colind, leaf_max=leaf)
     _compare(sol, sym, p.n)
+
+
+@pytest.mark.parametrize("dims,tau,scramble", [((12, 12, 12), 16, False), ((40, 40), 8, False),
+                                               ((20, 18, 16), 24, False), ((24, 24, 24), 40, False),
+                                               ((14, 14, 14), 20, True)])
+def test_coordinate_order_bit_exact_with_oracle(dims, tau, scramble):
+    """The block trees' column order inside large separators (§4.1) and their depths;
+    scrambled positions exercise the stable sort's ties and the longest-side choice."""
+    p = grid_problem(dims, sigma=1.0, seed=2)
+    xyz = grid_coordinates(dims)
+    if scramble:
+        rng = np.random.default_rng(7)
+        xyz = xyz[:, rng.permutation(3)] * rng.choice([1.0, 2.0], size=3) + rng.integers(0, 3, size=(p.n, 3))
+    sym = symbolic(p.n, p.rowptr, p.colind, 64, tau, xyz)
+    sol = RSCSolver(p.n, p.rowptr, p.colind, coords=xyz, tau_D=tau)
+    _compare(sol, sym, p.n)
+    assert np.array_equal(sol.tree_depths, sym.depth)
+    assert sym.depth.max() >= 1
+    # without positions the columns keep the dissection order; the depths are the same
+    sym0 = symbolic(p.n, p.rowptr, p.colind, 64, tau)
+    sol0 = RSCSolver(p.n, p.rowptr, p.colind, tau_D=tau)
+    _compare(sol0, sym0, p.n)
+    assert np.array_equal(sol0.tree_depths, sym.depth)
 
 
 def test_batched_symbolic_is_per_system_dissection():
@@ -102,12 +125,23 @@ def test_pattern_and_argument_errors():
     with pytest.raises(RSCError) as e:
         RSCSolver(p.n, rp2, ci2)
     assert e.value.code == RSC_ERR_PATTERN
-    for bad_opt in (dict(leaf_max=0), dict(sweep_small_c=-1), dict(sweep_small_c=1025), dict(gemm_tile=32)):
+    for bad_opt in (dict(leaf_max=0), dict(sweep_small_c=-1), dict(sweep_small_c=1025), dict(gemm_tile=32),
+                    dict(tau_D=-1), dict(tau_D=1), dict(alpha_D=0.0)):
         with pytest.raises(RSCError) as e:
             RSCSolver(p.n, p.rowptr, p.colind, **bad_opt)
         assert e.value.code == RSC_ERR_INVALID_ARG, bad_opt
     h = C.c_void_p()
     assert lib().rsc_analyze(-1, None, None, None, C.byref(h)) == RSC_ERR_INVALID_ARG
+    # positions: null, wrong shape, non-finite
+    assert lib().rsc_analyze_coords(p.n, p.rowptr.ctypes.data, p.colind.ctypes.data, None, None,
+                                    C.byref(h)) == RSC_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        RSCSolver(p.n, p.rowptr, p.colind, coords=np.zeros((p.n, 2)))
+    xyz = grid_coordinates((5, 5))
+    xyz[3, 1] = np.nan
+    with pytest.raises(RSCError) as e:
+        RSCSolver(p.n, p.rowptr, p.colind, coords=xyz, tau_D=4)
+    assert e.value.code == RSC_ERR_INVALID_ARG
 
 
 def test_stats_before_factor():
