@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-coordinates timing")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying hipGraphs")
+    ap.add_argument("--tree-tau", type=int, default=512,
+                    help="tau_D of the diagonal block-tree run timed beside (0 to skip)")
     ap.add_argument("--gemm-tile", type=int, default=0, choices=[0, 64, 128],
                     help="output tile edge of the product launches (0: autotuned)")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -168,6 +170,45 @@ def spectral_line(pattern, m=20, reps=3):
     return {"steps": m, "ms": round(ms, 3), "ritz": [float(x) for x in ritz],
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
                          "frac": round(gbs / 8000.0, 4), "bytes": byt}}
+
+
+def tree_line(cfg, p, vals, b, precision, tau, steps=2, warmup=1):
+    """Factor + PCG with diagonal block trees (paper Sec. 4.1-4.2, 5.3): separators of more
+    than tau columns store L^D_j as a block tree, ordered by the grid positions."""
+    import numpy as np
+    import torch
+    from paper_1507_05593_amd import RSCSolver
+    from workloads import grid_coordinates
+    xyz = grid_coordinates(p.dims)
+    t0 = time.perf_counter()
+    sol = RSCSolver(p.n, p.rowptr, p.colind, coords=xyz, tau_D=tau, precision=precision, seed=0)
+    t_an = time.perf_counter() - t0
+    info = None
+    for _ in range(warmup):
+        info = step(sol, vals, b, cfg, None)
+    torch.cuda.synchronize()
+    fms = pms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = step(sol, vals, b, cfg, None)
+        fms += sol.stats()["t_factor_ms"]
+        pms += info["t_pcg_ms"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = sol.stats()
+    first, _, _, _ = sol.supernode_info()
+    c = np.diff(first)[sol.tree_depths > 0].astype(np.int64)
+    out = {"tau_D": tau, "positions": "grid", "precision": precision, "ms_per_step": round(1e3 * dt, 3),
+           "factor_ms": round(fms / steps, 3), "pcg_ms": round(pms / steps, 3), "pcg_iters": info["iters"],
+           "true_residual": info["true_residual"], "analyze_s": round(t_an, 3),
+           "tree_supernodes": st["tree_supernodes"], "tree_blocks": st["tree_blocks"],
+           "tree_rank_sum": st["tree_rank_sum"], "tree_entries": st["tree_entries"],
+           "dense_diag_entries": int(np.sum(c * (c + 1) // 2)),
+           "factor_entries": st["factor_entries"], "alpha_D": st["alpha_D_used"],
+           "restarts": st["diag_restarts"], "device_gb": round(st["device_bytes"] / 1e9, 2)}
+    del sol
+    torch.cuda.synchronize()
+    return out
 
 
 # ------------------------------------------------------------------ one step
@@ -627,6 +668,8 @@ def main():
     line["pcg_hbm"] = pcg_hbm(desc, st, info["iters"], res["pcg_ms"])
     if not batched and not args.no_spectral:
         line["spectral_coordinates"] = spectral_line(pattern)
+    if not batched and args.tree_tau > 0 and len(p.dims) == 3 and extra is None:
+        line["diag_trees"] = tree_line(cfg, p, vals, b, precision, args.tree_tau)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name, cfg, args.cpu_sample_side, desc)
     print(json.dumps(line), flush=True)
