@@ -1441,8 +1441,7 @@ struct Builder {
   //    below it untouched, its inverse into its rows of M_j (which start as I);
   //  * internal block s: Algorithm 3 on L(R_s, C_s) = S(R_s, C_s) M_{s1}, M_{s1} the left
   //    subtree's (finished) part of M_j = (L^D_j)^{-T} -- Algorithm 4 as a product with
-  //    that explicit inverse -- at the fixed rank l_s (shifted Cholesky-QR3, no
-  //    truncation); then S(R_s, R_s) -= V_s V_s^T (every later block's term from block s,
+  //    that explicit inverse -- at the fixed rank l_s (no truncation); then S(R_s, R_s) -= V_s V_s^T (every later block's term from block s,
   //    Algorithms 5 and 6's loop over earlier blocks) and V_s U_s^T written over
   //    S(R_s, C_s), so that the panel holds the block tree's L^D_j;
   //  * once both subtrees of block t are done, M_j's coupling block
@@ -1576,9 +1575,13 @@ struct Builder {
             return tri(j, true, n.ca, nc, n.ell, n.tmp, nc, n.ypanel + n.ell, n.ell + nc);
           });
         }
-        // U = orth(Y): shifted Cholesky-QR3 (keeps every direction above Y's rounding)
+        // U = orth(Y): as for the off-diagonal blocks, two plain Cholesky-QR passes (the
+        // directions of Y below ~1e-7 of its largest are lost: far below the error of a
+        // fixed-rank block) for tol >= 1e-5, else shifted Cholesky-QR3, which keeps every
+        // direction above the rounding of Y
         ctx = RSC_K_ORTH;
-        for (int pass = 0; pass < 3; ++pass) qr(false, pass == 0);
+        const bool accurate = P.tol < 1e-5;
+        for (int pass = 0; pass < (accurate ? 3 : 2); ++pass) qr(false, accurate && pass == 0);
         // W = M_{s1} U, V = S(R, C) W = L(R, C) U
         ctx = RSC_K_BASIS;
         launch(lp_eig, [&](int32_t j) {
