@@ -25,6 +25,10 @@ Parity status per function (what pins it, see the tests named ``test_oracle_*``)
   block satisfies the block-Cholesky recurrences of the written-out factor (Schur
   complement, ``V_s = L(R_s, C_s) U_s``, ``U_s`` orthonormal and spanning the sample);
   the restart policy on a planted failure.
+* ``solve.apply_preconditioner(interior=True)`` / ``interior_blocks`` (§5.1): the closed
+  form ``L(R^B, C^B) = A(R^B, C^B) L(C^B, C^B)^{-T}`` against the block the factorization
+  computes, ``L(C^B, C^B)`` against the block's own dense Cholesky factor, the blocks'
+  maximality, and the apply through eq. interiorBlockMult against the stored-block apply.
 * ``philox``: the published known-answer vectors of Philox4x32-10.
 * ``spectral.spectral_coordinates`` (§4.3, block Lanczos on the graph Laplacian): the
   closed-form spectrum and cosine eigenvectors of grid graphs (distinct modes, and the
