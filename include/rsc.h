@@ -94,6 +94,15 @@ typedef struct {
                           k = min(rows, cols), and kept at that rank; an indefinite pivot makes
                           rsc_factor restart with alpha_D x 1.25 (Sec. 5.3) until it succeeds or
                           every block is sampled at full rank (0.5) */
+  int32_t interior;    /* interior blocks (Sec. 5.1), rank-structured factor: for each maximal
+                          subtree of the elimination tree without a compressed supernode (a
+                          subdomain the compressed separators cut out; columns C^B), keep only
+                          the rows of its L^O_j inside C^B; the preconditioner reaches the
+                          block L(R^B, C^B) = A(R^B, C^B) L(C^B, C^B)^{-T} through A's entries
+                          and two triangular solves with the block's own factor per sweep
+                          (eq. interiorBlockMult).  Same preconditioner; less factor memory,
+                          more work per apply (0) */
+  int32_t reserved2;
 } rsc_options;
 
 typedef struct {
@@ -130,6 +139,8 @@ typedef struct {
   double alpha_D_used;         /* the diagonal rank constant of the last factor */
   int32_t diag_restarts;       /* restarts of the last rsc_factor with a larger alpha_D */
   int32_t reserved1;
+  int64_t interior_blocks;     /* interior blocks of the last factor (rsc_options.interior) */
+  int64_t interior_dropped;    /* entries of L^O beyond the interior blocks not stored */
 } rsc_stats;
 
 /* Kernel-class timing (hipEvents around every launch of a class while enabled).  Classes
@@ -279,7 +290,9 @@ rsc_status rsc_get_ranks(rsc_handle h, int32_t* ell, int32_t* q);
  * LD (c x c, lower triangle valid), LO (r x c: the dense off-diagonal block
  * U^O_j (L^D_j)^{-T}; for a compressed supernode the block as computed before
  * compression, available only with rsc_options.keep_lo -- RSC_ERR_STATE otherwise --
- * the factor itself uses V_j, U_j), V (r x q), U (c x q).  Any pointer may be NULL. */
+ * the factor itself uses V_j, U_j; for a supernode of an interior block (rsc_options.
+ * interior) only its rows inside the block are stored: the others are returned as 0),
+ * V (r x q), U (c x q).  Any pointer may be NULL. */
 rsc_status rsc_get_block(rsc_handle h, int64_t j, double* LD, double* LO, double* V, double* U);
 rsc_status rsc_get_stats(rsc_handle h, rsc_stats* out);
 rsc_status rsc_profile_enable(rsc_handle h, int32_t on);   /* also resets the counters */
@@ -291,7 +304,7 @@ rsc_status rsc_get_profile(rsc_handle h, rsc_profile* out);
  * (both as for rsc_profile; launches whose extents depend on the kept ranks are counted
  * at the ranks of the factorisation that ran).  Any output may be NULL.  Errors:
  * RSC_ERR_INVALID_ARG for a null handle or k out of range. */
-#define RSC_KERNELS 39
+#define RSC_KERNELS 42
 rsc_status rsc_get_kernel_profile(rsc_handle h, int32_t k, const char** name, int64_t* launches,
                                   double* ms, double* flops, double* tile_flops);
 

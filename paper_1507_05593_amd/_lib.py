@@ -23,7 +23,7 @@ RSC_MIXED_FP32 = 2
 
 K_CLASSES = ["update", "panel_potrf", "panel_trsm", "panel_trailing", "truncation", "pcg", "other", "lo_product",
              "sample", "orthonormalise", "basis"]
-RSC_KERNELS = 39
+RSC_KERNELS = 42
 
 
 class Options(C.Structure):
@@ -32,7 +32,7 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("use_graph", C.c_int32), ("retry", C.c_int32),
                 ("gemm_tile", C.c_int32), ("keep_lo", C.c_int32),
                 ("sweep_small_c", C.c_int32), ("tau_D", C.c_int32), ("reserved0", C.c_int32),
-                ("alpha_D", C.c_double)]
+                ("alpha_D", C.c_double), ("interior", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class PcgResult(C.Structure):
@@ -51,7 +51,8 @@ class Stats(C.Structure):
                 ("t_factor_ms", C.c_double), ("t_pcg_ms", C.c_double), ("device_bytes", C.c_double),
                 ("gemm_tuned", C.c_int64), ("gemm_tile128", C.c_int64), ("tree_supernodes", C.c_int64),
                 ("tree_blocks", C.c_int64), ("tree_rank_sum", C.c_int64), ("tree_entries", C.c_int64),
-                ("alpha_D_used", C.c_double), ("diag_restarts", C.c_int32), ("reserved1", C.c_int32)]
+                ("alpha_D_used", C.c_double), ("diag_restarts", C.c_int32), ("reserved1", C.c_int32),
+                ("interior_blocks", C.c_int64), ("interior_dropped", C.c_int64)]
 
 
 ARITHS = ("f64", "f32", "bf16")

@@ -39,7 +39,7 @@ rsc_status check_options(const rsc_options& o) {
   if (o.leaf_max < 1 || o.tau_O < 1 || o.oversample < 0 || o.power_iters < 0 || !(o.alpha_O > 0) ||
       o.precision < RSC_FP64 || o.precision > RSC_MIXED_FP32 ||
       (o.gemm_tile != 0 && o.gemm_tile != 64 && o.gemm_tile != 128) || o.sweep_small_c < 0 ||
-      o.sweep_small_c > 1024 || o.tau_D < 0 || o.tau_D == 1 || !(o.alpha_D > 0) || !(o.alpha_D < 1e6))
+      o.sweep_small_c > 1024 || o.tau_D < 0 || o.tau_D == 1 || o.interior < 0 || o.interior > 1 || !(o.alpha_D > 0) || !(o.alpha_D < 1e6))
     return fail(RSC_ERR_INVALID_ARG, "option out of range");
   return RSC_OK;
 }
@@ -269,7 +269,14 @@ rsc_status rsc_get_block(rsc_handle H, int64_t j, double* LD, double* LO, double
     return fail(RSC_ERR_DEVICE, "copy LD");
   if (LO && comp && !h.opt.keep_lo)
     return fail(RSC_ERR_STATE, "L^O of a compressed supernode is not kept (rsc_options.keep_lo)");
-  if (LO && r > 0 && c > 0) {
+  const bool inb = h.fplan->compressed && h.opt.interior && h.iroot[j] >= 0 && r > 0;
+  if (LO && r > 0 && c > 0 && inb) {
+    // an interior block's supernode: its rows inside the block, the rest not stored
+    const int64_t ri = h.r_in[j];
+    std::memset(LO, 0, sizeof(double) * r * c);
+    if (ri > 0 && hipMemcpy2D(LO, r * 8, h.arena.p + h.lo_in[j], ri * 8, ri * 8, c, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(RSC_ERR_DEVICE, "copy LO");
+  } else if (LO && r > 0 && c > 0) {
     if (hipMemcpy(LO, h.arena.p + h.lo_off[j], sizeof(double) * r * c,
                          hipMemcpyDeviceToHost) != hipSuccess) {
       return fail(RSC_ERR_DEVICE, "copy LO");
@@ -350,9 +357,13 @@ rsc_status rsc_get_stats(rsc_handle H, rsc_stats* out) {
       out->sample_sum += h.comp[j].ell;
       if (q[j] == h.comp[j].ell && h.comp[j].ell < std::min(c, r)) out->rank_saturated++;
       entries += (c + r) * q[j];
+    } else if (comp && h.opt.interior && h.iroot[j] >= 0 && r > 0) {
+      entries += c * h.r_in[j];
+      out->interior_dropped += c * (r - h.r_in[j]);
     } else {
       entries += c * r;
     }
+    if (comp && h.opt.interior && h.iroot[j] == j && r > 0) out->interior_blocks++;
   }
   for (const rsc::Pair& pr : S.pairs) {
     const double m = (comp && h.compressible[pr.k]) ? q[pr.k] : S.c(pr.k);

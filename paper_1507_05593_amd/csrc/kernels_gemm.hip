@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_compact_rows(const CompactTask* __restr
         const bool in = rr < T.nrows && c0 + k < K;
         t[k][rr] = in ? v[u] : 0.0;
         // the sweeps' FP32 copy of the same block, column-major at the arena's offsets
-        if (f32 && in) f32[T.src + rr + (int64_t)(c0 + k) * T.ld] = (float)v[u];
+        if (f32 && in && T.f32 >= 0) f32[T.f32 + rr + (int64_t)(c0 + k) * T.ld] = (float)v[u];
       }
     } else {
       for (int idx = tid; idx < 64 * KC; idx += 256) t[idx >> 6][idx & 63] = 0.0;

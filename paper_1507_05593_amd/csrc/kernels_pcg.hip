@@ -530,6 +530,20 @@ __global__ __launch_bounds__(256) void k_to_f32(const ConvTask* __restrict__ tas
 void launch_to_f32(const ConvTask* t, int n, const double* arena, float* f32, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(n), dim3(256), 0, s, t, arena, f32);
 }
+
+// FP64 copy of a block (the rows of an interior supernode's L^O_k inside its block, from
+// the level pool to the factor's own storage): one task per block of at most 64 columns.
+__global__ __launch_bounds__(256) void k_copy_f64(const ConvTask* __restrict__ tasks, double* __restrict__ arena) {
+  const ConvTask T = tasks[blockIdx.x];
+  const int n = T.rows * T.cols;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const int c = e / T.rows, t = e - c * T.rows;
+    arena[T.dst + (int64_t)c * T.dld + t] = arena[T.off + (int64_t)c * T.ld + t];
+  }
+}
+void launch_copy_f64(const ConvTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy_f64, dim3(n), dim3(256), 0, s, t, arena);
+}
 void launch_part_apply(const PartApply* t, int n, const double* part, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_part_apply, dim3(n), dim3(64), 0, s, t, part, arena);
 }
@@ -573,6 +587,102 @@ void launch_sweep_bwd(const SweepTask* t, int n, int nt, int cpad, int lpad, int
     hipLaunchKernelGGL(k_sweep_bwd<double>, dim3(n), dim3(nt), lds, s, t, arena + a_w, arena + a_zz,
                        (const double*)arena, ilim, rows_idx, cpad, lpad);
 }
+// Interior blocks (Sec. 5.1), one workgroup (256 threads) per block, its supernodes in
+// turn (a block is a subtree: every row of a supernode's L^O_k inside the block belongs
+// to a later supernode of it).  The block's off-diagonal rows beyond it are not stored;
+// the sweeps reach them through A's coupling entries and these solves with the block's
+// own factor L^B = L(C^B, C^B) (eq. interiorBlockMult):
+//  !FWD: t = (L^B)^{-T} w, supernodes last to first: t_k = M_k (w_k - L^O_k(in)^T t_in);
+//   FWD: s = (L^B)^{-1} s in place (s in t), supernodes in order: s_k = M_k^T s_k, then
+//        s_in -= L^O_k(in) s_k; then w -= s over the block's columns.
+// Factor operands from `fac` (the FP64 arena or its FP32 copy), vectors FP64.
+template <typename TF, bool FWD>
+__global__ void __launch_bounds__(256) k_interior(const IntBlock* __restrict__ blocks,
+                                                  const IntSn* __restrict__ sns, const TF* __restrict__ fac,
+                                                  const int64_t* __restrict__ rows, double* __restrict__ w,
+                                                  double* __restrict__ t) {
+  __shared__ double in[kIntMaxC];
+  __shared__ double out[kIntMaxC];
+  const IntBlock B = blocks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nsn = B.s1 - B.s0;
+  for (int u = 0; u < nsn; ++u) {
+    const IntSn q = sns[FWD ? B.s0 + u : B.s1 - 1 - u];
+    if (!FWD) {
+      // in = w_k - L^O_k(in)^T t_in: a wave per column, its lanes down the rows
+      for (int col = wv; col < q.c; col += 4) {
+        double acc = 0.0;
+        for (int r = lane; r < q.rh; r += 64)
+          acc += (double)fac[q.lo + r + (int64_t)col * q.rh] * t[rows[q.rows + r]];
+        acc = wave_sum(acc);
+        if (lane == 0) in[col] = w[q.first + col] - acc;
+      }
+      __syncthreads();
+      // t_k = M_k in (M upper: row i needs columns m >= i)
+      for (int i = tid; i < q.c; i += 256) {
+        double acc = 0.0;
+        for (int m = i; m < q.c; ++m) acc += (double)fac[q.m + i + (int64_t)m * q.mld] * in[m];
+        t[q.first + i] = acc;
+      }
+      __syncthreads();
+    } else {
+      for (int i = tid; i < q.c; i += 256) in[i] = t[q.first + i];
+      __syncthreads();
+      // s_k = M_k^T s_k (column i of M: rows m <= i)
+      for (int i = tid; i < q.c; i += 256) {
+        double acc = 0.0;
+        for (int m = 0; m <= i; ++m) acc += (double)fac[q.m + m + (int64_t)i * q.mld] * in[m];
+        out[i] = acc;
+        t[q.first + i] = acc;
+      }
+      __syncthreads();
+      // s_in -= L^O_k(in) s_k, a thread per row
+      for (int r = tid; r < q.rh; r += 256) {
+        double acc = 0.0;
+        for (int i = 0; i < q.c; ++i) acc += (double)fac[q.lo + r + (int64_t)i * q.rh] * out[i];
+        t[rows[q.rows + r]] -= acc;
+      }
+      __syncthreads();
+    }
+  }
+  if (FWD)
+    for (int64_t i = B.a + tid; i < B.b; i += 256) w[i] -= t[i];
+}
+
+void launch_interior(const IntBlock* b, int n, bool fwd, const IntSn* sns, const double* arena, const float* f32,
+                     const int64_t* rows, double* w, double* t, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) {
+    if (fwd) hipLaunchKernelGGL((k_interior<float, true>), dim3(n), dim3(256), 0, s, b, sns, f32, rows, w, t);
+    else hipLaunchKernelGGL((k_interior<float, false>), dim3(n), dim3(256), 0, s, b, sns, f32, rows, w, t);
+  } else {
+    if (fwd) hipLaunchKernelGGL((k_interior<double, true>), dim3(n), dim3(256), 0, s, b, sns, arena, rows, w, t);
+    else hipLaunchKernelGGL((k_interior<double, false>), dim3(n), dim3(256), 0, s, b, sns, arena, rows, w, t);
+  }
+}
+
+// Coupling products with A over interior blocks: for target i,
+// out[tgt[i]] (-)= sum_e vals[vidx[e]] vec[xidx[e]] over e in [ptr[i], ptr[i+1]) (in list
+// order); `sub` subtracts from out, else it is assigned.  A thread per target.
+__global__ void k_coupling(const int64_t* __restrict__ tgt, const int64_t* __restrict__ ptr,
+                           const int64_t* __restrict__ vidx, const int64_t* __restrict__ xidx, int64_t n,
+                           const double* __restrict__ vals, const double* __restrict__ vec,
+                           double* __restrict__ out, int sub) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) acc += vals[vidx[e]] * vec[xidx[e]];
+  const int64_t o = tgt[i];
+  out[o] = sub ? out[o] - acc : acc;
+}
+
+void launch_coupling(const int64_t* tgt, const int64_t* ptr, const int64_t* vidx, const int64_t* xidx,
+                     int64_t n, const double* vals, const double* vec, double* out, bool sub, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_coupling, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tgt, ptr, vidx, xidx, n,
+                     vals, vec, out, sub ? 1 : 0);
+}
+
 void launch_gather_perm(int64_t n, const int64_t* perm, const double* src, double* dst, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(n)), dim3(256), 0, s, n, perm, src, dst);
 }

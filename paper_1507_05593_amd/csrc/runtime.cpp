@@ -106,6 +106,36 @@ void plan_layout(Handle& h) {
       h.sn_local[j] = (int32_t)(j - base);
     }
   }
+  // Interior blocks (Sec. 5.1): the maximal subtrees of the elimination tree holding no
+  // compressible supernode (the subdomains that the compressed separators cut out; a
+  // subtree's supernodes are consecutive, its root last).  With rsc_options.interior the
+  // rank-structured factor keeps of each of their L^O_j only the rows inside the block.
+  h.iroot.assign(M, -1);
+  h.r_in.assign(M, 0);
+  h.lo_in.assign(M, -1);
+  for (int64_t j = 0; j < M; ++j) h.r_in[j] = S.r(j);
+  const bool ib = h.opt.interior != 0;
+  if (ib) {
+    std::vector<char> clean(M, 0), kids_ok(M, 1);
+    std::vector<int64_t> size(M, 1);
+    for (int64_t j = 0; j < M; ++j) {   // children come before their parent
+      clean[j] = kids_ok[j] && !h.compressible[j] && S.c(j) <= kIntMaxC;
+      if (S.parent[j] >= 0) {
+        if (!clean[j]) kids_ok[S.parent[j]] = 0;
+        size[S.parent[j]] += size[j];
+      }
+    }
+    for (int64_t b = 0; b < M; ++b) {
+      if (!clean[b] || (S.parent[b] >= 0 && clean[S.parent[b]])) continue;
+      const int64_t end = S.first[b + 1];
+      for (int64_t k = b - size[b] + 1; k <= b; ++k) {
+        h.iroot[k] = (int32_t)b;
+        const int64_t* rb = S.rows.data() + S.rows_ptr[k];
+        h.r_in[k] = (int32_t)(std::lower_bound(rb, rb + S.r(k), end) - rb);
+      }
+    }
+  }
+  auto interior = [&](int64_t j) { return ib && h.iroot[j] >= 0 && S.r(j) > 0; };
   const int64_t n = S.n, nnz = S.nnz;
   const int32_t nseg = (int32_t)h.seg_first.size() - 1;
   // arena regions: values, PCG vectors, then the factor's persistent blocks, then the
@@ -122,6 +152,7 @@ void plan_layout(Handle& h) {
   h.a_s = a; a += align64(n);
   h.a_zz = a; a += align64(n);
   h.a_b = a; a += align64(n);
+  h.a_t = a; a += align64(n);
   h.a_zr = a; a += align64(std::max<int64_t>((int64_t)S.rows.size(), 1));
   // chunks of <= 256 rows inside one system
   int32_t nch = 0;
@@ -150,7 +181,7 @@ void plan_layout(Handle& h) {
   h.lo_off_exact.assign(M, -1);
   h.lo_off_comp.assign(M, -1);
   for (int64_t j = 0; j < M; ++j)
-    if (S.r(j) > 0 && !h.compressible[j]) {
+    if (S.r(j) > 0 && !h.compressible[j] && !interior(j)) {
       h.lo_off_exact[j] = h.lo_off_comp[j] = a;
       a += align64((int64_t)S.c(j) * S.r(j));
     }
@@ -160,7 +191,7 @@ void plan_layout(Handle& h) {
   const int64_t aX = a;
   int64_t ax = aX;
   for (int64_t j = 0; j < M; ++j)
-    if (h.compressible[j]) { h.lo_off_exact[j] = ax; ax += align64((int64_t)S.c(j) * S.r(j)); }
+    if (h.compressible[j] || interior(j)) { h.lo_off_exact[j] = ax; ax += align64((int64_t)S.c(j) * S.r(j)); }
   h.comp.assign(M, CompSlot());
   int32_t islot = 0;
   h.i_status = islot; islot += 4;
@@ -179,6 +210,9 @@ void plan_layout(Handle& h) {
     if (h.opt.keep_lo) { h.lo_off_comp[j] = ac; ac += align64((int64_t)c * r); }
     C.qslot = h.i_ranks + (int32_t)j;
   }
+  // interior blocks: the rows of L^O_j inside the block (r_in x c, ld r_in)
+  for (int64_t j = 0; j < M; ++j)
+    if (interior(j) && h.r_in[j] > 0) { h.lo_in[j] = ac; ac += align64((int64_t)h.r_in[j] * S.c(j)); }
   h.f32_end_exact = ax;
   h.f32_end_comp = ac;
   // Level pool: per elimination-tree level, U^O_j of its supernodes (assembled and
@@ -226,6 +260,11 @@ void plan_layout(Handle& h) {
         C.zdinv = p; p += ((l + 63) / 64) * 4096;
       }
     }
+    // interior blocks: the whole L^O_j of the level's interior supernodes, held only while
+    // the level is factored (its rows beyond the block feed the Schur updates' compact
+    // copies, then die)
+    for (int32_t j : S.by_level[L])
+      if (interior(j)) { h.lo_off_comp[j] = h.pool_base_comp + p; p += align64((int64_t)S.c(j) * S.r(j)); }
     h.lev_pool_comp[L] = p;
     pool_comp = std::max(pool_comp, p);
   }
@@ -1041,10 +1080,30 @@ struct Builder {
         t.nrows = std::min(kTile, r - r0);
         t.kdim = comp ? -(1 + h.comp[j].qslot) : S.c(j);
         t.kp = xc_kp[j];
+        // (an interior supernode's L^O_j sits in the level pool: the factor's FP32 copy
+        // takes only its rows inside the block, from their own storage)
+        t.f32 = in_block(j) ? -1 : t.src;
         P.compact.push_back(t);
       }
     }
     cmd(kCmdCompact, RSC_K_UPDATE, c0, (int64_t)P.compact.size() - c0, 0.0, lp_update);
+  }
+
+  // the rows of each interior supernode's L^O_j inside its block, from the level pool to
+  // the factor's own storage
+  bool in_block(int64_t j) const { return P.compressed && h.opt.interior && h.iroot[j] >= 0 && h.S.r(j) > 0; }
+  void interior_copy(const std::vector<int32_t>& level) {
+    const Symbolic& S = h.S;
+    const int64_t c0 = (int64_t)P.copy.size();
+    for (int32_t j : level) {
+      if (!in_block(j) || h.r_in[j] == 0) continue;
+      const int32_t c = S.c(j), r = S.r(j), ri = h.r_in[j];
+      for (int32_t j0 = 0; j0 < c; j0 += 64)
+        for (int32_t i0 = 0; i0 < ri; i0 += kConvRows)
+          P.copy.push_back(ConvTask{h.lo_off[j] + i0 + (int64_t)j0 * r, h.lo_in[j] + i0 + (int64_t)j0 * ri,
+                                    std::min(kConvRows, ri - i0), std::min(64, c - j0), r, ri});
+    }
+    cmd(kCmdCopy, RSC_K_OTHER, c0, (int64_t)P.copy.size() - c0, 0.0, 0);
   }
 
   // FP32 copy (mixed forms) of the factor operands the two sweeps of the preconditioner
@@ -1068,6 +1127,7 @@ struct Builder {
       add(h.panel_off[j] + c, h.panel_ld[j], h.m32_off[j], c, c, c, true);
       if (r == 0) continue;
       if (P.compressed && h.compressible[j]) add(h.comp[j].Uj, c, h.comp[j].Uj, c, c, h.comp[j].ell, false);
+      if (in_block(j) && h.r_in[j] > 0) add(h.lo_in[j], h.r_in[j], h.lo_in[j], h.r_in[j], h.r_in[j], c, false);
     }
     cmd(kCmdToF32, RSC_K_OTHER, c0, (int64_t)P.conv.size() - c0, 0.0, 0);
   }
@@ -1715,6 +1775,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
     if (!trees.empty()) B.diag_trees(trees);
     B.offdiag_solve(lev);
     B.compact_operands(lev, false);
+    if (compressed && h.opt.interior) B.interior_copy(lev);
     if (compressed) {
       B.compression(lev, tol);
       B.compact_operands(lev, true);
@@ -1771,6 +1832,7 @@ static Error build_factor_plan(Handle& h, bool compressed, double tol, int32_t p
   if ((e = upload(P->d_gs_n, P->gs_n)).code) return e;
   if ((e = upload(P->d_gs_m, P->gs_m)).code) return e;
   if ((e = upload(P->d_conv, P->conv)).code) return e;
+  if ((e = upload(P->d_copy, P->copy)).code) return e;
   // FP32 copy of the sweeps' operands: the compact M_j, dense L^O and region X of this layout
   const int64_t n32 = h.m32_size + (compressed ? h.f32_end_comp : h.f32_end_exact) - h.a_lo;
   if (!P->conv.empty() && h.arena32.n < n32) {
@@ -1849,7 +1911,8 @@ static const char* const kKernelNames[RSC_KERNELS] = {  // index = kernel_id()
     "trunc_compact", "assemble", "fill", "row_gather", "coldot", "row_part", "gemv_n",
     "gather", "part_apply", "other", "gemm_staged128_f64", "gemm_staged128_f32",
     "gemm_staged128_bf16x3", "gemm_staged128_bf16", "compact_rows", "gemm_reduce", "trunc_mfill",
-    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns", "sweep_fwd", "sweep_bwd", "gemm_potrf_f64"};
+    "trunc_flags", "trunc_copy", "to_f32", "trunc_ns", "sweep_fwd", "sweep_bwd", "gemm_potrf_f64",
+    "copy_f64", "interior_solve", "coupling"};
 
 int32_t kernel_id(int32_t type, int64_t a, int64_t b, bool post) {
   switch (type) {
@@ -1864,6 +1927,9 @@ int32_t kernel_id(int32_t type, int64_t a, int64_t b, bool post) {
     case kCmdTruncNs: return 35;
     case kCmdSweepFwd: return 36;
     case kCmdSweepBwd: return 37;
+    case kCmdCopy: return 39;
+    case kCmdInterior: return 40;
+    case kCmdCoupling: return 41;
     case kCmdPotrf: return 8;
     case kCmdPhilox: return 9;
     case kCmdGramScale: return 10;
@@ -1960,6 +2026,15 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
                         A + h.a_zr, A + h.a_y, s);
       break;
     case kCmdGatherPerm: launch_gather_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
+    case kCmdCopy: launch_copy_f64(P->d_copy.p + c.off, (int)c.count, A, s); break;
+    case kCmdInterior:
+      launch_interior(Q->d_iblocks.p + c.off, (int)c.count, c.a != 0, Q->d_isns.p, A, F32, h.d_rows.p, A + h.a_w,
+                      A + h.a_t, s);
+      break;
+    case kCmdCoupling:   // a = 0: y_R -= A(R, C) t (forward); a = 1: t_C = A(C, R) z (backward)
+      launch_coupling(Q->d_cp_tgt.p + c.off, Q->d_cp_ptr.p + c.off, Q->d_cp_vidx.p, Q->d_cp_xidx.p, c.count,
+                      A + h.a_values, A + (c.a ? h.a_zz : h.a_t), A + (c.a ? h.a_t : h.a_y), c.a == 0, s);
+      break;
     case kCmdScatterPerm: launch_scatter_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
     default: break;
   }
@@ -2207,6 +2282,11 @@ static Error build_solve_plan(Handle& h) {
   Q->f32_tasks = f32;
   auto m_off = [&](int64_t j) { return f32 ? h.m32_off[j] : h.panel_off[j] + S.c(j); };
   auto m_ld = [&](int64_t j) { return f32 ? S.c(j) : h.panel_ld[j]; };
+  // interior blocks (Sec. 5.1): the sweeps use only the rows of L^O_j inside the block
+  const bool ib = comp && h.opt.interior != 0;
+  auto inter = [&](int64_t j) { return ib && h.iroot[j] >= 0 && S.r(j) > 0; };
+  auto rr = [&](int64_t j) { return inter(j) ? h.r_in[j] : S.r(j); };          // rows of R_j used
+  auto lox = [&](int64_t j) { return inter(j) ? h.lo_in[j] : h.lo_off[j]; };   // their L^O_j
   double bytes = 0;
   // Small-supernode levels: the lowest levels whose supernodes all fit one workgroup
   // (at most sweep_small_c columns and kSweepMaxR rows) run each sweep step as one launch
@@ -2246,14 +2326,15 @@ static Error build_solve_plan(Handle& h) {
           lmax = std::max(lmax, C.ell);
           bytes += 2.0 * 8.0 * (double)(c + r) * C.ell;
         } else if (r > 0) {
-          t.x = h.lo_off[j];
-          bytes += 2.0 * 8.0 * (double)r * c;
+          t.x = lox(j);
+          t.r = rr(j);
+          bytes += 2.0 * 8.0 * (double)rr(j) * c;
         }
         bytes += 2.0 * 8.0 * c * (c + 1) / 2;
         Q->sweep.push_back(t);
         cmax = std::max(cmax, c);
         rmax = std::max(rmax, r);
-        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j + 1]; ++p) {
+        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j] + rr(j); ++p) {
           const int64_t row = S.rows[p];
           if (small_row(row)) ++ptr[row + 1];
           else outside.push_back({row, p});
@@ -2268,7 +2349,7 @@ static Error build_solve_plan(Handle& h) {
     std::vector<int64_t> next(ptr.begin(), ptr.end() - 1);
     for (int32_t L = 0; L < nsmall; ++L)
       for (int32_t j : S.by_level[L])
-        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j + 1]; ++p)
+        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j] + rr(j); ++p)
           if (small_row(S.rows[p])) Q->pull_idx[(size_t)next[S.rows[p]]++] = p;
     Q->pull_ptr = std::move(ptr);
     std::stable_sort(outside.begin(), outside.end(), [](const std::pair<int64_t, int64_t>& x,
@@ -2281,10 +2362,92 @@ static Error build_solve_plan(Handle& h) {
     c.a = sl.threads; c.b = sl.cpad; c.lds_l = sl.lpad; c.lds_r = sl.rmax;
     Q->fwd_bwd.push_back(c);
   };
+  // Interior blocks by the level of their root (eq. interiorBlockMult): forward, once the
+  // level is solved, t = (L^B)^{-T} w^B and y_{R^B} -= A(R^B, C^B) t; backward, before the
+  // level, t = A(C^B, R^B) z_{R^B}, t = (L^B)^{-1} t and w^B -= t.  A's entries are taken
+  // from the lower triangle of the original numbering, as the factorization takes them.
+  struct IntLevel { int64_t b0 = 0, nb = 0, f0 = 0, nf = 0, g0 = 0, ng = 0; };
+  std::vector<IntLevel> il(S.nlevels);
+  if (ib) {
+    auto lower_entry = [&](int64_t orow, int64_t ocol) {   // CSR index of A(max, min)
+      const int64_t i = std::max(orow, ocol), c = std::min(orow, ocol);
+      const int32_t* b = h.colind.data() + h.rowptr[i];
+      const int32_t* e = h.colind.data() + h.rowptr[i + 1];
+      return (int64_t)(std::lower_bound(b, e, (int32_t)c) - h.colind.data());
+    };
+    std::vector<std::vector<int32_t>> roots(S.nlevels);
+    for (int64_t b = 0; b < S.M(); ++b)
+      if (h.iroot[b] == b && S.r(b) > 0) roots[S.level[b]].push_back((int32_t)b);
+    for (int32_t L = 0; L < S.nlevels; ++L) {
+      IntLevel& q = il[L];
+      q.b0 = (int64_t)Q->iblocks.size();
+      q.g0 = (int64_t)Q->cp_tgt.size();          // backward targets: the blocks' columns
+      std::vector<std::array<int64_t, 3>> fe;   // (target row, column, value index)
+      for (int32_t b : roots[L]) {
+        int64_t s0 = b;
+        while (s0 > 0 && h.iroot[s0 - 1] == b) --s0;
+        IntBlock B{};
+        B.s0 = (int32_t)Q->isns.size(); B.a = S.first[s0]; B.b = S.first[b + 1];
+        for (int64_t k = s0; k <= b; ++k) {
+          IntSn t{};
+          t.m = m_off(k); t.mld = m_ld(k); t.lo = h.r_in[k] > 0 ? h.lo_in[k] : 0; t.rh = h.r_in[k];
+          t.rows = S.rows_ptr[k]; t.first = S.first[k]; t.c = S.c(k);
+          Q->isns.push_back(t);
+          bytes += 2.0 * 8.0 * ((double)t.c * (t.c + 1) / 2 + (double)t.rh * t.c);
+        }
+        B.s1 = (int32_t)Q->isns.size();
+        Q->iblocks.push_back(B);
+        // backward coupling: every column of the block (zero when it has no entry)
+        for (int64_t cn = B.a; cn < B.b; ++cn) {
+          const int64_t old = S.perm[cn];
+          std::vector<std::pair<int64_t, int64_t>> ent;   // (row, value index)
+          for (int64_t p = h.rowptr[old]; p < h.rowptr[old + 1]; ++p) {
+            const int64_t rn = S.iperm[h.colind[p]];
+            if (rn >= B.b) {
+              ent.push_back({rn, lower_entry(old, h.colind[p])});
+              fe.push_back({rn, cn, ent.back().second});
+            }
+          }
+          std::sort(ent.begin(), ent.end());
+          Q->cp_tgt.push_back(cn);
+          Q->cp_ptr.push_back((int64_t)Q->cp_vidx.size());
+          for (auto& e : ent) { Q->cp_vidx.push_back(e.second); Q->cp_xidx.push_back(e.first); }
+          bytes += 24.0 * (double)ent.size() + 8.0;
+        }
+      }
+      q.nb = (int64_t)Q->iblocks.size() - q.b0;
+      q.ng = (int64_t)Q->cp_tgt.size() - q.g0;
+      // forward coupling: each target row once, its entries by column
+      std::sort(fe.begin(), fe.end());
+      q.f0 = (int64_t)Q->cp_tgt.size();
+      for (size_t u = 0; u < fe.size(); ++u) {
+        if (u == 0 || fe[u][0] != fe[u - 1][0]) {
+          Q->cp_tgt.push_back(fe[u][0]);
+          Q->cp_ptr.push_back((int64_t)Q->cp_vidx.size());
+        }
+        Q->cp_vidx.push_back(fe[u][2]);
+        Q->cp_xidx.push_back(fe[u][1]);
+      }
+      q.nf = (int64_t)Q->cp_tgt.size() - q.f0;
+      bytes += 24.0 * (double)fe.size() + 16.0 * (double)q.nf;
+    }
+    Q->cp_ptr.push_back((int64_t)Q->cp_vidx.size());
+  }
+  auto fwd_tail = [&](int32_t L) {
+    if (!ib || il[L].nb == 0) return;
+    cmd(kCmdInterior, il[L].b0, il[L].nb, 0);
+    cmd(kCmdCoupling, il[L].f0, il[L].nf, 0);
+  };
+  auto bwd_tail = [&](int32_t L) {
+    if (!ib || il[L].nb == 0) return;
+    cmd(kCmdCoupling, il[L].g0, il[L].ng, 1);
+    cmd(kCmdInterior, il[L].b0, il[L].nb, 1);
+  };
   // forward sweep, levels ascending
   for (int32_t L = 0; L < S.nlevels; ++L) {
     if (L < nsmall) {
       small_cmd(kCmdSweepFwd, small[L]);
+      fwd_tail(L);
       continue;
     }
     if (L == nsmall && !outside.empty()) {
@@ -2331,14 +2494,14 @@ static Error build_solve_plan(Handle& h) {
     {
       const int64_t g0 = (int64_t)Q->gemv.size();
       for (int32_t j : lev) {
-        const int32_t c = S.c(j), r = S.r(j);
+        const int32_t c = S.c(j), r = rr(j);
         for (int32_t t0 = 0; t0 < r; t0 += 64) {
           GemvTask t{};
           if (iscomp(j)) {
             const CompSlot& C = h.comp[j];
             t.x = C.Vj + t0; t.kdim = -(1 + C.qslot); t.kmax = C.ell; t.v = C.tvq;
           } else {
-            t.x = h.lo_off[j] + t0; t.kdim = c; t.kmax = c; t.v = h.a_w + S.first[j];
+            t.x = lox(j) + t0; t.kdim = c; t.kmax = c; t.v = h.a_w + S.first[j];
           }
           t.ldx = r; t.rows = std::min(64, r - t0);
           t.out = h.a_zr + S.rows_ptr[j] + t0;
@@ -2351,7 +2514,7 @@ static Error build_solve_plan(Handle& h) {
     {
       std::vector<std::pair<int64_t, int64_t>> tc;   // (target row, zr index)
       for (int32_t j : lev)
-        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j + 1]; ++p) tc.push_back({S.rows[p], p});
+        for (int64_t p = S.rows_ptr[j]; p < S.rows_ptr[j] + rr(j); ++p) tc.push_back({S.rows[p], p});
       std::stable_sort(tc.begin(), tc.end(), [](const std::pair<int64_t, int64_t>& x,
                                                 const std::pair<int64_t, int64_t>& y) { return x.first < y.first; });
       const int64_t r0 = (int64_t)Q->rg_rows.size();
@@ -2365,10 +2528,12 @@ static Error build_solve_plan(Handle& h) {
       const int64_t nr = (int64_t)Q->rg_rows.size() - r0;
       if (nr > 0) cmd(kCmdRowGather, r0, nr, r0);
     }
+    fwd_tail(L);
   }
   Q->rg_ptr.push_back((int64_t)Q->rg_contrib.size());
   // backward sweep, levels descending
   for (int32_t L = S.nlevels - 1; L >= 0; --L) {
+    bwd_tail(L);
     if (L < nsmall) {
       small_cmd(kCmdSweepBwd, small[L]);
       continue;
@@ -2378,9 +2543,9 @@ static Error build_solve_plan(Handle& h) {
     {
       const int64_t g0q = (int64_t)Q->gath.size() / 2;
       for (int32_t j : lev)
-        for (int32_t t0 = 0; t0 < S.r(j); t0 += 1024) {   // pieces of <= 1024 rows, one workgroup each
+        for (int32_t t0 = 0; t0 < rr(j); t0 += 1024) {   // pieces of <= 1024 rows, one workgroup each
           Q->gath.push_back(S.rows_ptr[j] + t0);
-          Q->gath.push_back(std::min(1024, S.r(j) - t0));
+          Q->gath.push_back(std::min(1024, rr(j) - t0));
         }
       const int64_t ng = (int64_t)Q->gath.size() / 2 - g0q;
       if (ng > 0) {
@@ -2403,14 +2568,15 @@ static Error build_solve_plan(Handle& h) {
           st.push_back(t);
         }
       } else {
+        if (rr(j) == 0) continue;   // an interior supernode with no rows inside its block
         for (int32_t col0 = 0; col0 < c; col0 += 16) {
           ColDotTask t{};
-          t.x = h.lo_off[j]; t.ldx = r; t.in = h.a_zr + S.rows_ptr[j];
+          t.x = lox(j); t.ldx = rr(j); t.in = h.a_zr + S.rows_ptr[j];
           t.idx = -1; t.out = h.a_s + S.first[j];
-          t.rows = r; t.ncols = c; t.col0 = col0; t.tri = 0;
+          t.rows = rr(j); t.ncols = c; t.col0 = col0; t.tri = 0;
           st.push_back(t);
         }
-        bytes += 2.0 * 8.0 * (double)r * c;   // read by both sweeps
+        bytes += 2.0 * 8.0 * (double)rr(j) * c;   // read by both sweeps
       }
     }
     coldot_stage(st);
@@ -2445,7 +2611,7 @@ static Error build_solve_plan(Handle& h) {
           for (int32_t t0 = i0; t0 < c; t0 += width) {
             RowChunk t{};
             t.m = m_off(j); t.ld = m_ld(j); t.c = c; t.i0 = i0;
-            t.w = h.a_w + S.first[j]; t.s = r > 0 ? h.a_s + S.first[j] : -1;
+            t.w = h.a_w + S.first[j]; t.s = (iscomp(j) ? r : rr(j)) > 0 ? h.a_s + S.first[j] : -1;
             t.t0 = t0; t.t1 = std::min(c, t0 + width); t.slot = slot++;
             Q->rchunks.push_back(t);
           }
@@ -2461,6 +2627,12 @@ static Error build_solve_plan(Handle& h) {
   Q->bytes = bytes;
   Error e;
   if ((e = upload(Q->d_gemv, Q->gemv)).code) return e;
+  if ((e = upload(Q->d_iblocks, Q->iblocks)).code) return e;
+  if ((e = upload(Q->d_isns, Q->isns)).code) return e;
+  if ((e = upload(Q->d_cp_tgt, Q->cp_tgt)).code) return e;
+  if ((e = upload(Q->d_cp_ptr, Q->cp_ptr)).code) return e;
+  if ((e = upload(Q->d_cp_vidx, Q->cp_vidx)).code) return e;
+  if ((e = upload(Q->d_cp_xidx, Q->cp_xidx)).code) return e;
   if ((e = upload(Q->d_coldot, Q->coldot)).code) return e;
   if ((e = upload(Q->d_rchunks, Q->rchunks)).code) return e;
   if ((e = upload(Q->d_papply, Q->papply)).code) return e;

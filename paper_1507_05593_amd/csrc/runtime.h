@@ -26,7 +26,8 @@ enum CmdType : int32_t {
   kCmdPhilox, kCmdGramScale, kCmdTruncPrep, kCmdTruncPower, kCmdTruncX0, kCmdTruncP, kCmdTruncCompact,
   kCmdGemvN, kCmdColDot, kCmdRowPart, kCmdPartApply, kCmdRowGather, kCmdGatherPerm, kCmdScatterPerm,
   kCmdGatherRows, kCmdCompact, kCmdGemmReduce, kCmdTruncMfill, kCmdTruncFlags, kCmdTruncCopy,
-  kCmdToF32, kCmdTruncNs, kCmdAssembleLevel, kCmdSweepFwd, kCmdSweepBwd,
+  kCmdToF32, kCmdTruncNs, kCmdAssembleLevel, kCmdSweepFwd, kCmdSweepBwd, kCmdCopy, kCmdInterior,
+  kCmdCoupling,
 };
 
 // Kernel identity of a command for the per-kernel profile (index into kernel_name()).
@@ -125,6 +126,7 @@ struct FactorPlan {
   std::vector<int64_t> gs_g, gs_out;
   std::vector<int32_t> gs_ld, gs_n, gs_m;   // gs_m > 0: shifted Cholesky-QR pass over gs_m rows
   std::vector<ConvTask> conv;         // FP32 copy of the sweeps' operands (mixed forms)
+  std::vector<ConvTask> copy;         // interior blocks: L^O_k's rows inside the block, pool -> factor
   DevArray<GemmTask> d_gemm;
   DevArray<UpdTile> d_tiles;
   DevArray<UpdEntry> d_ents;
@@ -137,6 +139,7 @@ struct FactorPlan {
   DevArray<int64_t> d_gs_g, d_gs_out;
   DevArray<int32_t> d_gs_ld, d_gs_n, d_gs_m;
   DevArray<ConvTask> d_conv;
+  DevArray<ConvTask> d_copy;
   hipGraphExec_t graph = nullptr;
   double flops[6] = {0, 0, 0, 0, 0, 0};  // potrf, trsm, update, sample, orth, trunc
 };
@@ -162,6 +165,13 @@ struct SolvePlan {
   DevArray<double> d_part;
   DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib, d_gath;
   DevArray<SweepTask> d_sweep;
+  // interior blocks (Sec. 5.1): the block solves and A's coupling products of each level
+  std::vector<IntBlock> iblocks;
+  std::vector<IntSn> isns;
+  std::vector<int64_t> cp_tgt, cp_ptr, cp_vidx, cp_xidx;
+  DevArray<IntBlock> d_iblocks;
+  DevArray<IntSn> d_isns;
+  DevArray<int64_t> d_cp_tgt, d_cp_ptr, d_cp_vidx, d_cp_xidx;
   DevArray<int64_t> d_pull_ptr, d_pull_idx;
   hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
   double bytes = 0;                   // factor bytes read by one apply
@@ -202,6 +212,12 @@ struct Handle {
   std::vector<int64_t> lev_pool_comp;  // per level: its rank-structured pool end before the trees
   int64_t pool_comp_plain = 0;         // the largest of those
   int32_t diag_restarts = 0;           // refactorizations with a larger alpha_D (Sec. 5.3)
+  // interior blocks (Sec. 5.1, rank-structured layout with rsc_options.interior): per
+  // supernode the root of its block (-1: not in one), the rows of R_j inside the block
+  // (r_j otherwise) and the arena offset of those rows of L^O_j kept by the factor
+  std::vector<int32_t> iroot;
+  std::vector<int32_t> r_in;
+  std::vector<int64_t> lo_in;
   std::vector<int64_t> ident_slot;
   std::vector<int32_t> compressible;  // separator with c >= tau_O and r > 0
   std::vector<int32_t> sn_local;      // supernode index within its own system (sample key)
@@ -232,6 +248,7 @@ struct Handle {
   // arena regions
   int64_t a_values = 0, a_panels = 0;
   int64_t a_x, a_r, a_z, a_p, a_Ap, a_y, a_w, a_s, a_zz, a_b, a_zr, a_partial, a_seg;
+  int64_t a_t = 0;                    // interior blocks' solve vector (n)
   PcgScalars sc{};
   int32_t i_status = 0, i_ranks = 0;
   std::vector<CompSlot> comp;         // per supernode (compressible ones only)

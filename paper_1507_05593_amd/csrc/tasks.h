@@ -64,6 +64,7 @@ struct UpdEntry {
 struct CompactTask {
   int64_t src, dst;
   int32_t ld, nrows, kdim, kp;
+  int64_t f32;                 // offset of the block's FP32 column-major copy, or -1 for none
 };
 
 // Cholesky of one diagonal block (<= 64) of a panel plus the explicit inverse of
@@ -168,6 +169,19 @@ struct RowChunk {
 // M(i, t) = F[m + i + t*ld]); the off-diagonal operand X is L^O_j (r x c) or, compressed,
 // V_j (r x l) with U_j (c x l, ld c) and the rank in the int arena; both column major.
 constexpr int32_t kSweepMaxR = 2048;   // rows R_j of a small-sweep supernode (LDS)
+// Interior blocks (Sec. 5.1): the supernodes of one block are consecutive tasks.
+struct IntSn {
+  int64_t m;                   // M_k = (L^D_k)^{-T}, upper triangular, M(i, t) at m + i + t*mld
+  int64_t lo;                  // the rows of L^O_k inside the block (rh x c, ld rh)
+  int64_t rows;                // offset of R_k in the row list (its first rh rows are those)
+  int64_t first;               // first column (permuted index)
+  int32_t c, mld, rh, pad_;
+};
+struct IntBlock {
+  int32_t s0, s1;              // its supernodes: tasks [s0, s1)
+  int64_t a, b;                // its columns [a, b)
+};
+
 struct SweepTask {
   int64_t m, x, u;             // u < 0: explicit L^O_j
   int64_t first;               // first column of the supernode (permuted index)

@@ -61,7 +61,7 @@ def use_torch_allocator(on: bool = True) -> None:
 
 def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.0, seed=0,
                  precision="fp64", use_graph=True, retry=True, gemm_tile=0, keep_lo=False,
-                 sweep_small_c=64, tau_D=0, alpha_D=0.5) -> Options:
+                 sweep_small_c=64, tau_D=0, alpha_D=0.5, interior=False) -> Options:
     o = Options()
     lib().rsc_default_options(C.byref(o))
     o.leaf_max, o.tau_O, o.oversample, o.power_iters = leaf_max, tau_O, oversample, power_iters
@@ -72,6 +72,7 @@ def make_options(leaf_max=64, tau_O=32, oversample=10, power_iters=0, alpha_O=1.
     o.keep_lo = int(bool(keep_lo))
     o.sweep_small_c = int(sweep_small_c)
     o.tau_D, o.alpha_D = int(tau_D), float(alpha_D)
+    o.interior = int(bool(interior))
     return o
 
 
