@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-spectral", action="store_true", help="skip the spectral-coordinates timing")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying hipGraphs")
+    ap.add_argument("--no-interior", action="store_true", help="skip the interior-block run")
     ap.add_argument("--tree-tau", type=int, default=512,
                     help="tau_D of the diagonal block-tree run timed beside (0 to skip)")
     ap.add_argument("--gemm-tile", type=int, default=0, choices=[0, 64, 128],
@@ -172,16 +173,12 @@ def spectral_line(pattern, m=20, reps=3):
                          "frac": round(gbs / 8000.0, 4), "bytes": byt}}
 
 
-def tree_line(cfg, p, vals, b, precision, tau, steps=2, warmup=1):
-    """Factor + PCG with diagonal block trees (paper Sec. 4.1-4.2, 5.3): separators of more
-    than tau columns store L^D_j as a block tree, ordered by the grid positions."""
-    import numpy as np
+def variant_run(cfg, p, vals, b, precision, steps=2, warmup=1, **opts):
+    """Factor + PCG on the workload with extra solver options, timed like the headline."""
     import torch
     from paper_1507_05593_amd import RSCSolver
-    from workloads import grid_coordinates
-    xyz = grid_coordinates(p.dims)
     t0 = time.perf_counter()
-    sol = RSCSolver(p.n, p.rowptr, p.colind, coords=xyz, tau_D=tau, precision=precision, seed=0)
+    sol = RSCSolver(p.n, p.rowptr, p.colind, precision=precision, seed=0, **opts)
     t_an = time.perf_counter() - t0
     info = None
     for _ in range(warmup):
@@ -196,18 +193,36 @@ def tree_line(cfg, p, vals, b, precision, tau, steps=2, warmup=1):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     st = sol.stats()
+    out = {"precision": precision, "ms_per_step": round(1e3 * dt, 3), "factor_ms": round(fms / steps, 3),
+           "pcg_ms": round(pms / steps, 3), "pcg_iters": info["iters"], "true_residual": info["true_residual"],
+           "analyze_s": round(t_an, 3), "factor_entries": st["factor_entries"],
+           "device_gb": round(st["device_bytes"] / 1e9, 2),
+           "apply_gb": round(st["bytes_factor"] / 1e9, 3)}
+    return sol, st, out
+
+
+def tree_line(cfg, p, vals, b, precision, tau):
+    """Diagonal block trees (paper Sec. 4.1-4.2, 5.3): separators of more than tau columns
+    store L^D_j as a block tree, ordered by the grid positions."""
+    import numpy as np
+    from workloads import grid_coordinates
+    sol, st, out = variant_run(cfg, p, vals, b, precision, coords=grid_coordinates(p.dims), tau_D=tau)
     first, _, _, _ = sol.supernode_info()
     c = np.diff(first)[sol.tree_depths > 0].astype(np.int64)
-    out = {"tau_D": tau, "positions": "grid", "precision": precision, "ms_per_step": round(1e3 * dt, 3),
-           "factor_ms": round(fms / steps, 3), "pcg_ms": round(pms / steps, 3), "pcg_iters": info["iters"],
-           "true_residual": info["true_residual"], "analyze_s": round(t_an, 3),
-           "tree_supernodes": st["tree_supernodes"], "tree_blocks": st["tree_blocks"],
-           "tree_rank_sum": st["tree_rank_sum"], "tree_entries": st["tree_entries"],
-           "dense_diag_entries": int(np.sum(c * (c + 1) // 2)),
-           "factor_entries": st["factor_entries"], "alpha_D": st["alpha_D_used"],
-           "restarts": st["diag_restarts"], "device_gb": round(st["device_bytes"] / 1e9, 2)}
+    out.update({"tau_D": tau, "positions": "grid", "tree_supernodes": st["tree_supernodes"],
+                "tree_blocks": st["tree_blocks"], "tree_rank_sum": st["tree_rank_sum"],
+                "tree_entries": st["tree_entries"], "dense_diag_entries": int(np.sum(c * (c + 1) // 2)),
+                "alpha_D": st["alpha_D_used"], "restarts": st["diag_restarts"]})
     del sol
-    torch.cuda.synchronize()
+    return out
+
+
+def interior_line(cfg, p, vals, b, precision):
+    """Interior blocks (paper Sec. 5.1): the factor keeps only the rows of each interior
+    supernode's L^O_j inside its block; the sweeps reach the rest through A."""
+    sol, st, out = variant_run(cfg, p, vals, b, precision, interior=True)
+    out.update({"interior_blocks": st["interior_blocks"], "dropped_entries": st["interior_dropped"]})
+    del sol
     return out
 
 
@@ -645,6 +660,7 @@ def main():
     line["factor_tflop"] = round(fl / 1e12, 4)
     line["factor_tflop_per_s"] = round(fl / (res["factor_ms"] * 1e-3) / 1e12, 3)
     line["device_gb"] = round(st["device_bytes"] / 1e9, 2)
+    line["factor_entries"] = st["factor_entries"]
     line["tile_tuner"] = {"launches_tuned": st["gemm_tuned"], "launches_128": st["gemm_tile128"]}
     if cmp:
         line["fp64_form" if compare == "fp64" else "compare_form"] = {
@@ -670,6 +686,8 @@ def main():
         line["spectral_coordinates"] = spectral_line(pattern)
     if not batched and args.tree_tau > 0 and len(p.dims) == 3 and extra is None:
         line["diag_trees"] = tree_line(cfg, p, vals, b, precision, args.tree_tau)
+    if not batched and not args.no_interior and extra is None and cfg["tol"] > 0:
+        line["interior_blocks"] = interior_line(cfg, p, vals, b, precision)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(name, cfg, args.cpu_sample_side, desc)
     print(json.dumps(line), flush=True)

@@ -47,8 +47,9 @@ void launch_to_f32(const ConvTask* t, int n, const double* arena, float* f32, hi
 void launch_copy_f64(const ConvTask* t, int n, double* arena, hipStream_t s);
 // interior blocks: the block solves and A's coupling products
 constexpr int kIntMaxC = 1024;   // largest supernode of an interior block
-void launch_interior(const IntBlock* b, int n, bool fwd, const IntSn* sns, const double* arena, const float* f32,
-                     const int64_t* rows, double* w, double* t, hipStream_t s);
+void launch_interior(const IntSn* sns, int n, bool fwd, const double* arena, const float* f32,
+                     const int64_t* rows, const int64_t* pull_ptr, const int64_t* pull_idx, double* w,
+                     double* t, double* zr, hipStream_t s);
 void launch_coupling(const int64_t* tgt, const int64_t* ptr, const int64_t* vidx, const int64_t* xidx,
                      int64_t n, const double* vals, const double* vec, double* out, bool sub, hipStream_t s);
 void launch_part_apply(const PartApply* t, int n, const double* part, double* arena, hipStream_t s);

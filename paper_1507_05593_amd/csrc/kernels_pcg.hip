@@ -587,77 +587,104 @@ void launch_sweep_bwd(const SweepTask* t, int n, int nt, int cpad, int lpad, int
     hipLaunchKernelGGL(k_sweep_bwd<double>, dim3(n), dim3(nt), lds, s, t, arena + a_w, arena + a_zz,
                        (const double*)arena, ilim, rows_idx, cpad, lpad);
 }
-// Interior blocks (Sec. 5.1), one workgroup (256 threads) per block, its supernodes in
-// turn (a block is a subtree: every row of a supernode's L^O_k inside the block belongs
-// to a later supernode of it).  The block's off-diagonal rows beyond it are not stored;
-// the sweeps reach them through A's coupling entries and these solves with the block's
-// own factor L^B = L(C^B, C^B) (eq. interiorBlockMult):
-//  !FWD: t = (L^B)^{-T} w, supernodes last to first: t_k = M_k (w_k - L^O_k(in)^T t_in);
-//   FWD: s = (L^B)^{-1} s in place (s in t), supernodes in order: s_k = M_k^T s_k, then
-//        s_in -= L^O_k(in) s_k; then w -= s over the block's columns.
+// Interior blocks (Sec. 5.1): a step of a solve with a block's own factor L^B =
+// L(C^B, C^B), one workgroup (256 threads) per supernode, the supernodes of one
+// elimination-tree level in one launch.  The block's off-diagonal rows beyond it are not
+// stored; the sweeps reach them through A's coupling entries and these solves (eq.
+// interiorBlockMult):
+//  !FWD (levels from the block's root down): t_k = M_k (w_k - L^O_k(in)^T t_in), t = (L^B)^{-T} w;
+//   FWD (levels up to the root): s_k = M_k^T (s_k - the pulled products of its
+//        descendants), then L^O_k(in) s_k into the k's row slots of zr (pulled by the
+//        supernodes owning those rows, in a fixed order); the root then takes w -= s over
+//        the block's columns: s = (L^B)^{-1} s.
 // Factor operands from `fac` (the FP64 arena or its FP32 copy), vectors FP64.
 template <typename TF, bool FWD>
-__global__ void __launch_bounds__(256) k_interior(const IntBlock* __restrict__ blocks,
-                                                  const IntSn* __restrict__ sns, const TF* __restrict__ fac,
-                                                  const int64_t* __restrict__ rows, double* __restrict__ w,
-                                                  double* __restrict__ t) {
+__global__ void __launch_bounds__(256) k_interior(const IntSn* __restrict__ sns, const TF* __restrict__ fac,
+                                                  const int64_t* __restrict__ rows,
+                                                  const int64_t* __restrict__ pull_ptr,
+                                                  const int64_t* __restrict__ pull_idx, double* __restrict__ w,
+                                                  double* __restrict__ t, double* __restrict__ zr) {
   __shared__ double in[kIntMaxC];
   __shared__ double out[kIntMaxC];
-  const IntBlock B = blocks[blockIdx.x];
+  __shared__ double red[4][64];
+  const IntSn q = sns[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nsn = B.s1 - B.s0;
-  for (int u = 0; u < nsn; ++u) {
-    const IntSn q = sns[FWD ? B.s0 + u : B.s1 - 1 - u];
-    if (!FWD) {
-      // in = w_k - L^O_k(in)^T t_in: a wave per column, its lanes down the rows
+  if (!FWD) {
+    // in = w_k - L^O_k(in)^T t_in: t over the rows gathered into LDS (`out`) a chunk at a
+    // time, then a wave per column, its lanes down the rows
+    for (int i = tid; i < q.c; i += 256) in[i] = w[q.first + i];
+    for (int r0 = 0; r0 < q.rh; r0 += kIntMaxC) {
+      const int nr = min(kIntMaxC, q.rh - r0);
+      __syncthreads();
+      for (int r = tid; r < nr; r += 256) out[r] = t[rows[q.rows + r0 + r]];
+      __syncthreads();
       for (int col = wv; col < q.c; col += 4) {
+        const TF* L = fac + q.lo + r0 + (int64_t)col * q.rh;
         double acc = 0.0;
-        for (int r = lane; r < q.rh; r += 64)
-          acc += (double)fac[q.lo + r + (int64_t)col * q.rh] * t[rows[q.rows + r]];
+#pragma unroll 4
+        for (int r = lane; r < nr; r += 64) acc += (double)L[r] * out[r];
         acc = wave_sum(acc);
-        if (lane == 0) in[col] = w[q.first + col] - acc;
+        if (lane == 0) in[col] -= acc;
       }
-      __syncthreads();
-      // t_k = M_k in (M upper: row i needs columns m >= i)
-      for (int i = tid; i < q.c; i += 256) {
-        double acc = 0.0;
-        for (int m = i; m < q.c; ++m) acc += (double)fac[q.m + i + (int64_t)m * q.mld] * in[m];
-        t[q.first + i] = acc;
+    }
+    __syncthreads();
+    // t_k = M_k in, 64 rows at a time: the lanes on the rows, the waves on every fourth
+    // column (one coalesced column segment per step), then the four parts added
+    for (int i0 = 0; i0 < q.c; i0 += 64) {
+      const int i = i0 + lane;
+      double acc = 0.0;
+      if (i < q.c) {
+#pragma unroll 4
+        for (int m = i0 + wv; m < q.c; m += 4) acc += (double)fac[q.m + i + (int64_t)m * q.mld] * in[m];
       }
+      red[wv][lane] = acc;      // (M upper: the terms m < i are zeros of M)
       __syncthreads();
-    } else {
-      for (int i = tid; i < q.c; i += 256) in[i] = t[q.first + i];
-      __syncthreads();
-      // s_k = M_k^T s_k (column i of M: rows m <= i)
-      for (int i = tid; i < q.c; i += 256) {
-        double acc = 0.0;
-        for (int m = 0; m <= i; ++m) acc += (double)fac[q.m + m + (int64_t)i * q.mld] * in[m];
-        out[i] = acc;
-        t[q.first + i] = acc;
-      }
-      __syncthreads();
-      // s_in -= L^O_k(in) s_k, a thread per row
-      for (int r = tid; r < q.rh; r += 256) {
-        double acc = 0.0;
-        for (int i = 0; i < q.c; ++i) acc += (double)fac[q.lo + r + (int64_t)i * q.rh] * out[i];
-        t[rows[q.rows + r]] -= acc;
-      }
+      if (wv == 0 && i < q.c) t[q.first + i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
       __syncthreads();
     }
+  } else {
+    // in = s_k minus the products its descendants in the block left in zr for its rows
+    for (int i = tid; i < q.c; i += 256) {
+      const int64_t row = q.first + i;
+      double v = t[row];
+      for (int64_t e = pull_ptr[row]; e < pull_ptr[row + 1]; ++e) v -= zr[pull_idx[e]];
+      in[i] = v;
+    }
+    __syncthreads();
+    // s_k = M_k^T in: a wave per column i of M, its lanes down the rows m <= i
+    for (int i = wv; i < q.c; i += 4) {
+      double acc = 0.0;
+#pragma unroll 2
+      for (int m = lane; m <= i; m += 64) acc += (double)fac[q.m + m + (int64_t)i * q.mld] * in[m];
+      acc = wave_sum(acc);
+      if (lane == 0) { out[i] = acc; t[q.first + i] = acc; }
+    }
+    __syncthreads();
+    // its products for the rows inside the block, one slot per row of R_k
+    for (int r = tid; r < q.rh; r += 256) {
+      const TF* L = fac + q.lo + r;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < q.c; ++i) acc += (double)L[(int64_t)i * q.rh] * out[i];
+      zr[q.rows + r] = acc;
+    }
+    if (q.root) {
+      __syncthreads();
+      for (int64_t i = q.a + tid; i < q.b; i += 256) w[i] -= t[i];
+    }
   }
-  if (FWD)
-    for (int64_t i = B.a + tid; i < B.b; i += 256) w[i] -= t[i];
 }
 
-void launch_interior(const IntBlock* b, int n, bool fwd, const IntSn* sns, const double* arena, const float* f32,
-                     const int64_t* rows, double* w, double* t, hipStream_t s) {
+void launch_interior(const IntSn* sns, int n, bool fwd, const double* arena, const float* f32,
+                     const int64_t* rows, const int64_t* pull_ptr, const int64_t* pull_idx, double* w,
+                     double* t, double* zr, hipStream_t s) {
   if (n <= 0) return;
   if (f32) {
-    if (fwd) hipLaunchKernelGGL((k_interior<float, true>), dim3(n), dim3(256), 0, s, b, sns, f32, rows, w, t);
-    else hipLaunchKernelGGL((k_interior<float, false>), dim3(n), dim3(256), 0, s, b, sns, f32, rows, w, t);
+    if (fwd) hipLaunchKernelGGL((k_interior<float, true>), dim3(n), dim3(256), 0, s, sns, f32, rows, pull_ptr, pull_idx, w, t, zr);
+    else hipLaunchKernelGGL((k_interior<float, false>), dim3(n), dim3(256), 0, s, sns, f32, rows, pull_ptr, pull_idx, w, t, zr);
   } else {
-    if (fwd) hipLaunchKernelGGL((k_interior<double, true>), dim3(n), dim3(256), 0, s, b, sns, arena, rows, w, t);
-    else hipLaunchKernelGGL((k_interior<double, false>), dim3(n), dim3(256), 0, s, b, sns, arena, rows, w, t);
+    if (fwd) hipLaunchKernelGGL((k_interior<double, true>), dim3(n), dim3(256), 0, s, sns, arena, rows, pull_ptr, pull_idx, w, t, zr);
+    else hipLaunchKernelGGL((k_interior<double, false>), dim3(n), dim3(256), 0, s, sns, arena, rows, pull_ptr, pull_idx, w, t, zr);
   }
 }
 

@@ -2028,8 +2028,8 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdGatherPerm: launch_gather_perm(h.S.n, h.d_perm.p, A + c.a, A + c.b, s); break;
     case kCmdCopy: launch_copy_f64(P->d_copy.p + c.off, (int)c.count, A, s); break;
     case kCmdInterior:
-      launch_interior(Q->d_iblocks.p + c.off, (int)c.count, c.a != 0, Q->d_isns.p, A, F32, h.d_rows.p, A + h.a_w,
-                      A + h.a_t, s);
+      launch_interior(Q->d_isns.p + c.off, (int)c.count, c.a != 0, A, F32, h.d_rows.p, Q->d_ipull_ptr.p,
+                      Q->d_ipull_idx.p, A + h.a_w, A + h.a_t, A + h.a_zr, s);
       break;
     case kCmdCoupling:   // a = 0: y_R -= A(R, C) t (forward); a = 1: t_C = A(C, R) z (backward)
       launch_coupling(Q->d_cp_tgt.p + c.off, Q->d_cp_ptr.p + c.off, Q->d_cp_vidx.p, Q->d_cp_xidx.p, c.count,
@@ -2363,10 +2363,15 @@ static Error build_solve_plan(Handle& h) {
     Q->fwd_bwd.push_back(c);
   };
   // Interior blocks by the level of their root (eq. interiorBlockMult): forward, once the
-  // level is solved, t = (L^B)^{-T} w^B and y_{R^B} -= A(R^B, C^B) t; backward, before the
-  // level, t = A(C^B, R^B) z_{R^B}, t = (L^B)^{-1} t and w^B -= t.  A's entries are taken
-  // from the lower triangle of the original numbering, as the factorization takes them.
-  struct IntLevel { int64_t b0 = 0, nb = 0, f0 = 0, nf = 0, g0 = 0, ng = 0; };
+  // level is solved, t = (L^B)^{-T} w^B (the block's levels from its root down) and
+  // y_{R^B} -= A(R^B, C^B) t; backward, before the level, t = A(C^B, R^B) z_{R^B}, then
+  // t = (L^B)^{-1} t (the block's levels up to its root, whose step also takes
+  // w^B -= t).  A's entries are taken from the lower triangle of the original numbering,
+  // as the factorization takes them.
+  struct IntLevel {
+    std::vector<std::pair<int64_t, int64_t>> steps;   // per block level 0 .. L: task range
+    int64_t f0 = 0, nf = 0, g0 = 0, ng = 0;           // coupling targets: forward, backward
+  };
   std::vector<IntLevel> il(S.nlevels);
   if (ib) {
     auto lower_entry = [&](int64_t orow, int64_t ocol) {   // CSR index of A(max, min)
@@ -2378,32 +2383,46 @@ static Error build_solve_plan(Handle& h) {
     std::vector<std::vector<int32_t>> roots(S.nlevels);
     for (int64_t b = 0; b < S.M(); ++b)
       if (h.iroot[b] == b && S.r(b) > 0) roots[S.level[b]].push_back((int32_t)b);
+    // the forward solves' pull lists: per column, the zr slots of the in-block rows
+    std::vector<int64_t> cnt((size_t)S.n + 1, 0);
+    for (int64_t k = 0; k < S.M(); ++k)
+      if (inter(k))
+        for (int64_t p = S.rows_ptr[k]; p < S.rows_ptr[k] + rr(k); ++p) ++cnt[S.rows[p] + 1];
+    for (int64_t i = 0; i < S.n; ++i) cnt[i + 1] += cnt[i];
+    Q->ipull_idx.assign((size_t)cnt[S.n], 0);
+    {
+      std::vector<int64_t> nx(cnt.begin(), cnt.end() - 1);
+      for (int64_t k = 0; k < S.M(); ++k)
+        if (inter(k))
+          for (int64_t p = S.rows_ptr[k]; p < S.rows_ptr[k] + rr(k); ++p) Q->ipull_idx[(size_t)nx[S.rows[p]]++] = p;
+    }
+    Q->ipull_ptr = std::move(cnt);
     for (int32_t L = 0; L < S.nlevels; ++L) {
       IntLevel& q = il[L];
-      q.b0 = (int64_t)Q->iblocks.size();
+      if (roots[L].empty()) continue;
+      q.steps.assign(L + 1, {0, 0});
+      std::vector<std::vector<IntSn>> by_l(L + 1);
       q.g0 = (int64_t)Q->cp_tgt.size();          // backward targets: the blocks' columns
       std::vector<std::array<int64_t, 3>> fe;   // (target row, column, value index)
       for (int32_t b : roots[L]) {
         int64_t s0 = b;
         while (s0 > 0 && h.iroot[s0 - 1] == b) --s0;
-        IntBlock B{};
-        B.s0 = (int32_t)Q->isns.size(); B.a = S.first[s0]; B.b = S.first[b + 1];
+        const int64_t a = S.first[s0], e = S.first[b + 1];
         for (int64_t k = s0; k <= b; ++k) {
           IntSn t{};
           t.m = m_off(k); t.mld = m_ld(k); t.lo = h.r_in[k] > 0 ? h.lo_in[k] : 0; t.rh = h.r_in[k];
           t.rows = S.rows_ptr[k]; t.first = S.first[k]; t.c = S.c(k);
-          Q->isns.push_back(t);
+          t.a = a; t.b = e; t.root = (k == b);
+          by_l[S.level[k]].push_back(t);
           bytes += 2.0 * 8.0 * ((double)t.c * (t.c + 1) / 2 + (double)t.rh * t.c);
         }
-        B.s1 = (int32_t)Q->isns.size();
-        Q->iblocks.push_back(B);
         // backward coupling: every column of the block (zero when it has no entry)
-        for (int64_t cn = B.a; cn < B.b; ++cn) {
+        for (int64_t cn = a; cn < e; ++cn) {
           const int64_t old = S.perm[cn];
           std::vector<std::pair<int64_t, int64_t>> ent;   // (row, value index)
           for (int64_t p = h.rowptr[old]; p < h.rowptr[old + 1]; ++p) {
             const int64_t rn = S.iperm[h.colind[p]];
-            if (rn >= B.b) {
+            if (rn >= e) {
               ent.push_back({rn, lower_entry(old, h.colind[p])});
               fe.push_back({rn, cn, ent.back().second});
             }
@@ -2411,12 +2430,15 @@ static Error build_solve_plan(Handle& h) {
           std::sort(ent.begin(), ent.end());
           Q->cp_tgt.push_back(cn);
           Q->cp_ptr.push_back((int64_t)Q->cp_vidx.size());
-          for (auto& e : ent) { Q->cp_vidx.push_back(e.second); Q->cp_xidx.push_back(e.first); }
+          for (auto& en : ent) { Q->cp_vidx.push_back(en.second); Q->cp_xidx.push_back(en.first); }
           bytes += 24.0 * (double)ent.size() + 8.0;
         }
       }
-      q.nb = (int64_t)Q->iblocks.size() - q.b0;
       q.ng = (int64_t)Q->cp_tgt.size() - q.g0;
+      for (int32_t l = 0; l <= L; ++l) {
+        q.steps[l] = {(int64_t)Q->isns.size(), (int64_t)by_l[l].size()};
+        Q->isns.insert(Q->isns.end(), by_l[l].begin(), by_l[l].end());
+      }
       // forward coupling: each target row once, its entries by column
       std::sort(fe.begin(), fe.end());
       q.f0 = (int64_t)Q->cp_tgt.size();
@@ -2434,14 +2456,14 @@ static Error build_solve_plan(Handle& h) {
     Q->cp_ptr.push_back((int64_t)Q->cp_vidx.size());
   }
   auto fwd_tail = [&](int32_t L) {
-    if (!ib || il[L].nb == 0) return;
-    cmd(kCmdInterior, il[L].b0, il[L].nb, 0);
+    if (!ib || il[L].steps.empty()) return;
+    for (int32_t l = L; l >= 0; --l) cmd(kCmdInterior, il[L].steps[l].first, il[L].steps[l].second, 0);
     cmd(kCmdCoupling, il[L].f0, il[L].nf, 0);
   };
   auto bwd_tail = [&](int32_t L) {
-    if (!ib || il[L].nb == 0) return;
+    if (!ib || il[L].steps.empty()) return;
     cmd(kCmdCoupling, il[L].g0, il[L].ng, 1);
-    cmd(kCmdInterior, il[L].b0, il[L].nb, 1);
+    for (int32_t l = 0; l <= L; ++l) cmd(kCmdInterior, il[L].steps[l].first, il[L].steps[l].second, 1);
   };
   // forward sweep, levels ascending
   for (int32_t L = 0; L < S.nlevels; ++L) {
@@ -2627,8 +2649,9 @@ static Error build_solve_plan(Handle& h) {
   Q->bytes = bytes;
   Error e;
   if ((e = upload(Q->d_gemv, Q->gemv)).code) return e;
-  if ((e = upload(Q->d_iblocks, Q->iblocks)).code) return e;
   if ((e = upload(Q->d_isns, Q->isns)).code) return e;
+  if ((e = upload(Q->d_ipull_ptr, Q->ipull_ptr)).code) return e;
+  if ((e = upload(Q->d_ipull_idx, Q->ipull_idx)).code) return e;
   if ((e = upload(Q->d_cp_tgt, Q->cp_tgt)).code) return e;
   if ((e = upload(Q->d_cp_ptr, Q->cp_ptr)).code) return e;
   if ((e = upload(Q->d_cp_vidx, Q->cp_vidx)).code) return e;

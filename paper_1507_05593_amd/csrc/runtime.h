@@ -166,12 +166,12 @@ struct SolvePlan {
   DevArray<int64_t> d_rg_rows, d_rg_ptr, d_rg_contrib, d_gath;
   DevArray<SweepTask> d_sweep;
   // interior blocks (Sec. 5.1): the block solves and A's coupling products of each level
-  std::vector<IntBlock> iblocks;
   std::vector<IntSn> isns;
   std::vector<int64_t> cp_tgt, cp_ptr, cp_vidx, cp_xidx;
-  DevArray<IntBlock> d_iblocks;
+  std::vector<int64_t> ipull_ptr, ipull_idx;   // per column (n + 1): zr slots of the in-block
+                                               // products it pulls in the blocks' forward solve
   DevArray<IntSn> d_isns;
-  DevArray<int64_t> d_cp_tgt, d_cp_ptr, d_cp_vidx, d_cp_xidx;
+  DevArray<int64_t> d_cp_tgt, d_cp_ptr, d_cp_vidx, d_cp_xidx, d_ipull_ptr, d_ipull_idx;
   DevArray<int64_t> d_pull_ptr, d_pull_idx;
   hipGraphExec_t graph_a = nullptr, graph_b = nullptr, graph_apply = nullptr;
   double bytes = 0;                   // factor bytes read by one apply

@@ -169,17 +169,15 @@ struct RowChunk {
 // M(i, t) = F[m + i + t*ld]); the off-diagonal operand X is L^O_j (r x c) or, compressed,
 // V_j (r x l) with U_j (c x l, ld c) and the rank in the int arena; both column major.
 constexpr int32_t kSweepMaxR = 2048;   // rows R_j of a small-sweep supernode (LDS)
-// Interior blocks (Sec. 5.1): the supernodes of one block are consecutive tasks.
+// Interior blocks (Sec. 5.1): one step of a solve with a block's own factor for one of
+// its supernodes (the supernodes of one elimination-tree level run in the same launch).
 struct IntSn {
   int64_t m;                   // M_k = (L^D_k)^{-T}, upper triangular, M(i, t) at m + i + t*mld
   int64_t lo;                  // the rows of L^O_k inside the block (rh x c, ld rh)
   int64_t rows;                // offset of R_k in the row list (its first rh rows are those)
   int64_t first;               // first column (permuted index)
-  int32_t c, mld, rh, pad_;
-};
-struct IntBlock {
-  int32_t s0, s1;              // its supernodes: tasks [s0, s1)
-  int64_t a, b;                // its columns [a, b)
+  int64_t a, b;                // the block's columns [a, b) (used by its root)
+  int32_t c, mld, rh, root;    // root: this supernode is the block's root
 };
 
 struct SweepTask {
