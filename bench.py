@@ -586,8 +586,8 @@ def summarize_pmc(dirs, kernel, last, workload):
                                 "write_factor": wf},
            "hbm_bytes_per_launch": 1024.0 * (f_avg * ff + w_avg * wf),
            "commands": [
-               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-profile --compare none --no-graph",
-               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-profile --compare none --no-graph",
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-profile --compare none --no-graph --no-spectral --tree-tau 0 --no-interior",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-profile --compare none --no-graph --no-spectral --tree-tau 0 --no-interior",
                "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/copyfetch -o run -- python3 bench.py --calibrate-copy",
                "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/copywrite -o run -- python3 bench.py --calibrate-copy",
                f"python bench.py --summarize-pmc OUT/fetch OUT/write OUT/copyfetch OUT/copywrite --pmc-kernel {kernel} --pmc-last {last}"],
