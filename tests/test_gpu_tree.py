@@ -118,3 +118,28 @@ def test_tree_without_positions_and_spectral_positions():
         assert sol.stats()["tree_supernodes"] > 0
         it.append(res["iters"])
     assert max(it) <= 30, it
+
+
+def test_restart_matches_oracle():
+    """The alpha_D restart (§5.3) on a separator whose rank-one blocks make a leaf
+    indefinite: the device restarts as often as the oracle, ends at the same alpha_D,
+    and its block tree and preconditioner then agree with the oracle's."""
+    from paper_1507_05593_amd import RSCSolver
+    from workloads import clique_separator
+    print("case clique separator", flush=True)
+    n, rp, ci, v = clique_separator(8, 8, 32, 1e-3, 0)
+    sym = symbolic(n, rp, ci, 8, 4)
+    o = Options(tau_D=4, alpha_D=0.05, oversample=0, leaf_max=8)
+    F = o_factor(sym, n, rp, ci, v, 1e-2, o)
+    assert F.restarts > 0
+    sol = RSCSolver(n, rp, ci, leaf_max=8, tau_D=4, alpha_D=0.05, oversample=0)
+    sol.factor(torch.tensor(v, device=DEV), 1e-2)
+    st = sol.stats()
+    assert st["diag_restarts"] == F.restarts and st["alpha_D_used"] == pytest.approx(F.alpha_D)
+    j = sym.M - 1
+    Ld = F.LD[j].dense()
+    assert np.abs(np.tril(sol.block(j)["LD"]) - Ld).max() <= 1e-8 * np.abs(Ld).max()
+    r = np.random.default_rng(1).standard_normal(n)
+    z = sol.apply(torch.tensor(r, device=DEV)).cpu().numpy()
+    zo = o_apply(F, r)
+    assert np.abs(z - zo).max() <= 1e-6 * np.abs(zo).max()

@@ -152,6 +152,28 @@ def test_restart_raises_alpha_by_a_quarter(monkeypatch):
     assert sorted(set(seen)) == pytest.approx([0.5 * 1.25 ** k for k in range(5)])
 
 
+def test_restart_on_an_indefinite_approximation():
+    """A separator whose block is dense, unstructured and nearly singular: rank-one blocks
+    make a leaf's Schur complement indefinite.  Every single attempt below the final
+    alpha_D (0.05 x 1.25^k) meets a non-positive pivot, the final one does not, and the
+    factorization restarts exactly through that sequence (§5.3)."""
+    from oracle.factor import _factor_once
+    from workloads import clique_separator
+    n, rp, ci, v = clique_separator(8, 8, 32, 1e-3, 0)
+    sym = symbolic(n, rp, ci, 8, 4)
+    assert [int(d) for d in sym.depth] == [0, 0, 3] and int(sym.kind[2]) == 1
+    o = Options(tau_D=4, alpha_D=0.05, oversample=0, leaf_max=8)
+    F = factor(sym, n, rp, ci, v, tol=1e-2, opts=o)
+    assert F.restarts >= 5 and F.alpha_D == pytest.approx(0.05 * 1.25 ** F.restarts)
+    for k in range(F.restarts):
+        with pytest.raises(NotSPDError):
+            _factor_once(sym, n, rp, ci, v, 1e-2, o, 0.05 * 1.25 ** k, None, None)
+    L = F.dense_L()
+    assert np.all(np.diag(L) > 0)
+    A = F.Ap.toarray()
+    assert np.linalg.eigvalsh(L @ L.T).min() > 0 and np.abs(L @ L.T - A).max() < np.abs(A).max()
+
+
 def test_restart_stops_once_every_block_is_exact(monkeypatch):
     dims, tau = (16, 16), 4
     p = grid_problem(dims, sigma=1.0, seed=1)

@@ -10,6 +10,7 @@ from .grids import (  # noqa: F401
     GridProblem,
     grid_problem,
     grid_coordinates,
+    clique_separator,
     batched_problems,
     workload_config,
     WORKLOADS,

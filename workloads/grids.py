@@ -134,6 +134,32 @@ def grid_coordinates(dims) -> np.ndarray:
     return xyz
 
 
+def clique_separator(na: int, nb: int, m: int, lam_min: float, seed: int):
+    """Two cliques of ``na`` and ``nb`` unknowns joined through a separator clique of ``m``
+    (every separator unknown coupled to every other unknown): a pattern whose dissection
+    (leaves of at most ``max(na, nb)``) makes the ``m`` unknowns one separator.  The
+    separator block is ``Q diag(lambda) Q^T`` with ``Q`` a seeded random orthogonal matrix
+    and ``lambda`` geometric from ``lam_min`` to 1 (a dense, unstructured, nearly singular
+    block); the cliques' blocks are ``2 I + 0.1``; their couplings to the separator are
+    1e-6.  Returns ``(n, rowptr, colind, values)`` of the full symmetric CSR."""
+    rng = np.random.default_rng(seed)
+    n = na + nb + m
+    A = np.zeros((n, n))
+    a, b, s = np.arange(na), np.arange(na, na + nb), np.arange(na + nb, n)
+    A[np.ix_(a, a)] = 2.0 * np.eye(na) + 0.1
+    A[np.ix_(b, b)] = 2.0 * np.eye(nb) + 0.1
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    A[np.ix_(s, s)] = Q @ np.diag(np.geomspace(lam_min, 1.0, m)) @ Q.T
+    for blk in (a, b):
+        A[np.ix_(blk, s)] = 1e-6
+        A[np.ix_(s, blk)] = 1e-6
+    A = 0.5 * (A + A.T)
+    pat = (A != 0) | np.eye(n, dtype=bool)
+    rowptr = np.concatenate(([0], np.cumsum(pat.sum(axis=1)))).astype(np.int64)
+    colind = np.nonzero(pat)[1].astype(np.int32)
+    return n, rowptr, colind, A[pat]
+
+
 def grid_problem(dims, sigma: float = 0.0, seed: int = 0, unit: bool = False) -> GridProblem:
     """One seeded diffusion problem; ``unit=True`` sets every coefficient to 1."""
     dims = tuple(int(x) for x in dims)
