@@ -279,3 +279,39 @@ def test_fullsize_spectral_coordinates_64():
     qa, _ = np.linalg.qr(Y)
     qb, _ = np.linalg.qr(Yo)
     assert np.linalg.svd(qa.T @ qb, compute_uv=False).min() > 1 - 1e-7
+
+
+@pytest.mark.gpu
+def test_fullsize_diagonal_trees_and_interior_blocks_96():
+    """The benchmark workload with the diagonal block trees (§4.1-4.2, tau_D 512, grid
+    positions) and, separately, with interior blocks (§5.1): PCG converges to rtol in the
+    iterations of the plain factor (+-10 %); the trees store fewer entries than the dense
+    diagonal blocks they replace; interior blocks change the preconditioner only by
+    rounding (same iterations, the factor smaller by exactly the entries not stored)."""
+    torch = _gpu()
+    from paper_1507_05593_amd import RSCSolver
+    from workloads import grid_coordinates
+    print("case trees and interior diffusion3d_96", flush=True)
+    cfg, p = _problem("diffusion3d_96")
+    vals = torch.tensor(p.values, dtype=torch.float64, device="cuda:0")
+    b = torch.tensor(p.b, dtype=torch.float64, device="cuda:0")
+    out = {}
+    for name, kw in (("plain", {}), ("trees", dict(coords=grid_coordinates(p.dims), tau_D=512)),
+                     ("interior", dict(interior=True))):
+        sol = RSCSolver(p.n, p.rowptr, p.colind, precision="bf16", seed=0, **kw)
+        sol.factor(vals, cfg["tol"])
+        x, info = sol.pcg(b, rtol=cfg["rtol"])
+        st = sol.stats()
+        print(name, "iters", info["iters"], "entries", st["factor_entries"], flush=True)
+        assert info["converged"] and info["true_residual"] <= cfg["rtol"]
+        out[name] = (info, st, sol)
+    i0, s0, _ = out["plain"]
+    it, st, sol_t = out["trees"]
+    assert abs(it["iters"] - i0["iters"]) <= max(1, 0.1 * i0["iters"])
+    first, _, _, _ = sol_t.supernode_info()
+    c = np.diff(first)[sol_t.tree_depths > 0].astype(np.int64)
+    assert st["tree_supernodes"] == c.size > 0 and st["diag_restarts"] == 0
+    assert st["tree_entries"] < np.sum(c * (c + 1) // 2)
+    ii, si, _ = out["interior"]
+    assert ii["iters"] == i0["iters"] and si["interior_blocks"] > 0
+    assert si["factor_entries"] == s0["factor_entries"] - si["interior_dropped"]
