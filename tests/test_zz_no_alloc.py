@@ -1,8 +1,8 @@
 """The allocation-free preconditioner apply (rsc_apply_preconditioner_noalloc) against
 rsc_apply_preconditioner, through the C ABI: the same kernels on the same factor, so
 the results are identical bit for bit; two calls in a row, the second on a smaller
-system, each in the FP64 form and after a mixed-precision factorization (FP32 sweep
-operands)."""
+system, each in the FP64 form, after a mixed-precision factorization (FP32 sweep
+operands) and with interior blocks (their solves in the same apply)."""
 import ctypes as C
 
 import numpy as np
@@ -29,14 +29,14 @@ def _apply_both(sol, r):
     return z_ref.cpu().numpy(), z.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16"])
-def test_noalloc_apply_equals_apply_two_calls_smaller_second(precision):
+@pytest.mark.parametrize("precision,interior", [("fp64", False), ("bf16", False), ("fp64", True)])
+def test_noalloc_apply_equals_apply_two_calls_smaller_second(precision, interior):
     from paper_1507_05593_amd import RSCSolver
-    print("case noalloc apply", precision, flush=True)
+    print("case noalloc apply", precision, interior, flush=True)
     rng = np.random.default_rng(5)
     for dims in ((22, 21, 20), (9, 8, 7)):          # the second call's system is smaller
         p = grid_problem(dims, sigma=1.0, seed=3)
-        sol = RSCSolver(p.n, p.rowptr, p.colind, precision=precision, seed=1)
+        sol = RSCSolver(p.n, p.rowptr, p.colind, precision=precision, seed=1, interior=interior)
         sol.factor(torch.tensor(p.values, dtype=torch.float64, device=DEV), 1e-2)
         r = torch.tensor(rng.standard_normal(p.n), dtype=torch.float64, device=DEV)
         z_ref, z = _apply_both(sol, r)
