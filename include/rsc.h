@@ -292,7 +292,9 @@ rsc_status rsc_get_ranks(rsc_handle h, int32_t* ell, int32_t* q);
  * compression, available only with rsc_options.keep_lo -- RSC_ERR_STATE otherwise --
  * the factor itself uses V_j, U_j; for a supernode of an interior block (rsc_options.
  * interior) only its rows inside the block are stored: the others are returned as 0),
- * V (r x q), U (c x q).  Any pointer may be NULL. */
+ * V (r x q), U (c x q).  The factor keeps U_j as W_j = (L^D_j)^{-T} U_j, the form its
+ * sweeps apply; U is rebuilt here on the host as (L^D_j)^T W_j (O(c^2 q) host work).
+ * Any pointer may be NULL. */
 rsc_status rsc_get_block(rsc_handle h, int64_t j, double* LD, double* LO, double* V, double* U);
 rsc_status rsc_get_stats(rsc_handle h, rsc_stats* out);
 rsc_status rsc_profile_enable(rsc_handle h, int32_t on);   /* also resets the counters */

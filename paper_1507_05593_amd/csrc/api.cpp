@@ -289,9 +289,19 @@ rsc_status rsc_get_block(rsc_handle H, int64_t j, double* LD, double* LO, double
     if (V && q > 0 &&
         hipMemcpy(V, h.arena.p + h.comp[j].Vj, sizeof(double) * r * q, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(RSC_ERR_DEVICE, "copy V");
-    if (U && q > 0 &&
-        hipMemcpy(U, h.arena.p + h.comp[j].Uj, sizeof(double) * c * q, hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(RSC_ERR_DEVICE, "copy U");
+    if (U && q > 0) {
+      // the factor keeps W_j = (L^D_j)^{-T} U_j (the form the sweeps use): U_j = (L^D_j)^T W_j
+      std::vector<double> W((size_t)c * q), L((size_t)c * c);
+      if (hipMemcpy(W.data(), h.arena.p + h.comp[j].Uj, sizeof(double) * c * q, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy2D(L.data(), c * 8, P, ld * 8, c * 8, c, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(RSC_ERR_DEVICE, "copy U");
+      for (int64_t k = 0; k < q; ++k)
+        for (int64_t i = 0; i < c; ++i) {
+          double acc = 0.0;
+          for (int64_t t = i; t < c; ++t) acc += L[(size_t)t + (size_t)i * c] * W[(size_t)t + (size_t)k * c];
+          U[i + k * c] = acc;
+        }
+    }
   }
   return RSC_OK;
 }

@@ -40,8 +40,8 @@ void launch_trunc_ns(const TruncTask* t, int n, bool fp32, double* arena, const 
 // sweep kernels: f32 = FP32 copy of the factor operands (mixed forms), or null (arena)
 void launch_gemv_n(const GemvTask* t, int n, double* arena, const float* f32, const int32_t* ilim,
                    hipStream_t s);
-void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32, double* part,
-                     hipStream_t s);
+void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32,
+                     const int32_t* ilim, double* part, hipStream_t s);
 void launch_to_f32(const ConvTask* t, int n, const double* arena, float* f32, hipStream_t s);
 // FP64 block copies (off -> dst, rows x cols, ld -> dld)
 void launch_copy_f64(const ConvTask* t, int n, double* arena, hipStream_t s);

@@ -64,17 +64,20 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
 }
 
 // Backward diagonal solve chunk: rows i in [i0, i0 + 64) (lanes) of M (w - s) over the
-// columns [t0, t1); v = w - s is staged in LDS, the four waves take consecutive column
-// quarters, and their sums are added in a fixed order into one partial block.
+// columns [t0, t1) (kind 0), or of -W u over W's columns [t0, t1) below the device rank
+// (kind 1); the vector is staged in LDS, the four waves take consecutive column quarters,
+// and their sums are added in a fixed order into one partial block.
 template <typename TF>
 __global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ chunks,
                                                   const double* __restrict__ arena, const TF* __restrict__ F,
+                                                  const int32_t* __restrict__ ilim,
                                                   double* __restrict__ part) {
   __shared__ double v[kRowChunkMax];
   __shared__ double red[4][64];
   const RowChunk T = chunks[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int n = T.t1 - T.t0;
+  const int t1 = T.kind ? min(T.t1, min(ilim[T.qslot], T.kmax)) : T.t1;
+  const int n = max(0, t1 - T.t0);
   for (int t = threadIdx.x; t < n; t += 256) {
     const double a = arena[T.w + T.t0 + t];
     v[t] = T.s >= 0 ? a - arena[T.s + T.t0 + t] : a;
@@ -84,14 +87,17 @@ __global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ c
   double acc = 0.0;
   if (i < T.c) {
     const int per = (n + 3) / 4;
-    const int ta = T.t0 + w * per, tb = min(T.t1, ta + per);
+    const int ta = T.t0 + w * per, tb = min(t1, ta + per);
     const TF* M = F + T.m + i;
 #pragma unroll 8
-    for (int t = max(ta, i); t < tb; ++t) acc += (double)M[(int64_t)t * T.ld] * v[t - T.t0];
+    for (int t = T.kind ? ta : max(ta, i); t < tb; ++t) acc += (double)M[(int64_t)t * T.ld] * v[t - T.t0];
   }
   red[w][lane] = acc;
   __syncthreads();
-  if (w == 0) part[(int64_t)T.slot * 64 + lane] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (w == 0) {
+    const double sum = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    part[(int64_t)T.slot * 64 + lane] = T.kind ? -sum : sum;
+  }
 }
 
 // Applies the partial blocks of one vector block in slot order (see PartApply).
@@ -172,8 +178,9 @@ __device__ __forceinline__ double sum16(double acc) {
 }
 
 // Forward step:  y_C minus the descendants' contributions (pulled from zr in list order),
-// w_C = (L^D_j)^{-1} y_C = M_j^T y_C, and t = L^O_j w_C or V_j (U_j^T w_C) stored in the
-// supernode's zr slots, from which its ancestors pull.  LDS: y_C, w_C (cpad each), U^T w.
+// w_C = (L^D_j)^{-1} y_C = M_j^T y_C, and t = L^O_j w_C or V_j (U_j^T w_C) = V_j (W_j^T y_C)
+// stored in the supernode's zr slots, from which its ancestors pull.  LDS: y_C, w_C (cpad
+// each), W^T y.
 template <typename TF>
 __global__ __launch_bounds__(256) void k_sweep_fwd(const SweepTask* __restrict__ tasks,
                                                    const double* __restrict__ y, double* __restrict__ w,
@@ -211,9 +218,9 @@ __global__ __launch_bounds__(256) void k_sweep_fwd(const SweepTask* __restrict__
   if (T.u >= 0) {
     K = min(ilim[T.qslot], T.kmax);
     for (int k = g; k < K; k += ng) {
-      const TF* U = F + T.u + (int64_t)k * T.c;
+      const TF* W = F + T.u + (int64_t)k * T.c;
       double acc = 0.0;
-      for (int i = gl; i < T.c; i += 16) acc += (double)U[i] * wc[i];
+      for (int i = gl; i < T.c; i += 16) acc += (double)W[i] * yc[i];
       acc = sum16(acc);
       if (gl == 0) tq[k] = acc;
     }
@@ -230,8 +237,8 @@ __global__ __launch_bounds__(256) void k_sweep_fwd(const SweepTask* __restrict__
 }
 
 // Backward step:  z_R gathered from zz, s = (L^O_j)^T z_R or U_j (V_j^T z_R), and
-// z_C = (L^D_j)^{-T} (w_C - s) = M_j (w_C - s) into zz.  LDS: w_C - s (cpad), V^T z_R
-// (lpad), z_R.
+// z_C = (L^D_j)^{-T} (w_C - s) = M_j (w_C - s) into zz -- for a compressed supernode
+// M_j w_C - W_j (V_j^T z_R).  LDS: w_C - s (cpad), V^T z_R (lpad), z_R.
 template <typename TF>
 __global__ __launch_bounds__(256) void k_sweep_bwd(const SweepTask* __restrict__ tasks,
                                                    const double* __restrict__ w, double* __restrict__ zz,
@@ -265,21 +272,22 @@ __global__ __launch_bounds__(256) void k_sweep_bwd(const SweepTask* __restrict__
       acc = sum16(acc);
       if (gl == 0) uq[k] = acc;
     }
-    __syncthreads();
-    for (int i = tid; i < T.c; i += nt) {
-      const TF* U = F + T.u + i;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < K; ++k) acc += (double)U[(int64_t)k * T.c] * uq[k];
-      v[i] = w[T.first + i] - acc;
-    }
+    for (int i = tid; i < T.c; i += nt) v[i] = w[T.first + i];
   }
   __syncthreads();
+  const int K = T.u >= 0 ? min(ilim[T.qslot], T.kmax) : 0;
   for (int i = tid; i < T.c; i += nt) {
     const TF* M = F + T.m + i;
     double acc = 0.0;
 #pragma unroll 8
     for (int t = i; t < T.c; ++t) acc += (double)M[(int64_t)t * T.ld] * v[t];
+    if (K > 0) {
+      const TF* W = F + T.u + i;
+      double wu = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < K; ++k) wu += (double)W[(int64_t)k * T.c] * uq[k];
+      acc -= wu;
+    }
     zz[T.first + i] = acc;
   }
 }
@@ -500,11 +508,11 @@ void launch_gemv_n(const GemvTask* t, int n, double* arena, const float* f32, co
   if (f32) hipLaunchKernelGGL(k_gemv_n<float>, dim3(n), dim3(256), 0, s, t, arena, f32, ilim);
   else hipLaunchKernelGGL(k_gemv_n<double>, dim3(n), dim3(256), 0, s, t, arena, (const double*)arena, ilim);
 }
-void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32, double* part,
-                     hipStream_t s) {
+void launch_row_part(const RowChunk* c, int n, const double* arena, const float* f32,
+                     const int32_t* ilim, double* part, hipStream_t s) {
   if (n <= 0) return;
-  if (f32) hipLaunchKernelGGL(k_row_part<float>, dim3(n), dim3(256), 0, s, c, arena, f32, part);
-  else hipLaunchKernelGGL(k_row_part<double>, dim3(n), dim3(256), 0, s, c, arena, arena, part);
+  if (f32) hipLaunchKernelGGL(k_row_part<float>, dim3(n), dim3(256), 0, s, c, arena, f32, ilim, part);
+  else hipLaunchKernelGGL(k_row_part<double>, dim3(n), dim3(256), 0, s, c, arena, arena, ilim, part);
 }
 
 // FP32 copy of the factor operands the sweeps read, at the arena's offsets: one task per

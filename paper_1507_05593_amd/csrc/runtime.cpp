@@ -1474,12 +1474,15 @@ struct Builder {
       cmd(kCmdTruncCopy, RSC_K_EIG, t0, nt, 0, lmax);
     }
     credit(cs, m_eig);
-    // 9. U_j = U W, V_j = V W (columns beyond the device rank q_j are skipped)
+    // 9. the kept basis U_j = U Z and V_j = V Z (Z: the projector's basis, columns beyond
+    //    the device rank q_j skipped).  U_j is stored as W_j = M_j U_j = (M U) Z, from the
+    //    product M U that step 5 left in tmp: the sweeps apply (L^D_j)^{-1} and U_j^T in
+    //    one product, W_j^T y = U_j^T (L^D_j)^{-1} y.
     g0 = (int64_t)P.gemm.size(); fl = 0;
     for (int32_t j : js) {
       const CompSlot& C = h.comp[j];
-      const int32_t c = S.c(j), r = S.r(j), l = C.ell, ldy = l + c;
-      GemmTask t = gt(C.ypanel + l, 1, ldy, C.Om2, l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
+      const int32_t c = S.c(j), r = S.r(j), l = C.ell;
+      GemmTask t = gt(C.tmp, 1, c, C.Om2, l, 1, C.Uj, c, c, l, l, 1.0, 0.0);
       t.nlim = C.qslot;
       fl += tiles(t, 0, 0, false);
       GemmTask t2 = gt(C.V, 1, r, C.Om2, l, 1, C.Vj, r, r, l, l, 1.0, 0.0);
@@ -2004,7 +2007,7 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
     case kCmdTruncCopy: launch_trunc_copy(P->d_trunc.p + c.off, (int)c.count, (int)c.a, A, s); break;
     case kCmdGemvN: launch_gemv_n(Q->d_gemv.p + c.off, (int)c.count, A, F32, I, s); break;
     case kCmdColDot: launch_coldot(Q->d_coldot.p + c.off, (int)c.count, A, F32, h.d_rows.p, I, QP, s); break;
-    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, F32, QP, s); break;
+    case kCmdRowPart: launch_row_part(Q->d_rchunks.p + c.off, (int)c.count, A, F32, I, QP, s); break;
     case kCmdToF32: launch_to_f32(P->d_conv.p + c.off, (int)c.count, A, f32_base(h), s); break;
     case kCmdTruncNs:
       launch_trunc_ns(P->d_trunc.p + c.off, (int)c.count, c.a != 0, A, kNs, s);
@@ -2484,7 +2487,8 @@ static Error build_solve_plan(Handle& h) {
       cmd(kCmdRowGather, r0, (int64_t)Q->rg_rows.size() - r0, r0);
     }
     const auto& lev = S.by_level[L];
-    // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block)
+    // f3: w_C = L_j^{-1} y_C with the stored inverse (transposed upper block), and in the
+    //     same launch f4: t_j = U_j^T w_C = W_j^T y_C for compressed supernodes
     std::vector<ColDotTask> st;
     for (int32_t j : lev) {
       const int32_t c = S.c(j), r = S.r(j);
@@ -2497,15 +2501,12 @@ static Error build_solve_plan(Handle& h) {
       }
       bytes += 8.0 * c * (c + 1) / 2;
     }
-    coldot_stage(st);
-    // f4: t_j = U_j^T w_C for compressed supernodes
-    st.clear();
     for (int32_t j : lev) {
       if (!iscomp(j)) continue;
       const CompSlot& C = h.comp[j];
       for (int32_t col0 = 0; col0 < C.ell; col0 += 16) {
         ColDotTask t{};
-        t.x = C.Uj; t.ldx = S.c(j); t.in = h.a_w + S.first[j]; t.idx = -1; t.out = C.tvq;
+        t.x = C.Uj; t.ldx = S.c(j); t.in = h.a_y + S.first[j]; t.idx = -1; t.out = C.tvq;
         t.rows = S.c(j); t.ncols = -(1 + C.qslot); t.kmax = C.ell; t.col0 = col0; t.tri = 0;
         st.push_back(t);
       }
@@ -2602,22 +2603,12 @@ static Error build_solve_plan(Handle& h) {
       }
     }
     coldot_stage(st);
-    // b1': s_C = U_j u for compressed supernodes
-    int64_t g0 = (int64_t)Q->gemv.size();
-    for (int32_t j : lev) {
-      if (!iscomp(j)) continue;
-      const CompSlot& C = h.comp[j];
-      for (int32_t t0 = 0; t0 < S.c(j); t0 += 64) {
-        GemvTask t{};
-        t.x = C.Uj + t0; t.ldx = S.c(j); t.kdim = -(1 + C.qslot); t.kmax = C.ell; t.v = C.u;
-        t.rows = std::min(64, S.c(j) - t0); t.out = h.a_s + S.first[j] + t0;
-        Q->gemv.push_back(t);
-      }
-      bytes += 2.0 * 8.0 * (double)(S.c(j) + S.r(j)) * C.ell;
-    }
-    cmd(kCmdGemvN, g0, (int64_t)Q->gemv.size() - g0);
+    for (int32_t j : lev)
+      if (iscomp(j)) bytes += 2.0 * 8.0 * (double)(S.c(j) + S.r(j)) * h.comp[j].ell;
     // b2: z_C = L_j^{-T} (w_C - s_C) by 64-row blocks, the columns of each block cut
-    // into chunks (about 1024 per level) whose partial blocks are then stored in order
+    // into chunks (about 1024 per level) whose partial blocks are then stored in order;
+    // for a compressed supernode z_C = M_j w_C - W_j u (s_C = U_j u), the rows of W_j u
+    // as further chunks of the same blocks
     {
       double cols = 0;
       for (int32_t j : lev)
@@ -2627,15 +2618,25 @@ static Error build_solve_plan(Handle& h) {
       const int64_t c0r = (int64_t)Q->rchunks.size(), a0 = (int64_t)Q->papply.size();
       int32_t slot = 0;
       for (int32_t j : lev) {
-        const int32_t c = S.c(j), r = S.r(j);
+        const int32_t c = S.c(j);
         for (int32_t i0 = 0; i0 < c; i0 += 64) {
           const int32_t s0 = slot;
           for (int32_t t0 = i0; t0 < c; t0 += width) {
             RowChunk t{};
             t.m = m_off(j); t.ld = m_ld(j); t.c = c; t.i0 = i0;
-            t.w = h.a_w + S.first[j]; t.s = (iscomp(j) ? r : rr(j)) > 0 ? h.a_s + S.first[j] : -1;
+            t.w = h.a_w + S.first[j]; t.s = (!iscomp(j) && rr(j) > 0) ? h.a_s + S.first[j] : -1;
             t.t0 = t0; t.t1 = std::min(c, t0 + width); t.slot = slot++;
             Q->rchunks.push_back(t);
+          }
+          if (iscomp(j)) {
+            const CompSlot& C = h.comp[j];
+            for (int32_t t0 = 0; t0 < C.ell; t0 += width) {
+              RowChunk t{};
+              t.kind = 1; t.m = C.Uj; t.ld = c; t.c = c; t.i0 = i0; t.w = C.u; t.s = -1;
+              t.qslot = C.qslot; t.kmax = C.ell;
+              t.t0 = t0; t.t1 = std::min(C.ell, t0 + width); t.slot = slot++;
+              Q->rchunks.push_back(t);
+            }
           }
           Q->papply.push_back(PartApply{h.a_zz + S.first[j] + i0, std::min(64, c - i0), s0, slot - s0, 1});
         }

@@ -163,6 +163,11 @@ struct ConvTask {
 struct RowChunk {
   int64_t m, w, s;             // s < 0: no subtraction
   int32_t ld, c, i0, t0, t1, slot;
+  int32_t kind;                // 0: rows of M (w - s) over columns [t0, t1), M upper triangular;
+                               // 1: rows of -W u, W = M_j U_j (c x l at m, ld c), u at w, over
+                               //    columns [t0, t1) cut at the device rank
+  int32_t qslot, kmax;         // kind 1: int-arena slot of the rank and its bound
+  int32_t pad_;
 };
 // One supernode of a small-supernode sweep level: both sweeps of the level run in one
 // launch each, one workgroup per supernode.  M_j = (L^D_j)^{-T} (upper triangular,
@@ -181,7 +186,7 @@ struct IntSn {
 };
 
 struct SweepTask {
-  int64_t m, x, u;             // u < 0: explicit L^O_j
+  int64_t m, x, u;             // u < 0: explicit L^O_j, else W_j = M_j U_j (c x l, ld c)
   int64_t first;               // first column of the supernode (permuted index)
   int64_t rows;                // offset of its rows R_j in the row list and in zr
   int32_t c, r, ld;
