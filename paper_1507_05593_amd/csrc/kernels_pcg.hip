@@ -65,8 +65,10 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvTask* __restrict__ tas
 
 // Backward diagonal solve chunk: rows i in [i0, i0 + 64) (lanes) of M (w - s) over the
 // columns [t0, t1) (kind 0), or of -W u over W's columns [t0, t1) below the device rank
-// (kind 1); the vector is staged in LDS, the four waves take consecutive column quarters,
-// and their sums are added in a fixed order into one partial block.
+// (kind 1); the vector is staged in LDS (s or u added up from the column dots' partial
+// blocks when they were cut into row chunks), the four waves take consecutive column
+// quarters, and their sums are added in a fixed order into one partial block (at slots
+// past those it reads).
 template <typename TF>
 __global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ chunks,
                                                   const double* __restrict__ arena, const TF* __restrict__ F,
@@ -79,8 +81,18 @@ __global__ __launch_bounds__(256) void k_row_part(const RowChunk* __restrict__ c
   const int t1 = T.kind ? min(T.t1, min(ilim[T.qslot], T.kmax)) : T.t1;
   const int n = max(0, t1 - T.t0);
   for (int t = threadIdx.x; t < n; t += 256) {
-    const double a = arena[T.w + T.t0 + t];
-    v[t] = T.s >= 0 ? a - arena[T.s + T.t0 + t] : a;
+    const int col = T.t0 + t;
+    double sv = 0.0;                       // s or u from the column dots' partial blocks
+    if (T.sns > 0) {
+      const double* pp = part + ((int64_t)T.sbase + (int64_t)(col >> 4) * T.sns) * 64 + (col & 15);
+      for (int q = 0; q < T.sns; ++q) sv += pp[(int64_t)q * 64];
+    }
+    if (T.kind) {
+      v[t] = T.sns > 0 ? sv : arena[T.w + col];
+    } else {
+      const double a = arena[T.w + col];
+      v[t] = T.s >= 0 ? a - arena[T.s + col] : (T.sns > 0 ? a - sv : a);
+    }
   }
   __syncthreads();
   const int i = T.i0 + lane;

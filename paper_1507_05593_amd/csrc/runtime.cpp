@@ -2247,13 +2247,17 @@ static Error build_solve_plan(Handle& h) {
   // Column-dot launch of one sweep stage.  When the stage has fewer than 2048 tasks,
   // the rows of every task are cut into chunks (so that the stage has about 2048
   // workgroups) whose 16 sums go to partial blocks, stored in order by a second launch.
-  auto coldot_stage = [&](std::vector<ColDotTask>& ts) {
-    if (ts.empty()) return;
+  // With `kept`, the partial blocks of a chunked output vector are left for the next
+  // launch to add (kept[out] = first slot and chunks per 16-column task) instead.
+  // Returns the partial blocks used.
+  using KeptParts = std::map<int64_t, std::pair<int32_t, int32_t>>;
+  auto coldot_stage = [&](std::vector<ColDotTask>& ts, KeptParts* kept = nullptr) -> int32_t {
+    if (ts.empty()) return 0;
     const int64_t c0 = (int64_t)Q->coldot.size();
     if (ts.size() >= 2048) {
       for (auto& t : ts) { t.r0 = 0; t.r1 = INT_MAX; t.slot = -1; Q->coldot.push_back(t); }
       cmd(kCmdColDot, c0, (int64_t)ts.size());
-      return;
+      return 0;
     }
     double rows = 0;
     for (auto& t : ts) rows += t.tri ? std::min(t.rows, t.col0 + 16) : t.rows;
@@ -2269,6 +2273,10 @@ static Error build_solve_plan(Handle& h) {
         u.r0 = r0; u.r1 = std::min(R, r0 + chunk); u.slot = slot++;
         Q->coldot.push_back(u);
       }
+      if (kept) {
+        if (!kept->count(t.out)) (*kept)[t.out] = {s0, slot - s0};
+        continue;
+      }
       // a static column count ends the block at the supernode's last column; a device
       // rank may not, but those outputs are padded to a multiple of 64
       const int32_t nout = t.ncols >= 0 ? std::min(16, t.ncols - t.col0) : 16;
@@ -2277,6 +2285,7 @@ static Error build_solve_plan(Handle& h) {
     Q->part_slots = std::max<int64_t>(Q->part_slots, slot);
     cmd(kCmdColDot, c0, (int64_t)Q->coldot.size() - c0);
     if ((int64_t)Q->papply.size() > a0) cmd(kCmdPartApply, a0, (int64_t)Q->papply.size() - a0);
+    return slot;
   };
   auto iscomp = [&](int64_t j) { return comp && h.compressible[j]; };
   // the inverse diagonal blocks M_j: in the panels (FP64 sweeps), or the FP32 copy's
@@ -2602,7 +2611,8 @@ static Error build_solve_plan(Handle& h) {
         bytes += 2.0 * 8.0 * (double)rr(j) * c;   // read by both sweeps
       }
     }
-    coldot_stage(st);
+    KeptParts kept;                // chunked s_C and u: added up by the b2 chunks below
+    const int32_t b1_slots = coldot_stage(st, &kept);
     for (int32_t j : lev)
       if (iscomp(j)) bytes += 2.0 * 8.0 * (double)(S.c(j) + S.r(j)) * h.comp[j].ell;
     // b2: z_C = L_j^{-T} (w_C - s_C) by 64-row blocks, the columns of each block cut
@@ -2616,15 +2626,21 @@ static Error build_solve_plan(Handle& h) {
       const int32_t width =
           (int32_t)std::min<double>(kRowChunkMax, std::max(256.0, std::ceil(cols / 1024.0)));
       const int64_t c0r = (int64_t)Q->rchunks.size(), a0 = (int64_t)Q->papply.size();
-      int32_t slot = 0;
+      int32_t slot = b1_slots;     // past the column dots' blocks that the chunks read
       for (int32_t j : lev) {
         const int32_t c = S.c(j);
+        const int64_t sout = iscomp(j) ? h.comp[j].u : h.a_s + S.first[j];
+        const auto kp = kept.find(sout);
+        const int32_t sbase = kp == kept.end() ? 0 : kp->second.first;
+        const int32_t sns = kp == kept.end() ? 0 : kp->second.second;
         for (int32_t i0 = 0; i0 < c; i0 += 64) {
           const int32_t s0 = slot;
           for (int32_t t0 = i0; t0 < c; t0 += width) {
             RowChunk t{};
             t.m = m_off(j); t.ld = m_ld(j); t.c = c; t.i0 = i0;
-            t.w = h.a_w + S.first[j]; t.s = (!iscomp(j) && rr(j) > 0) ? h.a_s + S.first[j] : -1;
+            t.w = h.a_w + S.first[j];
+            t.s = (!iscomp(j) && rr(j) > 0 && sns == 0) ? h.a_s + S.first[j] : -1;
+            if (!iscomp(j)) { t.sbase = sbase; t.sns = sns; }
             t.t0 = t0; t.t1 = std::min(c, t0 + width); t.slot = slot++;
             Q->rchunks.push_back(t);
           }
@@ -2633,7 +2649,7 @@ static Error build_solve_plan(Handle& h) {
             for (int32_t t0 = 0; t0 < C.ell; t0 += width) {
               RowChunk t{};
               t.kind = 1; t.m = C.Uj; t.ld = c; t.c = c; t.i0 = i0; t.w = C.u; t.s = -1;
-              t.qslot = C.qslot; t.kmax = C.ell;
+              t.qslot = C.qslot; t.kmax = C.ell; t.sbase = sbase; t.sns = sns;
               t.t0 = t0; t.t1 = std::min(C.ell, t0 + width); t.slot = slot++;
               Q->rchunks.push_back(t);
             }

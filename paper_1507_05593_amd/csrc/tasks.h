@@ -167,6 +167,9 @@ struct RowChunk {
                                // 1: rows of -W u, W = M_j U_j (c x l at m, ld c), u at w, over
                                //    columns [t0, t1) cut at the device rank
   int32_t qslot, kmax;         // kind 1: int-arena slot of the rank and its bound
+  int32_t sbase, sns;          // sns > 0: s (kind 0) or u (kind 1) is the sum of column-dot
+                               // partial blocks: entry t is the sum over q < sns, in order, of
+                               // entry t % 16 of block sbase + (t / 16) sns + q
   int32_t pad_;
 };
 // One supernode of a small-supernode sweep level: both sweeps of the level run in one
