@@ -25,6 +25,10 @@ void launch_gram_scale(const int64_t* g, const int32_t* ld, const int32_t* nn, c
                        const int64_t* out, int n, double* arena, hipStream_t s);
 void launch_trunc_prep(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s);
+// the power iteration of k_trunc_power as one launch per product over 64-row blocks
+// (step it = 0..4; lmax: the largest l of the tasks), then lambda_max and theta
+void launch_trunc_pmv(const TruncTask* t, int n, int lmax, int it, double* arena, hipStream_t s);
+void launch_trunc_pfin(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_p(const TruncTask* t, int n, double* arena, hipStream_t s);
 void launch_trunc_compact(const TruncTask* t, int n, double* arena, int32_t* ints, hipStream_t s);

@@ -275,6 +275,78 @@ __global__ __launch_bounds__(1024) void k_trunc_power(const TruncTask* __restric
   if (threadIdx.x == 0) { arena[T.sc + 1] = lam; arena[T.sc + 2] = theta; }
 }
 
+// The same power iteration for large l, one launch per matrix-vector product over a grid
+// (64-row blocks, tasks): step it < 4 forms w_it = S32 v with v = w_{it-1} / |w_{it-1}| (the
+// start vector of k_trunc_power for it = 0); step 4 forms the Rayleigh quotient's partial
+// sums v^T (G v) and v^T v of each row block with v = w_3 / |w_3|.  The vectors alternate
+// between the first two l-blocks of the work block at wout (free until the projector
+// iteration), the partial sums go to sc[64 + 2 rb] and sc[65 + 2 rb]; every workgroup
+// forms the norm of the previous vector in the same order, so they all scale alike.
+__global__ __launch_bounds__(256) void k_trunc_pmv(const TruncTask* __restrict__ tasks,
+                                                   double* __restrict__ arena, int it) {
+  __shared__ double v[2048];            // l <= 2048 (checked by the planner)
+  __shared__ double red[4][64];
+  const TruncTask T = tasks[blockIdx.y];
+  const int l = T.l, r0 = 64 * blockIdx.x;
+  if (r0 >= l) return;
+  if (it == 0) {
+    for (int i = threadIdx.x; i < l; i += 256) {
+      uint32_t h = (uint32_t)i * 2654435761u + 0x9E3779B9u;
+      h ^= h >> 15; h *= 2246822519u; h ^= h >> 13;
+      v[i] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
+    }
+  } else {
+    const double* wp = arena + T.wout + (int64_t)((it - 1) & 1) * l;
+    double nn = 0.0;
+    for (int i = threadIdx.x; i < l; i += 256) nn += wp[i] * wp[i];
+    nn = block_sum256(nn);
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = threadIdx.x; i < l; i += 256) v[i] = wp[i] * inv;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, i = r0 + lane;
+  const double* Mx = arena + (it < 4 ? T.sb : T.g);
+  double acc = 0.0;
+  if (i < l) {
+    const int per = (l + 3) / 4, k0 = w * per, k1 = min(l, k0 + per);
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) acc += Mx[i + (int64_t)k * l] * v[k];
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w != 0) return;
+  const double y = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+  if (it < 4) {
+    if (i < l) arena[T.wout + (int64_t)(it & 1) * l + i] = y;
+    return;
+  }
+  double num = i < l ? v[i] * y : 0.0, den = i < l ? v[i] * v[i] : 0.0;
+  for (int o = 32; o > 0; o >>= 1) {
+    num += __shfl_xor(num, o, 64);
+    den += __shfl_xor(den, o, 64);
+  }
+  if (lane == 0) {
+    arena[T.sc + 64 + 2 * blockIdx.x] = num;
+    arena[T.sc + 65 + 2 * blockIdx.x] = den;
+  }
+}
+
+// lambda_max and theta from k_trunc_pmv's partial sums (row blocks in order).
+__global__ void k_trunc_pfin(const TruncTask* __restrict__ tasks, int n, double* __restrict__ arena) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const TruncTask T = tasks[t];
+  double num = 0.0, den = 0.0;
+  for (int rb = 0; rb < (T.l + 63) / 64; ++rb) {
+    num += arena[T.sc + 64 + 2 * rb];
+    den += arena[T.sc + 65 + 2 * rb];
+  }
+  double lam = (den > 0.0) ? num / den : 0.0;
+  if (!isfinite(lam) || lam < 0.0) lam = 0.0;
+  arena[T.sc + 1] = lam;
+  arena[T.sc + 2] = T.tol * T.tol * lam;
+}
+
 // The Cholesky panel [G + theta I; I] (ld 2l) of the truncation and its drop scale (the
 // largest diagonal entry); grid (blocks, tasks).
 __global__ __launch_bounds__(256) void k_trunc_mfill(const TruncTask* __restrict__ tasks,
@@ -591,6 +663,12 @@ void launch_trunc_copy(const TruncTask* t, int n, int lmax, double* arena, hipSt
 }
 void launch_trunc_power(const TruncTask* t, int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_power, dim3(n), dim3(1024), 0, s, t, arena);
+}
+void launch_trunc_pmv(const TruncTask* t, int n, int lmax, int it, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_pmv, dim3((lmax + 63) / 64, n), dim3(256), 0, s, t, arena, it);
+}
+void launch_trunc_pfin(const TruncTask* t, int n, double* arena, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_trunc_pfin, dim3((n + 63) / 64), dim3(64), 0, s, t, n, arena);
 }
 void launch_trunc_x0(const TruncTask* t, int n, double* arena, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_trunc_x0, dim3(64, n), dim3(256), 0, s, t, arena);

@@ -65,6 +65,9 @@ static NsSchedule ns_schedule() {
 }
 static const NsSchedule kNs = ns_schedule();
 static constexpr int32_t kOuter = 256;   // outer block width of the panel factorisation
+// levels whose largest sample count exceeds this run the truncation's power iteration as
+// row-block launches (one workgroup per supernode streams l^2 entries per product)
+static constexpr int32_t kPowerRowsMin = 256;
 
 int32_t sample_count(int32_t r, int32_t c, double alpha, int32_t p) {
   const int32_t k = std::min(r, c);
@@ -254,7 +257,7 @@ void plan_layout(Handle& h) {
       C.Mdinv = p; p += ((l + 63) / 64) * 4096;
       C.Wpan = p; p += align64(2 * l * l);
       C.Wdinv = p; p += ((l + 63) / 64) * 4096;
-      C.sc = p; p += 64;
+      C.sc = p; p += 128;   // scalars [0, 64), power-iteration partial sums [64, 128)
       if (h.opt.power_iters > 0) {
         C.zpanel = p; p += align64((l + r) * l);
         C.zdinv = p; p += ((l + 63) / 64) * 4096;
@@ -1362,7 +1365,17 @@ struct Builder {
     };
     cmd(kCmdTruncPrep, RSC_K_EIG, t0, nt, 0);          // sa = G / tr G
     for (int k = 0; k < 5; ++k) sq_gemm(k % 2 == 0, 1.0, 0.0, -1);   // sb = (G / tr G)^32
-    cmd(kCmdTruncPower, RSC_K_EIG, t0, nt, 0);         // lambda_max, theta
+    {
+      // lambda_max, theta: one workgroup per supernode, or for large l each product of
+      // the power iteration as its own launch over 64-row blocks
+      int32_t lmax = 0;
+      for (int32_t j : js) lmax = std::max(lmax, h.comp[j].ell);
+      if (lmax > kPowerRowsMin) {
+        for (int32_t it = 0; it <= 5; ++it) cmd(kCmdTruncPower, RSC_K_EIG, t0, nt, 0, lmax, it);
+      } else {
+        cmd(kCmdTruncPower, RSC_K_EIG, t0, nt, 0);
+      }
+    }
     cmd(kCmdTruncMfill, RSC_K_EIG, t0, nt, 0);         // [G + theta I; I]
     {
       std::vector<PanelDesc> pan;
@@ -1998,7 +2011,11 @@ static void launch_cmd(Handle& h, const Cmd& c, const FactorPlan* P, const Solve
                         P->d_gs_m.p + c.off, P->d_gs_out.p + c.off, (int)c.count, A, s);
       break;
     case kCmdTruncPrep: launch_trunc_prep(P->d_trunc.p + c.off, (int)c.count, A, s); break;
-    case kCmdTruncPower: launch_trunc_power(P->d_trunc.p + c.off, (int)c.count, A, s); break;
+    case kCmdTruncPower:
+      if (c.a == 0) launch_trunc_power(P->d_trunc.p + c.off, (int)c.count, A, s);
+      else if (c.b < 5) launch_trunc_pmv(P->d_trunc.p + c.off, (int)c.count, (int)c.a, (int)c.b, A, s);
+      else launch_trunc_pfin(P->d_trunc.p + c.off, (int)c.count, A, s);
+      break;
     case kCmdTruncX0: launch_trunc_x0(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncP: launch_trunc_p(P->d_trunc.p + c.off, (int)c.count, A, s); break;
     case kCmdTruncCompact: launch_trunc_compact(P->d_trunc.p + c.off, (int)c.count, A, I, s); break;
