@@ -104,7 +104,9 @@ __global__ void k_philox(const PhiloxTask* __restrict__ tasks, double* __restric
   const int64_t total = (int64_t)T.rows * ngrp;
   for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < total;
        id += (int64_t)gridDim.x * blockDim.x) {
-    const int row = (int)(id / ngrp), g = (int)(id % ngrp);
+    // consecutive threads on consecutive rows: each of the four column stores is
+    // coalesced (the values depend only on the counter (row, g), not on the thread)
+    const int row = (int)(id % T.rows), g = (int)(id / T.rows);
     uint32_t c[4] = {(uint32_t)row, (uint32_t)g, T.c2, 0u};
     philox4x32_10(c, T.k0, T.k1);
     double out[4];
