@@ -330,8 +330,25 @@ __global__ __launch_bounds__(256) void k_spmv_dot(const Chunk* __restrict__ chun
   const int64_t i = C.begin + threadIdx.x;
   double d = 0.0;
   if (i < C.end) {
+    // a row's entries eight at a time: the index and value loads of a group, then its
+    // gathers, are in flight together; the products are added in entry order as before
     double s = 0.0;
-    for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += vals[q] * p[colind[q]];
+    const int64_t q0 = rowptr[i], q1 = rowptr[i + 1];
+    for (int64_t qb = q0; qb < q1; qb += 8) {
+      int32_t cq[8];
+      double vq[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = qb + u < q1;
+        cq[u] = in ? colind[qb + u] : (int32_t)i;
+        vq[u] = in ? vals[qb + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double t = vq[u] * p[cq[u]];
+        if (qb + u < q1) s += t;
+      }
+    }
     Ap[i] = s;
     d = p[i] * s;
   }
