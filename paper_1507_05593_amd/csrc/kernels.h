@@ -101,12 +101,11 @@ void launch_resid_partial(const Chunk* c, int nc, const double* b, const double*
                           double* partial, hipStream_t s);
 void launch_seg_sum(const int32_t* seg_ptr, int32_t nseg, const double* partial, double* out,
                     hipStream_t s);
-void launch_pcg_alpha(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s);
+// per-system sum of partials, then alpha (kind 0), the convergence test (1) or beta (2)
+void launch_seg_step(const int32_t* seg_ptr, int32_t nseg, const double* partial, const PcgScalars& sc,
+                     double rtol, double* arena, int32_t* ints, int kind, hipStream_t s);
 void launch_pcg_xr(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
                    double* partial, hipStream_t s);
-void launch_pcg_check(int32_t nseg, const PcgScalars& sc, double rtol, double* arena, int32_t* ints,
-                      hipStream_t s);
-void launch_pcg_beta(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s);
 void launch_pcg_p(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
                   int first, hipStream_t s);
 void launch_pcg_start(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s);

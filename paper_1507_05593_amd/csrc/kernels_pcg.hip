@@ -395,25 +395,57 @@ __global__ __launch_bounds__(256) void k_seg_sum(const int32_t* __restrict__ seg
   if (threadIdx.x == 0) out[s] = acc;
 }
 
-// Per-system CG scalars.  sc layout (doubles, per segment s): see PcgScalars.
-__global__ void k_pcg_alpha(int32_t nseg, PcgScalars sc, double* __restrict__ arena,
-                            int32_t* __restrict__ ints) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  double* pAp = arena + sc.pAp;
-  double* rz = arena + sc.rz;
-  double* alpha = arena + sc.alpha;
+// A system's sum of chunk partials (as k_seg_sum) followed by the CG scalar step that
+// uses it, one workgroup per system: kind 0, p^T A p then alpha = r^T z / p^T A p (and
+// the "any system active" flag cleared for this iteration's test); kind 1, r^T r then
+// the convergence test |r| / |b| <= rtol, which counts the iteration; kind 2, the new
+// r^T z then beta.  A non-positive p^T A p or r^T z stops the system and flags a
+// breakdown.
+__global__ __launch_bounds__(256) void k_seg_step(const int32_t* __restrict__ seg_ptr,
+                                                  const double* __restrict__ partial, PcgScalars sc,
+                                                  double rtol, double* __restrict__ arena,
+                                                  int32_t* __restrict__ ints, int kind) {
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int c = seg_ptr[s] + threadIdx.x; c < seg_ptr[s + 1]; c += 256) acc += partial[c];
+  acc = block_sum(acc);
+  if (threadIdx.x != 0) return;
   int32_t* active = ints + sc.active;
-  double a = 0.0;
-  if (active[s]) {
-    if (!(pAp[s] > 0.0) || !(rz[s] > 0.0)) {
+  if (kind == 0) {
+    arena[sc.pAp + s] = acc;
+    if (s == 0) ints[sc.any] = 0;
+    const double rz = arena[sc.rz + s];
+    double a = 0.0;
+    if (active[s]) {
+      if (!(acc > 0.0) || !(rz > 0.0)) {
+        ints[sc.breakdown] = 1;
+        active[s] = 0;
+      } else {
+        a = rz / acc;
+      }
+    }
+    arena[sc.alpha + s] = a;
+  } else if (kind == 1) {
+    arena[sc.rr + s] = acc;
+    if (!active[s]) return;
+    ints[sc.iters + s] += 1;
+    const double rel = sqrt(acc) / arena[sc.bnorm + s];
+    arena[sc.rel + s] = rel;
+    if (rel <= rtol || !isfinite(rel)) active[s] = 0;
+    else atomicOr(ints + sc.any, 1);
+  } else {
+    arena[sc.rznew + s] = acc;
+    if (!active[s]) { arena[sc.beta + s] = 0.0; return; }
+    const double rzo = arena[sc.rz + s];
+    if (!(acc > 0.0) || !(rzo > 0.0)) {
       ints[sc.breakdown] = 1;
       active[s] = 0;
-    } else {
-      a = rz[s] / pAp[s];
+      arena[sc.beta + s] = 0.0;
+      return;
     }
+    arena[sc.beta + s] = acc / rzo;
+    arena[sc.rz + s] = acc;
   }
-  alpha[s] = a;
 }
 
 __global__ __launch_bounds__(256) void k_pcg_xr(const Chunk* __restrict__ chunks, PcgScalars sc,
@@ -437,41 +469,6 @@ __global__ __launch_bounds__(256) void k_pcg_xr(const Chunk* __restrict__ chunks
   }
   d = block_sum(d);
   if (threadIdx.x == 0) partial[blockIdx.x] = d;
-}
-
-// Convergence test ||r|| / ||b|| <= rtol per system; counts the iteration.
-__global__ void k_pcg_check(int32_t nseg, PcgScalars sc, double rtol, double* __restrict__ arena,
-                            int32_t* __restrict__ ints) {
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
-    int32_t* active = ints + sc.active;
-    if (!active[s]) continue;
-    ints[sc.iters + s] += 1;
-    const double rel = sqrt(arena[sc.rr + s]) / arena[sc.bnorm + s];
-    arena[sc.rel + s] = rel;
-    if (rel <= rtol || !isfinite(rel)) active[s] = 0;
-    else atomicOr(&any, 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) ints[sc.any] = any;
-}
-
-__global__ void k_pcg_beta(int32_t nseg, PcgScalars sc, double* __restrict__ arena,
-                           int32_t* __restrict__ ints) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  if (!ints[sc.active + s]) { arena[sc.beta + s] = 0.0; return; }
-  const double rzn = arena[sc.rznew + s], rzo = arena[sc.rz + s];
-  if (!(rzn > 0.0) || !(rzo > 0.0)) {
-    ints[sc.breakdown] = 1;
-    ints[sc.active + s] = 0;
-    arena[sc.beta + s] = 0.0;
-    return;
-  }
-  arena[sc.beta + s] = rzn / rzo;
-  arena[sc.rz + s] = rzn;
 }
 
 __global__ __launch_bounds__(256) void k_pcg_p(const Chunk* __restrict__ chunks, PcgScalars sc,
@@ -770,19 +767,14 @@ void launch_seg_sum(const int32_t* seg_ptr, int32_t nseg, const double* partial,
                     hipStream_t s) {
   if (nseg > 0) hipLaunchKernelGGL(k_seg_sum, dim3(nseg), dim3(256), 0, s, seg_ptr, nseg, partial, out);
 }
-void launch_pcg_alpha(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_alpha, dim3((nseg + 255) / 256), dim3(256), 0, s, nseg, sc, arena, ints);
+void launch_seg_step(const int32_t* seg_ptr, int32_t nseg, const double* partial, const PcgScalars& sc,
+                     double rtol, double* arena, int32_t* ints, int kind, hipStream_t s) {
+  if (nseg > 0)
+    hipLaunchKernelGGL(k_seg_step, dim3(nseg), dim3(256), 0, s, seg_ptr, partial, sc, rtol, arena, ints, kind);
 }
 void launch_pcg_xr(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
                    double* partial, hipStream_t s) {
   if (nc > 0) hipLaunchKernelGGL(k_pcg_xr, dim3(nc), dim3(256), 0, s, c, sc, arena, ints, partial);
-}
-void launch_pcg_check(int32_t nseg, const PcgScalars& sc, double rtol, double* arena, int32_t* ints,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, s, nseg, sc, rtol, arena, ints);
-}
-void launch_pcg_beta(int32_t nseg, const PcgScalars& sc, double* arena, int32_t* ints, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_beta, dim3((nseg + 255) / 256), dim3(256), 0, s, nseg, sc, arena, ints);
 }
 void launch_pcg_p(const Chunk* c, int nc, const PcgScalars& sc, double* arena, const int32_t* ints,
                   int first, hipStream_t s) {

@@ -2794,11 +2794,9 @@ Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, 
 
   auto part_a = [&](hipStream_t s) -> Error {
     launch_spmv_dot(ch, nc, h.d_rowptr.p, h.d_colind.p, vals, A + sc.p, A + sc.Ap, partial, s);
-    launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.pAp, s);
-    launch_pcg_alpha(nseg, sc, A, I, s);
+    launch_seg_step(h.d_seg_chunk_ptr.p, nseg, partial, sc, rtol, A, I, 0, s);   // p^T A p, alpha
     launch_pcg_xr(ch, nc, sc, A, I, partial, s);
-    launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rr, s);
-    launch_pcg_check(nseg, sc, rtol, A, I, s);
+    launch_seg_step(h.d_seg_chunk_ptr.p, nseg, partial, sc, rtol, A, I, 1, s);   // r^T r, test
     HIPCHK(hipGetLastError());
     return kOk;
   };
@@ -2806,8 +2804,7 @@ Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, 
     Error r = apply_cmds(h, s, nullptr);
     if (r.code) return r;
     launch_dot_partial(ch, nc, A + sc.r, A + sc.z, partial, s);
-    launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rznew, s);
-    launch_pcg_beta(nseg, sc, A, I, s);
+    launch_seg_step(h.d_seg_chunk_ptr.p, nseg, partial, sc, rtol, A, I, 2, s);   // r^T z, beta
     launch_pcg_p(ch, nc, sc, A, I, 0, s);
     HIPCHK(hipGetLastError());
     return kOk;
@@ -2858,8 +2855,7 @@ Error pcg(Handle& h, const double* b, double* x, double rtol, int32_t max_iter, 
       if (pe) {
         if ((e = apply_cmds(h, stream, pe)).code) return e;
         launch_dot_partial(ch, nc, A + sc.r, A + sc.z, partial, stream);
-        launch_seg_sum(h.d_seg_chunk_ptr.p, nseg, partial, A + sc.rznew, stream);
-        launch_pcg_beta(nseg, sc, A, I, stream);
+        launch_seg_step(h.d_seg_chunk_ptr.p, nseg, partial, sc, rtol, A, I, 2, stream);
         launch_pcg_p(ch, nc, sc, A, I, 0, stream);
       } else if ((e = part_b(stream)).code) {
         return e;
