@@ -32,9 +32,9 @@ __device__ double block_sum(double v) {
 
 // ---------------------------------------------------------------- sweeps
 
-// The factor operands of the sweeps (L^O_j, U_j, V_j, the inverse diagonal blocks) are
-// read through F: the arena itself (TF = double), or in the mixed forms its FP32 copy
-// (TF = float: L^O_j, U_j and V_j at their arena offsets, the inverse blocks M_j compact,
+// The factor operands of the sweeps (L^O_j, V_j, W_j = M_j U_j, the inverse diagonal
+// blocks) are read through F: the arena itself (TF = double), or in the mixed forms its
+// FP32 copy (TF = float: L^O_j, V_j and W_j at their arena offsets, the inverse blocks M_j compact,
 // written once the factorization is complete); the vectors and every sum stay FP64.
 
 // out[t] = sum_{m < K} X(t, m) v[m] for up to 64 rows: lane = row (coalesced column

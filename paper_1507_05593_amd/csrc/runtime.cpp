@@ -6,8 +6,8 @@
 //   start as the identity and end as M_j = (L^D_j)^{-T} (the same blocked factorisation
 //   step), the explicit inverse that the sweeps and the implicit products use.
 //   L^O_j (r_j x c_j, ld r_j, rows R_j in order) has a block of its own; a compressed
-//   supernode holds V_j (r x l_j) and U_j (c x l_j) instead (the first q_j columns are
-//   the kept basis).  The Schur update U^O_j and the range finder's work space live in a
+//   supernode holds V_j (r x l_j) and W_j = M_j U_j (c x l_j, the kept basis U_j in the
+//   form the sweeps apply) instead (the first q_j columns are the kept basis).  The Schur update U^O_j and the range finder's work space live in a
 //   level pool that every elimination-tree level reuses.
 #include "runtime.h"
 
@@ -189,8 +189,8 @@ void plan_layout(Handle& h) {
       a += align64((int64_t)S.c(j) * S.r(j));
     }
   // Region X.  Exact factor: the dense L^O_j of the compressible supernodes.  Rank-
-  // structured factor: their V_j, U_j and the sweeps' two small vectors (and L^O_j when
-  // it is kept for inspection).
+  // structured factor: their V_j, W_j = M_j U_j (slot Uj) and the sweeps' two small
+  // vectors (and L^O_j when it is kept for inspection).
   const int64_t aX = a;
   int64_t ax = aX;
   for (int64_t j = 0; j < M; ++j)
@@ -1110,7 +1110,7 @@ struct Builder {
   }
 
   // FP32 copy (mixed forms) of the factor operands the two sweeps of the preconditioner
-  // read: the inverse diagonal blocks M_j as compact c x c blocks, U_j at its arena
+  // read: the inverse diagonal blocks M_j as compact c x c blocks, W_j at its arena
   // offsets (L^O_j and V_j are copied by k_compact_rows along with their compact copies);
   // blocks of at most 64 columns and kConvRows rows.
   void f32_copy() {

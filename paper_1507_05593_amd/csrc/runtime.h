@@ -80,6 +80,7 @@ struct DevArray {
 // Per-supernode storage of the compressed form and its work space (arena offsets).
 struct CompSlot {
   int32_t ell = 0;
+  // Vj: V_j (r x l); Uj: the kept basis as W_j = M_j U_j (c x l), the form the sweeps apply
   int64_t omega = -1, ypanel = -1, ydinv = -1, V = -1, Vj = -1, Uj = -1, gscale = -1, tvq = -1,
           u = -1;
   int64_t tmp = -1;                  // c x l work block of the implicit products
@@ -230,7 +231,7 @@ struct Handle {
   int64_t arena_size_exact = 0, arena_size_comp = 0;   // length each layout needs
   int64_t panels_size = 0;
   int64_t f32_end_exact = 0, f32_end_comp = 0;          // end of the sweeps' operands per layout
-  // FP32 copy (mixed forms): offsets [a_lo, f32_end) mirror the arena (L^O_j, V_j, U_j);
+  // FP32 copy (mixed forms): offsets [a_lo, f32_end) mirror the arena (L^O_j, V_j, W_j);
   // below a_lo, m32_size floats hold each M_j compact (c x c, ld c) at m32_off[j]
   int64_t a_lo = 0, m32_size = 0;
   std::vector<int64_t> m32_off;

@@ -175,7 +175,8 @@ struct RowChunk {
 // One supernode of a small-supernode sweep level: both sweeps of the level run in one
 // launch each, one workgroup per supernode.  M_j = (L^D_j)^{-T} (upper triangular,
 // M(i, t) = F[m + i + t*ld]); the off-diagonal operand X is L^O_j (r x c) or, compressed,
-// V_j (r x l) with U_j (c x l, ld c) and the rank in the int arena; both column major.
+// V_j (r x l) with W_j = M_j U_j (c x l, ld c) and the rank in the int arena; both column
+// major.
 constexpr int32_t kSweepMaxR = 2048;   // rows R_j of a small-sweep supernode (LDS)
 // Interior blocks (Sec. 5.1): one step of a solve with a block's own factor for one of
 // its supernodes (the supernodes of one elimination-tree level run in the same launch).
